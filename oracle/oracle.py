@@ -1,0 +1,213 @@
+"""Python face of the FP64 CPU oracle (``rism_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by
+the CPU-baseline leg of the benchmark, never by the library.  It does not
+import the package under test; callers pass plain numpy arrays.
+
+Each function is a thin ctypes call into the C direct sums; see the C file
+for the definitions and the paper passages they follow.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rism_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_P = C.POINTER(C.c_double)
+_PI = C.POINTER(C.c_int32)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
+                               "-std=c99", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = C.CDLL(_LIB)
+        i64, i32, d = C.c_int64, C.c_int32, C.c_double
+        lib.oracle_potential_points.argtypes = [i64, _P, _P, _P, _P, i32, _P, _P, _P,
+                                                d, _P, C.c_int, i64, _P, _P]
+        lib.oracle_potential_grid.argtypes = [i64, _P, _P, _P, _P, i32, _P, _P, _P,
+                                              d, _P, C.c_int, _P, _P, _PI, _P]
+        lib.oracle_asymptotics_points.argtypes = [i64, _P, _P, i32, _P, _PI, d, d, d, d, d,
+                                                  i64, _P, _P, _P]
+        lib.oracle_asymptotics_grid.argtypes = [i64, _P, _P, i32, _P, _PI, d, d, d, d, d,
+                                                _P, _P, _PI, _P, _P]
+        lib.oracle_lj_rcut_from_tol.argtypes = [d, d, d]
+        lib.oracle_lj_rcut_from_tol.restype = d
+        lib.oracle_lj_rcut_table.argtypes = [i64, _P, _P, i32, _P, _P, d, d, _P]
+        lib.oracle_lj_tail.argtypes = [i64, _P, _P, i32, _P, _P, _P, _P]
+        lib.oracle_backward_points.argtypes = [i64, _P, _P, _P, _P, i32, _P, _P, _P, d, _P,
+                                               i64, _P, _P, _P, _P, _P, _P]
+        lib.oracle_grid_points.argtypes = [_P, _P, _PI, _P]
+        lib.oracle_num_threads.restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def _d(a):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def _ptr(a, t=_P):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def _atoms(xyz, q, sigma, eps):
+    return (_d(np.asarray(xyz).reshape(-1, 3)), _d(q), _d(sigma), _d(eps))
+
+
+def rcut_table(sigma, eps, site_sigma, site_eps, rcut=0.0, tol=0.0):
+    """[S][N] cut-off radii: ``rcut`` for all pairs, or per pair from ``tol``."""
+    lib = _load()
+    sigma, eps, ss, se = _d(sigma), _d(eps), _d(site_sigma), _d(site_eps)
+    out = np.empty((len(ss), len(sigma)))
+    rc = lib.oracle_lj_rcut_table(len(sigma), _ptr(sigma), _ptr(eps), len(ss), _ptr(ss),
+                                  _ptr(se), float(rcut), float(tol), _ptr(out))
+    if rc != 0:
+        raise ValueError("no LJ cut-off radius for this tolerance")
+    return out
+
+
+def lj_rcut_from_tol(sigma_pair, eps_pair, tol):
+    return float(_load().oracle_lj_rcut_from_tol(sigma_pair, eps_pair, tol))
+
+
+def lj_tail(sigma, eps, site_sigma, site_eps, rcut_tab):
+    lib = _load()
+    sigma, eps, ss, se = _d(sigma), _d(eps), _d(site_sigma), _d(site_eps)
+    rct = _d(rcut_tab)
+    out = np.empty(len(ss))
+    lib.oracle_lj_tail(len(sigma), _ptr(sigma), _ptr(eps), len(ss), _ptr(ss), _ptr(se),
+                       _ptr(rct), _ptr(out))
+    return out
+
+
+def potential_points(xyz, q, sigma, eps, site_q, site_sigma, site_eps, pts,
+                     kc, rcut_tab=None, terms=3):
+    """u[S][npts] at arbitrary points (npts, 3)."""
+    lib = _load()
+    xyz, q, sigma, eps = _atoms(xyz, q, sigma, eps)
+    sq, ss, se = _d(site_q), _d(site_sigma), _d(site_eps)
+    pts = _d(np.asarray(pts).reshape(-1, 3))
+    rct = _d(rcut_tab)
+    out = np.empty((len(sq), len(pts)))
+    rc = lib.oracle_potential_points(len(q), _ptr(xyz), _ptr(q), _ptr(sigma), _ptr(eps),
+                                     len(sq), _ptr(sq), _ptr(ss), _ptr(se), float(kc),
+                                     _ptr(rct), int(terms), len(pts), _ptr(pts), _ptr(out))
+    assert rc == 0
+    return out
+
+
+def potential_grid(xyz, q, sigma, eps, site_q, site_sigma, site_eps, origin, spacing,
+                   dims, kc, rcut_tab=None, terms=3):
+    """u[S][nz][ny][nx] on the grid origin + (i, j, k) * spacing."""
+    lib = _load()
+    xyz, q, sigma, eps = _atoms(xyz, q, sigma, eps)
+    sq, ss, se = _d(site_q), _d(site_sigma), _d(site_eps)
+    o, h = _d(origin), _d(spacing)
+    dm = np.ascontiguousarray(dims, dtype=np.int32)
+    rct = _d(rcut_tab)
+    out = np.empty((len(sq), int(dm[2]), int(dm[1]), int(dm[0])))
+    rc = lib.oracle_potential_grid(len(q), _ptr(xyz), _ptr(q), _ptr(sigma), _ptr(eps),
+                                   len(sq), _ptr(sq), _ptr(ss), _ptr(se), float(kc),
+                                   _ptr(rct), int(terms), _ptr(o), _ptr(h), _ptr(dm, _PI),
+                                   _ptr(out))
+    assert rc == 0
+    return out
+
+
+def asymptotics_points(xyz, q, site_q, ionic, pts, kc, eta, kappa, beta, diel,
+                       want_c=True, want_h=True):
+    lib = _load()
+    xyz = _d(np.asarray(xyz).reshape(-1, 3))
+    q, sq = _d(q), _d(site_q)
+    ion = np.ascontiguousarray(ionic, dtype=np.int32)
+    pts = _d(np.asarray(pts).reshape(-1, 3))
+    c = np.empty((len(sq), len(pts))) if want_c else None
+    h = np.empty((int(ion.sum()), len(pts))) if want_h else None
+    rc = lib.oracle_asymptotics_points(len(q), _ptr(xyz), _ptr(q), len(sq), _ptr(sq),
+                                       _ptr(ion, _PI), float(kc), float(eta), float(kappa),
+                                       float(beta), float(diel), len(pts), _ptr(pts),
+                                       _ptr(c), _ptr(h))
+    assert rc == 0
+    return c, h
+
+
+def asymptotics_grid(xyz, q, site_q, ionic, origin, spacing, dims, kc, eta, kappa,
+                     beta, diel, want_c=True, want_h=True):
+    lib = _load()
+    xyz = _d(np.asarray(xyz).reshape(-1, 3))
+    q, sq = _d(q), _d(site_q)
+    ion = np.ascontiguousarray(ionic, dtype=np.int32)
+    o, h_ = _d(origin), _d(spacing)
+    dm = np.ascontiguousarray(dims, dtype=np.int32)
+    shp = (int(dm[2]), int(dm[1]), int(dm[0]))
+    c = np.empty((len(sq),) + shp) if want_c else None
+    h = np.empty((int(ion.sum()),) + shp) if want_h else None
+    rc = lib.oracle_asymptotics_grid(len(q), _ptr(xyz), _ptr(q), len(sq), _ptr(sq),
+                                     _ptr(ion, _PI), float(kc), float(eta), float(kappa),
+                                     float(beta), float(diel), _ptr(o), _ptr(h_),
+                                     _ptr(dm, _PI), _ptr(c), _ptr(h))
+    assert rc == 0
+    return c, h
+
+
+def grid_points(origin, spacing, dims):
+    lib = _load()
+    o, h = _d(origin), _d(spacing)
+    dm = np.ascontiguousarray(dims, dtype=np.int32)
+    m = int(np.prod(dm.astype(np.int64)))
+    out = np.empty((m, 3))
+    lib.oracle_grid_points(_ptr(o), _ptr(h), _ptr(dm, _PI), _ptr(out))
+    return out
+
+
+def backward_points(xyz, q, sigma, eps, site_q, site_sigma, site_eps, pts, w, kc,
+                    rcut_tab=None):
+    """Gradients of L = sum w[S][npts] * u[S][npts] w.r.t. (xyz, q, eps, sigma)."""
+    lib = _load()
+    xyz, q, sigma, eps = _atoms(xyz, q, sigma, eps)
+    sq, ss, se = _d(site_q), _d(site_sigma), _d(site_eps)
+    pts = _d(np.asarray(pts).reshape(-1, 3))
+    w = _d(np.asarray(w).reshape(len(sq), -1))
+    rct = _d(rcut_tab)
+    n = len(q)
+    dxyz = np.empty((n, 3))
+    dq, de, ds = np.empty(n), np.empty(n), np.empty(n)
+    rc = lib.oracle_backward_points(n, _ptr(xyz), _ptr(q), _ptr(sigma), _ptr(eps), len(sq),
+                                    _ptr(sq), _ptr(ss), _ptr(se), float(kc), _ptr(rct),
+                                    len(pts), _ptr(pts), _ptr(w), _ptr(dxyz), _ptr(dq),
+                                    _ptr(de), _ptr(ds))
+    assert rc == 0
+    return dxyz, dq, de, ds
+
+
+def backward_grid(xyz, q, sigma, eps, site_q, site_sigma, site_eps, origin, spacing,
+                  dims, w, kc, rcut_tab=None):
+    pts = grid_points(origin, spacing, dims)
+    return backward_points(xyz, q, sigma, eps, site_q, site_sigma, site_eps, pts,
+                           np.asarray(w).reshape(len(site_q), -1), kc, rcut_tab)

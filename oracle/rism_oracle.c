@@ -1,0 +1,348 @@
+/*
+ * FP64 CPU oracle for the 3D-RISM initialisation quantities.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library links or calls this
+ * file; only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark do.  It shares no code, header, table or constant with the HIP
+ * path.
+ *
+ * Everything here is a plain direct sum over all (atom, point) pairs in
+ * double precision, atoms in input order, using libm erf/erfc/exp/sqrt.
+ * No tree, no splitting, no blocking.
+ *
+ * Paper: Wilson, Krasny & Luchko, "Accelerating the 3D-RISM theory of
+ * molecular solvation with treecode summation and cut-offs".
+ *
+ * Definitions followed (with the readings adopted where the paper is silent):
+ *  - u_gamma(r): Sec. 2.1 (potential = Coulomb + Lennard-Jones between the
+ *    solvent site and every solute atom) and Sec. 2.6 (LJ A/r^12 - B/r^6,
+ *    truncated form Eq. 28).  Reading: Coulomb carries the constant k_C
+ *    (units A, e, kcal/mol); A = 4 eps sigma^12, B = 4 eps sigma^6 with
+ *    Lorentz-Berthelot mixing sigma_ga = (sigma_g + sigma_a)/2,
+ *    eps_ga = sqrt(eps_g eps_a).  Cut-off: the pair is kept iff d < r_cut.
+ *    A grid point that coincides with an atom (d == 0) gets u = +inf.
+ *  - c^lr_gamma(r): Sec. 2.2, Eq. 4, times k_C; d == 0 takes the limit
+ *    erf(d/eta)/d -> 2/(eta sqrt(pi)).
+ *  - h^lr_j(r): Sec. 2.2, Eq. 6, times k_C, for ionic sites only; d == 0
+ *    takes the limit of the bracket / d:
+ *      4 exp(-kappa^2 eta^2/4)/(eta sqrt(pi)) - 2 kappa erfc(kappa eta/2).
+ *  - LJ cut-off from a tolerance: Sec. 2.6 (|u_LJ(r_cut)| = tol, beyond the
+ *    minimum), solved here by plain bisection.
+ *  - Tail constant: Sec. 2.6 (final result for the chemical-potential
+ *    correction): T_gamma = 4 pi sum_a int_{r_cut}^inf u_LJ(r) r^2 dr
+ *                        = (4 pi / 3) sum_a (A/(3 r_c^9) - B/r_c^3).
+ *  - Backward: gradient of L = sum_gamma sum_r w_gamma(r) u_gamma(r) with
+ *    respect to atom positions, charges, eps_a and sigma_a, differentiating
+ *    the definition of u above term by term (the jump at r_cut is ignored).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_PI 3.14159265358979323846
+
+/* ---------------------------------------------------------------- mixing */
+
+static void lb_mix(double sig_g, double eps_g, double sig_a, double eps_a,
+                   double *sig_ga, double *eps_ga)
+{
+    *sig_ga = 0.5 * (sig_g + sig_a);
+    *eps_ga = sqrt(eps_g * eps_a);
+}
+
+static double lj_pair(double sig, double eps, double d)
+{
+    double s = sig / d;
+    double s6 = s * s * s * s * s * s;
+    return 4.0 * eps * (s6 * s6 - s6);
+}
+
+/* ---------------------------------------------------------------- points */
+
+static void point_of(const double origin[3], const double spacing[3],
+                     const int32_t dims[3], int64_t idx, double p[3])
+{
+    int64_t nx = dims[0], ny = dims[1];
+    int64_t i = idx % nx, j = (idx / nx) % ny, k = idx / (nx * ny);
+    p[0] = origin[0] + (double)i * spacing[0];
+    p[1] = origin[1] + (double)j * spacing[1];
+    p[2] = origin[2] + (double)k * spacing[2];
+}
+
+/*
+ * u at one point for every site.  terms: bit 0 Coulomb, bit 1 LJ.
+ * rcut: [ns][n] per-pair cut-off radii, or NULL for no cut-off.
+ */
+static void potential_at(int64_t n, const double *xyz, const double *q,
+                         const double *sig, const double *eps,
+                         int32_t ns, const double *sq, const double *ssig,
+                         const double *seps, double kc, const double *rcut,
+                         int terms, const double p[3], double *out, int64_t stride)
+{
+    for (int32_t g = 0; g < ns; ++g) {
+        double coul = 0.0, lj = 0.0;
+        int hit = 0;
+        for (int64_t a = 0; a < n; ++a) {
+            double dx = p[0] - xyz[3 * a + 0];
+            double dy = p[1] - xyz[3 * a + 1];
+            double dz = p[2] - xyz[3 * a + 2];
+            double d = sqrt(dx * dx + dy * dy + dz * dz);
+            if (d == 0.0) { hit = 1; continue; }
+            if (terms & 1) coul += kc * q[a] * sq[g] / d;
+            if (terms & 2) {
+                double s_ga, e_ga;
+                lb_mix(ssig[g], seps[g], sig[a], eps[a], &s_ga, &e_ga);
+                if (rcut == NULL || d < rcut[(int64_t)g * n + a])
+                    lj += lj_pair(s_ga, e_ga, d);
+            }
+        }
+        out[(int64_t)g * stride] = hit ? INFINITY : coul + lj;
+    }
+}
+
+int oracle_potential_points(int64_t n, const double *xyz, const double *q,
+                            const double *sig, const double *eps, int32_t ns,
+                            const double *sq, const double *ssig, const double *seps,
+                            double kc, const double *rcut, int terms,
+                            int64_t npts, const double *pts, double *u)
+{
+    if (n < 0 || ns <= 0 || npts < 0) return -1;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < npts; ++i)
+        potential_at(n, xyz, q, sig, eps, ns, sq, ssig, seps, kc, rcut, terms,
+                     pts + 3 * i, u + i, npts);
+    return 0;
+}
+
+int oracle_potential_grid(int64_t n, const double *xyz, const double *q,
+                          const double *sig, const double *eps, int32_t ns,
+                          const double *sq, const double *ssig, const double *seps,
+                          double kc, const double *rcut, int terms,
+                          const double *origin, const double *spacing,
+                          const int32_t *dims, double *u)
+{
+    if (n < 0 || ns <= 0 || dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0) return -1;
+    int64_t m = (int64_t)dims[0] * dims[1] * dims[2];
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < m; ++i) {
+        double p[3];
+        point_of(origin, spacing, dims, i, p);
+        potential_at(n, xyz, q, sig, eps, ns, sq, ssig, seps, kc, rcut, terms,
+                     p, u + i, m);
+    }
+    return 0;
+}
+
+/* ----------------------------------------------------------- asymptotics */
+
+/* erf(d/eta)/d, with its d -> 0 limit. */
+static double dcf_kernel(double d, double eta)
+{
+    if (d == 0.0) return 2.0 / (eta * sqrt(ORACLE_PI));
+    return erf(d / eta) / d;
+}
+
+/* The bracket of Eq. 6 divided by d, with its d -> 0 limit. */
+static double tcf_kernel(double d, double eta, double kappa)
+{
+    double a = 0.5 * kappa * eta;
+    if (d == 0.0)
+        return 4.0 * exp(-a * a) / (eta * sqrt(ORACLE_PI)) - 2.0 * kappa * erfc(a);
+    double x = d / eta;
+    return (exp(-kappa * d) * erfc(a - x) - exp(kappa * d) * erfc(a + x)) / d;
+}
+
+static void asymptotics_at(int64_t n, const double *xyz, const double *q,
+                           int32_t ns, const double *sq, const int32_t *ionic,
+                           double kc, double eta, double kappa, double beta,
+                           double diel, const double p[3],
+                           double *c, double *h, int64_t stride)
+{
+    double sum_c = 0.0, sum_h = 0.0;
+    for (int64_t a = 0; a < n; ++a) {
+        double dx = p[0] - xyz[3 * a + 0];
+        double dy = p[1] - xyz[3 * a + 1];
+        double dz = p[2] - xyz[3 * a + 2];
+        double d = sqrt(dx * dx + dy * dy + dz * dz);
+        if (c) sum_c += q[a] * dcf_kernel(d, eta);
+        if (h) sum_h += q[a] * tcf_kernel(d, eta, kappa);
+    }
+    int32_t j = 0;
+    for (int32_t g = 0; g < ns; ++g) {
+        if (c) c[(int64_t)g * stride] = -beta * kc * sq[g] * sum_c;
+        if (ionic[g]) {
+            if (h)
+                h[(int64_t)j * stride] = -beta * kc * sq[g] / (2.0 * diel)
+                                         * exp(kappa * kappa * eta * eta / 4.0) * sum_h;
+            ++j;
+        }
+    }
+}
+
+int oracle_asymptotics_points(int64_t n, const double *xyz, const double *q,
+                              int32_t ns, const double *sq, const int32_t *ionic,
+                              double kc, double eta, double kappa, double beta,
+                              double diel, int64_t npts, const double *pts,
+                              double *c, double *h)
+{
+    if (n < 0 || ns <= 0 || npts < 0 || !(eta > 0.0) || kappa < 0.0 || !(diel > 0.0))
+        return -1;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < npts; ++i)
+        asymptotics_at(n, xyz, q, ns, sq, ionic, kc, eta, kappa, beta, diel,
+                       pts + 3 * i, c ? c + i : NULL, h ? h + i : NULL, npts);
+    return 0;
+}
+
+int oracle_asymptotics_grid(int64_t n, const double *xyz, const double *q,
+                            int32_t ns, const double *sq, const int32_t *ionic,
+                            double kc, double eta, double kappa, double beta,
+                            double diel, const double *origin, const double *spacing,
+                            const int32_t *dims, double *c, double *h)
+{
+    if (n < 0 || ns <= 0 || dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0 ||
+        !(eta > 0.0) || kappa < 0.0 || !(diel > 0.0))
+        return -1;
+    int64_t m = (int64_t)dims[0] * dims[1] * dims[2];
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < m; ++i) {
+        double p[3];
+        point_of(origin, spacing, dims, i, p);
+        asymptotics_at(n, xyz, q, ns, sq, ionic, kc, eta, kappa, beta, diel,
+                       p, c ? c + i : NULL, h ? h + i : NULL, m);
+    }
+    return 0;
+}
+
+/* -------------------------------------------------------- LJ cut-off, tail */
+
+/* Outermost r > r_min with |u_LJ(r)| = tol, by bisection (Sec. 2.6).
+ * Returns -1 if tol >= eps (no root beyond the minimum). */
+double oracle_lj_rcut_from_tol(double sig, double eps, double tol)
+{
+    if (!(tol > 0.0) || !(eps > 0.0) || !(sig > 0.0) || tol >= eps) return -1.0;
+    double lo = pow(2.0, 1.0 / 6.0) * sig;  /* minimum, |u| = eps > tol */
+    double hi = lo;
+    while (fabs(lj_pair(sig, eps, hi)) > tol) hi *= 2.0;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (fabs(lj_pair(sig, eps, mid)) > tol) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* Per-pair cut-off table [ns][n]: global radius if tol <= 0, else from tol. */
+int oracle_lj_rcut_table(int64_t n, const double *sig, const double *eps,
+                         int32_t ns, const double *ssig, const double *seps,
+                         double rcut, double tol, double *out)
+{
+    for (int32_t g = 0; g < ns; ++g)
+        for (int64_t a = 0; a < n; ++a) {
+            double s_ga, e_ga;
+            lb_mix(ssig[g], seps[g], sig[a], eps[a], &s_ga, &e_ga);
+            double r = tol > 0.0 ? oracle_lj_rcut_from_tol(s_ga, e_ga, tol) : rcut;
+            if (!(r > 0.0)) return -1;
+            out[(int64_t)g * n + a] = r;
+        }
+    return 0;
+}
+
+/* T_gamma = (4 pi / 3) sum_a (A/(3 r_c^9) - B/r_c^3)  (Sec. 2.6). */
+int oracle_lj_tail(int64_t n, const double *sig, const double *eps, int32_t ns,
+                   const double *ssig, const double *seps, const double *rcut,
+                   double *tail)
+{
+    for (int32_t g = 0; g < ns; ++g) {
+        double t = 0.0;
+        for (int64_t a = 0; a < n; ++a) {
+            double s_ga, e_ga;
+            lb_mix(ssig[g], seps[g], sig[a], eps[a], &s_ga, &e_ga);
+            double s3 = s_ga * s_ga * s_ga;
+            double A = 4.0 * e_ga * s3 * s3 * s3 * s3;
+            double B = 4.0 * e_ga * s3 * s3;
+            double rc = rcut[(int64_t)g * n + a];
+            double rc3 = rc * rc * rc;
+            t += A / (3.0 * rc3 * rc3 * rc3) - B / rc3;
+        }
+        tail[g] = 4.0 * ORACLE_PI / 3.0 * t;
+    }
+    return 0;
+}
+
+/* -------------------------------------------------------------- backward */
+
+/*
+ * L = sum_g sum_r w[g][r] u_g(r).  For atom a (d = |r - R_a|, s = sigma_ga/d):
+ *   dL/dQ_a     = k_C sum_g q_g sum_r w / d
+ *   dL/dR_a     = sum_g sum_r w [k_C Q_a q_g (r - R_a)/d^3
+ *                               + [d<rc] (4 eps_ga/d^2)(12 s^12 - 6 s^6)(r - R_a)]
+ *   dL/deps_a   = sum_g sum_r w [d<rc] u_LJ,ga / (2 eps_a)
+ *   dL/dsigma_a = sum_g sum_r w [d<rc] (2 eps_ga/sigma_ga)(12 s^12 - 6 s^6)
+ * Points with d == 0 are skipped.  Any output pointer may be NULL.
+ */
+int oracle_backward_points(int64_t n, const double *xyz, const double *q,
+                           const double *sig, const double *eps, int32_t ns,
+                           const double *sq, const double *ssig, const double *seps,
+                           double kc, const double *rcut, int64_t npts,
+                           const double *pts, const double *w,
+                           double *dxyz, double *dq, double *deps, double *dsig)
+{
+    if (n < 0 || ns <= 0 || npts < 0) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t a = 0; a < n; ++a) {
+        double gx = 0, gy = 0, gz = 0, gq = 0, ge = 0, gs = 0;
+        for (int32_t g = 0; g < ns; ++g) {
+            double s_ga, e_ga;
+            lb_mix(ssig[g], seps[g], sig[a], eps[a], &s_ga, &e_ga);
+            double rc = rcut ? rcut[(int64_t)g * n + a] : INFINITY;
+            for (int64_t i = 0; i < npts; ++i) {
+                double wv = w[(int64_t)g * npts + i];
+                double rx = pts[3 * i + 0] - xyz[3 * a + 0];
+                double ry = pts[3 * i + 1] - xyz[3 * a + 1];
+                double rz = pts[3 * i + 2] - xyz[3 * a + 2];
+                double d2 = rx * rx + ry * ry + rz * rz;
+                if (d2 == 0.0) continue;
+                double d = sqrt(d2);
+                double f = kc * q[a] * sq[g] / (d2 * d);
+                gq += wv * kc * sq[g] / d;
+                if (d < rc) {
+                    double s = s_ga / d;
+                    double s6 = s * s * s * s * s * s;
+                    double s12 = s6 * s6;
+                    f += 4.0 * e_ga / d2 * (12.0 * s12 - 6.0 * s6);
+                    if (eps[a] > 0.0) ge += wv * 4.0 * e_ga * (s12 - s6) / (2.0 * eps[a]);
+                    gs += wv * (2.0 * e_ga / s_ga) * (12.0 * s12 - 6.0 * s6);
+                }
+                gx += wv * f * rx;
+                gy += wv * f * ry;
+                gz += wv * f * rz;
+            }
+        }
+        if (dxyz) { dxyz[3 * a] = gx; dxyz[3 * a + 1] = gy; dxyz[3 * a + 2] = gz; }
+        if (dq) dq[a] = gq;
+        if (deps) deps[a] = ge;
+        if (dsig) dsig[a] = gs;
+    }
+    return 0;
+}
+
+int oracle_grid_points(const double *origin, const double *spacing,
+                       const int32_t *dims, double *pts)
+{
+    int64_t m = (int64_t)dims[0] * dims[1] * dims[2];
+    for (int64_t i = 0; i < m; ++i) point_of(origin, spacing, dims, i, pts + 3 * i);
+    return 0;
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

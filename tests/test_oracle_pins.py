@@ -1,0 +1,407 @@
+"""Pins of the FP64 oracle against facts fixed outside the oracle itself:
+closed forms of the kernels, the Poisson / screened-Poisson equations the
+smeared kernels solve, the paper's reciprocal-space forms (Sec. 2.2, Eqs. 5
+and 7), quadrature of the LJ tail (Sec. 2.6), multipole far fields,
+invariances, Euler homogeneity, finite differences, and 40-digit brute force
+on tiny inputs.  A plausible slip in the oracle (a dropped term, a wrong sign,
+power or index, a transposed axis) fails at least one of these."""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+from scipy import integrate
+
+from paper_2109_09772_amd import workloads as W
+
+KC = W.COULOMB_K
+BETA = W.beta()
+ETA = 1.0
+KAPPA = W.debye_kappa()
+DIEL = W.DIELECTRIC
+
+
+def _one_atom(q=1.0, sigma=3.0, eps=0.1, pos=(0.0, 0.0, 0.0)):
+    return (np.array([pos], float), np.array([q]), np.array([sigma]), np.array([eps]))
+
+
+def _radial_pts(r, direction=(0.3, -0.5, 0.8)):
+    u = np.asarray(direction, float)
+    u /= np.linalg.norm(u)
+    return np.outer(np.atleast_1d(r), u)
+
+
+# --------------------------------------------------------------------------- u
+
+def test_lj_zero_and_minimum_lb_mixing(oracle):
+    """Single atom, LJ only: zero at sigma_ga, minimum -eps_ga at 2^(1/6) sigma_ga,
+    with sigma_ga, eps_ga the Lorentz-Berthelot combination of site and atom."""
+    from scipy.optimize import minimize_scalar
+    sites = W.make_sites(W.SITES_SALT)
+    xyz, q, s, e = _one_atom(sigma=2.2, eps=0.07)
+    for g in range(sites.n):
+        sg = 0.5 * (sites.sigma[g] + 2.2)
+        eg = math.sqrt(sites.eps[g] * 0.07)
+        f = lambda r: oracle.potential_points(xyz, q, s, e, sites.q[g:g+1], sites.sigma[g:g+1],
+                                              sites.eps[g:g+1], _radial_pts([r]), KC, terms=2)[0, 0]
+        assert abs(f(sg)) < 1e-12 * eg
+        res = minimize_scalar(f, bracket=(0.9 * sg, 1.1 * sg, 2.0 * sg), tol=1e-12)
+        assert res.x == pytest.approx(2 ** (1 / 6) * sg, rel=1e-6)
+        assert res.fun == pytest.approx(-eg, rel=1e-10)
+
+
+def test_coulomb_multipole_far_field(oracle):
+    """Far from a neutral dipole the Coulomb sum tends to k_C q p.r/R^3, and
+    from a charged cluster to k_C q Q_tot/R (textbook multipole expansion)."""
+    d = np.array([[0.0, 0.0, 0.6], [0.0, 0.0, -0.6]])
+    qq = np.array([0.5, -0.5])
+    z = np.zeros(2)
+    R = 400.0
+    pts = np.array([[0, 0, R], [R, 0, 0], [0, R / math.sqrt(2), R / math.sqrt(2)]])
+    u = oracle.potential_points(d, qq, z + 1, z + 0.1, [1.0], [1.0], [0.1], pts, KC, terms=1)[0]
+    p = 0.5 * 1.2
+    expect = KC * p * pts[:, 2] / R ** 3
+    assert u[0] == pytest.approx(expect[0], rel=1e-5)
+    assert abs(u[1]) < 1e-12
+    assert u[2] == pytest.approx(expect[2], rel=1e-5)
+    # net charge
+    qq2 = np.array([0.7, 0.2])
+    u2 = oracle.potential_points(d, qq2, z + 1, z + 0.1, [-0.834], [1.0], [0.1], pts, KC, terms=1)[0]
+    assert u2[1] == pytest.approx(KC * 0.9 * -0.834 / R, rel=1e-5)
+
+
+def test_coulomb_harmonic_away_from_charges(oracle):
+    """The Coulomb sum is harmonic off the atoms: a 4th-order discrete Laplacian
+    is small compared with the individual second derivatives."""
+    wl = W.tiny(n_atoms=6, dims=(4, 4, 4), seed=5)
+    xyz = wl.solute.xyz
+    h = 1e-2
+    c = np.array([7.0, -5.0, 6.0])
+    offs = []
+    for a in range(3):
+        for k in (-2, -1, 1, 2):
+            v = np.zeros(3)
+            v[a] = k * h
+            offs.append(v)
+    pts = np.vstack([c, c + np.array(offs)])
+    u = oracle.potential_points(xyz, wl.solute.q, wl.solute.sigma, wl.solute.eps,
+                                [1.0], [1.0], [0.1], pts, 1.0, terms=1)[0]
+    lap, scale = 0.0, 0.0
+    for a in range(3):
+        m2, m1, p1, p2 = u[1 + 4 * a: 5 + 4 * a]
+        d2 = (-m2 + 16 * m1 - 30 * u[0] + 16 * p1 - p2) / (12 * h * h)
+        lap += d2
+        scale += abs(d2)
+    assert abs(lap) < 1e-6 * scale
+
+
+def test_grid_layout_and_points_agree(oracle):
+    """The grid entry point stores [site][z][y][x] with point (i,j,k) at
+    origin + (i,j,k)*spacing: rebuild the points with numpy and compare."""
+    wl = W.tiny(n_atoms=5, dims=(4, 5, 6))
+    s, sol, g = wl.sites, wl.solute, wl.grid
+    rc = oracle.rcut_table(sol.sigma, sol.eps, s.sigma, s.eps, rcut=2.5)
+    ug = oracle.potential_grid(sol.xyz, sol.q, sol.sigma, sol.eps, s.q, s.sigma, s.eps,
+                               g.origin, g.spacing, g.dims, KC, rc)
+    assert ug.shape == (s.n, 6, 5, 4)
+    zz, yy, xx = np.meshgrid(g.axis(2), g.axis(1), g.axis(0), indexing="ij")
+    pts = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
+    up = oracle.potential_points(sol.xyz, sol.q, sol.sigma, sol.eps, s.q, s.sigma, s.eps,
+                                 pts, KC, rc)
+    np.testing.assert_array_equal(ug.reshape(s.n, -1), up)
+
+
+def test_invariances(oracle):
+    """Atom permutation leaves u unchanged; a rigid shift of atoms and grid
+    origin together leaves u unchanged; u is linear in the atom charges."""
+    wl = W.tiny(n_atoms=7, dims=(5, 4, 3), seed=3)
+    s, sol, g = wl.sites, wl.solute, wl.grid
+    args = (s.q, s.sigma, s.eps)
+    base = oracle.potential_grid(sol.xyz, sol.q, sol.sigma, sol.eps, *args, g.origin,
+                                 g.spacing, g.dims, KC)
+    perm = np.random.default_rng(0).permutation(sol.n)
+    up = oracle.potential_grid(sol.xyz[perm], sol.q[perm], sol.sigma[perm], sol.eps[perm],
+                               *args, g.origin, g.spacing, g.dims, KC)
+    np.testing.assert_allclose(up, base, rtol=1e-13)
+    t = np.array([3.25, -1.5, 0.75])
+    ut = oracle.potential_grid(sol.xyz + t, sol.q, sol.sigma, sol.eps, *args, g.origin + t,
+                               g.spacing, g.dims, KC)
+    np.testing.assert_allclose(ut, base, rtol=1e-12)
+    q2 = np.random.default_rng(1).uniform(-1, 1, sol.n)
+    c1 = oracle.potential_grid(sol.xyz, sol.q, sol.sigma, sol.eps, *args, g.origin, g.spacing,
+                               g.dims, KC, terms=1)
+    c2 = oracle.potential_grid(sol.xyz, q2, sol.sigma, sol.eps, *args, g.origin, g.spacing,
+                               g.dims, KC, terms=1)
+    c12 = oracle.potential_grid(sol.xyz, sol.q + q2, sol.sigma, sol.eps, *args, g.origin,
+                                g.spacing, g.dims, KC, terms=1)
+    np.testing.assert_allclose(c12, c1 + c2, rtol=1e-12, atol=1e-12 * abs(c12).max())
+
+
+def test_point_on_atom_is_infinite(oracle):
+    xyz, q, s, e = _one_atom(q=-0.5)
+    u = oracle.potential_points(xyz, q, s, e, [0.417], [0.4], [0.046],
+                                np.array([[0.0, 0, 0], [1.0, 0, 0]]), KC)
+    assert u[0, 0] == np.inf and np.isfinite(u[0, 1])
+
+
+# ----------------------------------------------------------- LJ cut-off, tail
+
+def test_rcut_from_tolerance(oracle):
+    """|u_LJ(r_cut)| = tol beyond the minimum (Sec. 2.6)."""
+    for sg, eg, tol in [(3.0, 0.1, 1e-4), (1.8, 0.03, 1e-6), (4.2, 0.2, 1e-3)]:
+        rc = oracle.lj_rcut_from_tol(sg, eg, tol)
+        assert rc > 2 ** (1 / 6) * sg
+        xyz, q, s, e = _one_atom(q=0.0, sigma=2 * sg - 1.0, eps=eg * eg / 1.0)
+        u = oracle.potential_points(xyz, q, s, e, [0.0], [1.0], [1.0], _radial_pts([rc]),
+                                    KC, terms=2)[0, 0]
+        assert abs(u) == pytest.approx(tol, rel=1e-9)
+    assert oracle.lj_rcut_from_tol(3.0, 0.1, 0.2) < 0
+
+
+def test_cutoff_truncates_lj_only(oracle):
+    """With a cut-off the LJ term is dropped beyond r_cut, Coulomb is kept."""
+    xyz, q, s, e = _one_atom(q=0.3, sigma=3.0, eps=0.1)
+    rc = oracle.rcut_table(s, e, [3.15], [0.152], rcut=9.0)
+    pts = _radial_pts([8.999, 9.001])
+    full = oracle.potential_points(xyz, q, s, e, [-0.834], [3.15], [0.152], pts, KC)
+    cut = oracle.potential_points(xyz, q, s, e, [-0.834], [3.15], [0.152], pts, KC, rc)
+    coul = oracle.potential_points(xyz, q, s, e, [-0.834], [3.15], [0.152], pts, KC, terms=1)
+    assert cut[0, 0] == full[0, 0]
+    assert cut[0, 1] == coul[0, 1]
+    assert full[0, 1] != coul[0, 1]
+
+
+def test_tail_constant_matches_quadrature(oracle):
+    """T_gamma = 4 pi sum_a int_rc^inf u_LJ(r) r^2 dr: integrate the oracle's own
+    single-atom LJ values numerically and compare with the closed form."""
+    sol = W.ball_solute(4, 3.0, seed=9)
+    sites = W.make_sites(W.SITES_SALT)
+    rc = oracle.rcut_table(sol.sigma, sol.eps, sites.sigma, sites.eps, tol=1e-4)
+    tail = oracle.lj_tail(sol.sigma, sol.eps, sites.sigma, sites.eps, rc)
+    for g in range(sites.n):
+        tot = 0.0
+        for a in range(sol.n):
+            def f(r):
+                return oracle.potential_points(
+                    np.zeros((1, 3)), [0.0], sol.sigma[a:a+1], sol.eps[a:a+1], [0.0],
+                    sites.sigma[g:g+1], sites.eps[g:g+1], _radial_pts([r]), KC, terms=2)[0, 0] * r * r
+            v, _ = integrate.quad(f, rc[g, a], np.inf, epsabs=0, epsrel=1e-12, limit=200)
+            tot += 4 * math.pi * v
+        assert tail[g] == pytest.approx(tot, rel=1e-8)
+        assert tail[g] < 0
+
+
+# -------------------------------------------------------------- asymptotics
+
+def _c1(oracle, r, eta=ETA):
+    """erf-smeared unit-charge kernel f(r) = erf(r/eta)/r read back from c^lr."""
+    c, _ = oracle.asymptotics_points(np.zeros((1, 3)), [1.0], [1.0], [0], _radial_pts(r), 1.0,
+                                     eta, KAPPA, 1.0, DIEL, want_h=False)
+    return -c[0]
+
+
+def _h1(oracle, r, kappa=KAPPA, eta=ETA):
+    """g(r) = (exp(kappa^2 eta^2/4)/2) * bracket/d read back from h^lr."""
+    _, h = oracle.asymptotics_points(np.zeros((1, 3)), [1.0], [1.0], [1], _radial_pts(r), 1.0,
+                                     eta, kappa, 1.0, DIEL, want_c=False)
+    return -h[0] * DIEL
+
+
+def _radial_laplacian(f, r, dr=2e-3):
+    rr = np.array([r - 2 * dr, r - dr, r, r + dr, r + 2 * dr])
+    v = f(rr)
+    d1 = (v[0] - 8 * v[1] + 8 * v[3] - v[4]) / (12 * dr)
+    d2 = (-v[0] + 16 * v[1] - 30 * v[2] + 16 * v[3] - v[4]) / (12 * dr * dr)
+    return d2 + 2 * d1 / r
+
+
+def _gauss(r, eta=ETA):
+    return math.exp(-r * r / (eta * eta)) / (math.pi ** 1.5 * eta ** 3)
+
+
+@pytest.mark.parametrize("eta", [1.0, 0.7])
+def test_dcf_kernel_solves_poisson_with_gaussian_charge(oracle, eta):
+    """-lap f = 4 pi rho_G with rho_G the normalised Gaussian exp(-r^2/eta^2)
+    (the smeared charge behind Eq. 4); catches any slip in the erf argument."""
+    for r in [0.3, 0.8, 1.5, 2.5]:
+        lap = _radial_laplacian(lambda x: _c1(oracle, x, eta), r)
+        assert -lap == pytest.approx(4 * math.pi * _gauss(r, eta), rel=2e-6, abs=1e-9)
+
+
+@pytest.mark.parametrize("kappa", [KAPPA, 0.5])
+def test_tcf_kernel_solves_screened_poisson(oracle, kappa):
+    """(-lap + kappa^2) g = 4 pi rho_G: g is the Yukawa potential of the same
+    Gaussian charge, which pins both the bracket of Eq. 6 and its prefactor."""
+    for r in [0.3, 0.9, 1.7, 3.0]:
+        f = lambda x: _h1(oracle, x, kappa)
+        lhs = -_radial_laplacian(f, r) + kappa ** 2 * f(np.array([r]))[0]
+        assert lhs == pytest.approx(4 * math.pi * _gauss(r), rel=2e-6, abs=1e-9)
+
+
+def _radial_ft(f, k, rmax):
+    g = lambda r: 4 * math.pi * r * r * f(r) * math.sin(k * r) / (k * r)
+    v, _ = integrate.quad(g, 0, rmax, limit=400, epsabs=1e-13, epsrel=1e-11)
+    return v
+
+
+def test_dcf_real_space_matches_reciprocal_form(oracle):
+    """The Fourier transform of Eq. 4 must be Eq. 5: for the unit charge,
+    FT[erf(r/eta)/r] = 4 pi exp(-k^2 eta^2/4)/k^2.  Tested on the convergent
+    part 1/r - f(r) = erfc(r/eta)/r."""
+    f = lambda r: 1.0 / r - _c1(oracle, np.array([r]))[0]
+    for k in [0.3, 1.0, 2.2]:
+        ft = _radial_ft(f, k, 12.0)
+        expect = 4 * math.pi / k ** 2 * (1 - math.exp(-k * k * ETA * ETA / 4))
+        assert ft == pytest.approx(expect, rel=1e-7)
+
+
+def test_tcf_real_space_matches_reciprocal_form(oracle):
+    """The Fourier transform of Eq. 6 must be Eq. 7.  For a unit solute charge
+    and unit site charge with beta = k_C = 1, the oracle's h is
+    -(1/(2 eps)) e^{kappa^2 eta^2/4} sum Q bracket/d, whose transform must be
+    -4 pi exp(-k^2 eta^2/4) / (eps (k^2 + kappa^2))."""
+    kappa = 0.4
+
+    def h(r):
+        _, hh = oracle.asymptotics_points(np.zeros((1, 3)), [1.0], [1.0], [1], _radial_pts([r]),
+                                          1.0, ETA, kappa, 1.0, DIEL, want_c=False)
+        return hh[0, 0]
+
+    for k in [0.2, 0.8, 1.9]:
+        ft = _radial_ft(h, k, 120.0)
+        expect = -4 * math.pi * math.exp(-k * k * ETA * ETA / 4) / (DIEL * (k * k + kappa ** 2))
+        assert ft == pytest.approx(expect, rel=1e-6)
+
+
+def test_asymptotics_limits_and_identities(oracle):
+    wl = W.tiny(n_atoms=6, dims=(4, 5, 3), seed=4)
+    s, sol, g = wl.sites, wl.solute, wl.grid
+    # kappa -> 0: the bracket becomes 2 erf(d/eta), so h_j = c_j / eps
+    c, h = oracle.asymptotics_grid(sol.xyz, sol.q, s.q, s.ionic, g.origin, g.spacing, g.dims,
+                                   KC, ETA, 0.0, BETA, DIEL)
+    ion = np.nonzero(s.ionic)[0]
+    np.testing.assert_allclose(h, c[ion] / DIEL, rtol=1e-12, atol=1e-14 * abs(c).max())
+    # far field: c -> Coulomb, h -> 2 exp(-kappa d)/d times the prefactor
+    pts = _radial_pts([9.0, 15.0])
+    c1 = -_c1(oracle, np.array([9.0, 15.0]))
+    np.testing.assert_allclose(-c1, 1 / np.array([9.0, 15.0]), rtol=1e-15)
+    g1 = _h1(oracle, np.array([9.0, 15.0]))
+    r = np.array([9.0, 15.0])
+    np.testing.assert_allclose(g1, math.exp(KAPPA ** 2 / 4) * np.exp(-KAPPA * r) / r, rtol=1e-14)
+    # d -> 0 continuity of both limits
+    for fn in (_c1, _h1):
+        v0 = fn(oracle, np.array([0.0]))[0]
+        v1 = fn(oracle, np.array([1e-5]))[0]
+        assert v1 == pytest.approx(v0, rel=1e-8)
+
+
+# --------------------------------------------------------------- brute force
+
+def _mp_potential(xyz, q, sig, eps, sq, ssig, seps, p, kc, rcut=None):
+    out = []
+    for g in range(len(sq)):
+        tot = mp.mpf(0)
+        for a in range(len(q)):
+            d = mp.sqrt(sum((mp.mpf(p[i]) - mp.mpf(xyz[a][i])) ** 2 for i in range(3)))
+            tot += mp.mpf(kc) * mp.mpf(q[a]) * mp.mpf(sq[g]) / d
+            sga = (mp.mpf(ssig[g]) + mp.mpf(sig[a])) / 2
+            ega = mp.sqrt(mp.mpf(seps[g]) * mp.mpf(eps[a]))
+            if rcut is None or d < rcut[g][a]:
+                tot += 4 * ega * ((sga / d) ** 12 - (sga / d) ** 6)
+        out.append(tot)
+    return out
+
+
+def test_bruteforce_40_digits(oracle):
+    mp.mp.dps = 40
+    wl = W.tiny(n_atoms=4, dims=(2, 2, 2), seed=21)
+    s, sol, g = wl.sites, wl.solute, wl.grid
+    rc = oracle.rcut_table(sol.sigma, sol.eps, s.sigma, s.eps, rcut=2.0)
+    u = oracle.potential_grid(sol.xyz, sol.q, sol.sigma, sol.eps, s.q, s.sigma, s.eps,
+                              g.origin, g.spacing, g.dims, KC, rc)
+    c, h = oracle.asymptotics_grid(sol.xyz, sol.q, s.q, s.ionic, g.origin, g.spacing, g.dims,
+                                   KC, ETA, KAPPA, BETA, DIEL)
+    pts = oracle.grid_points(g.origin, g.spacing, g.dims)
+    for i, p in enumerate(pts):
+        ref = _mp_potential(sol.xyz, sol.q, sol.sigma, sol.eps, s.q, s.sigma, s.eps, p, KC, rc)
+        for gg in range(s.n):
+            assert float(ref[gg]) == pytest.approx(u.reshape(s.n, -1)[gg, i], rel=1e-13)
+        sc, sh = mp.mpf(0), mp.mpf(0)
+        kap, eta = mp.mpf(KAPPA), mp.mpf(ETA)
+        for a in range(sol.n):
+            d = mp.sqrt(sum((mp.mpf(p[k]) - mp.mpf(sol.xyz[a][k])) ** 2 for k in range(3)))
+            sc += mp.mpf(sol.q[a]) * mp.erf(d / eta) / d
+            sh += mp.mpf(sol.q[a]) * (mp.exp(-kap * d) * mp.erfc(kap * eta / 2 - d / eta)
+                                      - mp.exp(kap * d) * mp.erfc(kap * eta / 2 + d / eta)) / d
+        j = 0
+        for gg in range(s.n):
+            cref = -mp.mpf(BETA) * KC * mp.mpf(s.q[gg]) * sc
+            assert float(cref) == pytest.approx(c.reshape(s.n, -1)[gg, i], rel=1e-13)
+            if s.ionic[gg]:
+                href = (-mp.mpf(BETA) * KC * mp.mpf(s.q[gg]) / (2 * mp.mpf(DIEL))
+                        * mp.exp(kap * kap * eta * eta / 4) * sh)
+                assert float(href) == pytest.approx(h.reshape(-1, len(pts))[j, i], rel=1e-12)
+                j += 1
+
+
+# ----------------------------------------------------------------- backward
+
+def _per_atom_L(oracle, wl, w, a, xyz=None, q=None, sig=None, eps=None, pts=None, terms=3):
+    """sum_g sum_r w u_ga over the contribution of atom a alone."""
+    sol, s = wl.solute, wl.sites
+    xyz = sol.xyz[a:a+1] if xyz is None else xyz
+    q = sol.q[a:a+1] if q is None else q
+    sig = sol.sigma[a:a+1] if sig is None else sig
+    eps = sol.eps[a:a+1] if eps is None else eps
+    u = oracle.potential_points(xyz, q, sig, eps, s.q, s.sigma, s.eps, pts, KC, terms=terms)
+    return float((u * w).sum())
+
+
+def test_backward_matches_finite_differences(oracle):
+    """Central differences with Richardson extrapolation on each atom's own
+    contribution (no cut-off), against the oracle's analytic gradient."""
+    wl = W.tiny(n_atoms=4, dims=(5, 4, 6), seed=8, spacing=0.9)
+    sol, s, g = wl.solute, wl.sites, wl.grid
+    pts = oracle.grid_points(g.origin, g.spacing, g.dims)
+    w = np.random.default_rng(2).uniform(0, 1, (s.n, len(pts)))
+    dx, dq, de, ds = oracle.backward_points(sol.xyz, sol.q, sol.sigma, sol.eps, s.q, s.sigma,
+                                            s.eps, pts, w, KC)
+    for a in range(sol.n):
+        for k in range(3):
+            def L(hh):
+                x = sol.xyz[a:a+1].copy()
+                x[0, k] += hh
+                return _per_atom_L(oracle, wl, w, a, xyz=x, pts=pts)
+            h = 1e-4
+            d1 = (L(h) - L(-h)) / (2 * h)
+            d2 = (L(h / 2) - L(-h / 2)) / h
+            fd = (4 * d2 - d1) / 3
+            assert dx[a, k] == pytest.approx(fd, rel=1e-6, abs=1e-8 * abs(dx).max())
+        # L is linear in Q (only the Coulomb term depends on it)
+        fq = (_per_atom_L(oracle, wl, w, a, q=sol.q[a:a+1] + 0.5, pts=pts, terms=1)
+              - _per_atom_L(oracle, wl, w, a, q=sol.q[a:a+1] - 0.5, pts=pts, terms=1))
+        assert dq[a] == pytest.approx(fq, rel=1e-10)
+        for arr, name, grad in ((sol.eps, "eps", de), (sol.sigma, "sig", ds)):
+            h = 1e-6 * arr[a]
+            kw_p = {name: arr[a:a+1] + h}
+            kw_m = {name: arr[a:a+1] - h}
+            fd = (_per_atom_L(oracle, wl, w, a, pts=pts, terms=2, **kw_p)
+                  - _per_atom_L(oracle, wl, w, a, pts=pts, terms=2, **kw_m)) / (2 * h)
+            assert grad[a] == pytest.approx(fd, rel=1e-6)
+
+
+def test_backward_euler_homogeneity(oracle):
+    """Coulomb is degree 1 in Q, LJ degree 1/2 in eps_a (geometric mixing):
+    sum_a Q_a dL/dQ_a = L_coul and sum_a eps_a dL/deps_a = L_LJ / 2."""
+    wl = W.tiny(n_atoms=6, dims=(4, 4, 4), seed=12)
+    sol, s, g = wl.solute, wl.sites, wl.grid
+    pts = oracle.grid_points(g.origin, g.spacing, g.dims)
+    w = np.random.default_rng(3).normal(size=(s.n, len(pts)))
+    _, dq, de, _ = oracle.backward_points(sol.xyz, sol.q, sol.sigma, sol.eps, s.q, s.sigma,
+                                          s.eps, pts, w, KC)
+    uc = oracle.potential_points(sol.xyz, sol.q, sol.sigma, sol.eps, s.q, s.sigma, s.eps, pts,
+                                 KC, terms=1)
+    ul = oracle.potential_points(sol.xyz, sol.q, sol.sigma, sol.eps, s.q, s.sigma, s.eps, pts,
+                                 KC, terms=2)
+    assert (sol.q * dq).sum() == pytest.approx((w * uc).sum(), rel=1e-10)
+    assert (sol.eps * de).sum() == pytest.approx(0.5 * (w * ul).sum(), rel=1e-10)
