@@ -1,0 +1,480 @@
+// Direct-sum kernels: atom staging, LJ tail constants, the FP64 reference
+// direct sum, the FP32 compensated direct sum, and the error report.
+//
+// Thread mapping of the direct sums: one thread per grid point, a 256-thread
+// workgroup covers a 16 x 4 x 4 brick (a wave is a 16 x 4 slab, so its rows
+// write 64 contiguous bytes and its points stay within 8 A x 2 A, which keeps
+// the divergent short-range branch rare).  Every thread walks the whole atom
+// array; atom records are wave-uniform and arrive through scalar loads.
+#include <cmath>
+
+#include "rism_internal.h"
+
+namespace rism {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ void two_sum_acc(float &s, float &c, float x)
+{
+    // Knuth's TwoSum: s + c carries the running sum with its rounding error.
+    float t = s + x;
+    float z = t - s;
+    c += (s - (t - z)) + (x - z);
+    s = t;
+}
+
+__device__ __forceinline__ void store_val(void *base, int f64, int64_t idx, double v)
+{
+    if (f64)
+        static_cast<double *>(base)[idx] = v;
+    else
+        static_cast<float *>(base)[idx] = static_cast<float>(v);
+}
+
+struct BrickIndex {
+    int i, j, k;
+    bool valid;
+};
+
+__device__ __forceinline__ BrickIndex brick_index(const GridParams &g)
+{
+    const int bx = (g.nx + 15) / 16, by = (g.ny + 3) / 4;
+    int b = blockIdx.x;
+    int bi = b % bx;
+    b /= bx;
+    int bj = b % by;
+    int bk = b / by;
+    int t = threadIdx.x;
+    BrickIndex r;
+    r.i = bi * 16 + (t & 15);
+    r.j = bj * 4 + ((t >> 4) & 3);
+    r.k = bk * 4 + (t >> 6);
+    r.valid = r.i < g.nx && r.j < g.ny && r.k < g.nz;
+    return r;
+}
+
+inline int brick_blocks(const GridParams &g)
+{
+    return ((g.nx + 15) / 16) * ((g.ny + 3) / 4) * ((g.nz + 3) / 4);
+}
+
+// ------------------------------------------------------------------ staging
+
+// Lorentz-Berthelot mixing and the A, B, r_cut of every (site, atom) pair,
+// plus the FP32 hi/lo split of the atom coordinates relative to the grid
+// origin.  Padding atoms (a >= n) carry no charge and no LJ and sit far away.
+template <int NS>
+__global__ __launch_bounds__(kBlock) void k_stage(SiteParams sp, StageArgs a)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= a.npad) return;
+    double x = kFarAway, y = kFarAway, z = kFarAway, q = 0.0, sig = 0.0, eps = 0.0;
+    bool real = i < a.n;
+    if (real) {
+        x = a.xyz[3 * i] - a.origin[0];
+        y = a.xyz[3 * i + 1] - a.origin[1];
+        z = a.xyz[3 * i + 2] - a.origin[2];
+        q = a.q[i];
+        sig = a.sig[i];
+        eps = a.eps[i];
+        bool bad = !(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(q) &&
+                     isfinite(sig) && isfinite(eps)) || sig < 0.0 || eps < 0.0;
+        if (bad) a.err_flags[0] = 1;
+        if (a.check_eps && !(eps > 0.0)) a.err_flags[1] = 1;
+    }
+    double A[NS], B[NS], rc[NS];
+#pragma unroll
+    for (int g = 0; g < NS; ++g) {
+        A[g] = 0.0;
+        B[g] = 0.0;
+        rc[g] = INFINITY;
+        if (real && g < sp.ns) {
+            double s_ga = 0.5 * (sp.sig[g] + sig);
+            double e_ga = sqrt(sp.eps[g] * eps);
+            double s2 = s_ga * s_ga, s6 = s2 * s2 * s2;
+            A[g] = 4.0 * e_ga * s6 * s6;
+            B[g] = 4.0 * e_ga * s6;
+            if (a.lj_mode == LJ_CUT) {
+                if (a.lj_tol > 0.0) {
+                    // |u(r)| = tol beyond the minimum: with t = (s_ga/r)^6,
+                    // 4 e (t^2 - t) = -tol, smaller root, written without
+                    // cancellation: t = (z/2) / (1 + sqrt(1 - z)), z = tol/e.
+                    double zz = a.lj_tol / e_ga;
+                    if (!(zz < 1.0)) {
+                        a.err_flags[1] = 1;
+                        rc[g] = 0.0;
+                    } else {
+                        double t = 0.5 * zz / (1.0 + sqrt(1.0 - zz));
+                        rc[g] = s_ga * pow(t, -1.0 / 6.0);
+                    }
+                } else {
+                    rc[g] = a.lj_cutoff;
+                }
+            }
+            if (a.rcut) a.rcut[(int64_t)g * a.n + i] = rc[g];
+        }
+    }
+    if (a.rec64) {
+        AtomF64<NS> r;
+        r.x = x; r.y = y; r.z = z; r.q = q;
+#pragma unroll
+        for (int g = 0; g < NS; ++g) { r.A[g] = A[g]; r.B[g] = B[g]; r.rc2[g] = rc[g] * rc[g]; }
+        static_cast<AtomF64<NS> *>(a.rec64)[i] = r;
+    }
+    if (a.rec32) {
+        AtomF32<NS> r;
+        r.xh = (float)x; r.xl = (float)(x - (double)r.xh);
+        r.yh = (float)y; r.yl = (float)(y - (double)r.yh);
+        r.zh = (float)z; r.zl = (float)(z - (double)r.zh);
+        r.q = (float)q;
+        r.pad = 0.f;
+#pragma unroll
+        for (int g = 0; g < NS; ++g) {
+            r.A[g] = (float)A[g];
+            r.B[g] = (float)B[g];
+            r.rc2[g] = (float)(rc[g] * rc[g]);
+        }
+        static_cast<AtomF32<NS> *>(a.rec32)[i] = r;
+    }
+}
+
+int launch_stage(const SiteParams &sp, const StageArgs &a, hipStream_t s)
+{
+    int blocks = (int)((a.npad + kBlock - 1) / kBlock);
+    if (blocks == 0) return RISM_OK;
+    switch (sp.ns_pad) {
+    case 1: hipLaunchKernelGGL(k_stage<1>, blocks, kBlock, 0, s, sp, a); break;
+    case 2: hipLaunchKernelGGL(k_stage<2>, blocks, kBlock, 0, s, sp, a); break;
+    case 4: hipLaunchKernelGGL(k_stage<4>, blocks, kBlock, 0, s, sp, a); break;
+    default: hipLaunchKernelGGL(k_stage<8>, blocks, kBlock, 0, s, sp, a); break;
+    }
+    RISM_HIP(hipGetLastError());
+    return RISM_OK;
+}
+
+// T_g = (4 pi / 3) sum_a (A/(3 rc^9) - B/rc^3), one workgroup per site,
+// fixed-order reduction (bitwise reproducible).
+__global__ __launch_bounds__(kBlock) void k_lj_tail(SiteParams sp, const double *rcut,
+                                                    const double *sig, const double *eps,
+                                                    int64_t n, double *tail)
+{
+    __shared__ double red[kBlock];
+    int g = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+        double s_ga = 0.5 * (sp.sig[g] + sig[i]);
+        double e_ga = sqrt(sp.eps[g] * eps[i]);
+        double s2 = s_ga * s_ga, s6 = s2 * s2 * s2;
+        double A = 4.0 * e_ga * s6 * s6, B = 4.0 * e_ga * s6;
+        double rc = rcut[(int64_t)g * n + i];
+        double rc3 = rc * rc * rc;
+        acc += A / (3.0 * rc3 * rc3 * rc3) - B / rc3;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tail[g] = 4.0 * kPi / 3.0 * red[0];
+}
+
+int launch_lj_tail(const SiteParams &sp, const double *rcut, const double *sig, const double *eps,
+                   int64_t n, double *tail_dev, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lj_tail, sp.ns, kBlock, 0, s, sp, rcut, sig, eps, n, tail_dev);
+    RISM_HIP(hipGetLastError());
+    return RISM_OK;
+}
+
+// ---------------------------------------------------------- FP64 direct sum
+
+// The definitions term by term in FP64: Coulomb, LJ (all pairs or truncated),
+// erf(d/eta)/d and the Eq. 6 bracket over d, each pair evaluated in full.
+template <int NS>
+__global__ __launch_bounds__(kBlock) void k_direct_f64(SiteParams sp, DirectArgs a)
+{
+    const GridParams &g = a.g;
+    BrickIndex bi = brick_index(g);
+    int i = bi.valid ? bi.i : 0, j = bi.valid ? bi.j : 0, k = bi.valid ? bi.k : 0;
+    const double gx = i * g.h[0], gy = j * g.h[1], gz = k * g.h[2];
+    const AtomF64<NS> *__restrict__ atoms = static_cast<const AtomF64<NS> *>(a.atoms);
+    const bool want_u = a.out.want_u, want_c = a.out.want_c && a.asym_on,
+               want_h = a.out.want_h && a.asym_on;
+    const int ljm = a.lj_mode;
+    const double inv_eta = a.asym.inv_eta, kap = a.asym.kappa, aa = a.asym.a;
+    double coul = 0.0, sc = 0.0, sh = 0.0;
+    double lj[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) lj[s] = 0.0;
+    bool hit = false;
+    for (int64_t n = 0; n < a.n; ++n) {
+        const AtomF64<NS> at = atoms[n];
+        double dx = gx - at.x, dy = gy - at.y, dz = gz - at.z;
+        double d2 = dx * dx + dy * dy + dz * dz;
+        if (d2 == 0.0) {
+            hit = true;
+            sc += at.q * a.asym.dcf0;
+            sh += at.q * a.asym.tcf0;
+            continue;
+        }
+        double d = sqrt(d2);
+        double ri = 1.0 / d;
+        if (want_u) {
+            coul += at.q * ri;
+            if (ljm != LJ_NONE) {
+                double r2 = ri * ri, r6 = r2 * r2 * r2;
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+                    if (ljm == LJ_ALL || d2 < at.rc2[s]) lj[s] += (at.A[s] * r6 - at.B[s]) * r6;
+            }
+        }
+        if (want_c) sc += at.q * erf(d * inv_eta) * ri;
+        if (want_h) {
+            double x = d * inv_eta;
+            // erfc(aa + x) is exactly 0 in FP64 beyond 26.6; skipping the
+            // product there avoids inf * 0 when exp(kappa d) overflows
+            double t2 = aa + x < 27.0 ? exp(kap * d) * erfc(aa + x) : 0.0;
+            sh += at.q * (exp(-kap * d) * erfc(aa - x) - t2) * ri;
+        }
+    }
+    if (!bi.valid) return;
+    const int64_t p = ((int64_t)k * g.ny + j) * g.nx + i;
+    const OutParams &o = a.out;
+    if (want_u)
+        for (int s = 0; s < o.ns; ++s)
+            store_val(o.u, o.f64, s * g.m + p, hit ? INFINITY : o.u_coul[s] * coul + lj[s]);
+    if (want_c)
+        for (int s = 0; s < o.ns; ++s) store_val(o.c, o.f64, s * g.m + p, o.c_scale[s] * sc);
+    if (want_h)
+        for (int s = 0; s < o.n_ionic; ++s) store_val(o.h, o.f64, s * g.m + p, o.h_scale[s] * sh);
+}
+
+int launch_direct_f64(const SiteParams &sp, const DirectArgs &a, hipStream_t s)
+{
+    int blocks = brick_blocks(a.g);
+    switch (sp.ns_pad) {
+    case 1: hipLaunchKernelGGL(k_direct_f64<1>, blocks, kBlock, 0, s, sp, a); break;
+    case 2: hipLaunchKernelGGL(k_direct_f64<2>, blocks, kBlock, 0, s, sp, a); break;
+    case 4: hipLaunchKernelGGL(k_direct_f64<4>, blocks, kBlock, 0, s, sp, a); break;
+    default: hipLaunchKernelGGL(k_direct_f64<8>, blocks, kBlock, 0, s, sp, a); break;
+    }
+    RISM_HIP(hipGetLastError());
+    return RISM_OK;
+}
+
+// ------------------------------------------------- FP32 compensated direct sum
+
+// Per pair, in FP32: d from hi/lo coordinates, 1/d by rsqrt, Coulomb Q/d,
+// Yukawa Q e^{-kappa d}/d (exp2), LJ (A r^-6 - B) r^-6 per site; within
+// R_s the smeared-kernel corrections
+//   c: -Q erfc(d/eta)/d
+//   h: -Q [e^{-kappa d} erfc(d/eta - kappa eta/2) + e^{kappa d} erfc(d/eta + kappa eta/2)]/d
+// so that erf(d/eta)/d = 1/d + c-correction and the Eq. 6 bracket over d =
+// 2 e^{-kappa d}/d + h-correction hold exactly for d < R_s and to < 1e-12
+// beyond it.  Partial sums over 8 atoms are flushed into FP64 (electrostatic
+// sums, which cancel in sign) or into TwoSum-compensated FP32 (LJ).
+template <int NS, int LJM, bool ASYM, bool EXACT>
+__global__ __launch_bounds__(kBlock) void k_direct_f32(SiteParams sp, DirectArgs a)
+{
+    const GridParams &g = a.g;
+    BrickIndex bi = brick_index(g);
+    int i = bi.valid ? bi.i : 0, j = bi.valid ? bi.j : 0, k = bi.valid ? bi.k : 0;
+    const double gxd = i * g.h[0], gyd = j * g.h[1], gzd = k * g.h[2];
+    const float gxh = (float)gxd, gyh = (float)gyd, gzh = (float)gzd;
+    const float gxl = (float)(gxd - (double)gxh), gyl = (float)(gyd - (double)gyh),
+                gzl = (float)(gzd - (double)gzh);
+    const AtomF32<NS> *__restrict__ atoms = static_cast<const AtomF32<NS> *>(a.atoms);
+    const float yk = (float)a.asym.yk, inv_eta = (float)a.asym.inv_eta,
+                aa = (float)a.asym.a, rs2 = (float)a.asym.rs2;
+    const float dcf0 = (float)a.asym.dcf0, tcf0 = (float)a.asym.tcf0;
+
+    double accC = 0.0, accY = 0.0, accSC = 0.0, accSH = 0.0;
+    float ljs[NS], ljc[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) { ljs[s] = 0.f; ljc[s] = 0.f; }
+    bool hit = false;
+
+    for (int64_t n0 = 0; n0 < a.npad; n0 += kAtomPad) {
+        float pC = 0.f, pY = 0.f, pSC = 0.f, pSH = 0.f;
+        float pL[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) pL[s] = 0.f;
+#pragma unroll 2
+        for (int t = 0; t < kAtomPad; ++t) {
+            const AtomF32<NS> &at = atoms[n0 + t];
+            float dx, dy, dz;
+            if (EXACT) {
+                dx = (gxh - at.xh) - at.xl;
+                dy = (gyh - at.yh) - at.yl;
+                dz = (gzh - at.zh) - at.zl;
+            } else {
+                dx = (gxh - at.xh) + (gxl - at.xl);
+                dy = (gyh - at.yh) + (gyl - at.yl);
+                dz = (gzh - at.zh) + (gzl - at.zl);
+            }
+            float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            // raw v_rsq_f32 (d2 is never denormal unless a point sits within
+            // 1e-19 A of an atom); coincident points get 1/d = 0 and are
+            // handled through `hit` and the d -> 0 limits
+            float ri = d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
+            hit |= (d2 == 0.f);
+            // LJ first, so that the per-site parameters die before the
+            // divergent short-range branch below
+            if (LJM != LJ_NONE) {
+                float r2 = ri * ri;
+                float r6 = r2 * r2 * r2;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    float r6s = r6;
+                    if (LJM == LJ_CUT) r6s = d2 < at.rc2[s] ? r6 : 0.f;
+                    pL[s] = fmaf(fmaf(at.A[s], r6s, -at.B[s]), r6s, pL[s]);
+                }
+            }
+            const float aq = at.q;
+            float qr = aq * ri;
+            pC += qr;
+            if (ASYM) {
+                float d = d2 * ri;
+                float e = __builtin_amdgcn_exp2f(yk * d);
+                pY = fmaf(qr, e, pY);
+                if (d2 < rs2) {
+                    float x = d * inv_eta;
+                    pSC = fmaf(-qr, erfcf(x), pSC);
+                    float ep = __builtin_amdgcn_rcpf(e);
+                    float br = fmaf(e, erfcf(x - aa), ep * erfcf(x + aa));
+                    pSH = fmaf(-qr, br, pSH);
+                    if (d2 == 0.f) {
+                        pSC = fmaf(aq, dcf0, pSC);
+                        pSH = fmaf(aq, tcf0, pSH);
+                    }
+                }
+            }
+        }
+        accC += (double)pC;
+        if (ASYM) {
+            accY += (double)pY;
+            accSC += (double)pSC;
+            accSH += (double)pSH;
+        }
+        if (LJM != LJ_NONE) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) two_sum_acc(ljs[s], ljc[s], pL[s]);
+        }
+    }
+    if (!bi.valid) return;
+    const int64_t p = ((int64_t)k * g.ny + j) * g.nx + i;
+    const OutParams &o = a.out;
+    if (o.want_u) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (s < o.ns) {
+                double lj = LJM != LJ_NONE ? (double)ljs[s] + (double)ljc[s] : 0.0;
+                store_val(o.u, o.f64, s * g.m + p, hit ? INFINITY : o.u_coul[s] * accC + lj);
+            }
+        }
+    }
+    if (ASYM) {
+        if (o.want_c)
+            for (int s = 0; s < o.ns; ++s)
+                store_val(o.c, o.f64, s * g.m + p, o.c_scale[s] * (accC + accSC));
+        if (o.want_h)
+            for (int s = 0; s < o.n_ionic; ++s)
+                store_val(o.h, o.f64, s * g.m + p, o.h_scale[s] * (2.0 * accY + accSH));
+    }
+}
+
+template <int NS, int LJM, bool ASYM>
+static void launch_f32_exact(bool exact, int blocks, const SiteParams &sp, const DirectArgs &a,
+                             hipStream_t s)
+{
+    if (exact)
+        hipLaunchKernelGGL((k_direct_f32<NS, LJM, ASYM, true>), blocks, kBlock, 0, s, sp, a);
+    else
+        hipLaunchKernelGGL((k_direct_f32<NS, LJM, ASYM, false>), blocks, kBlock, 0, s, sp, a);
+}
+
+template <int NS>
+static void launch_f32_ns(int blocks, const SiteParams &sp, const DirectArgs &a, hipStream_t s)
+{
+    bool ex = a.g.exact != 0;
+    if (a.asym_on) {
+        if (a.lj_mode == LJ_NONE) launch_f32_exact<NS, LJ_NONE, true>(ex, blocks, sp, a, s);
+        else if (a.lj_mode == LJ_ALL) launch_f32_exact<NS, LJ_ALL, true>(ex, blocks, sp, a, s);
+        else launch_f32_exact<NS, LJ_CUT, true>(ex, blocks, sp, a, s);
+    } else {
+        if (a.lj_mode == LJ_NONE) launch_f32_exact<NS, LJ_NONE, false>(ex, blocks, sp, a, s);
+        else if (a.lj_mode == LJ_ALL) launch_f32_exact<NS, LJ_ALL, false>(ex, blocks, sp, a, s);
+        else launch_f32_exact<NS, LJ_CUT, false>(ex, blocks, sp, a, s);
+    }
+}
+
+int launch_direct_f32(const SiteParams &sp, const DirectArgs &a, hipStream_t s)
+{
+    int blocks = brick_blocks(a.g);
+    switch (sp.ns_pad) {
+    case 1: launch_f32_ns<1>(blocks, sp, a, s); break;
+    case 2: launch_f32_ns<2>(blocks, sp, a, s); break;
+    case 4: launch_f32_ns<4>(blocks, sp, a, s); break;
+    default: launch_f32_ns<8>(blocks, sp, a, s); break;
+    }
+    RISM_HIP(hipGetLastError());
+    return RISM_OK;
+}
+
+// ------------------------------------------------------------- error report
+
+// Partial sums per workgroup (fixed order within the group); the host adds
+// the per-group partials in group order.
+__global__ __launch_bounds__(kBlock) void k_compare(const void *x, int f64, const double *ref,
+                                                    int64_t n, double cap, double *part)
+{
+    __shared__ double r0[kBlock], r1[kBlock], r2[kBlock], r3[kBlock], r4[kBlock];
+    double se = 0.0, sr = 0.0, mx = 0.0, ex = 0.0, mism = 0.0;
+    int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += stride) {
+        double v = f64 ? static_cast<const double *>(x)[i] : (double)static_cast<const float *>(x)[i];
+        double r = ref[i];
+        bool vr = isfinite(v) && (cap <= 0.0 || fabs(v) <= cap);
+        bool rr = isfinite(r) && (cap <= 0.0 || fabs(r) <= cap);
+        if (vr && rr) {
+            double d = v - r;
+            se += d * d;
+            sr += r * r;
+            mx = fmax(mx, fabs(d));
+        } else {
+            ex += 1.0;
+            if (vr != rr) mism += 1.0;
+        }
+    }
+    int t = threadIdx.x;
+    r0[t] = se; r1[t] = sr; r2[t] = mx; r3[t] = ex; r4[t] = mism;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            r0[t] += r0[t + w];
+            r1[t] += r1[t + w];
+            r2[t] = fmax(r2[t], r2[t + w]);
+            r3[t] += r3[t + w];
+            r4[t] += r4[t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        part[5 * blockIdx.x + 0] = r0[0];
+        part[5 * blockIdx.x + 1] = r1[0];
+        part[5 * blockIdx.x + 2] = r2[0];
+        part[5 * blockIdx.x + 3] = r3[0];
+        part[5 * blockIdx.x + 4] = r4[0];
+    }
+}
+
+int launch_compare(const void *x, int f64, const double *ref, int64_t n, double cap,
+                   double *partials, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_compare, nblocks, kBlock, 0, s, x, f64, ref, n, cap, partials);
+    RISM_HIP(hipGetLastError());
+    return RISM_OK;
+}
+
+}  // namespace rism
