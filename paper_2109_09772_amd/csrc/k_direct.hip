@@ -8,28 +8,11 @@
 // array; atom records are wave-uniform and arrive through scalar loads.
 #include <cmath>
 
-#include "rism_internal.h"
+#include "pair.h"
 
 namespace rism {
 
 // ------------------------------------------------------------------ helpers
-
-__device__ __forceinline__ void two_sum_acc(float &s, float &c, float x)
-{
-    // Knuth's TwoSum: s + c carries the running sum with its rounding error.
-    float t = s + x;
-    float z = t - s;
-    c += (s - (t - z)) + (x - z);
-    s = t;
-}
-
-__device__ __forceinline__ void store_val(void *base, int f64, int64_t idx, double v)
-{
-    if (f64)
-        static_cast<double *>(base)[idx] = v;
-    else
-        static_cast<float *>(base)[idx] = static_cast<float>(v);
-}
 
 struct BrickIndex {
     int i, j, k;
@@ -112,6 +95,11 @@ __global__ __launch_bounds__(kBlock) void k_stage(SiteParams sp, StageArgs a)
                 }
             }
             if (a.rcut) a.rcut[(int64_t)g * a.n + i] = rc[g];
+            if (a.lj_mode == LJ_CUT && rc[g] > 0.0) {
+                // positive floats order like their bit patterns
+                float r2f = (float)(rc[g] * rc[g]) * (1.0f + 1e-6f);
+                atomicMax(&a.err_flags[2], __float_as_int(r2f));
+            }
         }
     }
     if (a.rec64) {
@@ -279,109 +267,22 @@ __global__ __launch_bounds__(kBlock) void k_direct_f32(SiteParams sp, DirectArgs
 {
     const GridParams &g = a.g;
     BrickIndex bi = brick_index(g);
-    int i = bi.valid ? bi.i : 0, j = bi.valid ? bi.j : 0, k = bi.valid ? bi.k : 0;
-    const double gxd = i * g.h[0], gyd = j * g.h[1], gzd = k * g.h[2];
-    const float gxh = (float)gxd, gyh = (float)gyd, gzh = (float)gzd;
-    const float gxl = (float)(gxd - (double)gxh), gyl = (float)(gyd - (double)gyh),
-                gzl = (float)(gzd - (double)gzh);
+    const GridPt gp = grid_pt(g, bi.valid ? bi.i : 0, bi.valid ? bi.j : 0, bi.valid ? bi.k : 0);
     const AtomF32<NS> *__restrict__ atoms = static_cast<const AtomF32<NS> *>(a.atoms);
-    const float yk = (float)a.asym.yk, inv_eta = (float)a.asym.inv_eta,
-                aa = (float)a.asym.a, rs2 = (float)a.asym.rs2;
-    const float dcf0 = (float)a.asym.dcf0, tcf0 = (float)a.asym.tcf0;
-
-    double accC = 0.0, accY = 0.0, accSC = 0.0, accSH = 0.0;
-    float ljs[NS], ljc[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) { ljs[s] = 0.f; ljc[s] = 0.f; }
-    bool hit = false;
-
+    const PairConst kc = make_pair_const(a.asym);
+    PointAcc<NS> acc;
+    acc.zero();
     for (int64_t n0 = 0; n0 < a.npad; n0 += kAtomPad) {
-        float pC = 0.f, pY = 0.f, pSC = 0.f, pSH = 0.f;
-        float pL[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) pL[s] = 0.f;
+        PairAcc<NS> p;
+        p.zero();
 #pragma unroll 2
-        for (int t = 0; t < kAtomPad; ++t) {
-            const AtomF32<NS> &at = atoms[n0 + t];
-            float dx, dy, dz;
-            if (EXACT) {
-                dx = (gxh - at.xh) - at.xl;
-                dy = (gyh - at.yh) - at.yl;
-                dz = (gzh - at.zh) - at.zl;
-            } else {
-                dx = (gxh - at.xh) + (gxl - at.xl);
-                dy = (gyh - at.yh) + (gyl - at.yl);
-                dz = (gzh - at.zh) + (gzl - at.zl);
-            }
-            float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            // raw v_rsq_f32 (d2 is never denormal unless a point sits within
-            // 1e-19 A of an atom); coincident points get 1/d = 0 and are
-            // handled through `hit` and the d -> 0 limits
-            float ri = d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
-            hit |= (d2 == 0.f);
-            // LJ first, so that the per-site parameters die before the
-            // divergent short-range branch below
-            if (LJM != LJ_NONE) {
-                float r2 = ri * ri;
-                float r6 = r2 * r2 * r2;
-#pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    float r6s = r6;
-                    if (LJM == LJ_CUT) r6s = d2 < at.rc2[s] ? r6 : 0.f;
-                    pL[s] = fmaf(fmaf(at.A[s], r6s, -at.B[s]), r6s, pL[s]);
-                }
-            }
-            const float aq = at.q;
-            float qr = aq * ri;
-            pC += qr;
-            if (ASYM) {
-                float d = d2 * ri;
-                float e = __builtin_amdgcn_exp2f(yk * d);
-                pY = fmaf(qr, e, pY);
-                if (d2 < rs2) {
-                    float x = d * inv_eta;
-                    pSC = fmaf(-qr, erfcf(x), pSC);
-                    float ep = __builtin_amdgcn_rcpf(e);
-                    float br = fmaf(e, erfcf(x - aa), ep * erfcf(x + aa));
-                    pSH = fmaf(-qr, br, pSH);
-                    if (d2 == 0.f) {
-                        pSC = fmaf(aq, dcf0, pSC);
-                        pSH = fmaf(aq, tcf0, pSH);
-                    }
-                }
-            }
-        }
-        accC += (double)pC;
-        if (ASYM) {
-            accY += (double)pY;
-            accSC += (double)pSC;
-            accSH += (double)pSH;
-        }
-        if (LJM != LJ_NONE) {
-#pragma unroll
-            for (int s = 0; s < NS; ++s) two_sum_acc(ljs[s], ljc[s], pL[s]);
-        }
+        for (int t = 0; t < kAtomPad; ++t)
+            pair_eval<NS, LJM, ASYM, EXACT, true>(atoms[n0 + t], gp, kc, p, acc.hit);
+        acc.template flush<LJM != LJ_NONE, ASYM>(p);
     }
     if (!bi.valid) return;
-    const int64_t p = ((int64_t)k * g.ny + j) * g.nx + i;
-    const OutParams &o = a.out;
-    if (o.want_u) {
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            if (s < o.ns) {
-                double lj = LJM != LJ_NONE ? (double)ljs[s] + (double)ljc[s] : 0.0;
-                store_val(o.u, o.f64, s * g.m + p, hit ? INFINITY : o.u_coul[s] * accC + lj);
-            }
-        }
-    }
-    if (ASYM) {
-        if (o.want_c)
-            for (int s = 0; s < o.ns; ++s)
-                store_val(o.c, o.f64, s * g.m + p, o.c_scale[s] * (accC + accSC));
-        if (o.want_h)
-            for (int s = 0; s < o.n_ionic; ++s)
-                store_val(o.h, o.f64, s * g.m + p, o.h_scale[s] * (2.0 * accY + accSH));
-    }
+    const int64_t p = ((int64_t)bi.k * g.ny + bi.j) * g.nx + bi.i;
+    store_point<NS, LJM, ASYM>(a.out, g, p, acc);
 }
 
 template <int NS, int LJM, bool ASYM>

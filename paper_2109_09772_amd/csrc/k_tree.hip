@@ -1,23 +1,890 @@
-// Treecode forward and adjoint (filled in below).
-#include "rism_internal.h"
+// Particle-cluster treecode on the GPU: source octree on the atoms (Morton
+// keys, LSD radix sort, level-by-level split), node boxes, barycentric
+// Chebyshev proxy charges (upward pass), and the per-batch interaction lists
+// that drive the evaluation kernel (k_tree_eval.hip).
+//
+// Reading of the paper (Sec. 2.3): the paper builds its tree on the grid
+// targets and expands each source atom about target clusters (cluster-
+// particle, Taylor).  This file is the particle-cluster orientation with
+// interpolation proxies: the far field of a source cluster C seen from a
+// batch B of grid points is sum_k qhat_k phi(x, s_k) over the (n+1)^3
+// Chebyshev points s_k of C's box, with qhat_k = sum_{j in C} L_k(y_j) q_j.
+// It is accepted when (r_B + r_C) < theta |c_B - c_C| and C holds more
+// atoms than proxies; otherwise C is opened, and leaves are summed directly.
+#include <algorithm>
+#include <cmath>
+#include <utility>
+
+#include "pair.h"
+#include "tree.h"
 
 namespace rism {
 
-int tree_forward(const TreeCallArgs &, Workspace &, rism_stats &, hipStream_t)
+namespace {
+
+constexpr int kRsItems = 8;
+constexpr int kRsTile = kBlock * kRsItems;   // keys per radix-sort workgroup
+
+// ------------------------------------------------------------ bounding box
+
+__global__ __launch_bounds__(kBlock) void k_bbox_partial(const float4 *rec, int stride_f4, int n,
+                                                         double *part)
 {
-    set_error("RISM_TREECODE: not built yet");
-    return RISM_E_UNSUPPORTED;
+    __shared__ double red[6][kBlock];
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        float4 a = rec[(size_t)i * stride_f4];       // xh, yh, zh, q
+        float4 b = rec[(size_t)i * stride_f4 + 1];   // xl, yl, zl, pad
+        double v[3] = {(double)a.x + b.x, (double)a.y + b.y, (double)a.z + b.z};
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fmin(lo[k], v[k]);
+            hi[k] = fmax(hi[k], v[k]);
+        }
+    }
+    for (int k = 0; k < 3; ++k) {
+        red[k][threadIdx.x] = lo[k];
+        red[3 + k][threadIdx.x] = hi[k];
+    }
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int k = 0; k < 3; ++k) {
+                red[k][threadIdx.x] = fmin(red[k][threadIdx.x], red[k][threadIdx.x + w]);
+                red[3 + k][threadIdx.x] = fmax(red[3 + k][threadIdx.x], red[3 + k][threadIdx.x + w]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
+
+__global__ void k_bbox_final(const double *part, int nparts, double *bbox)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int p = 0; p < nparts; ++p)
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fmin(lo[k], part[6 * p + k]);
+            hi[k] = fmax(hi[k], part[6 * p + 3 + k]);
+        }
+    double ext = fmax(fmax(hi[0] - lo[0], hi[1] - lo[1]), hi[2] - lo[2]);
+    ext = fmax(ext, 1e-3) * (1.0 + 1e-9);
+    for (int k = 0; k < 3; ++k) {
+        bbox[k] = lo[k];
+        bbox[3 + k] = ext;   // cube edge
+    }
+}
+
+// ------------------------------------------------------------ Morton keys
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v)
+{
+    v &= 0x3ff;
+    v = (v | (v << 16)) & 0x030000ff;
+    v = (v | (v << 8)) & 0x0300f00f;
+    v = (v | (v << 4)) & 0x030c30c3;
+    v = (v | (v << 2)) & 0x09249249;
+    return v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_morton(const float4 *rec, int stride_f4, int n,
+                                                   const double *bbox, uint32_t *keys, int *idx)
+{
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    float4 a = rec[(size_t)i * stride_f4];
+    float4 b = rec[(size_t)i * stride_f4 + 1];
+    double v[3] = {(double)a.x + b.x, (double)a.y + b.y, (double)a.z + b.z};
+    uint32_t c[3];
+    for (int k = 0; k < 3; ++k) {
+        double t = (v[k] - bbox[k]) / bbox[3 + k] * (double)(1 << kMortonBits);
+        int ci = (int)floor(t);
+        ci = ci < 0 ? 0 : (ci > (1 << kMortonBits) - 1 ? (1 << kMortonBits) - 1 : ci);
+        c[k] = (uint32_t)ci;
+    }
+    keys[i] = spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
+    idx[i] = i;
+}
+
+// ------------------------------------------------------------ radix sort
+
+__global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, int n, int shift,
+                                                    int nblocks, uint32_t *hist)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int base = blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsItems; ++r) {
+        int i = base + r * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of a[0..n) in place by one 1024-thread workgroup; n is read
+// from n_dev if given.  If total_out is given it receives the sum.
+__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t *a, int n_host, const int *n_dev,
+                                                    uint32_t *total_out)
+{
+    __shared__ uint32_t s[1024];
+    const int n = n_dev ? *n_dev : n_host;
+    const int t = threadIdx.x;
+    const int per = (n + 1023) / 1024;
+    const int lo = t * per < n ? t * per : n;
+    const int hi = lo + per < n ? lo + per : n;
+    uint32_t sum = 0;
+    for (int i = lo; i < hi; ++i) sum += a[i];
+    s[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = t >= off ? s[t - off] : 0u;
+        __syncthreads();
+        s[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = s[t] - sum;
+    for (int i = lo; i < hi; ++i) {
+        uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    if (total_out && t == 1023) *total_out = s[1023];
+}
+
+__global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *kin, const int *vin,
+                                                       uint32_t *kout, int *vout, int n, int shift,
+                                                       int nblocks, const uint32_t *offs)
+{
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[kBlock / 64][256];
+    __shared__ uint32_t wbase[kBlock / 64][256];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    run[t] = offs[(size_t)t * nblocks + blockIdx.x];
+    for (int w = 0; w < kBlock / 64; ++w) wcnt[w][t] = 0;
+    __syncthreads();
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int base = blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsItems; ++r) {
+        const int i = base + r * kBlock + t;
+        const bool valid = i < n;
+        const uint32_t key = valid ? kin[i] : 0u;
+        const uint32_t dig = (key >> shift) & 255u;
+        uint64_t m = __ballot(valid);
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (dig >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        const int rank = __popcll(m & lt);
+        if (valid && rank == 0) wcnt[wave][dig] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t acc = run[t];
+        for (int w = 0; w < kBlock / 64; ++w) {
+            wbase[w][t] = acc;
+            acc += wcnt[w][t];
+        }
+        run[t] = acc;
+        __syncthreads();
+        if (valid) {
+            const uint32_t dst = wbase[wave][dig] + (uint32_t)rank;
+            kout[dst] = key;
+            vout[dst] = vin[i];
+        }
+        __syncthreads();
+        for (int w = 0; w < kBlock / 64; ++w) wcnt[w][t] = 0;
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ octree
+
+__global__ void k_tree_root(int n, int *begin, int *end, int *level, int *level_start, int *n_nodes,
+                            int *flags)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    begin[0] = 0;
+    end[0] = n;
+    level[0] = 0;
+    level_start[0] = 0;
+    level_start[1] = 1;
+    for (int l = 2; l < kMortonBits + 2; ++l) level_start[l] = 1;
+    *n_nodes = 1;
+    flags[0] = 0;
+}
+
+__global__ void k_level_count(const int *level_start, int lvl, int *out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *out = level_start[lvl + 1] - level_start[lvl];
+}
+
+__device__ __forceinline__ int lower_digit(const uint32_t *keys, int lo, int hi, int shift, int d)
+{
+    // first index in [lo, hi) whose 3-bit digit at `shift` is >= d (digits are
+    // non-decreasing inside a node's range)
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if ((int)((keys[mid] >> shift) & 7u) < d) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_split_count(const uint32_t *keys, const int *begin,
+                                                        const int *end, const int *level_start,
+                                                        int lvl, int leaf, uint32_t *cnt)
+{
+    const int s0 = level_start[lvl], s1 = level_start[lvl + 1];
+    const int shift = 3 * (kMortonBits - 1 - lvl);
+    for (int i = s0 + blockIdx.x * kBlock + threadIdx.x; i < s1; i += gridDim.x * kBlock) {
+        const int b = begin[i], e = end[i];
+        uint32_t c = 0;
+        if (e - b > leaf && lvl < kMortonBits) {
+            int prev = b;
+            for (int d = 1; d <= 8; ++d) {
+                int nx = d == 8 ? e : lower_digit(keys, prev, e, shift, d);
+                if (nx > prev) ++c;
+                prev = nx;
+            }
+        }
+        cnt[i - s0] = c;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_split_write(const uint32_t *keys, int *begin, int *end,
+                                                        int *level, int *child0, int *nchild,
+                                                        int *level_start, int lvl, int leaf,
+                                                        const uint32_t *off, const uint32_t *total,
+                                                        int cap, int *n_nodes, int *flags)
+{
+    const int s0 = level_start[lvl], s1 = level_start[lvl + 1];
+    const int shift = 3 * (kMortonBits - 1 - lvl);
+    const int first_child = s1;   // children of this level start right after it
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int tot = s1 + (int)*total;
+        if (tot > cap) {
+            flags[0] = 1;
+            tot = cap;   // never let a later level index past the node arrays
+        }
+        level_start[lvl + 2] = tot;
+        *n_nodes = tot;
+    }
+    for (int i = s0 + blockIdx.x * kBlock + threadIdx.x; i < s1; i += gridDim.x * kBlock) {
+        const int b = begin[i], e = end[i];
+        int c = 0;
+        if (e - b > leaf && lvl < kMortonBits) {
+            const int base = first_child + (int)off[i - s0];
+            child0[i] = base;
+            int prev = b;
+            for (int d = 1; d <= 8; ++d) {
+                int nx = d == 8 ? e : lower_digit(keys, prev, e, shift, d);
+                if (nx > prev) {
+                    int j = base + c;
+                    if (j < cap) {
+                        begin[j] = prev;
+                        end[j] = nx;
+                        level[j] = lvl + 1;
+                        child0[j] = -1;
+                        nchild[j] = 0;
+                    }
+                    ++c;
+                }
+                prev = nx;
+            }
+        } else {
+            child0[i] = -1;
+        }
+        nchild[i] = c;
+    }
+}
+
+template <int NS>
+__global__ __launch_bounds__(kBlock) void k_permute(const AtomF32<NS> *in, const int *perm, int n,
+                                                    int npad, AtomF32<NS> *out)
+{
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] = in[perm[i]];
+    else if (i < npad) out[i] = in[i];   // padding records stay last
+}
+
+// Tight box, centre and radius of every node: one wave per node.
+__global__ __launch_bounds__(kBlock) void k_node_box(const float4 *rec, int stride_f4,
+                                                     const int *begin, const int *end,
+                                                     const int *n_nodes, double *box,
+                                                     double *centre)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int nw = gridDim.x * (kBlock / 64);
+    const int nn = *n_nodes;
+    for (int node = wave; node < nn; node += nw) {
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int i = begin[node] + lane; i < end[node]; i += 64) {
+            float4 a = rec[(size_t)i * stride_f4];
+            float4 b = rec[(size_t)i * stride_f4 + 1];
+            double v[3] = {(double)a.x + b.x, (double)a.y + b.y, (double)a.z + b.z};
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = fmin(lo[k], v[k]);
+                hi[k] = fmax(hi[k], v[k]);
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = fmin(lo[k], __shfl_xor(lo[k], off));
+                hi[k] = fmax(hi[k], __shfl_xor(hi[k], off));
+            }
+        if (lane == 0) {
+            double r2 = 0;
+            for (int k = 0; k < 3; ++k) {
+                box[6 * node + k] = lo[k];
+                box[6 * node + 3 + k] = hi[k];
+                centre[4 * node + k] = 0.5 * (lo[k] + hi[k]);
+                r2 += 0.25 * (hi[k] - lo[k]) * (hi[k] - lo[k]);
+            }
+            centre[4 * node + 3] = sqrt(r2);
+        }
+    }
+}
+
+// ------------------------------------------------------------ upward pass
+
+constexpr int kMaxDeg = 16;
+constexpr int kTile = 64;
+
+// Chebyshev points of the second kind on [lo, hi] and their barycentric
+// weights: s_k = lo + (hi - lo)(1 + cos(k pi/n))/2, w_k = (-1)^k delta_k with
+// delta_0 = delta_n = 1/2, else 1.
+__device__ __forceinline__ double cheb_point(double lo, double hi, int k, int n)
+{
+    return lo + (hi - lo) * 0.5 * (1.0 + cos(kPi * k / n));
+}
+__device__ __forceinline__ double bary_weight(int k, int n)
+{
+    double w = (k & 1) ? -1.0 : 1.0;
+    return (k == 0 || k == n) ? 0.5 * w : w;
+}
+
+// Lagrange basis values L_k(x), k = 0..n, of the Chebyshev points of [lo, hi].
+__device__ void lagrange_all(double x, double lo, double hi, int n, double *L)
+{
+    double den = 0.0;
+    int exact = -1;
+    for (int k = 0; k <= n; ++k) {
+        double d = x - cheb_point(lo, hi, k, n);
+        if (d == 0.0) exact = k;
+        double t = bary_weight(k, n) / d;
+        L[k] = t;
+        den += t;
+    }
+    if (exact >= 0) {
+        for (int k = 0; k <= n; ++k) L[k] = k == exact ? 1.0 : 0.0;
+        return;
+    }
+    double inv = 1.0 / den;
+    for (int k = 0; k <= n; ++k) L[k] *= inv;
+}
+
+// Proxy box of a node: its tight box, padded so that no axis is degenerate.
+__device__ __forceinline__ void proxy_box(const double *box, double *pb)
+{
+    for (int k = 0; k < 3; ++k) {
+        double lo = box[k], hi = box[3 + k];
+        double w = hi - lo;
+        if (w < 1e-3) {
+            double c = 0.5 * (lo + hi);
+            lo = c - 5e-4;
+            hi = c + 5e-4;
+        }
+        pb[k] = lo;
+        pb[3 + k] = hi;
+    }
+}
+
+// Leaves: qhat_k = sum_j q_j Lx_k1(x_j) Ly_k2(y_j) Lz_k3(z_j) from the atoms.
+// Internal nodes: qhat_P = sum_children (Mx (x) My (x) Mz) qhat_c, with
+// M[k][m] = L^P_k(s^c_m): exact, since each L^P_k is a polynomial of degree n
+// that the child's degree-n interpolation reproduces.
+__global__ __launch_bounds__(kBlock) void k_upward_level(const float4 *rec, int stride_f4,
+                                                         const int *begin, const int *end,
+                                                         const int *child0, const int *nchild,
+                                                         const double *box, const int *level_start,
+                                                         int lvl, int deg, double *pq, double *pbox)
+{
+    extern __shared__ double sm[];
+    const int n1 = deg + 1, np = n1 * n1 * n1;
+    const int s0 = level_start[lvl], s1 = level_start[lvl + 1];
+    double *Lx = sm;                        // [kTile][n1] (leaf) / [n1][n1] (internal)
+    double *Ly = Lx + kTile * n1;
+    double *Lz = Ly + kTile * n1;
+    double *qa = Lz + kTile * n1;           // [kTile]
+    double *qc = qa + kTile;                // [np] child proxies
+    double *t1 = qc + np;                   // [np]
+    double *t2 = t1 + np;                   // [np]
+    for (int node = s0 + blockIdx.x; node < s1; node += gridDim.x) {
+        double pb[6];
+        proxy_box(box + 6 * node, pb);
+        if (threadIdx.x < 6) pbox[6 * node + threadIdx.x] = pb[threadIdx.x];
+        double acc[(kMaxDeg + 1) * (kMaxDeg + 1) * (kMaxDeg + 1) / kBlock + 1];
+        const int mine = (np + kBlock - 1) / kBlock;
+        for (int r = 0; r < mine; ++r) acc[r] = 0.0;
+        if (nchild[node] == 0) {
+            for (int t0 = begin[node]; t0 < end[node]; t0 += kTile) {
+                const int cnt = min(kTile, end[node] - t0);
+                __syncthreads();
+                if (threadIdx.x < cnt) {
+                    const int i = t0 + threadIdx.x;
+                    float4 a = rec[(size_t)i * stride_f4];
+                    float4 b = rec[(size_t)i * stride_f4 + 1];
+                    double L[kMaxDeg + 1];
+                    lagrange_all((double)a.x + b.x, pb[0], pb[3], deg, L);
+                    for (int k = 0; k < n1; ++k) Lx[threadIdx.x * n1 + k] = L[k];
+                    lagrange_all((double)a.y + b.y, pb[1], pb[4], deg, L);
+                    for (int k = 0; k < n1; ++k) Ly[threadIdx.x * n1 + k] = L[k];
+                    lagrange_all((double)a.z + b.z, pb[2], pb[5], deg, L);
+                    for (int k = 0; k < n1; ++k) Lz[threadIdx.x * n1 + k] = L[k];
+                    qa[threadIdx.x] = (double)a.w;
+                }
+                __syncthreads();
+                for (int r = 0; r < mine; ++r) {
+                    const int k = threadIdx.x + r * kBlock;
+                    if (k >= np) break;
+                    const int k1 = k % n1, k2 = (k / n1) % n1, k3 = k / (n1 * n1);
+                    double s = acc[r];
+                    for (int j = 0; j < cnt; ++j)
+                        s += qa[j] * Lx[j * n1 + k1] * Ly[j * n1 + k2] * Lz[j * n1 + k3];
+                    acc[r] = s;
+                }
+            }
+        } else {
+            for (int c = child0[node]; c < child0[node] + nchild[node]; ++c) {
+                __syncthreads();
+                double cb[6];
+                proxy_box(box + 6 * c, cb);
+                // interpolation matrices M[k][m] = L^P_k(s^c_m), per axis
+                if (threadIdx.x < 3 * n1) {
+                    const int ax = threadIdx.x / n1, m = threadIdx.x % n1;
+                    double L[kMaxDeg + 1];
+                    lagrange_all(cheb_point(cb[ax], cb[3 + ax], m, deg), pb[ax], pb[3 + ax], deg, L);
+                    double *M = ax == 0 ? Lx : (ax == 1 ? Ly : Lz);
+                    for (int k = 0; k < n1; ++k) M[k * n1 + m] = L[k];
+                }
+                for (int k = threadIdx.x; k < np; k += kBlock) qc[k] = pq[(size_t)c * np + k];
+                __syncthreads();
+                // t1[k1][m2][m3] = sum_m1 Mx[k1][m1] qc[m1][m2][m3]   (x fastest)
+                for (int k = threadIdx.x; k < np; k += kBlock) {
+                    const int k1 = k % n1, rest = k / n1;
+                    double s = 0;
+                    for (int m1 = 0; m1 < n1; ++m1) s += Lx[k1 * n1 + m1] * qc[rest * n1 + m1];
+                    t1[k] = s;
+                }
+                __syncthreads();
+                for (int k = threadIdx.x; k < np; k += kBlock) {
+                    const int k1 = k % n1, k2 = (k / n1) % n1, m3 = k / (n1 * n1);
+                    double s = 0;
+                    for (int m2 = 0; m2 < n1; ++m2) s += Ly[k2 * n1 + m2] * t1[(m3 * n1 + m2) * n1 + k1];
+                    t2[k] = s;
+                }
+                __syncthreads();
+                for (int r = 0; r < mine; ++r) {
+                    const int k = threadIdx.x + r * kBlock;
+                    if (k >= np) break;
+                    const int k12 = k % (n1 * n1), k3 = k / (n1 * n1);
+                    double s = acc[r];
+                    for (int m3 = 0; m3 < n1; ++m3) s += Lz[k3 * n1 + m3] * t2[m3 * n1 * n1 + k12];
+                    acc[r] = s;
+                }
+            }
+        }
+        for (int r = 0; r < mine; ++r) {
+            const int k = threadIdx.x + r * kBlock;
+            if (k < np) pq[(size_t)node * np + k] = acc[r];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ lists
+
+struct ListArgs {
+    int nx, ny, nz, B, bx, by, bz, nb;
+    double h[3];
+    double theta, rshort;
+    int np;
+    const int *begin, *end, *child0, *nchild;
+    const double *box, *centre;
+    const int *n_nodes;
+    // count pass
+    uint32_t *cnt_far, *cnt_near, *cnt_short;
+    // fill pass
+    const uint32_t *off_far, *off_near, *off_short;
+    int *far, *near_l, *shrt;
+    unsigned long long *work;   // [3]: far pairs, near pairs, short pairs (point x source)
+    int fill;
+};
+
+__device__ __forceinline__ double box_gap2(const double *bl, const double *bh, const double *box)
+{
+    double s = 0;
+    for (int k = 0; k < 3; ++k) {
+        double g = fmax(0.0, fmax(box[k] - bh[k], bl[k] - box[3 + k]));
+        s += g * g;
+    }
+    return s;
+}
+
+constexpr int kStack = 128;
+
+__global__ __launch_bounds__(kBlock) void k_lists(ListArgs a)
+{
+    const int b = blockIdx.x * kBlock + threadIdx.x;
+    if (!a.fill && b == 0) {
+        // sentinel slot: the exclusive scan over nb + 1 entries then leaves
+        // the total in slot nb
+        a.cnt_far[a.nb] = 0;
+        a.cnt_near[a.nb] = 0;
+        a.cnt_short[a.nb] = 0;
+    }
+    if (b >= a.nb) return;
+    const int bi = b % a.bx, bj = (b / a.bx) % a.by, bk = b / (a.bx * a.by);
+    const int i0 = bi * a.B, j0 = bj * a.B, k0 = bk * a.B;
+    const int i1 = min(i0 + a.B, a.nx), j1 = min(j0 + a.B, a.ny), k1 = min(k0 + a.B, a.nz);
+    const double bl[3] = {i0 * a.h[0], j0 * a.h[1], k0 * a.h[2]};
+    const double bh[3] = {(i1 - 1) * a.h[0], (j1 - 1) * a.h[1], (k1 - 1) * a.h[2]};
+    double cb[3], rb2 = 0;
+    for (int k = 0; k < 3; ++k) {
+        cb[k] = 0.5 * (bl[k] + bh[k]);
+        rb2 += 0.25 * (bh[k] - bl[k]) * (bh[k] - bl[k]);
+    }
+    const double rb = sqrt(rb2);
+    const double npts = (double)(i1 - i0) * (j1 - j0) * (k1 - k0);
+    const double rs2 = a.rshort * a.rshort;
+    uint32_t nf = 0, nn = 0, ns = 0;
+    uint32_t of = 0, on = 0, os = 0;
+    if (a.fill) {
+        of = a.off_far[b];
+        on = a.off_near[b];
+        os = a.off_short[b];
+    }
+    unsigned long long wf = 0, wn = 0, ws = 0;
+    int stack[kStack];
+    int sp = 0;
+    stack[sp++] = 0;
+    while (sp > 0) {
+        const int node = stack[--sp];
+        const double *c = a.centre + 4 * node;
+        const double dx = c[0] - cb[0], dy = c[1] - cb[1], dz = c[2] - cb[2];
+        const double R = sqrt(dx * dx + dy * dy + dz * dz);
+        const int cnt = a.end[node] - a.begin[node];
+        if (cnt > a.np && rb + c[3] < a.theta * R) {
+            if (a.fill) a.far[of + nf] = node;
+            ++nf;
+            wf += (unsigned long long)a.np;
+            // leaves of this cluster that reach the batch's short range
+            if (a.rshort > 0 && box_gap2(bl, bh, a.box + 6 * node) < rs2) {
+                int st2[kStack];
+                int sp2 = 0;
+                st2[sp2++] = node;
+                while (sp2 > 0) {
+                    const int m = st2[--sp2];
+                    if (box_gap2(bl, bh, a.box + 6 * m) >= rs2) continue;
+                    if (a.nchild[m] == 0) {
+                        if (a.fill) a.shrt[os + ns] = m;
+                        ++ns;
+                        ws += (unsigned long long)(a.end[m] - a.begin[m]);
+                    } else {
+                        for (int ch = a.child0[m] + a.nchild[m] - 1; ch >= a.child0[m]; --ch)
+                            if (sp2 < kStack) st2[sp2++] = ch;
+                    }
+                }
+            }
+        } else if (a.nchild[node] == 0) {
+            if (a.fill) a.near_l[on + nn] = node;
+            ++nn;
+            wn += (unsigned long long)cnt;
+        } else {
+            for (int ch = a.child0[node] + a.nchild[node] - 1; ch >= a.child0[node]; --ch)
+                if (sp < kStack) stack[sp++] = ch;
+        }
+    }
+    if (!a.fill) {
+        a.cnt_far[b] = nf;
+        a.cnt_near[b] = nn;
+        a.cnt_short[b] = ns;
+        atomicAdd(&a.work[0], (unsigned long long)(wf * npts));
+        atomicAdd(&a.work[1], (unsigned long long)(wn * npts));
+        atomicAdd(&a.work[2], (unsigned long long)(ws * npts));
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+
+}  // namespace
+
+// ------------------------------------------------------------ drivers
+
+int build_source_tree(const TreeCallArgs &a, Workspace &ws, TreeDev &t, rism_stats &st,
+                      hipStream_t s)
+{
+    const int n = (int)a.solute->n;
+    const int leaf = a.opts->leaf_size;
+    const int stride_f4 = (int)(rec32_bytes_of(a.sp.ns_pad) / sizeof(float4));
+    const float4 *rec = static_cast<const float4 *>(a.rec32);
+    t.n_atoms = n;
+    // node capacity: at most 8 * floor(n / (leaf + 1)) nodes per level below
+    // the root (parents are disjoint and hold more than `leaf` atoms)
+    long cap = 1;
+    long split_max = (long)n / (leaf + 1);
+    for (int l = 1; l <= kMortonBits; ++l) {
+        long p8 = 1;
+        for (int k = 0; k < l && p8 < (1L << 40); ++k) p8 *= 8;
+        cap += std::min(p8, 8 * split_max);
+    }
+    t.cap_nodes = (int)std::min<long>(cap, 1L << 30);
+    const int nparts = 64;
+    double *part = ws.get<double>(6 * nparts);
+    double *bbox = ws.get<double>(6);
+    uint32_t *k0 = ws.get<uint32_t>(n), *k1 = ws.get<uint32_t>(n);
+    int *v0 = ws.get<int>(n), *v1 = ws.get<int>(n);
+    const int nrs = (n + kRsTile - 1) / kRsTile;
+    uint32_t *hist = ws.get<uint32_t>((size_t)256 * nrs);
+    t.n_nodes = ws.get<int>(1);
+    t.level_start = ws.get<int>(kMortonBits + 2);
+    int *flags = ws.get<int>(2);
+    t.begin = ws.get<int>(t.cap_nodes);
+    t.end = ws.get<int>(t.cap_nodes);
+    t.child0 = ws.get<int>(t.cap_nodes);
+    t.nchild = ws.get<int>(t.cap_nodes);
+    t.level = ws.get<int>(t.cap_nodes);
+    t.box = ws.get<double>((size_t)6 * t.cap_nodes);
+    t.centre = ws.get<double>((size_t)4 * t.cap_nodes);
+    uint32_t *cnt = ws.get<uint32_t>(t.cap_nodes);
+    uint32_t *total = ws.get<uint32_t>(1);
+    t.sorted_rec = ws.alloc(rec32_bytes_of(a.sp.ns_pad) * a.npad);
+    if (ws.status()) return ws.status();
+
+    const int nb = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_bbox_partial, nparts, kBlock, 0, s, rec, stride_f4, n, part);
+    hipLaunchKernelGGL(k_bbox_final, 1, 1, 0, s, part, nparts, bbox);
+    hipLaunchKernelGGL(k_morton, nb, kBlock, 0, s, rec, stride_f4, n, bbox, k0, v0);
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_rs_hist, nrs, kBlock, 0, s, k0, n, shift, nrs, hist);
+        hipLaunchKernelGGL(k_scan_excl, 1, 1024, 0, s, hist, 256 * nrs, (const int *)nullptr,
+                           (uint32_t *)nullptr);
+        hipLaunchKernelGGL(k_rs_scatter, nrs, kBlock, 0, s, k0, v0, k1, v1, n, shift, nrs, hist);
+        std::swap(k0, k1);
+        std::swap(v0, v1);
+    }
+    t.perm = v0;
+    hipLaunchKernelGGL(k_tree_root, 1, 1, 0, s, n, t.begin, t.end, t.level, t.level_start,
+                       t.n_nodes, flags);
+    const int gb = 256;
+    for (int lvl = 0; lvl < kMortonBits; ++lvl) {
+        hipLaunchKernelGGL(k_split_count, gb, kBlock, 0, s, k0, t.begin, t.end, t.level_start, lvl,
+                           leaf, cnt);
+        // scan the split counts of this level's nodes (count read on device)
+        hipLaunchKernelGGL(k_level_count, 1, 1, 0, s, t.level_start, lvl, flags + 1);
+        hipLaunchKernelGGL(k_scan_excl, 1, 1024, 0, s, cnt, 0, (const int *)(flags + 1), total);
+        hipLaunchKernelGGL(k_split_write, gb, kBlock, 0, s, k0, t.begin, t.end, t.level, t.child0,
+                           t.nchild, t.level_start, lvl, leaf, cnt, total, t.cap_nodes, t.n_nodes,
+                           flags);
+    }
+    RISM_HIP(hipGetLastError());
+    switch (a.sp.ns_pad) {
+    case 1: hipLaunchKernelGGL(k_permute<1>, (int)((a.npad + kBlock - 1) / kBlock), kBlock, 0, s, (const AtomF32<1> *)a.rec32, t.perm, n, (int)a.npad, (AtomF32<1> *)t.sorted_rec); break;
+    case 2: hipLaunchKernelGGL(k_permute<2>, (int)((a.npad + kBlock - 1) / kBlock), kBlock, 0, s, (const AtomF32<2> *)a.rec32, t.perm, n, (int)a.npad, (AtomF32<2> *)t.sorted_rec); break;
+    case 4: hipLaunchKernelGGL(k_permute<4>, (int)((a.npad + kBlock - 1) / kBlock), kBlock, 0, s, (const AtomF32<4> *)a.rec32, t.perm, n, (int)a.npad, (AtomF32<4> *)t.sorted_rec); break;
+    default: hipLaunchKernelGGL(k_permute<8>, (int)((a.npad + kBlock - 1) / kBlock), kBlock, 0, s, (const AtomF32<8> *)a.rec32, t.perm, n, (int)a.npad, (AtomF32<8> *)t.sorted_rec); break;
+    }
+    hipLaunchKernelGGL(k_node_box, 1024, kBlock, 0, s, (const float4 *)t.sorted_rec, stride_f4,
+                       t.begin, t.end, t.n_nodes, t.box, t.centre);
+    RISM_HIP(hipGetLastError());
+    (void)st;
+    return RISM_OK;
+}
+
+int build_proxies(const TreeDev &t, int degree, Workspace &ws, ProxyDev &p, int n_nodes,
+                  hipStream_t s, int stride_f4, int max_level)
+{
+    p.degree = degree;
+    const int n1 = degree + 1;
+    p.np = n1 * n1 * n1;
+    p.q = ws.get<double>((size_t)n_nodes * p.np);
+    p.pbox = ws.get<double>((size_t)n_nodes * 6);
+    if (ws.status()) return ws.status();
+    const size_t shm = (3 * (size_t)kTile * n1 + kTile + 3 * (size_t)p.np) * sizeof(double);
+    int dev = 0, lds_max = 0;
+    RISM_HIP(hipGetDevice(&dev));
+    RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if (shm > (size_t)lds_max) {
+        set_error("treecode: degree too high for the LDS of this device");
+        return RISM_E_UNSUPPORTED;
+    }
+    for (int lvl = max_level; lvl >= 0; --lvl)
+        hipLaunchKernelGGL(k_upward_level, 1024, kBlock, shm, s, (const float4 *)t.sorted_rec,
+                           stride_f4, t.begin, t.end, t.child0, t.nchild, t.box, t.level_start,
+                           lvl, degree, p.q, p.pbox);
+    RISM_HIP(hipGetLastError());
+    return RISM_OK;
+}
+
+int build_lists(const TreeCallArgs &a, const TreeDev &t, int n_nodes, double r_short,
+                Workspace &ws, ListsDev &l, rism_stats &st, hipStream_t s)
+{
+    const int B = a.opts->batch_edge;
+    const int n1 = a.opts->degree + 1;
+    ListArgs la{};
+    la.nx = a.g.nx;
+    la.ny = a.g.ny;
+    la.nz = a.g.nz;
+    la.B = B;
+    la.bx = (a.g.nx + B - 1) / B;
+    la.by = (a.g.ny + B - 1) / B;
+    la.bz = (a.g.nz + B - 1) / B;
+    la.nb = la.bx * la.by * la.bz;
+    for (int k = 0; k < 3; ++k) la.h[k] = a.g.h[k];
+    la.theta = a.opts->theta;
+    la.rshort = r_short;
+    la.np = n1 * n1 * n1;
+    la.begin = t.begin;
+    la.end = t.end;
+    la.child0 = t.child0;
+    la.nchild = t.nchild;
+    la.box = t.box;
+    la.centre = t.centre;
+    la.n_nodes = t.n_nodes;
+    l.nb = la.nb;
+    l.bx = la.bx;
+    l.by = la.by;
+    l.bz = la.bz;
+    uint32_t *cf = ws.get<uint32_t>(la.nb + 1), *cn = ws.get<uint32_t>(la.nb + 1),
+             *cs = ws.get<uint32_t>(la.nb + 1);
+    uint32_t *tot = ws.get<uint32_t>(4);
+    la.work = ws.get<unsigned long long>(4);
+    if (ws.status()) return ws.status();
+    la.cnt_far = cf;
+    la.cnt_near = cn;
+    la.cnt_short = cs;
+    const int grid = (la.nb + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_zero_u64, 1, 64, 0, s, la.work, 4);
+    la.fill = 0;
+    {
+        PhaseTimer pt(a.opts->flags & RISM_FLAG_PHASE_EVENTS, RISM_PHASE_LISTS, s);
+        hipLaunchKernelGGL(k_lists, grid, kBlock, 0, s, la);
+        hipLaunchKernelGGL(k_scan_excl, 1, 1024, 0, s, cf, la.nb + 1, (const int *)nullptr, tot + 0);
+        hipLaunchKernelGGL(k_scan_excl, 1, 1024, 0, s, cn, la.nb + 1, (const int *)nullptr, tot + 1);
+        hipLaunchKernelGGL(k_scan_excl, 1, 1024, 0, s, cs, la.nb + 1, (const int *)nullptr, tot + 2);
+    }
+    RISM_HIP(hipGetLastError());
+    uint32_t htot[4];
+    unsigned long long hwork[4];
+    RISM_HIP(hipMemcpyAsync(htot, tot, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    RISM_HIP(hipMemcpyAsync(hwork, la.work, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    RISM_HIP(hipStreamSynchronize(s));
+    l.far_off = (int *)cf;
+    l.near_off = (int *)cn;
+    l.short_off = (int *)cs;
+    l.far = ws.get<int>(htot[0] + 1);
+    l.near = ws.get<int>(htot[1] + 1);
+    l.shrt = ws.get<int>(htot[2] + 1);
+    if (ws.status()) return ws.status();
+    la.off_far = cf;
+    la.off_near = cn;
+    la.off_short = cs;
+    la.far = l.far;
+    la.near_l = l.near;
+    la.shrt = l.shrt;
+    la.fill = 1;
+    {
+        PhaseTimer pt(a.opts->flags & RISM_FLAG_PHASE_EVENTS, RISM_PHASE_LISTS, s);
+        hipLaunchKernelGGL(k_lists, grid, kBlock, 0, s, la);
+    }
+    RISM_HIP(hipGetLastError());
+    st.pairs_far = (double)hwork[0];
+    st.pairs_direct = (double)hwork[1];
+    st.pairs_short = (double)hwork[2];
+    st.n_batches = la.nb;
+    (void)n_nodes;
+    return RISM_OK;
+}
+
+int tree_forward(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStream_t s)
+{
+    const bool ev = a.opts->flags & RISM_FLAG_PHASE_EVENTS;
+    TreeDev t{};
+    int rc;
+    {
+        PhaseTimer pt(ev, RISM_PHASE_TREE_BUILD, s);
+        rc = build_source_tree(a, ws, t, st, s);
+    }
+    if (rc) return rc;
+    int hn[2 + kMortonBits + 2];
+    RISM_HIP(hipMemcpyAsync(hn, t.n_nodes, sizeof(int), hipMemcpyDeviceToHost, s));
+    RISM_HIP(hipMemcpyAsync(hn + 2, t.level_start, (kMortonBits + 2) * sizeof(int),
+                            hipMemcpyDeviceToHost, s));
+    RISM_HIP(hipStreamSynchronize(s));
+    const int n_nodes = hn[0];
+    int hflag = 0;
+    (void)hflag;
+    int max_level = 0;
+    for (int l = 0; l <= kMortonBits; ++l)
+        if (hn[2 + l + 1] > hn[2 + l]) max_level = l;
+    st.n_nodes = n_nodes;
+    if (n_nodes > t.cap_nodes) {
+        set_error("treecode: node capacity exceeded");
+        return RISM_E_NOMEM;
+    }
+    const int stride_f4 = (int)(rec32_bytes_of(a.sp.ns_pad) / sizeof(float4));
+    ProxyDev p{};
+    {
+        PhaseTimer pt(ev, RISM_PHASE_UPWARD, s);
+        rc = build_proxies(t, a.opts->degree, ws, p, n_nodes, s, stride_f4, max_level);
+    }
+    if (rc) return rc;
+    // short-range radius: the LJ cut-off (largest per-pair radius) and R_s
+    double rshort = a.asym_on ? std::sqrt(a.asym.rs2) : 0.0;
+    if (a.lj_mode == LJ_CUT) rshort = std::max(rshort, a.rmax_short);
+    ListsDev l{};
+    rc = build_lists(a, t, n_nodes, rshort, ws, l, st, s);
+    if (rc) return rc;
+    TreeEvalArgs ea{};
+    ea.g = a.g;
+    ea.out = a.out;
+    ea.asym = a.asym;
+    ea.rec = t.sorted_rec;
+    ea.begin = t.begin;
+    ea.end = t.end;
+    ea.pq = p.q;
+    ea.pbox = p.pbox;
+    ea.degree = p.degree;
+    ea.np = p.np;
+    ea.l = l;
+    ea.rshort2 = (float)(rshort * rshort);
+    {
+        PhaseTimer pt(ev, RISM_PHASE_EVAL, s);
+        rc = launch_tree_eval(a.sp, a.lj_mode, a.asym_on, a.opts->batch_edge, ea, s);
+    }
+    return rc;
+}
+
+}  // namespace rism
+
+namespace rism {
 
 int tree_forward_cp(const TreeCallArgs &, Workspace &, rism_stats &, hipStream_t)
 {
-    set_error("RISM_TREECODE_CP: not built yet");
+    set_error("RISM_TREECODE_CP: not available in this build");
     return RISM_E_UNSUPPORTED;
 }
 
 int adjoint_tree(const AdjointArgs &, Workspace &, rism_stats &, hipStream_t)
 {
-    set_error("RISM_TREECODE backward: not built yet");
+    set_error("RISM_TREECODE backward: not available in this build");
     return RISM_E_UNSUPPORTED;
 }
 

@@ -10,7 +10,7 @@
 #include <utility>
 #include <vector>
 
-#include "rism_internal.h"
+#include "pair.h"
 
 namespace rism {
 
@@ -273,8 +273,7 @@ static void prep_asym(double eta, double kappa, double beta, double diel, double
 
 static size_t rec_bytes(int ns_pad, bool f64)
 {
-    size_t nf = 3 * (size_t)ns_pad;
-    return f64 ? (4 + nf) * sizeof(double) : (8 + nf) * sizeof(float);
+    return f64 ? rec64_bytes_of(ns_pad) : rec32_bytes_of(ns_pad);
 }
 
 // Stages the atoms into FP32 and/or FP64 records, optionally the cut-off
@@ -282,7 +281,7 @@ static size_t rec_bytes(int ns_pad, bool f64)
 // caller opted out.
 static int stage_atoms(const rism_solute *so, const Prep &p, const rism_opts *op, bool want32,
                        bool want64, bool check_eps, Workspace &ws, void **rec32, void **rec64,
-                       double **rcut, hipStream_t s)
+                       double **rcut, hipStream_t s, double *max_rcut = nullptr)
 {
     StageArgs a{};
     a.xyz = so->xyz;
@@ -296,12 +295,12 @@ static int stage_atoms(const rism_solute *so, const Prep &p, const rism_opts *op
     a.lj_tol = op->lj_tol;
     a.lj_mode = p.lj_mode;
     a.check_eps = check_eps;
-    a.err_flags = ws.get<int>(2);
+    a.err_flags = ws.get<int>(4);
     a.rec32 = want32 ? ws.alloc(rec_bytes(p.sp.ns_pad, false) * p.npad) : nullptr;
     a.rec64 = want64 ? ws.alloc(rec_bytes(p.sp.ns_pad, true) * p.npad) : nullptr;
     a.rcut = rcut ? ws.get<double>((size_t)p.sp.ns * (so->n > 0 ? so->n : 1)) : nullptr;
     if (ws.status() != RISM_OK) return ws.status();
-    hipLaunchKernelGGL(k_fill_i32, 1, 64, 0, s, a.err_flags, 2, 0);
+    hipLaunchKernelGGL(k_fill_i32, 1, 64, 0, s, a.err_flags, 4, 0);
     RISM_HIP(hipGetLastError());
     int rc;
     {
@@ -313,12 +312,17 @@ static int stage_atoms(const rism_solute *so, const Prep &p, const rism_opts *op
     if (need_check && so->n > 0) {
         int *h = pinned_flags();
         if (!h) return fail(RISM_E_HIP, "pinned host buffer allocation failed");
-        RISM_HIP(hipMemcpyAsync(h, a.err_flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        RISM_HIP(hipMemcpyAsync(h, a.err_flags, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
         RISM_HIP(hipStreamSynchronize(s));
         if (h[0]) return fail(RISM_E_INVALID, "non-finite atom input or negative sigma/eps");
         if (h[1])
             return fail(RISM_E_INVALID, check_eps ? "dL/deps needs eps_a > 0 for every atom"
                                                   : "lj_tol must be below eps_ga of every pair");
+        if (max_rcut) {
+            float r2;
+            std::memcpy(&r2, &h[2], sizeof(float));
+            *max_rcut = std::sqrt((double)r2);
+        }
     }
     if (rec32) *rec32 = a.rec32;
     if (rec64) *rec64 = a.rec64;
@@ -388,8 +392,9 @@ static int forward(const rism_solute *so, const rism_sites *si, const rism_grid 
     void *rec32 = nullptr, *rec64 = nullptr;
     double *rcut = nullptr;
     bool want_rcut = lj_tail && p.lj_mode == LJ_CUT;
+    double max_rcut = op->lj_cutoff;
     rc = stage_atoms(so, p, op, !f64path, f64path, false, ws, &rec32, &rec64,
-                     want_rcut ? &rcut : nullptr, s);
+                     want_rcut ? &rcut : nullptr, s, &max_rcut);
     if (rc) return rc;
 
     if (u || c || h) {
@@ -424,18 +429,9 @@ static int forward(const rism_solute *so, const rism_sites *si, const rism_grid 
             ta.asym_on = asym_on;
             ta.rec32 = rec32;
             ta.npad = p.npad;
-            double rmax = 0.0;
-            if (asym_on) rmax = std::sqrt(p.asym.rs2);
-            if (da.lj_mode == LJ_CUT) {
-                double rl = op->lj_cutoff;
-                if (op->lj_tol > 0) {
-                    // largest per-pair radius: bounded by the smallest eps_ga;
-                    // the tree code computes the exact maximum on device.
-                    rl = -1.0;
-                }
-                rmax = rl < 0 ? -1.0 : std::max(rmax, rl);
-            }
-            ta.rmax_short = rmax;
+            // largest LJ cut-off radius (read back with the device checks,
+            // which lj_tol > 0 always runs)
+            ta.rmax_short = op->lj_tol > 0 ? max_rcut : op->lj_cutoff;
             rc = op->method == RISM_TREECODE ? tree_forward(ta, ws, st, s)
                                              : tree_forward_cp(ta, ws, st, s);
         }

@@ -135,7 +135,8 @@ struct StageArgs {
     double lj_tol;      // > 0 per-pair radius from tolerance (overrides)
     int lj_mode;        // LjMode
     int check_eps;      // flag eps_a <= 0 as an error (backward dL/deps)
-    int *err_flags;     // device int[2]: [0] non-finite input, [1] tol >= eps_ga / eps <= 0
+    int *err_flags;     // device int[3]: [0] non-finite input, [1] tol >= eps_ga / eps <= 0,
+                        // [2] bits of the largest squared cut-off radius (float)
     void *rec32;        // AtomF32<ns_pad>[npad] or null
     void *rec64;        // AtomF64<ns_pad>[npad] or null
     double *rcut;       // [ns][n] FP64 cut-off radii or null
