@@ -70,6 +70,8 @@ extern "C" {
                                           of atom inputs (saves one stream sync) */
 #define RISM_FLAG_PHASE_EVENTS 2u     /* record HIP events around every kernel
                                           phase (read with rism_phase_times) */
+#define RISM_FLAG_STATS 4u            /* count evaluated interactions of the
+                                          treecodes exactly (one extra sync) */
 
 /* Kernel phases reported by rism_phase_times. */
 #define RISM_PHASE_STAGE 0        /* mixing, cut-offs, FP32/FP64 atom records */

@@ -30,6 +30,7 @@ METHODS = {"direct_f64": 0, "direct_f32c": 1, "treecode": 2, "treecode_cp": 3}
 DTYPES = {"f32": 0, "f64": 1}
 FLAG_NO_DEVICE_CHECK = 1
 FLAG_PHASE_EVENTS = 2
+FLAG_STATS = 4
 MAX_SITES = 8
 PHASES = ["stage", "direct_f64", "direct_f32", "tree_build", "upward", "lists", "eval",
           "downward", "adjoint", "adjoint_reduce", "other"]
@@ -119,6 +120,7 @@ class Opts:
     batch_edge: int = 8
     device_check: bool = True
     phase_events: bool = False
+    stats: bool = False
     max_workspace_bytes: int = 0
 
     def to_c(self) -> OptsC:
@@ -134,7 +136,7 @@ class Opts:
         o.leaf_size = self.leaf_size
         o.batch_edge = self.batch_edge
         o.flags = (0 if self.device_check else FLAG_NO_DEVICE_CHECK) | \
-            (FLAG_PHASE_EVENTS if self.phase_events else 0)
+            (FLAG_PHASE_EVENTS if self.phase_events else 0) | (FLAG_STATS if self.stats else 0)
         o.max_workspace_bytes = self.max_workspace_bytes
         return o
 

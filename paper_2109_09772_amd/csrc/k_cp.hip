@@ -1,0 +1,915 @@
+// Cluster-particle treecode: the orientation of the paper (Sec. 2.3), where
+// the tree is built on the grid targets, written with barycentric Chebyshev
+// interpolation on the target clusters instead of Taylor expansions.
+//
+// Target tree: the implicit octree of the grid.  Level 0 are blocks of B^3
+// points (leaves); a level-l cluster is a block of (B 2^l)^3 points, clipped to
+// the grid; the top level T is a single cluster covering the grid.
+//
+// For an atom y and the chain of clusters C_T ... C_1 that contain a target
+// leaf, the atom is assigned to the coarsest level l at which it is well
+// separated, r_{C_l} < theta |y - c_{C_l}| (the paper's MAC r/R < theta), and
+// to the leaf's direct sum if it is well separated at no level >= 1
+// (Eq. 10).  Clusters at level >= 1 hold (n+1)^3 proxy values: the far field
+// of their assigned atoms evaluated at the Chebyshev points of the cluster
+// box.  The proxies are pushed down level by level (each child's proxy
+// values += the parent's interpolant evaluated at the child's proxy points),
+// and finally interpolated to the grid points of every leaf.  Level 0 sums
+// its assigned atoms directly, since a B^3 leaf has fewer points than proxies.
+//
+// Far field: 1/d (Coulomb, c^lr) and e^{-kappa d}/d (h^lr), FP32 pair
+// arithmetic, FP64 accumulation per proxy and in the interpolation passes.
+// Short range (LJ within its cut-off, smeared-kernel corrections within R_s)
+// is evaluated per leaf for every atom within reach, whatever level the atom
+// was assigned to.
+#include <algorithm>
+#include <cmath>
+
+#include "cheb.h"
+#include "pair.h"
+#include "tree.h"
+
+namespace rism {
+
+namespace {
+
+constexpr int kCpMaxLev = 20;
+constexpr int kCpChunkLeaves = 16;   // candidate source leaves per far work item
+constexpr int kCpProxPass = 1024;    // proxies per pass of the far kernel (4 per thread)
+constexpr int kCpMaxCand = 2048;     // candidate leaves staged per round of the leaf kernel
+
+struct CpLevels {
+    int B, T, nx, ny, nz;
+    double h[3];
+    double theta;
+    int cx[kCpMaxLev + 1], cy[kCpMaxLev + 1], cz[kCpMaxLev + 1];
+    int off[kCpMaxLev + 2];   // first id of level l (l = 1..T); off[T + 1] = clusters
+};
+
+__host__ __device__ inline void cp_box(const CpLevels &L, int lvl, int I, int J, int K,
+                                       double lo[3], double hi[3])
+{
+    const int e = L.B << lvl;
+    const int il = I * e, jl = J * e, kl = K * e;
+    const int ih = (il + e < L.nx ? il + e : L.nx) - 1;
+    const int jh = (jl + e < L.ny ? jl + e : L.ny) - 1;
+    const int kh = (kl + e < L.nz ? kl + e : L.nz) - 1;
+    lo[0] = il * L.h[0];
+    lo[1] = jl * L.h[1];
+    lo[2] = kl * L.h[2];
+    hi[0] = ih * L.h[0];
+    hi[1] = jh * L.h[1];
+    hi[2] = kh * L.h[2];
+}
+
+__host__ __device__ inline void cp_centre(const CpLevels &L, int lvl, int I, int J, int K,
+                                          double c[3], double &r)
+{
+    double lo[3], hi[3];
+    cp_box(L, lvl, I, J, K, lo, hi);
+    double r2 = 0;
+    for (int k = 0; k < 3; ++k) {
+        c[k] = 0.5 * (lo[k] + hi[k]);
+        r2 += 0.25 * (hi[k] - lo[k]) * (hi[k] - lo[k]);
+    }
+    r = sqrt(r2);
+}
+
+// Proxy box of a cluster: its box, widened to half a spacing around a single
+// grid plane so that no axis is degenerate.
+__device__ inline void cp_proxy_box(const CpLevels &L, int lvl, int I, int J, int K, double pb[6])
+{
+    double lo[3], hi[3];
+    cp_box(L, lvl, I, J, K, lo, hi);
+    for (int k = 0; k < 3; ++k) {
+        if (hi[k] - lo[k] < 0.25 * L.h[k]) {
+            lo[k] -= 0.5 * L.h[k];
+            hi[k] += 0.5 * L.h[k];
+        }
+        pb[k] = lo[k];
+        pb[3 + k] = hi[k];
+    }
+}
+
+__device__ inline void cp_decode(const CpLevels &L, int id, int &lvl, int &I, int &J, int &K)
+{
+    lvl = 1;
+    while (lvl < L.T && id >= L.off[lvl + 1]) ++lvl;
+    int r = id - L.off[lvl];
+    I = r % L.cx[lvl];
+    r /= L.cx[lvl];
+    J = r % L.cy[lvl];
+    K = r / L.cy[lvl];
+}
+
+__device__ inline int cp_id(const CpLevels &L, int lvl, int I, int J, int K)
+{
+    return L.off[lvl] + (K * L.cy[lvl] + J) * L.cx[lvl] + I;
+}
+
+__device__ inline bool cp_mac(const CpLevels &L, int lvl, int I, int J, int K, const double y[3])
+{
+    double c[3], r;
+    cp_centre(L, lvl, I, J, K, c, r);
+    const double dx = y[0] - c[0], dy = y[1] - c[1], dz = y[2] - c[2];
+    return r * r < L.theta * L.theta * (dx * dx + dy * dy + dz * dz);
+}
+
+// Coarsest level in [stop, T] along the chain of the level-0 block (I0, J0,
+// K0) at which y is well separated; 0 if none.
+__device__ inline int cp_accept_level(const CpLevels &L, int I0, int J0, int K0, const double y[3],
+                                      int stop)
+{
+    for (int lvl = L.T; lvl >= stop; --lvl)
+        if (cp_mac(L, lvl, I0 >> lvl, J0 >> lvl, K0 >> lvl, y)) return lvl;
+    return 0;
+}
+
+__device__ __forceinline__ double gap2_point_box(const double c[3], const double *box)
+{
+    double s = 0;
+    for (int k = 0; k < 3; ++k) {
+        double g = fmax(0.0, fmax(box[k] - c[k], c[k] - box[3 + k]));
+        s += g * g;
+    }
+    return s;
+}
+
+__device__ __forceinline__ double gap2_box_box(const double lo[3], const double hi[3],
+                                               const double *box)
+{
+    double s = 0;
+    for (int k = 0; k < 3; ++k) {
+        double g = fmax(0.0, fmax(box[k] - hi[k], lo[k] - box[3 + k]));
+        s += g * g;
+    }
+    return s;
+}
+
+__device__ __forceinline__ void atom_pos(const float4 *rec, int stride_f4, int i, double y[3])
+{
+    const float4 a = rec[(size_t)i * stride_f4];
+    const float4 b = rec[(size_t)i * stride_f4 + 1];
+    y[0] = (double)a.x + b.x;
+    y[1] = (double)a.y + b.y;
+    y[2] = (double)a.z + b.z;
+}
+
+// ----------------------------------------------------------------- scans
+
+// Exclusive scan of a[0..n) in place by one 1024-thread workgroup; the sum is
+// written to *total.
+__global__ __launch_bounds__(1024) void k_scan_excl_u32(uint32_t *a, int n, uint32_t *total)
+{
+    __shared__ uint32_t s[1024];
+    const int t = threadIdx.x;
+    const int per = (n + 1023) / 1024;
+    const int lo = t * per < n ? t * per : n;
+    const int hi = lo + per < n ? lo + per : n;
+    uint32_t sum = 0;
+    for (int i = lo; i < hi; ++i) sum += a[i];
+    s[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = t >= off ? s[t - off] : 0u;
+        __syncthreads();
+        s[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = s[t] - sum;
+    for (int i = lo; i < hi; ++i) {
+        uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    if (t == 1023) *total = s[1023];
+}
+
+// ----------------------------------------------------------------- queries
+
+// Candidate source leaves of every target query.
+//  mode 0 (clusters, levels 1..T): leaves reaching the ball (c_P, r_P/theta)
+//         of the parent P, or every leaf for the top cluster;
+//  mode 1 (level-0 blocks): leaves reaching the ball of the level-1 ancestor
+//         or the short range of the block.
+struct CpQueryArgs {
+    CpLevels L;
+    int mode, nq;
+    double rshort;
+    const int *begin, *end, *child0, *nchild;
+    const double *box;
+    uint32_t *cnt, *items;     // count pass (nq + 1 entries each)
+    const uint32_t *off;       // fill pass
+    int *list;
+    int fill;
+};
+
+constexpr int kQStack = 128;
+
+__global__ __launch_bounds__(kBlock) void k_cp_query(CpQueryArgs a)
+{
+    const int q = blockIdx.x * kBlock + threadIdx.x;
+    if (!a.fill && q == 0) {
+        a.cnt[a.nq] = 0;
+        if (a.items) a.items[a.nq] = 0;
+    }
+    if (q >= a.nq) return;
+    const CpLevels &L = a.L;
+    bool all = false, has_ball = false, has_box = false;
+    double bc[3] = {0, 0, 0}, br2 = 0, blo[3] = {0, 0, 0}, bhi[3] = {0, 0, 0};
+    if (a.mode == 0) {
+        int lvl, I, J, K;
+        cp_decode(L, q, lvl, I, J, K);
+        if (lvl == L.T) {
+            all = true;
+        } else {
+            double r;
+            cp_centre(L, lvl + 1, I >> 1, J >> 1, K >> 1, bc, r);
+            br2 = (r / L.theta) * (r / L.theta);
+            has_ball = true;
+        }
+    } else {
+        const int I = q % L.cx[0], J = (q / L.cx[0]) % L.cy[0], K = q / (L.cx[0] * L.cy[0]);
+        if (L.T == 0) {
+            all = true;
+        } else {
+            double r;
+            cp_centre(L, 1, I >> 1, J >> 1, K >> 1, bc, r);
+            br2 = (r / L.theta) * (r / L.theta);
+            has_ball = true;
+        }
+        if (a.rshort > 0) {
+            cp_box(L, 0, I, J, K, blo, bhi);
+            has_box = true;
+        }
+    }
+    const double rs2 = a.rshort * a.rshort;
+    uint32_t n = 0;
+    const uint32_t o = a.fill ? a.off[q] : 0u;
+    int stack[kQStack];
+    int sp = 0;
+    stack[sp++] = 0;
+    while (sp > 0) {
+        const int node = stack[--sp];
+        const double *nb = a.box + 6 * node;
+        bool hit = all;
+        if (!hit && has_ball) hit = gap2_point_box(bc, nb) < br2;
+        if (!hit && has_box) hit = gap2_box_box(blo, bhi, nb) < rs2;
+        if (!hit) continue;
+        if (a.nchild[node] == 0) {
+            if (a.fill) a.list[o + n] = node;
+            ++n;
+        } else {
+            for (int ch = a.child0[node] + a.nchild[node] - 1; ch >= a.child0[node]; --ch)
+                if (sp < kQStack) stack[sp++] = ch;
+        }
+    }
+    if (!a.fill) {
+        a.cnt[q] = n;
+        if (a.items) a.items[q] = (n + kCpChunkLeaves - 1) / kCpChunkLeaves;
+    }
+}
+
+// Work items of the far kernel: (cluster, first candidate, last candidate).
+__global__ __launch_bounds__(kBlock) void k_cp_items(int nq, const uint32_t *cand_off,
+                                                     const uint32_t *item_off, int *it_cl,
+                                                     int *it_c0, int *it_c1)
+{
+    const int q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= nq) return;
+    const int c0 = (int)cand_off[q], c1 = (int)cand_off[q + 1];
+    int it = (int)item_off[q];
+    for (int c = c0; c < c1; c += kCpChunkLeaves, ++it) {
+        it_cl[it] = q;
+        it_c0[it] = c;
+        it_c1[it] = c + kCpChunkLeaves < c1 ? c + kCpChunkLeaves : c1;
+    }
+}
+
+// ----------------------------------------------------------------- far
+
+struct CpFarArgs {
+    CpLevels L;
+    const int *it_cl, *it_c0, *it_c1;
+    const int *cand;
+    const int *begin, *end;
+    const float4 *rec;
+    int stride_f4;
+    int degree, np;
+    float yk;
+    double *part;   // [items][2][np]
+    unsigned long long *work;   // optional: (atom, proxy) pairs
+};
+
+// One workgroup per work item.  Each thread owns up to four proxies per pass;
+// the accepted atoms of one candidate leaf at a time are compacted (in atom
+// order) into LDS as (position relative to the cluster centre, charge) and
+// swept by every thread.
+template <bool ASYM>
+__global__ __launch_bounds__(kBlock) void k_cp_far(CpFarArgs a)
+{
+    __shared__ float4 stg[kBlock];
+    __shared__ int wcount[kBlock / 64];
+    const int item = blockIdx.x;
+    const int cl = a.it_cl[item];
+    int lvl, I, J, K;
+    cp_decode(a.L, cl, lvl, I, J, K);
+    double pb[6], cc[3], rr;
+    cp_proxy_box(a.L, lvl, I, J, K, pb);
+    cp_centre(a.L, lvl, I, J, K, cc, rr);
+    const int n1 = a.degree + 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k0 = 0; k0 < a.np; k0 += kCpProxPass) {
+        float px[4], py[4], pz[4];
+        double aC[4], aY[4];
+        float pC[4], pY[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = k0 + r * kBlock + threadIdx.x;
+            const int kk = k < a.np ? k : 0;
+            const int k1 = kk % n1, k2 = (kk / n1) % n1, k3 = kk / (n1 * n1);
+            px[r] = (float)(cheb_point(pb[0], pb[3], k1, a.degree) - cc[0]);
+            py[r] = (float)(cheb_point(pb[1], pb[4], k2, a.degree) - cc[1]);
+            pz[r] = (float)(cheb_point(pb[2], pb[5], k3, a.degree) - cc[2]);
+            aC[r] = aY[r] = 0.0;
+            pC[r] = pY[r] = 0.f;
+        }
+        int since_flush = 0;
+        int n_acc = 0;
+        for (int c = a.it_c0[item]; c < a.it_c1[item]; ++c) {
+            const int leaf = a.cand[c];
+            const int ab = a.begin[leaf], ae = a.end[leaf];
+            for (int t0 = ab; t0 < ae; t0 += kBlock) {
+                // filter: accepted at this cluster (coarsest well-separated level)
+                const int i = t0 + threadIdx.x;
+                bool acc = false;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (i < ae) {
+                    double y[3];
+                    atom_pos(a.rec, a.stride_f4, i, y);
+                    acc = cp_accept_level(a.L, I << lvl, J << lvl, K << lvl, y, lvl) == lvl;
+                    v.x = (float)(y[0] - cc[0]);
+                    v.y = (float)(y[1] - cc[1]);
+                    v.z = (float)(y[2] - cc[2]);
+                    v.w = a.rec[(size_t)i * a.stride_f4].w;
+                }
+                const uint64_t m = __ballot(acc);
+                const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+                const int pos = __popcll(m & lt);
+                __syncthreads();   // previous round's readers are done with stg
+                if (lane == 0) wcount[wave] = __popcll(m);
+                __syncthreads();
+                int base = 0, total = 0;
+                for (int w = 0; w < kBlock / 64; ++w) {
+                    if (w < wave) base += wcount[w];
+                    total += wcount[w];
+                }
+                if (acc) stg[base + pos] = v;
+                __syncthreads();
+                n_acc += total;
+                for (int s = 0; s < total; ++s) {
+                    const float4 at = stg[s];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float dx = px[r] - at.x, dy = py[r] - at.y, dz = pz[r] - at.z;
+                        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                        const float ri = __builtin_amdgcn_rsqf(d2);
+                        const float qr = at.w * ri;
+                        pC[r] += qr;
+                        if (ASYM) pY[r] = fmaf(qr, __builtin_amdgcn_exp2f(a.yk * (d2 * ri)), pY[r]);
+                    }
+                    if (++since_flush == 16) {
+                        since_flush = 0;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            aC[r] += (double)pC[r];
+                            aY[r] += (double)pY[r];
+                            pC[r] = pY[r] = 0.f;
+                        }
+                    }
+                }
+            }
+        }
+        if (a.work && threadIdx.x == 0 && k0 == 0)
+            atomicAdd(a.work, (unsigned long long)n_acc * (unsigned long long)a.np);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            aC[r] += (double)pC[r];
+            aY[r] += (double)pY[r];
+            const int k = k0 + r * kBlock + threadIdx.x;
+            if (k < a.np) {
+                a.part[((size_t)item * 2 + 0) * a.np + k] = aC[r];
+                a.part[((size_t)item * 2 + 1) * a.np + k] = aY[r];
+            }
+        }
+    }
+}
+
+// V[cl] = sum of the partials of its items, in item order.
+__global__ __launch_bounds__(kBlock) void k_cp_reduce(int nclusters, int np, const uint32_t *item_off,
+                                                      const double *part, double *V)
+{
+    const int cl = blockIdx.x;
+    if (cl >= nclusters) return;
+    const int i0 = (int)item_off[cl], i1 = (int)item_off[cl + 1];
+    for (int k = threadIdx.x; k < 2 * np; k += kBlock) {
+        double s = 0.0;
+        for (int it = i0; it < i1; ++it) s += part[(size_t)it * 2 * np + k];
+        V[(size_t)cl * 2 * np + k] = s;
+    }
+}
+
+// ----------------------------------------------------------------- downward
+
+// Children at level lvl: V[child] += (Mx (x) My (x) Mz) V[parent], with
+// M[k][m] = L^P_m(s^C_k): the parent's interpolant evaluated at the child's
+// proxy points, separably, in FP64.
+__global__ __launch_bounds__(kBlock) void k_cp_down(CpLevels L, int lvl, int degree, double *V)
+{
+    extern __shared__ double sm[];
+    const int n1 = degree + 1, np = n1 * n1 * n1;
+    double *M = sm;                 // [3][n1][n1]
+    double *src = M + 3 * n1 * n1;  // [np]
+    double *t1 = src + np;          // [np]
+    double *t2 = t1 + np;           // [np]
+    const int q = blockIdx.x;
+    const int I = q % L.cx[lvl], J = (q / L.cx[lvl]) % L.cy[lvl], K = q / (L.cx[lvl] * L.cy[lvl]);
+    const int id = cp_id(L, lvl, I, J, K);
+    const int pid = cp_id(L, lvl + 1, I >> 1, J >> 1, K >> 1);
+    double cb[6], pbx[6];
+    cp_proxy_box(L, lvl, I, J, K, cb);
+    cp_proxy_box(L, lvl + 1, I >> 1, J >> 1, K >> 1, pbx);
+    if (threadIdx.x < 3 * n1) {
+        const int ax = threadIdx.x / n1, k = threadIdx.x % n1;
+        double Lv[kMaxDeg + 1];
+        lagrange_all(cheb_point(cb[ax], cb[3 + ax], k, degree), pbx[ax], pbx[3 + ax], degree, Lv);
+        for (int m = 0; m < n1; ++m) M[(ax * n1 + k) * n1 + m] = Lv[m];
+    }
+    for (int comp = 0; comp < 2; ++comp) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < np; k += kBlock) src[k] = V[((size_t)pid * 2 + comp) * np + k];
+        __syncthreads();
+        // index (z, y, x) with x fastest; contract x, then y, then z
+        for (int k = threadIdx.x; k < np; k += kBlock) {
+            const int k1 = k % n1, rest = k / n1;
+            double s = 0;
+            for (int m = 0; m < n1; ++m) s += M[(0 * n1 + k1) * n1 + m] * src[rest * n1 + m];
+            t1[k] = s;
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < np; k += kBlock) {
+            const int k1 = k % n1, k2 = (k / n1) % n1, m3 = k / (n1 * n1);
+            double s = 0;
+            for (int m = 0; m < n1; ++m) s += M[(1 * n1 + k2) * n1 + m] * t1[(m3 * n1 + m) * n1 + k1];
+            t2[k] = s;
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < np; k += kBlock) {
+            const int k12 = k % (n1 * n1), k3 = k / (n1 * n1);
+            double s = 0;
+            for (int m = 0; m < n1; ++m) s += M[(2 * n1 + k3) * n1 + m] * t2[m * n1 * n1 + k12];
+            V[((size_t)id * 2 + comp) * np + k] += s;
+        }
+    }
+}
+
+// ----------------------------------------------------------------- leaves
+
+struct CpLeafArgs {
+    CpLevels L;
+    GridParams g;
+    OutParams out;
+    AsymParams asym;
+    const void *rec;
+    int stride_f4;
+    const int *begin, *end;
+    const uint32_t *cand_off;
+    const int *cand;
+    const double *V;       // proxy values of level >= 1 clusters
+    int degree, np;
+    double rshort;
+    unsigned long long *work;   // optional: [0] direct pairs, [1] short-range pairs
+};
+
+template <int B>
+struct LeafShape {
+    static constexpr int threads = B == 4 ? 64 : 256;
+    static constexpr int ppt = B == 4 ? 1 : 2;
+    static constexpr int passes = (B * B * B) / (threads * ppt);
+};
+
+// One workgroup per level-0 block: far field interpolated from the level-1
+// ancestor's proxies, then the directly summed atoms (assigned to no level
+// >= 1) with the full pair, and the short-range terms of every other atom
+// within reach.  The per-atom class is decided once per block by the
+// filtering threads and kept in LDS as index lists.
+template <int NS, int LJM, bool ASYM, int B>
+__global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
+{
+    using S = LeafShape<B>;
+    constexpr int PPT = S::ppt;
+    constexpr int NT = S::threads;
+    extern __shared__ double sm[];
+    const int n1 = a.degree + 1;
+    double *Vs = sm;                  // [np]
+    double *T1 = Vs + a.np;           // [n1][n1][B]
+    double *T2 = T1 + n1 * n1 * B;    // [n1][B][B]
+    double *Lb = T2 + n1 * B * B;     // [3][B][n1]
+    int *lists = reinterpret_cast<int *>(Lb + 3 * B * n1);   // [2][NT]
+    __shared__ int wcnt[2][NT / 64];
+    const CpLevels &L = a.L;
+    const GridParams &g = a.g;
+    const int q = blockIdx.x;
+    const int I = q % L.cx[0], J = (q / L.cx[0]) % L.cy[0], K = q / (L.cx[0] * L.cy[0]);
+    const int i0 = I * B, j0 = J * B, k0 = K * B;
+    const PairConst kc = make_pair_const(a.asym);
+    const AtomF32<NS> *__restrict__ rec = static_cast<const AtomF32<NS> *>(a.rec);
+    const float4 *rec4 = static_cast<const float4 *>(a.rec);
+    double blo[3], bhi[3];
+    cp_box(L, 0, I, J, K, blo, bhi);
+    const double rs2 = a.rshort * a.rshort;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    // level-1 ancestor basis tables: L_k(coordinate of the block's points)
+    if (L.T >= 1) {
+        double pb[6];
+        cp_proxy_box(L, 1, I >> 1, J >> 1, K >> 1, pb);
+        for (int t = threadIdx.x; t < 3 * B; t += NT) {
+            const int ax = t / B, l = t % B;
+            const int base = ax == 0 ? i0 : (ax == 1 ? j0 : k0);
+            double Lv[kMaxDeg + 1];
+            lagrange_all((base + l) * g.h[ax], pb[ax], pb[3 + ax], a.degree, Lv);
+            for (int k = 0; k < n1; ++k) Lb[(ax * B + l) * n1 + k] = Lv[k];
+        }
+    }
+
+    for (int pass = 0; pass < S::passes; ++pass) {
+        int li[PPT], lj[PPT], lk[PPT];
+        bool valid[PPT];
+        GridPt gp[PPT];
+        PointAcc<NS> acc[PPT];
+#pragma unroll
+        for (int qq = 0; qq < PPT; ++qq) {
+            const int l = (pass * PPT + qq) * NT + threadIdx.x;
+            li[qq] = l % B;
+            lj[qq] = (l / B) % B;
+            lk[qq] = l / (B * B);
+            valid[qq] = i0 + li[qq] < g.nx && j0 + lj[qq] < g.ny && k0 + lk[qq] < g.nz;
+            gp[qq] = grid_pt(g, valid[qq] ? i0 + li[qq] : i0, valid[qq] ? j0 + lj[qq] : j0,
+                             valid[qq] ? k0 + lk[qq] : k0);
+            acc[qq].zero();
+        }
+
+        // ---------------------------------------------- far: interpolation
+        if (L.T >= 1) {
+            const int a1 = cp_id(L, 1, I >> 1, J >> 1, K >> 1);
+            for (int comp = 0; comp < (ASYM ? 2 : 1); ++comp) {
+                __syncthreads();
+                for (int k = threadIdx.x; k < a.np; k += NT)
+                    Vs[k] = a.V[((size_t)a1 * 2 + comp) * a.np + k];
+                __syncthreads();
+                // T1[k1][k2][z] = sum_k3 V[k3][k2][k1] Lz[z][k3]
+                for (int t = threadIdx.x; t < n1 * n1 * B; t += NT) {
+                    const int z = t % B, k12 = t / B;
+                    double s = 0;
+                    for (int k3 = 0; k3 < n1; ++k3) s += Vs[k3 * n1 * n1 + k12] * Lb[(2 * B + z) * n1 + k3];
+                    T1[t] = s;
+                }
+                __syncthreads();
+                // T2[k1][y][z] = sum_k2 T1[k1][k2][z] Ly[y][k2]     (k12 = k2 n1 + k1)
+                for (int t = threadIdx.x; t < n1 * B * B; t += NT) {
+                    const int z = t % B, y = (t / B) % B, k1 = t / (B * B);
+                    double s = 0;
+                    for (int k2 = 0; k2 < n1; ++k2)
+                        s += T1[(k2 * n1 + k1) * B + z] * Lb[(1 * B + y) * n1 + k2];
+                    T2[t] = s;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int qq = 0; qq < PPT; ++qq) {
+                    double s = 0;
+                    for (int k1 = 0; k1 < n1; ++k1)
+                        s += T2[(k1 * B + lj[qq]) * B + lk[qq]] * Lb[(0 * B + li[qq]) * n1 + k1];
+                    if (comp == 0) acc[qq].C = s;
+                    else acc[qq].Y = s;
+                }
+            }
+        }
+
+        // ---------------------------------------------- direct and short
+        const int c0 = (int)a.cand_off[q], c1 = (int)a.cand_off[q + 1];
+        for (int c = c0; c < c1; ++c) {
+            const int leaf = a.cand[c];
+            const int ab = a.begin[leaf], ae = a.end[leaf];
+            for (int t0 = ab; t0 < ae; t0 += NT) {
+                const int i = t0 + threadIdx.x;
+                int cls = 0;   // 0 skip, 1 direct (full pair), 2 short range only
+                if (i < ae) {
+                    double y[3];
+                    atom_pos(rec4, a.stride_f4, i, y);
+                    const int lvl = L.T >= 1 ? cp_accept_level(L, I, J, K, y, 1) : 0;
+                    if (lvl == 0) cls = 1;
+                    else {
+                        double gp2 = 0;
+                        for (int k = 0; k < 3; ++k) {
+                            double gg = fmax(0.0, fmax(blo[k] - y[k], y[k] - bhi[k]));
+                            gp2 += gg * gg;
+                        }
+                        cls = gp2 < rs2 ? 2 : 0;
+                    }
+                }
+                const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+                const uint64_t m1 = __ballot(cls == 1), m2 = __ballot(cls == 2);
+                __syncthreads();
+                if (lane == 0) {
+                    wcnt[0][wave] = __popcll(m1);
+                    wcnt[1][wave] = __popcll(m2);
+                }
+                __syncthreads();
+                int b1 = 0, b2 = 0, n1c = 0, n2c = 0;
+                for (int w = 0; w < NT / 64; ++w) {
+                    if (w < wave) {
+                        b1 += wcnt[0][w];
+                        b2 += wcnt[1][w];
+                    }
+                    n1c += wcnt[0][w];
+                    n2c += wcnt[1][w];
+                }
+                if (cls == 1) lists[b1 + __popcll(m1 & lt)] = i;
+                if (cls == 2) lists[NT + b2 + __popcll(m2 & lt)] = i;
+                __syncthreads();
+                if (a.work && threadIdx.x == 0 && pass == 0) {
+                    const unsigned long long np_blk =
+                        (unsigned long long)(min(B, g.nx - i0) * min(B, g.ny - j0) * min(B, g.nz - k0));
+                    atomicAdd(&a.work[0], (unsigned long long)n1c * np_blk);
+                    atomicAdd(&a.work[1], (unsigned long long)n2c * np_blk);
+                }
+                for (int s0 = 0; s0 < n1c; s0 += kAtomPad) {
+                    PairAcc<NS> p[PPT];
+#pragma unroll
+                    for (int qq = 0; qq < PPT; ++qq) p[qq].zero();
+                    const int s1 = min(s0 + kAtomPad, n1c);
+                    for (int s = s0; s < s1; ++s) {
+                        const int ai = __builtin_amdgcn_readfirstlane(lists[s]);
+                        const AtomF32<NS> &at = rec[ai];
+#pragma unroll
+                        for (int qq = 0; qq < PPT; ++qq)
+                            pair_eval<NS, LJM, ASYM, false, true>(at, gp[qq], kc, p[qq], acc[qq].hit);
+                    }
+#pragma unroll
+                    for (int qq = 0; qq < PPT; ++qq) acc[qq].template flush<LJM != LJ_NONE, ASYM>(p[qq]);
+                }
+                for (int s0 = 0; s0 < n2c; s0 += kAtomPad) {
+                    PairAcc<NS> p[PPT];
+#pragma unroll
+                    for (int qq = 0; qq < PPT; ++qq) p[qq].zero();
+                    const int s1 = min(s0 + kAtomPad, n2c);
+                    for (int s = s0; s < s1; ++s) {
+                        const int ai = __builtin_amdgcn_readfirstlane(lists[NT + s]);
+                        const AtomF32<NS> &at = rec[ai];
+#pragma unroll
+                        for (int qq = 0; qq < PPT; ++qq)
+                            pair_eval<NS, LJM, ASYM, false, false>(at, gp[qq], kc, p[qq], acc[qq].hit);
+                    }
+#pragma unroll
+                    for (int qq = 0; qq < PPT; ++qq) acc[qq].template flush<LJM != LJ_NONE, ASYM>(p[qq]);
+                }
+            }
+        }
+
+#pragma unroll
+        for (int qq = 0; qq < PPT; ++qq) {
+            if (!valid[qq]) continue;
+            const int64_t p = ((int64_t)(k0 + lk[qq]) * g.ny + (j0 + lj[qq])) * g.nx + (i0 + li[qq]);
+            store_point<NS, LJM, ASYM>(a.out, g, p, acc[qq]);
+        }
+    }
+}
+
+template <int NS, int LJM, bool ASYM>
+void launch_leaf_b(int B, int nleaf, size_t shm, const CpLeafArgs &a, hipStream_t s)
+{
+    if (B == 4)
+        hipLaunchKernelGGL((k_cp_leaf<NS, LJM, ASYM, 4>), nleaf, LeafShape<4>::threads, shm, s, a);
+    else if (B == 8)
+        hipLaunchKernelGGL((k_cp_leaf<NS, LJM, ASYM, 8>), nleaf, LeafShape<8>::threads, shm, s, a);
+    else
+        hipLaunchKernelGGL((k_cp_leaf<NS, LJM, ASYM, 16>), nleaf, LeafShape<16>::threads, shm, s, a);
+}
+
+template <int NS>
+void launch_leaf_ns(int lj_mode, bool asym, int B, int nleaf, size_t shm, const CpLeafArgs &a,
+                    hipStream_t s)
+{
+    if (lj_mode == LJ_CUT) {
+        if (asym) launch_leaf_b<NS, LJ_CUT, true>(B, nleaf, shm, a, s);
+        else launch_leaf_b<NS, LJ_CUT, false>(B, nleaf, shm, a, s);
+    } else {
+        if (asym) launch_leaf_b<NS, LJ_NONE, true>(B, nleaf, shm, a, s);
+        else launch_leaf_b<NS, LJ_NONE, false>(B, nleaf, shm, a, s);
+    }
+}
+
+}  // namespace
+
+int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStream_t s)
+{
+    const bool ev = a.opts->flags & RISM_FLAG_PHASE_EVENTS;
+    const int B = a.opts->batch_edge;
+    const int deg = a.opts->degree;
+    const int n1 = deg + 1, np = n1 * n1 * n1;
+    // implicit target octree
+    CpLevels L{};
+    L.B = B;
+    L.nx = a.g.nx;
+    L.ny = a.g.ny;
+    L.nz = a.g.nz;
+    for (int k = 0; k < 3; ++k) L.h[k] = a.g.h[k];
+    L.theta = a.opts->theta;
+    L.T = 0;
+    const int maxdim = std::max(L.nx, std::max(L.ny, L.nz));
+    while ((B << L.T) < maxdim) ++L.T;
+    if (L.T > kCpMaxLev) {
+        set_error("treecode_cp: grid too large for the target octree");
+        return RISM_E_UNSUPPORTED;
+    }
+    for (int l = 0; l <= L.T; ++l) {
+        const int e = B << l;
+        L.cx[l] = (L.nx + e - 1) / e;
+        L.cy[l] = (L.ny + e - 1) / e;
+        L.cz[l] = (L.nz + e - 1) / e;
+    }
+    L.off[1] = 0;
+    for (int l = 1; l <= L.T; ++l) L.off[l + 1] = L.off[l] + L.cx[l] * L.cy[l] * L.cz[l];
+    const int ncl = L.T >= 1 ? L.off[L.T + 1] : 0;
+    const int nleaf = L.cx[0] * L.cy[0] * L.cz[0];
+
+    // source tree on the atoms (Morton sort, boxes) for the neighbour queries
+    TreeDev t{};
+    int rc;
+    {
+        PhaseTimer pt(ev, RISM_PHASE_TREE_BUILD, s);
+        rc = build_source_tree(a, ws, t, st, s);
+    }
+    if (rc) return rc;
+    const int stride_f4 = (int)(rec32_bytes_of(a.sp.ns_pad) / sizeof(float4));
+    double rshort = a.asym_on ? std::sqrt(a.asym.rs2) : 0.0;
+    if (a.lj_mode == LJ_CUT) rshort = std::max(rshort, a.rmax_short);
+
+    // queries: clusters (mode 0) and leaves (mode 1), count pass
+    uint32_t *ccnt = ws.get<uint32_t>(ncl + 1), *citems = ws.get<uint32_t>(ncl + 1);
+    uint32_t *lcnt = ws.get<uint32_t>(nleaf + 1);
+    uint32_t *tot = ws.get<uint32_t>(4);
+    if (ws.status()) return ws.status();
+    CpQueryArgs qa{};
+    qa.L = L;
+    qa.rshort = rshort;
+    qa.begin = t.begin;
+    qa.end = t.end;
+    qa.child0 = t.child0;
+    qa.nchild = t.nchild;
+    qa.box = t.box;
+    {
+        PhaseTimer pt(ev, RISM_PHASE_LISTS, s);
+        if (ncl > 0) {
+            qa.mode = 0;
+            qa.nq = ncl;
+            qa.cnt = ccnt;
+            qa.items = citems;
+            qa.fill = 0;
+            hipLaunchKernelGGL(k_cp_query, (ncl + kBlock - 1) / kBlock, kBlock, 0, s, qa);
+            hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, ccnt, ncl + 1, tot + 0);
+            hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, citems, ncl + 1, tot + 1);
+        }
+        qa.mode = 1;
+        qa.nq = nleaf;
+        qa.cnt = lcnt;
+        qa.items = nullptr;
+        qa.fill = 0;
+        hipLaunchKernelGGL(k_cp_query, (nleaf + kBlock - 1) / kBlock, kBlock, 0, s, qa);
+        hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, lcnt, nleaf + 1, tot + 2);
+    }
+    RISM_HIP(hipGetLastError());
+    uint32_t ht[4] = {0, 0, 0, 0};
+    RISM_HIP(hipMemcpyAsync(ht, tot, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    RISM_HIP(hipStreamSynchronize(s));
+    if (ncl == 0) ht[0] = ht[1] = 0;
+    int *ccand = ws.get<int>(ht[0] + 1), *lcand = ws.get<int>(ht[2] + 1);
+    int *it_cl = ws.get<int>(ht[1] + 1), *it_c0 = ws.get<int>(ht[1] + 1),
+        *it_c1 = ws.get<int>(ht[1] + 1);
+    double *part = ws.get<double>((size_t)(ht[1] + 1) * 2 * np);
+    double *V = ws.get<double>((size_t)(ncl + 1) * 2 * np);
+    const bool want_stats = a.opts->flags & RISM_FLAG_STATS;
+    unsigned long long *work = want_stats ? ws.get<unsigned long long>(4) : nullptr;
+    if (ws.status()) return ws.status();
+    if (work) RISM_HIP(hipMemsetAsync(work, 0, 4 * sizeof(unsigned long long), s));
+    {
+        PhaseTimer pt(ev, RISM_PHASE_LISTS, s);
+        if (ncl > 0) {
+            qa.mode = 0;
+            qa.nq = ncl;
+            qa.off = ccnt;
+            qa.list = ccand;
+            qa.fill = 1;
+            qa.items = nullptr;
+            hipLaunchKernelGGL(k_cp_query, (ncl + kBlock - 1) / kBlock, kBlock, 0, s, qa);
+            hipLaunchKernelGGL(k_cp_items, (ncl + kBlock - 1) / kBlock, kBlock, 0, s, ncl, ccnt,
+                               citems, it_cl, it_c0, it_c1);
+        }
+        qa.mode = 1;
+        qa.nq = nleaf;
+        qa.off = lcnt;
+        qa.list = lcand;
+        qa.fill = 1;
+        hipLaunchKernelGGL(k_cp_query, (nleaf + kBlock - 1) / kBlock, kBlock, 0, s, qa);
+    }
+    RISM_HIP(hipGetLastError());
+
+    // far field into the target proxies, reduction, downward pass
+    if (ncl > 0) {
+        {
+            PhaseTimer pt(ev, RISM_PHASE_UPWARD, s);
+            CpFarArgs fa{};
+            fa.L = L;
+            fa.it_cl = it_cl;
+            fa.it_c0 = it_c0;
+            fa.it_c1 = it_c1;
+            fa.cand = ccand;
+            fa.begin = t.begin;
+            fa.end = t.end;
+            fa.rec = static_cast<const float4 *>(t.sorted_rec);
+            fa.stride_f4 = stride_f4;
+            fa.degree = deg;
+            fa.np = np;
+            fa.yk = (float)a.asym.yk;
+            fa.part = part;
+            fa.work = work ? work + 2 : nullptr;
+            if (ht[1] > 0) {
+                if (a.asym_on)
+                    hipLaunchKernelGGL(k_cp_far<true>, (int)ht[1], kBlock, 0, s, fa);
+                else
+                    hipLaunchKernelGGL(k_cp_far<false>, (int)ht[1], kBlock, 0, s, fa);
+            }
+            hipLaunchKernelGGL(k_cp_reduce, ncl, kBlock, 0, s, ncl, np, citems, part, V);
+        }
+        {
+            PhaseTimer pt(ev, RISM_PHASE_DOWNWARD, s);
+            const size_t shm = (3 * (size_t)n1 * n1 + 3 * (size_t)np) * sizeof(double);
+            for (int lvl = L.T - 1; lvl >= 1; --lvl)
+                hipLaunchKernelGGL(k_cp_down, L.cx[lvl] * L.cy[lvl] * L.cz[lvl], kBlock, shm, s, L,
+                                   lvl, deg, V);
+        }
+        RISM_HIP(hipGetLastError());
+    }
+
+    // leaves
+    CpLeafArgs la{};
+    la.L = L;
+    la.g = a.g;
+    la.out = a.out;
+    la.asym = a.asym;
+    la.rec = t.sorted_rec;
+    la.stride_f4 = stride_f4;
+    la.begin = t.begin;
+    la.end = t.end;
+    la.cand_off = lcnt;
+    la.cand = lcand;
+    la.V = V;
+    la.degree = deg;
+    la.np = np;
+    la.rshort = rshort;
+    la.work = work;
+    const int NT = B == 4 ? 64 : 256;
+    const size_t shm = ((size_t)np + (size_t)n1 * n1 * B + (size_t)n1 * B * B + 3 * (size_t)B * n1) *
+                           sizeof(double) + 2 * (size_t)NT * sizeof(int);
+    int dev = 0, lds_max = 0;
+    RISM_HIP(hipGetDevice(&dev));
+    RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if (shm + 2048 > (size_t)lds_max) {
+        set_error("treecode_cp: degree / batch edge too large for the LDS of this device");
+        return RISM_E_UNSUPPORTED;
+    }
+    {
+        PhaseTimer pt(ev, RISM_PHASE_EVAL, s);
+        switch (a.sp.ns_pad) {
+        case 1: launch_leaf_ns<1>(a.lj_mode, a.asym_on, B, nleaf, shm, la, s); break;
+        case 2: launch_leaf_ns<2>(a.lj_mode, a.asym_on, B, nleaf, shm, la, s); break;
+        case 4: launch_leaf_ns<4>(a.lj_mode, a.asym_on, B, nleaf, shm, la, s); break;
+        default: launch_leaf_ns<8>(a.lj_mode, a.asym_on, B, nleaf, shm, la, s); break;
+        }
+    }
+    RISM_HIP(hipGetLastError());
+    st.n_batches = nleaf;
+    st.n_nodes = ncl;
+    if (work) {
+        unsigned long long hw[4];
+        RISM_HIP(hipMemcpyAsync(hw, work, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        RISM_HIP(hipStreamSynchronize(s));
+        st.pairs_direct = (double)hw[0];
+        st.pairs_short = (double)hw[1];
+        st.pairs_far = (double)hw[2];
+    }
+    return RISM_OK;
+}
+
+}  // namespace rism

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <utility>
 
+#include "cheb.h"
 #include "pair.h"
 #include "tree.h"
 
@@ -348,57 +349,7 @@ __global__ __launch_bounds__(kBlock) void k_node_box(const float4 *rec, int stri
 
 // ------------------------------------------------------------ upward pass
 
-constexpr int kMaxDeg = 16;
 constexpr int kTile = 64;
-
-// Chebyshev points of the second kind on [lo, hi] and their barycentric
-// weights: s_k = lo + (hi - lo)(1 + cos(k pi/n))/2, w_k = (-1)^k delta_k with
-// delta_0 = delta_n = 1/2, else 1.
-__device__ __forceinline__ double cheb_point(double lo, double hi, int k, int n)
-{
-    return lo + (hi - lo) * 0.5 * (1.0 + cos(kPi * k / n));
-}
-__device__ __forceinline__ double bary_weight(int k, int n)
-{
-    double w = (k & 1) ? -1.0 : 1.0;
-    return (k == 0 || k == n) ? 0.5 * w : w;
-}
-
-// Lagrange basis values L_k(x), k = 0..n, of the Chebyshev points of [lo, hi].
-__device__ void lagrange_all(double x, double lo, double hi, int n, double *L)
-{
-    double den = 0.0;
-    int exact = -1;
-    for (int k = 0; k <= n; ++k) {
-        double d = x - cheb_point(lo, hi, k, n);
-        if (d == 0.0) exact = k;
-        double t = bary_weight(k, n) / d;
-        L[k] = t;
-        den += t;
-    }
-    if (exact >= 0) {
-        for (int k = 0; k <= n; ++k) L[k] = k == exact ? 1.0 : 0.0;
-        return;
-    }
-    double inv = 1.0 / den;
-    for (int k = 0; k <= n; ++k) L[k] *= inv;
-}
-
-// Proxy box of a node: its tight box, padded so that no axis is degenerate.
-__device__ __forceinline__ void proxy_box(const double *box, double *pb)
-{
-    for (int k = 0; k < 3; ++k) {
-        double lo = box[k], hi = box[3 + k];
-        double w = hi - lo;
-        if (w < 1e-3) {
-            double c = 0.5 * (lo + hi);
-            lo = c - 5e-4;
-            hi = c + 5e-4;
-        }
-        pb[k] = lo;
-        pb[3 + k] = hi;
-    }
-}
 
 // Leaves: qhat_k = sum_j q_j Lx_k1(x_j) Ly_k2(y_j) Lz_k3(z_j) from the atoms.
 // Internal nodes: qhat_P = sum_children (Mx (x) My (x) Mz) qhat_c, with
@@ -875,12 +826,6 @@ int tree_forward(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStream
 }  // namespace rism
 
 namespace rism {
-
-int tree_forward_cp(const TreeCallArgs &, Workspace &, rism_stats &, hipStream_t)
-{
-    set_error("RISM_TREECODE_CP: not available in this build");
-    return RISM_E_UNSUPPORTED;
-}
 
 int adjoint_tree(const AdjointArgs &, Workspace &, rism_stats &, hipStream_t)
 {

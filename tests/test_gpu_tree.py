@@ -19,7 +19,7 @@ def _run(wl, cut=9.0, tol=0.0, **kw):
     api = _api()
     xyz, q, s, e = api.solute_to_device(wl.solute)
     opts = api.Opts(method=kw.pop("method", "treecode"), out_dtype="f32", lj_cutoff=cut,
-                    lj_tol=tol, **kw)
+                    lj_tol=tol, stats=True, **kw)
     out = api.initialize(xyz, q, s, e, api.sites_from(wl.sites), api.grid_from(wl.grid), opts,
                          ETA, KAPPA, BETA, DIEL)
     torch.cuda.synchronize()
@@ -40,26 +40,39 @@ def _np(t):
     return None if t is None else t.double().cpu().numpy()
 
 
+METHODS = ["treecode", "treecode_cp"]
+# (theta, degree) meeting 1e-6 per method.  The particle-cluster MAC,
+# (r_B + r_C)/R < theta, bounds both radii; the cluster-particle MAC of the
+# paper, r_C/|y - c_C| < theta, bounds only the target cluster's, so it needs a
+# smaller theta or a higher degree for the same error (theta 0.7 / degree 8
+# leaves ~7e-6 on the smeared grids of the 2,500-atom workload).
+TOL_PARAMS = {"treecode": (0.7, 8), "treecode_cp": (0.6, 10)}
+
+
+@pytest.mark.parametrize("method", METHODS)
 @pytest.mark.parametrize("batch", [4, 8, 16])
 @pytest.mark.parametrize("leaf", [8, 64])
-def test_ragged_grid_all_near(oracle, batch, leaf):
-    """Ragged 37x29x23 grid, non-dyadic spacing, 4 sites: few atoms, so every
-    source cluster is smaller than its proxy set and the treecode reduces to
-    its near-field and short-range paths (checked against the oracle)."""
+def test_ragged_grid(oracle, method, batch, leaf):
+    """Ragged 37x29x23 grid, non-dyadic spacing, 4 sites, several leaf sizes
+    and batch edges, against the oracle on the full grid."""
     wl = W.tiny(n_atoms=60, dims=(37, 29, 23), seed=7, spacing=0.3)
     wl.solute.xyz *= 1.6
-    (u, c, h), st = _run(wl, batch_edge=batch, leaf_size=leaf)
+    th, dg = TOL_PARAMS[method]
+    (u, c, h), st = _run(wl, batch_edge=batch, leaf_size=leaf, method=method, theta=th, degree=dg)
     ur, cr, hr = _oracle_grids(oracle, wl)
-    assert st["pairs_far"] == 0
+    if method == "treecode":
+        assert st["pairs_far"] == 0   # every source cluster is smaller than its proxy set
     assert_close_grid(_np(u), ur, 1e-6, cap=FP32_CAP, what="u")
     assert_close_grid(_np(c), cr, 1e-6, cap=FP32_CAP, what="c")
     assert_close_grid(_np(h), hr, 1e-6, cap=FP32_CAP, what="h")
 
 
-def test_lj_tolerance_cutoffs(oracle):
+@pytest.mark.parametrize("method", METHODS)
+def test_lj_tolerance_cutoffs(oracle, method):
     wl = W.tiny(n_atoms=40, dims=(30, 26, 22), seed=17, spacing=0.5)
     wl.solute.xyz *= 1.8
-    (u, c, h), _ = _run(wl, cut=0.0, tol=1e-4, leaf_size=8)
+    th, dg = TOL_PARAMS[method]
+    (u, c, h), _ = _run(wl, cut=0.0, tol=1e-4, leaf_size=8, method=method, theta=th, degree=dg)
     ur, cr, hr = _oracle_grids(oracle, wl, cut=0.0, tol=1e-4)
     assert_close_grid(_np(u), ur, 1e-6, cap=FP32_CAP, what="u")
 
@@ -72,7 +85,8 @@ def _far_case():
                       W.centred_grid([0.0, 0.0, 0.0], 0.5, 80), 31)
 
 
-def test_far_field_converges_with_degree(oracle):
+@pytest.mark.parametrize("method", METHODS)
+def test_far_field_converges_with_degree(oracle, method):
     """Far field exercised (degree 2..6 proxy sets are smaller than the
     clusters): the error against the oracle falls as the degree rises, and
     theta 0.5 / degree 10 meets 1e-6 on every grid."""
@@ -89,29 +103,32 @@ def test_far_field_converges_with_degree(oracle):
     pick = lambda a: _np(a)[:, idx[:, 2], idx[:, 1], idx[:, 0]]
     errs = []
     for deg in (2, 4, 6):
-        (u, c, h), stt = _run(wl, theta=0.7, degree=deg, leaf_size=32)
+        (u, c, h), stt = _run(wl, theta=0.7, degree=deg, leaf_size=32, method=method)
         assert stt["pairs_far"] > 0
         e = max(np.linalg.norm(pick(c)[k] - cr[k]) / np.linalg.norm(cr[k]) for k in range(4))
         errs.append(e)
     print("far-field c rel-L2 by degree 2/4/6:", errs)
     assert errs[0] > errs[1] > errs[2]
-    (u, c, h), stt = _run(wl, theta=0.5, degree=10, leaf_size=32)
+    (u, c, h), stt = _run(wl, theta=0.5, degree=10, leaf_size=32, method=method)
     print("theta 0.5 degree 10 far pairs", stt["pairs_far"])
     assert_close_grid(pick(u), ur, 1e-6, cap=FP32_CAP, what="u")
     assert_close_grid(pick(c), cr, 1e-6, cap=FP32_CAP, what="c")
     assert_close_grid(pick(h), hr, 1e-6, cap=FP32_CAP, what="h")
 
 
-def test_protein_2500_vs_f64_direct(oracle):
-    """The benchmark workload at theta 0.7, degree 8, 9 A cut-off: full-grid
-    rel-L2 against the GPU FP64 direct sum (same cut-off) <= 1e-6."""
+@pytest.mark.parametrize("method", METHODS)
+def test_protein_2500_vs_f64_direct(oracle, method):
+    """The benchmark workload with a 9 A cut-off (particle-cluster theta 0.7 /
+    degree 8, cluster-particle theta 0.6 / degree 8): full-grid rel-L2 against
+    the GPU FP64 direct sum (same cut-off) <= 1e-6."""
     api = _api()
     wl = W.protein_2500()
     xyz, q, s, e = api.solute_to_device(wl.solute)
     sites, grid = api.sites_from(wl.sites), api.grid_from(wl.grid)
     o64 = api.Opts(method="direct_f64", out_dtype="f64", lj_cutoff=9.0)
     ref = api.initialize(xyz, q, s, e, sites, grid, o64, ETA, KAPPA, BETA, DIEL)
-    (u, c, h), st = _run(wl)
+    th, dg = {"treecode": (0.7, 8), "treecode_cp": (0.6, 8)}[method]
+    (u, c, h), st = _run(wl, method=method, theta=th, degree=dg)
     print("stats", st)
     for name, x, r in zip("uch", (u, c, h), ref):
         for k in range(x.shape[0]):
