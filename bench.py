@@ -66,9 +66,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--method", default="treecode",
+    ap.add_argument("--method", default="treecode_cp",
                     choices=["treecode", "treecode_cp", "direct_f32c"])
-    ap.add_argument("--theta", type=float, default=0.7)
+    ap.add_argument("--theta", type=float, default=0.6)
     ap.add_argument("--degree", type=int, default=8)
     ap.add_argument("--lj-cutoff", type=float, default=9.0)
     ap.add_argument("--workload", default="protein_2500",
@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after the run, copy a device buffer of this size (MiB) once: a "
+                         "kernel of known traffic for scaling HBM byte counters")
     return ap.parse_args()
 
 
@@ -258,6 +261,15 @@ def main():
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl, args.lj_cutoff, args.cpu_seconds)
+
+    if args.copy_probe_mb > 0:
+        nel = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(nel, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_probe_bytes"] = {"read": nel * 4, "write": nel * 4}
 
     print(json.dumps(result))
 
