@@ -824,13 +824,3 @@ int tree_forward(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStream
 }
 
 }  // namespace rism
-
-namespace rism {
-
-int adjoint_tree(const AdjointArgs &, Workspace &, rism_stats &, hipStream_t)
-{
-    set_error("RISM_TREECODE backward: not available in this build");
-    return RISM_E_UNSUPPORTED;
-}
-
-}  // namespace rism

@@ -506,11 +506,9 @@ int rism_potential_backward(const rism_solute *so, const rism_sites *si, const r
     int rc = check_common(so, si, gr, op);
     if (rc) return rc;
     if (!w) return fail(RISM_E_INVALID, "dL_du is NULL");
-    if (op->method == RISM_TREECODE_CP)
-        return fail(RISM_E_UNSUPPORTED, "backward: use RISM_TREECODE for the tree adjoint");
     Prep p;
     prep_common(so, si, gr, op, p);
-    if (op->method == RISM_TREECODE && p.lj_mode != LJ_CUT)
+    if (op->method >= RISM_TREECODE && p.lj_mode != LJ_CUT)
         return fail(RISM_E_UNSUPPORTED, "treecode backward needs an LJ cut-off");
     rism_stats st{};
     if (so->n == 0 || (!dxyz && !dq && !deps && !dsig)) {
@@ -523,7 +521,9 @@ int rism_potential_backward(const rism_solute *so, const rism_sites *si, const r
     Workspace ws(dev, stream, op->max_workspace_bytes);
     const bool f64path = op->method == RISM_DIRECT_F64;
     void *rec32 = nullptr, *rec64 = nullptr;
-    rc = stage_atoms(so, p, op, !f64path, f64path, deps != nullptr, ws, &rec32, &rec64, nullptr, s);
+    double max_rcut = op->lj_cutoff;
+    rc = stage_atoms(so, p, op, !f64path, f64path, deps != nullptr, ws, &rec32, &rec64, nullptr, s,
+                     &max_rcut);
     if (rc) return rc;
     AdjointArgs a{};
     a.atoms = f64path ? rec64 : rec32;
@@ -542,8 +542,8 @@ int rism_potential_backward(const rism_solute *so, const rism_sites *si, const r
     a.deps = deps;
     a.dsig = dsig;
     a.opts = op;
-    a.rmax_lj = op->lj_tol > 0 ? -1.0 : op->lj_cutoff;
-    rc = op->method == RISM_TREECODE ? adjoint_tree(a, ws, st, s)
+    a.rmax_lj = op->lj_tol > 0 ? max_rcut : op->lj_cutoff;
+    rc = op->method >= RISM_TREECODE ? adjoint_tree(a, ws, st, s)
                                      : adjoint_direct(a, f64path, ws, st, s);
     if (rc) return rc;
     st.workspace_bytes = (int64_t)ws.in_use();

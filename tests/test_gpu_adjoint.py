@@ -86,3 +86,76 @@ def test_adjoint_protein_2500_sampled_atoms(oracle):
     assert _rel(dq[pick], rq) < 1e-5
     assert _rel(de[pick], re_) < 1e-5
     assert _rel(ds[pick], rs) < 1e-5
+
+
+# ------------------------------------------------------------------ tree adjoint
+
+def _tree_opts(method="treecode_cp", theta=0.6, degree=10, cut=6.0, batch=8):
+    from paper_2109_09772_amd import api
+    return api.Opts(method=method, out_dtype="f32", lj_cutoff=cut, theta=theta, degree=degree,
+                    batch_edge=batch, leaf_size=16)
+
+
+@pytest.mark.parametrize("batch", [4, 8])
+def test_tree_adjoint_is_transpose_of_tree_forward(batch):
+    """With LJ switched off (site eps = 0), L = sum w u_tree(Q) is linear in Q,
+    so sum_a Q_a dL/dQ_a from the tree adjoint must equal L from the tree
+    forward (same assignment of atoms to target clusters) to FP32 rounding,
+    while the exact L differs from both by the treecode error."""
+    from paper_2109_09772_amd import api
+    wl, w = _grad_case(seed=6, n=70, dims=(40, 36, 30), spacing=0.5)
+    wl.solute.xyz *= 2.0
+    wl.sites.eps[:] = 0.0
+    xyz, q, s, e = api.solute_to_device(wl.solute)
+    sites, grid = api.sites_from(wl.sites), api.grid_from(wl.grid)
+    o = _tree_opts(theta=0.7, degree=4, batch=batch)   # coarse on purpose: large tree error
+    u = api.potential(xyz, q, s, e, sites, grid, o)
+    wt = torch.as_tensor(w, device="cuda", dtype=torch.float32)
+    L_tree = float((u.double() * wt.double()).sum())
+    _, dq, _, _ = api.potential_backward(xyz, q, s, e, sites, grid, o, wt)
+    L_adj = float((q * dq).sum())
+    o_ex = api.Opts(method="direct_f64", out_dtype="f64", lj_cutoff=6.0)
+    L_exact = float((api.potential(xyz, q, s, e, sites, grid, o_ex) * wt.double()).sum())
+    print("L tree", L_tree, "adjoint", L_adj, "exact", L_exact)
+    assert abs(L_adj - L_tree) <= 2e-6 * abs(L_tree)
+    assert abs(L_exact - L_tree) > 10 * abs(L_adj - L_tree)
+
+
+@pytest.mark.parametrize("method", ["treecode", "treecode_cp"])
+def test_tree_adjoint_vs_oracle(oracle, method):
+    wl, w = _grad_case(seed=4, n=60, dims=(37, 29, 23), spacing=0.4)
+    wl.solute.xyz *= 2.0
+    from paper_2109_09772_amd import api
+    xyz, q, s, e = api.solute_to_device(wl.solute)
+    o = _tree_opts(method=method)
+    wt = torch.as_tensor(w, device="cuda", dtype=torch.float32)
+    dx, dq, de, ds = api.potential_backward(xyz, q, s, e, api.sites_from(wl.sites),
+                                            api.grid_from(wl.grid), o, wt)
+    sol, st, g = wl.solute, wl.sites, wl.grid
+    rc = oracle_rcut(oracle, wl, 6.0)
+    rx, rq, re_, rs = oracle.backward_grid(sol.xyz, sol.q, sol.sigma, sol.eps, st.q, st.sigma,
+                                           st.eps, g.origin, g.spacing, g.dims,
+                                           wt.double().cpu().numpy(), KC, rc)
+    for name, x, r in (("dxyz", dx, rx), ("dq", dq, rq), ("deps", de, re_), ("dsigma", ds, rs)):
+        err = _rel(x.cpu().numpy(), r)
+        print(method, name, f"{err:.2e}")
+        assert err < 1e-5, (name, err)
+
+
+def test_tree_adjoint_protein_2500():
+    """The 2,500-atom / 128^3 workload with the 9 A cut-off: cluster-particle
+    tree adjoint against the GPU FP64 direct adjoint, per gradient <= 1e-5."""
+    from paper_2109_09772_amd import api
+    wl = W.protein_2500()
+    w = W.smooth_upstream(wl.grid, wl.sites, seed=4)
+    xyz, q, s, e = api.solute_to_device(wl.solute)
+    sites, grid = api.sites_from(wl.sites), api.grid_from(wl.grid)
+    wt = torch.as_tensor(w, device="cuda", dtype=torch.float32)
+    o = _tree_opts(theta=0.6, degree=8, cut=9.0)
+    got = api.potential_backward(xyz, q, s, e, sites, grid, o, wt)
+    o64 = api.Opts(method="direct_f64", out_dtype="f64", lj_cutoff=9.0)
+    ref = api.potential_backward(xyz, q, s, e, sites, grid, o64, wt.double())
+    for name, x, r in zip(("dxyz", "dq", "deps", "dsigma"), got, ref):
+        err = _rel(x.cpu().numpy(), r.cpu().numpy())
+        print(name, f"{err:.2e}")
+        assert err < 1e-5, (name, err)
