@@ -80,22 +80,45 @@ struct CpQueryArgs {
     double rshort;
     const int *begin, *end, *child0, *nchild;
     const double *box;
-    uint32_t *cnt, *items;     // count pass (nq + 1 entries each)
-    const uint32_t *off;       // fill pass
+    const int *n_nodes;
+    uint32_t *cnt, *items, *acnt;   // count pass (nq + 1 entries each; items, acnt optional)
+    const uint32_t *off;            // fill pass
     int *list;
+    int *overflow;
     int fill;
 };
 
-constexpr int kQStack = 128;
+constexpr int kQStackW = 1024;   // per-wave DFS stack (LDS)
 
+__device__ __forceinline__ int wave_incl_scan(int v, int lane)
+{
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(v, off);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// One wave per query.  The DFS pops up to 64 nodes at a time (one per lane),
+// appends the hit leaves in lane order and pushes the children of the other
+// hits; the resulting candidate order is deterministic.
 __global__ __launch_bounds__(kBlock) void k_cp_query(CpQueryArgs a)
 {
-    const int q = blockIdx.x * kBlock + threadIdx.x;
-    if (!a.fill && q == 0) {
+    __shared__ int stk[kBlock / 64][kQStackW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = blockIdx.x * (kBlock / 64) + wave;
+    if (!a.fill && blockIdx.x == 0 && threadIdx.x == 0) {
         a.cnt[a.nq] = 0;
         if (a.items) a.items[a.nq] = 0;
+        if (a.acnt) a.acnt[a.nq] = 0;
     }
-    if (q >= a.nq) return;
+    if (q >= a.nq) return;   // the whole wave leaves together
     const CpLevels &L = a.L;
     bool all = false, has_ball = false, has_box = false;
     double bc[3] = {0, 0, 0}, br2 = 0, blo[3] = {0, 0, 0}, bhi[3] = {0, 0, 0};
@@ -126,29 +149,127 @@ __global__ __launch_bounds__(kBlock) void k_cp_query(CpQueryArgs a)
         }
     }
     const double rs2 = a.rshort * a.rshort;
-    uint32_t n = 0;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint32_t o = a.fill ? a.off[q] : 0u;
-    int stack[kQStack];
-    int sp = 0;
-    stack[sp++] = 0;
-    while (sp > 0) {
-        const int node = stack[--sp];
-        const double *nb = a.box + 6 * node;
-        bool hit = all;
-        if (!hit && has_ball) hit = gap2_point_box(bc, nb) < br2;
-        if (!hit && has_box) hit = gap2_box_box(blo, bhi, nb) < rs2;
-        if (!hit) continue;
-        if (a.nchild[node] == 0) {
-            if (a.fill) a.list[o + n] = node;
-            ++n;
-        } else {
-            for (int ch = a.child0[node] + a.nchild[node] - 1; ch >= a.child0[node]; --ch)
-                if (sp < kQStack) stack[sp++] = ch;
+    uint32_t n = 0, nat = 0;
+    if (all) {
+        // every leaf, in node order
+        const int nn = *a.n_nodes;
+        for (int i0 = 0; i0 < nn; i0 += 64) {
+            const int node = i0 + lane;
+            const bool lf = node < nn && a.nchild[node] == 0;
+            const uint64_t m = __ballot(lf);
+            if (lf) {
+                if (a.fill) a.list[o + n + __popcll(m & lt)] = node;
+                nat += (uint32_t)(a.end[node] - a.begin[node]);
+            }
+            n += (uint32_t)__popcll(m);
+        }
+    } else {
+        int *st = stk[wave];
+        st[0] = 0;   // every lane writes the same value
+        int sp = 1;
+        while (sp > 0) {
+            const int take = sp < 64 ? sp : 64;
+            const int base = sp - take;
+            const int node = lane < take ? st[base + lane] : -1;
+            sp = base;
+            bool hit = false;
+            if (node >= 0) {
+                const double *nb = a.box + 6 * node;
+                if (has_ball) hit = gap2_point_box(bc, nb) < br2;
+                if (!hit && has_box) hit = gap2_box_box(blo, bhi, nb) < rs2;
+            }
+            const int nch = node >= 0 ? a.nchild[node] : 0;
+            const bool lf = hit && nch == 0;
+            const uint64_t m = __ballot(lf);
+            if (lf) {
+                if (a.fill) a.list[o + n + __popcll(m & lt)] = node;
+                nat += (uint32_t)(a.end[node] - a.begin[node]);
+            }
+            n += (uint32_t)__popcll(m);
+            const int nc = (hit && nch > 0) ? nch : 0;
+            const int incl = wave_incl_scan(nc, lane);
+            const int total = __shfl(incl, 63);
+            if (sp + total > kQStackW) {
+                if (lane == 0) *a.overflow = 1;
+                break;
+            }
+            const int c0 = nc > 0 ? a.child0[node] : 0;
+            for (int k = 0; k < nc; ++k) st[sp + incl - nc + k] = c0 + k;
+            sp += total;
         }
     }
-    if (!a.fill) {
+    nat = wave_sum_u32(nat);
+    if (!a.fill && lane == 0) {
         a.cnt[q] = n;
         if (a.items) a.items[q] = (n + kCpChunkLeaves - 1) / kCpChunkLeaves;
+        if (a.acnt) a.acnt[q] = nat;
+    }
+}
+
+// Classification of every candidate atom of a level-0 block, once: direct
+// (assigned to no level >= 1: full pair), short-range only (within the
+// short range of the block), or skipped.  One wave per block; the two index
+// lists keep the candidates' order.
+struct CpClassArgs {
+    CpLevels L;
+    int nq;
+    double rshort;
+    const uint32_t *cand_off;
+    const int *cand;
+    const int *begin, *end;
+    const float4 *rec;
+    int stride_f4;
+    const uint32_t *aoff;      // first slot of each block's lists
+    int *dlist, *slist;
+    uint32_t *nd, *ns;
+};
+
+__global__ __launch_bounds__(kBlock) void k_cp_classify(CpClassArgs a)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = blockIdx.x * (kBlock / 64) + wave;
+    if (q >= a.nq) return;
+    const CpLevels &L = a.L;
+    const int I = q % L.cx[0], J = (q / L.cx[0]) % L.cy[0], K = q / (L.cx[0] * L.cy[0]);
+    double blo[3], bhi[3];
+    cp_box(L, 0, I, J, K, blo, bhi);
+    const double rs2 = a.rshort * a.rshort;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t base = a.aoff[q];
+    uint32_t nd = 0, ns = 0;
+    for (uint32_t c = a.cand_off[q]; c < a.cand_off[q + 1]; ++c) {
+        const int leaf = a.cand[c];
+        const int ab = a.begin[leaf], ae = a.end[leaf];
+        for (int t0 = ab; t0 < ae; t0 += 64) {
+            const int i = t0 + lane;
+            int cls = 0;
+            if (i < ae) {
+                double y[3];
+                atom_pos(a.rec, a.stride_f4, i, y);
+                const int lvl = L.T >= 1 ? cp_accept_level(L, I, J, K, y, 1) : 0;
+                if (lvl == 0) {
+                    cls = 1;
+                } else {
+                    double g2 = 0;
+                    for (int k = 0; k < 3; ++k) {
+                        const double gg = fmax(0.0, fmax(blo[k] - y[k], y[k] - bhi[k]));
+                        g2 += gg * gg;
+                    }
+                    cls = g2 < rs2 ? 2 : 0;
+                }
+            }
+            const uint64_t m1 = __ballot(cls == 1), m2 = __ballot(cls == 2);
+            if (cls == 1) a.dlist[base + nd + __popcll(m1 & lt)] = i;
+            if (cls == 2) a.slist[base + ns + __popcll(m2 & lt)] = i;
+            nd += (uint32_t)__popcll(m1);
+            ns += (uint32_t)__popcll(m2);
+        }
+    }
+    if (lane == 0) {
+        a.nd[q] = nd;
+        a.ns[q] = ns;
     }
 }
 
@@ -183,15 +304,18 @@ struct CpFarArgs {
     unsigned long long *work;   // optional: (atom, proxy) pairs
 };
 
-// One workgroup per work item.  Each thread owns up to four proxies per pass;
-// the accepted atoms of one candidate leaf at a time are compacted (in atom
-// order) into LDS as (position relative to the cluster centre, charge) and
-// swept by every thread.
+// One workgroup per work item.  Each thread owns up to four proxies per pass.
+// The candidate atoms of the item's leaves are taken 256 at a time (one per
+// thread); those assigned to this cluster are compacted, in candidate order,
+// into LDS as (position relative to the cluster centre, charge) and swept by
+// every thread.
 template <bool ASYM>
 __global__ __launch_bounds__(kBlock) void k_cp_far(CpFarArgs a)
 {
     __shared__ float4 stg[kBlock];
     __shared__ int wcount[kBlock / 64];
+    __shared__ int pre[kCpChunkLeaves + 1];
+    __shared__ int lbeg[kCpChunkLeaves];
     const int item = blockIdx.x;
     const int cl = a.it_cl[item];
     int lvl, I, J, K;
@@ -201,6 +325,20 @@ __global__ __launch_bounds__(kBlock) void k_cp_far(CpFarArgs a)
     cp_centre(a.L, lvl, I, J, K, cc, rr);
     const int n1 = a.degree + 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c0 = a.it_c0[item], nlf = a.it_c1[item] - c0;   // <= kCpChunkLeaves
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int l = 0; l < nlf; ++l) {
+            const int leaf = a.cand[c0 + l];
+            pre[l] = acc;
+            lbeg[l] = a.begin[leaf];
+            acc += a.end[leaf] - a.begin[leaf];
+        }
+        pre[nlf] = acc;
+    }
+    __syncthreads();
+    const int natoms = pre[nlf];
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     for (int k0 = 0; k0 < a.np; k0 += kCpProxPass) {
         float px[4], py[4], pz[4];
         double aC[4], aY[4];
@@ -216,58 +354,54 @@ __global__ __launch_bounds__(kBlock) void k_cp_far(CpFarArgs a)
             aC[r] = aY[r] = 0.0;
             pC[r] = pY[r] = 0.f;
         }
-        int since_flush = 0;
-        int n_acc = 0;
-        for (int c = a.it_c0[item]; c < a.it_c1[item]; ++c) {
-            const int leaf = a.cand[c];
-            const int ab = a.begin[leaf], ae = a.end[leaf];
-            for (int t0 = ab; t0 < ae; t0 += kBlock) {
-                // filter: accepted at this cluster (coarsest well-separated level)
-                const int i = t0 + threadIdx.x;
-                bool acc = false;
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (i < ae) {
-                    double y[3];
-                    atom_pos(a.rec, a.stride_f4, i, y);
-                    acc = cp_accept_level(a.L, I << lvl, J << lvl, K << lvl, y, lvl) == lvl;
-                    v.x = (float)(y[0] - cc[0]);
-                    v.y = (float)(y[1] - cc[1]);
-                    v.z = (float)(y[2] - cc[2]);
-                    v.w = a.rec[(size_t)i * a.stride_f4].w;
+        int since_flush = 0, n_acc = 0;
+        for (int t0 = 0; t0 < natoms; t0 += kBlock) {
+            const int t = t0 + threadIdx.x;
+            bool acc = false;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (t < natoms) {
+                int l = 0;
+                while (l + 1 < nlf && pre[l + 1] <= t) ++l;
+                const int i = lbeg[l] + (t - pre[l]);
+                double y[3];
+                atom_pos(a.rec, a.stride_f4, i, y);
+                acc = cp_accept_level(a.L, I << lvl, J << lvl, K << lvl, y, lvl) == lvl;
+                v.x = (float)(y[0] - cc[0]);
+                v.y = (float)(y[1] - cc[1]);
+                v.z = (float)(y[2] - cc[2]);
+                v.w = a.rec[(size_t)i * a.stride_f4].w;
+            }
+            const uint64_t m = __ballot(acc);
+            const int pos = __popcll(m & lt);
+            __syncthreads();   // previous round's readers are done with stg
+            if (lane == 0) wcount[wave] = __popcll(m);
+            __syncthreads();
+            int base = 0, total = 0;
+            for (int w = 0; w < kBlock / 64; ++w) {
+                if (w < wave) base += wcount[w];
+                total += wcount[w];
+            }
+            if (acc) stg[base + pos] = v;
+            __syncthreads();
+            n_acc += total;
+            for (int s = 0; s < total; ++s) {
+                const float4 at = stg[s];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float dx = px[r] - at.x, dy = py[r] - at.y, dz = pz[r] - at.z;
+                    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    const float ri = __builtin_amdgcn_rsqf(d2);
+                    const float qr = at.w * ri;
+                    pC[r] += qr;
+                    if (ASYM) pY[r] = fmaf(qr, __builtin_amdgcn_exp2f(a.yk * (d2 * ri)), pY[r]);
                 }
-                const uint64_t m = __ballot(acc);
-                const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-                const int pos = __popcll(m & lt);
-                __syncthreads();   // previous round's readers are done with stg
-                if (lane == 0) wcount[wave] = __popcll(m);
-                __syncthreads();
-                int base = 0, total = 0;
-                for (int w = 0; w < kBlock / 64; ++w) {
-                    if (w < wave) base += wcount[w];
-                    total += wcount[w];
-                }
-                if (acc) stg[base + pos] = v;
-                __syncthreads();
-                n_acc += total;
-                for (int s = 0; s < total; ++s) {
-                    const float4 at = stg[s];
+                if (++since_flush == 16) {
+                    since_flush = 0;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const float dx = px[r] - at.x, dy = py[r] - at.y, dz = pz[r] - at.z;
-                        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                        const float ri = __builtin_amdgcn_rsqf(d2);
-                        const float qr = at.w * ri;
-                        pC[r] += qr;
-                        if (ASYM) pY[r] = fmaf(qr, __builtin_amdgcn_exp2f(a.yk * (d2 * ri)), pY[r]);
-                    }
-                    if (++since_flush == 16) {
-                        since_flush = 0;
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            aC[r] += (double)pC[r];
-                            aY[r] += (double)pY[r];
-                            pC[r] = pY[r] = 0.f;
-                        }
+                        aC[r] += (double)pC[r];
+                        aY[r] += (double)pY[r];
+                        pC[r] = pY[r] = 0.f;
                     }
                 }
             }
@@ -363,14 +497,12 @@ struct CpLeafArgs {
     OutParams out;
     AsymParams asym;
     const void *rec;
-    int stride_f4;
-    const int *begin, *end;
-    const uint32_t *cand_off;
-    const int *cand;
-    const double *V;       // proxy values of level >= 1 clusters
+    const uint32_t *aoff;      // first slot of each block's index lists
+    const int *dlist, *slist;  // direct / short-range atoms per block
+    const uint32_t *nd, *ns;
+    const double *V;           // proxy values of level >= 1 clusters
     int degree, np;
-    double rshort;
-    unsigned long long *work;   // optional: [0] direct pairs, [1] short-range pairs
+    unsigned long long *work;  // optional: [0] direct pairs, [1] short-range pairs
 };
 
 template <int B>
@@ -381,10 +513,9 @@ struct LeafShape {
 };
 
 // One workgroup per level-0 block: far field interpolated from the level-1
-// ancestor's proxies, then the directly summed atoms (assigned to no level
-// >= 1) with the full pair, and the short-range terms of every other atom
-// within reach.  The per-atom class is decided once per block by the
-// filtering threads and kept in LDS as index lists.
+// ancestor's proxies, then the directly summed atoms (full pair) and the
+// short-range-only atoms from the block's index lists.  Atom indices and
+// records are wave-uniform (scalar loads); no barrier in the pair loops.
 template <int NS, int LJM, bool ASYM, int B>
 __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
 {
@@ -393,24 +524,23 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
     constexpr int NT = S::threads;
     extern __shared__ double sm[];
     const int n1 = a.degree + 1;
-    double *Vs = sm;                  // [np]
+    float4 *tab = reinterpret_cast<float4 *>(sm);          // smeared-kernel table (ASYM)
+    double *Vs = sm + (ASYM ? 4 * kSmearIntervals : 0);    // [np]
     double *T1 = Vs + a.np;           // [n1][n1][B]
     double *T2 = T1 + n1 * n1 * B;    // [n1][B][B]
     double *Lb = T2 + n1 * B * B;     // [3][B][n1]
-    int *lists = reinterpret_cast<int *>(Lb + 3 * B * n1);   // [2][NT]
-    __shared__ int wcnt[2][NT / 64];
     const CpLevels &L = a.L;
     const GridParams &g = a.g;
     const int q = blockIdx.x;
     const int I = q % L.cx[0], J = (q / L.cx[0]) % L.cy[0], K = q / (L.cx[0] * L.cy[0]);
     const int i0 = I * B, j0 = J * B, k0 = K * B;
     const PairConst kc = make_pair_const(a.asym);
-    const AtomF32<NS> *__restrict__ rec = static_cast<const AtomF32<NS> *>(a.rec);
-    const float4 *rec4 = static_cast<const float4 *>(a.rec);
-    double blo[3], bhi[3];
-    cp_box(L, 0, I, J, K, blo, bhi);
-    const double rs2 = a.rshort * a.rshort;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    ConstAS<AtomF32<NS>> *rec = as_const(static_cast<const AtomF32<NS> *>(a.rec));
+    const uint32_t base = as_const(a.aoff)[q];
+    ConstAS<int> *dl = as_const(a.dlist + base);
+    ConstAS<int> *sl = as_const(a.slist + base);
+    const int ndir = (int)as_const(a.nd)[q], nsh = (int)as_const(a.ns)[q];
+    if (ASYM) load_smear_table(tab, a.asym.tab, NT);
 
     // level-1 ancestor basis tables: L_k(coordinate of the block's points)
     if (L.T >= 1) {
@@ -418,11 +548,17 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
         cp_proxy_box(L, 1, I >> 1, J >> 1, K >> 1, pb);
         for (int t = threadIdx.x; t < 3 * B; t += NT) {
             const int ax = t / B, l = t % B;
-            const int base = ax == 0 ? i0 : (ax == 1 ? j0 : k0);
+            const int b0 = ax == 0 ? i0 : (ax == 1 ? j0 : k0);
             double Lv[kMaxDeg + 1];
-            lagrange_all((base + l) * g.h[ax], pb[ax], pb[3 + ax], a.degree, Lv);
+            lagrange_all((b0 + l) * g.h[ax], pb[ax], pb[3 + ax], a.degree, Lv);
             for (int k = 0; k < n1; ++k) Lb[(ax * B + l) * n1 + k] = Lv[k];
         }
+    }
+    if (a.work && threadIdx.x == 0) {
+        const unsigned long long np_blk =
+            (unsigned long long)(min(B, g.nx - i0) * min(B, g.ny - j0) * min(B, g.nz - k0));
+        atomicAdd(&a.work[0], (unsigned long long)ndir * np_blk);
+        atomicAdd(&a.work[1], (unsigned long long)nsh * np_blk);
     }
 
     for (int pass = 0; pass < S::passes; ++pass) {
@@ -479,84 +615,35 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
         }
 
         // ---------------------------------------------- direct and short
-        const int c0 = (int)a.cand_off[q], c1 = (int)a.cand_off[q + 1];
-        for (int c = c0; c < c1; ++c) {
-            const int leaf = a.cand[c];
-            const int ab = a.begin[leaf], ae = a.end[leaf];
-            for (int t0 = ab; t0 < ae; t0 += NT) {
-                const int i = t0 + threadIdx.x;
-                int cls = 0;   // 0 skip, 1 direct (full pair), 2 short range only
-                if (i < ae) {
-                    double y[3];
-                    atom_pos(rec4, a.stride_f4, i, y);
-                    const int lvl = L.T >= 1 ? cp_accept_level(L, I, J, K, y, 1) : 0;
-                    if (lvl == 0) cls = 1;
-                    else {
-                        double gp2 = 0;
-                        for (int k = 0; k < 3; ++k) {
-                            double gg = fmax(0.0, fmax(blo[k] - y[k], y[k] - bhi[k]));
-                            gp2 += gg * gg;
-                        }
-                        cls = gp2 < rs2 ? 2 : 0;
-                    }
-                }
-                const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-                const uint64_t m1 = __ballot(cls == 1), m2 = __ballot(cls == 2);
-                __syncthreads();
-                if (lane == 0) {
-                    wcnt[0][wave] = __popcll(m1);
-                    wcnt[1][wave] = __popcll(m2);
-                }
-                __syncthreads();
-                int b1 = 0, b2 = 0, n1c = 0, n2c = 0;
-                for (int w = 0; w < NT / 64; ++w) {
-                    if (w < wave) {
-                        b1 += wcnt[0][w];
-                        b2 += wcnt[1][w];
-                    }
-                    n1c += wcnt[0][w];
-                    n2c += wcnt[1][w];
-                }
-                if (cls == 1) lists[b1 + __popcll(m1 & lt)] = i;
-                if (cls == 2) lists[NT + b2 + __popcll(m2 & lt)] = i;
-                __syncthreads();
-                if (a.work && threadIdx.x == 0 && pass == 0) {
-                    const unsigned long long np_blk =
-                        (unsigned long long)(min(B, g.nx - i0) * min(B, g.ny - j0) * min(B, g.nz - k0));
-                    atomicAdd(&a.work[0], (unsigned long long)n1c * np_blk);
-                    atomicAdd(&a.work[1], (unsigned long long)n2c * np_blk);
-                }
-                for (int s0 = 0; s0 < n1c; s0 += kAtomPad) {
-                    PairAcc<NS> p[PPT];
+        for (int s0 = 0; s0 < ndir; s0 += kAtomPad) {
+            PairAcc<NS> p[PPT];
 #pragma unroll
-                    for (int qq = 0; qq < PPT; ++qq) p[qq].zero();
-                    const int s1 = min(s0 + kAtomPad, n1c);
-                    for (int s = s0; s < s1; ++s) {
-                        const int ai = __builtin_amdgcn_readfirstlane(lists[s]);
-                        const AtomF32<NS> &at = rec[ai];
+            for (int qq = 0; qq < PPT; ++qq) p[qq].zero();
+            const int s1 = min(s0 + kAtomPad, ndir);
+#pragma unroll 2
+            for (int s = s0; s < s1; ++s) {
+                ConstAS<AtomF32<NS>> &at = rec[dl[s]];
 #pragma unroll
-                        for (int qq = 0; qq < PPT; ++qq)
-                            pair_eval<NS, LJM, ASYM, false, true>(at, gp[qq], kc, p[qq], acc[qq].hit);
-                    }
-#pragma unroll
-                    for (int qq = 0; qq < PPT; ++qq) acc[qq].template flush<LJM != LJ_NONE, ASYM>(p[qq]);
-                }
-                for (int s0 = 0; s0 < n2c; s0 += kAtomPad) {
-                    PairAcc<NS> p[PPT];
-#pragma unroll
-                    for (int qq = 0; qq < PPT; ++qq) p[qq].zero();
-                    const int s1 = min(s0 + kAtomPad, n2c);
-                    for (int s = s0; s < s1; ++s) {
-                        const int ai = __builtin_amdgcn_readfirstlane(lists[NT + s]);
-                        const AtomF32<NS> &at = rec[ai];
-#pragma unroll
-                        for (int qq = 0; qq < PPT; ++qq)
-                            pair_eval<NS, LJM, ASYM, false, false>(at, gp[qq], kc, p[qq], acc[qq].hit);
-                    }
-#pragma unroll
-                    for (int qq = 0; qq < PPT; ++qq) acc[qq].template flush<LJM != LJ_NONE, ASYM>(p[qq]);
-                }
+                for (int qq = 0; qq < PPT; ++qq)
+                    pair_eval<NS, LJM, ASYM, false, true>(at, gp[qq], kc, tab, p[qq], acc[qq].hit);
             }
+#pragma unroll
+            for (int qq = 0; qq < PPT; ++qq) acc[qq].template flush<LJM != LJ_NONE, ASYM>(p[qq]);
+        }
+        for (int s0 = 0; s0 < nsh; s0 += kAtomPad) {
+            PairAcc<NS> p[PPT];
+#pragma unroll
+            for (int qq = 0; qq < PPT; ++qq) p[qq].zero();
+            const int s1 = min(s0 + kAtomPad, nsh);
+#pragma unroll 2
+            for (int s = s0; s < s1; ++s) {
+                ConstAS<AtomF32<NS>> &at = rec[sl[s]];
+#pragma unroll
+                for (int qq = 0; qq < PPT; ++qq)
+                    pair_eval<NS, LJM, ASYM, false, false>(at, gp[qq], kc, tab, p[qq], acc[qq].hit);
+            }
+#pragma unroll
+            for (int qq = 0; qq < PPT; ++qq) acc[qq].template flush<LJM != LJ_NONE, ASYM>(p[qq]);
         }
 
 #pragma unroll
@@ -623,8 +710,9 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
 
     // queries: clusters (mode 0) and leaves (mode 1), count pass
     uint32_t *ccnt = ws.get<uint32_t>(ncl + 1), *citems = ws.get<uint32_t>(ncl + 1);
-    uint32_t *lcnt = ws.get<uint32_t>(nleaf + 1);
+    uint32_t *lcnt = ws.get<uint32_t>(nleaf + 1), *lacnt = ws.get<uint32_t>(nleaf + 1);
     uint32_t *tot = ws.get<uint32_t>(4);
+    int *overflow = ws.get<int>(1);
     if (ws.status()) return ws.status();
     CpQueryArgs qa{};
     qa.L = L;
@@ -634,15 +722,20 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     qa.child0 = t.child0;
     qa.nchild = t.nchild;
     qa.box = t.box;
+    qa.n_nodes = t.n_nodes;
+    qa.overflow = overflow;
+    const int wpb = kBlock / 64;
     {
         PhaseTimer pt(ev, RISM_PHASE_LISTS, s);
+        RISM_HIP(hipMemsetAsync(overflow, 0, sizeof(int), s));
         if (ncl > 0) {
             qa.mode = 0;
             qa.nq = ncl;
             qa.cnt = ccnt;
             qa.items = citems;
+            qa.acnt = nullptr;
             qa.fill = 0;
-            hipLaunchKernelGGL(k_cp_query, (ncl + kBlock - 1) / kBlock, kBlock, 0, s, qa);
+            hipLaunchKernelGGL(k_cp_query, (ncl + wpb - 1) / wpb, kBlock, 0, s, qa);
             hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, ccnt, ncl + 1, tot + 0);
             hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, citems, ncl + 1, tot + 1);
         }
@@ -650,18 +743,27 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         qa.nq = nleaf;
         qa.cnt = lcnt;
         qa.items = nullptr;
+        qa.acnt = lacnt;
         qa.fill = 0;
-        hipLaunchKernelGGL(k_cp_query, (nleaf + kBlock - 1) / kBlock, kBlock, 0, s, qa);
+        hipLaunchKernelGGL(k_cp_query, (nleaf + wpb - 1) / wpb, kBlock, 0, s, qa);
         hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, lcnt, nleaf + 1, tot + 2);
+        hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, lacnt, nleaf + 1, tot + 3);
     }
     RISM_HIP(hipGetLastError());
-    uint32_t ht[4] = {0, 0, 0, 0};
-    RISM_HIP(hipMemcpyAsync(ht, tot, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    uint32_t ht[5] = {0, 0, 0, 0, 0};
+    RISM_HIP(hipMemcpyAsync(ht, tot, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    RISM_HIP(hipMemcpyAsync(ht + 4, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
     RISM_HIP(hipStreamSynchronize(s));
+    if (ht[4]) {
+        set_error("treecode_cp: neighbour query stack overflow");
+        return RISM_E_UNSUPPORTED;
+    }
     if (ncl == 0) ht[0] = ht[1] = 0;
     int *ccand = ws.get<int>(ht[0] + 1), *lcand = ws.get<int>(ht[2] + 1);
     int *it_cl = ws.get<int>(ht[1] + 1), *it_c0 = ws.get<int>(ht[1] + 1),
         *it_c1 = ws.get<int>(ht[1] + 1);
+    int *dlist = ws.get<int>(ht[3] + 1), *slist = ws.get<int>(ht[3] + 1);
+    uint32_t *nd = ws.get<uint32_t>(nleaf), *nsh = ws.get<uint32_t>(nleaf);
     double *part = ws.get<double>((size_t)(ht[1] + 1) * 2 * np);
     double *V = ws.get<double>((size_t)(ncl + 1) * 2 * np);
     const bool want_stats = a.opts->flags & RISM_FLAG_STATS;
@@ -677,7 +779,8 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             qa.list = ccand;
             qa.fill = 1;
             qa.items = nullptr;
-            hipLaunchKernelGGL(k_cp_query, (ncl + kBlock - 1) / kBlock, kBlock, 0, s, qa);
+            qa.acnt = nullptr;
+            hipLaunchKernelGGL(k_cp_query, (ncl + wpb - 1) / wpb, kBlock, 0, s, qa);
             hipLaunchKernelGGL(k_cp_items, (ncl + kBlock - 1) / kBlock, kBlock, 0, s, ncl, ccnt,
                                citems, it_cl, it_c0, it_c1);
         }
@@ -686,7 +789,24 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         qa.off = lcnt;
         qa.list = lcand;
         qa.fill = 1;
-        hipLaunchKernelGGL(k_cp_query, (nleaf + kBlock - 1) / kBlock, kBlock, 0, s, qa);
+        qa.acnt = nullptr;
+        hipLaunchKernelGGL(k_cp_query, (nleaf + wpb - 1) / wpb, kBlock, 0, s, qa);
+        CpClassArgs ca{};
+        ca.L = L;
+        ca.nq = nleaf;
+        ca.rshort = rshort;
+        ca.cand_off = lcnt;
+        ca.cand = lcand;
+        ca.begin = t.begin;
+        ca.end = t.end;
+        ca.rec = static_cast<const float4 *>(t.sorted_rec);
+        ca.stride_f4 = stride_f4;
+        ca.aoff = lacnt;
+        ca.dlist = dlist;
+        ca.slist = slist;
+        ca.nd = nd;
+        ca.ns = nsh;
+        hipLaunchKernelGGL(k_cp_classify, (nleaf + wpb - 1) / wpb, kBlock, 0, s, ca);
     }
     RISM_HIP(hipGetLastError());
 
@@ -734,19 +854,20 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     la.out = a.out;
     la.asym = a.asym;
     la.rec = t.sorted_rec;
-    la.stride_f4 = stride_f4;
-    la.begin = t.begin;
-    la.end = t.end;
-    la.cand_off = lcnt;
-    la.cand = lcand;
+    la.aoff = lacnt;
+    la.dlist = dlist;
+    la.slist = slist;
+    la.nd = nd;
+    la.ns = nsh;
     la.V = V;
     la.degree = deg;
     la.np = np;
-    la.rshort = rshort;
     la.work = work;
     const int NT = B == 4 ? 64 : 256;
     const size_t shm = ((size_t)np + (size_t)n1 * n1 * B + (size_t)n1 * B * B + 3 * (size_t)B * n1) *
-                           sizeof(double) + 2 * (size_t)NT * sizeof(int);
+                           sizeof(double) +
+                       (a.asym_on ? 2 * kSmearIntervals * sizeof(float4) : 0);
+    (void)NT;
     int dev = 0, lds_max = 0;
     RISM_HIP(hipGetDevice(&dev));
     RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));

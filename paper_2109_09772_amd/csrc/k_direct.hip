@@ -251,25 +251,81 @@ int launch_direct_f64(const SiteParams &sp, const DirectArgs &a, hipStream_t s)
     return RISM_OK;
 }
 
+// ------------------------------------------------------ smeared-kernel table
+
+// erf(d/eta)/d and [e^{-kappa d} erfc(a - d/eta) - e^{kappa d} erfc(a + d/eta)]/d
+// (a = kappa eta / 2) in FP64, with their d -> 0 limits.
+__device__ inline void smear_f64(const AsymParams &A, double d, double &fc, double &fh)
+{
+    if (d == 0.0) {
+        fc = A.dcf0;
+        fh = A.tcf0;
+        return;
+    }
+    const double x = d * A.inv_eta;
+    fc = erf(x) / d;
+    const double t2 = A.a + x < 27.0 ? exp(A.kappa * d) * erfc(A.a + x) : 0.0;
+    fh = (exp(-A.kappa * d) * erfc(A.a - x) - t2) / d;
+}
+
+// One thread per interval: the cubic through the four Chebyshev nodes of the
+// interval (Newton form, expanded to monomials in the local variable t).
+__global__ void k_smear_table(AsymParams A, float4 *tab)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kSmearIntervals) return;
+    const double h = 1.0 / A.tab_inv_h;
+    double t[4], vc[4], vh[4];
+    for (int j = 0; j < 4; ++j) {
+        t[j] = 0.5 * (1.0 - cos((2 * j + 1) * kPi / 8.0));
+        smear_f64(A, (i + t[j]) * h, vc[j], vh[j]);
+    }
+    double *v[2] = {vc, vh};
+    for (int f = 0; f < 2; ++f) {
+        double d0 = v[f][0], d1 = v[f][1], d2 = v[f][2], d3 = v[f][3];
+        // divided differences
+        const double a1 = (d1 - d0) / (t[1] - t[0]);
+        const double b1 = (d2 - d1) / (t[2] - t[1]);
+        const double c1 = (d3 - d2) / (t[3] - t[2]);
+        const double a2 = (b1 - a1) / (t[2] - t[0]);
+        const double b2 = (c1 - b1) / (t[3] - t[1]);
+        const double a3 = (b2 - a2) / (t[3] - t[0]);
+        const double s3 = t[0] + t[1] + t[2];
+        const double p2 = t[0] * t[1] + t[0] * t[2] + t[1] * t[2];
+        float4 c;
+        c.w = (float)a3;
+        c.z = (float)(a2 - a3 * s3);
+        c.y = (float)(a1 - a2 * (t[0] + t[1]) + a3 * p2);
+        c.x = (float)(d0 - a1 * t[0] + a2 * t[0] * t[1] - a3 * t[0] * t[1] * t[2]);
+        tab[2 * i + f] = c;
+    }
+}
+
+int launch_smear_table(const AsymParams &a, float4 *tab, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_smear_table, (kSmearIntervals + 63) / 64, 64, 0, s, a, tab);
+    RISM_HIP(hipGetLastError());
+    return RISM_OK;
+}
+
 // ------------------------------------------------- FP32 compensated direct sum
 
 // Per pair, in FP32: d from hi/lo coordinates, 1/d by rsqrt, Coulomb Q/d,
-// Yukawa Q e^{-kappa d}/d (exp2), LJ (A r^-6 - B) r^-6 per site; within
-// R_s the smeared-kernel corrections
-//   c: -Q erfc(d/eta)/d
-//   h: -Q [e^{-kappa d} erfc(d/eta - kappa eta/2) + e^{kappa d} erfc(d/eta + kappa eta/2)]/d
-// so that erf(d/eta)/d = 1/d + c-correction and the Eq. 6 bracket over d =
-// 2 e^{-kappa d}/d + h-correction hold exactly for d < R_s and to < 1e-12
-// beyond it.  Partial sums over 8 atoms are flushed into FP64 (electrostatic
-// sums, which cancel in sign) or into TwoSum-compensated FP32 (LJ).
+// LJ (A r^-6 - B) r^-6 per site; beyond R_s the smeared kernels are 1/d and
+// 2 e^{-kappa d}/d (exp2) to < 1e-12, within R_s they come from the cubic
+// table in LDS.  Partial sums over 8 atoms are flushed into FP64
+// (electrostatic sums, which cancel in sign) or into TwoSum-compensated FP32
+// (LJ).
 template <int NS, int LJM, bool ASYM, bool EXACT>
 __global__ __launch_bounds__(kBlock) void k_direct_f32(SiteParams sp, DirectArgs a)
 {
     const GridParams &g = a.g;
     BrickIndex bi = brick_index(g);
     const GridPt gp = grid_pt(g, bi.valid ? bi.i : 0, bi.valid ? bi.j : 0, bi.valid ? bi.k : 0);
-    const AtomF32<NS> *__restrict__ atoms = static_cast<const AtomF32<NS> *>(a.atoms);
+    ConstAS<AtomF32<NS>> *atoms = as_const(static_cast<const AtomF32<NS> *>(a.atoms));
     const PairConst kc = make_pair_const(a.asym);
+    __shared__ float4 tab[ASYM ? 2 * kSmearIntervals : 1];
+    if (ASYM) load_smear_table(tab, a.asym.tab, kBlock);
     PointAcc<NS> acc;
     acc.zero();
     for (int64_t n0 = 0; n0 < a.npad; n0 += kAtomPad) {
@@ -277,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_direct_f32(SiteParams sp, DirectArgs
         p.zero();
 #pragma unroll 2
         for (int t = 0; t < kAtomPad; ++t)
-            pair_eval<NS, LJM, ASYM, EXACT, true>(atoms[n0 + t], gp, kc, p, acc.hit);
+            pair_eval<NS, LJM, ASYM, EXACT, true>(atoms[n0 + t], gp, kc, tab, p, acc.hit);
         acc.template flush<LJM != LJ_NONE, ASYM>(p);
     }
     if (!bi.valid) return;

@@ -5,9 +5,10 @@
 //          relative to the batch's first point, computed in FP64, and the
 //          FP32 proxy charge); every lane reads the same entry (broadcast).
 //  near  : atoms of the leaves that were not accepted -> the full pair
-//          (Coulomb, Yukawa, LJ within the cut-off, smeared corrections).
+//          (Coulomb, Yukawa, LJ within the cut-off, smeared kernels).
 //  short : atoms of leaves inside accepted clusters that still come within
-//          the short range of the batch -> LJ and smeared corrections only.
+//          the short range of the batch -> LJ, and the smeared kernels less
+//          1/d and 2 e^{-kappa d}/d within R_s.
 // Partial sums over 16 proxies / 8 atoms are flushed into FP64 (electrostatic
 // sums) and TwoSum FP32 (LJ), as in the direct kernel.
 #include <cmath>
@@ -41,13 +42,19 @@ __global__ __launch_bounds__(EvalShape<B>::threads) void k_tree_eval(SiteParams 
     using S = EvalShape<B>;
     constexpr int PPT = S::ppt;
     __shared__ float4 prox[kChunk];
+    __shared__ float4 tab[ASYM ? 2 * kSmearIntervals : 1];
     const GridParams &g = a.g;
     const int b = blockIdx.x;
     const int bi = b % a.l.bx, bj = (b / a.l.bx) % a.l.by, bk = b / (a.l.bx * a.l.by);
     const int i0 = bi * B, j0 = bj * B, k0 = bk * B;
     const double r0[3] = {i0 * g.h[0], j0 * g.h[1], k0 * g.h[2]};
     const PairConst kc = make_pair_const(a.asym);
-    const AtomF32<NS> *__restrict__ rec = static_cast<const AtomF32<NS> *>(a.rec);
+    if (ASYM) load_smear_table(tab, a.asym.tab, S::threads);
+    ConstAS<AtomF32<NS>> *rec = as_const(static_cast<const AtomF32<NS> *>(a.rec));
+    ConstAS<int> *begin = as_const(a.begin);
+    ConstAS<int> *end = as_const(a.end);
+    ConstAS<int> *near_l = as_const(a.l.near);
+    ConstAS<int> *short_l = as_const(a.l.shrt);
     const int n1 = a.degree + 1;
     const int f0 = a.l.far_off[b], f1 = a.l.far_off[b + 1];
     const int e0 = a.l.near_off[b], e1 = a.l.near_off[b + 1];
@@ -121,18 +128,18 @@ __global__ __launch_bounds__(EvalShape<B>::threads) void k_tree_eval(SiteParams 
 
         // ---------------------------------------------------------- near
         for (int e = e0; e < e1; ++e) {
-            const int leaf = a.l.near[e];
-            const int ab = a.begin[leaf], ae = a.end[leaf];
+            const int leaf = near_l[e];
+            const int ab = begin[leaf], ae = end[leaf];
             for (int t0 = ab; t0 < ae; t0 += kAtomPad) {
                 PairAcc<NS> p[PPT];
 #pragma unroll
                 for (int q = 0; q < PPT; ++q) p[q].zero();
                 const int tend = min(t0 + kAtomPad, ae);
                 for (int t = t0; t < tend; ++t) {
-                    const AtomF32<NS> &at = rec[t];
+                    ConstAS<AtomF32<NS>> &at = rec[t];
 #pragma unroll
                     for (int q = 0; q < PPT; ++q)
-                        pair_eval<NS, LJM, ASYM, false, true>(at, gp[q], kc, p[q], acc[q].hit);
+                        pair_eval<NS, LJM, ASYM, false, true>(at, gp[q], kc, tab, p[q], acc[q].hit);
                 }
 #pragma unroll
                 for (int q = 0; q < PPT; ++q) acc[q].template flush<LJM != LJ_NONE, ASYM>(p[q]);
@@ -142,18 +149,18 @@ __global__ __launch_bounds__(EvalShape<B>::threads) void k_tree_eval(SiteParams 
         // ---------------------------------------------------------- short
         if (LJM != LJ_NONE || ASYM) {
             for (int e = s0; e < s1; ++e) {
-                const int leaf = a.l.shrt[e];
-                const int ab = a.begin[leaf], ae = a.end[leaf];
+                const int leaf = short_l[e];
+                const int ab = begin[leaf], ae = end[leaf];
                 for (int t0 = ab; t0 < ae; t0 += kAtomPad) {
                     PairAcc<NS> p[PPT];
 #pragma unroll
                     for (int q = 0; q < PPT; ++q) p[q].zero();
                     const int tend = min(t0 + kAtomPad, ae);
                     for (int t = t0; t < tend; ++t) {
-                        const AtomF32<NS> &at = rec[t];
+                        ConstAS<AtomF32<NS>> &at = rec[t];
 #pragma unroll
                         for (int q = 0; q < PPT; ++q)
-                            pair_eval<NS, LJM, ASYM, false, false>(at, gp[q], kc, p[q],
+                            pair_eval<NS, LJM, ASYM, false, false>(at, gp[q], kc, tab, p[q],
                                                                   acc[q].hit);
                     }
 #pragma unroll

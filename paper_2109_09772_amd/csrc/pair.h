@@ -6,6 +6,7 @@
 namespace rism {
 
 struct PairConst {
+    float tinv;     // table intervals per angstrom
     float yk;       // -kappa log2(e)
     float inv_eta;  // 1/eta
     float aa;       // kappa eta / 2
@@ -17,6 +18,7 @@ struct PairConst {
 __host__ __device__ inline PairConst make_pair_const(const AsymParams &a)
 {
     PairConst c;
+    c.tinv = (float)a.tab_inv_h;
     c.yk = (float)a.yk;
     c.inv_eta = (float)a.inv_eta;
     c.aa = (float)a.a;
@@ -26,14 +28,31 @@ __host__ __device__ inline PairConst make_pair_const(const AsymParams &a)
     return c;
 }
 
+// Read-only data in the constant address space: uniform loads through such a
+// pointer are always served by the scalar data cache (s_load), also after
+// stores or atomics earlier in the kernel that would otherwise make the
+// compiler fall back to per-lane vector loads.
+template <class T>
+using ConstAS = const __attribute__((address_space(4))) T;
+
+template <class T>
+__device__ __forceinline__ ConstAS<T> *as_const(const T *p)
+{
+    return (ConstAS<T> *)p;
+}
+
 // Partial sums of one grid point over a block of sources.
+// C: Coulomb 1/d of the atoms beyond R_s (or of all atoms when the smeared
+// sums are off), CN: Coulomb 1/d within R_s, Y: e^{-kappa d}/d beyond R_s,
+// SC / SH: the smeared kernels themselves within R_s (or, for atoms whose far
+// field comes from proxies, their difference to 1/d and 2 e^{-kappa d}/d).
 template <int NS>
 struct PairAcc {
-    float C, Y, SC, SH;
+    float C, CN, Y, SC, SH;
     float L[NS];
     __device__ __forceinline__ void zero()
     {
-        C = Y = SC = SH = 0.f;
+        C = CN = Y = SC = SH = 0.f;
 #pragma unroll
         for (int s = 0; s < NS; ++s) L[s] = 0.f;
     }
@@ -43,12 +62,12 @@ struct PairAcc {
 // sign across sources), LJ sums as TwoSum-compensated FP32 pairs.
 template <int NS>
 struct PointAcc {
-    double C, Y, SC, SH;
+    double C, CN, Y, SC, SH;
     float ls[NS], lc[NS];
     bool hit;
     __device__ __forceinline__ void zero()
     {
-        C = Y = SC = SH = 0.0;
+        C = CN = Y = SC = SH = 0.0;
         hit = false;
 #pragma unroll
         for (int s = 0; s < NS; ++s) { ls[s] = 0.f; lc[s] = 0.f; }
@@ -58,6 +77,7 @@ struct PointAcc {
     {
         C += (double)p.C;
         if (ASYM) {
+            CN += (double)p.CN;
             Y += (double)p.Y;
             SC += (double)p.SC;
             SH += (double)p.SH;
@@ -90,17 +110,32 @@ __device__ __forceinline__ GridPt grid_pt(const GridParams &g, int i, int j, int
     return p;
 }
 
-// One (point, atom) pair.  FULL: Coulomb and Yukawa for every pair plus the
-// short-range terms; otherwise only the short-range terms (LJ within the
-// cut-off, smeared-kernel corrections within R_s) of an atom whose far field
-// is accounted for elsewhere.
-//   c correction: -Q erfc(d/eta)/d                          (d < R_s)
-//   h correction: -Q [e^{-kd} erfc(d/eta - a) + e^{kd} erfc(d/eta + a)]/d
-// so that 1/d + c-corr = erf(d/eta)/d and 2 e^{-kd}/d + h-corr = the Eq. 6
-// bracket over d, exactly for d < R_s and to < 1e-12 beyond.
-template <int NS, int LJM, bool ASYM, bool EXACT, bool FULL>
-__device__ __forceinline__ void pair_eval(const AtomF32<NS> &at, const GridPt &g,
-                                          const PairConst &k, PairAcc<NS> &p, bool &hit)
+// Cubic interpolation of both smeared kernels at distance d < R_s.
+__device__ __forceinline__ void smear_eval(const float4 *tab, float tinv, float d, float &gc,
+                                           float &gh)
+{
+    const float u = d * tinv;
+    int i = (int)u;
+    i = i < kSmearIntervals - 1 ? i : kSmearIntervals - 1;
+    const float t = u - (float)i;
+    const float4 c = tab[2 * i], h = tab[2 * i + 1];
+    gc = fmaf(fmaf(fmaf(c.w, t, c.z), t, c.y), t, c.x);
+    gh = fmaf(fmaf(fmaf(h.w, t, h.z), t, h.y), t, h.x);
+}
+
+// One (point, atom) pair.  FULL: every term of the atom, with the smeared
+// sums split at R_s:
+//   d >= R_s:  erf(d/eta)/d -> 1/d (into C), bracket/d -> 2 e^{-kappa d}/d (into Y),
+//              exact to < 1e-12 relative there;
+//   d <  R_s:  1/d into CN (for u only) and the smeared kernels themselves
+//              from the table (into SC, SH), so nothing cancels near an atom.
+// Not FULL (the atom's 1/d and e^{-kappa d}/d reach the point through
+// proxies): only LJ within the cut-off and, for d < R_s, the differences
+// erf(d/eta)/d - 1/d and bracket/d - 2 e^{-kappa d}/d.
+template <int NS, int LJM, bool ASYM, bool EXACT, bool FULL, class Rec>
+__device__ __forceinline__ void pair_eval(const Rec &at, const GridPt &g,
+                                          const PairConst &k, const float4 *tab, PairAcc<NS> &p,
+                                          bool &hit)
 {
     float dx, dy, dz;
     if (EXACT) {
@@ -114,8 +149,8 @@ __device__ __forceinline__ void pair_eval(const AtomF32<NS> &at, const GridPt &g
     }
     const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     // raw v_rsq_f32 (d2 is never denormal unless a point sits within 1e-19 A
-    // of an atom); a coincident point gets 1/d = 0 and is handled through
-    // `hit` and the d -> 0 limits
+    // of an atom); a coincident point gets 1/d = 0: u is set to +inf through
+    // `hit`, and the smeared kernels take their d = 0 values from the table
     const float ri = d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
     if (FULL) hit |= (d2 == 0.f);
     if (LJM != LJ_NONE) {
@@ -130,23 +165,36 @@ __device__ __forceinline__ void pair_eval(const AtomF32<NS> &at, const GridPt &g
     }
     const float aq = at.q;
     const float qr = aq * ri;
-    if (FULL) p.C += qr;
-    if (ASYM) {
-        const float d = d2 * ri;
-        const float e = __builtin_amdgcn_exp2f(k.yk * d);
-        if (FULL) p.Y = fmaf(qr, e, p.Y);
-        if (d2 < k.rs2) {
-            const float x = d * k.inv_eta;
-            p.SC = fmaf(-qr, erfcf(x), p.SC);
-            const float ep = __builtin_amdgcn_rcpf(e);
-            const float br = fmaf(e, erfcf(x - k.aa), ep * erfcf(x + k.aa));
-            p.SH = fmaf(-qr, br, p.SH);
-            if (FULL && d2 == 0.f) {
-                p.SC = fmaf(aq, k.dcf0, p.SC);
-                p.SH = fmaf(aq, k.tcf0, p.SH);
-            }
+    if (!ASYM) {
+        if (FULL) p.C += qr;
+        return;
+    }
+    const bool nearp = d2 < k.rs2;
+    const float d = d2 * ri;
+    const float e = __builtin_amdgcn_exp2f(k.yk * d);
+    if (FULL) {
+        p.C += nearp ? 0.f : qr;
+        p.CN += nearp ? qr : 0.f;
+        p.Y = fmaf(nearp ? 0.f : qr, e, p.Y);
+    }
+    if (nearp) {
+        float gc, gh;
+        smear_eval(tab, k.tinv, d, gc, gh);
+        if (FULL) {
+            p.SC = fmaf(aq, gc, p.SC);
+            p.SH = fmaf(aq, gh, p.SH);
+        } else {
+            p.SC = fmaf(aq, gc, p.SC - qr);
+            p.SH = fmaf(aq, gh, fmaf(-qr, e + e, p.SH));
         }
     }
+}
+
+// Copies the smeared-kernel table into LDS (every thread of the block).
+__device__ __forceinline__ void load_smear_table(float4 *dst, const float4 *src, int nthreads)
+{
+    for (int i = threadIdx.x; i < 2 * kSmearIntervals; i += nthreads) dst[i] = src[i];
+    __syncthreads();
 }
 
 __device__ __forceinline__ void store_val(void *base, int f64, int64_t idx, double v)
@@ -163,11 +211,12 @@ __device__ __forceinline__ void store_point(const OutParams &o, const GridParams
                                             const PointAcc<NS> &acc)
 {
     if (o.want_u) {
+        const double coul = acc.C + acc.CN;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             if (s < o.ns) {
                 double lj = LJM != LJ_NONE ? (double)acc.ls[s] + (double)acc.lc[s] : 0.0;
-                store_val(o.u, o.f64, s * g.m + p, acc.hit ? INFINITY : o.u_coul[s] * acc.C + lj);
+                store_val(o.u, o.f64, s * g.m + p, acc.hit ? INFINITY : o.u_coul[s] * coul + lj);
             }
         }
     }

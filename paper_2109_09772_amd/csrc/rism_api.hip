@@ -262,6 +262,8 @@ static void prep_asym(double eta, double kappa, double beta, double diel, double
     A.dcf0 = 2.0 / (eta * std::sqrt(kPi));
     A.tcf0 = 4.0 * std::exp(-A.a * A.a) / (eta * std::sqrt(kPi)) - 2.0 * kappa * std::erfc(A.a);
     A.yk = -kappa / std::log(2.0);
+    A.tab = nullptr;
+    A.tab_inv_h = kSmearIntervals / rs;
     int j = 0;
     for (int g = 0; g < p.sp.ns; ++g) {
         p.out.c_scale[g] = -beta * kc * p.sp.q[g];
@@ -396,6 +398,12 @@ static int forward(const rism_solute *so, const rism_sites *si, const rism_grid 
     rc = stage_atoms(so, p, op, !f64path, f64path, false, ws, &rec32, &rec64,
                      want_rcut ? &rcut : nullptr, s, &max_rcut);
     if (rc) return rc;
+    if (asym_on && !f64path) {
+        float4 *tab = ws.get<float4>(2 * kSmearIntervals);
+        if (!tab) return ws.status();
+        if ((rc = launch_smear_table(p.asym, tab, s))) return rc;
+        p.asym.tab = tab;
+    }
 
     if (u || c || h) {
         DirectArgs da{};

@@ -71,7 +71,14 @@ struct OutParams {
     double h_scale[kMaxSites];  // per ionic slot: -(beta k_C q_j/(2 eps)) e^{kappa^2 eta^2/4}
 };
 
+// Cubic table of the smeared kernels on [0, R_s] (FP32 coefficients in the
+// local variable t in [0, 1) of each interval): tab[2 i] for erf(d/eta)/d and
+// tab[2 i + 1] for the Eq. 6 bracket over d, each as (c0, c1, c2, c3).
+constexpr int kSmearIntervals = 256;
+
 struct AsymParams {
+    const float4 *tab;  // device table, 2 * kSmearIntervals entries (FP32 paths)
+    double tab_inv_h;   // intervals per angstrom: kSmearIntervals / R_s
     double eta, kappa;
     double inv_eta;     // 1/eta
     double a;           // kappa eta / 2
@@ -156,6 +163,9 @@ struct DirectArgs {
     int asym_on;        // compute the smeared sums (c and/or h)
 };
 int launch_direct_f64(const SiteParams &sp, const DirectArgs &a, hipStream_t s);
+// Fills the 2 * kSmearIntervals cubic pieces of erf(d/eta)/d and of the Eq. 6
+// bracket over d on [0, R_s] (FP64 evaluation, FP32 coefficients).
+int launch_smear_table(const AsymParams &a, float4 *tab, hipStream_t s);
 int launch_direct_f32(const SiteParams &sp, const DirectArgs &a, hipStream_t s);
 
 int launch_compare(const void *x, int f64, const double *ref, int64_t n, double cap,
