@@ -21,8 +21,10 @@ __device__ __forceinline__ double bary_weight(int k, int n)
     return (k == 0 || k == n) ? 0.5 * w : w;
 }
 
-// Lagrange basis values L_k(x), k = 0..n, of the Chebyshev points of [lo, hi].
-__device__ inline void lagrange_all(double x, double lo, double hi, int n, double *L)
+// Lagrange basis values L_k(x), k = 0..n, of the Chebyshev points of [lo, hi],
+// written to dst[k * stride] (LDS or global memory; a per-thread array with a
+// run-time bound would live in scratch memory).
+__device__ inline void lagrange_to(double x, double lo, double hi, int n, double *dst, int stride)
 {
     double den = 0.0;
     int exact = -1;
@@ -30,15 +32,19 @@ __device__ inline void lagrange_all(double x, double lo, double hi, int n, doubl
         double d = x - cheb_point(lo, hi, k, n);
         if (d == 0.0) exact = k;
         double t = bary_weight(k, n) / d;
-        L[k] = t;
+        dst[k * stride] = t;
         den += t;
     }
-    if (exact >= 0) {
-        for (int k = 0; k <= n; ++k) L[k] = k == exact ? 1.0 : 0.0;
-        return;
-    }
-    double inv = 1.0 / den;
-    for (int k = 0; k <= n; ++k) L[k] *= inv;
+    const double inv = 1.0 / den;
+    for (int k = 0; k <= n; ++k)
+        dst[k * stride] = exact >= 0 ? (k == exact ? 1.0 : 0.0) : dst[k * stride] * inv;
+}
+
+// Element ax (0, 1, 2) of a three-vector held in registers (a run-time index
+// into a private array would place it in scratch memory).
+__device__ __forceinline__ double pick3(const double *v, int ax)
+{
+    return ax == 0 ? v[0] : (ax == 1 ? v[1] : v[2]);
 }
 
 // Proxy box of a node: its tight box, padded so that no axis is degenerate.

@@ -77,10 +77,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_up1(CpLevels L, int deg, const d
         const int ext = ax == 0 ? ex : (ax == 1 ? ey : ez);
         const int base = ax == 0 ? i0 : (ax == 1 ? j0 : k0);
         double *Lt = ax == 0 ? Lx : (ax == 1 ? Ly : Lz);
-        double Lv[kMaxDeg + 1];
-        if (l < ext) lagrange_all((base + l) * L.h[ax], pb[ax], pb[3 + ax], deg, Lv);
-        else for (int k = 0; k < n1; ++k) Lv[k] = 0.0;
-        for (int k = 0; k < n1; ++k) Lt[l * n1 + k] = Lv[k];
+        if (l < ext)
+            lagrange_to((base + l) * pick3(L.h, ax), pick3(pb, ax), pick3(pb + 3, ax), deg,
+                        Lt + l * n1, 1);
+        else
+            for (int k = 0; k < n1; ++k) Lt[l * n1 + k] = 0.0;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < ez * ey * n1; t += kBlock) {
@@ -117,14 +118,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_up(CpLevels L, int lvl, int deg,
     double *src = M + 3 * n1 * n1;   // [np]
     double *t1 = src + np;
     double *t2 = t1 + np;
+    double *acc = t2 + np;           // [np], each entry owned by one thread
     const int q = blockIdx.x;
     const int I = q % L.cx[lvl], J = (q / L.cx[lvl]) % L.cy[lvl], K = q / (L.cx[lvl] * L.cy[lvl]);
     const int id = cp_id(L, lvl, I, J, K);
     double pbx[6];
     cp_proxy_box(L, lvl, I, J, K, pbx);
-    double acc[(kMaxDeg + 1) * (kMaxDeg + 1) * (kMaxDeg + 1) / kBlock + 1];
-    const int mine = (np + kBlock - 1) / kBlock;
-    for (int r = 0; r < mine; ++r) acc[r] = 0.0;
+    for (int k = threadIdx.x; k < np; k += kBlock) acc[k] = 0.0;
     for (int cz = 0; cz < 2; ++cz)
         for (int cy = 0; cy < 2; ++cy)
             for (int cx = 0; cx < 2; ++cx) {
@@ -136,9 +136,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_up(CpLevels L, int lvl, int deg,
                 __syncthreads();
                 if (threadIdx.x < 3 * n1) {
                     const int ax = threadIdx.x / n1, k = threadIdx.x % n1;
-                    double Lv[kMaxDeg + 1];
-                    lagrange_all(cheb_point(cb[ax], cb[3 + ax], k, deg), pbx[ax], pbx[3 + ax], deg, Lv);
-                    for (int m = 0; m < n1; ++m) M[(ax * n1 + k) * n1 + m] = Lv[m];
+                    lagrange_to(cheb_point(pick3(cb, ax), pick3(cb + 3, ax), k, deg), pick3(pbx, ax),
+                                pick3(pbx + 3, ax), deg, M + (ax * n1 + k) * n1, 1);
                 }
                 for (int k = threadIdx.x; k < np; k += kBlock) src[k] = What[(size_t)cid * np + k];
                 __syncthreads();
@@ -159,19 +158,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_up(CpLevels L, int lvl, int deg,
                 }
                 __syncthreads();
                 // What_P[m3][m2][m1] += sum_k3 M[2][k3][m3] t2[k3][m2][m1]
-                for (int r = 0; r < mine; ++r) {
-                    const int k = threadIdx.x + r * kBlock;
-                    if (k >= np) break;
+                for (int k = threadIdx.x; k < np; k += kBlock) {
                     const int m12 = k % (n1 * n1), m3 = k / (n1 * n1);
-                    double s = acc[r];
+                    double s = acc[k];
                     for (int k3 = 0; k3 < n1; ++k3) s += M[(2 * n1 + k3) * n1 + m3] * t2[k3 * n1 * n1 + m12];
-                    acc[r] = s;
+                    acc[k] = s;
                 }
             }
-    for (int r = 0; r < mine; ++r) {
-        const int k = threadIdx.x + r * kBlock;
-        if (k < np) What[(size_t)id * np + k] = acc[r];
-    }
+    for (int k = threadIdx.x; k < np; k += kBlock) What[(size_t)id * np + k] = acc[k];
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -460,7 +454,7 @@ int adjoint_tree(const AdjointArgs &a, Workspace &ws, rism_stats &st, hipStream_
     RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const size_t shm_up1 = (3 * (size_t)(2 * B) * n1 + (size_t)(2 * B) * (2 * B) * n1 +
                             (size_t)(2 * B) * n1 * n1) * sizeof(double);
-    const size_t shm_up = (3 * (size_t)n1 * n1 + 3 * (size_t)np) * sizeof(double);
+    const size_t shm_up = (3 * (size_t)n1 * n1 + 4 * (size_t)np) * sizeof(double);
     if (std::max(shm_up1, shm_up) > (size_t)lds_max) {
         set_error("treecode backward: degree / batch edge too large for the LDS of this device");
         return RISM_E_UNSUPPORTED;

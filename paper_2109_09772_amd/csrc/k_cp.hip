@@ -457,9 +457,8 @@ __global__ __launch_bounds__(kBlock) void k_cp_down(CpLevels L, int lvl, int deg
     cp_proxy_box(L, lvl + 1, I >> 1, J >> 1, K >> 1, pbx);
     if (threadIdx.x < 3 * n1) {
         const int ax = threadIdx.x / n1, k = threadIdx.x % n1;
-        double Lv[kMaxDeg + 1];
-        lagrange_all(cheb_point(cb[ax], cb[3 + ax], k, degree), pbx[ax], pbx[3 + ax], degree, Lv);
-        for (int m = 0; m < n1; ++m) M[(ax * n1 + k) * n1 + m] = Lv[m];
+        lagrange_to(cheb_point(pick3(cb, ax), pick3(cb + 3, ax), k, degree), pick3(pbx, ax),
+                    pick3(pbx + 3, ax), degree, M + (ax * n1 + k) * n1, 1);
     }
     for (int comp = 0; comp < 2; ++comp) {
         __syncthreads();
@@ -512,48 +511,121 @@ struct LeafShape {
     static constexpr int passes = (B * B * B) / (threads * ppt);
 };
 
-// One workgroup per level-0 block: far field interpolated from the level-1
-// ancestor's proxies, then the directly summed atoms (full pair) and the
-// short-range-only atoms from the block's index lists.  Atom indices and
-// records are wave-uniform (scalar loads); no barrier in the pair loops.
+// Atoms staged in LDS per round of the leaf kernel.
+constexpr int kCpStage = 128;
+
+// Dynamic LDS of the leaf kernel, in bytes (layout in k_cp_leaf).
+inline size_t cp_leaf_lds(int B, int degree, bool asym, size_t rec_bytes)
+{
+    const size_t n1 = degree + 1, np = n1 * n1 * n1;
+    const size_t ncomp = asym ? 2 : 1;
+    const size_t uni = std::max((np + n1 * n1 * B) * sizeof(double), kCpStage * rec_bytes);
+    return (asym ? 2 * kSmearIntervals * sizeof(float4) : 0) +
+           (ncomp * n1 * B * B + 3 * (size_t)B * n1) * sizeof(double) + uni;
+}
+
+// The staged atoms against the PPT points of this thread, flushed every
+// kAtomPad atoms.
+template <int NS, int LJM, bool ASYM, bool EXACT, bool FULL, int PPT>
+__device__ __forceinline__ void leaf_atoms(const AtomF32<NS> *st, int cnt, const GridPt *gp,
+                                           const PairConst &kc, const float4 *tab,
+                                           PointAcc<NS> *acc)
+{
+    for (int s0 = 0; s0 < cnt; s0 += kAtomPad) {
+        PairAcc<NS> p[PPT];
+#pragma unroll
+        for (int qq = 0; qq < PPT; ++qq) p[qq].zero();
+        const int s1 = min(s0 + kAtomPad, cnt);
+#pragma unroll 2
+        for (int s = s0; s < s1; ++s) {
+            const AtomF32<NS> &at = st[s];
+#pragma unroll
+            for (int qq = 0; qq < PPT; ++qq)
+                pair_eval<NS, LJM, ASYM, EXACT, FULL>(at, gp[qq], kc, tab, p[qq], acc[qq].hit);
+        }
+#pragma unroll
+        for (int qq = 0; qq < PPT; ++qq) acc[qq].template flush<LJM != LJ_NONE, ASYM>(p[qq]);
+    }
+}
+
+// One workgroup per level-0 block.  Far field: the level-1 ancestor's proxy
+// values interpolated onto the block by three one-axis contractions (the
+// first two once per block, into LDS; the last per point).  Near field: the
+// block's direct atoms (full pair) and short-range atoms (LJ and the smeared
+// kernels less their far-field forms), gathered from the sorted records into
+// LDS in rounds of kCpStage atoms and read back as broadcasts.
+//
+// LDS: [smeared table (ASYM)] [T2 per component: n1 x B x B] [Lb: 3 x B x n1]
+//      [union: Vs (np) + T1 (n1 x n1 x B) while interpolating | atom stage]
 template <int NS, int LJM, bool ASYM, int B>
 __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
 {
     using S = LeafShape<B>;
     constexpr int PPT = S::ppt;
     constexpr int NT = S::threads;
+    constexpr int NCOMP = ASYM ? 2 : 1;
+    constexpr int R4 = sizeof(AtomF32<NS>) / sizeof(float4);
+    static_assert(sizeof(AtomF32<NS>) % sizeof(float4) == 0, "record size");
     extern __shared__ double sm[];
     const int n1 = a.degree + 1;
-    float4 *tab = reinterpret_cast<float4 *>(sm);          // smeared-kernel table (ASYM)
-    double *Vs = sm + (ASYM ? 4 * kSmearIntervals : 0);    // [np]
-    double *T1 = Vs + a.np;           // [n1][n1][B]
-    double *T2 = T1 + n1 * n1 * B;    // [n1][B][B]
-    double *Lb = T2 + n1 * B * B;     // [3][B][n1]
+    float4 *tab = reinterpret_cast<float4 *>(sm);
+    double *T2 = sm + (ASYM ? 4 * kSmearIntervals : 0);   // [NCOMP][n1][B][B]
+    double *Lb = T2 + NCOMP * n1 * B * B;                  // [3][B][n1]
+    double *Vs = Lb + 3 * B * n1;                          // [np]
+    double *T1 = Vs + a.np;                                // [n1][n1][B]
+    AtomF32<NS> *stage = reinterpret_cast<AtomF32<NS> *>(Vs);
     const CpLevels &L = a.L;
     const GridParams &g = a.g;
     const int q = blockIdx.x;
     const int I = q % L.cx[0], J = (q / L.cx[0]) % L.cy[0], K = q / (L.cx[0] * L.cy[0]);
     const int i0 = I * B, j0 = J * B, k0 = K * B;
     const PairConst kc = make_pair_const(a.asym);
-    ConstAS<AtomF32<NS>> *rec = as_const(static_cast<const AtomF32<NS> *>(a.rec));
+    const float4 *rec4 = static_cast<const float4 *>(a.rec);
     const uint32_t base = as_const(a.aoff)[q];
-    ConstAS<int> *dl = as_const(a.dlist + base);
-    ConstAS<int> *sl = as_const(a.slist + base);
+    const int *dl = a.dlist + base;
+    const int *sl = a.slist + base;
     const int ndir = (int)as_const(a.nd)[q], nsh = (int)as_const(a.ns)[q];
-    if (ASYM) load_smear_table(tab, a.asym.tab, NT);
+    if (ASYM)
+        for (int i = threadIdx.x; i < 2 * kSmearIntervals; i += NT) tab[i] = a.asym.tab[i];
 
-    // level-1 ancestor basis tables: L_k(coordinate of the block's points)
+    // ------------------------------- far: first two contractions, per block
     if (L.T >= 1) {
         double pb[6];
         cp_proxy_box(L, 1, I >> 1, J >> 1, K >> 1, pb);
+        // level-1 ancestor basis tables: L_k(coordinate of the block's points)
         for (int t = threadIdx.x; t < 3 * B; t += NT) {
             const int ax = t / B, l = t % B;
             const int b0 = ax == 0 ? i0 : (ax == 1 ? j0 : k0);
-            double Lv[kMaxDeg + 1];
-            lagrange_all((b0 + l) * g.h[ax], pb[ax], pb[3 + ax], a.degree, Lv);
-            for (int k = 0; k < n1; ++k) Lb[(ax * B + l) * n1 + k] = Lv[k];
+            lagrange_to((b0 + l) * pick3(g.h, ax), pick3(pb, ax), pick3(pb + 3, ax), a.degree,
+                        Lb + (ax * B + l) * n1, 1);
+        }
+        const int a1 = cp_id(L, 1, I >> 1, J >> 1, K >> 1);
+        for (int comp = 0; comp < NCOMP; ++comp) {
+            __syncthreads();
+            for (int k = threadIdx.x; k < a.np; k += NT)
+                Vs[k] = a.V[((size_t)a1 * 2 + comp) * a.np + k];
+            __syncthreads();
+            // T1[k1][k2][z] = sum_k3 V[k3][k2][k1] Lz[z][k3]
+            for (int t = threadIdx.x; t < n1 * n1 * B; t += NT) {
+                const int z = t % B, k12 = t / B;
+                double s = 0;
+                for (int k3 = 0; k3 < n1; ++k3) s += Vs[k3 * n1 * n1 + k12] * Lb[(2 * B + z) * n1 + k3];
+                T1[t] = s;
+            }
+            __syncthreads();
+            // T2[k1][y][z] = sum_k2 T1[k1][k2][z] Ly[y][k2]     (k12 = k2 n1 + k1)
+            double *T2c = T2 + comp * n1 * B * B;
+            for (int t = threadIdx.x; t < n1 * B * B; t += NT) {
+                const int z = t % B, y = (t / B) % B, k1 = t / (B * B);
+                double s = 0;
+                for (int k2 = 0; k2 < n1; ++k2)
+                    s += T1[(k2 * n1 + k1) * B + z] * Lb[(1 * B + y) * n1 + k2];
+                T2c[t] = s;
+            }
         }
     }
+    __syncthreads();
+
     if (a.work && threadIdx.x == 0) {
         const unsigned long long np_blk =
             (unsigned long long)(min(B, g.nx - i0) * min(B, g.ny - j0) * min(B, g.nz - k0));
@@ -578,36 +650,15 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
             acc[qq].zero();
         }
 
-        // ---------------------------------------------- far: interpolation
+        // ---------------------------------------------- far: last contraction
         if (L.T >= 1) {
-            const int a1 = cp_id(L, 1, I >> 1, J >> 1, K >> 1);
-            for (int comp = 0; comp < (ASYM ? 2 : 1); ++comp) {
-                __syncthreads();
-                for (int k = threadIdx.x; k < a.np; k += NT)
-                    Vs[k] = a.V[((size_t)a1 * 2 + comp) * a.np + k];
-                __syncthreads();
-                // T1[k1][k2][z] = sum_k3 V[k3][k2][k1] Lz[z][k3]
-                for (int t = threadIdx.x; t < n1 * n1 * B; t += NT) {
-                    const int z = t % B, k12 = t / B;
-                    double s = 0;
-                    for (int k3 = 0; k3 < n1; ++k3) s += Vs[k3 * n1 * n1 + k12] * Lb[(2 * B + z) * n1 + k3];
-                    T1[t] = s;
-                }
-                __syncthreads();
-                // T2[k1][y][z] = sum_k2 T1[k1][k2][z] Ly[y][k2]     (k12 = k2 n1 + k1)
-                for (int t = threadIdx.x; t < n1 * B * B; t += NT) {
-                    const int z = t % B, y = (t / B) % B, k1 = t / (B * B);
-                    double s = 0;
-                    for (int k2 = 0; k2 < n1; ++k2)
-                        s += T1[(k2 * n1 + k1) * B + z] * Lb[(1 * B + y) * n1 + k2];
-                    T2[t] = s;
-                }
-                __syncthreads();
 #pragma unroll
-                for (int qq = 0; qq < PPT; ++qq) {
+            for (int qq = 0; qq < PPT; ++qq) {
+                for (int comp = 0; comp < NCOMP; ++comp) {
+                    const double *T2c = T2 + comp * n1 * B * B;
                     double s = 0;
                     for (int k1 = 0; k1 < n1; ++k1)
-                        s += T2[(k1 * B + lj[qq]) * B + lk[qq]] * Lb[(0 * B + li[qq]) * n1 + k1];
+                        s += T2c[(k1 * B + lj[qq]) * B + lk[qq]] * Lb[(0 * B + li[qq]) * n1 + k1];
                     if (comp == 0) acc[qq].C = s;
                     else acc[qq].Y = s;
                 }
@@ -615,35 +666,31 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
         }
 
         // ---------------------------------------------- direct and short
-        for (int s0 = 0; s0 < ndir; s0 += kAtomPad) {
-            PairAcc<NS> p[PPT];
-#pragma unroll
-            for (int qq = 0; qq < PPT; ++qq) p[qq].zero();
-            const int s1 = min(s0 + kAtomPad, ndir);
-#pragma unroll 2
-            for (int s = s0; s < s1; ++s) {
-                ConstAS<AtomF32<NS>> &at = rec[dl[s]];
-#pragma unroll
-                for (int qq = 0; qq < PPT; ++qq)
-                    pair_eval<NS, LJM, ASYM, false, true>(at, gp[qq], kc, tab, p[qq], acc[qq].hit);
+        for (int lst = 0; lst < 2; ++lst) {
+            if (lst == 1 && !(LJM != LJ_NONE || ASYM)) break;
+            const int cnt_all = lst == 0 ? ndir : nsh;
+            const int *il = lst == 0 ? dl : sl;
+            for (int c0 = 0; c0 < cnt_all; c0 += kCpStage) {
+                const int cnt = min(kCpStage, cnt_all - c0);
+                __syncthreads();
+                float4 *dst = reinterpret_cast<float4 *>(stage);
+                for (int t = threadIdx.x; t < cnt * R4; t += NT) {
+                    const int at = t / R4;
+                    dst[t] = rec4[(size_t)il[c0 + at] * R4 + (t - at * R4)];
+                }
+                __syncthreads();
+                if (g.exact) {
+                    if (lst == 0)
+                        leaf_atoms<NS, LJM, ASYM, true, true, PPT>(stage, cnt, gp, kc, tab, acc);
+                    else
+                        leaf_atoms<NS, LJM, ASYM, true, false, PPT>(stage, cnt, gp, kc, tab, acc);
+                } else {
+                    if (lst == 0)
+                        leaf_atoms<NS, LJM, ASYM, false, true, PPT>(stage, cnt, gp, kc, tab, acc);
+                    else
+                        leaf_atoms<NS, LJM, ASYM, false, false, PPT>(stage, cnt, gp, kc, tab, acc);
+                }
             }
-#pragma unroll
-            for (int qq = 0; qq < PPT; ++qq) acc[qq].template flush<LJM != LJ_NONE, ASYM>(p[qq]);
-        }
-        for (int s0 = 0; s0 < nsh; s0 += kAtomPad) {
-            PairAcc<NS> p[PPT];
-#pragma unroll
-            for (int qq = 0; qq < PPT; ++qq) p[qq].zero();
-            const int s1 = min(s0 + kAtomPad, nsh);
-#pragma unroll 2
-            for (int s = s0; s < s1; ++s) {
-                ConstAS<AtomF32<NS>> &at = rec[sl[s]];
-#pragma unroll
-                for (int qq = 0; qq < PPT; ++qq)
-                    pair_eval<NS, LJM, ASYM, false, false>(at, gp[qq], kc, tab, p[qq], acc[qq].hit);
-            }
-#pragma unroll
-            for (int qq = 0; qq < PPT; ++qq) acc[qq].template flush<LJM != LJ_NONE, ASYM>(p[qq]);
         }
 
 #pragma unroll
@@ -863,11 +910,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     la.degree = deg;
     la.np = np;
     la.work = work;
-    const int NT = B == 4 ? 64 : 256;
-    const size_t shm = ((size_t)np + (size_t)n1 * n1 * B + (size_t)n1 * B * B + 3 * (size_t)B * n1) *
-                           sizeof(double) +
-                       (a.asym_on ? 2 * kSmearIntervals * sizeof(float4) : 0);
-    (void)NT;
+    const size_t shm = cp_leaf_lds(B, deg, a.asym_on, rec32_bytes_of(a.sp.ns_pad));
     int dev = 0, lds_max = 0;
     RISM_HIP(hipGetDevice(&dev));
     RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));

@@ -371,13 +371,12 @@ __global__ __launch_bounds__(kBlock) void k_upward_level(const float4 *rec, int 
     double *qc = qa + kTile;                // [np] child proxies
     double *t1 = qc + np;                   // [np]
     double *t2 = t1 + np;                   // [np]
+    double *acc = t2 + np;                  // [np], each entry owned by one thread
     for (int node = s0 + blockIdx.x; node < s1; node += gridDim.x) {
         double pb[6];
         proxy_box(box + 6 * node, pb);
-        if (threadIdx.x < 6) pbox[6 * node + threadIdx.x] = pb[threadIdx.x];
-        double acc[(kMaxDeg + 1) * (kMaxDeg + 1) * (kMaxDeg + 1) / kBlock + 1];
-        const int mine = (np + kBlock - 1) / kBlock;
-        for (int r = 0; r < mine; ++r) acc[r] = 0.0;
+        if (threadIdx.x < 6) pbox[6 * node + threadIdx.x] = pick3(threadIdx.x < 3 ? pb : pb + 3, threadIdx.x % 3);
+        for (int k = threadIdx.x; k < np; k += kBlock) acc[k] = 0.0;
         if (nchild[node] == 0) {
             for (int t0 = begin[node]; t0 < end[node]; t0 += kTile) {
                 const int cnt = min(kTile, end[node] - t0);
@@ -386,24 +385,18 @@ __global__ __launch_bounds__(kBlock) void k_upward_level(const float4 *rec, int 
                     const int i = t0 + threadIdx.x;
                     float4 a = rec[(size_t)i * stride_f4];
                     float4 b = rec[(size_t)i * stride_f4 + 1];
-                    double L[kMaxDeg + 1];
-                    lagrange_all((double)a.x + b.x, pb[0], pb[3], deg, L);
-                    for (int k = 0; k < n1; ++k) Lx[threadIdx.x * n1 + k] = L[k];
-                    lagrange_all((double)a.y + b.y, pb[1], pb[4], deg, L);
-                    for (int k = 0; k < n1; ++k) Ly[threadIdx.x * n1 + k] = L[k];
-                    lagrange_all((double)a.z + b.z, pb[2], pb[5], deg, L);
-                    for (int k = 0; k < n1; ++k) Lz[threadIdx.x * n1 + k] = L[k];
+                    lagrange_to((double)a.x + b.x, pb[0], pb[3], deg, Lx + threadIdx.x * n1, 1);
+                    lagrange_to((double)a.y + b.y, pb[1], pb[4], deg, Ly + threadIdx.x * n1, 1);
+                    lagrange_to((double)a.z + b.z, pb[2], pb[5], deg, Lz + threadIdx.x * n1, 1);
                     qa[threadIdx.x] = (double)a.w;
                 }
                 __syncthreads();
-                for (int r = 0; r < mine; ++r) {
-                    const int k = threadIdx.x + r * kBlock;
-                    if (k >= np) break;
+                for (int k = threadIdx.x; k < np; k += kBlock) {
                     const int k1 = k % n1, k2 = (k / n1) % n1, k3 = k / (n1 * n1);
-                    double s = acc[r];
+                    double s = acc[k];
                     for (int j = 0; j < cnt; ++j)
                         s += qa[j] * Lx[j * n1 + k1] * Ly[j * n1 + k2] * Lz[j * n1 + k3];
-                    acc[r] = s;
+                    acc[k] = s;
                 }
             }
         } else {
@@ -414,10 +407,9 @@ __global__ __launch_bounds__(kBlock) void k_upward_level(const float4 *rec, int 
                 // interpolation matrices M[k][m] = L^P_k(s^c_m), per axis
                 if (threadIdx.x < 3 * n1) {
                     const int ax = threadIdx.x / n1, m = threadIdx.x % n1;
-                    double L[kMaxDeg + 1];
-                    lagrange_all(cheb_point(cb[ax], cb[3 + ax], m, deg), pb[ax], pb[3 + ax], deg, L);
                     double *M = ax == 0 ? Lx : (ax == 1 ? Ly : Lz);
-                    for (int k = 0; k < n1; ++k) M[k * n1 + m] = L[k];
+                    lagrange_to(cheb_point(pick3(cb, ax), pick3(cb + 3, ax), m, deg), pick3(pb, ax),
+                                pick3(pb + 3, ax), deg, M + m, n1);
                 }
                 for (int k = threadIdx.x; k < np; k += kBlock) qc[k] = pq[(size_t)c * np + k];
                 __syncthreads();
@@ -436,20 +428,15 @@ __global__ __launch_bounds__(kBlock) void k_upward_level(const float4 *rec, int 
                     t2[k] = s;
                 }
                 __syncthreads();
-                for (int r = 0; r < mine; ++r) {
-                    const int k = threadIdx.x + r * kBlock;
-                    if (k >= np) break;
+                for (int k = threadIdx.x; k < np; k += kBlock) {
                     const int k12 = k % (n1 * n1), k3 = k / (n1 * n1);
-                    double s = acc[r];
+                    double s = acc[k];
                     for (int m3 = 0; m3 < n1; ++m3) s += Lz[k3 * n1 + m3] * t2[m3 * n1 * n1 + k12];
-                    acc[r] = s;
+                    acc[k] = s;
                 }
             }
         }
-        for (int r = 0; r < mine; ++r) {
-            const int k = threadIdx.x + r * kBlock;
-            if (k < np) pq[(size_t)node * np + k] = acc[r];
-        }
+        for (int k = threadIdx.x; k < np; k += kBlock) pq[(size_t)node * np + k] = acc[k];
         __syncthreads();
     }
 }
@@ -668,7 +655,7 @@ int build_proxies(const TreeDev &t, int degree, Workspace &ws, ProxyDev &p, int 
     p.q = ws.get<double>((size_t)n_nodes * p.np);
     p.pbox = ws.get<double>((size_t)n_nodes * 6);
     if (ws.status()) return ws.status();
-    const size_t shm = (3 * (size_t)kTile * n1 + kTile + 3 * (size_t)p.np) * sizeof(double);
+    const size_t shm = (3 * (size_t)kTile * n1 + kTile + 4 * (size_t)p.np) * sizeof(double);
     int dev = 0, lds_max = 0;
     RISM_HIP(hipGetDevice(&dev));
     RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
