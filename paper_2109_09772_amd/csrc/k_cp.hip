@@ -273,6 +273,36 @@ __global__ __launch_bounds__(kBlock) void k_cp_classify(CpClassArgs a)
     }
 }
 
+// Launch order of the leaf kernel: blocks sorted by decreasing work (number
+// of direct plus short-range atoms, in power-of-two classes), so that the
+// heaviest blocks start first and the light ones fill the end of the launch.
+// Results do not depend on the order.  One workgroup.
+constexpr int kCostClasses = 33;
+__device__ __forceinline__ int cost_class(uint32_t c)
+{
+    return c == 0 ? 0 : 32 - __clz(c);
+}
+__global__ __launch_bounds__(1024) void k_cp_order(int nq, const uint32_t *nd, const uint32_t *ns,
+                                                   int *order)
+{
+    __shared__ unsigned int cnt[kCostClasses];
+    if (threadIdx.x < kCostClasses) cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int q = threadIdx.x; q < nq; q += blockDim.x) atomicAdd(&cnt[cost_class(nd[q] + ns[q])], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int run = 0;
+        for (int c = kCostClasses - 1; c >= 0; --c) {
+            const unsigned int k = cnt[c];
+            cnt[c] = run;
+            run += k;
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nq; q += blockDim.x)
+        order[atomicAdd(&cnt[cost_class(nd[q] + ns[q])], 1u)] = q;
+}
+
 // Work items of the far kernel: (cluster, first candidate, last candidate).
 __global__ __launch_bounds__(kBlock) void k_cp_items(int nq, const uint32_t *cand_off,
                                                      const uint32_t *item_off, int *it_cl,
@@ -499,6 +529,7 @@ struct CpLeafArgs {
     const uint32_t *aoff;      // first slot of each block's index lists
     const int *dlist, *slist;  // direct / short-range atoms per block
     const uint32_t *nd, *ns;
+    const int *order;          // block -> level-0 block, heaviest first
     const double *V;           // proxy values of level >= 1 clusters
     int degree, np;
     unsigned long long *work;  // optional: [0] direct pairs, [1] short-range pairs
@@ -576,7 +607,7 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
     AtomF32<NS> *stage = reinterpret_cast<AtomF32<NS> *>(Vs);
     const CpLevels &L = a.L;
     const GridParams &g = a.g;
-    const int q = blockIdx.x;
+    const int q = as_const(a.order)[blockIdx.x];
     const int I = q % L.cx[0], J = (q / L.cx[0]) % L.cy[0], K = q / (L.cx[0] * L.cy[0]);
     const int i0 = I * B, j0 = J * B, k0 = K * B;
     const PairConst kc = make_pair_const(a.asym);
@@ -906,6 +937,9 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     la.slist = slist;
     la.nd = nd;
     la.ns = nsh;
+    int *order = ws.get<int>(nleaf);
+    if (!order) return ws.status();
+    la.order = order;
     la.V = V;
     la.degree = deg;
     la.np = np;
@@ -920,6 +954,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     }
     {
         PhaseTimer pt(ev, RISM_PHASE_EVAL, s);
+        hipLaunchKernelGGL(k_cp_order, 1, 1024, 0, s, nleaf, nd, nsh, order);
         switch (a.sp.ns_pad) {
         case 1: launch_leaf_ns<1>(a.lj_mode, a.asym_on, B, nleaf, shm, la, s); break;
         case 2: launch_leaf_ns<2>(a.lj_mode, a.asym_on, B, nleaf, shm, la, s); break;
