@@ -88,7 +88,13 @@ struct CpQueryArgs {
     int fill;
 };
 
-constexpr int kQStackW = 1024;   // per-wave DFS stack (LDS)
+// Per-wave DFS stack of the neighbour queries (LDS, one wave per
+// workgroup).  A step pops up to 64 nodes from the top and pushes at most 8
+// children each; below the newest layer the stack keeps at most one partial
+// layer of at most 7 x 64 nodes per tree depth, so a tree of depth D =
+// kMortonBits needs at most 448 (D - 1) + 512 = 4544 slots.
+constexpr int kQStackW = 4608;
+static_assert(kQStackW >= 448 * (kMortonBits - 1) + 512, "query stack bound");
 
 __device__ __forceinline__ int wave_incl_scan(int v, int lane)
 {
@@ -108,11 +114,11 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
 // One wave per query.  The DFS pops up to 64 nodes at a time (one per lane),
 // appends the hit leaves in lane order and pushes the children of the other
 // hits; the resulting candidate order is deterministic.
-__global__ __launch_bounds__(kBlock) void k_cp_query(CpQueryArgs a)
+__global__ __launch_bounds__(64) void k_cp_query(CpQueryArgs a)
 {
-    __shared__ int stk[kBlock / 64][kQStackW];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int q = blockIdx.x * (kBlock / 64) + wave;
+    __shared__ int stk[kQStackW];
+    const int lane = threadIdx.x;
+    const int q = blockIdx.x;
     if (!a.fill && blockIdx.x == 0 && threadIdx.x == 0) {
         a.cnt[a.nq] = 0;
         if (a.items) a.items[a.nq] = 0;
@@ -166,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_cp_query(CpQueryArgs a)
             n += (uint32_t)__popcll(m);
         }
     } else {
-        int *st = stk[wave];
+        int *st = stk;
         st[0] = 0;   // every lane writes the same value
         int sp = 1;
         while (sp > 0) {
@@ -813,7 +819,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             qa.items = citems;
             qa.acnt = nullptr;
             qa.fill = 0;
-            hipLaunchKernelGGL(k_cp_query, (ncl + wpb - 1) / wpb, kBlock, 0, s, qa);
+            hipLaunchKernelGGL(k_cp_query, ncl, 64, 0, s, qa);
             hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, ccnt, ncl + 1, tot + 0);
             hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, citems, ncl + 1, tot + 1);
         }
@@ -823,7 +829,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         qa.items = nullptr;
         qa.acnt = lacnt;
         qa.fill = 0;
-        hipLaunchKernelGGL(k_cp_query, (nleaf + wpb - 1) / wpb, kBlock, 0, s, qa);
+        hipLaunchKernelGGL(k_cp_query, nleaf, 64, 0, s, qa);
         hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, lcnt, nleaf + 1, tot + 2);
         hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, lacnt, nleaf + 1, tot + 3);
     }
@@ -858,7 +864,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             qa.fill = 1;
             qa.items = nullptr;
             qa.acnt = nullptr;
-            hipLaunchKernelGGL(k_cp_query, (ncl + wpb - 1) / wpb, kBlock, 0, s, qa);
+            hipLaunchKernelGGL(k_cp_query, ncl, 64, 0, s, qa);
             hipLaunchKernelGGL(k_cp_items, (ncl + kBlock - 1) / kBlock, kBlock, 0, s, ncl, ccnt,
                                citems, it_cl, it_c0, it_c1);
         }
@@ -868,7 +874,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         qa.list = lcand;
         qa.fill = 1;
         qa.acnt = nullptr;
-        hipLaunchKernelGGL(k_cp_query, (nleaf + wpb - 1) / wpb, kBlock, 0, s, qa);
+        hipLaunchKernelGGL(k_cp_query, nleaf, 64, 0, s, qa);
         CpClassArgs ca{};
         ca.L = L;
         ca.nq = nleaf;

@@ -292,6 +292,28 @@ def smooth_upstream(grid: Grid, sites: Sites, seed: int, filt_sigma=2.0) -> np.n
     return out
 
 
+def analytic_upstream(grid: Grid, sites: Sites, seed: int, wavelength=(12.0, 20.0)) -> np.ndarray:
+    """A smooth seeded upstream for grids too large to filter white noise:
+    dL/du_gamma = rho_gamma * g_gamma, g_gamma = 1.5 + 1.5 fx(x) fy(y) fz(z)
+    with fa = sin(2 pi a / L_a + phi_a), wavelengths and phases drawn per site
+    and axis, so that g lies in [0, 3].  FP32, shape [S][nz][ny][nx]."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = (int(v) for v in grid.dims)
+    out = np.empty((sites.n, nz, ny, nx), dtype=np.float32)
+    for s in range(sites.n):
+        f = []
+        for ax, n in enumerate((nx, ny, nz)):
+            lam = rng.uniform(*wavelength)
+            phi = rng.uniform(0.0, 2.0 * np.pi)
+            a = grid.origin[ax] + grid.spacing[ax] * np.arange(n)
+            f.append(np.sin(2.0 * np.pi * a / lam + phi).astype(np.float32))
+        g = f[2][:, None, None] * f[1][None, :, None]
+        out[s] = f[0][None, None, :] * g
+        out[s] *= np.float32(1.5 * sites.rho[s])
+        out[s] += np.float32(1.5 * sites.rho[s])
+    return out
+
+
 def sample_points(grid: Grid, n: int, seed: int) -> np.ndarray:
     """Indices (n, 3) as (i, j, k) of distinct random grid points."""
     rng = np.random.default_rng(seed)
