@@ -80,10 +80,15 @@ __device__ inline int cp_id(const CpLevels &L, int lvl, int I, int J, int K)
 
 __device__ inline bool cp_mac(const CpLevels &L, int lvl, int I, int J, int K, const double y[3])
 {
-    double c[3], r;
-    cp_centre(L, lvl, I, J, K, c, r);
-    const double dx = y[0] - c[0], dy = y[1] - c[1], dz = y[2] - c[2];
-    return r * r < L.theta * L.theta * (dx * dx + dy * dy + dz * dz);
+    double lo[3], hi[3];
+    cp_box(L, lvl, I, J, K, lo, hi);
+    double r2 = 0, d2 = 0;
+    for (int k = 0; k < 3; ++k) {
+        const double w = hi[k] - lo[k], d = y[k] - 0.5 * (lo[k] + hi[k]);
+        r2 += 0.25 * w * w;
+        d2 += d * d;
+    }
+    return r2 < L.theta * L.theta * d2;
 }
 
 // Coarsest level in [stop, T] along the chain of the level-0 block (I0, J0,

@@ -34,8 +34,7 @@ namespace rism {
 
 namespace {
 
-constexpr int kCpChunkLeaves = 16;   // candidate source leaves per far work item
-constexpr int kCpProxPass = 1024;    // proxies per pass of the far kernel (4 per thread)
+constexpr int kCpChunkLeaves = 32;   // candidate source leaves per far work item
 
 // ----------------------------------------------------------------- scans
 
@@ -84,6 +83,7 @@ struct CpQueryArgs {
     uint32_t *cnt, *items, *acnt;   // count pass (nq + 1 entries each; items, acnt optional)
     const uint32_t *off;            // fill pass
     int *list;
+    uint32_t *apre;                 // fill pass, optional: candidate atoms before each entry
     int *overflow;
     int fill;
 };
@@ -102,12 +102,6 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane)
         const int t = __shfl_up(v, off);
         if (lane >= off) v += t;
     }
-    return v;
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
-{
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     return v;
 }
 
@@ -157,7 +151,7 @@ __global__ __launch_bounds__(64) void k_cp_query(CpQueryArgs a)
     const double rs2 = a.rshort * a.rshort;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint32_t o = a.fill ? a.off[q] : 0u;
-    uint32_t n = 0, nat = 0;
+    uint32_t n = 0, nat = 0;   // wave-uniform running counts of leaves and atoms
     if (all) {
         // every leaf, in node order
         const int nn = *a.n_nodes;
@@ -165,11 +159,15 @@ __global__ __launch_bounds__(64) void k_cp_query(CpQueryArgs a)
             const int node = i0 + lane;
             const bool lf = node < nn && a.nchild[node] == 0;
             const uint64_t m = __ballot(lf);
-            if (lf) {
-                if (a.fill) a.list[o + n + __popcll(m & lt)] = node;
-                nat += (uint32_t)(a.end[node] - a.begin[node]);
+            const int sz = lf ? a.end[node] - a.begin[node] : 0;
+            const int incl = wave_incl_scan(sz, lane);
+            if (lf && a.fill) {
+                const uint32_t at = o + n + (uint32_t)__popcll(m & lt);
+                a.list[at] = node;
+                if (a.apre) a.apre[at] = nat + (uint32_t)(incl - sz);
             }
             n += (uint32_t)__popcll(m);
+            nat += (uint32_t)__shfl(incl, 63);
         }
     } else {
         int *st = stk;
@@ -189,11 +187,15 @@ __global__ __launch_bounds__(64) void k_cp_query(CpQueryArgs a)
             const int nch = node >= 0 ? a.nchild[node] : 0;
             const bool lf = hit && nch == 0;
             const uint64_t m = __ballot(lf);
-            if (lf) {
-                if (a.fill) a.list[o + n + __popcll(m & lt)] = node;
-                nat += (uint32_t)(a.end[node] - a.begin[node]);
+            const int sz = lf ? a.end[node] - a.begin[node] : 0;
+            const int isz = wave_incl_scan(sz, lane);
+            if (lf && a.fill) {
+                const uint32_t at = o + n + (uint32_t)__popcll(m & lt);
+                a.list[at] = node;
+                if (a.apre) a.apre[at] = nat + (uint32_t)(isz - sz);
             }
             n += (uint32_t)__popcll(m);
+            nat += (uint32_t)__shfl(isz, 63);
             const int nc = (hit && nch > 0) ? nch : 0;
             const int incl = wave_incl_scan(nc, lane);
             const int total = __shfl(incl, 63);
@@ -206,7 +208,6 @@ __global__ __launch_bounds__(64) void k_cp_query(CpQueryArgs a)
             sp += total;
         }
     }
-    nat = wave_sum_u32(nat);
     if (!a.fill && lane == 0) {
         a.cnt[q] = n;
         if (a.items) a.items[q] = (n + kCpChunkLeaves - 1) / kCpChunkLeaves;
@@ -279,22 +280,23 @@ __global__ __launch_bounds__(kBlock) void k_cp_classify(CpClassArgs a)
     }
 }
 
-// Launch order of the leaf kernel: blocks sorted by decreasing work (number
-// of direct plus short-range atoms, in power-of-two classes), so that the
-// heaviest blocks start first and the light ones fill the end of the launch.
-// Results do not depend on the order.  One workgroup.
+// Launch orders: work items sorted by decreasing cost (c1 + c2, in
+// power-of-two classes), so that the heaviest items start first and the light
+// ones fill the end of the launch.  Results do not depend on the order.  One
+// workgroup.
 constexpr int kCostClasses = 33;
 __device__ __forceinline__ int cost_class(uint32_t c)
 {
     return c == 0 ? 0 : 32 - __clz(c);
 }
-__global__ __launch_bounds__(1024) void k_cp_order(int nq, const uint32_t *nd, const uint32_t *ns,
-                                                   int *order)
+__global__ __launch_bounds__(1024) void k_order_by_cost(int n, const uint32_t *c1,
+                                                        const uint32_t *c2, int *order)
 {
     __shared__ unsigned int cnt[kCostClasses];
     if (threadIdx.x < kCostClasses) cnt[threadIdx.x] = 0u;
     __syncthreads();
-    for (int q = threadIdx.x; q < nq; q += blockDim.x) atomicAdd(&cnt[cost_class(nd[q] + ns[q])], 1u);
+    for (int q = threadIdx.x; q < n; q += blockDim.x)
+        atomicAdd(&cnt[cost_class(c1[q] + (c2 ? c2[q] : 0u))], 1u);
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned int run = 0;
@@ -305,14 +307,19 @@ __global__ __launch_bounds__(1024) void k_cp_order(int nq, const uint32_t *nd, c
         }
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < nq; q += blockDim.x)
-        order[atomicAdd(&cnt[cost_class(nd[q] + ns[q])], 1u)] = q;
+    for (int q = threadIdx.x; q < n; q += blockDim.x)
+        order[atomicAdd(&cnt[cost_class(c1[q] + (c2 ? c2[q] : 0u))], 1u)] = q;
 }
 
-// Work items of the far kernel: (cluster, first candidate, last candidate).
+// Work items of the far field: (cluster, first candidate, last candidate),
+// and the item's slot range in the buffer of assigned atoms: the cluster's
+// candidate atoms start at atom_off[cluster], items follow in order, each
+// with room for all of its candidate atoms.
 __global__ __launch_bounds__(kBlock) void k_cp_items(int nq, const uint32_t *cand_off,
-                                                     const uint32_t *item_off, int *it_cl,
-                                                     int *it_c0, int *it_c1)
+                                                     const uint32_t *item_off,
+                                                     const uint32_t *atom_off,
+                                                     const uint32_t *cand_apre, int *it_cl,
+                                                     int *it_c0, int *it_c1, uint32_t *it_slot)
 {
     const int q = blockIdx.x * kBlock + threadIdx.x;
     if (q >= nq) return;
@@ -322,33 +329,32 @@ __global__ __launch_bounds__(kBlock) void k_cp_items(int nq, const uint32_t *can
         it_cl[it] = q;
         it_c0[it] = c;
         it_c1[it] = c + kCpChunkLeaves < c1 ? c + kCpChunkLeaves : c1;
+        it_slot[it] = atom_off[q] + cand_apre[c];
     }
 }
 
 // ----------------------------------------------------------------- far
 
-struct CpFarArgs {
+// Assignment of the candidate atoms of one far work item: an atom belongs to
+// this cluster when the cluster is the coarsest one on the atom's chain that
+// satisfies the MAC.  The assigned atoms are written, in candidate order, as
+// (position relative to the cluster centre, charge) from the item's slot on.
+struct CpAssignArgs {
     CpLevels L;
     const int *it_cl, *it_c0, *it_c1;
+    const uint32_t *it_slot;
     const int *cand;
     const int *begin, *end;
     const float4 *rec;
     int stride_f4;
-    int degree, np;
-    float yk;
-    double *part;   // [items][2][np]
-    unsigned long long *work;   // optional: (atom, proxy) pairs
+    float4 *abuf;              // assigned atoms
+    uint32_t *it_n;            // assigned atoms per item
+    unsigned long long *work;  // optional: (atom, proxy) pairs
+    int np;
 };
 
-// One workgroup per work item.  Each thread owns up to four proxies per pass.
-// The candidate atoms of the item's leaves are taken 256 at a time (one per
-// thread); those assigned to this cluster are compacted, in candidate order,
-// into LDS as (position relative to the cluster centre, charge) and swept by
-// every thread.
-template <bool ASYM>
-__global__ __launch_bounds__(kBlock) void k_cp_far(CpFarArgs a)
+__global__ __launch_bounds__(kBlock) void k_cp_assign(CpAssignArgs a)
 {
-    __shared__ float4 stg[kBlock];
     __shared__ int wcount[kBlock / 64];
     __shared__ int pre[kCpChunkLeaves + 1];
     __shared__ int lbeg[kCpChunkLeaves];
@@ -356,10 +362,8 @@ __global__ __launch_bounds__(kBlock) void k_cp_far(CpFarArgs a)
     const int cl = a.it_cl[item];
     int lvl, I, J, K;
     cp_decode(a.L, cl, lvl, I, J, K);
-    double pb[6], cc[3], rr;
-    cp_proxy_box(a.L, lvl, I, J, K, pb);
+    double cc[3], rr;
     cp_centre(a.L, lvl, I, J, K, cc, rr);
-    const int n1 = a.degree + 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c0 = a.it_c0[item], nlf = a.it_c1[item] - c0;   // <= kCpChunkLeaves
     if (threadIdx.x == 0) {
@@ -374,86 +378,147 @@ __global__ __launch_bounds__(kBlock) void k_cp_far(CpFarArgs a)
     }
     __syncthreads();
     const int natoms = pre[nlf];
+    float4 *out = a.abuf + a.it_slot[item];
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    for (int k0 = 0; k0 < a.np; k0 += kCpProxPass) {
-        float px[4], py[4], pz[4];
-        double aC[4], aY[4];
-        float pC[4], pY[4];
+    int filled = 0;
+    for (int t0 = 0; t0 < natoms; t0 += kBlock) {
+        const int t = t0 + threadIdx.x;
+        bool acc = false;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (t < natoms) {
+            // leaf of candidate t: the last l with pre[l] <= t
+            int l = 0, hi = nlf - 1;
+            while (l < hi) {
+                const int mid = (l + hi + 1) >> 1;
+                if (pre[mid] <= t) l = mid;
+                else hi = mid - 1;
+            }
+            const int i = lbeg[l] + (t - pre[l]);
+            double y[3];
+            atom_pos(a.rec, a.stride_f4, i, y);
+            // well separated from this cluster and from none of its ancestors
+            acc = cp_mac(a.L, lvl, I, J, K, y) &&
+                  (lvl == a.L.T ||
+                   cp_accept_level(a.L, I << lvl, J << lvl, K << lvl, y, lvl + 1) == 0);
+            v.x = (float)(y[0] - cc[0]);
+            v.y = (float)(y[1] - cc[1]);
+            v.z = (float)(y[2] - cc[2]);
+            v.w = a.rec[(size_t)i * a.stride_f4].w;
+        }
+        const uint64_t m = __ballot(acc);
+        if (lane == 0) wcount[wave] = __popcll(m);
+        __syncthreads();
+        int base = filled, total = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            if (w < wave) base += wcount[w];
+            total += wcount[w];
+        }
+        if (acc) out[base + __popcll(m & lt)] = v;
+        filled += total;
+        __syncthreads();   // wcount is rewritten by the next step
+    }
+    if (threadIdx.x == 0) {
+        a.it_n[item] = (uint32_t)filled;
+        if (a.work) atomicAdd(a.work, (unsigned long long)filled * (unsigned long long)a.np);
+    }
+}
+
+// Far field of one work item into its cluster's proxies: every thread owns NR
+// proxies per pass (NR = ceil(np / 256) up to 4, so that no lane sweeps an
+// empty slot for the common degrees) and sweeps the item's assigned atoms,
+// which are read as wave-uniform scalar loads in the order they were written.
+// Items are launched heaviest first.
+struct CpSweepArgs {
+    CpLevels L;
+    const int *order, *it_cl;
+    const uint32_t *it_slot, *it_n;
+    const float4 *abuf;
+    int degree, np;
+    float yk;
+    double *part;   // [items][2][np]
+};
+
+struct Quad {
+    float x, y, z, w;
+};
+
+template <bool ASYM, int NR>
+__global__ __launch_bounds__(kBlock) void k_cp_sweep(CpSweepArgs a)
+{
+    __shared__ float node[3][kMaxDeg + 1];
+    const int item = as_const(a.order)[blockIdx.x];
+    const int cl = as_const(a.it_cl)[item];
+    const int n = (int)as_const(a.it_n)[item];
+    ConstAS<Quad> *at = as_const(reinterpret_cast<const Quad *>(a.abuf + as_const(a.it_slot)[item]));
+    const int n1 = a.degree + 1;
+    if (threadIdx.x < 3 * n1) {
+        int lvl, I, J, K;
+        cp_decode(a.L, cl, lvl, I, J, K);
+        double pb[6], cc[3], rr;
+        cp_proxy_box(a.L, lvl, I, J, K, pb);
+        cp_centre(a.L, lvl, I, J, K, cc, rr);
+        const int ax = threadIdx.x / n1, k = threadIdx.x % n1;
+        node[ax][k] = (float)(cheb_point(pick3(pb, ax), pick3(pb + 3, ax), k, a.degree) -
+                              pick3(cc, ax));
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < a.np; k0 += NR * kBlock) {
+        float px[NR], py[NR], pz[NR];
+        double aC[NR], aY[NR];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < NR; ++r) {
             const int k = k0 + r * kBlock + threadIdx.x;
             const int kk = k < a.np ? k : 0;
             const int k1 = kk % n1, k2 = (kk / n1) % n1, k3 = kk / (n1 * n1);
-            px[r] = (float)(cheb_point(pb[0], pb[3], k1, a.degree) - cc[0]);
-            py[r] = (float)(cheb_point(pb[1], pb[4], k2, a.degree) - cc[1]);
-            pz[r] = (float)(cheb_point(pb[2], pb[5], k3, a.degree) - cc[2]);
+            px[r] = node[0][k1];
+            py[r] = node[1][k2];
+            pz[r] = node[2][k3];
             aC[r] = aY[r] = 0.0;
-            pC[r] = pY[r] = 0.f;
         }
-        int since_flush = 0, n_acc = 0;
-        for (int t0 = 0; t0 < natoms; t0 += kBlock) {
-            const int t = t0 + threadIdx.x;
-            bool acc = false;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (t < natoms) {
-                int l = 0;
-                while (l + 1 < nlf && pre[l + 1] <= t) ++l;
-                const int i = lbeg[l] + (t - pre[l]);
-                double y[3];
-                atom_pos(a.rec, a.stride_f4, i, y);
-                acc = cp_accept_level(a.L, I << lvl, J << lvl, K << lvl, y, lvl) == lvl;
-                v.x = (float)(y[0] - cc[0]);
-                v.y = (float)(y[1] - cc[1]);
-                v.z = (float)(y[2] - cc[2]);
-                v.w = a.rec[(size_t)i * a.stride_f4].w;
-            }
-            const uint64_t m = __ballot(acc);
-            const int pos = __popcll(m & lt);
-            __syncthreads();   // previous round's readers are done with stg
-            if (lane == 0) wcount[wave] = __popcll(m);
-            __syncthreads();
-            int base = 0, total = 0;
-            for (int w = 0; w < kBlock / 64; ++w) {
-                if (w < wave) base += wcount[w];
-                total += wcount[w];
-            }
-            if (acc) stg[base + pos] = v;
-            __syncthreads();
-            n_acc += total;
-            for (int s = 0; s < total; ++s) {
-                const float4 at = stg[s];
+        for (int s0 = 0; s0 < n; s0 += 16) {
+            float pC[NR], pY[NR];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float dx = px[r] - at.x, dy = py[r] - at.y, dz = pz[r] - at.z;
+            for (int r = 0; r < NR; ++r) pC[r] = pY[r] = 0.f;
+            const int s1 = min(s0 + 16, n);
+#pragma unroll 2
+            for (int s = s0; s < s1; ++s) {
+                ConstAS<Quad> &v = at[s];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    const float dx = px[r] - v.x, dy = py[r] - v.y, dz = pz[r] - v.z;
                     const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                     const float ri = __builtin_amdgcn_rsqf(d2);
-                    const float qr = at.w * ri;
+                    const float qr = v.w * ri;
                     pC[r] += qr;
                     if (ASYM) pY[r] = fmaf(qr, __builtin_amdgcn_exp2f(a.yk * (d2 * ri)), pY[r]);
                 }
-                if (++since_flush == 16) {
-                    since_flush = 0;
+            }
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        aC[r] += (double)pC[r];
-                        aY[r] += (double)pY[r];
-                        pC[r] = pY[r] = 0.f;
-                    }
-                }
+            for (int r = 0; r < NR; ++r) {
+                aC[r] += (double)pC[r];
+                aY[r] += (double)pY[r];
             }
         }
-        if (a.work && threadIdx.x == 0 && k0 == 0)
-            atomicAdd(a.work, (unsigned long long)n_acc * (unsigned long long)a.np);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            aC[r] += (double)pC[r];
-            aY[r] += (double)pY[r];
+        for (int r = 0; r < NR; ++r) {
             const int k = k0 + r * kBlock + threadIdx.x;
             if (k < a.np) {
                 a.part[((size_t)item * 2 + 0) * a.np + k] = aC[r];
                 a.part[((size_t)item * 2 + 1) * a.np + k] = aY[r];
             }
         }
+    }
+}
+
+template <bool ASYM>
+void launch_sweep(int nitems, int np, const CpSweepArgs &sa, hipStream_t s)
+{
+    const int nr = np <= 3 * kBlock ? (np + kBlock - 1) / kBlock : 4;
+    switch (nr) {
+    case 1: hipLaunchKernelGGL((k_cp_sweep<ASYM, 1>), nitems, kBlock, 0, s, sa); break;
+    case 2: hipLaunchKernelGGL((k_cp_sweep<ASYM, 2>), nitems, kBlock, 0, s, sa); break;
+    case 3: hipLaunchKernelGGL((k_cp_sweep<ASYM, 3>), nitems, kBlock, 0, s, sa); break;
+    default: hipLaunchKernelGGL((k_cp_sweep<ASYM, 4>), nitems, kBlock, 0, s, sa); break;
     }
 }
 
@@ -541,68 +606,58 @@ struct CpLeafArgs {
     unsigned long long *work;  // optional: [0] direct pairs, [1] short-range pairs
 };
 
+// One grid point per thread, up to 512 threads per block.
 template <int B>
 struct LeafShape {
-    static constexpr int threads = B == 4 ? 64 : 256;
-    static constexpr int ppt = B == 4 ? 1 : 2;
-    static constexpr int passes = (B * B * B) / (threads * ppt);
+    static constexpr int threads = B * B * B < 512 ? B * B * B : 512;
+    static constexpr int passes = (B * B * B) / threads;
 };
 
-// Atoms staged in LDS per round of the leaf kernel.
-constexpr int kCpStage = 128;
-
 // Dynamic LDS of the leaf kernel, in bytes (layout in k_cp_leaf).
-inline size_t cp_leaf_lds(int B, int degree, bool asym, size_t rec_bytes)
+inline size_t cp_leaf_lds(int B, int degree, bool asym)
 {
     const size_t n1 = degree + 1, np = n1 * n1 * n1;
     const size_t ncomp = asym ? 2 : 1;
-    const size_t uni = std::max((np + n1 * n1 * B) * sizeof(double), kCpStage * rec_bytes);
     return (asym ? 2 * kSmearIntervals * sizeof(float4) : 0) +
-           (ncomp * n1 * B * B + 3 * (size_t)B * n1) * sizeof(double) + uni;
+           (ncomp * n1 * B * B + 3 * (size_t)B * n1 + np + n1 * n1 * B) * sizeof(double);
 }
 
-// The staged atoms against the PPT points of this thread, flushed every
-// kAtomPad atoms.
-template <int NS, int LJM, bool ASYM, bool EXACT, bool FULL, int PPT>
-__device__ __forceinline__ void leaf_atoms(const AtomF32<NS> *st, int cnt, const GridPt *gp,
-                                           const PairConst &kc, const float4 *tab,
-                                           PointAcc<NS> *acc)
+// The atoms of one index list against this thread's point, flushed every
+// kAtomPad atoms.  Indices and records are wave-uniform scalar loads, so the
+// pair arithmetic reads the atom's fields from scalar registers.
+template <int NS, int LJM, bool ASYM, bool EXACT, bool FULL>
+__device__ __forceinline__ void leaf_atoms(ConstAS<AtomF32<NS>> *rec, ConstAS<int> *il, int cnt,
+                                           const GridPt &gp, const PairConst &kc,
+                                           const float4 *tab, PointAcc<NS> &acc)
 {
     for (int s0 = 0; s0 < cnt; s0 += kAtomPad) {
-        PairAcc<NS> p[PPT];
-#pragma unroll
-        for (int qq = 0; qq < PPT; ++qq) p[qq].zero();
+        PairAcc<NS> p;
+        p.zero();
         const int s1 = min(s0 + kAtomPad, cnt);
 #pragma unroll 2
         for (int s = s0; s < s1; ++s) {
-            const AtomF32<NS> &at = st[s];
-#pragma unroll
-            for (int qq = 0; qq < PPT; ++qq)
-                pair_eval<NS, LJM, ASYM, EXACT, FULL>(at, gp[qq], kc, tab, p[qq], acc[qq].hit);
+            ConstAS<AtomF32<NS>> &at = rec[il[s]];
+            pair_eval<NS, LJM, ASYM, EXACT, FULL>(at, gp, kc, tab, p, acc.hit);
         }
-#pragma unroll
-        for (int qq = 0; qq < PPT; ++qq) acc[qq].template flush<LJM != LJ_NONE, ASYM>(p[qq]);
+        acc.template flush<LJM != LJ_NONE, ASYM>(p);
     }
 }
 
-// One workgroup per level-0 block.  Far field: the level-1 ancestor's proxy
-// values interpolated onto the block by three one-axis contractions (the
-// first two once per block, into LDS; the last per point).  Near field: the
-// block's direct atoms (full pair) and short-range atoms (LJ and the smeared
-// kernels less their far-field forms), gathered from the sorted records into
-// LDS in rounds of kCpStage atoms and read back as broadcasts.
+// One workgroup per level-0 block, blocks launched heaviest first.  Far
+// field: the level-1 ancestor's proxy values interpolated onto the block by
+// three one-axis contractions (the first two once per block, into LDS; the
+// last per point).  Near field: the block's direct atoms (full pair) and
+// short-range atoms (LJ and the smeared kernels less their far-field forms)
+// from the block's index lists.
 //
 // LDS: [smeared table (ASYM)] [T2 per component: n1 x B x B] [Lb: 3 x B x n1]
-//      [union: Vs (np) + T1 (n1 x n1 x B) while interpolating | atom stage]
+//      [Vs (np)] [T1 (n1 x n1 x B)]
 template <int NS, int LJM, bool ASYM, int B>
 __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
 {
     using S = LeafShape<B>;
-    constexpr int PPT = S::ppt;
     constexpr int NT = S::threads;
     constexpr int NCOMP = ASYM ? 2 : 1;
-    constexpr int R4 = sizeof(AtomF32<NS>) / sizeof(float4);
-    static_assert(sizeof(AtomF32<NS>) % sizeof(float4) == 0, "record size");
     extern __shared__ double sm[];
     const int n1 = a.degree + 1;
     float4 *tab = reinterpret_cast<float4 *>(sm);
@@ -610,17 +665,16 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
     double *Lb = T2 + NCOMP * n1 * B * B;                  // [3][B][n1]
     double *Vs = Lb + 3 * B * n1;                          // [np]
     double *T1 = Vs + a.np;                                // [n1][n1][B]
-    AtomF32<NS> *stage = reinterpret_cast<AtomF32<NS> *>(Vs);
     const CpLevels &L = a.L;
     const GridParams &g = a.g;
     const int q = as_const(a.order)[blockIdx.x];
     const int I = q % L.cx[0], J = (q / L.cx[0]) % L.cy[0], K = q / (L.cx[0] * L.cy[0]);
     const int i0 = I * B, j0 = J * B, k0 = K * B;
     const PairConst kc = make_pair_const(a.asym);
-    const float4 *rec4 = static_cast<const float4 *>(a.rec);
+    ConstAS<AtomF32<NS>> *rec = as_const(static_cast<const AtomF32<NS> *>(a.rec));
     const uint32_t base = as_const(a.aoff)[q];
-    const int *dl = a.dlist + base;
-    const int *sl = a.slist + base;
+    ConstAS<int> *dl = as_const(a.dlist + base);
+    ConstAS<int> *sl = as_const(a.slist + base);
     const int ndir = (int)as_const(a.nd)[q], nsh = (int)as_const(a.ns)[q];
     if (ASYM)
         for (int i = threadIdx.x; i < 2 * kSmearIntervals; i += NT) tab[i] = a.asym.tab[i];
@@ -671,70 +725,40 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
     }
 
     for (int pass = 0; pass < S::passes; ++pass) {
-        int li[PPT], lj[PPT], lk[PPT];
-        bool valid[PPT];
-        GridPt gp[PPT];
-        PointAcc<NS> acc[PPT];
-#pragma unroll
-        for (int qq = 0; qq < PPT; ++qq) {
-            const int l = (pass * PPT + qq) * NT + threadIdx.x;
-            li[qq] = l % B;
-            lj[qq] = (l / B) % B;
-            lk[qq] = l / (B * B);
-            valid[qq] = i0 + li[qq] < g.nx && j0 + lj[qq] < g.ny && k0 + lk[qq] < g.nz;
-            gp[qq] = grid_pt(g, valid[qq] ? i0 + li[qq] : i0, valid[qq] ? j0 + lj[qq] : j0,
-                             valid[qq] ? k0 + lk[qq] : k0);
-            acc[qq].zero();
-        }
+        const int l = pass * NT + threadIdx.x;
+        const int li = l % B, lj = (l / B) % B, lk = l / (B * B);
+        const bool valid = i0 + li < g.nx && j0 + lj < g.ny && k0 + lk < g.nz;
+        const GridPt gp = grid_pt(g, valid ? i0 + li : i0, valid ? j0 + lj : j0,
+                                  valid ? k0 + lk : k0);
+        PointAcc<NS> acc;
+        acc.zero();
 
         // ---------------------------------------------- far: last contraction
         if (L.T >= 1) {
-#pragma unroll
-            for (int qq = 0; qq < PPT; ++qq) {
-                for (int comp = 0; comp < NCOMP; ++comp) {
-                    const double *T2c = T2 + comp * n1 * B * B;
-                    double s = 0;
-                    for (int k1 = 0; k1 < n1; ++k1)
-                        s += T2c[(k1 * B + lj[qq]) * B + lk[qq]] * Lb[(0 * B + li[qq]) * n1 + k1];
-                    if (comp == 0) acc[qq].C = s;
-                    else acc[qq].Y = s;
-                }
+            for (int comp = 0; comp < NCOMP; ++comp) {
+                const double *T2c = T2 + comp * n1 * B * B;
+                double s = 0;
+                for (int k1 = 0; k1 < n1; ++k1)
+                    s += T2c[(k1 * B + lj) * B + lk] * Lb[(0 * B + li) * n1 + k1];
+                if (comp == 0) acc.C = s;
+                else acc.Y = s;
             }
         }
 
         // ---------------------------------------------- direct and short
-        for (int lst = 0; lst < 2; ++lst) {
-            if (lst == 1 && !(LJM != LJ_NONE || ASYM)) break;
-            const int cnt_all = lst == 0 ? ndir : nsh;
-            const int *il = lst == 0 ? dl : sl;
-            for (int c0 = 0; c0 < cnt_all; c0 += kCpStage) {
-                const int cnt = min(kCpStage, cnt_all - c0);
-                __syncthreads();
-                float4 *dst = reinterpret_cast<float4 *>(stage);
-                for (int t = threadIdx.x; t < cnt * R4; t += NT) {
-                    const int at = t / R4;
-                    dst[t] = rec4[(size_t)il[c0 + at] * R4 + (t - at * R4)];
-                }
-                __syncthreads();
-                if (g.exact) {
-                    if (lst == 0)
-                        leaf_atoms<NS, LJM, ASYM, true, true, PPT>(stage, cnt, gp, kc, tab, acc);
-                    else
-                        leaf_atoms<NS, LJM, ASYM, true, false, PPT>(stage, cnt, gp, kc, tab, acc);
-                } else {
-                    if (lst == 0)
-                        leaf_atoms<NS, LJM, ASYM, false, true, PPT>(stage, cnt, gp, kc, tab, acc);
-                    else
-                        leaf_atoms<NS, LJM, ASYM, false, false, PPT>(stage, cnt, gp, kc, tab, acc);
-                }
-            }
+        if (g.exact) {
+            leaf_atoms<NS, LJM, ASYM, true, true>(rec, dl, ndir, gp, kc, tab, acc);
+            if (LJM != LJ_NONE || ASYM)
+                leaf_atoms<NS, LJM, ASYM, true, false>(rec, sl, nsh, gp, kc, tab, acc);
+        } else {
+            leaf_atoms<NS, LJM, ASYM, false, true>(rec, dl, ndir, gp, kc, tab, acc);
+            if (LJM != LJ_NONE || ASYM)
+                leaf_atoms<NS, LJM, ASYM, false, false>(rec, sl, nsh, gp, kc, tab, acc);
         }
 
-#pragma unroll
-        for (int qq = 0; qq < PPT; ++qq) {
-            if (!valid[qq]) continue;
-            const int64_t p = ((int64_t)(k0 + lk[qq]) * g.ny + (j0 + lj[qq])) * g.nx + (i0 + li[qq]);
-            store_point<NS, LJM, ASYM>(a.out, g, p, acc[qq]);
+        if (valid) {
+            const int64_t p = ((int64_t)(k0 + lk) * g.ny + (j0 + lj)) * g.nx + (i0 + li);
+            store_point<NS, LJM, ASYM>(a.out, g, p, acc);
         }
     }
 }
@@ -794,8 +818,9 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
 
     // queries: clusters (mode 0) and leaves (mode 1), count pass
     uint32_t *ccnt = ws.get<uint32_t>(ncl + 1), *citems = ws.get<uint32_t>(ncl + 1);
+    uint32_t *cacnt = ws.get<uint32_t>(ncl + 1);
     uint32_t *lcnt = ws.get<uint32_t>(nleaf + 1), *lacnt = ws.get<uint32_t>(nleaf + 1);
-    uint32_t *tot = ws.get<uint32_t>(4);
+    uint32_t *tot = ws.get<uint32_t>(5);
     int *overflow = ws.get<int>(1);
     if (ws.status()) return ws.status();
     CpQueryArgs qa{};
@@ -817,11 +842,12 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             qa.nq = ncl;
             qa.cnt = ccnt;
             qa.items = citems;
-            qa.acnt = nullptr;
+            qa.acnt = cacnt;
             qa.fill = 0;
             hipLaunchKernelGGL(k_cp_query, ncl, 64, 0, s, qa);
             hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, ccnt, ncl + 1, tot + 0);
             hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, citems, ncl + 1, tot + 1);
+            hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, cacnt, ncl + 1, tot + 4);
         }
         qa.mode = 1;
         qa.nq = nleaf;
@@ -834,18 +860,23 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, lacnt, nleaf + 1, tot + 3);
     }
     RISM_HIP(hipGetLastError());
-    uint32_t ht[5] = {0, 0, 0, 0, 0};
-    RISM_HIP(hipMemcpyAsync(ht, tot, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    RISM_HIP(hipMemcpyAsync(ht + 4, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
+    // totals: [0] cluster candidates, [1] far items, [2] leaf candidates,
+    // [3] leaf candidate atoms, [4] cluster candidate atoms, [5] overflow flag
+    uint32_t ht[6] = {0, 0, 0, 0, 0, 0};
+    RISM_HIP(hipMemcpyAsync(ht, tot, 5 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    RISM_HIP(hipMemcpyAsync(ht + 5, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
     RISM_HIP(hipStreamSynchronize(s));
-    if (ht[4]) {
+    if (ht[5]) {
         set_error("treecode_cp: neighbour query stack overflow");
         return RISM_E_UNSUPPORTED;
     }
-    if (ncl == 0) ht[0] = ht[1] = 0;
+    if (ncl == 0) ht[0] = ht[1] = ht[4] = 0;
     int *ccand = ws.get<int>(ht[0] + 1), *lcand = ws.get<int>(ht[2] + 1);
+    uint32_t *capre = ws.get<uint32_t>(ht[0] + 1);
     int *it_cl = ws.get<int>(ht[1] + 1), *it_c0 = ws.get<int>(ht[1] + 1),
-        *it_c1 = ws.get<int>(ht[1] + 1);
+        *it_c1 = ws.get<int>(ht[1] + 1), *it_order = ws.get<int>(ht[1] + 1);
+    uint32_t *it_slot = ws.get<uint32_t>(ht[1] + 1), *it_n = ws.get<uint32_t>(ht[1] + 1);
+    float4 *abuf = ws.get<float4>((size_t)ht[4] + 1);
     int *dlist = ws.get<int>(ht[3] + 1), *slist = ws.get<int>(ht[3] + 1);
     uint32_t *nd = ws.get<uint32_t>(nleaf), *nsh = ws.get<uint32_t>(nleaf);
     double *part = ws.get<double>((size_t)(ht[1] + 1) * 2 * np);
@@ -861,12 +892,14 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             qa.nq = ncl;
             qa.off = ccnt;
             qa.list = ccand;
+            qa.apre = capre;
             qa.fill = 1;
             qa.items = nullptr;
             qa.acnt = nullptr;
             hipLaunchKernelGGL(k_cp_query, ncl, 64, 0, s, qa);
+            qa.apre = nullptr;
             hipLaunchKernelGGL(k_cp_items, (ncl + kBlock - 1) / kBlock, kBlock, 0, s, ncl, ccnt,
-                               citems, it_cl, it_c0, it_c1);
+                               citems, cacnt, capre, it_cl, it_c0, it_c1, it_slot);
         }
         qa.mode = 1;
         qa.nq = nleaf;
@@ -898,26 +931,38 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     if (ncl > 0) {
         {
             PhaseTimer pt(ev, RISM_PHASE_UPWARD, s);
-            CpFarArgs fa{};
-            fa.L = L;
-            fa.it_cl = it_cl;
-            fa.it_c0 = it_c0;
-            fa.it_c1 = it_c1;
-            fa.cand = ccand;
-            fa.begin = t.begin;
-            fa.end = t.end;
-            fa.rec = static_cast<const float4 *>(t.sorted_rec);
-            fa.stride_f4 = stride_f4;
-            fa.degree = deg;
-            fa.np = np;
-            fa.yk = (float)a.asym.yk;
-            fa.part = part;
-            fa.work = work ? work + 2 : nullptr;
             if (ht[1] > 0) {
-                if (a.asym_on)
-                    hipLaunchKernelGGL(k_cp_far<true>, (int)ht[1], kBlock, 0, s, fa);
-                else
-                    hipLaunchKernelGGL(k_cp_far<false>, (int)ht[1], kBlock, 0, s, fa);
+                CpAssignArgs aa{};
+                aa.L = L;
+                aa.it_cl = it_cl;
+                aa.it_c0 = it_c0;
+                aa.it_c1 = it_c1;
+                aa.it_slot = it_slot;
+                aa.cand = ccand;
+                aa.begin = t.begin;
+                aa.end = t.end;
+                aa.rec = static_cast<const float4 *>(t.sorted_rec);
+                aa.stride_f4 = stride_f4;
+                aa.abuf = abuf;
+                aa.it_n = it_n;
+                aa.work = work ? work + 2 : nullptr;
+                aa.np = np;
+                hipLaunchKernelGGL(k_cp_assign, (int)ht[1], kBlock, 0, s, aa);
+                hipLaunchKernelGGL(k_order_by_cost, 1, 1024, 0, s, (int)ht[1], it_n,
+                                   (const uint32_t *)nullptr, it_order);
+                CpSweepArgs sa{};
+                sa.L = L;
+                sa.order = it_order;
+                sa.it_cl = it_cl;
+                sa.it_slot = it_slot;
+                sa.it_n = it_n;
+                sa.abuf = abuf;
+                sa.degree = deg;
+                sa.np = np;
+                sa.yk = (float)a.asym.yk;
+                sa.part = part;
+                if (a.asym_on) launch_sweep<true>((int)ht[1], np, sa, s);
+                else launch_sweep<false>((int)ht[1], np, sa, s);
             }
             hipLaunchKernelGGL(k_cp_reduce, ncl, kBlock, 0, s, ncl, np, citems, part, V);
         }
@@ -950,7 +995,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     la.degree = deg;
     la.np = np;
     la.work = work;
-    const size_t shm = cp_leaf_lds(B, deg, a.asym_on, rec32_bytes_of(a.sp.ns_pad));
+    const size_t shm = cp_leaf_lds(B, deg, a.asym_on);
     int dev = 0, lds_max = 0;
     RISM_HIP(hipGetDevice(&dev));
     RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -960,7 +1005,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     }
     {
         PhaseTimer pt(ev, RISM_PHASE_EVAL, s);
-        hipLaunchKernelGGL(k_cp_order, 1, 1024, 0, s, nleaf, nd, nsh, order);
+        hipLaunchKernelGGL(k_order_by_cost, 1, 1024, 0, s, nleaf, nd, nsh, order);
         switch (a.sp.ns_pad) {
         case 1: launch_leaf_ns<1>(a.lj_mode, a.asym_on, B, nleaf, shm, la, s); break;
         case 2: launch_leaf_ns<2>(a.lj_mode, a.asym_on, B, nleaf, shm, la, s); break;
