@@ -58,6 +58,17 @@ __global__ __launch_bounds__(kBlock) void k_bbox_partial(const float4 *rec, int 
     if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Key cube of the atoms: lower corner and edge (the largest extent, padded).
+__device__ __forceinline__ void bbox_cube(const double lo[3], const double hi[3], double *bbox)
+{
+    double ext = fmax(fmax(hi[0] - lo[0], hi[1] - lo[1]), hi[2] - lo[2]);
+    ext = fmax(ext, 1e-3) * (1.0 + 1e-9);
+    for (int k = 0; k < 3; ++k) {
+        bbox[k] = lo[k];
+        bbox[3 + k] = ext;   // cube edge
+    }
+}
+
 __global__ void k_bbox_final(const double *part, int nparts, double *bbox)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -67,12 +78,7 @@ __global__ void k_bbox_final(const double *part, int nparts, double *bbox)
             lo[k] = fmin(lo[k], part[6 * p + k]);
             hi[k] = fmax(hi[k], part[6 * p + 3 + k]);
         }
-    double ext = fmax(fmax(hi[0] - lo[0], hi[1] - lo[1]), hi[2] - lo[2]);
-    ext = fmax(ext, 1e-3) * (1.0 + 1e-9);
-    for (int k = 0; k < 3; ++k) {
-        bbox[k] = lo[k];
-        bbox[3 + k] = ext;   // cube edge
-    }
+    bbox_cube(lo, hi, bbox);
 }
 
 // ------------------------------------------------------------ Morton keys
@@ -87,11 +93,10 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v)
     return v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_morton(const float4 *rec, int stride_f4, int n,
-                                                   const double *bbox, uint32_t *keys, int *idx)
+// 30-bit Morton key of atom i in the key cube.
+__device__ __forceinline__ uint32_t atom_key(const float4 *rec, int stride_f4, int i,
+                                             const double *bbox)
 {
-    int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
     float4 a = rec[(size_t)i * stride_f4];
     float4 b = rec[(size_t)i * stride_f4 + 1];
     double v[3] = {(double)a.x + b.x, (double)a.y + b.y, (double)a.z + b.z};
@@ -102,7 +107,15 @@ __global__ __launch_bounds__(kBlock) void k_morton(const float4 *rec, int stride
         ci = ci < 0 ? 0 : (ci > (1 << kMortonBits) - 1 ? (1 << kMortonBits) - 1 : ci);
         c[k] = (uint32_t)ci;
     }
-    keys[i] = spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
+    return spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2);
+}
+
+__global__ __launch_bounds__(kBlock) void k_morton(const float4 *rec, int stride_f4, int n,
+                                                   const double *bbox, uint32_t *keys, int *idx)
+{
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = atom_key(rec, stride_f4, i, bbox);
     idx[i] = i;
 }
 
@@ -297,6 +310,183 @@ __global__ __launch_bounds__(kBlock) void k_split_write(const uint32_t *keys, in
         }
         nchild[i] = c;
     }
+}
+
+// ------------------------------------------------- one-workgroup builder
+
+// The whole build of a small tree in one workgroup: key cube, Morton keys,
+// sort of the (key, input index) pairs in LDS (bitonic; unique pairs, so the
+// order equals the stable radix sort's), and the level-by-level split with
+// block-wide scans.  Produces the same permutation and nodes as the
+// multi-kernel build.
+constexpr int kSmallThreads = 1024;
+
+__device__ __forceinline__ int block_excl_scan(int v, int *wsum, int &total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int w = 0; w < kSmallThreads / 64; ++w) {
+        if (w < wave) base += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();   // wsum is reused by the next scan
+    total = tot;
+    return base + x - v;
+}
+
+__device__ __forceinline__ int lower_digit_lds(const unsigned long long *sk, int lo, int hi,
+                                               int shift, int d)
+{
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if ((int)((sk[mid] >> (32 + shift)) & 7u) < d) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kSmallThreads) void k_tree_small(
+    const float4 *rec, int stride_f4, int n, int npow2, int leaf, int cap, int *perm, int *begin,
+    int *end, int *level, int *child0, int *nchild, int *level_start_out, int *n_nodes_out,
+    int *flags)
+{
+    extern __shared__ unsigned long long sk[];   // [npow2] (key << 32) | index
+    __shared__ double red[6][kSmallThreads / 64];
+    __shared__ double bb[6];
+    __shared__ int wsum[kSmallThreads / 64];
+    __shared__ int ls[kMortonBits + 2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    // key cube
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int i = tid; i < n; i += kSmallThreads) {
+        float4 a = rec[(size_t)i * stride_f4];
+        float4 b = rec[(size_t)i * stride_f4 + 1];
+        double v[3] = {(double)a.x + b.x, (double)a.y + b.y, (double)a.z + b.z};
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fmin(lo[k], v[k]);
+            hi[k] = fmax(hi[k], v[k]);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fmin(lo[k], __shfl_xor(lo[k], off));
+            hi[k] = fmax(hi[k], __shfl_xor(hi[k], off));
+        }
+    if (lane == 0)
+        for (int k = 0; k < 3; ++k) {
+            red[k][wave] = lo[k];
+            red[3 + k][wave] = hi[k];
+        }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < kSmallThreads / 64; ++w)
+            for (int k = 0; k < 3; ++k) {
+                red[k][0] = fmin(red[k][0], red[k][w]);
+                red[3 + k][0] = fmax(red[3 + k][0], red[3 + k][w]);
+            }
+        const double l3[3] = {red[0][0], red[1][0], red[2][0]};
+        const double h3[3] = {red[3][0], red[4][0], red[5][0]};
+        bbox_cube(l3, h3, bb);
+    }
+    __syncthreads();
+
+    // keys and bitonic sort
+    for (int i = tid; i < npow2; i += kSmallThreads)
+        sk[i] = i < n ? ((unsigned long long)atom_key(rec, stride_f4, i, bb) << 32) | (unsigned)i
+                      : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= npow2; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < npow2; i += kSmallThreads) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const unsigned long long a = sk[i], b = sk[ixj];
+                    if ((a > b) == ((i & k) == 0)) {
+                        sk[i] = b;
+                        sk[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = tid; i < n; i += kSmallThreads) perm[i] = (int)(sk[i] & 0xffffffffu);
+
+    // octree, level by level
+    if (tid == 0) {
+        begin[0] = 0;
+        end[0] = n;
+        level[0] = 0;
+        ls[0] = 0;
+        for (int l = 1; l < kMortonBits + 2; ++l) ls[l] = 1;
+        flags[0] = 0;
+    }
+    __syncthreads();
+    for (int lvl = 0; lvl < kMortonBits; ++lvl) {
+        const int s0 = ls[lvl], s1 = ls[lvl + 1];
+        const int shift = 3 * (kMortonBits - 1 - lvl);
+        int running = 0;
+        for (int c0 = s0; c0 < s1; c0 += kSmallThreads) {
+            const int i = c0 + tid;
+            int c = 0, b = 0, e = 0;
+            const bool split = i < s1 && (e = end[i]) - (b = begin[i]) > leaf;
+            if (split) {
+                int prev = b;
+                for (int d = 1; d <= 8; ++d) {
+                    const int nx = d == 8 ? e : lower_digit_lds(sk, prev, e, shift, d);
+                    if (nx > prev) ++c;
+                    prev = nx;
+                }
+            }
+            int tot;
+            const int off = block_excl_scan(c, wsum, tot);
+            if (i < s1) {
+                if (split) {
+                    const int base = s1 + running + off;
+                    child0[i] = base;
+                    int prev = b, cc = 0;
+                    for (int d = 1; d <= 8; ++d) {
+                        const int nx = d == 8 ? e : lower_digit_lds(sk, prev, e, shift, d);
+                        if (nx > prev) {
+                            const int j = base + cc;
+                            if (j < cap) {
+                                begin[j] = prev;
+                                end[j] = nx;
+                                level[j] = lvl + 1;
+                                child0[j] = -1;
+                                nchild[j] = 0;
+                            }
+                            ++cc;
+                        }
+                        prev = nx;
+                    }
+                } else {
+                    child0[i] = -1;
+                }
+                nchild[i] = c;
+            }
+            running += tot;
+        }
+        __syncthreads();   // children written before the next level reads them
+        if (tid == 0) {
+            int t = s1 + running;
+            if (t > cap) {
+                flags[0] = 1;
+                t = cap;
+            }
+            ls[lvl + 2] = t;
+        }
+        __syncthreads();
+    }
+    if (tid < kMortonBits + 2) level_start_out[tid] = ls[tid];
+    if (tid == 0) *n_nodes_out = ls[kMortonBits + 1];
 }
 
 template <int NS>
@@ -605,6 +795,22 @@ int build_source_tree(const TreeCallArgs &a, Workspace &ws, TreeDev &t, rism_sta
     t.sorted_rec = ws.alloc(rec32_bytes_of(a.sp.ns_pad) * a.npad);
     if (ws.status()) return ws.status();
 
+    // small trees: the whole build in one workgroup, keys sorted in LDS
+    int npow2 = 1;
+    while (npow2 < n) npow2 <<= 1;
+    int dev = 0, lds_max = 0;
+    RISM_HIP(hipGetDevice(&dev));
+    RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t small_shm = (size_t)npow2 * sizeof(unsigned long long);
+    // (up to 8192 keys: beyond that the bitonic passes of one workgroup take
+    // longer than the multi-kernel radix sort)
+    const bool small = npow2 <= 8192 && small_shm + 4096 <= (size_t)lds_max;
+    if (small) {
+        hipLaunchKernelGGL(k_tree_small, 1, kSmallThreads, small_shm, s, rec, stride_f4, n, npow2,
+                           leaf, t.cap_nodes, v0, t.begin, t.end, t.level, t.child0, t.nchild,
+                           t.level_start, t.n_nodes, flags);
+        t.perm = v0;
+    } else {
     const int nb = (n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_bbox_partial, nparts, kBlock, 0, s, rec, stride_f4, n, part);
     hipLaunchKernelGGL(k_bbox_final, 1, 1, 0, s, part, nparts, bbox);
@@ -631,6 +837,7 @@ int build_source_tree(const TreeCallArgs &a, Workspace &ws, TreeDev &t, rism_sta
         hipLaunchKernelGGL(k_split_write, gb, kBlock, 0, s, k0, t.begin, t.end, t.level, t.child0,
                            t.nchild, t.level_start, lvl, leaf, cnt, total, t.cap_nodes, t.n_nodes,
                            flags);
+    }
     }
     RISM_HIP(hipGetLastError());
     switch (a.sp.ns_pad) {
