@@ -3,15 +3,15 @@
 A step is one initialisation of the 2,500-atom / 128^3-grid / 4-site
 workload (u for all sites with a 9 A LJ cut-off, c^lr for all sites, h^lr for
 the two ionic sites), computed by the FP32 path selected with --method
-(default: the particle-cluster treecode, theta 0.7, degree 8).  Inputs are
+(default: the cluster-particle treecode, theta 0.6, degree 8).  Inputs are
 resident in HBM before the timed region.
 
 Also measured (outside the timed steps, reported in the same JSON line):
 the GPU FP64 direct sum of the same quantities (the comparison of the
-metric), the error of the FP32 path against it, the adjoint, the dominant
-kernel's duration from HIP events recorded by the library on the call's
-stream (roofline), and the FP64 CPU oracle on a bounded sample of grid points
-(cpu_baseline).
+metric), the error of the FP32 path against it, the adjoint, the per-phase
+durations from HIP events recorded by the library on the call's stream
+(roofline of the dominant kernel), and the FP64 CPU oracle on a bounded
+sample of grid points (cpu_baseline).
 """
 from __future__ import annotations
 
@@ -29,13 +29,16 @@ sys.path.insert(0, ROOT)
 METRIC = "3D-RISM init time (s) & Gpair-interactions/s, FP32 treecode vs FP64 direct @1e-6"
 UNIT = "Gpair-interactions/s"
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz.  Packed FP32 instructions are
-# disabled in this build, so an FP32 VALU lane retires one op per clock:
-# 256*64*2.4e9 = 39.3e12 lane-ops/s, 78.6 TFLOP/s counting an FMA as 2.
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz.  One wave64 VALU instruction
+# per SIMD every 4 clocks is 39.3e12 lane-ops/s (78.6 TFLOP/s counting an FMA
+# as 2); the SIMD can issue a second VALU instruction in the same cycle (dual
+# issue, counted by SQ_ACTIVE_INST_VALU2), which doubles that to the
+# published FP32 vector peak of 157.3 TFLOP/s, the roofline used here.
 VALU_LANE_OPS = 256 * 64 * 2.4e9
-FP32_VALU_PEAK_TFLOPS = 2 * VALU_LANE_OPS / 1e12       # 78.6 (non-packed)
-FP32_VALU_PUBLISHED_TFLOPS = 157.3                     # with packed FP32
+FP32_VALU_PEAK_TFLOPS = 157.3
+FP32_VALU_SINGLE_ISSUE_TFLOPS = 2 * VALU_LANE_OPS / 1e12   # 78.6
 HBM_PEAK_GBS = 8000.0
+ROOT_PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 
 
 def flops_per_pair_direct_f32(ns, asym, lj):
@@ -51,14 +54,59 @@ def flops_per_pair_direct_f32(ns, asym, lj):
     return f
 
 
-def issue_slots_per_pair_direct_f32(ns, asym, lj):
-    """Ideal VALU issue slots of the same pair (a transcendental takes 4)."""
-    s = 6 + 3 + 4 + 2 + 2 + 2   # diffs, d^2, rsq, select, Coulomb, hit flag
+def flops_per_pair_short_f32(ns, asym, lj):
+    """A short-range pair of the treecode leaf kernel (the atom's far field
+    comes from proxies): hi/lo differences 6, d^2 5, 1/d 1; LJ as above; the
+    smeared kernels' range test and exp2 of the Yukawa term: d 1, scale 1,
+    exp2 1 (the table lookup of the pairs within R_s is not counted)."""
+    f = 6 + 5 + 1
     if asym:
-        s += 2 + 4 + 1 + 1      # d, scale, exp2, fma, branch test
+        f += 3
     if lj:
-        s += 3 + 4 * ns
-    return s
+        f += 3 + 4 * ns
+    return f
+
+
+def flops_per_far_pair(asym):
+    """One (atom, proxy) pair of the far-field sweep: differences 3, d^2 5,
+    1/d 1, Coulomb 2; Yukawa: d 1, scale 1, exp2 1, accumulate 2."""
+    return 11 + (5 if asym else 0)
+
+
+def leaf_interp_flops(points, blocks, degree, batch, ncomp):
+    """FP64 interpolation of the level-1 proxy values onto the grid: per
+    component the two block-level contractions and the per-point one."""
+    n1 = degree + 1
+    per_block = 2 * (n1 ** 3 * batch + n1 ** 2 * batch ** 2)
+    return ncomp * (2 * n1 * points + per_block * blocks)
+
+
+def source_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    profiles/<kernel>_<workload>_counters.txt, or None when it is absent or
+    was taken from other kernel sources than the ones in the tree."""
+    path = os.path.join(ROOT_PROFILES, f"{kernel}_{workload}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    files = kv.get("sources", "").split()
+    if not files or source_hash(files) != kv.get("sources_sha256"):
+        return None
+    return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
 
 
 def parse():
@@ -154,6 +202,9 @@ def main():
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t0
     ms_per_step = 1e3 * t_total / args.steps
+    # interaction counts (opt-in device counters, outside the timed steps)
+    step(api.Opts(**{**opts.__dict__, "stats": True}))
+    torch.cuda.synchronize()
     stats = api.last_stats()
 
     # per-kernel durations from the library's own HIP events (same stream)
@@ -163,7 +214,9 @@ def main():
     for _ in range(args.steps):
         step(ev_opts)
     torch.cuda.synchronize()
-    phases = {k: (v[0] / v[1], v[1] / args.steps) for k, v in api.phase_times().items()}
+    # per phase: (ms per timed launch, launches per step, ms per step)
+    phases = {k: (v[0] / v[1], v[1] / args.steps, v[0] / args.steps)
+              for k, v in api.phase_times().items()}
     dominant = max(phases, key=lambda k: phases[k][0] * phases[k][1])
 
     result = {
@@ -186,26 +239,53 @@ def main():
                    "method": args.method, "theta": args.theta, "degree": args.degree,
                    "eta_A": eta, "kappa_per_A": kap},
         "init_time_s": ms_per_step * 1e-3,
-        "phases_ms": {k: round(v[0], 4) for k, v in phases.items()},
+        "phases_ms": {k: round(v[2], 4) for k, v in phases.items()},
         "stats": {k: stats[k] for k in ("pairs_direct", "pairs_far", "pairs_short", "n_nodes",
                                         "n_batches")},
     }
 
-    # roofline of the dominant kernel
-    ms_dom, per_step = phases[dominant]
-    if dominant == "direct_f32":
-        fl = flops_per_pair_direct_f32(st.n, True, True) * n * m
-        slots = issue_slots_per_pair_direct_f32(st.n, True, True) * n * m
-        achieved = fl / (ms_dom * 1e-3) / 1e12
+    # roofline of the dominant kernel: algorithmic flops of each modelled
+    # phase (from the library's interaction counts) over its measured time
+    ni_asym = True
+    work = {}
+    if "direct_f32" in phases:
+        work["direct_f32"] = ("k_direct_f32",
+                              flops_per_pair_direct_f32(st.n, ni_asym, True) * n * m)
+    if args.method == "treecode_cp":
+        B = 8
+        blocks = -(-int(g.dims[0]) // B) * -(-int(g.dims[1]) // B) * -(-int(g.dims[2]) // B)
+        work["eval"] = ("k_cp_leaf",
+                        flops_per_pair_direct_f32(st.n, True, True) * stats["pairs_direct"]
+                        + flops_per_pair_short_f32(st.n, True, True) * stats["pairs_short"]
+                        + leaf_interp_flops(m, blocks, args.degree, B, 2))
+        work["upward"] = ("k_cp_sweep", flops_per_far_pair(True) * stats["pairs_far"])
+    elif args.method == "treecode":
+        work["eval"] = ("k_tree_eval",
+                        flops_per_pair_direct_f32(st.n, True, True) * stats["pairs_direct"]
+                        + flops_per_far_pair(True) * stats["pairs_far"])
+    rl = {}
+    for ph, (kern, fl) in work.items():
+        if ph not in phases:
+            continue
+        ms_ph = phases[ph][0]
+        ach = fl / (ms_ph * 1e-3) / 1e12
+        rl[ph] = {"kernel": kern, "flops": fl, "ms": ms_ph, "achieved": ach,
+                  "frac": ach / FP32_VALU_PEAK_TFLOPS}
+    dom = max(rl, key=lambda k: rl[k]["ms"]) if rl else None
+    if dom is not None:
+        d = rl[dom]
+        traffic = counter_traffic(d["kernel"], wl.name)
         result["roofline"] = {
-            "kernel": "k_direct_f32", "bound": "alu", "achieved": achieved,
-            "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK_TFLOPS,
-            "traffic": None, "issue_frac": slots / (ms_dom * 1e-3) / VALU_LANE_OPS,
-            "peak_published_packed": FP32_VALU_PUBLISHED_TFLOPS, "kernel_ms": ms_dom}
+            "kernel": d["kernel"], "phase": dom, "bound": "alu", "achieved": d["achieved"],
+            "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": d["frac"],
+            "traffic": traffic, "kernel_ms": d["ms"],
+            "peak_single_issue": FP32_VALU_SINGLE_ISSUE_TFLOPS,
+            "other_phases": {k: {kk: v[kk] for kk in ("kernel", "achieved", "frac", "ms")}
+                             for k, v in rl.items() if k != dom}}
     else:
         result["roofline"] = {"kernel": dominant, "bound": "alu", "achieved": None,
                               "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": None,
-                              "traffic": None, "kernel_ms": ms_dom}
+                              "traffic": None}
 
     # FP64 direct: the comparison of the metric, and the accuracy reference
     if not args.no_f64:

@@ -930,8 +930,8 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     // far field into the target proxies, reduction, downward pass
     if (ncl > 0) {
         {
-            PhaseTimer pt(ev, RISM_PHASE_UPWARD, s);
             if (ht[1] > 0) {
+                PhaseTimer pl(ev, RISM_PHASE_LISTS, s);
                 CpAssignArgs aa{};
                 aa.L = L;
                 aa.it_cl = it_cl;
@@ -950,6 +950,9 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
                 hipLaunchKernelGGL(k_cp_assign, (int)ht[1], kBlock, 0, s, aa);
                 hipLaunchKernelGGL(k_order_by_cost, 1, 1024, 0, s, (int)ht[1], it_n,
                                    (const uint32_t *)nullptr, it_order);
+            }
+            if (ht[1] > 0) {
+                PhaseTimer pu(ev, RISM_PHASE_UPWARD, s);
                 CpSweepArgs sa{};
                 sa.L = L;
                 sa.order = it_order;
@@ -964,10 +967,10 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
                 if (a.asym_on) launch_sweep<true>((int)ht[1], np, sa, s);
                 else launch_sweep<false>((int)ht[1], np, sa, s);
             }
-            hipLaunchKernelGGL(k_cp_reduce, ncl, kBlock, 0, s, ncl, np, citems, part, V);
         }
         {
             PhaseTimer pt(ev, RISM_PHASE_DOWNWARD, s);
+            hipLaunchKernelGGL(k_cp_reduce, ncl, kBlock, 0, s, ncl, np, citems, part, V);
             const size_t shm = (3 * (size_t)n1 * n1 + 3 * (size_t)np) * sizeof(double);
             for (int lvl = L.T - 1; lvl >= 1; --lvl)
                 hipLaunchKernelGGL(k_cp_down, L.cx[lvl] * L.cy[lvl] * L.cz[lvl], kBlock, shm, s, L,
@@ -1004,8 +1007,11 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         return RISM_E_UNSUPPORTED;
     }
     {
+        {
+            PhaseTimer pl(ev, RISM_PHASE_LISTS, s);
+            hipLaunchKernelGGL(k_order_by_cost, 1, 1024, 0, s, nleaf, nd, nsh, order);
+        }
         PhaseTimer pt(ev, RISM_PHASE_EVAL, s);
-        hipLaunchKernelGGL(k_order_by_cost, 1, 1024, 0, s, nleaf, nd, nsh, order);
         switch (a.sp.ns_pad) {
         case 1: launch_leaf_ns<1>(a.lj_mode, a.asym_on, B, nleaf, shm, la, s); break;
         case 2: launch_leaf_ns<2>(a.lj_mode, a.asym_on, B, nleaf, shm, la, s); break;
