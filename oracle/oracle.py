@@ -56,6 +56,10 @@ def _load():
         lib.oracle_backward_points.argtypes = [i64, _P, _P, _P, _P, i32, _P, _P, _P, d, _P,
                                                i64, _P, _P, _P, _P, _P, _P]
         lib.oracle_grid_points.argtypes = [_P, _P, _PI, _P]
+        lib.oracle_asymptotics_k.argtypes = [i64, _P, _P, i32, _P, _PI, d, d, d, d, d,
+                                             _P, _P, _PI, d, d, _P, _P]
+        lib.oracle_kcut.argtypes = [C.c_int, d, d, d, d, d, d, d, d]
+        lib.oracle_kcut.restype = d
         lib.oracle_num_threads.restype = C.c_int
         _lib = lib
     return _lib
@@ -174,6 +178,36 @@ def asymptotics_grid(xyz, q, site_q, ionic, origin, spacing, dims, kc, eta, kapp
                                      _ptr(dm, _PI), _ptr(c), _ptr(h))
     assert rc == 0
     return c, h
+
+
+def asymptotics_k(xyz, q, site_q, ionic, origin, spacing, dims, kc, eta, kappa, beta,
+                  diel, kcut_c=0.0, kcut_h=0.0, want_c=True, want_h=True):
+    """c^lr(k) [S][nz][ny][nx//2+1] and h^lr(k) [n_ionic][...] as complex128
+    (Sec. 2.2, Eqs. 5 and 7; transform-order frequencies, see the C file)."""
+    lib = _load()
+    xyz = _d(np.asarray(xyz).reshape(-1, 3))
+    q, sq = _d(q), _d(site_q)
+    ion = np.ascontiguousarray(ionic, dtype=np.int32)
+    o, h_ = _d(origin), _d(spacing)
+    dm = np.ascontiguousarray(dims, dtype=np.int32)
+    shp = (int(dm[2]), int(dm[1]), int(dm[0]) // 2 + 1)
+    c = np.empty((len(sq),) + shp + (2,)) if want_c else None
+    h = np.empty((int(ion.sum()),) + shp + (2,)) if want_h else None
+    rc = lib.oracle_asymptotics_k(len(q), _ptr(xyz), _ptr(q), len(sq), _ptr(sq),
+                                  _ptr(ion, _PI), float(kc), float(eta), float(kappa),
+                                  float(beta), float(diel), _ptr(o), _ptr(h_), _ptr(dm, _PI),
+                                  float(kcut_c), float(kcut_h), _ptr(c), _ptr(h))
+    assert rc == 0
+    cz = None if c is None else c[..., 0] + 1j * c[..., 1]
+    hz = None if h is None else h[..., 0] + 1j * h[..., 1]
+    return cz, hz
+
+
+def kcut(which, tol, qmax, qabs_sum, kc, eta, kappa, beta, diel):
+    """Frequency cut-off of the c^lr ('c') or h^lr ('h') bound of Sec. 2.5."""
+    return float(_load().oracle_kcut(0 if which == "c" else 1, float(tol), float(qmax),
+                                     float(qabs_sum), float(kc), float(eta), float(kappa),
+                                     float(beta), float(diel)))
 
 
 def grid_points(origin, spacing, dims):

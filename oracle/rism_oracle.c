@@ -31,6 +31,20 @@
  *  - Tail constant: Sec. 2.6 (final result for the chemical-potential
  *    correction): T_gamma = 4 pi sum_a int_{r_cut}^inf u_LJ(r) r^2 dr
  *                        = (4 pi / 3) sum_a (A/(3 r_c^9) - B/r_c^3).
+ *  - c^lr_gamma(k), h^lr_j(k): Sec. 2.2, Eqs. 5 and 7, times k_C, on the half
+ *    grid of a real-to-complex transform of the [nz][ny][nx] grid (entries
+ *    [mz][my][mx], mx = 0..nx/2; my, mz in transform order 0, 1, ..., then
+ *    the negative frequencies), k = 2 pi (mx/(nx hx), my/(ny hy), mz/(nz hz)).
+ *    Reading: the structure factor is S(k) = sum_a Q_a exp(-i k.(R_a - o)),
+ *    o the grid origin, i.e. the sign and anchor of a forward discrete
+ *    transform of the grid (the paper writes exp(+i k.R): the same quantity
+ *    under the opposite sign convention).  c^lr(k = 0) is set to 0 (1/k^2
+ *    with S(0) = 0 for a neutral solute).  Entries beyond the frequency
+ *    cut-off are 0.
+ *  - Frequency cut-off: Sec. 2.5, Eq. 26 and the h^lr bound after it.
+ *    Reading: the bound uses sum_a |Q_a| (the signed sum vanishes for a
+ *    neutral solute) and the largest |q| of the sites concerned; the root
+ *    k_cut of bound(k) = tol is found here by plain bisection.
  *  - Backward: gradient of L = sum_gamma sum_r w_gamma(r) u_gamma(r) with
  *    respect to atom positions, charges, eps_a and sigma_a, differentiating
  *    the definition of u above term by term (the jump at r_cut is ignored).
@@ -216,6 +230,94 @@ int oracle_asymptotics_grid(int64_t n, const double *xyz, const double *q,
                        p, c ? c + i : NULL, h ? h + i : NULL, m);
     }
     return 0;
+}
+
+/* --------------------------------------------- reciprocal-space asymptotics */
+
+/* Frequency index of transform position j on an axis of n points. */
+static int freq_index(int j, int n)
+{
+    return j <= (n - 1) / 2 ? j : j - n;
+}
+
+int oracle_asymptotics_k(int64_t n, const double *xyz, const double *q,
+                         int32_t ns, const double *sq, const int32_t *ionic,
+                         double kc, double eta, double kappa, double beta,
+                         double diel, const double *origin, const double *spacing,
+                         const int32_t *dims, double kcut_c, double kcut_h,
+                         double *c, double *h)
+{
+    if (n < 0 || ns <= 0 || dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0 ||
+        !(eta > 0.0) || kappa < 0.0 || !(diel > 0.0))
+        return -1;
+    const int nxh = dims[0] / 2 + 1;
+    const int64_t mk = (int64_t)nxh * dims[1] * dims[2];
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t e = 0; e < mk; ++e) {
+        const int jx = (int)(e % nxh);
+        const int jy = (int)((e / nxh) % dims[1]);
+        const int jz = (int)(e / ((int64_t)nxh * dims[1]));
+        double k[3];
+        k[0] = 2.0 * ORACLE_PI * jx / (dims[0] * spacing[0]);
+        k[1] = 2.0 * ORACLE_PI * freq_index(jy, dims[1]) / (dims[1] * spacing[1]);
+        k[2] = 2.0 * ORACLE_PI * freq_index(jz, dims[2]) / (dims[2] * spacing[2]);
+        const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+        const double kk = sqrt(k2);
+        double sre = 0.0, sim = 0.0;
+        for (int64_t a = 0; a < n; ++a) {
+            double ph = 0.0;
+            for (int d = 0; d < 3; ++d) ph += k[d] * (xyz[3 * a + d] - origin[d]);
+            sre += q[a] * cos(ph);
+            sim -= q[a] * sin(ph);
+        }
+        const double gauss = exp(-k2 * eta * eta / 4.0);
+        int32_t j = 0;
+        for (int32_t g = 0; g < ns; ++g) {
+            if (c) {
+                double f = 0.0;
+                if (k2 > 0.0 && !(kcut_c > 0.0 && kk > kcut_c))
+                    f = -4.0 * ORACLE_PI * beta * kc * sq[g] * gauss / k2;
+                c[2 * ((int64_t)g * mk + e)] = f * sre;
+                c[2 * ((int64_t)g * mk + e) + 1] = f * sim;
+            }
+            if (ionic[g]) {
+                if (h) {
+                    double f = 0.0;
+                    if (!(kcut_h > 0.0 && kk > kcut_h))
+                        f = -4.0 * ORACLE_PI * beta * kc * sq[g] * gauss / (diel * (k2 + kappa * kappa));
+                    h[2 * ((int64_t)j * mk + e)] = f * sre;
+                    h[2 * ((int64_t)j * mk + e) + 1] = f * sim;
+                }
+                ++j;
+            }
+        }
+    }
+    return 0;
+}
+
+/* Cut-off wave number of the c^lr (which = 0) or h^lr (which = 1) bound of
+ * Sec. 2.5: the k > 0 where bound(k) = tol, bound(k) =
+ * 4 sqrt(2) pi beta k_C qmax sum|Q| exp(-k^2 eta^2/4) / (k^2 [+ kappa^2] [eps]).
+ * The bound decreases in k, so the root is bracketed and bisected.  Returns
+ * 0 if tol <= 0 or the bound never exceeds tol (no cut-off needed at k > 0
+ * would be 0 too: every k is below tol). */
+double oracle_kcut(int which, double tol, double qmax, double qabs_sum, double kc,
+                   double eta, double kappa, double beta, double diel)
+{
+    if (!(tol > 0.0)) return 0.0;
+    const double pref = 4.0 * sqrt(2.0) * ORACLE_PI * beta * kc * fabs(qmax) * qabs_sum;
+    double lo = 1e-12, hi = 1.0;
+#define BOUND(k) (which == 0 ? pref * exp(-(k) * (k) * eta * eta / 4.0) / ((k) * (k)) \
+                             : pref * exp(-(k) * (k) * eta * eta / 4.0) / (diel * ((k) * (k) + kappa * kappa)))
+    if (BOUND(lo) <= tol) return 0.0;
+    while (BOUND(hi) > tol) hi *= 2.0;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (BOUND(mid) > tol) lo = mid;
+        else hi = mid;
+    }
+#undef BOUND
+    return 0.5 * (lo + hi);
 }
 
 /* -------------------------------------------------------- LJ cut-off, tail */

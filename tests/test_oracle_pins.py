@@ -405,3 +405,114 @@ def test_backward_euler_homogeneity(oracle):
                                  KC, terms=2)
     assert (sol.q * dq).sum() == pytest.approx((w * uc).sum(), rel=1e-10)
     assert (sol.eps * de).sum() == pytest.approx(0.5 * (w * ul).sum(), rel=1e-10)
+
+
+# ------------------------------------------------- reciprocal-space asymptotics
+
+def test_reciprocal_grid_matches_transform_of_real_space_grid(oracle):
+    """Sec. 2.2: Eq. 7 is the Fourier transform of Eq. 6.  On a grid, the
+    forward discrete transform (numpy's rfftn, sign exp(-i k.r), positions
+    relative to the grid origin) of the real-space oracle's h^lr times the
+    cell volume must give the reciprocal-space oracle's h^lr(k) entry by
+    entry: layout, frequency order, phase anchor and prefactors at once.
+    kappa = 3 makes h^lr(r) decay to < 1e-9 at the box faces, and the
+    Gaussian makes aliasing negligible at 0.3 A."""
+    dims = np.array([64, 60, 56], np.int32)
+    sp = np.array([0.3, 0.3, 0.3])
+    origin = np.array([-9.4, -8.7, -8.1])
+    centre = origin + sp * (dims - 1) / 2
+    rng = np.random.default_rng(8)
+    xyz = centre + rng.uniform(-1.2, 1.2, size=(3, 3))
+    q = np.array([0.7, -0.4, 0.9])
+    sq, ionic = np.array([1.0, -0.5]), np.array([1, 1], np.int32)
+    kappa = 3.0
+    _, hr = oracle.asymptotics_grid(xyz, q, sq, ionic, origin, sp, dims, KC, ETA, kappa, BETA,
+                                    DIEL, want_c=False)
+    _, hk = oracle.asymptotics_k(xyz, q, sq, ionic, origin, sp, dims, KC, ETA, kappa, BETA,
+                                 DIEL, want_c=False)
+    ft = np.fft.rfftn(hr, axes=(1, 2, 3)) * np.prod(sp)
+    assert ft.shape == hk.shape
+    err = np.linalg.norm(ft - hk) / np.linalg.norm(hk)
+    assert err < 1e-9
+
+
+def test_reciprocal_c_is_eps_times_h_without_screening(oracle):
+    """Eqs. 5 and 7 at kappa = 0 differ only by the dielectric (as Eqs. 4 and
+    6 do in real space): c_g(k) = eps h_g(k) for every k != 0; c(0) = 0 and
+    h(0) at kappa > 0 is the structure factor at k = 0 (the net charge)."""
+    wl = W.tiny(n_atoms=7, dims=(9, 8, 7), seed=12, spacing=0.6)
+    sol, st, g = wl.solute, wl.sites, wl.grid
+    ck, hk = oracle.asymptotics_k(sol.xyz, sol.q, st.q, st.ionic, g.origin, g.spacing, g.dims,
+                                  KC, ETA, 0.0, BETA, DIEL)
+    ion = np.nonzero(st.ionic)[0]
+    nz = np.ones(ck.shape[1:], bool)
+    nz[0, 0, 0] = False
+    np.testing.assert_allclose(ck[ion][:, nz], DIEL * hk[:, nz], rtol=1e-12)
+    assert np.all(ck[:, 0, 0, 0] == 0)
+    _, hk = oracle.asymptotics_k(sol.xyz, sol.q, st.q, st.ionic, g.origin, g.spacing, g.dims,
+                                 KC, ETA, 0.5, BETA, DIEL, want_c=False)
+    expect = -4 * math.pi * BETA * KC * st.q[ion] * sol.q.sum() / (DIEL * 0.25)
+    np.testing.assert_allclose(hk[:, 0, 0, 0].real, expect, rtol=1e-12, atol=1e-12)
+
+
+def test_reciprocal_bruteforce_40_digits(oracle):
+    """Every entry of a tiny odd/even grid against a 40-digit sum with the
+    frequencies taken from numpy's transform-frequency helpers."""
+    mp.mp.dps = 40
+    rng = np.random.default_rng(5)
+    xyz = rng.uniform(-1.5, 1.5, size=(3, 3))
+    q = np.array([0.5, -0.8, 0.3])
+    sq, ionic = np.array([-0.834, 1.0]), np.array([0, 1], np.int32)
+    dims = np.array([5, 4, 3], np.int32)
+    sp = np.array([0.7, 0.55, 0.9])
+    origin = np.array([-1.1, 0.4, -0.6])
+    kappa = 0.3
+    ck, hk = oracle.asymptotics_k(xyz, q, sq, ionic, origin, sp, dims, KC, ETA, kappa, BETA, DIEL)
+    fx = np.fft.rfftfreq(int(dims[0]), sp[0])
+    fy = np.fft.fftfreq(int(dims[1]), sp[1])
+    fz = np.fft.fftfreq(int(dims[2]), sp[2])
+    for iz, vz in enumerate(fz):
+        for iy, vy in enumerate(fy):
+            for ix, vx in enumerate(fx):
+                k = [2 * mp.pi * mp.mpf(float(v)) for v in (vx, vy, vz)]
+                k2 = sum(kk * kk for kk in k)
+                s = mp.mpc(0)
+                for a in range(3):
+                    ph = sum(k[d] * (mp.mpf(float(xyz[a, d])) - mp.mpf(float(origin[d])))
+                             for d in range(3))
+                    s += mp.mpf(float(q[a])) * mp.exp(-1j * ph)
+                gauss = mp.exp(-k2 * ETA * ETA / 4)
+                for g in range(2):
+                    cv = 0 if k2 == 0 else -4 * mp.pi * BETA * KC * sq[g] * gauss / k2 * s
+                    assert abs(complex(cv) - ck[g, iz, iy, ix]) <= 1e-12 * (abs(complex(cv)) + 1e-30)
+                hv = -4 * mp.pi * BETA * KC * sq[1] * gauss / (DIEL * (k2 + kappa * kappa)) * s
+                assert abs(complex(hv) - hk[0, iz, iy, ix]) <= 1e-12 * abs(complex(hv))
+
+
+def test_frequency_cutoff(oracle):
+    """Sec. 2.5: the bound of Eq. 26 (and of h^lr) at the returned k_cut
+    equals the tolerance; tighter tolerances cut later; entries beyond the
+    cut-off are exactly zero and the others are untouched."""
+    qmax, qabs = 1.0, 37.5
+    prev = {"c": 0.0, "h": 0.0}
+    for tol in (1e-2, 1e-4, 1e-6, 1e-8):
+        for which in ("c", "h"):
+            kc_ = oracle.kcut(which, tol, qmax, qabs, KC, ETA, KAPPA, BETA, DIEL)
+            pref = 4 * math.sqrt(2) * math.pi * BETA * KC * qmax * qabs
+            den = kc_ ** 2 if which == "c" else DIEL * (kc_ ** 2 + KAPPA ** 2)
+            assert pref * math.exp(-kc_ ** 2 * ETA ** 2 / 4) / den == pytest.approx(tol, rel=1e-9)
+            assert kc_ > prev[which]
+            prev[which] = kc_
+    wl = W.tiny(n_atoms=5, dims=(12, 10, 9), seed=6, spacing=0.4)
+    sol, st, g = wl.solute, wl.sites, wl.grid
+    full = oracle.asymptotics_k(sol.xyz, sol.q, st.q, st.ionic, g.origin, g.spacing, g.dims,
+                                KC, ETA, KAPPA, BETA, DIEL)
+    cut = oracle.asymptotics_k(sol.xyz, sol.q, st.q, st.ionic, g.origin, g.spacing, g.dims,
+                               KC, ETA, KAPPA, BETA, DIEL, kcut_c=4.0, kcut_h=3.0)
+    kx = 2 * np.pi * np.fft.rfftfreq(int(g.dims[0]), g.spacing[0])
+    ky = 2 * np.pi * np.fft.fftfreq(int(g.dims[1]), g.spacing[1])
+    kz = 2 * np.pi * np.fft.fftfreq(int(g.dims[2]), g.spacing[2])
+    kk = np.sqrt(kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2)
+    for f, c_, lim in ((full[0], cut[0], 4.0), (full[1], cut[1], 3.0)):
+        assert np.all(c_[:, kk > lim] == 0)
+        np.testing.assert_array_equal(c_[:, kk <= lim], f[:, kk <= lim])
