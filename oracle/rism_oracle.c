@@ -39,7 +39,8 @@
  *    o the grid origin, i.e. the sign and anchor of a forward discrete
  *    transform of the grid (the paper writes exp(+i k.R): the same quantity
  *    under the opposite sign convention).  c^lr(k = 0) is set to 0 (1/k^2
- *    with S(0) = 0 for a neutral solute).  Entries beyond the frequency
+ *    with S(0) = 0 for a neutral solute), and so is h^lr(k = 0) when
+ *    kappa = 0 (the same singularity).  Entries beyond the frequency
  *    cut-off are 0.
  *  - Frequency cut-off: Sec. 2.5, Eq. 26 and the h^lr bound after it.
  *    Reading: the bound uses sum_a |Q_a| (the signed sum vanishes for a
@@ -240,20 +241,24 @@ static int freq_index(int j, int n)
     return j <= (n - 1) / 2 ? j : j - n;
 }
 
-int oracle_asymptotics_k(int64_t n, const double *xyz, const double *q,
-                         int32_t ns, const double *sq, const int32_t *ionic,
-                         double kc, double eta, double kappa, double beta,
-                         double diel, const double *origin, const double *spacing,
-                         const int32_t *dims, double kcut_c, double kcut_h,
-                         double *c, double *h)
+/* Entries e of the half grid (all of them when entries is NULL, else the
+ * n_entries listed flat indices); outputs [site][entry][re, im]. */
+int oracle_asymptotics_k_entries(int64_t n, const double *xyz, const double *q,
+                                 int32_t ns, const double *sq, const int32_t *ionic,
+                                 double kc, double eta, double kappa, double beta,
+                                 double diel, const double *origin, const double *spacing,
+                                 const int32_t *dims, double kcut_c, double kcut_h,
+                                 int64_t n_entries, const int64_t *entries,
+                                 double *c, double *h)
 {
     if (n < 0 || ns <= 0 || dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0 ||
         !(eta > 0.0) || kappa < 0.0 || !(diel > 0.0))
         return -1;
     const int nxh = dims[0] / 2 + 1;
-    const int64_t mk = (int64_t)nxh * dims[1] * dims[2];
+    const int64_t mk = entries ? n_entries : (int64_t)nxh * dims[1] * dims[2];
 #pragma omp parallel for schedule(dynamic, 16)
-    for (int64_t e = 0; e < mk; ++e) {
+    for (int64_t ie = 0; ie < mk; ++ie) {
+        const int64_t e = entries ? entries[ie] : ie;
         const int jx = (int)(e % nxh);
         const int jy = (int)((e / nxh) % dims[1]);
         const int jz = (int)(e / ((int64_t)nxh * dims[1]));
@@ -277,22 +282,33 @@ int oracle_asymptotics_k(int64_t n, const double *xyz, const double *q,
                 double f = 0.0;
                 if (k2 > 0.0 && !(kcut_c > 0.0 && kk > kcut_c))
                     f = -4.0 * ORACLE_PI * beta * kc * sq[g] * gauss / k2;
-                c[2 * ((int64_t)g * mk + e)] = f * sre;
-                c[2 * ((int64_t)g * mk + e) + 1] = f * sim;
+                c[2 * ((int64_t)g * mk + ie)] = f * sre;
+                c[2 * ((int64_t)g * mk + ie) + 1] = f * sim;
             }
             if (ionic[g]) {
                 if (h) {
                     double f = 0.0;
-                    if (!(kcut_h > 0.0 && kk > kcut_h))
+                    if (!(kcut_h > 0.0 && kk > kcut_h) && k2 + kappa * kappa > 0.0)
                         f = -4.0 * ORACLE_PI * beta * kc * sq[g] * gauss / (diel * (k2 + kappa * kappa));
-                    h[2 * ((int64_t)j * mk + e)] = f * sre;
-                    h[2 * ((int64_t)j * mk + e) + 1] = f * sim;
+                    h[2 * ((int64_t)j * mk + ie)] = f * sre;
+                    h[2 * ((int64_t)j * mk + ie) + 1] = f * sim;
                 }
                 ++j;
             }
         }
     }
     return 0;
+}
+
+int oracle_asymptotics_k(int64_t n, const double *xyz, const double *q,
+                         int32_t ns, const double *sq, const int32_t *ionic,
+                         double kc, double eta, double kappa, double beta,
+                         double diel, const double *origin, const double *spacing,
+                         const int32_t *dims, double kcut_c, double kcut_h,
+                         double *c, double *h)
+{
+    return oracle_asymptotics_k_entries(n, xyz, q, ns, sq, ionic, kc, eta, kappa, beta, diel,
+                                        origin, spacing, dims, kcut_c, kcut_h, 0, NULL, c, h);
 }
 
 /* Cut-off wave number of the c^lr (which = 0) or h^lr (which = 1) bound of

@@ -448,7 +448,7 @@ def test_reciprocal_c_is_eps_times_h_without_screening(oracle):
     nz = np.ones(ck.shape[1:], bool)
     nz[0, 0, 0] = False
     np.testing.assert_allclose(ck[ion][:, nz], DIEL * hk[:, nz], rtol=1e-12)
-    assert np.all(ck[:, 0, 0, 0] == 0)
+    assert np.all(ck[:, 0, 0, 0] == 0) and np.all(hk[:, 0, 0, 0] == 0)
     _, hk = oracle.asymptotics_k(sol.xyz, sol.q, st.q, st.ionic, g.origin, g.spacing, g.dims,
                                  KC, ETA, 0.5, BETA, DIEL, want_c=False)
     expect = -4 * math.pi * BETA * KC * st.q[ion] * sol.q.sum() / (DIEL * 0.25)
@@ -516,3 +516,16 @@ def test_frequency_cutoff(oracle):
     for f, c_, lim in ((full[0], cut[0], 4.0), (full[1], cut[1], 3.0)):
         assert np.all(c_[:, kk > lim] == 0)
         np.testing.assert_array_equal(c_[:, kk <= lim], f[:, kk <= lim])
+
+
+def test_reciprocal_entries_agree_with_full_grid(oracle):
+    wl = W.tiny(n_atoms=6, dims=(8, 7, 6), seed=9, spacing=0.45)
+    sol, st, g = wl.solute, wl.sites, wl.grid
+    c, h = oracle.asymptotics_k(sol.xyz, sol.q, st.q, st.ionic, g.origin, g.spacing, g.dims, KC,
+                                ETA, KAPPA, BETA, DIEL, kcut_c=5.0, kcut_h=4.0)
+    ent = np.array([0, 3, 17, 40, 111, c[0].size - 1])
+    ce, he = oracle.asymptotics_k_entries(sol.xyz, sol.q, st.q, st.ionic, g.origin, g.spacing,
+                                          g.dims, ent, KC, ETA, KAPPA, BETA, DIEL, kcut_c=5.0,
+                                          kcut_h=4.0)
+    np.testing.assert_array_equal(ce, c.reshape(c.shape[0], -1)[:, ent])
+    np.testing.assert_array_equal(he, h.reshape(h.shape[0], -1)[:, ent])
