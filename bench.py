@@ -125,6 +125,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-recip", action="store_true",
+                    help="skip the reciprocal-space asymptotics timing")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the run, copy a device buffer of this size (MiB) once: a "
                          "kernel of known traffic for scaling HBM byte counters")
@@ -338,6 +340,28 @@ def main():
             api.potential_backward(xyz, q, s, e, sites, grid, ao, w)
         torch.cuda.synchronize()
         result["adjoint"] = {"method": ao.method, "time_s": (time.perf_counter() - t0) / reps}
+
+    # reciprocal-space asymptotics (the next row after the real-space path):
+    # c^lr(k) and h^lr(k) on the half grid, frequency cut-off at tol 1e-6
+    if not args.no_recip:
+        ck = (torch.empty((st.n, shp[0], shp[1], shp[2] // 2 + 1, 2), device=dev),
+              torch.empty((ni, shp[0], shp[1], shp[2] // 2 + 1, 2), device=dev) if ni else None)
+        ok = api.Opts(**{**opts.__dict__})
+        api.asymptotics_k(xyz, q, s, e, sites, grid, ok, eta, kap, beta, diel, tol=1e-6, outs=ck)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            api.asymptotics_k(xyz, q, s, e, sites, grid, ok, eta, kap, beta, diel, tol=1e-6,
+                              outs=ck)
+        torch.cuda.synchronize()
+        tk = (time.perf_counter() - t0) / reps
+        terms = n * shp[0] * shp[1] * (shp[2] // 2 + 1)
+        result["asymptotics_k"] = {"time_s": tk, "tol": 1e-6,
+                                   "gterm_per_s": terms / tk / 1e9,
+                                   "note": "structure-factor terms (atom, k-point) per second "
+                                           "over the whole half grid"}
+        del ck
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl, args.lj_cutoff, args.cpu_seconds)

@@ -17,7 +17,10 @@
  * Streams: `stream` is a hipStream_t (NULL = the default stream).  Work is
  * enqueued on it; outputs are valid once the stream has been synchronised.
  * A call may synchronise the stream internally (tree sizes, device-side
- * input checks, host outputs such as lj_tail).  Calls that use the same
+ * input checks, host outputs such as lj_tail); RISM_TREECODE_CP returns only
+ * after its work has completed (it reads back list sizes at the end and, if
+ * buffers sized from an earlier call of the same problem shape were too
+ * small, runs its second half again).  Calls that use the same
  * device and stream from several host threads must be serialised by the
  * caller; scratch memory is kept per (device, stream) and reused.
  *
@@ -47,9 +50,9 @@ extern "C" {
  *                   definitions term by term (GPU reference).
  * RISM_DIRECT_F32C  FP32 pair arithmetic over every pair, blocked partial
  *                   sums flushed into FP64 (electrostatics) or compensated
- *                   FP32 (LJ) accumulators; the smeared kernels are split
- *                   exactly into 1/d and exp(-kappa d)/d far parts plus a
- *                   short-range correction (d < R_s).
+ *                   FP32 (LJ) accumulators; the smeared kernels are 1/d and
+ *                   2 exp(-kappa d)/d beyond R_s (to < 1e-12) and come from a
+ *                   cubic table (FP64-fitted) within R_s.
  * RISM_TREECODE     as DIRECT_F32C, but the far parts 1/d and exp(-kappa d)/d
  *                   come from a particle-cluster treecode: Morton-sorted
  *                   octree on the atoms, barycentric Chebyshev proxy charges,
@@ -182,6 +185,29 @@ int rism_asymptotics(const rism_solute *solute, const rism_sites *sites,
                      const rism_grid *grid, const rism_opts *opts,
                      double eta, double kappa, double beta, double dielectric,
                      void *c_lr, void *h_lr, void *stream);
+
+/*
+ * Reciprocal-space long-range asymptotics (Sec. 2.2, Eqs. 5 and 7, times
+ * coulomb_k) on the half grid of a real-to-complex transform of the grid:
+ *   c_k [device] [S][nz][ny][nx/2+1][2]       (re, im), of out_dtype;
+ *   h_k [device] [n_ionic][nz][ny][nx/2+1][2] (ionic sites only).
+ * Entry (jz, jy, jx) is k = 2 pi (jx/(nx hx), fy/(ny hy), fz/(nz hz)) with
+ * fy = jy for jy <= (ny-1)/2, else jy - ny (likewise fz): the order of a
+ * forward discrete transform.  The structure factor is
+ *   S(k) = sum_a Q_a exp(-i k.(R_a - origin)),
+ * i.e. the transform of a grid anchored at `origin` with the exp(-i k.r)
+ * sign (the paper's exp(+i k.R) is the same quantity under the opposite
+ * sign convention).  c_k at k = 0 is 0, and so is h_k at k = 0 when kappa = 0.
+ * tol > 0 applies the frequency cut-off of Sec. 2.5: entries with |k| above
+ * the root of the error bound (Eq. 26 for c, its analogue for h; the bound
+ * uses sum_a |Q_a| and the largest |q| of the sites concerned) are 0 and not
+ * summed; tol <= 0 sums every entry.  Either output may be NULL (h_k is
+ * ignored without ionic sites).  opts->method is not used.
+ */
+int rism_asymptotics_k(const rism_solute *solute, const rism_sites *sites,
+                       const rism_grid *grid, const rism_opts *opts,
+                       double eta, double kappa, double beta, double dielectric, double tol,
+                       void *c_k, void *h_k, void *stream);
 
 /*
  * Fused initialisation: rism_potential and rism_asymptotics in one pass

@@ -89,6 +89,7 @@ def lib():
         L.rism_potential.argtypes = common + [vp, P(C.c_double), vp]
         L.rism_asymptotics.argtypes = common + [d, d, d, d, vp, vp, vp]
         L.rism_initialize.argtypes = common + [d, d, d, d, vp, P(C.c_double), vp, vp, vp]
+        L.rism_asymptotics_k.argtypes = common + [d, d, d, d, d, vp, vp, vp]
         L.rism_potential_backward.argtypes = common + [vp, vp, vp, vp, vp, vp]
         L.rism_compare.argtypes = [vp, C.c_int32, vp, C.c_int64, d, P(C.c_double), vp]
         L.rism_last_stats.argtypes = [P(Stats)]
@@ -96,7 +97,8 @@ def lib():
         L.rism_phase_times.argtypes = [P(C.c_double), P(C.c_int64)]
         L.rism_phase_times.restype = C.c_int
         for f in ("rism_potential", "rism_asymptotics", "rism_initialize",
-                  "rism_potential_backward", "rism_compare", "rism_last_stats"):
+                  "rism_potential_backward", "rism_compare", "rism_last_stats",
+                  "rism_asymptotics_k"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -231,6 +233,31 @@ def asymptotics(xyz, q, sites, grid, opts: Opts, eta, kappa, beta, dielectric, w
     _check(L.rism_asymptotics(C.byref(so), C.byref(sites), C.byref(grid), C.byref(oc), eta, kappa,
                               beta, dielectric, _ptr(c), _ptr(h), _stream()))
     return c, h
+
+
+def asymptotics_k(xyz, q, sigma, eps, sites, grid, opts: Opts, eta, kappa, beta, dielectric,
+                  tol=0.0, want_c=True, want_h=True, outs=None):
+    """Reciprocal-space c^lr(k) [S][nz][ny][nx//2+1] and h^lr(k) [n_ionic][...]
+    as complex tensors (views of interleaved real buffers); ``tol`` > 0
+    applies the frequency cut-off.  ``outs`` may supply the real (c, h)
+    buffers of shape [...][2]."""
+    L = lib()
+    so = make_solute(xyz, q, sigma, eps)
+    oc = opts.to_c()
+    nz, ny, nx = _grid_shape(grid)
+    shp = (nz, ny, nx // 2 + 1, 2)
+    ni = n_ionic(np.ctypeslib.as_array(sites.ionic, shape=(sites.n,)))
+    if outs is None:
+        dt, dev = opts.torch_dtype, xyz.device
+        c = torch.empty((sites.n,) + shp, dtype=dt, device=dev) if want_c else None
+        h = torch.empty((ni,) + shp, dtype=dt, device=dev) if (want_h and ni) else None
+    else:
+        c, h = outs
+    _check(L.rism_asymptotics_k(C.byref(so), C.byref(sites), C.byref(grid), C.byref(oc), eta,
+                                kappa, beta, dielectric, float(tol), _ptr(c), _ptr(h), _stream()))
+    cz = None if c is None else torch.view_as_complex(c)
+    hz = None if h is None else torch.view_as_complex(h)
+    return cz, hz
 
 
 def initialize(xyz, q, sigma, eps, sites, grid, opts: Opts, eta, kappa, beta, dielectric,

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librism.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["rism_api.hip", "k_direct.hip", "k_adjoint.hip", "k_tree.hip", "k_tree_eval.hip", "k_cp.hip", "k_adj_tree.hip"]
+SOURCES = ["rism_api.hip", "k_direct.hip", "k_adjoint.hip", "k_tree.hip", "k_tree_eval.hip", "k_cp.hip",
+           "k_adj_tree.hip", "k_asym_k.hip"]
 ARCH = os.environ.get("RISM_OFFLOAD_ARCH", "gfx950")
 
 CFLAGS = [

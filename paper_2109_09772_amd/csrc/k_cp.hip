@@ -23,6 +23,8 @@
 // is evaluated per leaf for every atom within reach, whatever level the atom
 // was assigned to.
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <cmath>
 
 #include "cheb.h"
@@ -38,32 +40,115 @@ constexpr int kCpChunkLeaves = 32;   // candidate source leaves per far work ite
 
 // ----------------------------------------------------------------- scans
 
-// Exclusive scan of a[0..n) in place by one 1024-thread workgroup; the sum is
-// written to *total.
-__global__ __launch_bounds__(1024) void k_scan_excl_u32(uint32_t *a, int n, uint32_t *total)
+// Exclusive scans in place of up to four arrays of n entries each (one
+// launch per step for all of them): tile sums, a scan of the tile sums per
+// array (its total to *total[k]), then each tile scanned from LDS with its
+// offset added.  Tiles are 2048 entries, 8 per thread.
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 8;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+struct ScanBatch {
+    uint32_t *a[4];
+    uint32_t *total[4];
+    int n, na;
+};
+
+__device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t *red)
 {
-    __shared__ uint32_t s[1024];
-    const int t = threadIdx.x;
-    const int per = (n + 1023) / 1024;
-    const int lo = t * per < n ? t * per : n;
-    const int hi = lo + per < n ? lo + per : n;
-    uint32_t sum = 0;
-    for (int i = lo; i < hi; ++i) sum += a[i];
-    s[t] = sum;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) red[wave] = v;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t v = t >= off ? s[t - off] : 0u;
+    uint32_t t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    __syncthreads();
+    return t;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(ScanBatch b, uint32_t *bsum,
+                                                            int ntiles)
+{
+    __shared__ uint32_t red[kScanThreads / 64];
+    const uint32_t *a = b.a[blockIdx.y];
+    const int base = blockIdx.x * kScanTile;
+    uint32_t v = 0;
+    for (int k = 0; k < kScanPer; ++k) {
+        const int i = base + k * kScanThreads + threadIdx.x;
+        if (i < b.n) v += a[i];
+    }
+    v = block_sum_u32(v, red);
+    if (threadIdx.x == 0) bsum[blockIdx.y * ntiles + blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(ScanBatch b, uint32_t *bsum, int ntiles)
+{
+    __shared__ uint32_t sc[1024];
+    uint32_t *bs = bsum + blockIdx.x * ntiles;
+    uint32_t carry = 0;
+    for (int c0 = 0; c0 < ntiles; c0 += 1024) {
+        const int i = c0 + threadIdx.x;
+        const uint32_t v = i < ntiles ? bs[i] : 0u;
+        sc[threadIdx.x] = v;
         __syncthreads();
-        s[t] += v;
+        for (int off = 1; off < 1024; off <<= 1) {
+            const uint32_t u = threadIdx.x >= off ? sc[threadIdx.x - off] : 0u;
+            __syncthreads();
+            sc[threadIdx.x] += u;
+            __syncthreads();
+        }
+        if (i < ntiles) bs[i] = carry + sc[threadIdx.x] - v;
+        carry += sc[1023];
         __syncthreads();
     }
-    uint32_t run = s[t] - sum;
-    for (int i = lo; i < hi; ++i) {
-        uint32_t v = a[i];
-        a[i] = run;
-        run += v;
+    if (threadIdx.x == 0) *b.total[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(ScanBatch b, const uint32_t *bsum,
+                                                            int ntiles)
+{
+    __shared__ uint32_t tile[kScanTile];
+    __shared__ uint32_t tsum[kScanThreads];
+    uint32_t *a = b.a[blockIdx.y];
+    const int base = blockIdx.x * kScanTile;
+    for (int k = 0; k < kScanPer; ++k) {
+        const int j = k * kScanThreads + threadIdx.x;
+        tile[j] = base + j < b.n ? a[base + j] : 0u;
     }
-    if (t == 1023) *total = s[1023];
+    __syncthreads();
+    uint32_t loc[kScanPer], run = 0;
+    for (int k = 0; k < kScanPer; ++k) {
+        loc[k] = run;
+        run += tile[threadIdx.x * kScanPer + k];
+    }
+    tsum[threadIdx.x] = run;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        const uint32_t u = threadIdx.x >= off ? tsum[threadIdx.x - off] : 0u;
+        __syncthreads();
+        tsum[threadIdx.x] += u;
+        __syncthreads();
+    }
+    const uint32_t off0 = bsum[blockIdx.y * ntiles + blockIdx.x] + tsum[threadIdx.x] - run;
+    for (int k = 0; k < kScanPer; ++k) tile[threadIdx.x * kScanPer + k] = off0 + loc[k];
+    __syncthreads();
+    for (int k = 0; k < kScanPer; ++k) {
+        const int j = k * kScanThreads + threadIdx.x;
+        if (base + j < b.n) a[base + j] = tile[j];
+    }
+}
+
+static int scan_batch(const ScanBatch &b, Workspace &ws, hipStream_t s)
+{
+    if (b.n <= 0 || b.na <= 0) return RISM_OK;
+    const int ntiles = (b.n + kScanTile - 1) / kScanTile;
+    uint32_t *bsum = ws.get<uint32_t>((size_t)ntiles * b.na);
+    if (!bsum) return ws.status();
+    hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles, b.na), kScanThreads, 0, s, b, bsum, ntiles);
+    hipLaunchKernelGGL(k_scan_sums, b.na, 1024, 0, s, b, bsum, ntiles);
+    hipLaunchKernelGGL(k_scan_apply, dim3(ntiles, b.na), kScanThreads, 0, s, b, bsum, ntiles);
+    RISM_HIP(hipGetLastError());
+    return RISM_OK;
 }
 
 // ----------------------------------------------------------------- queries
@@ -84,6 +169,7 @@ struct CpQueryArgs {
     const uint32_t *off;            // fill pass
     int *list;
     uint32_t *apre;                 // fill pass, optional: candidate atoms before each entry
+    const int *bad;                 // fill pass: lists sized too small, write nothing
     int *overflow;
     int fill;
 };
@@ -113,6 +199,7 @@ __global__ __launch_bounds__(64) void k_cp_query(CpQueryArgs a)
     __shared__ int stk[kQStackW];
     const int lane = threadIdx.x;
     const int q = blockIdx.x;
+    if (a.fill && *a.bad) return;
     if (!a.fill && blockIdx.x == 0 && threadIdx.x == 0) {
         a.cnt[a.nq] = 0;
         if (a.items) a.items[a.nq] = 0;
@@ -231,13 +318,19 @@ struct CpClassArgs {
     const uint32_t *aoff;      // first slot of each block's lists
     int *dlist, *slist;
     uint32_t *nd, *ns;
+    const int *bad;            // lists sized too small: write nothing
 };
+
+// Candidate leaves per LDS window of the classification.
+constexpr int kClsWin = 256;
 
 __global__ __launch_bounds__(kBlock) void k_cp_classify(CpClassArgs a)
 {
+    __shared__ int wbeg[kBlock / 64][kClsWin];
+    __shared__ int wpre[kBlock / 64][kClsWin + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int q = blockIdx.x * (kBlock / 64) + wave;
-    if (q >= a.nq) return;
+    if (q >= a.nq || *a.bad) return;   // whole waves leave; no block barrier below
     const CpLevels &L = a.L;
     const int I = q % L.cx[0], J = (q / L.cx[0]) % L.cy[0], K = q / (L.cx[0] * L.cy[0]);
     double blo[3], bhi[3];
@@ -245,14 +338,41 @@ __global__ __launch_bounds__(kBlock) void k_cp_classify(CpClassArgs a)
     const double rs2 = a.rshort * a.rshort;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint32_t base = a.aoff[q];
+    int *beg = wbeg[wave], *pre = wpre[wave];
     uint32_t nd = 0, ns = 0;
-    for (uint32_t c = a.cand_off[q]; c < a.cand_off[q + 1]; ++c) {
-        const int leaf = a.cand[c];
-        const int ab = a.begin[leaf], ae = a.end[leaf];
-        for (int t0 = ab; t0 < ae; t0 += 64) {
-            const int i = t0 + lane;
-            int cls = 0;
-            if (i < ae) {
+    const int c0 = (int)a.cand_off[q], c1 = (int)a.cand_off[q + 1];
+    for (int cw = c0; cw < c1; cw += kClsWin) {
+        // window of candidate leaves: first atom and atom prefix, in list order
+        const int nw = min(kClsWin, c1 - cw);
+        int run = 0;
+        for (int k0 = 0; k0 < nw; k0 += 64) {
+            const int k = k0 + lane;
+            int sz = 0;
+            if (k < nw) {
+                const int leaf = a.cand[cw + k];
+                beg[k] = a.begin[leaf];
+                sz = a.end[leaf] - a.begin[leaf];
+            }
+            const int incl = wave_incl_scan(sz, lane);
+            if (k < nw) pre[k] = run + incl - sz;
+            run += __shfl(incl, 63);
+        }
+        if (lane == 0) pre[nw] = run;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // the window's atoms, 64 at a time
+        for (int t0 = 0; t0 < run; t0 += 64) {
+            const int t = t0 + lane;
+            int cls = 0, i = 0;
+            if (t < run) {
+                int lo = 0, hi = nw - 1;   // last k with pre[k] <= t
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (pre[mid] <= t) lo = mid;
+                    else hi = mid - 1;
+                }
+                i = beg[lo] + (t - pre[lo]);
                 double y[3];
                 atom_pos(a.rec, a.stride_f4, i, y);
                 const int lvl = L.T >= 1 ? cp_accept_level(L, I, J, K, y, 1) : 0;
@@ -273,6 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_cp_classify(CpClassArgs a)
             nd += (uint32_t)__popcll(m1);
             ns += (uint32_t)__popcll(m2);
         }
+        __builtin_amdgcn_wave_barrier();   // the window is read before the next one is written
     }
     if (lane == 0) {
         a.nd[q] = nd;
@@ -289,10 +410,13 @@ __device__ __forceinline__ int cost_class(uint32_t c)
 {
     return c == 0 ? 0 : 32 - __clz(c);
 }
-__global__ __launch_bounds__(1024) void k_order_by_cost(int n, const uint32_t *c1,
+__global__ __launch_bounds__(1024) void k_order_by_cost(int n, const uint32_t *n_dev,
+                                                        const int *bad, const uint32_t *c1,
                                                         const uint32_t *c2, int *order)
 {
     __shared__ unsigned int cnt[kCostClasses];
+    if (*bad) return;
+    if (n_dev) n = min(n, (int)*n_dev);
     if (threadIdx.x < kCostClasses) cnt[threadIdx.x] = 0u;
     __syncthreads();
     for (int q = threadIdx.x; q < n; q += blockDim.x)
@@ -318,11 +442,12 @@ __global__ __launch_bounds__(1024) void k_order_by_cost(int n, const uint32_t *c
 __global__ __launch_bounds__(kBlock) void k_cp_items(int nq, const uint32_t *cand_off,
                                                      const uint32_t *item_off,
                                                      const uint32_t *atom_off,
-                                                     const uint32_t *cand_apre, int *it_cl,
-                                                     int *it_c0, int *it_c1, uint32_t *it_slot)
+                                                     const uint32_t *cand_apre, const int *bad,
+                                                     int *it_cl, int *it_c0, int *it_c1,
+                                                     uint32_t *it_slot)
 {
     const int q = blockIdx.x * kBlock + threadIdx.x;
-    if (q >= nq) return;
+    if (q >= nq || *bad) return;
     const int c0 = (int)cand_off[q], c1 = (int)cand_off[q + 1];
     int it = (int)item_off[q];
     for (int c = c0; c < c1; c += kCpChunkLeaves, ++it) {
@@ -351,6 +476,8 @@ struct CpAssignArgs {
     uint32_t *it_n;            // assigned atoms per item
     unsigned long long *work;  // optional: (atom, proxy) pairs
     int np;
+    const uint32_t *n_items;   // items on the device (the launch may have more blocks)
+    const int *bad;            // buffers sized too small: do nothing
 };
 
 __global__ __launch_bounds__(kBlock) void k_cp_assign(CpAssignArgs a)
@@ -359,6 +486,7 @@ __global__ __launch_bounds__(kBlock) void k_cp_assign(CpAssignArgs a)
     __shared__ int pre[kCpChunkLeaves + 1];
     __shared__ int lbeg[kCpChunkLeaves];
     const int item = blockIdx.x;
+    if (*a.bad || item >= (int)*a.n_items) return;   // whole workgroup
     const int cl = a.it_cl[item];
     int lvl, I, J, K;
     cp_decode(a.L, cl, lvl, I, J, K);
@@ -436,6 +564,8 @@ struct CpSweepArgs {
     int degree, np;
     float yk;
     double *part;   // [items][2][np]
+    const uint32_t *n_items;
+    const int *bad;
 };
 
 struct Quad {
@@ -446,6 +576,7 @@ template <bool ASYM, int NR>
 __global__ __launch_bounds__(kBlock) void k_cp_sweep(CpSweepArgs a)
 {
     __shared__ float node[3][kMaxDeg + 1];
+    if (*a.bad || (int)blockIdx.x >= (int)*a.n_items) return;   // whole workgroup
     const int item = as_const(a.order)[blockIdx.x];
     const int cl = as_const(a.it_cl)[item];
     const int n = (int)as_const(a.it_n)[item];
@@ -524,10 +655,10 @@ void launch_sweep(int nitems, int np, const CpSweepArgs &sa, hipStream_t s)
 
 // V[cl] = sum of the partials of its items, in item order.
 __global__ __launch_bounds__(kBlock) void k_cp_reduce(int nclusters, int np, const uint32_t *item_off,
-                                                      const double *part, double *V)
+                                                      const int *bad, const double *part, double *V)
 {
     const int cl = blockIdx.x;
-    if (cl >= nclusters) return;
+    if (cl >= nclusters || *bad) return;
     const int i0 = (int)item_off[cl], i1 = (int)item_off[cl + 1];
     for (int k = threadIdx.x; k < 2 * np; k += kBlock) {
         double s = 0.0;
@@ -601,6 +732,7 @@ struct CpLeafArgs {
     const int *dlist, *slist;  // direct / short-range atoms per block
     const uint32_t *nd, *ns;
     const int *order;          // block -> level-0 block, heaviest first
+    const int *bad;            // lists sized too small: do nothing
     const double *V;           // proxy values of level >= 1 clusters
     int degree, np;
     unsigned long long *work;  // optional: [0] direct pairs, [1] short-range pairs
@@ -665,6 +797,7 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
     double *Lb = T2 + NCOMP * n1 * B * B;                  // [3][B][n1]
     double *Vs = Lb + 3 * B * n1;                          // [np]
     double *T1 = Vs + a.np;                                // [n1][n1][B]
+    if (*a.bad) return;   // whole workgroup
     const CpLevels &L = a.L;
     const GridParams &g = a.g;
     const int q = as_const(a.order)[blockIdx.x];
@@ -778,7 +911,10 @@ template <int NS>
 void launch_leaf_ns(int lj_mode, bool asym, int B, int nleaf, size_t shm, const CpLeafArgs &a,
                     hipStream_t s)
 {
-    if (lj_mode == LJ_CUT) {
+    if (lj_mode == LJ_CUT1) {
+        if (asym) launch_leaf_b<NS, LJ_CUT1, true>(B, nleaf, shm, a, s);
+        else launch_leaf_b<NS, LJ_CUT1, false>(B, nleaf, shm, a, s);
+    } else if (lj_mode == LJ_CUT) {
         if (asym) launch_leaf_b<NS, LJ_CUT, true>(B, nleaf, shm, a, s);
         else launch_leaf_b<NS, LJ_CUT, false>(B, nleaf, shm, a, s);
     } else {
@@ -786,6 +922,67 @@ void launch_leaf_ns(int lj_mode, bool asym, int B, int nleaf, size_t shm, const 
         else launch_leaf_b<NS, LJ_NONE, false>(B, nleaf, shm, a, s);
     }
 }
+
+__global__ void k_fill_int(int *p, int n, int v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// Pinned host staging for the small end-of-call read-back.
+uint32_t *pinned_u32(int n)
+{
+    static thread_local uint32_t *p = nullptr;
+    if (!p && hipHostMalloc((void **)&p, 64 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
+        p = nullptr;
+    return n <= 64 ? p : nullptr;
+}
+
+// Sizes of the list buffers: [0] cluster candidates, [1] far items, [2] leaf
+// candidates, [3] leaf candidate atoms, [4] cluster candidate atoms.
+struct CpCaps {
+    uint32_t c[5];
+};
+
+// bad = some total exceeds its capacity, or a neighbour query overflowed.
+__global__ void k_cp_check(const uint32_t *tot, CpCaps cap, const int *overflow, int *bad)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int b = *overflow != 0;
+    for (int k = 0; k < 5; ++k) b |= tot[k] > cap.c[k];
+    *bad = b;
+}
+
+// Capacities seen for a problem shape (device, atoms, blocks, clusters,
+// degree, theta, leaf size, short range): a later call of the same shape sizes
+// its buffers from them and enqueues all its kernels without waiting for the
+// counts; the kernels do nothing when the device-side check fails, and the
+// call then runs again with the counts it read back.
+struct CpShape {
+    int dev, leaf, deg;
+    int64_t n;
+    int nleaf, ncl;
+    double theta, rshort;
+    bool operator<(const CpShape &o) const
+    {
+        if (dev != o.dev) return dev < o.dev;
+        if (n != o.n) return n < o.n;
+        if (nleaf != o.nleaf) return nleaf < o.nleaf;
+        if (ncl != o.ncl) return ncl < o.ncl;
+        if (deg != o.deg) return deg < o.deg;
+        if (leaf != o.leaf) return leaf < o.leaf;
+        if (theta != o.theta) return theta < o.theta;
+        return rshort < o.rshort;
+    }
+};
+std::mutex g_cp_caps_mu;
+std::map<CpShape, CpCaps> g_cp_caps;
 
 }  // namespace
 
@@ -836,7 +1033,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     const int wpb = kBlock / 64;
     {
         PhaseTimer pt(ev, RISM_PHASE_LISTS, s);
-        RISM_HIP(hipMemsetAsync(overflow, 0, sizeof(int), s));
+        hipLaunchKernelGGL(k_fill_int, 1, 64, 0, s, overflow, 1, 0);
         if (ncl > 0) {
             qa.mode = 0;
             qa.nq = ncl;
@@ -845,9 +1042,16 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             qa.acnt = cacnt;
             qa.fill = 0;
             hipLaunchKernelGGL(k_cp_query, ncl, 64, 0, s, qa);
-            hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, ccnt, ncl + 1, tot + 0);
-            hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, citems, ncl + 1, tot + 1);
-            hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, cacnt, ncl + 1, tot + 4);
+            ScanBatch sb{};
+            sb.a[0] = ccnt;
+            sb.a[1] = citems;
+            sb.a[2] = cacnt;
+            sb.total[0] = tot + 0;
+            sb.total[1] = tot + 1;
+            sb.total[2] = tot + 4;
+            sb.n = ncl + 1;
+            sb.na = 3;
+            if ((rc = scan_batch(sb, ws, s))) return rc;
         }
         qa.mode = 1;
         qa.nq = nleaf;
@@ -856,81 +1060,94 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         qa.acnt = lacnt;
         qa.fill = 0;
         hipLaunchKernelGGL(k_cp_query, nleaf, 64, 0, s, qa);
-        hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, lcnt, nleaf + 1, tot + 2);
-        hipLaunchKernelGGL(k_scan_excl_u32, 1, 1024, 0, s, lacnt, nleaf + 1, tot + 3);
-    }
-    RISM_HIP(hipGetLastError());
-    // totals: [0] cluster candidates, [1] far items, [2] leaf candidates,
-    // [3] leaf candidate atoms, [4] cluster candidate atoms, [5] overflow flag
-    uint32_t ht[6] = {0, 0, 0, 0, 0, 0};
-    RISM_HIP(hipMemcpyAsync(ht, tot, 5 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    RISM_HIP(hipMemcpyAsync(ht + 5, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
-    RISM_HIP(hipStreamSynchronize(s));
-    if (ht[5]) {
-        set_error("treecode_cp: neighbour query stack overflow");
-        return RISM_E_UNSUPPORTED;
-    }
-    if (ncl == 0) ht[0] = ht[1] = ht[4] = 0;
-    int *ccand = ws.get<int>(ht[0] + 1), *lcand = ws.get<int>(ht[2] + 1);
-    uint32_t *capre = ws.get<uint32_t>(ht[0] + 1);
-    int *it_cl = ws.get<int>(ht[1] + 1), *it_c0 = ws.get<int>(ht[1] + 1),
-        *it_c1 = ws.get<int>(ht[1] + 1), *it_order = ws.get<int>(ht[1] + 1);
-    uint32_t *it_slot = ws.get<uint32_t>(ht[1] + 1), *it_n = ws.get<uint32_t>(ht[1] + 1);
-    float4 *abuf = ws.get<float4>((size_t)ht[4] + 1);
-    int *dlist = ws.get<int>(ht[3] + 1), *slist = ws.get<int>(ht[3] + 1);
-    uint32_t *nd = ws.get<uint32_t>(nleaf), *nsh = ws.get<uint32_t>(nleaf);
-    double *part = ws.get<double>((size_t)(ht[1] + 1) * 2 * np);
-    double *V = ws.get<double>((size_t)(ncl + 1) * 2 * np);
-    const bool want_stats = a.opts->flags & RISM_FLAG_STATS;
-    unsigned long long *work = want_stats ? ws.get<unsigned long long>(4) : nullptr;
-    if (ws.status()) return ws.status();
-    if (work) RISM_HIP(hipMemsetAsync(work, 0, 4 * sizeof(unsigned long long), s));
-    {
-        PhaseTimer pt(ev, RISM_PHASE_LISTS, s);
-        if (ncl > 0) {
-            qa.mode = 0;
-            qa.nq = ncl;
-            qa.off = ccnt;
-            qa.list = ccand;
-            qa.apre = capre;
-            qa.fill = 1;
-            qa.items = nullptr;
-            qa.acnt = nullptr;
-            hipLaunchKernelGGL(k_cp_query, ncl, 64, 0, s, qa);
-            qa.apre = nullptr;
-            hipLaunchKernelGGL(k_cp_items, (ncl + kBlock - 1) / kBlock, kBlock, 0, s, ncl, ccnt,
-                               citems, cacnt, capre, it_cl, it_c0, it_c1, it_slot);
-        }
-        qa.mode = 1;
-        qa.nq = nleaf;
-        qa.off = lcnt;
-        qa.list = lcand;
-        qa.fill = 1;
-        qa.acnt = nullptr;
-        hipLaunchKernelGGL(k_cp_query, nleaf, 64, 0, s, qa);
-        CpClassArgs ca{};
-        ca.L = L;
-        ca.nq = nleaf;
-        ca.rshort = rshort;
-        ca.cand_off = lcnt;
-        ca.cand = lcand;
-        ca.begin = t.begin;
-        ca.end = t.end;
-        ca.rec = static_cast<const float4 *>(t.sorted_rec);
-        ca.stride_f4 = stride_f4;
-        ca.aoff = lacnt;
-        ca.dlist = dlist;
-        ca.slist = slist;
-        ca.nd = nd;
-        ca.ns = nsh;
-        hipLaunchKernelGGL(k_cp_classify, (nleaf + wpb - 1) / wpb, kBlock, 0, s, ca);
+        ScanBatch sb{};
+        sb.a[0] = lcnt;
+        sb.a[1] = lacnt;
+        sb.total[0] = tot + 2;
+        sb.total[1] = tot + 3;
+        sb.n = nleaf + 1;
+        sb.na = 2;
+        if ((rc = scan_batch(sb, ws, s))) return rc;
     }
     RISM_HIP(hipGetLastError());
 
-    // far field into the target proxies, reduction, downward pass
-    if (ncl > 0) {
+    int dev = 0, lds_max = 0;
+    RISM_HIP(hipGetDevice(&dev));
+    RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t leaf_shm = cp_leaf_lds(B, deg, a.asym_on);
+    if (leaf_shm + 2048 > (size_t)lds_max) {
+        set_error("treecode_cp: degree / batch edge too large for the LDS of this device");
+        return RISM_E_UNSUPPORTED;
+    }
+    const bool want_stats = a.opts->flags & RISM_FLAG_STATS;
+    unsigned long long *work = want_stats ? ws.get<unsigned long long>(4) : nullptr;
+    int *bad = ws.get<int>(1);
+    uint32_t *nd = ws.get<uint32_t>(nleaf), *nsh = ws.get<uint32_t>(nleaf);
+    int *order = ws.get<int>(nleaf);
+    double *V = ws.get<double>((size_t)(ncl + 1) * 2 * np);
+    if (ws.status()) return ws.status();
+
+    // Everything after the counts, with buffers of the given capacities.
+    auto second_half = [&](const CpCaps &cap) -> int {
+        int *ccand = ws.get<int>(cap.c[0] + 1), *lcand = ws.get<int>(cap.c[2] + 1);
+        uint32_t *capre = ws.get<uint32_t>(cap.c[0] + 1);
+        int *it_cl = ws.get<int>(cap.c[1] + 1), *it_c0 = ws.get<int>(cap.c[1] + 1),
+            *it_c1 = ws.get<int>(cap.c[1] + 1), *it_order = ws.get<int>(cap.c[1] + 1);
+        uint32_t *it_slot = ws.get<uint32_t>(cap.c[1] + 1),
+                 *it_n = ws.get<uint32_t>(cap.c[1] + 1);
+        float4 *abuf = ws.get<float4>((size_t)cap.c[4] + 1);
+        int *dlist = ws.get<int>(cap.c[3] + 1), *slist = ws.get<int>(cap.c[3] + 1);
+        double *part = ws.get<double>((size_t)(cap.c[1] + 1) * 2 * np);
+        if (ws.status()) return ws.status();
+        if (work) hipLaunchKernelGGL(k_fill_u64, 1, 64, 0, s, work, 4);
+        qa.bad = bad;
         {
-            if (ht[1] > 0) {
+            PhaseTimer pt(ev, RISM_PHASE_LISTS, s);
+            if (ncl > 0) {
+                qa.mode = 0;
+                qa.nq = ncl;
+                qa.off = ccnt;
+                qa.list = ccand;
+                qa.apre = capre;
+                qa.fill = 1;
+                qa.items = nullptr;
+                qa.acnt = nullptr;
+                hipLaunchKernelGGL(k_cp_query, ncl, 64, 0, s, qa);
+                qa.apre = nullptr;
+                hipLaunchKernelGGL(k_cp_items, (ncl + kBlock - 1) / kBlock, kBlock, 0, s, ncl,
+                                   ccnt, citems, cacnt, capre, (const int *)bad, it_cl, it_c0,
+                                   it_c1, it_slot);
+            }
+            qa.mode = 1;
+            qa.nq = nleaf;
+            qa.off = lcnt;
+            qa.list = lcand;
+            qa.fill = 1;
+            qa.acnt = nullptr;
+            hipLaunchKernelGGL(k_cp_query, nleaf, 64, 0, s, qa);
+            CpClassArgs ca{};
+            ca.L = L;
+            ca.nq = nleaf;
+            ca.rshort = rshort;
+            ca.cand_off = lcnt;
+            ca.cand = lcand;
+            ca.begin = t.begin;
+            ca.end = t.end;
+            ca.rec = static_cast<const float4 *>(t.sorted_rec);
+            ca.stride_f4 = stride_f4;
+            ca.aoff = lacnt;
+            ca.dlist = dlist;
+            ca.slist = slist;
+            ca.nd = nd;
+            ca.ns = nsh;
+            ca.bad = bad;
+            hipLaunchKernelGGL(k_cp_classify, (nleaf + wpb - 1) / wpb, kBlock, 0, s, ca);
+        }
+        RISM_HIP(hipGetLastError());
+
+        // far field into the target proxies, reduction, downward pass
+        if (ncl > 0 && cap.c[1] > 0) {
+            {
                 PhaseTimer pl(ev, RISM_PHASE_LISTS, s);
                 CpAssignArgs aa{};
                 aa.L = L;
@@ -947,11 +1164,14 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
                 aa.it_n = it_n;
                 aa.work = work ? work + 2 : nullptr;
                 aa.np = np;
-                hipLaunchKernelGGL(k_cp_assign, (int)ht[1], kBlock, 0, s, aa);
-                hipLaunchKernelGGL(k_order_by_cost, 1, 1024, 0, s, (int)ht[1], it_n,
+                aa.n_items = tot + 1;
+                aa.bad = bad;
+                hipLaunchKernelGGL(k_cp_assign, (int)cap.c[1], kBlock, 0, s, aa);
+                hipLaunchKernelGGL(k_order_by_cost, 1, 1024, 0, s, (int)cap.c[1],
+                                   (const uint32_t *)(tot + 1), (const int *)bad, it_n,
                                    (const uint32_t *)nullptr, it_order);
             }
-            if (ht[1] > 0) {
+            {
                 PhaseTimer pu(ev, RISM_PHASE_UPWARD, s);
                 CpSweepArgs sa{};
                 sa.L = L;
@@ -964,60 +1184,111 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
                 sa.np = np;
                 sa.yk = (float)a.asym.yk;
                 sa.part = part;
-                if (a.asym_on) launch_sweep<true>((int)ht[1], np, sa, s);
-                else launch_sweep<false>((int)ht[1], np, sa, s);
+                sa.n_items = tot + 1;
+                sa.bad = bad;
+                if (a.asym_on) launch_sweep<true>((int)cap.c[1], np, sa, s);
+                else launch_sweep<false>((int)cap.c[1], np, sa, s);
             }
         }
-        {
+        if (ncl > 0) {
             PhaseTimer pt(ev, RISM_PHASE_DOWNWARD, s);
-            hipLaunchKernelGGL(k_cp_reduce, ncl, kBlock, 0, s, ncl, np, citems, part, V);
+            hipLaunchKernelGGL(k_cp_reduce, ncl, kBlock, 0, s, ncl, np, citems, (const int *)bad,
+                               part, V);
             const size_t shm = (3 * (size_t)n1 * n1 + 3 * (size_t)np) * sizeof(double);
             for (int lvl = L.T - 1; lvl >= 1; --lvl)
-                hipLaunchKernelGGL(k_cp_down, L.cx[lvl] * L.cy[lvl] * L.cz[lvl], kBlock, shm, s, L,
-                                   lvl, deg, V);
+                hipLaunchKernelGGL(k_cp_down, L.cx[lvl] * L.cy[lvl] * L.cz[lvl], kBlock, shm, s,
+                                   L, lvl, deg, V);
         }
         RISM_HIP(hipGetLastError());
-    }
 
-    // leaves
-    CpLeafArgs la{};
-    la.L = L;
-    la.g = a.g;
-    la.out = a.out;
-    la.asym = a.asym;
-    la.rec = t.sorted_rec;
-    la.aoff = lacnt;
-    la.dlist = dlist;
-    la.slist = slist;
-    la.nd = nd;
-    la.ns = nsh;
-    int *order = ws.get<int>(nleaf);
-    if (!order) return ws.status();
-    la.order = order;
-    la.V = V;
-    la.degree = deg;
-    la.np = np;
-    la.work = work;
-    const size_t shm = cp_leaf_lds(B, deg, a.asym_on);
-    int dev = 0, lds_max = 0;
-    RISM_HIP(hipGetDevice(&dev));
-    RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    if (shm + 2048 > (size_t)lds_max) {
-        set_error("treecode_cp: degree / batch edge too large for the LDS of this device");
-        return RISM_E_UNSUPPORTED;
-    }
-    {
+        // leaves
+        CpLeafArgs la{};
+        la.L = L;
+        la.g = a.g;
+        la.out = a.out;
+        la.asym = a.asym;
+        la.rec = t.sorted_rec;
+        la.aoff = lacnt;
+        la.dlist = dlist;
+        la.slist = slist;
+        la.nd = nd;
+        la.ns = nsh;
+        la.order = order;
+        la.bad = bad;
+        la.V = V;
+        la.degree = deg;
+        la.np = np;
+        la.work = work;
         {
             PhaseTimer pl(ev, RISM_PHASE_LISTS, s);
-            hipLaunchKernelGGL(k_order_by_cost, 1, 1024, 0, s, nleaf, nd, nsh, order);
+            hipLaunchKernelGGL(k_order_by_cost, 1, 1024, 0, s, nleaf, (const uint32_t *)nullptr,
+                               (const int *)bad, nd, nsh, order);
         }
-        PhaseTimer pt(ev, RISM_PHASE_EVAL, s);
-        switch (a.sp.ns_pad) {
-        case 1: launch_leaf_ns<1>(a.lj_mode, a.asym_on, B, nleaf, shm, la, s); break;
-        case 2: launch_leaf_ns<2>(a.lj_mode, a.asym_on, B, nleaf, shm, la, s); break;
-        case 4: launch_leaf_ns<4>(a.lj_mode, a.asym_on, B, nleaf, shm, la, s); break;
-        default: launch_leaf_ns<8>(a.lj_mode, a.asym_on, B, nleaf, shm, la, s); break;
+        {
+            PhaseTimer pt(ev, RISM_PHASE_EVAL, s);
+            const int ljm = a.lj_mode == LJ_CUT && a.lj_uniform ? LJ_CUT1 : a.lj_mode;
+            switch (a.sp.ns_pad) {
+            case 1: launch_leaf_ns<1>(ljm, a.asym_on, B, nleaf, leaf_shm, la, s); break;
+            case 2: launch_leaf_ns<2>(ljm, a.asym_on, B, nleaf, leaf_shm, la, s); break;
+            case 4: launch_leaf_ns<4>(ljm, a.asym_on, B, nleaf, leaf_shm, la, s); break;
+            default: launch_leaf_ns<8>(ljm, a.asym_on, B, nleaf, leaf_shm, la, s); break;
+            }
         }
+        RISM_HIP(hipGetLastError());
+        return RISM_OK;
+    };
+
+    // totals and flags read back at the end of a pass: [0..4] counts as in
+    // CpCaps, [5] query stack overflow, [6] capacity check failed
+    uint32_t *hres = pinned_u32(8);
+    if (!hres) {
+        set_error("treecode_cp: pinned host buffer allocation failed");
+        return RISM_E_HIP;
+    }
+    auto read_back = [&]() -> int {
+        RISM_HIP(hipMemcpyAsync(hres, tot, 5 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        RISM_HIP(hipMemcpyAsync(hres + 5, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
+        RISM_HIP(hipMemcpyAsync(hres + 6, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        RISM_HIP(hipStreamSynchronize(s));
+        if (hres[5]) {
+            set_error("treecode_cp: neighbour query stack overflow");
+            return RISM_E_UNSUPPORTED;
+        }
+        if (ncl == 0) hres[0] = hres[1] = hres[4] = 0;
+        return RISM_OK;
+    };
+    const CpShape shape{dev, a.opts->leaf_size, deg, a.solute->n, nleaf, ncl, a.opts->theta, rshort};
+    CpCaps cached{};
+    bool have = false;
+    {
+        std::lock_guard<std::mutex> lk(g_cp_caps_mu);
+        auto it = g_cp_caps.find(shape);
+        if (it != g_cp_caps.end()) {
+            cached = it->second;
+            have = true;
+        }
+    }
+    bool done = false;
+    if (have) {
+        // speculative pass with the cached capacities
+        hipLaunchKernelGGL(k_cp_check, 1, 1, 0, s, (const uint32_t *)tot, cached,
+                           (const int *)overflow, bad);
+        if ((rc = second_half(cached))) return rc;
+        if ((rc = read_back())) return rc;
+        done = hres[6] == 0;
+    } else {
+        if ((rc = read_back())) return rc;
+    }
+    if (!done) {
+        // exact capacities from the counts just read
+        CpCaps exact{};
+        for (int k = 0; k < 5; ++k) exact.c[k] = hres[k];
+        hipLaunchKernelGGL(k_fill_int, 1, 64, 0, s, bad, 1, 0);
+        if ((rc = second_half(exact))) return rc;
+        std::lock_guard<std::mutex> lk(g_cp_caps_mu);
+        if (g_cp_caps.size() > 64) g_cp_caps.clear();
+        CpCaps &c = g_cp_caps[shape];
+        for (int k = 0; k < 5; ++k) c.c[k] = std::max(c.c[k], exact.c[k]);
     }
     RISM_HIP(hipGetLastError());
     st.n_batches = nleaf;

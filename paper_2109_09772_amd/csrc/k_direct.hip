@@ -358,10 +358,12 @@ static void launch_f32_ns(int blocks, const SiteParams &sp, const DirectArgs &a,
     if (a.asym_on) {
         if (a.lj_mode == LJ_NONE) launch_f32_exact<NS, LJ_NONE, true>(ex, blocks, sp, a, s);
         else if (a.lj_mode == LJ_ALL) launch_f32_exact<NS, LJ_ALL, true>(ex, blocks, sp, a, s);
+        else if (a.lj_uniform) launch_f32_exact<NS, LJ_CUT1, true>(ex, blocks, sp, a, s);
         else launch_f32_exact<NS, LJ_CUT, true>(ex, blocks, sp, a, s);
     } else {
         if (a.lj_mode == LJ_NONE) launch_f32_exact<NS, LJ_NONE, false>(ex, blocks, sp, a, s);
         else if (a.lj_mode == LJ_ALL) launch_f32_exact<NS, LJ_ALL, false>(ex, blocks, sp, a, s);
+        else if (a.lj_uniform) launch_f32_exact<NS, LJ_CUT1, false>(ex, blocks, sp, a, s);
         else launch_f32_exact<NS, LJ_CUT, false>(ex, blocks, sp, a, s);
     }
 }

@@ -437,13 +437,13 @@ __global__ __launch_bounds__(kSmallThreads) void k_tree_small(
             const int i = c0 + tid;
             int c = 0, b = 0, e = 0;
             const bool split = i < s1 && (e = end[i]) - (b = begin[i]) > leaf;
+            // child boundaries: bnd[d] = first atom whose digit is >= d
+            int bnd[9];
+            bnd[0] = b;
+            bnd[8] = e;
             if (split) {
-                int prev = b;
-                for (int d = 1; d <= 8; ++d) {
-                    const int nx = d == 8 ? e : lower_digit_lds(sk, prev, e, shift, d);
-                    if (nx > prev) ++c;
-                    prev = nx;
-                }
+                for (int d = 1; d < 8; ++d) bnd[d] = lower_digit_lds(sk, bnd[d - 1], e, shift, d);
+                for (int d = 0; d < 8; ++d) c += bnd[d + 1] > bnd[d] ? 1 : 0;
             }
             int tot;
             const int off = block_excl_scan(c, wsum, tot);
@@ -451,21 +451,19 @@ __global__ __launch_bounds__(kSmallThreads) void k_tree_small(
                 if (split) {
                     const int base = s1 + running + off;
                     child0[i] = base;
-                    int prev = b, cc = 0;
-                    for (int d = 1; d <= 8; ++d) {
-                        const int nx = d == 8 ? e : lower_digit_lds(sk, prev, e, shift, d);
-                        if (nx > prev) {
+                    int cc = 0;
+                    for (int d = 0; d < 8; ++d) {
+                        if (bnd[d + 1] > bnd[d]) {
                             const int j = base + cc;
                             if (j < cap) {
-                                begin[j] = prev;
-                                end[j] = nx;
+                                begin[j] = bnd[d];
+                                end[j] = bnd[d + 1];
                                 level[j] = lvl + 1;
                                 child0[j] = -1;
                                 nchild[j] = 0;
                             }
                             ++cc;
                         }
-                        prev = nx;
                     }
                 } else {
                     child0[i] = -1;

@@ -155,7 +155,8 @@ __device__ __forceinline__ void pair_eval(const Rec &at, const GridPt &g,
     if (FULL) hit |= (d2 == 0.f);
     if (LJM != LJ_NONE) {
         const float r2 = ri * ri;
-        const float r6 = r2 * r2 * r2;
+        float r6 = r2 * r2 * r2;
+        if (LJM == LJ_CUT1) r6 = d2 < at.rc2[0] ? r6 : 0.f;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             float r6s = r6;

@@ -413,6 +413,7 @@ static int forward(const rism_solute *so, const rism_sites *si, const rism_grid 
         da.out = p.out;
         da.asym = p.asym;
         da.lj_mode = u ? p.lj_mode : LJ_NONE;
+        da.lj_uniform = op->lj_tol <= 0 && op->lj_cutoff > 0;
         da.asym_on = asym_on;
         const bool ev = op->flags & RISM_FLAG_PHASE_EVENTS;
         if (f64path) {
@@ -434,6 +435,7 @@ static int forward(const rism_solute *so, const rism_sites *si, const rism_grid 
             ta.asym = p.asym;
             ta.opts = op;
             ta.lj_mode = da.lj_mode;
+            ta.lj_uniform = da.lj_uniform;
             ta.asym_on = asym_on;
             ta.rec32 = rec32;
             ta.npad = p.npad;
@@ -498,6 +500,74 @@ int rism_asymptotics(const rism_solute *so, const rism_sites *si, const rism_gri
 {
     if (!c && !h) return fail(RISM_E_INVALID, "no output requested (c_lr and h_lr are NULL)");
     return forward(so, si, gr, op, true, eta, kappa, beta, diel, nullptr, nullptr, c, h, stream);
+}
+
+int rism_asymptotics_k(const rism_solute *so, const rism_sites *si, const rism_grid *gr,
+                       const rism_opts *op, double eta, double kappa, double beta, double diel,
+                       double tol, void *c, void *h, void *stream)
+{
+    int rc = check_common(so, si, gr, op);
+    if (rc) return rc;
+    if (!(eta > 0) || !std::isfinite(eta)) return fail(RISM_E_INVALID, "eta must be > 0");
+    if (!(kappa >= 0) || !std::isfinite(kappa)) return fail(RISM_E_INVALID, "kappa must be >= 0");
+    if (!(beta > 0) || !std::isfinite(beta)) return fail(RISM_E_INVALID, "beta must be > 0");
+    if (!(diel > 0) || !std::isfinite(diel)) return fail(RISM_E_INVALID, "dielectric must be > 0");
+    if (!std::isfinite(tol)) return fail(RISM_E_INVALID, "tol must be finite");
+    Prep p;
+    prep_common(so, si, gr, op, p);
+    if (p.n_ionic == 0) h = nullptr;
+    if (!c && !h) return fail(RISM_E_INVALID, "no output requested (c and h are NULL)");
+    AkArgs ak{};
+    ak.g.nx = gr->dims[0];
+    ak.g.ny = gr->dims[1];
+    ak.g.nz = gr->dims[2];
+    ak.g.nxh = gr->dims[0] / 2 + 1;
+    for (int a = 0; a < 3; ++a) {
+        ak.g.o[a] = gr->origin[a];
+        ak.g.h[a] = gr->spacing[a];
+    }
+    ak.n = so->n;
+    ak.eta2_4 = eta * eta / 4.0;
+    ak.kappa2 = kappa * kappa;
+    ak.c = c;
+    ak.h = h;
+    ak.f64 = op->out_dtype == RISM_F64;
+    ak.ns = si->n;
+    ak.n_ionic = p.n_ionic;
+    double qc = 0.0, qh = 0.0;
+    for (int g = 0, j = 0; g < si->n; ++g) {
+        ak.c_scale[g] = -4.0 * kPi * beta * op->coulomb_k * si->q[g];
+        qc = std::max(qc, std::fabs(si->q[g]));
+        if (p.sp.ionic[g]) {
+            ak.h_scale[j++] = -4.0 * kPi * beta * op->coulomb_k * si->q[g] / diel;
+            qh = std::max(qh, std::fabs(si->q[g]));
+        }
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    RISM_HIP(hipGetDevice(&dev));
+    Workspace ws(dev, stream, op->max_workspace_bytes);
+    const int64_t nt = so->n > 0 ? so->n : 1;
+    float2 *ex = ws.get<float2>((size_t)nt * ak.g.nxh);
+    float2 *ey = ws.get<float2>((size_t)nt * ak.g.ny);
+    float2 *ez = ws.get<float2>((size_t)nt * ak.g.nz);
+    double *k2cut = ws.get<double>(3);
+    if (ws.status()) return ws.status();
+    // the bound of Sec. 2.5 per unit sum |Q_a| (summed on the device)
+    const double pre = 4.0 * std::sqrt(2.0) * kPi * beta * std::fabs(op->coulomb_k);
+    if ((rc = launch_ak_cutoffs(so->q, so->n, tol, pre * qc, pre * qh, eta, kappa, diel, k2cut, s)))
+        return rc;
+    ak.k2cut = k2cut;
+    {
+        PhaseTimer pt(op->flags & RISM_FLAG_PHASE_EVENTS, RISM_PHASE_OTHER, s);
+        rc = launch_asym_k(ak, so->xyz, so->q, ex, ey, ez, s);
+    }
+    if (rc) return rc;
+    rism_stats st{};
+    st.pairs_direct = (double)so->n * ak.g.nxh * ak.g.ny * ak.g.nz;
+    st.workspace_bytes = (int64_t)ws.in_use();
+    g_stats = st;
+    return RISM_OK;
 }
 
 int rism_initialize(const rism_solute *so, const rism_sites *si, const rism_grid *gr,

@@ -50,7 +50,9 @@ struct SiteParams {
     int ionic[kMaxSites];
 };
 
-enum LjMode { LJ_NONE = 0, LJ_ALL = 1, LJ_CUT = 2 };
+// LJ_CUT1 is a kernel template value only: LJ_CUT where every site of an atom
+// has the same cut-off radius (a fixed lj_cutoff), so one test serves all sites.
+enum LjMode { LJ_NONE = 0, LJ_ALL = 1, LJ_CUT = 2, LJ_CUT1 = 3 };
 
 struct GridParams {
     double o[3];
@@ -160,6 +162,7 @@ struct DirectArgs {
     OutParams out;
     AsymParams asym;
     int lj_mode;
+    int lj_uniform;     // LJ_CUT with one radius for all sites (fixed lj_cutoff)
     int asym_on;        // compute the smeared sums (c and/or h)
 };
 int launch_direct_f64(const SiteParams &sp, const DirectArgs &a, hipStream_t s);
@@ -180,6 +183,7 @@ struct TreeCallArgs {
     AsymParams asym;
     const rism_opts *opts;
     int lj_mode;
+    int lj_uniform;         // LJ_CUT with one radius for all sites
     int asym_on;
     const void *rec32;      // staged FP32 atom records (input order)
     int64_t npad;
@@ -187,6 +191,34 @@ struct TreeCallArgs {
 };
 int tree_forward(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStream_t s);
 int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStream_t s);
+
+// Reciprocal-space asymptotics; defined in k_asym_k.hip.
+struct AkGrid {
+    int nx, ny, nz, nxh;   // nxh = nx / 2 + 1 entries along the halved axis
+    double o[3], h[3];
+};
+struct AkArgs {
+    AkGrid g;
+    int64_t n;
+    const float2 *ex, *ey, *ezq;   // phase tables (set by launch_asym_k)
+    int chunk;                     // atoms per LDS round (set by launch_asym_k)
+    const double *k2cut;           // device [3]: squared cut-offs of c and h, net charge
+    double eta2_4, kappa2;
+    void *c, *h;                   // [S][nz][ny][nxh][2], [n_ionic][...][2]
+    int f64, ns, n_ionic;
+    double c_scale[kMaxSites];     // -4 pi beta k_C q_g
+    double h_scale[kMaxSites];     // -4 pi beta k_C q_j / eps
+};
+// Frequency cut-off of Sec. 2.5 (Newton's method, bracketed); 0 = none.
+__host__ __device__ double ak_kcut(bool for_h, double tol, double pref, double eta, double kappa,
+                                   double diel);
+int launch_asym_k(const AkArgs &a, const double *xyz, const double *q, float2 *ex, float2 *ey,
+                  float2 *ezq, hipStream_t s);
+// Squared cut-offs into k2cut[0..1] (INFINITY where tol <= 0 or nothing is
+// cut) and the net charge into k2cut[2]; pref_c / pref_h are the bounds'
+// prefactors without sum |Q_a|.
+int launch_ak_cutoffs(const double *q, int64_t n, double tol, double pref_c, double pref_h,
+                      double eta, double kappa, double diel, double *k2cut, hipStream_t s);
 
 // Adjoint; defined in k_adjoint.hip.
 struct AdjointArgs {

@@ -20,7 +20,8 @@ def _declared():
 def test_header_declares_the_boundary():
     names = _declared()
     for n in ("rism_potential", "rism_asymptotics", "rism_potential_backward", "rism_last_error",
-              "rism_initialize", "rism_default_opts", "rism_compare", "rism_last_stats"):
+              "rism_initialize", "rism_default_opts", "rism_compare", "rism_last_stats",
+              "rism_asymptotics_k"):
         assert n in names
 
 
@@ -110,3 +111,22 @@ def test_site_parameter_validation():
     assert _call_potential(so, si, g, o) == api.RISM_E_INVALID
     si = api.make_sites([-0.834, float("nan")], [3.15, 0.4], [0.152, 0.046])
     assert _call_potential(so, si, g, o) == api.RISM_E_INVALID
+
+
+def test_reciprocal_asymptotics_validation():
+    from paper_2109_09772_amd import api
+    so, si, g, o = _valid()
+    L = api.lib()
+    args = (C.byref(so), C.byref(si), C.byref(g), C.byref(o))
+    fake = C.c_void_p(16)
+    assert L.rism_asymptotics_k(*args, 1.0, 0.1, 1.0, 78.0, 0.0, None, None,
+                                None) == api.RISM_E_INVALID
+    assert "no output" in L.rism_last_error().decode()
+    assert L.rism_asymptotics_k(*args, 0.0, 0.1, 1.0, 78.0, 0.0, fake, None,
+                                None) == api.RISM_E_INVALID
+    assert "eta" in L.rism_last_error().decode()
+    assert L.rism_asymptotics_k(*args, 1.0, -0.1, 1.0, 78.0, 0.0, fake, None,
+                                None) == api.RISM_E_INVALID
+    assert L.rism_asymptotics_k(*args, 1.0, 0.1, 1.0, 78.0, float("nan"), fake, None,
+                                None) == api.RISM_E_INVALID
+    assert "tol" in L.rism_last_error().decode()

@@ -1,0 +1,116 @@
+"""GPU parity of the reciprocal-space long-range asymptotics (Sec. 2.2,
+Eqs. 5 and 7) and their frequency cut-off (Sec. 2.5) against the FP64
+oracle: every entry of small odd/even grids, sampled entries of the 2,500-atom
+128^3 workload, and the zero pattern of the cut-off."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import BETA, DIEL, ETA, KAPPA, KC
+from paper_2109_09772_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2109_09772_amd import api
+    return api
+
+
+def _gpu(wl, tol=0.0, out_dtype="f32", kappa=KAPPA):
+    api = _api()
+    xyz, q, s, e = api.solute_to_device(wl.solute)
+    opts = api.Opts(method="direct_f32c", out_dtype=out_dtype)
+    c, h = api.asymptotics_k(xyz, q, s, e, api.sites_from(wl.sites), api.grid_from(wl.grid), opts,
+                             ETA, kappa, BETA, DIEL, tol=tol)
+    torch.cuda.synchronize()
+    return (c.to(torch.complex128).cpu().numpy(),
+            None if h is None else h.to(torch.complex128).cpu().numpy())
+
+
+def _kcuts(oracle, wl, tol, kappa=KAPPA):
+    st, q = wl.sites, wl.solute.q
+    qa = np.abs(q).sum()
+    qc = np.abs(st.q).max()
+    qh = np.abs(st.q[st.ionic.astype(bool)]).max() if st.ionic.any() else 0.0
+    return (oracle.kcut("c", tol, qc, qa, KC, ETA, kappa, BETA, DIEL),
+            oracle.kcut("h", tol, qh, qa, KC, ETA, kappa, BETA, DIEL))
+
+
+def _rel(x, r):
+    return np.linalg.norm(x - r) / np.linalg.norm(r)
+
+
+@pytest.mark.parametrize("dims,spacing,n", [((9, 8, 7), 0.6, 11), ((12, 10, 9), 0.45, 40),
+                                            ((33, 20, 17), 0.5, 70)])
+@pytest.mark.parametrize("out_dtype", ["f32", "f64"])
+def test_small_grids_every_entry(oracle, dims, spacing, n, out_dtype):
+    wl = W.tiny(n_atoms=n, dims=dims, seed=13, spacing=spacing)
+    sol, st, g = wl.solute, wl.sites, wl.grid
+    c, h = _gpu(wl, out_dtype=out_dtype)
+    cr, hr = oracle.asymptotics_k(sol.xyz, sol.q, st.q, st.ionic, g.origin, g.spacing, g.dims,
+                                  KC, ETA, KAPPA, BETA, DIEL)
+    assert c.shape == cr.shape and h.shape == hr.shape
+    for k in range(c.shape[0]):
+        assert _rel(c[k], cr[k]) < 1e-6
+    for k in range(h.shape[0]):
+        assert _rel(h[k], hr[k]) < 1e-6
+    assert np.all(c[:, 0, 0, 0] == 0)
+
+
+def test_cutoff_zero_pattern(oracle):
+    wl = W.tiny(n_atoms=30, dims=(24, 20, 18), seed=21, spacing=0.35)
+    sol, st, g = wl.solute, wl.sites, wl.grid
+    tol = 1e-3
+    kc_, kh_ = _kcuts(oracle, wl, tol)
+    c, h = _gpu(wl, tol=tol)
+    cr, hr = oracle.asymptotics_k(sol.xyz, sol.q, st.q, st.ionic, g.origin, g.spacing, g.dims,
+                                  KC, ETA, KAPPA, BETA, DIEL, kcut_c=kc_, kcut_h=kh_)
+    np.testing.assert_array_equal(c == 0, cr == 0)
+    np.testing.assert_array_equal(h == 0, hr == 0)
+    assert (cr == 0).sum() > 0 and (cr != 0).sum() > 0
+    for k in range(c.shape[0]):
+        assert _rel(c[k], cr[k]) < 1e-6
+    for k in range(h.shape[0]):
+        assert _rel(h[k], hr[k]) < 1e-6
+
+
+def test_no_atoms_and_kappa_zero(oracle):
+    wl = W.tiny(n_atoms=8, dims=(10, 9, 8), seed=2, spacing=0.5)
+    sol, st, g = wl.solute, wl.sites, wl.grid
+    c, h = _gpu(wl, kappa=0.0)
+    cr, hr = oracle.asymptotics_k(sol.xyz, sol.q, st.q, st.ionic, g.origin, g.spacing, g.dims,
+                                  KC, ETA, 0.0, BETA, DIEL)
+    assert _rel(c, cr) < 1e-6 and _rel(h, hr) < 1e-6
+    wl.solute = W.Solute(np.zeros((0, 3)), np.zeros(0), np.zeros(0), np.zeros(0))
+    c, h = _gpu(wl)
+    assert np.all(c == 0) and np.all(h == 0)
+
+
+def test_protein_2500_sampled_entries(oracle):
+    """The 2,500-atom workload's 128 x 128 x 65 half grid with the cut-off at
+    tol 1e-6, checked at 3,000 seeded entries (the oracle sums those one by
+    one), plus the cut-off's zero pattern on the whole grid."""
+    wl = W.protein_2500()
+    sol, st, g = wl.solute, wl.sites, wl.grid
+    tol = 1e-6
+    kc_, kh_ = _kcuts(oracle, wl, tol)
+    c, h = _gpu(wl, tol=tol)
+    nxh = int(g.dims[0]) // 2 + 1
+    mk = nxh * int(g.dims[1]) * int(g.dims[2])
+    ent = np.random.default_rng(77).choice(mk, 3000, replace=False)
+    cr, hr = oracle.asymptotics_k_entries(sol.xyz, sol.q, st.q, st.ionic, g.origin, g.spacing,
+                                          g.dims, ent, KC, ETA, KAPPA, BETA, DIEL, kcut_c=kc_,
+                                          kcut_h=kh_)
+    cs = c.reshape(c.shape[0], -1)[:, ent]
+    hs = h.reshape(h.shape[0], -1)[:, ent]
+    np.testing.assert_array_equal(cs == 0, cr == 0)
+    for k in range(cs.shape[0]):
+        assert _rel(cs[k], cr[k]) < 1e-6
+    for k in range(hs.shape[0]):
+        assert _rel(hs[k], hr[k]) < 1e-6
+    kx = 2 * np.pi * np.fft.rfftfreq(int(g.dims[0]), g.spacing[0])
+    ky = 2 * np.pi * np.fft.fftfreq(int(g.dims[1]), g.spacing[1])
+    kz = 2 * np.pi * np.fft.fftfreq(int(g.dims[2]), g.spacing[2])
+    kk = np.sqrt(kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2)
+    assert np.all(c[:, kk > kc_] == 0) and np.all(h[:, kk > kh_] == 0)

@@ -136,3 +136,32 @@ def test_protein_2500_vs_f64_direct(oracle, method):
             err = (se / sr) ** 0.5
             print(f"{name}[{k}] rel-L2 {err:.2e}")
             assert mism == 0 and err <= 1e-6
+
+
+def test_cp_buffer_reuse_across_calls(oracle):
+    """Repeated cluster-particle calls of one problem shape size their list
+    buffers from the previous call and check the counts on the device: a
+    denser placement of the same atoms (more candidates than the first call
+    saw) must be detected and recomputed, and the sparse placement must
+    still be right afterwards."""
+    th, dg = TOL_PARAMS["treecode_cp"]
+    sparse = W.tiny(n_atoms=90, dims=(36, 30, 26), seed=23, spacing=0.5)
+    sparse.solute.xyz *= 2.2
+    dense = W.tiny(n_atoms=90, dims=(36, 30, 26), seed=23, spacing=0.5)
+    dense.solute.xyz *= 1.5
+    ref = {}
+    for i, (name, wl) in enumerate((("sparse", sparse), ("dense", dense), ("sparse", sparse),
+                                    ("dense", dense))):
+        (u, c, h), st = _run(wl, leaf_size=8, method="treecode_cp", theta=th, degree=dg)
+        print(name, st)
+        got = [_np(x) for x in (u, c, h)]
+        if name in ref:
+            # the call that reused buffer sizes gives the same bits as the first
+            for x, r in zip(got, ref[name]):
+                np.testing.assert_array_equal(x, r)
+            continue
+        ref[name] = got
+        ur, cr, hr = _oracle_grids(oracle, wl)
+        assert_close_grid(got[0], ur, 1e-6, cap=FP32_CAP, what=f"{name} u")
+        assert_close_grid(got[1], cr, 1e-6, cap=FP32_CAP, what=f"{name} c")
+        assert_close_grid(got[2], hr, 1e-6, cap=FP32_CAP, what=f"{name} h")
