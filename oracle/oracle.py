@@ -58,6 +58,9 @@ def _load():
         lib.oracle_grid_points.argtypes = [_P, _P, _PI, _P]
         lib.oracle_asymptotics_k.argtypes = [i64, _P, _P, i32, _P, _PI, d, d, d, d, d,
                                              _P, _P, _PI, d, d, _P, _P]
+        lib.oracle_asymptotics_k_entries.argtypes = [i64, _P, _P, i32, _P, _PI, d, d, d, d, d,
+                                                     _P, _P, _PI, d, d, i64,
+                                                     C.POINTER(C.c_int64), _P, _P]
         lib.oracle_kcut.argtypes = [C.c_int, d, d, d, d, d, d, d, d]
         lib.oracle_kcut.restype = d
         lib.oracle_num_threads.restype = C.c_int
@@ -201,6 +204,29 @@ def asymptotics_k(xyz, q, site_q, ionic, origin, spacing, dims, kc, eta, kappa, 
     cz = None if c is None else c[..., 0] + 1j * c[..., 1]
     hz = None if h is None else h[..., 0] + 1j * h[..., 1]
     return cz, hz
+
+
+def asymptotics_k_entries(xyz, q, site_q, ionic, origin, spacing, dims, entries, kc, eta,
+                          kappa, beta, diel, kcut_c=0.0, kcut_h=0.0):
+    """The same quantities at listed flat indices of the half grid:
+    c [S][len(entries)], h [n_ionic][len(entries)], complex128."""
+    lib = _load()
+    xyz = _d(np.asarray(xyz).reshape(-1, 3))
+    q, sq = _d(q), _d(site_q)
+    ion = np.ascontiguousarray(ionic, dtype=np.int32)
+    o, h_ = _d(origin), _d(spacing)
+    dm = np.ascontiguousarray(dims, dtype=np.int32)
+    ent = np.ascontiguousarray(entries, dtype=np.int64)
+    c = np.empty((len(sq), len(ent), 2))
+    h = np.empty((int(ion.sum()), len(ent), 2))
+    rc = lib.oracle_asymptotics_k_entries(len(q), _ptr(xyz), _ptr(q), len(sq), _ptr(sq),
+                                          _ptr(ion, _PI), float(kc), float(eta), float(kappa),
+                                          float(beta), float(diel), _ptr(o), _ptr(h_),
+                                          _ptr(dm, _PI), float(kcut_c), float(kcut_h), len(ent),
+                                          ent.ctypes.data_as(C.POINTER(C.c_int64)), _ptr(c),
+                                          _ptr(h))
+    assert rc == 0
+    return c[..., 0] + 1j * c[..., 1], h[..., 0] + 1j * h[..., 1]
 
 
 def kcut(which, tol, qmax, qabs_sum, kc, eta, kappa, beta, diel):
