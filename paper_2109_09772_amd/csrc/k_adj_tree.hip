@@ -26,6 +26,7 @@
 // Determinism: every atom is reduced by one wave in a fixed order; no
 // floating-point atomics.
 #include <cmath>
+#include <type_traits>
 
 #include "cheb.h"
 #include "cp.h"
@@ -174,6 +175,84 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// ------------------------------------------------------------ atom schedule
+// The per-atom kernels below read the grid data (W, w) around their atom.
+// They visit the atoms in a spatial order, a counting sort by the level-0
+// block that holds the atom (z-major, atoms off the grid clamped to the
+// nearest block), and workgroup b takes position (b mod 8) ceil(n/8) + b/8
+// of it: consecutive workgroups go to the 8 XCDs in turn, so each XCD works
+// through one contiguous stretch of space and its L2 keeps serving it.  The
+// order within a block comes from atomics; it only decides which workgroup
+// handles an atom, and every atom's result is computed the same way by one
+// workgroup, so results do not depend on it.
+constexpr int kXcds = 8;
+
+__global__ __launch_bounds__(kBlock) void k_adj_fill(int *p, int n)
+{
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_adj_cell(const float4 *rec, int stride_f4, int n,
+                                                     CpLevels L, int *cell, int *count)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const float4 r0 = rec[(size_t)i * stride_f4];
+    const float4 r1 = rec[(size_t)i * stride_f4 + 1];
+    const double y[3] = {(double)r0.x + r1.x, (double)r0.y + r1.y, (double)r0.z + r1.z};
+    const int nb[3] = {L.cx[0], L.cy[0], L.cz[0]};
+    int c[3];
+    for (int k = 0; k < 3; ++k) {
+        const double f = floor(y[k] / (L.h[k] * L.B));
+        c[k] = f >= 0 ? (f <= nb[k] - 1 ? (int)f : nb[k] - 1) : 0;   // NaN -> 0
+    }
+    const int id = (c[2] * nb[1] + c[1]) * nb[0] + c[0];
+    cell[i] = id;
+    atomicAdd(&count[id], 1);
+}
+
+// In-place exclusive scan of count[0..m) by one workgroup of 1024 threads,
+// each owning a contiguous run.
+__global__ __launch_bounds__(1024) void k_adj_scan(int *count, int m)
+{
+    __shared__ int sums[1024];
+    const int t = threadIdx.x;
+    const int per = (m + 1023) / 1024;
+    const int b = min(t * per, m), e = min(b + per, m);
+    int s = 0;
+    for (int i = b; i < e; ++i) s += count[i];
+    sums[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = t >= off ? sums[t - off] : 0;
+        __syncthreads();
+        sums[t] += v;
+        __syncthreads();
+    }
+    int run = sums[t] - s;
+    for (int i = b; i < e; ++i) {
+        const int c = count[i];
+        count[i] = run;
+        run += c;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_adj_scatter(const int *cell, int n, int *next,
+                                                        int *order)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    order[atomicAdd(&next[cell[i]], 1)] = i;
+}
+
+// The atom of this workgroup, or -1 for the few padding workgroups.
+__device__ __forceinline__ int64_t adj_atom(const int *order, int64_t n)
+{
+    const int64_t per = (n + kXcds - 1) / kXcds;
+    const int64_t pos = (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    return pos < n ? order[pos] : -1;
+}
+
 struct AdjWalkArgs {
     CpLevels L;
     const float4 *rec;     // staged FP32 records, input order
@@ -182,30 +261,148 @@ struct AdjWalkArgs {
     int deg, np;
     const double *What;
     const float *Wf;       // W on the grid (FP32)
+    const int *order;      // spatial order of the atoms
     double *dxyz, *dq;
 };
 
-// One wave per atom: the forward's assignment walk, proxies or direct points.
+// Waves that share one atom in the adjoint kernels; their partial sums meet
+// in LDS and are added in wave order, so the result does not depend on timing.
+constexpr int kAdjWaves = kBlock / 64;
+constexpr int kAdjMaxDegree = 16;
+
+__device__ __forceinline__ void block_reduce_store(double (*part)[8], const double *v, int nv,
+                                                   int lane, int wave)
+{
+    for (int i = 0; i < nv; ++i) {
+        const double s = wave_sum(v[i]);
+        if (lane == 0) part[wave][i] = s;
+    }
+}
+
+// One workgroup per atom: every wave repeats the forward's assignment walk
+// (a few hundred MAC tests) and evaluates every kAdjWaves-th of the items it
+// meets, an item being an accepted cluster (its proxies) or a level-0 block
+// reached unassigned (its grid points).
 __global__ __launch_bounds__(kBlock) void k_adj_walk(AdjWalkArgs a)
 {
-    __shared__ long long stack[kBlock / 64][kStackPerWave];
+    __shared__ long long stack[kAdjWaves][kStackPerWave];
+    __shared__ double cosk[kAdjMaxDegree + 1];
+    __shared__ double part[kAdjWaves][8];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t atom = blockIdx.x * (int64_t)(kBlock / 64) + wave;
-    if (atom >= a.n) return;   // whole wave leaves together; no block barrier below
+    const int64_t atom = adj_atom(a.order, a.n);
+    if (atom < 0) return;   // whole workgroup, before any barrier
     const CpLevels &L = a.L;
     const float4 r0 = a.rec[(size_t)atom * a.stride_f4];
     const float4 r1 = a.rec[(size_t)atom * a.stride_f4 + 1];
     const double y[3] = {(double)r0.x + r1.x, (double)r0.y + r1.y, (double)r0.z + r1.z};
     const int n1 = a.deg + 1;
+    if (threadIdx.x < n1) cosk[threadIdx.x] = cos(kPi * threadIdx.x / a.deg);
+    // digits of 64 and of the lane index in base n1 (proxy k = (k3 n1 + k2) n1 + k1)
+    const int c1 = 64 % n1, c2 = (64 / n1) % n1, c3 = 64 / (n1 * n1);
+    const int c1l = lane % n1, c2l = (lane / n1) % n1, c3l = lane / (n1 * n1);
+    __syncthreads();
     double pot = 0, fx = 0, fy = 0, fz = 0;
+    int item = 0;
+
+    // accepted cluster: potential and field of its proxy weights at the atom
+    auto far_item = [&](int lvl, int I, int J, int K) {
+        if (item++ % kAdjWaves != wave) return;
+        double pb[6], cc[3], rr;
+        cp_proxy_box(L, lvl, I, J, K, pb);
+        cp_centre(L, lvl, I, J, K, cc, rr);
+        const double *Wh = a.What + (size_t)cp_id(L, lvl, I, J, K) * a.np;
+        // lane l < 3 (n+1) holds Chebyshev node l % (n+1) of axis l / (n+1),
+        // relative to the atom; other lanes read it by shuffle
+        float node = 0.f;
+        if (lane < 3 * n1) {
+            const int ax = lane / n1, kk = lane % n1;
+            const double lo = pb[ax], hi = pb[3 + ax];
+            const float yc = (float)(y[ax] - cc[ax]);
+            node = (float)(lo + (hi - lo) * 0.5 * (1.0 + cosk[kk]) - cc[ax]) - yc;
+        }
+        float p = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        int cnt = 0;
+        // lane's proxy (k1, k2, k3), stepped by 64 = c3 n1^2 + c2 n1 + c1
+        int k1 = c1l, k2 = c2l, k3 = c3l;
+        for (int k0 = 0; k0 < a.np; k0 += 64) {
+            const int k = k0 + lane;
+            const bool in = k < a.np;
+            const float dx = __shfl(node, k1);
+            const float dy = __shfl(node, n1 + k2);
+            const float dz = __shfl(node, 2 * n1 + (in ? k3 : 0));
+            k1 += c1; k2 += c2; k3 += c3;
+            if (k1 >= n1) { k1 -= n1; ++k2; }
+            if (k2 >= n1) { k2 -= n1; ++k3; }
+            if (in) {
+                const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                const float ri = __builtin_amdgcn_rsqf(d2);
+                const float wr = (float)Wh[k] * ri;
+                const float wr3 = wr * ri * ri;
+                p += wr;
+                gx = fmaf(wr3, dx, gx);
+                gy = fmaf(wr3, dy, gy);
+                gz = fmaf(wr3, dz, gz);
+            }
+            if (++cnt == 8) {
+                pot += p; fx += gx; fy += gy; fz += gz;
+                p = gx = gy = gz = 0.f;
+                cnt = 0;
+            }
+        }
+        pot += p; fx += gx; fy += gy; fz += gz;
+    };
+
+    // level-0 block reached unassigned: direct over its grid points, offsets
+    // formed in FP64 and rounded once
+    auto direct_item = [&](int I, int J, int K) {
+        if (item++ % kAdjWaves != wave) return;
+        const int i0 = I * L.B, j0 = J * L.B, k0 = K * L.B;
+        const int ex = min(L.B, L.nx - i0), ey = min(L.B, L.ny - j0), ez = min(L.B, L.nz - k0);
+        const int npts = ex * ey * ez;
+        float p = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        int cnt = 0;
+        // lane's point (li, lj, lk) of the block, stepped by 64 points
+        const int s1 = 64 % ex, s2 = (64 / ex) % ey, s3 = 64 / (ex * ey);
+        int li = lane % ex, lj = (lane / ex) % ey, lk = lane / (ex * ey);
+        for (int t = lane; t < npts; t += 64) {
+            const int gi = i0 + li, gj = j0 + lj, gk = k0 + lk;
+            li += s1; lj += s2; lk += s3;
+            if (li >= ex) { li -= ex; ++lj; }
+            if (lj >= ey) { lj -= ey; ++lk; }
+            const float dx = (float)fma((double)gi, L.h[0], -y[0]);
+            const float dy = (float)fma((double)gj, L.h[1], -y[1]);
+            const float dz = (float)fma((double)gk, L.h[2], -y[2]);
+            const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            const float ri = d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
+            const float wr = a.Wf[((int64_t)gk * L.ny + gj) * L.nx + gi] * ri;
+            const float wr3 = wr * ri * ri;
+            p += wr;
+            gx = fmaf(wr3, dx, gx);
+            gy = fmaf(wr3, dy, gy);
+            gz = fmaf(wr3, dz, gz);
+            if (++cnt == 8) {
+                pot += p; fx += gx; fy += gy; fz += gz;
+                p = gx = gy = gz = 0.f;
+                cnt = 0;
+            }
+        }
+        pot += p; fx += gx; fy += gy; fz += gz;
+    };
+
+    // The walk: depth first over the clusters that fail the MAC; the (up to
+    // 8) children of a popped cluster are classified by lanes 0..7 at once.
+    // The stack is wave-uniform: every lane writes the same value.
     long long *st = stack[wave];
     int sp = 0;
     auto enc = [](int lvl, int I, int J, int K) -> long long {
         return ((long long)lvl << 54) | ((long long)I << 36) | ((long long)J << 18) | (long long)K;
     };
-    // the stack is wave-uniform: every lane writes the same value
-    st[0] = enc(L.T, 0, 0, 0);
-    sp = 1;
+    if (L.T == 0)
+        direct_item(0, 0, 0);
+    else if (cp_mac(L, L.T, 0, 0, 0, y))
+        far_item(L.T, 0, 0, 0);
+    else
+        st[sp++] = enc(L.T, 0, 0, 0);
     __builtin_amdgcn_wave_barrier();
     while (sp > 0) {
         --sp;
@@ -213,103 +410,39 @@ __global__ __launch_bounds__(kBlock) void k_adj_walk(AdjWalkArgs a)
         __builtin_amdgcn_wave_barrier();
         const int lvl = (int)(c >> 54), I = (int)((c >> 36) & 0x3ffff),
                   J = (int)((c >> 18) & 0x3ffff), K = (int)(c & 0x3ffff);
-        if (lvl >= 1 && cp_mac(L, lvl, I, J, K, y)) {
-            // accepted: potential and field of the cluster's proxy weights
-            double pb[6], cc[3], rr;
-            cp_proxy_box(L, lvl, I, J, K, pb);
-            cp_centre(L, lvl, I, J, K, cc, rr);
-            const float yx = (float)(y[0] - cc[0]), yy = (float)(y[1] - cc[1]), yz = (float)(y[2] - cc[2]);
-            const double *Wh = a.What + (size_t)cp_id(L, lvl, I, J, K) * a.np;
-            // lane l < 3 (n+1) holds Chebyshev node l % (n+1) of axis l / (n+1),
-            // relative to the atom; other lanes read it by shuffle
-            float node = 0.f;
-            if (lane < 3 * n1) {
-                const int ax = lane / n1, kk = lane % n1;
-                const float yc = ax == 0 ? yx : (ax == 1 ? yy : yz);
-                node = (float)(cheb_point(pb[ax], pb[3 + ax], kk, a.deg) - cc[ax]) - yc;
-            }
-            float p = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
-            int cnt = 0;
-            for (int k0 = 0; k0 < a.np; k0 += 64) {
-                const int k = k0 + lane;
-                const int kc = k < a.np ? k : 0;
-                const int k1 = kc % n1, k2 = (kc / n1) % n1, k3 = kc / (n1 * n1);
-                const float dx = __shfl(node, k1);
-                const float dy = __shfl(node, n1 + k2);
-                const float dz = __shfl(node, 2 * n1 + k3);
-                if (k < a.np) {
-                    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    const float ri = __builtin_amdgcn_rsqf(d2);
-                    const float wr = (float)Wh[k] * ri;
-                    const float wr3 = wr * ri * ri;
-                    p += wr;
-                    gx = fmaf(wr3, dx, gx);
-                    gy = fmaf(wr3, dy, gy);
-                    gz = fmaf(wr3, dz, gz);
-                }
-                if (++cnt == 8) {
-                    pot += p; fx += gx; fy += gy; fz += gz;
-                    p = gx = gy = gz = 0.f;
-                    cnt = 0;
-                }
-            }
-            pot += p; fx += gx; fy += gy; fz += gz;
-        } else if (lvl >= 1) {
-            for (int cz = 1; cz >= 0; --cz)
-                for (int cy = 1; cy >= 0; --cy)
-                    for (int cx = 1; cx >= 0; --cx) {
-                        const int ci = 2 * I + cx, cj = 2 * J + cy, ck = 2 * K + cz;
-                        if (ci < L.cx[lvl - 1] && cj < L.cy[lvl - 1] && ck < L.cz[lvl - 1] &&
-                            sp < kStackPerWave) {
-                            st[sp] = enc(lvl - 1, ci, cj, ck);
-                            ++sp;
-                        }
-                    }
-            __builtin_amdgcn_wave_barrier();
-        } else {
-            // level-0 block reached unassigned: direct over its grid points
-            const int i0 = I * L.B, j0 = J * L.B, k0 = K * L.B;
-            const int ex = min(L.B, L.nx - i0), ey = min(L.B, L.ny - j0), ez = min(L.B, L.nz - k0);
-            const int npts = ex * ey * ez;
-            const float yxh = r0.x, yyh = r0.y, yzh = r0.z, yxl = r1.x, yyl = r1.y, yzl = r1.z;
-            float p = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
-            int cnt = 0;
-            for (int t = lane; t < npts; t += 64) {
-                const int li = t % ex, lj = (t / ex) % ey, lk = t / (ex * ey);
-                const int gi = i0 + li, gj = j0 + lj, gk = k0 + lk;
-                const double xd = gi * L.h[0], yd = gj * L.h[1], zd = gk * L.h[2];
-                const float xh = (float)xd, yh = (float)yd, zh = (float)zd;
-                const float dx = (xh - yxh) + ((float)(xd - (double)xh) - yxl);
-                const float dy = (yh - yyh) + ((float)(yd - (double)yh) - yyl);
-                const float dz = (zh - yzh) + ((float)(zd - (double)zh) - yzl);
-                const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                const float ri = d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
-                const float wr = a.Wf[((int64_t)gk * L.ny + gj) * L.nx + gi] * ri;
-                const float wr3 = wr * ri * ri;
-                p += wr;
-                gx = fmaf(wr3, dx, gx);
-                gy = fmaf(wr3, dy, gy);
-                gz = fmaf(wr3, dz, gz);
-                if (++cnt == 8) {
-                    pot += p; fx += gx; fy += gy; fz += gz;
-                    p = gx = gy = gz = 0.f;
-                    cnt = 0;
-                }
-            }
-            pot += p; fx += gx; fy += gy; fz += gz;
+        const int cl = lvl - 1;
+        bool valid = false, acc = false;
+        if (lane < 8) {
+            const int ci = 2 * I + (lane & 1), cj = 2 * J + ((lane >> 1) & 1), ck = 2 * K + (lane >> 2);
+            valid = ci < L.cx[cl] && cj < L.cy[cl] && ck < L.cz[cl];
+            acc = valid && cl >= 1 && cp_mac(L, cl, ci, cj, ck, y);
         }
+        const unsigned long long vm = __ballot(valid), am = __ballot(acc);
+        for (int ch = 7; ch >= 0; --ch) {
+            if (!((vm >> ch) & 1)) continue;
+            const int ci = 2 * I + (ch & 1), cj = 2 * J + ((ch >> 1) & 1), ck = 2 * K + (ch >> 2);
+            if (cl == 0)
+                direct_item(ci, cj, ck);
+            else if ((am >> ch) & 1)
+                far_item(cl, ci, cj, ck);
+            else if (sp < kStackPerWave)
+                st[sp++] = enc(cl, ci, cj, ck);
+        }
+        __builtin_amdgcn_wave_barrier();
     }
-    pot = wave_sum(pot);
-    fx = wave_sum(fx);
-    fy = wave_sum(fy);
-    fz = wave_sum(fz);
-    if (lane == 0) {
+    const double v[4] = {pot, fx, fy, fz};
+    block_reduce_store(part, v, 4, lane, wave);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s[4] = {0, 0, 0, 0};
+        for (int w = 0; w < kAdjWaves; ++w)
+            for (int i = 0; i < 4; ++i) s[i] += part[w][i];
         const double q = (double)r0.w;
-        if (a.dq) a.dq[atom] = pot;
+        if (a.dq) a.dq[atom] = s[0];
         if (a.dxyz) {
-            a.dxyz[3 * atom] = q * fx;
-            a.dxyz[3 * atom + 1] = q * fy;
-            a.dxyz[3 * atom + 2] = q * fz;
+            a.dxyz[3 * atom] = q * s[1];
+            a.dxyz[3 * atom + 1] = q * s[2];
+            a.dxyz[3 * atom + 2] = q * s[3];
         }
     }
 }
@@ -322,29 +455,52 @@ struct AdjLjArgs {
     const void *w;
     int w_f64;
     double rcut_max;
+    int off_cap;           // LDS entries reserved for the x offsets
+    const int *order;      // spatial order of the atoms
     const double *eps_in;
     double *dxyz, *deps, *dsig;
     int add_xyz;           // dxyz already holds the Coulomb part
 };
 
-// One wave per atom: LJ adjoint over the grid points inside the cut-off box.
-template <int NS>
+// Grid points of one axis within r of the coordinate y: the closed index
+// range [lo, hi], empty when lo > hi.
+__device__ __forceinline__ void axis_range(double y, double r, double h, int n, int &lo, int &hi)
+{
+    lo = max((int)ceil((y - r) / h), 0);
+    hi = min((int)floor((y + r) / h), n - 1);
+}
+
+// One workgroup per atom: the LJ adjoint over the grid points within the
+// atom's largest cut-off radius, per site masked by its own radius.  Wave w
+// takes the z planes w, w + kAdjWaves, ... of the cut-off box; in each plane
+// it visits the square bounding the sphere's section (2/3 of the box's
+// points).  Point offsets come from per-axis tables of FP64 differences
+// rounded once to FP32.
+template <int NS, bool W64>
 __global__ __launch_bounds__(kBlock) void k_adj_lj(AdjLjArgs a)
 {
+    extern __shared__ float offs[];    // [off_cap] x offsets, then y offsets
+    __shared__ double part[kAdjWaves][8];
+    __shared__ double part2[kAdjWaves][2 * NS];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t atom = blockIdx.x * (int64_t)(kBlock / 64) + wave;
-    if (atom >= a.n) return;
+    const int64_t atom = adj_atom(a.order, a.n);
+    if (atom < 0) return;   // whole workgroup, before any barrier
     const AtomF32<NS> &rc = static_cast<const AtomF32<NS> *>(a.rec)[atom];
     const GridParams &g = a.g;
     const double y[3] = {(double)rc.xh + rc.xl, (double)rc.yh + rc.yl, (double)rc.zh + rc.zl};
+    // the sphere is widened by 1e-6 of its radius, far more than FP32
+    // rounding of a distance, so that the per-site FP32 masks decide at the edge
+    const double R = a.rcut_max * (1.0 + 1e-6);
     int lo[3], hi[3];
-    const int dims[3] = {g.nx, g.ny, g.nz};
-    for (int k = 0; k < 3; ++k) {
-        lo[k] = (int)ceil((y[k] - a.rcut_max) / g.h[k]);
-        hi[k] = (int)floor((y[k] + a.rcut_max) / g.h[k]);
-        lo[k] = lo[k] < 0 ? 0 : lo[k];
-        hi[k] = hi[k] > dims[k] - 1 ? dims[k] - 1 : hi[k];
-    }
+    axis_range(y[0], R, g.h[0], g.nx, lo[0], hi[0]);
+    axis_range(y[1], R, g.h[1], g.ny, lo[1], hi[1]);
+    axis_range(y[2], R, g.h[2], g.nz, lo[2], hi[2]);
+    float *ox = offs, *oy = offs + a.off_cap;
+    for (int t = threadIdx.x; t <= hi[0] - lo[0]; t += kBlock)
+        ox[t] = (float)fma((double)(lo[0] + t), g.h[0], -y[0]);
+    for (int t = threadIdx.x; t <= hi[1] - lo[1]; t += kBlock)
+        oy[t] = (float)fma((double)(lo[1] + t), g.h[1], -y[1]);
+    __syncthreads();
     float sg6[NS], e24[NS], rc2[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -356,32 +512,57 @@ __global__ __launch_bounds__(kBlock) void k_adj_lj(AdjLjArgs a)
     double gx = 0, gy = 0, gz = 0, gE[NS], gS[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) { gE[s] = 0; gS[s] = 0; }
-    if (lo[0] <= hi[0] && lo[1] <= hi[1] && lo[2] <= hi[2]) {
-        const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
-        const int64_t npts = (int64_t)ex * ey * ez;
+    for (int gk = lo[2] + wave; gk <= hi[2]; gk += kAdjWaves) {
+        const double dzd = fma((double)gk, g.h[2], -y[2]);
+        const double r2p = R * R - dzd * dzd;
+        if (r2p < 0) continue;
+        const double half = sqrt(r2p);
+        int ilo, ihi, jlo, jhi;
+        axis_range(y[0], half, g.h[0], g.nx, ilo, ihi);
+        axis_range(y[1], half, g.h[1], g.ny, jlo, jhi);
+        ilo = max(ilo, lo[0]); ihi = min(ihi, hi[0]);
+        jlo = max(jlo, lo[1]); jhi = min(jhi, hi[1]);
+        if (ilo > ihi || jlo > jhi) continue;
+        const int ex = ihi - ilo + 1, npl = ex * (jhi - jlo + 1);
+        const float dz = (float)dzd;
+        const float dz2 = dz * dz;
+        const int64_t plane = (int64_t)gk * g.ny * g.nx;
+        // lane's (li, lj) within the plane's rectangle, stepped by 64 points
+        int li = lane % ex, lj = lane / ex;
+        const int qs = 64 / ex, rs = 64 % ex;
         float fx = 0, fy = 0, fz = 0, fE[NS], fS[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) { fE[s] = 0; fS[s] = 0; }
         int cnt = 0;
-        for (int64_t t = lane; t < npts; t += 64) {
-            const int li = (int)(t % ex), lj = (int)((t / ex) % ey), lk = (int)(t / ((int64_t)ex * ey));
-            const int gi = lo[0] + li, gj = lo[1] + lj, gk = lo[2] + lk;
-            const double xd = gi * g.h[0], yd = gj * g.h[1], zd = gk * g.h[2];
-            const float xh = (float)xd, yh = (float)yd, zh = (float)zd;
-            const float dx = (xh - rc.xh) + ((float)(xd - (double)xh) - rc.xl);
-            const float dy = (yh - rc.yh) + ((float)(yd - (double)yh) - rc.yl);
-            const float dz = (zh - rc.zh) + ((float)(zd - (double)zh) - rc.zl);
-            const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            const float ri = d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
-            const float r2 = ri * ri, r6 = r2 * r2 * r2;
-            const int64_t p = ((int64_t)gk * g.ny + gj) * g.nx + gi;
+        // the next point's offsets and weights are loaded one step ahead
+        float ndx = 0.f, ndy = 0.f, nw[NS];
+        auto fetch = [&]() {
+            ndx = ox[ilo - lo[0] + li];
+            ndy = oy[jlo - lo[1] + lj];
+            const int64_t p = plane + (int64_t)(jlo + lj) * g.nx + (ilo + li);
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                nw[s] = s < a.ns ? (W64 ? (float)static_cast<const double *>(a.w)[s * g.m + p]
+                                        : static_cast<const float *>(a.w)[s * g.m + p])
+                                 : 0.f;
+            li += rs;
+            lj += qs;
+            if (li >= ex) { li -= ex; ++lj; }
+        };
+        if (lane < npl) fetch();
+        for (int t = lane; t < npl; t += 64) {
+            const float dx = ndx, dy = ndy;
+            float wv[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) wv[s] = nw[s];
+            if (t + 64 < npl) fetch();
+            const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz2));
+            const float r2 = d2 > 0.f ? __builtin_amdgcn_rcpf(d2) : 0.f;
+            const float r6 = r2 * r2 * r2;
             float Flj = 0.f;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                if (s >= a.ns) break;
-                float ws = a.w_f64 ? (float)static_cast<const double *>(a.w)[s * g.m + p]
-                                   : static_cast<const float *>(a.w)[s * g.m + p];
-                ws = d2 < rc2[s] ? ws : 0.f;
+                const float ws = d2 < rc2[s] ? wv[s] : 0.f;
                 const float s6 = sg6[s] * r6;
                 const float ws6 = ws * s6;
                 const float v = ws6 * (s6 + s6 - 1.f);
@@ -405,34 +586,40 @@ __global__ __launch_bounds__(kBlock) void k_adj_lj(AdjLjArgs a)
 #pragma unroll
         for (int s = 0; s < NS; ++s) { gE[s] += fE[s]; gS[s] += fS[s]; }
     }
-    gx = wave_sum(gx);
-    gy = wave_sum(gy);
-    gz = wave_sum(gz);
-    double e_sum = 0, s_sum = 0;
+    const double v[3] = {gx, gy, gz};
+    block_reduce_store(part, v, 3, lane, wave);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const double E = wave_sum(gE[s]), Sg = wave_sum(gS[s]);
+        if (lane == 0) { part2[wave][2 * s] = E; part2[wave][2 * s + 1] = Sg; }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double sx = 0, sy = 0, sz = 0, e_sum = 0, s_sum = 0;
+    for (int w = 0; w < kAdjWaves; ++w) { sx += part[w][0]; sy += part[w][1]; sz += part[w][2]; }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        double E = 0, Sg = 0;
+        for (int w = 0; w < kAdjWaves; ++w) { E += part2[w][2 * s]; Sg += part2[w][2 * s + 1]; }
         const double A = (double)rc.A[s], B = (double)rc.B[s];
         const double e_ga = A > 0 ? B * B / (4.0 * A) : 0.0;
         const double sg = B > 0 ? pow(A / B, 1.0 / 6.0) : 0.0;
         e_sum += 2.0 * e_ga * E;
         s_sum += sg > 0 ? 12.0 * e_ga / sg * Sg : 0.0;
     }
-    if (lane == 0) {
-        if (a.dxyz) {
-            if (a.add_xyz) {
-                a.dxyz[3 * atom] += gx;
-                a.dxyz[3 * atom + 1] += gy;
-                a.dxyz[3 * atom + 2] += gz;
-            } else {
-                a.dxyz[3 * atom] = gx;
-                a.dxyz[3 * atom + 1] = gy;
-                a.dxyz[3 * atom + 2] = gz;
-            }
+    if (a.dxyz) {
+        if (a.add_xyz) {
+            a.dxyz[3 * atom] += sx;
+            a.dxyz[3 * atom + 1] += sy;
+            a.dxyz[3 * atom + 2] += sz;
+        } else {
+            a.dxyz[3 * atom] = sx;
+            a.dxyz[3 * atom + 1] = sy;
+            a.dxyz[3 * atom + 2] = sz;
         }
-        if (a.deps) a.deps[atom] = e_sum / a.eps_in[atom];
-        if (a.dsig) a.dsig[atom] = s_sum;
     }
+    if (a.deps) a.deps[atom] = e_sum / a.eps_in[atom];
+    if (a.dsig) a.dsig[atom] = s_sum;
 }
 
 }  // namespace
@@ -476,7 +663,42 @@ int adjoint_tree(const AdjointArgs &a, Workspace &ws, rism_stats &st, hipStream_
     }
     RISM_HIP(hipGetLastError());
     const int stride_f4 = (int)(rec32_bytes_of(a.sp.ns_pad) / sizeof(float4));
-    const int nblk = (int)((a.n + 3) / 4);
+    if (a.n == 0) return RISM_OK;
+    if (deg > kAdjMaxDegree) {
+        set_error("treecode backward: degree above 16");
+        return RISM_E_UNSUPPORTED;
+    }
+    // LJ gather: per-axis offset tables in LDS, sized for the widest cut-off box
+    auto axis_cap = [&](double h, int n) {
+        return (int)std::min<double>(n, std::floor(2.0 * a.rmax_lj * (1.0 + 1e-6) / h) + 2.0);
+    };
+    const int off_cap = axis_cap(a.g.h[0], a.g.nx), off_cap_y = axis_cap(a.g.h[1], a.g.ny);
+    const size_t shm_lj = (size_t)(off_cap + off_cap_y) * sizeof(float);
+    if ((a.dxyz || a.deps || a.dsig) && shm_lj + 4096 > (size_t)lds_max) {
+        set_error("treecode backward: LJ cut-off box too wide for the LDS of this device");
+        return RISM_E_UNSUPPORTED;
+    }
+    if (a.n > INT32_MAX / 2) {
+        set_error("treecode backward: too many atoms");
+        return RISM_E_UNSUPPORTED;
+    }
+    const int n = (int)a.n;
+    const int ncell = L.cx[0] * L.cy[0] * L.cz[0];
+    int *cell = ws.get<int>(n);
+    int *next = ws.get<int>(ncell);
+    int *order = ws.get<int>(n);
+    if (ws.status()) return ws.status();
+    {
+        PhaseTimer pt(ev, RISM_PHASE_TREE_BUILD, s);   // atom schedule
+        const int nb = (n + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL(k_adj_fill, std::min((ncell + kBlock - 1) / kBlock, 1024), kBlock, 0, s,
+                           next, ncell);
+        hipLaunchKernelGGL(k_adj_cell, nb, kBlock, 0, s, static_cast<const float4 *>(a.atoms),
+                           stride_f4, n, L, cell, next);
+        hipLaunchKernelGGL(k_adj_scan, 1, 1024, 0, s, next, ncell);
+        hipLaunchKernelGGL(k_adj_scatter, nb, kBlock, 0, s, cell, n, next, order);
+    }
+    const int nblk = (int)(((int64_t)n + kXcds - 1) / kXcds * kXcds);
     {
         PhaseTimer pt(ev, RISM_PHASE_ADJOINT, s);
         if (a.dq || a.dxyz) {
@@ -489,6 +711,7 @@ int adjoint_tree(const AdjointArgs &a, Workspace &ws, rism_stats &st, hipStream_
             wa.np = np;
             wa.What = What;
             wa.Wf = Wf;
+            wa.order = order;
             wa.dxyz = a.dxyz;
             wa.dq = a.dq;
             hipLaunchKernelGGL(k_adj_walk, nblk, kBlock, 0, s, wa);
@@ -502,16 +725,25 @@ int adjoint_tree(const AdjointArgs &a, Workspace &ws, rism_stats &st, hipStream_
             la.w = a.w;
             la.w_f64 = a.w_f64;
             la.rcut_max = a.rmax_lj;
+            la.off_cap = off_cap;
+            la.order = order;
             la.eps_in = a.eps_in;
             la.dxyz = a.dxyz;
             la.deps = a.deps;
             la.dsig = a.dsig;
             la.add_xyz = 1;
+            auto launch = [&](auto ns_c) {
+                constexpr int NS = decltype(ns_c)::value;
+                if (a.w_f64)
+                    hipLaunchKernelGGL((k_adj_lj<NS, true>), nblk, kBlock, shm_lj, s, la);
+                else
+                    hipLaunchKernelGGL((k_adj_lj<NS, false>), nblk, kBlock, shm_lj, s, la);
+            };
             switch (a.sp.ns_pad) {
-            case 1: hipLaunchKernelGGL(k_adj_lj<1>, nblk, kBlock, 0, s, la); break;
-            case 2: hipLaunchKernelGGL(k_adj_lj<2>, nblk, kBlock, 0, s, la); break;
-            case 4: hipLaunchKernelGGL(k_adj_lj<4>, nblk, kBlock, 0, s, la); break;
-            default: hipLaunchKernelGGL(k_adj_lj<8>, nblk, kBlock, 0, s, la); break;
+            case 1: launch(std::integral_constant<int, 1>{}); break;
+            case 2: launch(std::integral_constant<int, 2>{}); break;
+            case 4: launch(std::integral_constant<int, 4>{}); break;
+            default: launch(std::integral_constant<int, 8>{}); break;
             }
         }
     }

@@ -159,3 +159,31 @@ def test_tree_adjoint_protein_2500():
         err = _rel(x.cpu().numpy(), r.cpu().numpy())
         print(name, f"{err:.2e}")
         assert err < 1e-5, (name, err)
+
+
+def test_tree_adjoint_per_pair_cutoff_anisotropic(oracle):
+    """Per-pair LJ cut-offs from lj_tol (radii differ by site and atom) on a
+    grid with a different spacing per axis and atoms beyond its faces: the
+    LJ gather's per-plane bounds and the walk's direct blocks against the
+    oracle's FP64 gradient."""
+    from paper_2109_09772_amd import api
+    wl, w = _grad_case(seed=12, n=55, dims=(41, 30, 27), spacing=0.5)
+    wl.grid = W.centred_grid([0.4, -0.3, 0.2], [0.42, 0.55, 0.61], (41, 30, 27))
+    wl.solute.xyz *= 2.2
+    w = W.smooth_upstream(wl.grid, wl.sites, seed=112)
+    xyz, q, s, e = api.solute_to_device(wl.solute)
+    o = api.Opts(method="treecode_cp", out_dtype="f32", lj_tol=1e-4, theta=0.5, degree=10,
+                 batch_edge=8, leaf_size=16)
+    wt = torch.as_tensor(w, device="cuda", dtype=torch.float32)
+    dx, dq, de, ds = api.potential_backward(xyz, q, s, e, api.sites_from(wl.sites),
+                                            api.grid_from(wl.grid), o, wt)
+    sol, st, g = wl.solute, wl.sites, wl.grid
+    rc = oracle_rcut(oracle, wl, lj_tol=1e-4)
+    assert np.ptp(rc) > 1.0
+    rx, rq, re_, rs = oracle.backward_grid(sol.xyz, sol.q, sol.sigma, sol.eps, st.q, st.sigma,
+                                           st.eps, g.origin, g.spacing, g.dims,
+                                           wt.double().cpu().numpy(), KC, rc)
+    for name, x, r in (("dxyz", dx, rx), ("dq", dq, rq), ("deps", de, re_), ("dsigma", ds, rs)):
+        err = _rel(x.cpu().numpy(), r)
+        print(name, f"{err:.2e}")
+        assert err < 1e-5, (name, err)
