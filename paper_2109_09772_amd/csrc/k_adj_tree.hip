@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_w(const void *w, int w_f64, int 
 
 // Level-1 proxy weights: What[k3][k2][k1] = sum_{z,y,x} Lz[z][k3] Ly[y][k2] Lx[x][k1] W[z][y][x].
 __global__ __launch_bounds__(kBlock) void k_adj_up1(CpLevels L, int deg, const double *W,
-                                                    double *What)
+                                                    double *What, float *Whatf)
 {
     extern __shared__ double sm[];
     const int n1 = deg + 1, np = n1 * n1 * n1;
@@ -106,12 +106,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_up1(CpLevels L, int deg, const d
         double s = 0;
         for (int z = 0; z < ez; ++z) s += T2[z * n1 * n1 + k12] * Lz[z * n1 + k3];
         What[(size_t)id * np + k] = s;
+        Whatf[(size_t)id * np + k] = (float)s;
     }
 }
 
 // Parent proxy weights from the children: What_P = sum_c (Mx (x) My (x) Mz)^T What_c,
-// M[k][m] = L^P_m(s^c_k), children in (z, y, x) order.
-__global__ __launch_bounds__(kBlock) void k_adj_up(CpLevels L, int lvl, int deg, double *What)
+// M[k][m] = L^P_m(s^c_k).  One workgroup per child writes its term; a second
+// kernel adds the (up to 8) terms of each parent in the fixed (z, y, x) order.
+__global__ __launch_bounds__(kBlock) void k_adj_up_child(CpLevels L, int lvl, int deg,
+                                                         const double *What, double *term)
 {
     extern __shared__ double sm[];
     const int n1 = deg + 1, np = n1 * n1 * n1;
@@ -119,54 +122,65 @@ __global__ __launch_bounds__(kBlock) void k_adj_up(CpLevels L, int lvl, int deg,
     double *src = M + 3 * n1 * n1;   // [np]
     double *t1 = src + np;
     double *t2 = t1 + np;
-    double *acc = t2 + np;           // [np], each entry owned by one thread
+    const int cl = lvl - 1;
+    const int q = blockIdx.x;
+    const int ci = q % L.cx[cl], cj = (q / L.cx[cl]) % L.cy[cl], ck = q / (L.cx[cl] * L.cy[cl]);
+    double pbx[6], cb[6];
+    cp_proxy_box(L, lvl, ci >> 1, cj >> 1, ck >> 1, pbx);
+    cp_proxy_box(L, cl, ci, cj, ck, cb);
+    if (threadIdx.x < 3 * n1) {
+        const int ax = threadIdx.x / n1, k = threadIdx.x % n1;
+        lagrange_to(cheb_point(pick3(cb, ax), pick3(cb + 3, ax), k, deg), pick3(pbx, ax),
+                    pick3(pbx + 3, ax), deg, M + (ax * n1 + k) * n1, 1);
+    }
+    const int cid = cp_id(L, cl, ci, cj, ck);
+    for (int k = threadIdx.x; k < np; k += kBlock) src[k] = What[(size_t)cid * np + k];
+    __syncthreads();
+    // t1[k3][k2][m1] = sum_k1 M[0][k1][m1] src[k3][k2][k1]
+    for (int k = threadIdx.x; k < np; k += kBlock) {
+        const int m1 = k % n1, rest = k / n1;
+        double s = 0;
+        for (int k1 = 0; k1 < n1; ++k1) s += M[(0 * n1 + k1) * n1 + m1] * src[rest * n1 + k1];
+        t1[k] = s;
+    }
+    __syncthreads();
+    // t2[k3][m2][m1] = sum_k2 M[1][k2][m2] t1[k3][k2][m1]
+    for (int k = threadIdx.x; k < np; k += kBlock) {
+        const int m1 = k % n1, m2 = (k / n1) % n1, k3 = k / (n1 * n1);
+        double s = 0;
+        for (int k2 = 0; k2 < n1; ++k2) s += M[(1 * n1 + k2) * n1 + m2] * t1[(k3 * n1 + k2) * n1 + m1];
+        t2[k] = s;
+    }
+    __syncthreads();
+    // term[m3][m2][m1] = sum_k3 M[2][k3][m3] t2[k3][m2][m1]
+    for (int k = threadIdx.x; k < np; k += kBlock) {
+        const int m12 = k % (n1 * n1), m3 = k / (n1 * n1);
+        double s = 0;
+        for (int k3 = 0; k3 < n1; ++k3) s += M[(2 * n1 + k3) * n1 + m3] * t2[k3 * n1 * n1 + m12];
+        term[(size_t)q * np + k] = s;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_adj_up_sum(CpLevels L, int lvl, int np,
+                                                       const double *term, double *What,
+                                                       float *Whatf)
+{
     const int q = blockIdx.x;
     const int I = q % L.cx[lvl], J = (q / L.cx[lvl]) % L.cy[lvl], K = q / (L.cx[lvl] * L.cy[lvl]);
+    const int cl = lvl - 1;
     const int id = cp_id(L, lvl, I, J, K);
-    double pbx[6];
-    cp_proxy_box(L, lvl, I, J, K, pbx);
-    for (int k = threadIdx.x; k < np; k += kBlock) acc[k] = 0.0;
-    for (int cz = 0; cz < 2; ++cz)
-        for (int cy = 0; cy < 2; ++cy)
-            for (int cx = 0; cx < 2; ++cx) {
-                const int ci = 2 * I + cx, cj = 2 * J + cy, ck = 2 * K + cz;
-                if (ci >= L.cx[lvl - 1] || cj >= L.cy[lvl - 1] || ck >= L.cz[lvl - 1]) continue;
-                const int cid = cp_id(L, lvl - 1, ci, cj, ck);
-                double cb[6];
-                cp_proxy_box(L, lvl - 1, ci, cj, ck, cb);
-                __syncthreads();
-                if (threadIdx.x < 3 * n1) {
-                    const int ax = threadIdx.x / n1, k = threadIdx.x % n1;
-                    lagrange_to(cheb_point(pick3(cb, ax), pick3(cb + 3, ax), k, deg), pick3(pbx, ax),
-                                pick3(pbx + 3, ax), deg, M + (ax * n1 + k) * n1, 1);
+    for (int k = threadIdx.x; k < np; k += kBlock) {
+        double s = 0;
+        for (int cz = 0; cz < 2; ++cz)
+            for (int cy = 0; cy < 2; ++cy)
+                for (int cx = 0; cx < 2; ++cx) {
+                    const int ci = 2 * I + cx, cj = 2 * J + cy, ck = 2 * K + cz;
+                    if (ci >= L.cx[cl] || cj >= L.cy[cl] || ck >= L.cz[cl]) continue;
+                    s += term[((size_t)(ck * L.cy[cl] + cj) * L.cx[cl] + ci) * np + k];
                 }
-                for (int k = threadIdx.x; k < np; k += kBlock) src[k] = What[(size_t)cid * np + k];
-                __syncthreads();
-                // t1[k3][k2][m1] = sum_k1 M[0][k1][m1] src[k3][k2][k1]
-                for (int k = threadIdx.x; k < np; k += kBlock) {
-                    const int m1 = k % n1, rest = k / n1;
-                    double s = 0;
-                    for (int k1 = 0; k1 < n1; ++k1) s += M[(0 * n1 + k1) * n1 + m1] * src[rest * n1 + k1];
-                    t1[k] = s;
-                }
-                __syncthreads();
-                // t2[k3][m2][m1] = sum_k2 M[1][k2][m2] t1[k3][k2][m1]
-                for (int k = threadIdx.x; k < np; k += kBlock) {
-                    const int m1 = k % n1, m2 = (k / n1) % n1, k3 = k / (n1 * n1);
-                    double s = 0;
-                    for (int k2 = 0; k2 < n1; ++k2) s += M[(1 * n1 + k2) * n1 + m2] * t1[(k3 * n1 + k2) * n1 + m1];
-                    t2[k] = s;
-                }
-                __syncthreads();
-                // What_P[m3][m2][m1] += sum_k3 M[2][k3][m3] t2[k3][m2][m1]
-                for (int k = threadIdx.x; k < np; k += kBlock) {
-                    const int m12 = k % (n1 * n1), m3 = k / (n1 * n1);
-                    double s = acc[k];
-                    for (int k3 = 0; k3 < n1; ++k3) s += M[(2 * n1 + k3) * n1 + m3] * t2[k3 * n1 * n1 + m12];
-                    acc[k] = s;
-                }
-            }
-    for (int k = threadIdx.x; k < np; k += kBlock) What[(size_t)id * np + k] = acc[k];
+        What[(size_t)id * np + k] = s;
+        Whatf[(size_t)id * np + k] = (float)s;
+    }
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -253,13 +267,31 @@ __device__ __forceinline__ int64_t adj_atom(const int *order, int64_t n)
     return pos < n ? order[pos] : -1;
 }
 
+// Absolute Chebyshev node coordinates of every cluster's proxy box:
+// nodes[id][axis][k], so the walk forms node - atom offsets with one FP64
+// subtraction each.
+__global__ __launch_bounds__(kBlock) void k_adj_nodes(CpLevels L, int deg, double *nodes)
+{
+    const int n1 = deg + 1;
+    const int ncl = L.off[L.T + 1];
+    for (int t = blockIdx.x * kBlock + threadIdx.x; t < ncl * 3 * n1; t += gridDim.x * kBlock) {
+        const int id = t / (3 * n1), r = t % (3 * n1), ax = r / n1, k = r % n1;
+        int lvl, I, J, K;
+        cp_decode(L, id, lvl, I, J, K);
+        double pb[6];
+        cp_proxy_box(L, lvl, I, J, K, pb);
+        nodes[t] = cheb_point(pb[ax], pb[3 + ax], k, deg);
+    }
+}
+
 struct AdjWalkArgs {
     CpLevels L;
     const float4 *rec;     // staged FP32 records, input order
     int stride_f4;
     int64_t n;
     int deg, np;
-    const double *What;
+    const float *Whatf;    // proxy weights rounded to FP32
+    const double *nodes;   // [cluster][3][n + 1] node coordinates
     const float *Wf;       // W on the grid (FP32)
     const int *order;      // spatial order of the atoms
     double *dxyz, *dq;
@@ -286,9 +318,9 @@ __device__ __forceinline__ void block_reduce_store(double (*part)[8], const doub
 __global__ __launch_bounds__(kBlock) void k_adj_walk(AdjWalkArgs a)
 {
     __shared__ long long stack[kAdjWaves][kStackPerWave];
-    __shared__ double cosk[kAdjMaxDegree + 1];
     __shared__ double part[kAdjWaves][8];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ float nodes[kAdjWaves][64];
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t atom = adj_atom(a.order, a.n);
     if (atom < 0) return;   // whole workgroup, before any barrier
     const CpLevels &L = a.L;
@@ -296,58 +328,79 @@ __global__ __launch_bounds__(kBlock) void k_adj_walk(AdjWalkArgs a)
     const float4 r1 = a.rec[(size_t)atom * a.stride_f4 + 1];
     const double y[3] = {(double)r0.x + r1.x, (double)r0.y + r1.y, (double)r0.z + r1.z};
     const int n1 = a.deg + 1;
-    if (threadIdx.x < n1) cosk[threadIdx.x] = cos(kPi * threadIdx.x / a.deg);
-    // digits of 64 and of the lane index in base n1 (proxy k = (k3 n1 + k2) n1 + k1)
-    const int c1 = 64 % n1, c2 = (64 / n1) % n1, c3 = 64 / (n1 * n1);
-    const int c1l = lane % n1, c2l = (lane / n1) % n1, c3l = lane / (n1 * n1);
-    __syncthreads();
+    // q / n1 for 0 <= q < n1^3 as (int)((q + 1/2) / n1) in FP32: the
+    // quotient's fractional part stays >= 1/(2 n1) away from an integer
+    const float rn1 = 1.f / (float)n1;
     double pot = 0, fx = 0, fy = 0, fz = 0;
     int item = 0;
 
     // accepted cluster: potential and field of its proxy weights at the atom
-    auto far_item = [&](int lvl, int I, int J, int K) {
+    auto far_item = [&](int cid) {
         if (item++ % kAdjWaves != wave) return;
-        double pb[6], cc[3], rr;
-        cp_proxy_box(L, lvl, I, J, K, pb);
-        cp_centre(L, lvl, I, J, K, cc, rr);
-        const double *Wh = a.What + (size_t)cp_id(L, lvl, I, J, K) * a.np;
-        // lane l < 3 (n+1) holds Chebyshev node l % (n+1) of axis l / (n+1),
-        // relative to the atom; other lanes read it by shuffle
-        float node = 0.f;
+        const float *Wh = a.Whatf + (size_t)cid * a.np;
+        // nd[l], l < 3 (n+1): Chebyshev node l % (n+1) of axis l / (n+1),
+        // relative to the atom, in the wave's LDS row (LDS reads, unlike
+        // shuffles, let the compiler unroll the loops below)
+        float *nd = nodes[wave];
+        __builtin_amdgcn_wave_barrier();
         if (lane < 3 * n1) {
-            const int ax = lane / n1, kk = lane % n1;
-            const double lo = pb[ax], hi = pb[3 + ax];
-            const float yc = (float)(y[ax] - cc[ax]);
-            node = (float)(lo + (hi - lo) * 0.5 * (1.0 + cosk[kk]) - cc[ax]) - yc;
+            const int ax = lane >= 2 * n1 ? 2 : (lane >= n1 ? 1 : 0);
+            nd[lane] = (float)(a.nodes[(size_t)cid * 3 * n1 + lane] - (ax == 0 ? y[0] : ax == 1 ? y[1] : y[2]));
         }
+        __builtin_amdgcn_wave_barrier();
+        // Lanes take (k1, k2) pairs, each running over k3, so dx, dy and
+        // their squares are formed once per pass; the weights of one k3 are
+        // consecutive.  With n1^2 > 64 every lane walks all k3 in step (dz
+        // is wave-uniform); below, several k3 share a pass.  Idle lanes run
+        // on a clamped index, so the loads of an unrolled stretch carry no
+        // lane mask and issue together; their sums are dropped.
+        const int P = n1 * n1;
+        if (P > 64) {
+            for (int pb = 0; pb < P; pb += 64) {
+                const int pair = pb + lane;
+                const bool act = pair < P;
+                const int pc = act ? pair : 0;
+                const int k2 = (int)(((float)pc + 0.5f) * rn1), k1 = pc - k2 * n1;
+                const float dx = nd[k1], dy = nd[n1 + k2];
+                const float dxy2 = fmaf(dx, dx, dy * dy);
+                const float *col = Wh + pc;
+                float p = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll 4
+                for (int k3 = 0; k3 < n1; ++k3) {
+                    const float dz = nd[2 * n1 + k3];
+                    const float ri = __builtin_amdgcn_rsqf(fmaf(dz, dz, dxy2));
+                    const float wr = col[k3 * P] * ri;
+                    const float wr3 = wr * ri * ri;
+                    p += wr;
+                    gx = fmaf(wr3, dx, gx);
+                    gy = fmaf(wr3, dy, gy);
+                    gz = fmaf(wr3, dz, gz);
+                }
+                if (act) { pot += p; fx += gx; fy += gy; fz += gz; }
+            }
+            return;
+        }
+        const int G = 64 / P;   // k3 values per pass
+        const int g = (int)(((float)lane + 0.5f) / (float)P), pair = lane - g * P;
+        const bool act = g < G;
+        const int k2 = (int)(((float)pair + 0.5f) * rn1), k1 = pair - k2 * n1;
+        const float dx = nd[k1], dy = nd[n1 + k2];
+        const float dxy2 = fmaf(dx, dx, dy * dy);
+        const float *col = Wh + pair;
         float p = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
-        int cnt = 0;
-        // lane's proxy (k1, k2, k3), stepped by 64 = c3 n1^2 + c2 n1 + c1
-        int k1 = c1l, k2 = c2l, k3 = c3l;
-        for (int k0 = 0; k0 < a.np; k0 += 64) {
-            const int k = k0 + lane;
-            const bool in = k < a.np;
-            const float dx = __shfl(node, k1);
-            const float dy = __shfl(node, n1 + k2);
-            const float dz = __shfl(node, 2 * n1 + (in ? k3 : 0));
-            k1 += c1; k2 += c2; k3 += c3;
-            if (k1 >= n1) { k1 -= n1; ++k2; }
-            if (k2 >= n1) { k2 -= n1; ++k3; }
-            if (in) {
-                const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                const float ri = __builtin_amdgcn_rsqf(d2);
-                const float wr = (float)Wh[k] * ri;
-                const float wr3 = wr * ri * ri;
-                p += wr;
-                gx = fmaf(wr3, dx, gx);
-                gy = fmaf(wr3, dy, gy);
-                gz = fmaf(wr3, dz, gz);
-            }
-            if (++cnt == 8) {
-                pot += p; fx += gx; fy += gy; fz += gz;
-                p = gx = gy = gz = 0.f;
-                cnt = 0;
-            }
+#pragma unroll 4
+        for (int k3b = 0; k3b < n1; k3b += G) {
+            const int k3 = min(k3b + g, n1 - 1);
+            const bool live = act && k3b + g < n1;
+            const float dz = nd[2 * n1 + k3];
+            const float w = col[k3 * P];
+            const float ri = live ? __builtin_amdgcn_rsqf(fmaf(dz, dz, dxy2)) : 0.f;
+            const float wr = w * ri;
+            const float wr3 = wr * ri * ri;
+            p += wr;
+            gx = fmaf(wr3, dx, gx);
+            gy = fmaf(wr3, dy, gy);
+            gz = fmaf(wr3, dz, gz);
         }
         pot += p; fx += gx; fy += gy; fz += gz;
     };
@@ -358,7 +411,63 @@ __global__ __launch_bounds__(kBlock) void k_adj_walk(AdjWalkArgs a)
         if (item++ % kAdjWaves != wave) return;
         const int i0 = I * L.B, j0 = J * L.B, k0 = K * L.B;
         const int ex = min(L.B, L.nx - i0), ey = min(L.B, L.ny - j0), ez = min(L.B, L.nz - k0);
-        const int npts = ex * ey * ez;
+        const int P = ex * ey;
+        if (P <= 64) {
+            // lanes take (x, y) columns of the block, several z per pass
+            // when the column count is below 64; unmasked loads as above
+            // small quotients in FP32 as in the far items
+            const int g = (int)(((float)lane + 0.5f) / (float)P), pair = lane - g * P;
+            const int G = (int)((64.5f) / (float)P);
+            const bool act = g < G;
+            const int lj = (int)(((float)pair + 0.5f) / (float)ex), li = pair - lj * ex;
+            const float dx = (float)fma((double)(i0 + li), L.h[0], -y[0]);
+            const float dy = (float)fma((double)(j0 + lj), L.h[1], -y[1]);
+            const float dxy2 = fmaf(dx, dx, dy * dy);
+            const int64_t plane = (int64_t)L.ny * L.nx;
+            const float *col = a.Wf + ((int64_t)k0 * L.ny + (j0 + lj)) * L.nx + (i0 + li);
+            float p = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+            if (G == 1) {
+                // 33 to 64 columns: every lane walks the block's z in step,
+                // dz from a per-wave LDS row
+                float *dzs = nodes[wave];
+                __builtin_amdgcn_wave_barrier();
+                if (lane < ez) dzs[lane] = (float)fma((double)(k0 + lane), L.h[2], -y[2]);
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll 4
+                for (int lk = 0; lk < ez; ++lk) {
+                    const float dz = dzs[lk];
+                    const float d2 = fmaf(dz, dz, dxy2);
+                    const float w = col[lk * plane];
+                    const float ri = d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
+                    const float wr = w * ri;
+                    const float wr3 = wr * ri * ri;
+                    p += wr;
+                    gx = fmaf(wr3, dx, gx);
+                    gy = fmaf(wr3, dy, gy);
+                    gz = fmaf(wr3, dz, gz);
+                }
+                if (act) { pot += p; fx += gx; fy += gy; fz += gz; }
+                return;
+            }
+#pragma unroll 4
+            for (int lkb = 0; lkb < ez; lkb += G) {
+                const int lk = min(lkb + g, ez - 1);
+                const bool live = act && lkb + g < ez;
+                const float dz = (float)fma((double)(k0 + lk), L.h[2], -y[2]);
+                const float w = col[lk * plane];
+                const float d2 = fmaf(dz, dz, dxy2);
+                const float ri = live && d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
+                const float wr = w * ri;
+                const float wr3 = wr * ri * ri;
+                p += wr;
+                gx = fmaf(wr3, dx, gx);
+                gy = fmaf(wr3, dy, gy);
+                gz = fmaf(wr3, dz, gz);
+            }
+            pot += p; fx += gx; fy += gy; fz += gz;
+            return;
+        }
+        const int npts = P * ez;
         float p = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
         int cnt = 0;
         // lane's point (li, lj, lk) of the block, stepped by 64 points
@@ -400,21 +509,31 @@ __global__ __launch_bounds__(kBlock) void k_adj_walk(AdjWalkArgs a)
     if (L.T == 0)
         direct_item(0, 0, 0);
     else if (cp_mac(L, L.T, 0, 0, 0, y))
-        far_item(L.T, 0, 0, 0);
+        far_item(cp_id(L, L.T, 0, 0, 0));
     else
         st[sp++] = enc(L.T, 0, 0, 0);
     __builtin_amdgcn_wave_barrier();
     while (sp > 0) {
         --sp;
-        const long long c = st[sp];
+        // every lane holds the same entry: make it scalar, so the walk's
+        // indices, CpLevels lookups and counters stay in SGPRs
+        const long long cv = st[sp];
+        const long long c =
+            ((long long)__builtin_amdgcn_readfirstlane((int)(cv >> 32)) << 32) |
+            (unsigned)__builtin_amdgcn_readfirstlane((int)cv);
         __builtin_amdgcn_wave_barrier();
         const int lvl = (int)(c >> 54), I = (int)((c >> 36) & 0x3ffff),
                   J = (int)((c >> 18) & 0x3ffff), K = (int)(c & 0x3ffff);
         const int cl = lvl - 1;
+        // the children's level extents and first id, read once as scalars
+        const int ncx = __builtin_amdgcn_readfirstlane(L.cx[cl]);
+        const int ncy = __builtin_amdgcn_readfirstlane(L.cy[cl]);
+        const int ncz = __builtin_amdgcn_readfirstlane(L.cz[cl]);
+        const int off = __builtin_amdgcn_readfirstlane(cl >= 1 ? L.off[cl] : 0);
         bool valid = false, acc = false;
         if (lane < 8) {
             const int ci = 2 * I + (lane & 1), cj = 2 * J + ((lane >> 1) & 1), ck = 2 * K + (lane >> 2);
-            valid = ci < L.cx[cl] && cj < L.cy[cl] && ck < L.cz[cl];
+            valid = ci < ncx && cj < ncy && ck < ncz;
             acc = valid && cl >= 1 && cp_mac(L, cl, ci, cj, ck, y);
         }
         const unsigned long long vm = __ballot(valid), am = __ballot(acc);
@@ -424,7 +543,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_walk(AdjWalkArgs a)
             if (cl == 0)
                 direct_item(ci, cj, ck);
             else if ((am >> ch) & 1)
-                far_item(cl, ci, cj, ck);
+                far_item(off + (ck * ncy + cj) * ncx + ci);
             else if (sp < kStackPerWave)
                 st[sp++] = enc(cl, ci, cj, ck);
         }
@@ -641,7 +760,7 @@ int adjoint_tree(const AdjointArgs &a, Workspace &ws, rism_stats &st, hipStream_
     RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const size_t shm_up1 = (3 * (size_t)(2 * B) * n1 + (size_t)(2 * B) * (2 * B) * n1 +
                             (size_t)(2 * B) * n1 * n1) * sizeof(double);
-    const size_t shm_up = (3 * (size_t)n1 * n1 + 4 * (size_t)np) * sizeof(double);
+    const size_t shm_up = (3 * (size_t)n1 * n1 + 3 * (size_t)np) * sizeof(double);
     if (std::max(shm_up1, shm_up) > (size_t)lds_max) {
         set_error("treecode backward: degree / batch edge too large for the LDS of this device");
         return RISM_E_UNSUPPORTED;
@@ -649,16 +768,25 @@ int adjoint_tree(const AdjointArgs &a, Workspace &ws, rism_stats &st, hipStream_
     double *W = ws.get<double>(a.g.m);
     float *Wf = ws.get<float>(a.g.m);
     double *What = ws.get<double>((size_t)(ncl + 1) * np);
+    float *Whatf = ws.get<float>((size_t)(ncl + 1) * np);
+    double *nodes = ws.get<double>((size_t)(ncl + 1) * 3 * n1);
+    // per-child terms of the upward pass, sized for the level-1 clusters
+    double *term = L.T >= 2 ? ws.get<double>((size_t)L.cx[1] * L.cy[1] * L.cz[1] * np) : nullptr;
     if (ws.status()) return ws.status();
     {
         PhaseTimer pt(ev, RISM_PHASE_UPWARD, s);
         hipLaunchKernelGGL(k_adj_w, 2048, kBlock, 0, s, a.w, a.w_f64, a.sp.ns, a.g.m, a.sp, a.kc, W, Wf);
         if (L.T >= 1) {
+            hipLaunchKernelGGL(k_adj_nodes, std::min((ncl * 3 * n1 + kBlock - 1) / kBlock, 1024),
+                               kBlock, 0, s, L, deg, nodes);
             hipLaunchKernelGGL(k_adj_up1, L.cx[1] * L.cy[1] * L.cz[1], kBlock, shm_up1, s, L, deg, W,
-                               What);
-            for (int lvl = 2; lvl <= L.T; ++lvl)
-                hipLaunchKernelGGL(k_adj_up, L.cx[lvl] * L.cy[lvl] * L.cz[lvl], kBlock, shm_up, s, L,
-                                   lvl, deg, What);
+                               What, Whatf);
+            for (int lvl = 2; lvl <= L.T; ++lvl) {
+                hipLaunchKernelGGL(k_adj_up_child, L.cx[lvl - 1] * L.cy[lvl - 1] * L.cz[lvl - 1],
+                                   kBlock, shm_up, s, L, lvl, deg, What, term);
+                hipLaunchKernelGGL(k_adj_up_sum, L.cx[lvl] * L.cy[lvl] * L.cz[lvl], kBlock, 0, s, L,
+                                   lvl, np, term, What, Whatf);
+            }
         }
     }
     RISM_HIP(hipGetLastError());
@@ -709,9 +837,10 @@ int adjoint_tree(const AdjointArgs &a, Workspace &ws, rism_stats &st, hipStream_
             wa.n = a.n;
             wa.deg = deg;
             wa.np = np;
-            wa.What = What;
+            wa.Whatf = Whatf;
             wa.Wf = Wf;
             wa.order = order;
+            wa.nodes = nodes;
             wa.dxyz = a.dxyz;
             wa.dq = a.dq;
             hipLaunchKernelGGL(k_adj_walk, nblk, kBlock, 0, s, wa);
