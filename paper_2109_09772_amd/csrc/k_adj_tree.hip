@@ -350,21 +350,21 @@ __global__ __launch_bounds__(kBlock) void k_adj_walk(AdjWalkArgs a)
         __builtin_amdgcn_wave_barrier();
         // Lanes take (k1, k2) pairs, each running over k3, so dx, dy and
         // their squares are formed once per pass; the weights of one k3 are
-        // consecutive.  With n1^2 > 64 every lane walks all k3 in step (dz
-        // is wave-uniform); below, several k3 share a pass.  Idle lanes run
-        // on a clamped index, so the loads of an unrolled stretch carry no
-        // lane mask and issue together; their sums are dropped.
+        // consecutive.  A pass of 64 pairs walks k3 in step (dz is
+        // wave-uniform); a last pass of r < 64 pairs runs 64 / r values of
+        // k3 side by side.  Idle lanes run on a clamped index, so the loads
+        // of an unrolled stretch carry no lane mask and issue together;
+        // their sums are dropped.
         const int P = n1 * n1;
-        if (P > 64) {
-            for (int pb = 0; pb < P; pb += 64) {
+        for (int pb = 0; pb < P; pb += 64) {
+            const int r = min(64, P - pb);
+            float p = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+            if (r == 64) {
                 const int pair = pb + lane;
-                const bool act = pair < P;
-                const int pc = act ? pair : 0;
-                const int k2 = (int)(((float)pc + 0.5f) * rn1), k1 = pc - k2 * n1;
+                const int k2 = (int)(((float)pair + 0.5f) * rn1), k1 = pair - k2 * n1;
                 const float dx = nd[k1], dy = nd[n1 + k2];
                 const float dxy2 = fmaf(dx, dx, dy * dy);
-                const float *col = Wh + pc;
-                float p = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+                const float *col = Wh + pair;
 #pragma unroll 4
                 for (int k3 = 0; k3 < n1; ++k3) {
                     const float dz = nd[2 * n1 + k3];
@@ -376,33 +376,34 @@ __global__ __launch_bounds__(kBlock) void k_adj_walk(AdjWalkArgs a)
                     gy = fmaf(wr3, dy, gy);
                     gz = fmaf(wr3, dz, gz);
                 }
-                if (act) { pot += p; fx += gx; fy += gy; fz += gz; }
+                pot += p; fx += gx; fy += gy; fz += gz;
+                continue;
             }
-            return;
-        }
-        const int G = 64 / P;   // k3 values per pass
-        const int g = (int)(((float)lane + 0.5f) / (float)P), pair = lane - g * P;
-        const bool act = g < G;
-        const int k2 = (int)(((float)pair + 0.5f) * rn1), k1 = pair - k2 * n1;
-        const float dx = nd[k1], dy = nd[n1 + k2];
-        const float dxy2 = fmaf(dx, dx, dy * dy);
-        const float *col = Wh + pair;
-        float p = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+            const int G = 64 / r;   // k3 values per pass (uniform)
+            const int g = (int)(((float)lane + 0.5f) / (float)r);
+            const int pair = pb + lane - g * r;
+            const bool act = g < G;
+            const int pc = act ? pair : pb;
+            const int k2 = (int)(((float)pc + 0.5f) * rn1), k1 = pc - k2 * n1;
+            const float dx = nd[k1], dy = nd[n1 + k2];
+            const float dxy2 = fmaf(dx, dx, dy * dy);
+            const float *col = Wh + pc;
 #pragma unroll 4
-        for (int k3b = 0; k3b < n1; k3b += G) {
-            const int k3 = min(k3b + g, n1 - 1);
-            const bool live = act && k3b + g < n1;
-            const float dz = nd[2 * n1 + k3];
-            const float w = col[k3 * P];
-            const float ri = live ? __builtin_amdgcn_rsqf(fmaf(dz, dz, dxy2)) : 0.f;
-            const float wr = w * ri;
-            const float wr3 = wr * ri * ri;
-            p += wr;
-            gx = fmaf(wr3, dx, gx);
-            gy = fmaf(wr3, dy, gy);
-            gz = fmaf(wr3, dz, gz);
+            for (int k3b = 0; k3b < n1; k3b += G) {
+                const int k3 = min(k3b + g, n1 - 1);
+                const bool live = act && k3b + g < n1;
+                const float dz = nd[2 * n1 + k3];
+                const float w = col[k3 * P];
+                const float ri = live ? __builtin_amdgcn_rsqf(fmaf(dz, dz, dxy2)) : 0.f;
+                const float wr = w * ri;
+                const float wr3 = wr * ri * ri;
+                p += wr;
+                gx = fmaf(wr3, dx, gx);
+                gy = fmaf(wr3, dy, gy);
+                gz = fmaf(wr3, dz, gz);
+            }
+            pot += p; fx += gx; fy += gy; fz += gz;
         }
-        pot += p; fx += gx; fy += gy; fz += gz;
     };
 
     // level-0 block reached unassigned: direct over its grid points, offsets
@@ -581,27 +582,35 @@ struct AdjLjArgs {
     int add_xyz;           // dxyz already holds the Coulomb part
 };
 
-// Grid points of one axis within r of the coordinate y: the closed index
-// range [lo, hi], empty when lo > hi.
-__device__ __forceinline__ void axis_range(double y, double r, double h, int n, int &lo, int &hi)
+// Fourth word of a raw (stride 0) buffer resource on gfx9-family GPUs.
+constexpr int kBufferWord3 = 0x00020000;
+
+// Grid points of one axis within r of the coordinate y (ih = 1 / spacing):
+// the closed index range [lo, hi], empty when lo > hi.  Products by 1/h may
+// misplace a point lying exactly at distance r; callers widen r so that such
+// points lie beyond every cut-off.
+__device__ __forceinline__ void axis_range(double y, double r, double ih, int n, int &lo, int &hi)
 {
-    lo = max((int)ceil((y - r) / h), 0);
-    hi = min((int)floor((y + r) / h), n - 1);
+    lo = max((int)ceil((y - r) * ih), 0);
+    hi = min((int)floor((y + r) * ih), n - 1);
 }
 
 // One workgroup per atom: the LJ adjoint over the grid points within the
-// atom's largest cut-off radius, per site masked by its own radius.  Wave w
-// takes the z planes w, w + kAdjWaves, ... of the cut-off box; in each plane
-// it visits the square bounding the sphere's section (2/3 of the box's
-// points).  Point offsets come from per-axis tables of FP64 differences
-// rounded once to FP32.
-template <int NS, bool W64>
+// atom's largest cut-off radius, per site masked by its own radius (UNI: one
+// radius for all pairs, a single test).  Wave w takes the z planes w,
+// w + kAdjWaves, ... of the cut-off box; in each plane it visits the square
+// bounding the sphere's section (2/3 of the box's points), 64 points per
+// step over a uniform step count: lanes past the end run on a clamped point
+// with a zero kernel, so no load carries a lane mask.  Point offsets come
+// from per-axis tables of FP64 differences rounded once to FP32.  Padded
+// sites (A = B = 0) read the last real site's plane and add zero.
+template <int NS, bool W64, bool UNI>
 __global__ __launch_bounds__(kBlock) void k_adj_lj(AdjLjArgs a)
 {
     extern __shared__ float offs[];    // [off_cap] x offsets, then y offsets
     __shared__ double part[kAdjWaves][8];
     __shared__ double part2[kAdjWaves][2 * NS];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t atom = adj_atom(a.order, a.n);
     if (atom < 0) return;   // whole workgroup, before any barrier
     const AtomF32<NS> &rc = static_cast<const AtomF32<NS> *>(a.rec)[atom];
@@ -610,10 +619,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_lj(AdjLjArgs a)
     // the sphere is widened by 1e-6 of its radius, far more than FP32
     // rounding of a distance, so that the per-site FP32 masks decide at the edge
     const double R = a.rcut_max * (1.0 + 1e-6);
+    const double ih[3] = {1.0 / g.h[0], 1.0 / g.h[1], 1.0 / g.h[2]};
     int lo[3], hi[3];
-    axis_range(y[0], R, g.h[0], g.nx, lo[0], hi[0]);
-    axis_range(y[1], R, g.h[1], g.ny, lo[1], hi[1]);
-    axis_range(y[2], R, g.h[2], g.nz, lo[2], hi[2]);
+    axis_range(y[0], R, ih[0], g.nx, lo[0], hi[0]);
+    axis_range(y[1], R, ih[1], g.ny, lo[1], hi[1]);
+    axis_range(y[2], R, ih[2], g.nz, lo[2], hi[2]);
     float *ox = offs, *oy = offs + a.off_cap;
     for (int t = threadIdx.x; t <= hi[0] - lo[0]; t += kBlock)
         ox[t] = (float)fma((double)(lo[0] + t), g.h[0], -y[0]);
@@ -621,12 +631,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_lj(AdjLjArgs a)
         oy[t] = (float)fma((double)(lo[1] + t), g.h[1], -y[1]);
     __syncthreads();
     float sg6[NS], e24[NS], rc2[NS];
+    const void *wp[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const float A = rc.A[s], B = rc.B[s];
         sg6[s] = B > 0.f ? A / B : 0.f;
         e24[s] = A > 0.f ? 6.f * B * B / A : 0.f;
         rc2[s] = rc.rc2[s];
+        const int64_t off = (int64_t)min(s, a.ns - 1) * g.m;
+        wp[s] = W64 ? (const void *)(static_cast<const double *>(a.w) + off)
+                    : (const void *)(static_cast<const float *>(a.w) + off);
     }
     double gx = 0, gy = 0, gz = 0, gE[NS], gS[NS];
 #pragma unroll
@@ -637,51 +651,64 @@ __global__ __launch_bounds__(kBlock) void k_adj_lj(AdjLjArgs a)
         if (r2p < 0) continue;
         const double half = sqrt(r2p);
         int ilo, ihi, jlo, jhi;
-        axis_range(y[0], half, g.h[0], g.nx, ilo, ihi);
-        axis_range(y[1], half, g.h[1], g.ny, jlo, jhi);
+        axis_range(y[0], half, ih[0], g.nx, ilo, ihi);
+        axis_range(y[1], half, ih[1], g.ny, jlo, jhi);
         ilo = max(ilo, lo[0]); ihi = min(ihi, hi[0]);
         jlo = max(jlo, lo[1]); jhi = min(jhi, hi[1]);
         if (ilo > ihi || jlo > jhi) continue;
-        const int ex = ihi - ilo + 1, npl = ex * (jhi - jlo + 1);
+        const int ex = ihi - ilo + 1, ey = jhi - jlo + 1, npl = ex * ey;
         const float dz = (float)dzd;
         const float dz2 = dz * dz;
-        const int64_t plane = (int64_t)gk * g.ny * g.nx;
-        // lane's (li, lj) within the plane's rectangle, stepped by 64 points
-        int li = lane % ex, lj = lane / ex;
-        const int qs = 64 / ex, rs = 64 % ex;
+        // per-site buffer resource (SGPRs) based at the rectangle's first
+        // point, covering the rest of the site's grid up to 2 GiB; points
+        // add a 32-bit byte offset, and a load past the range returns 0
+        const int64_t rect = ((int64_t)gk * g.ny + jlo) * g.nx + ilo;
+        constexpr int esz = W64 ? 8 : 4;
+        const int32_t nbytes = (int32_t)min((g.m - rect) * esz, (int64_t)0x7fffffff);
+        __amdgpu_buffer_rsrc_t rb[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            rb[s] = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<char *>(static_cast<const char *>(wp[s])) + rect * esz, 0, nbytes,
+                kBufferWord3);
+        const float *oxp = ox + (ilo - lo[0]), *oyp = oy + (jlo - lo[1]);
+        // lane's (li, lj) in the plane's rectangle, stepped by 64 points
+        // (quotients in FP32: (q + 1/2) / ex stays 1/(2 ex) off an integer)
+        const float rex = 1.f / (float)ex;
+        int lj = (int)(((float)lane + 0.5f) * rex), li = lane - lj * ex;
+        const int qs = (int)(64.5f * rex), rs = 64 - qs * ex;
+        const int nit = (npl + 63) >> 6;
         float fx = 0, fy = 0, fz = 0, fE[NS], fS[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) { fE[s] = 0; fS[s] = 0; }
         int cnt = 0;
-        // the next point's offsets and weights are loaded one step ahead
-        float ndx = 0.f, ndy = 0.f, nw[NS];
-        auto fetch = [&]() {
-            ndx = ox[ilo - lo[0] + li];
-            ndy = oy[jlo - lo[1] + lj];
-            const int64_t p = plane + (int64_t)(jlo + lj) * g.nx + (ilo + li);
-#pragma unroll
-            for (int s = 0; s < NS; ++s)
-                nw[s] = s < a.ns ? (W64 ? (float)static_cast<const double *>(a.w)[s * g.m + p]
-                                        : static_cast<const float *>(a.w)[s * g.m + p])
-                                 : 0.f;
+#pragma unroll 2
+        for (int it = 0; it < nit; ++it) {
+            const bool valid = lane + (it << 6) < npl;
+            const int ljc = min(lj, ey - 1);
+            const float dx = oxp[li], dy = oyp[ljc];
+            const int p = (ljc * g.nx + li) * esz;
             li += rs;
             lj += qs;
             if (li >= ex) { li -= ex; ++lj; }
-        };
-        if (lane < npl) fetch();
-        for (int t = lane; t < npl; t += 64) {
-            const float dx = ndx, dy = ndy;
             float wv[NS];
 #pragma unroll
-            for (int s = 0; s < NS; ++s) wv[s] = nw[s];
-            if (t + 64 < npl) fetch();
+            for (int s = 0; s < NS; ++s) {
+                if (W64) {
+                    const auto b = __builtin_amdgcn_raw_buffer_load_b64(rb[s], p, 0, 0);
+                    wv[s] = (float)__builtin_bit_cast(double, b);
+                } else {
+                    wv[s] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb[s], p, 0, 0));
+                }
+            }
             const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz2));
-            const float r2 = d2 > 0.f ? __builtin_amdgcn_rcpf(d2) : 0.f;
+            const bool ok = valid && d2 > 0.f && (!UNI || d2 < rc2[0]);
+            const float r2 = ok ? __builtin_amdgcn_rcpf(d2) : 0.f;
             const float r6 = r2 * r2 * r2;
             float Flj = 0.f;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                const float ws = d2 < rc2[s] ? wv[s] : 0.f;
+                const float ws = UNI || d2 < rc2[s] ? wv[s] : 0.f;
                 const float s6 = sg6[s] * r6;
                 const float ws6 = ws * s6;
                 const float v = ws6 * (s6 + s6 - 1.f);
@@ -802,6 +829,10 @@ int adjoint_tree(const AdjointArgs &a, Workspace &ws, rism_stats &st, hipStream_
     };
     const int off_cap = axis_cap(a.g.h[0], a.g.nx), off_cap_y = axis_cap(a.g.h[1], a.g.ny);
     const size_t shm_lj = (size_t)(off_cap + off_cap_y) * sizeof(float);
+    if ((int64_t)a.g.nx * a.g.ny >= (int64_t(1) << 28)) {
+        set_error("treecode backward: grid planes above 2^28 points");
+        return RISM_E_UNSUPPORTED;
+    }
     if ((a.dxyz || a.deps || a.dsig) && shm_lj + 4096 > (size_t)lds_max) {
         set_error("treecode backward: LJ cut-off box too wide for the LDS of this device");
         return RISM_E_UNSUPPORTED;
@@ -861,12 +892,14 @@ int adjoint_tree(const AdjointArgs &a, Workspace &ws, rism_stats &st, hipStream_
             la.deps = a.deps;
             la.dsig = a.dsig;
             la.add_xyz = 1;
+            const bool uni = a.opts->lj_tol <= 0 && a.opts->lj_cutoff > 0;
             auto launch = [&](auto ns_c) {
                 constexpr int NS = decltype(ns_c)::value;
+                auto go = [&](auto kern) { hipLaunchKernelGGL(kern, nblk, kBlock, shm_lj, s, la); };
                 if (a.w_f64)
-                    hipLaunchKernelGGL((k_adj_lj<NS, true>), nblk, kBlock, shm_lj, s, la);
+                    uni ? go(k_adj_lj<NS, true, true>) : go(k_adj_lj<NS, true, false>);
                 else
-                    hipLaunchKernelGGL((k_adj_lj<NS, false>), nblk, kBlock, shm_lj, s, la);
+                    uni ? go(k_adj_lj<NS, false, true>) : go(k_adj_lj<NS, false, false>);
             };
             switch (a.sp.ns_pad) {
             case 1: launch(std::integral_constant<int, 1>{}); break;

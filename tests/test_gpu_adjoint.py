@@ -121,14 +121,18 @@ def test_tree_adjoint_is_transpose_of_tree_forward(batch):
     assert abs(L_exact - L_tree) > 10 * abs(L_adj - L_tree)
 
 
-@pytest.mark.parametrize("method", ["treecode", "treecode_cp"])
-def test_tree_adjoint_vs_oracle(oracle, method):
+@pytest.mark.parametrize("method,dtype", [("treecode", "f32"), ("treecode_cp", "f32"),
+                                          ("treecode_cp", "f64")])
+def test_tree_adjoint_vs_oracle(oracle, method, dtype):
+    """Both treecodes' adjoints, with the upstream gradient in FP32 and (for
+    the cluster-particle one) in FP64."""
     wl, w = _grad_case(seed=4, n=60, dims=(37, 29, 23), spacing=0.4)
     wl.solute.xyz *= 2.0
     from paper_2109_09772_amd import api
     xyz, q, s, e = api.solute_to_device(wl.solute)
     o = _tree_opts(method=method)
-    wt = torch.as_tensor(w, device="cuda", dtype=torch.float32)
+    o.out_dtype = dtype
+    wt = torch.as_tensor(w, device="cuda", dtype=o.torch_dtype)
     dx, dq, de, ds = api.potential_backward(xyz, q, s, e, api.sites_from(wl.sites),
                                             api.grid_from(wl.grid), o, wt)
     sol, st, g = wl.solute, wl.sites, wl.grid
