@@ -516,6 +516,15 @@ def test_frequency_cutoff(oracle):
     for f, c_, lim in ((full[0], cut[0], 4.0), (full[1], cut[1], 3.0)):
         assert np.all(c_[:, kk > lim] == 0)
         np.testing.assert_array_equal(c_[:, kk <= lim], f[:, kk <= lim])
+    # the bound holds: every uncut entry at or beyond k_cut(tol) is below tol
+    qa = np.abs(sol.q).sum()
+    for tol in (1e-1, 1e-2):
+        kcc = oracle.kcut("c", tol, np.abs(st.q).max(), qa, KC, ETA, KAPPA, BETA, DIEL)
+        kch = oracle.kcut("h", tol, np.abs(st.q[st.ionic.astype(bool)]).max(), qa, KC, ETA,
+                          KAPPA, BETA, DIEL)
+        assert kcc < kk.max() and kch < kk.max()
+        assert np.abs(full[0][:, kk >= kcc]).max() <= tol
+        assert np.abs(full[1][:, kk >= kch]).max() <= tol
 
 
 def test_reciprocal_entries_agree_with_full_grid(oracle):
