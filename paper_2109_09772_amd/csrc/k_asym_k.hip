@@ -9,13 +9,9 @@
 // rounded to FP32 complex tables, and the sum over atoms is a separable
 // contraction:
 //   S[jz][jy][jx] = sum_a (Q_a ez[a][jz]) (ey[a][jy] ex[a][jx]).
-// A workgroup owns 256 consecutive (jy, jx) entries and kAkZ consecutive jz;
-// per atom a thread forms ey ex once (4 FP32 ops) and adds it, scaled by the
-// kAkZ wave-uniform Q ez factors (scalar loads), into its kAkZ accumulators
-// (4 ops each).  The (atom, jx) and (atom, jy) factors of a chunk of atoms
-// are staged in LDS (shared by the block's rows and columns).  FP32 partial
-// sums over a chunk are flushed into FP64.
-// Entries beyond the cut-off are written as zero without being summed.
+// The contraction is a complex matrix product per jy (or per jx) and runs on
+// the matrix cores (below).  Entries beyond the cut-off are written as zero;
+// whole tiles beyond it are not summed.
 #include <cmath>
 
 #include "pair.h"
@@ -24,8 +20,7 @@ namespace rism {
 
 namespace {
 
-constexpr int kAkThreads = 256;
-constexpr int kAkZ = 8;        // jz values per workgroup
+constexpr int kAkThreads = 256;   // phase tables and cut-offs
 
 __device__ __forceinline__ int freq_of(int j, int n)
 {
@@ -33,13 +28,14 @@ __device__ __forceinline__ int freq_of(int j, int n)
 }
 
 // Phase tables: for atom a, ex[a][0..nxh), ey[a][0..ny), ezq[a][0..nz) with
-// ez scaled by Q_a; FP64 phase and sincos, stored as (re, im) FP32.
+// ez scaled by Q_a; FP64 phase and sincos, stored as (re, im) FP32.  Rows
+// n .. npad - 1 are padding: ex = ey = 1, ezq = 0.
 __global__ __launch_bounds__(kAkThreads) void k_phase_tables(const double *xyz, const double *q,
-                                                             int64_t n, AkGrid g, float2 *ex,
-                                                             float2 *ey, float2 *ezq)
+                                                             int64_t n, int64_t npad, AkGrid g,
+                                                             float2 *ex, float2 *ey, float2 *ezq)
 {
     const int per = g.nxh + g.ny + g.nz;
-    const int64_t tot = n * per;
+    const int64_t tot = npad * per;
     for (int64_t t = blockIdx.x * (int64_t)kAkThreads + threadIdx.x; t < tot;
          t += (int64_t)gridDim.x * kAkThreads) {
         const int64_t a = t / per;
@@ -60,139 +56,241 @@ __global__ __launch_bounds__(kAkThreads) void k_phase_tables(const double *xyz, 
             f = freq_of(j, g.nz);
             nn = g.nz;
         }
-        const double k = 2.0 * kPi * f / (nn * g.h[ax]);
-        const double ph = k * (xyz[3 * a + ax] - g.o[ax]);
-        double sn, cs;
-        sincos(ph, &sn, &cs);
+        double sn = 0.0, cs = 1.0, qa = 0.0;
+        if (a < n) {
+            const double k = 2.0 * kPi * f / (nn * g.h[ax]);
+            const double ph = k * (xyz[3 * a + ax] - g.o[ax]);
+            sincos(ph, &sn, &cs);
+            qa = q[a];
+        }
         if (ax == 0) {
             ex[a * g.nxh + j] = make_float2((float)cs, (float)-sn);
         } else if (ax == 1) {
             ey[a * g.ny + j] = make_float2((float)cs, (float)-sn);
         } else {
-            ezq[a * g.nz + j] = make_float2((float)(q[a] * cs), (float)(-q[a] * sn));
+            ezq[a * g.nz + j] = make_float2((float)(qa * cs), (float)(-qa * sn));
         }
     }
 }
 
-struct Quad2 {
-    float x, y;
+// ------------------------------------------------------- matrix-core path
+// For each jy the structure factor is a complex matrix product over atoms,
+//   S[jz][jx] = sum_a Z[a][jz] T[a][jx],   Z = Q ez,  T = ey[a][jy] ex[a][jx],
+// run on v_mfma_f32_32x32x2_f32 with K = 2 holding the real and imaginary
+// parts of one atom's factors: A[i][k] = (Re, Im) Z[a][jz_i], and
+//   B = (Re T, -Im T) for Re S,   B = (Im T, Re T) for Im S.
+// A workgroup owns 32 MFMA columns, 4 rows (one per wave) and 64 jz (two
+// 32-row tiles per wave: four independent accumulator chains per wave).
+// Columns are 32 consecutive jx and rows are jy (YC = false: the full
+// 32-column tiles of the half grid), or columns are jy and rows the jx
+// past the last full tile (YC = true: the Nyquist column of an even nx, or
+// every jx of a half grid narrower than 32).  The phase factors of 32 atoms
+// at a time (the columns' and rows' ex / ey and the 64 jz's Q ez: 25 KB) are
+// staged in LDS, double buffered: the next 32 atoms are fetched into
+// registers while the matrix cores work on the current ones.  T is formed
+// per lane.  FP32 matrix sums over 32 atoms are flushed into FP64 registers.
+// The tables are padded to a multiple of 32 atoms with Q = 0, so no atom
+// needs a test; columns and rows past the grid run on clamped indices and
+// are not stored.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kMfCols = 32;    // MFMA columns per workgroup
+constexpr int kMfZ = 64;       // jz per workgroup
+constexpr int kMfWaves = 4;    // rows per workgroup, one per wave
+constexpr int kMfFlush = 32;   // atoms per LDS stage and per FP32 matrix sum
+constexpr int kMfThreads = 64 * kMfWaves;
+
+struct MfStage {
+    float2 c[kMfFlush][kMfCols];   // column factors
+    float z[kMfFlush][kMfZ][2];    // Q ez
+    float2 r[kMfFlush][kMfWaves];  // row factors
 };
 
-// LDS stage of one chunk of atoms: the ex factors of the block's jx values
-// (all of them when the row has at most kAkThreads entries, else one per
-// thread) and the ey factors of its rows.
-struct AkStage {
-    int xs, ys;   // entries per atom
-};
-__host__ __device__ inline AkStage ak_stage(int nxh)
+// Output of one half-grid entry from its structure factor (sr, si): the
+// Eq. 5 / Eq. 7 factors, the cut-offs, and S(0) = the FP64 net charge.
+__device__ void ak_store(const AkArgs &a, int jx, int jy, int jz, double sr, double si)
 {
-    AkStage st;
-    st.xs = nxh <= kAkThreads ? nxh : kAkThreads;
-    st.ys = (kAkThreads + nxh - 1) / nxh + 1;
-    return st;
-}
-
-__global__ __launch_bounds__(kAkThreads) void k_asym_k(AkArgs a)
-{
-    extern __shared__ float2 stage[];
     const AkGrid &g = a.g;
-    const AkStage st = ak_stage(g.nxh);
-    const int chunk = a.chunk;
-    float2 *sx = stage;                 // [chunk][xs]
-    float2 *sy = stage + chunk * st.xs; // [chunk][ys]
-    const int nxy = g.nxh * g.ny;
-    const int p0 = blockIdx.x * kAkThreads;
-    const int p = p0 + threadIdx.x;
-    const bool valid = p < nxy;
-    const int pc = valid ? p : p0;
-    const int jy = pc / g.nxh, jx = pc % g.nxh;
-    const int jy0 = p0 / g.nxh;
-    const int rows = (min(p0 + kAkThreads, nxy) - 1) / g.nxh - jy0 + 1;
-    const int xi = g.nxh <= kAkThreads ? jx : (int)threadIdx.x;   // column in sx
-    const int jz0 = blockIdx.y * kAkZ;
+    if (jx == 0 && jy == 0 && jz == 0) {
+        // k = 0: S is the net charge; its FP32 terms would leave ~1e-7 sum |Q|
+        sr = as_const(a.k2cut)[2];
+        si = 0.0;
+    }
     const double kx = 2.0 * kPi * jx / (g.nx * g.h[0]);
     const double ky = 2.0 * kPi * freq_of(jy, g.ny) / (g.ny * g.h[1]);
-    auto k2_of = [&](int z) {
-        const int jz = jz0 + z;
-        const double kz = 2.0 * kPi * freq_of(jz < g.nz ? jz : 0, g.nz) / (g.nz * g.h[2]);
-        return kx * kx + ky * ky + kz * kz;
-    };
+    const double kz = 2.0 * kPi * freq_of(jz, g.nz) / (g.nz * g.h[2]);
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    const double k2c = as_const(a.k2cut)[0], k2h = as_const(a.k2cut)[1];
+    const bool in_c = k2 > 0.0 && k2 <= k2c;
+    const bool in_h = k2 <= k2h && k2 + a.kappa2 > 0.0;   // h(0) at kappa = 0 is 0
+    const double gauss = exp(-k2 * a.eta2_4);
+    const double fc = in_c ? gauss / k2 : 0.0;
+    const double fh = in_h ? gauss / (k2 + a.kappa2) : 0.0;
+    const int64_t nxy = (int64_t)g.nxh * g.ny, mk = nxy * g.nz;
+    const int64_t e = (int64_t)jz * nxy + (int64_t)jy * g.nxh + jx;
+    if (a.c)
+        for (int s = 0; s < a.ns; ++s) {
+            const double f = a.c_scale[s] * fc;
+            store_val(a.c, a.f64, 2 * (s * mk + e), f * sr);
+            store_val(a.c, a.f64, 2 * (s * mk + e) + 1, f * si);
+        }
+    if (a.h)
+        for (int s = 0; s < a.n_ionic; ++s) {
+            const double f = a.h_scale[s] * fh;
+            store_val(a.h, a.f64, 2 * (s * mk + e), f * sr);
+            store_val(a.h, a.f64, 2 * (s * mk + e) + 1, f * si);
+        }
+}
+
+// A region: the jx in [x0, x0 + xw), every jy and jz; its entry idx =
+// (jz ny + jy) xw + jx - x0.  With ks > 1 the atoms are split into ks
+// contiguous groups of 32-atom chunks, one per workgroup layer, and each
+// layer writes its FP64 partial sums to part[layer][idx][re, im]; a second
+// kernel adds the layers in order.
+struct AkRegion {
+    int x0, xw, ks;
+    int64_t count;     // entries
+    double *part;      // [ks][count][2] when ks > 1
+};
+
+template <bool YC>
+__global__ __launch_bounds__(kMfThreads) void k_asym_k_mfma(AkArgs a, AkRegion rg)
+{
+    const int x0 = rg.x0;
+    __shared__ MfStage st[2];
+    const AkGrid &g = a.g;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, half = lane >> 5, col = lane & 31;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // columns c0 + col below clim, rows r0 + wave below rlim
+    const int c0 = blockIdx.x * kMfCols, clim = YC ? g.ny : g.nxh;
+    const int r0 = (YC ? x0 : 0) + blockIdx.y * kMfWaves, rlim = YC ? g.nxh : g.ny;
+    const float2 *ctab = YC ? a.ey : a.ex, *rtab = YC ? a.ex : a.ey;
+    const int cstride = YC ? g.ny : g.nxh, rstride = YC ? g.nxh : g.ny;
+    const int ci = c0 + col, ri = r0 + wave;
+    const int jx = YC ? ri : ci, jy = YC ? ci : ri;
+    const int zt = (g.nz + kMfZ - 1) / kMfZ;
+    const int layer = blockIdx.z / zt;
+    const int jz0 = (blockIdx.z % zt) * kMfZ;
+    const int nch_all = (int)((a.n + kMfFlush - 1) / kMfFlush);
+    const int cb = (int)((int64_t)layer * nch_all / rg.ks);
+    const int ce = (int)((int64_t)(layer + 1) * nch_all / rg.ks);
+    auto kx_of = [&](int x) { return 2.0 * kPi * x / (g.nx * g.h[0]); };
+    auto ky_of = [&](int y) { return 2.0 * kPi * freq_of(y, g.ny) / (g.ny * g.h[1]); };
+    auto kz_of = [&](int z) { return 2.0 * kPi * freq_of(z, g.nz) / (g.nz * g.h[2]); };
     const double k2c = as_const(a.k2cut)[0], k2h = as_const(a.k2cut)[1];
     const double k2max = k2c > k2h ? k2c : k2h;
-    bool any = false;
+    // smallest |k|^2 of the workgroup's tile: skip the sum beyond both cut-offs
+    // (kx grows with jx; the first column or row holds the smallest)
+    double ky2min = INFINITY, kz2min = INFINITY;
+    const int ylo = YC ? c0 : r0, yn = YC ? kMfCols : kMfWaves;
+    for (int y = ylo; y < ylo + yn && y < g.ny; ++y) ky2min = fmin(ky2min, ky_of(y) * ky_of(y));
+    for (int z = jz0; z < jz0 + kMfZ && z < g.nz; ++z) kz2min = fmin(kz2min, kz_of(z) * kz_of(z));
+    const double kx2min = kx_of(YC ? r0 : c0) * kx_of(YC ? r0 : c0);
+    const bool work = ce > cb && kx2min + ky2min + kz2min <= k2max;
+
+    // staging: thread tid carries 4 column, 8 Q ez and (tid < 128) 1 row value per stage
+    float2 rc[4], rz[8], rr = make_float2(0.f, 0.f);
+    auto fetch = [&](int64_t a0) {
 #pragma unroll
-    for (int z = 0; z < kAkZ; ++z) any |= valid && jz0 + z < g.nz && k2_of(z) <= k2max;
-    double Sr[kAkZ], Si[kAkZ];
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + u * kMfThreads, at = e / kMfCols, c = e % kMfCols;
+            rc[u] = ctab[(a0 + at) * cstride + min(c0 + c, clim - 1)];
+        }
 #pragma unroll
-    for (int z = 0; z < kAkZ; ++z) Sr[z] = Si[z] = 0.0;
-    if (__syncthreads_or(any)) {
-        ConstAS<Quad2> *ezq = as_const(reinterpret_cast<const Quad2 *>(a.ezq));
-        for (int64_t a0 = 0; a0 < a.n; a0 += chunk) {
-            const int cnt = (int)min((int64_t)chunk, a.n - a0);
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + u * kMfThreads, at = e / kMfZ, z = e % kMfZ;
+            rz[u] = a.ezq[(a0 + at) * g.nz + min(jz0 + z, g.nz - 1)];
+        }
+        if (tid < kMfFlush * kMfWaves) {
+            const int at = tid / kMfWaves, w = tid % kMfWaves;
+            rr = rtab[(a0 + at) * rstride + min(r0 + w, rlim - 1)];
+        }
+    };
+    auto stash = [&](MfStage &b) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + u * kMfThreads;
+            b.c[e / kMfCols][e % kMfCols] = rc[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + u * kMfThreads;
+            b.z[e / kMfZ][e % kMfZ][0] = rz[u].x;
+            b.z[e / kMfZ][e % kMfZ][1] = rz[u].y;
+        }
+        if (tid < kMfFlush * kMfWaves) b.r[tid / kMfWaves][tid % kMfWaves] = rr;
+    };
+
+    double Sr[2][16], Si[2][16];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Sr[t][r] = Si[t][r] = 0.0;
+    if (work) {
+        fetch((int64_t)cb * kMfFlush);
+        stash(st[0]);
+        __syncthreads();
+        for (int c = cb; c < ce; ++c) {
+            const MfStage &b = st[(c - cb) & 1];
+            if (c + 1 < ce) fetch((int64_t)(c + 1) * kMfFlush);
+            f32x16 accR0 = {}, accI0 = {}, accR1 = {}, accI1 = {};
+#pragma unroll 8
+            for (int i = 0; i < kMfFlush; ++i) {
+                const float2 X = b.c[i][col], Y = b.r[i][wave];
+                const float tr = fmaf(Y.x, X.x, -Y.y * X.y);
+                const float ti = fmaf(Y.x, X.y, Y.y * X.x);
+                const float bre = half ? -ti : tr, bim = half ? tr : ti;
+                const float za = b.z[i][col][half], zb = b.z[i][32 + col][half];
+                accR0 = __builtin_amdgcn_mfma_f32_32x32x2f32(za, bre, accR0, 0, 0, 0);
+                accI0 = __builtin_amdgcn_mfma_f32_32x32x2f32(za, bim, accI0, 0, 0, 0);
+                accR1 = __builtin_amdgcn_mfma_f32_32x32x2f32(zb, bre, accR1, 0, 0, 0);
+                accI1 = __builtin_amdgcn_mfma_f32_32x32x2f32(zb, bim, accI1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                Sr[0][r] += (double)accR0[r];
+                Si[0][r] += (double)accI0[r];
+                Sr[1][r] += (double)accR1[r];
+                Si[1][r] += (double)accI1[r];
+            }
+            if (c + 1 < ce) stash(st[(c + 1 - cb) & 1]);
             __syncthreads();
-            for (int t = threadIdx.x; t < cnt * st.xs; t += kAkThreads) {
-                const int at = t / st.xs, l = t % st.xs;
-                const int col = g.nxh <= kAkThreads ? l : min(p0 + l, nxy - 1) % g.nxh;
-                sx[at * st.xs + l] = a.ex[(a0 + at) * g.nxh + col];
-            }
-            for (int t = threadIdx.x; t < cnt * rows; t += kAkThreads) {
-                const int at = t / rows, r = t % rows;
-                sy[at * st.ys + r] = a.ey[(a0 + at) * g.ny + jy0 + r];
-            }
-            __syncthreads();
-            float pr[kAkZ], pi[kAkZ];
-#pragma unroll
-            for (int z = 0; z < kAkZ; ++z) pr[z] = pi[z] = 0.f;
-            for (int at = 0; at < cnt; ++at) {
-                const float2 vx = sx[at * st.xs + xi], vy = sy[at * st.ys + (jy - jy0)];
-                const float tr = fmaf(vy.x, vx.x, -vy.y * vx.y);
-                const float ti = fmaf(vy.x, vx.y, vy.y * vx.x);
-                ConstAS<Quad2> *ez = ezq + (a0 + at) * g.nz;
-#pragma unroll
-                for (int z = 0; z < kAkZ; ++z) {
-                    const int jz = jz0 + z < g.nz ? jz0 + z : g.nz - 1;   // in range; unused past nz
-                    const float wr = ez[jz].x, wi = ez[jz].y;
-                    pr[z] = fmaf(wr, tr, fmaf(-wi, ti, pr[z]));
-                    pi[z] = fmaf(wr, ti, fmaf(wi, tr, pi[z]));
-                }
-            }
-#pragma unroll
-            for (int z = 0; z < kAkZ; ++z) {
-                Sr[z] += (double)pr[z];
-                Si[z] += (double)pi[z];
-            }
         }
     }
-    if (!valid) return;
-    if (p == 0 && jz0 == 0) {
-        // k = 0: S is the net charge; its FP32 terms would leave ~1e-7 sum |Q|
-        Sr[0] = as_const(a.k2cut)[2];
-        Si[0] = 0.0;
-    }
-    const int64_t mk = (int64_t)nxy * g.nz;
+    if (ri >= rlim || ci >= clim) return;
+    // output: register r of this lane is row 8 (r / 4) + 4 half + r % 4 of
+    // the tile, column col
 #pragma unroll
-    for (int z = 0; z < kAkZ; ++z) {
-        const int jz = jz0 + z;
-        if (jz >= g.nz) continue;
-        const int64_t e = (int64_t)jz * nxy + p;
-        const double k2 = k2_of(z);
-        const bool in_c = k2 > 0.0 && k2 <= k2c;
-        const bool in_h = k2 <= k2h && k2 + a.kappa2 > 0.0;   // h(0) at kappa = 0 is 0, as c(0)
-        const double gauss = exp(-k2 * a.eta2_4);
-        const double fc = in_c ? gauss / k2 : 0.0;
-        const double fh = in_h ? gauss / (k2 + a.kappa2) : 0.0;
-        if (a.c)
-            for (int s = 0; s < a.ns; ++s) {
-                const double f = a.c_scale[s] * fc;
-                store_val(a.c, a.f64, 2 * (s * mk + e), f * Sr[z]);
-                store_val(a.c, a.f64, 2 * (s * mk + e) + 1, f * Si[z]);
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int jz = jz0 + 32 * t + 8 * (r / 4) + 4 * half + (r % 4);
+            if (jz >= g.nz) continue;
+            if (rg.ks == 1) {
+                ak_store(a, jx, jy, jz, Sr[t][r], Si[t][r]);
+            } else {
+                const int64_t idx = ((int64_t)jz * g.ny + jy) * rg.xw + (jx - rg.x0);
+                double *q = rg.part + 2 * (layer * rg.count + idx);
+                q[0] = Sr[t][r];
+                q[1] = Si[t][r];
             }
-        if (a.h)
-            for (int s = 0; s < a.n_ionic; ++s) {
-                const double f = a.h_scale[s] * fh;
-                store_val(a.h, a.f64, 2 * (s * mk + e), f * Sr[z]);
-                store_val(a.h, a.f64, 2 * (s * mk + e) + 1, f * Si[z]);
-            }
+        }
+}
+
+__global__ __launch_bounds__(kAkThreads) void k_ak_reduce(AkArgs a, AkRegion rg)
+{
+    for (int64_t idx = blockIdx.x * (int64_t)kAkThreads + threadIdx.x; idx < rg.count;
+         idx += (int64_t)gridDim.x * kAkThreads) {
+        double sr = 0.0, si = 0.0;
+        for (int l = 0; l < rg.ks; ++l) {
+            sr += rg.part[2 * (l * rg.count + idx)];
+            si += rg.part[2 * (l * rg.count + idx) + 1];
+        }
+        const int jx = rg.x0 + (int)(idx % rg.xw);
+        const int jy = (int)((idx / rg.xw) % a.g.ny);
+        const int jz = (int)(idx / ((int64_t)rg.xw * a.g.ny));
+        ak_store(a, jx, jy, jz, sr, si);
     }
 }
 
@@ -279,25 +377,60 @@ int launch_ak_cutoffs(const double *q, int64_t n, double tol, double pref_c, dou
     return RISM_OK;
 }
 
-int launch_asym_k(const AkArgs &a, const double *xyz, const double *q, float2 *ex, float2 *ey,
-                  float2 *ezq, hipStream_t s)
+int launch_asym_k(const AkArgs &a, const double *xyz, const double *q, Workspace &ws,
+                  hipStream_t s)
 {
-    const int64_t tot = a.n * (int64_t)(a.g.nxh + a.g.ny + a.g.nz);
-    if (tot > 0) {
+    // phase tables padded to a multiple of kMfFlush atoms (padding rows carry Q = 0)
+    const int64_t npad = (std::max<int64_t>(a.n, 1) + kMfFlush - 1) / kMfFlush * kMfFlush;
+    const int nch = (int)(npad / kMfFlush);
+    float2 *ex = ws.get<float2>((size_t)npad * a.g.nxh);
+    float2 *ey = ws.get<float2>((size_t)npad * a.g.ny);
+    float2 *ezq = ws.get<float2>((size_t)npad * a.g.nz);
+    // full 32-column jx tiles with jy rows; the remaining jx (the Nyquist
+    // column of an even nx) as rows against 32-column jy tiles.  A region
+    // with fewer waves than the chip holds twice over splits its atoms.
+    int cus = 0, dev = 0;
+    RISM_HIP(hipGetDevice(&dev));
+    RISM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int nxm = a.g.nxh / kMfCols * kMfCols, xw = a.g.nxh - nxm;
+    const int zt = (a.g.nz + kMfZ - 1) / kMfZ;
+    dim3 grids[2];
+    AkRegion rg[2];
+    for (int yc = 0; yc < 2; ++yc) {
+        const int w = yc ? xw : nxm;
+        rg[yc] = AkRegion{yc ? nxm : 0, w, 1, (int64_t)w * a.g.ny * a.g.nz, nullptr};
+        if (w == 0) continue;
+        grids[yc] = yc ? dim3((a.g.ny + kMfCols - 1) / kMfCols, (w + kMfWaves - 1) / kMfWaves, zt)
+                       : dim3(w / kMfCols, (a.g.ny + kMfWaves - 1) / kMfWaves, zt);
+        const int64_t waves = (int64_t)grids[yc].x * grids[yc].y * grids[yc].z * kMfWaves;
+        const int64_t want = (int64_t)8 * std::max(cus, 1);   // 2 waves per SIMD
+        rg[yc].ks = (int)std::max<int64_t>(1, std::min<int64_t>(nch, want / waves));
+        if (rg[yc].ks > 1) rg[yc].part = ws.get<double>((size_t)2 * rg[yc].ks * rg[yc].count);
+        grids[yc].z *= rg[yc].ks;
+    }
+    if (ws.status()) return ws.status();
+    {
+        const int64_t tot = npad * (int64_t)(a.g.nxh + a.g.ny + a.g.nz);
         const int blocks = (int)std::min<int64_t>((tot + kAkThreads - 1) / kAkThreads, 65536);
-        hipLaunchKernelGGL(k_phase_tables, blocks, kAkThreads, 0, s, xyz, q, a.n, a.g, ex, ey,
-                           ezq);
+        hipLaunchKernelGGL(k_phase_tables, blocks, kAkThreads, 0, s, xyz, q, a.n, npad, a.g, ex,
+                           ey, ezq);
     }
     AkArgs b = a;
     b.ex = ex;
     b.ey = ey;
     b.ezq = ezq;
-    const AkStage st = ak_stage(a.g.nxh);
-    const size_t per_atom = (size_t)(st.xs + st.ys) * sizeof(float2);
-    b.chunk = (int)std::max<size_t>(1, std::min<size_t>(64, (48 * 1024) / per_atom));
-    const int nxy = a.g.nxh * a.g.ny;
-    dim3 grid((nxy + kAkThreads - 1) / kAkThreads, (a.g.nz + kAkZ - 1) / kAkZ);
-    hipLaunchKernelGGL(k_asym_k, grid, kAkThreads, b.chunk * per_atom, s, b);
+    for (int yc = 0; yc < 2; ++yc) {
+        if (rg[yc].xw == 0) continue;
+        if (yc)
+            hipLaunchKernelGGL(k_asym_k_mfma<true>, grids[yc], kMfThreads, 0, s, b, rg[yc]);
+        else
+            hipLaunchKernelGGL(k_asym_k_mfma<false>, grids[yc], kMfThreads, 0, s, b, rg[yc]);
+        if (rg[yc].ks > 1) {
+            const int blocks =
+                (int)std::min<int64_t>((rg[yc].count + kAkThreads - 1) / kAkThreads, 8192);
+            hipLaunchKernelGGL(k_ak_reduce, blocks, kAkThreads, 0, s, b, rg[yc]);
+        }
+    }
     RISM_HIP(hipGetLastError());
     return RISM_OK;
 }

@@ -547,10 +547,6 @@ int rism_asymptotics_k(const rism_solute *so, const rism_sites *si, const rism_g
     int dev = 0;
     RISM_HIP(hipGetDevice(&dev));
     Workspace ws(dev, stream, op->max_workspace_bytes);
-    const int64_t nt = so->n > 0 ? so->n : 1;
-    float2 *ex = ws.get<float2>((size_t)nt * ak.g.nxh);
-    float2 *ey = ws.get<float2>((size_t)nt * ak.g.ny);
-    float2 *ez = ws.get<float2>((size_t)nt * ak.g.nz);
     double *k2cut = ws.get<double>(3);
     if (ws.status()) return ws.status();
     // the bound of Sec. 2.5 per unit sum |Q_a| (summed on the device)
@@ -560,7 +556,7 @@ int rism_asymptotics_k(const rism_solute *so, const rism_sites *si, const rism_g
     ak.k2cut = k2cut;
     {
         PhaseTimer pt(op->flags & RISM_FLAG_PHASE_EVENTS, RISM_PHASE_OTHER, s);
-        rc = launch_asym_k(ak, so->xyz, so->q, ex, ey, ez, s);
+        rc = launch_asym_k(ak, so->xyz, so->q, ws, s);
     }
     if (rc) return rc;
     rism_stats st{};

@@ -201,7 +201,6 @@ struct AkArgs {
     AkGrid g;
     int64_t n;
     const float2 *ex, *ey, *ezq;   // phase tables (set by launch_asym_k)
-    int chunk;                     // atoms per LDS round (set by launch_asym_k)
     const double *k2cut;           // device [3]: squared cut-offs of c and h, net charge
     double eta2_4, kappa2;
     void *c, *h;                   // [S][nz][ny][nxh][2], [n_ionic][...][2]
@@ -212,8 +211,9 @@ struct AkArgs {
 // Frequency cut-off of Sec. 2.5 (Newton's method, bracketed); 0 = none.
 __host__ __device__ double ak_kcut(bool for_h, double tol, double pref, double eta, double kappa,
                                    double diel);
-int launch_asym_k(const AkArgs &a, const double *xyz, const double *q, float2 *ex, float2 *ey,
-                  float2 *ezq, hipStream_t s);
+// Phase tables, matrix-core contraction and outputs; scratch from ws.
+int launch_asym_k(const AkArgs &a, const double *xyz, const double *q, Workspace &ws,
+                  hipStream_t s);
 // Squared cut-offs into k2cut[0..1] (INFINITY where tol <= 0 or nothing is
 // cut) and the net charge into k2cut[2]; pref_c / pref_h are the bounds'
 // prefactors without sum |Q_a|.

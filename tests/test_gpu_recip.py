@@ -42,9 +42,14 @@ def _rel(x, r):
 
 
 @pytest.mark.parametrize("dims,spacing,n", [((9, 8, 7), 0.6, 11), ((12, 10, 9), 0.45, 40),
-                                            ((33, 20, 17), 0.5, 70)])
+                                            ((33, 20, 17), 0.5, 70), ((66, 23, 37), 0.5, 45),
+                                            ((128, 9, 70), 0.4, 33)])
 @pytest.mark.parametrize("out_dtype", ["f32", "f64"])
 def test_small_grids_every_entry(oracle, dims, spacing, n, out_dtype):
+    """Every entry against the oracle.  Half-grid rows of 34 and 65 entries
+    exercise the matrix-core tiles (full 32-column tiles, partial 4-row and
+    64-jz tiles, atom counts padded to 32) and the vector kernel's column
+    window beside them; the smaller grids run on the vector kernel alone."""
     wl = W.tiny(n_atoms=n, dims=dims, seed=13, spacing=spacing)
     sol, st, g = wl.solute, wl.sites, wl.grid
     c, h = _gpu(wl, out_dtype=out_dtype)
