@@ -37,6 +37,8 @@ UNIT = "Gpair-interactions/s"
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 FP32_VALU_PEAK_TFLOPS = 157.3
 FP32_VALU_SINGLE_ISSUE_TFLOPS = 2 * VALU_LANE_OPS / 1e12   # 78.6
+# dense FP32 matrix-core (MFMA) peak, published: the same 157.3 TFLOP/s
+FP32_MFMA_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 ROOT_PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 
@@ -357,10 +359,26 @@ def main():
         torch.cuda.synchronize()
         tk = (time.perf_counter() - t0) / reps
         terms = n * shp[0] * shp[1] * (shp[2] // 2 + 1)
+        # the matrix-core kernel's own duration (HIP events on the call's stream):
+        # it sums the full 32-column tiles of the half grid, 8 flops per
+        # (atom, k-point) term (complex multiply-add as 4 FP32 MFMA products)
+        ok.phase_events = True
+        api.phase_times()
+        api.asymptotics_k(xyz, q, s, e, sites, grid, ok, eta, kap, beta, diel, tol=1e-6, outs=ck)
+        ph = api.phase_times()
+        ok.phase_events = False
+        nxm = (shp[2] // 2 + 1) // 32 * 32
+        mf_ms = ph["recip"][0] / ph["recip"][1]
+        mf_tf = 8.0 * n * nxm * shp[1] * shp[0] / (mf_ms * 1e-3) / 1e12
         result["asymptotics_k"] = {"time_s": tk, "tol": 1e-6,
                                    "gterm_per_s": terms / tk / 1e9,
                                    "note": "structure-factor terms (atom, k-point) per second "
-                                           "over the whole half grid"}
+                                           "over the whole half grid",
+                                   "roofline": {"kernel": "k_asym_k_mfma", "bound": "mfma",
+                                                "achieved": mf_tf, "peak": FP32_MFMA_PEAK_TFLOPS,
+                                                "unit": "TFLOP/s",
+                                                "frac": mf_tf / FP32_MFMA_PEAK_TFLOPS,
+                                                "kernel_ms": mf_ms}}
         del ck
 
     if not args.no_cpu_baseline:

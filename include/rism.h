@@ -88,7 +88,8 @@ extern "C" {
 #define RISM_PHASE_ADJOINT 8      /* adjoint pair kernels */
 #define RISM_PHASE_ADJ_REDUCE 9   /* adjoint partial-sum reduction */
 #define RISM_PHASE_OTHER 10
-#define RISM_NUM_PHASES 11
+#define RISM_PHASE_RECIP 11       /* reciprocal-space structure factor on the matrix cores */
+#define RISM_NUM_PHASES 12
 
 /* Regular grid (Sec. 2.1: u, c and h live on one 3-D grid). */
 typedef struct rism_grid {

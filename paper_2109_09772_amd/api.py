@@ -33,7 +33,7 @@ FLAG_PHASE_EVENTS = 2
 FLAG_STATS = 4
 MAX_SITES = 8
 PHASES = ["stage", "direct_f64", "direct_f32", "tree_build", "upward", "lists", "eval",
-          "downward", "adjoint", "adjoint_reduce", "other"]
+          "downward", "adjoint", "adjoint_reduce", "other", "recip"]
 
 
 class RismError(RuntimeError):

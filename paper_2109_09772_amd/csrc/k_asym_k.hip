@@ -377,7 +377,7 @@ int launch_ak_cutoffs(const double *q, int64_t n, double tol, double pref_c, dou
     return RISM_OK;
 }
 
-int launch_asym_k(const AkArgs &a, const double *xyz, const double *q, Workspace &ws,
+int launch_asym_k(const AkArgs &a, const double *xyz, const double *q, Workspace &ws, bool ev,
                   hipStream_t s)
 {
     // phase tables padded to a multiple of kMfFlush atoms (padding rows carry Q = 0)
@@ -410,6 +410,7 @@ int launch_asym_k(const AkArgs &a, const double *xyz, const double *q, Workspace
     }
     if (ws.status()) return ws.status();
     {
+        PhaseTimer pt(ev, RISM_PHASE_OTHER, s);
         const int64_t tot = npad * (int64_t)(a.g.nxh + a.g.ny + a.g.nz);
         const int blocks = (int)std::min<int64_t>((tot + kAkThreads - 1) / kAkThreads, 65536);
         hipLaunchKernelGGL(k_phase_tables, blocks, kAkThreads, 0, s, xyz, q, a.n, npad, a.g, ex,
@@ -421,11 +422,15 @@ int launch_asym_k(const AkArgs &a, const double *xyz, const double *q, Workspace
     b.ezq = ezq;
     for (int yc = 0; yc < 2; ++yc) {
         if (rg[yc].xw == 0) continue;
-        if (yc)
+        if (yc) {
+            PhaseTimer pt(ev, RISM_PHASE_OTHER, s);
             hipLaunchKernelGGL(k_asym_k_mfma<true>, grids[yc], kMfThreads, 0, s, b, rg[yc]);
-        else
+        } else {
+            PhaseTimer pt(ev, RISM_PHASE_RECIP, s);
             hipLaunchKernelGGL(k_asym_k_mfma<false>, grids[yc], kMfThreads, 0, s, b, rg[yc]);
+        }
         if (rg[yc].ks > 1) {
+            PhaseTimer pt(ev, RISM_PHASE_OTHER, s);
             const int blocks =
                 (int)std::min<int64_t>((rg[yc].count + kAkThreads - 1) / kAkThreads, 8192);
             hipLaunchKernelGGL(k_ak_reduce, blocks, kAkThreads, 0, s, b, rg[yc]);

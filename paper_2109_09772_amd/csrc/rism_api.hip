@@ -554,10 +554,7 @@ int rism_asymptotics_k(const rism_solute *so, const rism_sites *si, const rism_g
     if ((rc = launch_ak_cutoffs(so->q, so->n, tol, pre * qc, pre * qh, eta, kappa, diel, k2cut, s)))
         return rc;
     ak.k2cut = k2cut;
-    {
-        PhaseTimer pt(op->flags & RISM_FLAG_PHASE_EVENTS, RISM_PHASE_OTHER, s);
-        rc = launch_asym_k(ak, so->xyz, so->q, ws, s);
-    }
+    rc = launch_asym_k(ak, so->xyz, so->q, ws, op->flags & RISM_FLAG_PHASE_EVENTS, s);
     if (rc) return rc;
     rism_stats st{};
     st.pairs_direct = (double)so->n * ak.g.nxh * ak.g.ny * ak.g.nz;

@@ -212,7 +212,9 @@ struct AkArgs {
 __host__ __device__ double ak_kcut(bool for_h, double tol, double pref, double eta, double kappa,
                                    double diel);
 // Phase tables, matrix-core contraction and outputs; scratch from ws.
-int launch_asym_k(const AkArgs &a, const double *xyz, const double *q, Workspace &ws,
+// ev: record the phase events (RISM_PHASE_RECIP for the main matrix-core
+// kernel, RISM_PHASE_OTHER for the rest).
+int launch_asym_k(const AkArgs &a, const double *xyz, const double *q, Workspace &ws, bool ev,
                   hipStream_t s);
 // Squared cut-offs into k2cut[0..1] (INFINITY where tol <= 0 or nothing is
 // cut) and the net charge into k2cut[2]; pref_c / pref_h are the bounds'
