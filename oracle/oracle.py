@@ -64,6 +64,10 @@ def _load():
         lib.oracle_kcut.argtypes = [C.c_int, d, d, d, d, d, d, d, d]
         lib.oracle_kcut.restype = d
         lib.oracle_num_threads.restype = C.c_int
+        lib.oracle_taylor_coeffs.argtypes = [C.c_int, _P, C.c_int, d, d, _P]
+        lib.oracle_taylor_cp_points.argtypes = [i64, _P, _P, _P, _P, i32, _P, _P, _P, _PI, d,
+                                                _P, d, d, d, d, _P, _P, _PI, i32, d, i32, i64,
+                                                _PI, _P, _P, _P]
         _lib = lib
     return _lib
 
@@ -271,3 +275,45 @@ def backward_grid(xyz, q, sigma, eps, site_q, site_sigma, site_eps, origin, spac
     pts = grid_points(origin, spacing, dims)
     return backward_points(xyz, q, sigma, eps, site_q, site_sigma, site_eps, pts,
                            np.asarray(w).reshape(len(site_q), -1), kc, rcut_tab)
+
+
+TAYLOR_KINDS = {"coulomb": 0, "dcf": 1, "screened": 2}
+
+
+def taylor_coeffs(kind, v, p, eta=1.0, kappa=0.0):
+    """Order-p Taylor coefficients t[k3][k2][k1] = (1/k!) d^k phi/dx^k of the
+    kernel ``kind`` ('coulomb' 1/R, 'dcf' erf(R/eta)/R, 'screened'
+    2 exp(-kappa R)/R) at a centre x with v = y - x, by the paper's
+    recurrences (zero where |k| > p)."""
+    out = np.empty((p + 1, p + 1, p + 1))
+    vv = _d(np.asarray(v, dtype=np.float64).reshape(3))
+    rc = _load().oracle_taylor_coeffs(TAYLOR_KINDS[kind], _ptr(vv), int(p), float(eta),
+                                      float(kappa), _ptr(out))
+    assert rc == 0
+    return out
+
+
+def taylor_cp_points(xyz, q, sigma, eps, site_q, site_sigma, site_eps, ionic, origin,
+                     spacing, dims, ijk, kc, eta, kappa, beta, diel, batch_edge, theta, p,
+                     rcut_tab=None):
+    """The Taylor-recurrence cluster-particle treecode at grid points ijk
+    (npts, 3): u [S][npts], c [S][npts], h [n_ionic][npts]."""
+    lib = _load()
+    xyz, q, sigma, eps = _atoms(xyz, q, sigma, eps)
+    sq, ss, se = _d(site_q), _d(site_sigma), _d(site_eps)
+    ion = np.ascontiguousarray(ionic, dtype=np.int32)
+    o, h_ = _d(origin), _d(spacing)
+    dm = np.ascontiguousarray(dims, dtype=np.int32)
+    g = np.ascontiguousarray(np.asarray(ijk).reshape(-1, 3), dtype=np.int32)
+    rct = _d(rcut_tab)
+    u = np.empty((len(sq), len(g)))
+    c = np.empty((len(sq), len(g)))
+    h = np.empty((int(ion.sum()), len(g)))
+    rc = lib.oracle_taylor_cp_points(len(q), _ptr(xyz), _ptr(q), _ptr(sigma), _ptr(eps),
+                                     len(sq), _ptr(sq), _ptr(ss), _ptr(se), _ptr(ion, _PI),
+                                     float(kc), _ptr(rct), float(eta), float(kappa),
+                                     float(beta), float(diel), _ptr(o), _ptr(h_),
+                                     _ptr(dm, _PI), int(batch_edge), float(theta), int(p),
+                                     len(g), _ptr(g, _PI), _ptr(u), _ptr(c), _ptr(h))
+    assert rc == 0
+    return u, c, h

@@ -49,6 +49,11 @@
  *  - Backward: gradient of L = sum_gamma sum_r w_gamma(r) u_gamma(r) with
  *    respect to atom positions, charges, eps_a and sigma_a, differentiating
  *    the definition of u above term by term (the jump at r_cut is ignored).
+ *
+ * One part is not a direct sum: the Taylor-recurrence treecode at the end
+ * of the file (Secs. 2.3 and 2.4), an approximation whose steps are taken
+ * here in the paper's order, pair by pair, with no moments, shifts or
+ * blocking.
  */
 #include <math.h>
 #include <stdint.h>
@@ -463,4 +468,228 @@ int oracle_num_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------ Taylor-recurrence treecode */
+
+/*
+ * Taylor coefficients of a radial kernel phi(|x - y|) about a target centre
+ * x (Sec. 2.3.1, Eq. taylor_coefficients), times (-1)^|k|:
+ *   t_k = ((-1)^|k| / k!) d^k phi/dy^k = (1/k!) d^k phi/dx^k,
+ * so that phi(x', y) ~ sum_{|k| <= p} t_k (x' - x)^k.  In terms of v = y - x
+ * the paper's recurrences keep their printed form (odd orders flip sign
+ * together with x - y):
+ *  kind 0, 1/R (Sec. 2.3.2): for |k| >= 1
+ *    t_k = [(2 - 1/|k|) sum_i v_i t_{k-e_i} - (1 - 1/|k|) sum_i t_{k-2e_i}] / R^2;
+ *  kind 1, erf(R/eta)/R (Sec. 2.4.1): the same plus g_k / R^2, g the
+ *    coefficients of the auxiliary Gaussian, g_k = 2/(eta^2 |k|) [sum_i v_i
+ *    g_{k-e_i} - sum_i g_{k-2e_i}].  Reading: g_0 = -(eta/sqrt(pi))
+ *    exp(-R^2/eta^2); with the printed exp(-R^2/eta^2) alone the recurrence
+ *    does not reproduce the kernel's derivatives;
+ *  kind 2, 2 exp(-kappa R)/R (Sec. 2.4.2, the far-field form of the TCF
+ *    kernel): the 1/R form plus (kappa/|k|) [sum_i v_i b_{k-e_i} - sum_i
+ *    b_{k-2e_i}] / R^2, b the coefficients of 2 exp(-kappa R),
+ *    b_k = (kappa/|k|) [sum_i v_i t_{k-e_i} - sum_i t_{k-2e_i}].  Reading:
+ *    the printed factor kappa lacks the 1/|k| that the derivatives require.
+ * Components with a negative index are zero.  out: cube [(p+1)^3] with
+ * k = (k3 (p+1) + k2)(p+1) + k1, zero where |k| > p.
+ */
+static double tc_get(const double *t, int p, int k1, int k2, int k3)
+{
+    if (k1 < 0 || k2 < 0 || k3 < 0) return 0.0;
+    return t[((int64_t)k3 * (p + 1) + k2) * (p + 1) + k1];
+}
+
+static double tc_rec(const double *t, int p, int k1, int k2, int k3, const double v[3],
+                     double *second)
+{
+    /* sum_i v_i t_{k-e_i}, and sum_i t_{k-2e_i} into *second */
+    *second = tc_get(t, p, k1 - 2, k2, k3) + tc_get(t, p, k1, k2 - 2, k3) +
+              tc_get(t, p, k1, k2, k3 - 2);
+    return v[0] * tc_get(t, p, k1 - 1, k2, k3) + v[1] * tc_get(t, p, k1, k2 - 1, k3) +
+           v[2] * tc_get(t, p, k1, k2, k3 - 1);
+}
+
+int oracle_taylor_coeffs(int kind, const double v[3], int p, double eta, double kappa,
+                         double *out)
+{
+    if (p < 0 || p > 40 || kind < 0 || kind > 2) return -1;
+    const int n1 = p + 1;
+    const int64_t m = (int64_t)n1 * n1 * n1;
+    double *aux = calloc((size_t)m, sizeof(double));
+    if (!aux) return -1;
+    for (int64_t i = 0; i < m; ++i) out[i] = 0.0;
+    const double R2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const double R = sqrt(R2);
+    if (kind == 0) {
+        out[0] = 1.0 / R;
+    } else if (kind == 1) {
+        out[0] = erf(R / eta) / R;
+        aux[0] = -(eta / sqrt(ORACLE_PI)) * exp(-R2 / (eta * eta));
+    } else {
+        out[0] = 2.0 * exp(-kappa * R) / R;
+        aux[0] = 2.0 * exp(-kappa * R);
+    }
+    for (int d = 1; d <= p; ++d)
+        for (int k3 = 0; k3 <= d; ++k3)
+            for (int k2 = 0; k2 <= d - k3; ++k2) {
+                const int k1 = d - k3 - k2;
+                const int64_t idx = ((int64_t)k3 * n1 + k2) * n1 + k1;
+                double s2;
+                const double s1 = tc_rec(out, p, k1, k2, k3, v, &s2);
+                double t = (2.0 - 1.0 / d) * s1 - (1.0 - 1.0 / d) * s2;
+                if (kind == 1) {
+                    double g2;
+                    const double g1 = tc_rec(aux, p, k1, k2, k3, v, &g2);
+                    aux[idx] = 2.0 / (eta * eta * d) * (g1 - g2);
+                    t += aux[idx];
+                } else if (kind == 2) {
+                    double b2;
+                    const double b1 = tc_rec(aux, p, k1, k2, k3, v, &b2);
+                    t += kappa / d * (b1 - b2);
+                    /* b_k from the t of lower orders (already final) */
+                    aux[idx] = kappa / d * (s1 - s2);
+                }
+                out[idx] = t / R2;
+            }
+    free(aux);
+    return 0;
+}
+
+/* Order-p Taylor polynomial of kernel `kind` about centre c, for the atom at
+ * y, evaluated at x. */
+static double taylor_eval(int kind, const double c[3], const double y[3], const double x[3],
+                          int p, double eta, double kappa, double *coef)
+{
+    const double v[3] = {y[0] - c[0], y[1] - c[1], y[2] - c[2]};
+    oracle_taylor_coeffs(kind, v, p, eta, kappa, coef);
+    const int n1 = p + 1;
+    double s = 0.0;
+    for (int k3 = 0; k3 <= p; ++k3)
+        for (int k2 = 0; k2 <= p - k3; ++k2)
+            for (int k1 = 0; k1 <= p - k3 - k2; ++k1)
+                s += coef[((int64_t)k3 * n1 + k2) * n1 + k1] * pow(x[0] - c[0], k1) *
+                     pow(x[1] - c[1], k2) * pow(x[2] - c[2], k3);
+    return s;
+}
+
+/*
+ * The cluster-particle treecode of Sec. 2.3.1 with Taylor far fields, at
+ * listed grid points (ijk [npts][3] grid indices).  Target tree: cubes of
+ * B^3 grid points (level 0) merged 2 x 2 x 2 per level up to the level T
+ * whose single cluster covers the grid (a cubic octree; reading of the
+ * paper's splitting rule).  For a point x in level-0 block (I, J, K) and an
+ * atom y, the atom is taken in the far field of the coarsest ancestor
+ * cluster C (level >= 1) with r_C < theta |y - c_C|, r_C the half-diagonal
+ * of C's box of grid points and c_C its centre (reading of the garbled MAC),
+ * else directly.  Far fields are the order-p Taylor polynomials about c_C
+ * of 1/d (u's Coulomb term and the long-range part of c^lr) and of
+ * 2 exp(-kappa d)/d (h^lr's kernel at large d, Sec. 2.4.2); the remainders
+ * erf(d/eta)/d - 1/d and the Eq. 6 bracket / d - 2 exp(-kappa d)/d are added
+ * exactly where d < Rs = eta (5 + kappa eta/2), beyond which they are below
+ * 1e-12 relative (reading: an exact split of the smeared kernels in place
+ * of the erf-kernel expansion and the erfc asymptotics of Sec. 2.4).  LJ is
+ * exact within each pair's cut-off.  Outputs as oracle_potential_points and
+ * oracle_asymptotics_points: u [S][npts], c [S][npts], h [n_ionic][npts];
+ * any may be NULL.
+ */
+int oracle_taylor_cp_points(int64_t n, const double *xyz, const double *q,
+                            const double *sig, const double *eps, int32_t ns,
+                            const double *sq, const double *ssig, const double *seps,
+                            const int32_t *ionic, double kc, const double *rcut,
+                            double eta, double kappa, double beta, double diel,
+                            const double *origin, const double *spacing,
+                            const int32_t *dims, int32_t B, double theta, int32_t p,
+                            int64_t npts, const int32_t *ijk,
+                            double *u, double *c, double *h)
+{
+    if (n < 0 || ns <= 0 || npts < 0 || B <= 0 || p < 0 || p > 40 || !(theta > 0.0))
+        return -1;
+    int32_t maxdim = dims[0];
+    if (dims[1] > maxdim) maxdim = dims[1];
+    if (dims[2] > maxdim) maxdim = dims[2];
+    int T = 0;
+    while (((int64_t)B << T) < maxdim) ++T;
+    const double rs = eta * (5.0 + 0.5 * kappa * eta);
+    const int64_t ncoef = (int64_t)(p + 1) * (p + 1) * (p + 1);
+    int failed = 0;
+#pragma omp parallel
+    {
+        double *coef = malloc((size_t)ncoef * sizeof(double));
+        double *uacc = malloc((size_t)ns * sizeof(double));
+        if (!coef || !uacc) failed = 1;
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t i = 0; i < npts; ++i) {
+            if (!coef || !uacc) continue;
+            const int32_t *g = ijk + 3 * i;
+            const double x[3] = {origin[0] + g[0] * spacing[0], origin[1] + g[1] * spacing[1],
+                                 origin[2] + g[2] * spacing[2]};
+            double coul = 0.0, sc = 0.0, sh = 0.0;
+            int hit = 0;
+            for (int32_t s = 0; s < ns; ++s) uacc[s] = 0.0;
+            for (int64_t a = 0; a < n; ++a) {
+                const double *y = xyz + 3 * a;
+                const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+                const double d = sqrt(dx * dx + dy * dy + dz * dz);
+                /* coarsest ancestor cluster satisfying the MAC */
+                int acc = 0;
+                double cc[3] = {0, 0, 0};
+                for (int lvl = T; lvl >= 1 && !acc; --lvl) {
+                    const int64_t e = (int64_t)B << lvl;
+                    double r2 = 0.0, R2 = 0.0, ctr[3];
+                    for (int ax = 0; ax < 3; ++ax) {
+                        const int64_t lo = (g[ax] / e) * e;
+                        int64_t hi = lo + e - 1;
+                        if (hi > dims[ax] - 1) hi = dims[ax] - 1;
+                        const double xl = origin[ax] + lo * spacing[ax];
+                        const double xh = origin[ax] + hi * spacing[ax];
+                        ctr[ax] = 0.5 * (xl + xh);
+                        r2 += 0.25 * (xh - xl) * (xh - xl);
+                        R2 += (y[ax] - ctr[ax]) * (y[ax] - ctr[ax]);
+                    }
+                    if (r2 < theta * theta * R2) {
+                        acc = 1;
+                        for (int ax = 0; ax < 3; ++ax) cc[ax] = ctr[ax];
+                    }
+                }
+                if (acc) {
+                    coul += q[a] * taylor_eval(0, cc, y, x, p, eta, kappa, coef);
+                    sh += q[a] * taylor_eval(2, cc, y, x, p, eta, kappa, coef);
+                    if (d < rs) {
+                        sc += q[a] * (dcf_kernel(d, eta) - 1.0 / d);
+                        sh += q[a] * (tcf_kernel(d, eta, kappa) - 2.0 * exp(-kappa * d) / d);
+                    }
+                } else if (d == 0.0) {
+                    hit = 1;
+                    sc += q[a] * dcf_kernel(d, eta);
+                    sh += q[a] * tcf_kernel(d, eta, kappa);
+                } else {
+                    coul += q[a] / d;
+                    sc += q[a] * (dcf_kernel(d, eta) - 1.0 / d);
+                    sh += q[a] * tcf_kernel(d, eta, kappa);
+                }
+                if (d > 0.0)
+                    for (int32_t s = 0; s < ns; ++s) {
+                        double s_ga, e_ga;
+                        lb_mix(ssig[s], seps[s], sig[a], eps[a], &s_ga, &e_ga);
+                        if (rcut == NULL || d < rcut[(int64_t)s * n + a])
+                            uacc[s] += lj_pair(s_ga, e_ga, d);
+                    }
+            }
+            int32_t j = 0;
+            for (int32_t s = 0; s < ns; ++s) {
+                if (u) u[(int64_t)s * npts + i] = hit ? INFINITY : kc * sq[s] * coul + uacc[s];
+                if (c) c[(int64_t)s * npts + i] = -beta * kc * sq[s] * (coul + sc);
+                if (ionic[s]) {
+                    if (h)
+                        h[(int64_t)j * npts + i] = -beta * kc * sq[s] / (2.0 * diel) *
+                                                   exp(kappa * kappa * eta * eta / 4.0) * sh;
+                    ++j;
+                }
+            }
+        }
+        free(coef);
+        free(uacc);
+    }
+    return failed ? -1 : 0;
 }
