@@ -59,11 +59,17 @@ extern "C" {
  *                   batches of grid points as targets; LJ needs a cut-off.
  * RISM_TREECODE_CP  as RISM_TREECODE with the cluster-particle orientation of
  *                   the paper (Sec. 2.3): the tree is built on the grid
- *                   targets and atoms are interpolated into target clusters. */
+ *                   targets and atoms are interpolated into target clusters.
+ * RISM_TREECODE_TAYLOR  as RISM_TREECODE_CP with the paper's own far field:
+ *                   order-p Taylor polynomials of 1/d and exp(-kappa d)/d about
+ *                   the target clusters' centres, their coefficients from the
+ *                   recurrences of Secs. 2.3.2 and 2.4.2 (p = degree, 1..12);
+ *                   no adjoint (rism_potential_backward: RISM_E_UNSUPPORTED). */
 #define RISM_DIRECT_F64 0
 #define RISM_DIRECT_F32C 1
 #define RISM_TREECODE 2
 #define RISM_TREECODE_CP 3
+#define RISM_TREECODE_TAYLOR 4
 
 #define RISM_F32 0
 #define RISM_F64 1
@@ -122,7 +128,7 @@ typedef struct rism_sites {
 } rism_sites;
 
 typedef struct rism_opts {
-    int32_t method;        /* RISM_DIRECT_F64 / _F32C / RISM_TREECODE / _CP */
+    int32_t method;        /* RISM_DIRECT_F64 / _F32C / RISM_TREECODE / _CP / _TAYLOR */
     int32_t out_dtype;     /* RISM_F32 or RISM_F64 for every grid buffer */
     double coulomb_k;      /* k_C in kcal*A/(mol*e^2); default 332.0522173 */
     double lj_cutoff;      /* A; > 0: LJ pairs with d >= lj_cutoff are dropped

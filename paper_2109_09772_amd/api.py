@@ -26,7 +26,8 @@ RISM_E_NOMEM = -2
 RISM_E_HIP = -3
 RISM_E_UNSUPPORTED = -4
 
-METHODS = {"direct_f64": 0, "direct_f32c": 1, "treecode": 2, "treecode_cp": 3}
+METHODS = {"direct_f64": 0, "direct_f32c": 1, "treecode": 2, "treecode_cp": 3,
+           "treecode_taylor": 4}
 DTYPES = {"f32": 0, "f64": 1}
 FLAG_NO_DEVICE_CHECK = 1
 FLAG_PHASE_EVENTS = 2

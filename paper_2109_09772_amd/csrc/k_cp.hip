@@ -563,6 +563,7 @@ struct CpSweepArgs {
     const float4 *abuf;
     int degree, np;
     float yk;
+    double kappa;   // Taylor moments of the screened kernel
     double *part;   // [items][2][np]
     const uint32_t *n_items;
     const int *bad;
@@ -653,6 +654,130 @@ void launch_sweep(int nitems, int np, const CpSweepArgs &sa, hipStream_t s)
     }
 }
 
+// ----------------------------------------------------- Taylor far field
+// The paper's own far field (Secs. 2.3.1, 2.3.2, 2.4.2), as the method
+// RISM_TREECODE_TAYLOR: per target cluster the moments
+//   m_k = sum_atoms Q t_k(y - c),   |k| <= p,
+// of the order-p Taylor polynomials of 1/d and exp(-kappa d)/d about the
+// cluster centre c (the screened kernel's factor 2 is applied with h's other
+// terms), by the recurrences in terms of v = y - c:
+//   t_k = [(2 - 1/|k|) sum_i v_i t_{k-e_i} - (1 - 1/|k|) sum_i t_{k-2e_i}
+//          + (kappa/|k|)(sum_i v_i b_{k-e_i} - sum_i b_{k-2e_i})] / R^2,
+//   b_k = (kappa/|k|)(sum_i v_i t_{k-e_i} - sum_i t_{k-2e_i}),
+// the b terms for the screened kernel only, with t_0 = 1/R or
+// exp(-kappa R)/R and b_0 = exp(-kappa R).  The moments take the place of
+// the proxy values: the downward pass shifts them to the children's centres
+// and the leaves evaluate the polynomial at their points.
+//
+// One workgroup per work item; its atoms are dealt to the four waves.  A
+// wave runs one atom's recurrence degree by degree, a lane per coefficient
+// of the degree, with the coefficients in LDS in FP64 (tetrahedral layout:
+// degree d starts at d(d+1)(d+2)/6; within it, k = (k1, k2, k3) sits at
+// (d-k1)(d-k1+1)/2 + k3).  The wave's moments are in LDS too, each entry
+// owned by one lane; the four waves' moments are added in wave order into
+// the item's partial, in the cube layout [(p+1)^3] of the proxy values
+// (zero above order p).
+constexpr int kMaxTaylor = 12;
+
+__host__ __device__ inline int tet_off(int d) { return d * (d + 1) * (d + 2) / 6; }
+
+inline size_t cp_taylor_lds(int p, bool asym)
+{
+    return (size_t)(kBlock / 64) * (asym ? 5 : 2) * tet_off(p + 1) * sizeof(double);
+}
+
+template <bool ASYM>
+__global__ __launch_bounds__(kBlock) void k_cp_taylor(CpSweepArgs a)
+{
+    extern __shared__ double sm[];
+    if (*a.bad || (int)blockIdx.x >= (int)*a.n_items) return;   // whole workgroup
+    const int item = as_const(a.order)[blockIdx.x];
+    const int n = (int)as_const(a.it_n)[item];
+    ConstAS<Quad> *at = as_const(reinterpret_cast<const Quad *>(a.abuf + as_const(a.it_slot)[item]));
+    const int p = a.degree, n1 = p + 1, nt = tet_off(p + 1);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr int NA = ASYM ? 5 : 2;   // per wave: tC, mC [, tS, bS, mS]
+    double *tC = sm + (size_t)wave * NA * nt, *mC = tC + nt;
+    double *tS = tC + 2 * nt, *bS = tC + 3 * nt, *mS = tC + 4 * nt;
+    for (int i = lane; i < nt; i += 64) {
+        mC[i] = 0.0;
+        if (ASYM) mS[i] = 0.0;
+    }
+    const double kap = a.kappa;
+    for (int s = wave; s < n; s += kBlock / 64) {
+        ConstAS<Quad> &av = at[s];
+        const double v[3] = {av.x, av.y, av.z}, q = av.w;
+        const double R2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        const double R = sqrt(R2), iR2 = 1.0 / R2;
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+            tC[0] = 1.0 / R;
+            mC[0] += q * tC[0];
+            if (ASYM) {
+                const double e = exp(-kap * R);
+                tS[0] = e / R;
+                bS[0] = e;
+                mS[0] += q * tS[0];
+            }
+        }
+        for (int d = 1; d <= p; ++d) {
+            __builtin_amdgcn_wave_barrier();   // degree d - 1 written by every lane
+            const int Ld = (d + 1) * (d + 2) / 2;
+            const int o0 = tet_off(d), o1 = tet_off(d - 1), o2 = d >= 2 ? tet_off(d - 2) : 0;
+            const double c1 = 2.0 - 1.0 / d, c2 = 1.0 - 1.0 / d, kd = kap / d;
+            for (int pos = lane; pos < Ld; pos += 64) {
+                // pos = m(m+1)/2 + k3 with m = d - k1
+                int m = (int)((sqrtf(8.f * pos + 1.f) - 1.f) * 0.5f);
+                m -= m * (m + 1) / 2 > pos;
+                m += (m + 1) * (m + 2) / 2 <= pos;
+                const int k3 = pos - m * (m + 1) / 2, k1 = d - m, k2 = m - k3;
+                const int T1 = m >= 1 ? (m - 1) * m / 2 : 0, T2 = m >= 2 ? (m - 2) * (m - 1) / 2 : 0;
+                // sum_i v_i f_{k-e_i} and sum_i f_{k-2e_i} over one coefficient array
+                auto sums = [&](const double *f, double &s2) {
+                    double s1 = 0.0;
+                    s2 = 0.0;
+                    if (k1 >= 1) s1 += v[0] * f[o1 + pos];
+                    if (k2 >= 1) s1 += v[1] * f[o1 + T1 + k3];
+                    if (k3 >= 1) s1 += v[2] * f[o1 + T1 + k3 - 1];
+                    if (k1 >= 2) s2 += f[o2 + pos];
+                    if (k2 >= 2) s2 += f[o2 + T2 + k3];
+                    if (k3 >= 2) s2 += f[o2 + T2 + k3 - 2];
+                    return s1;
+                };
+                double s2;
+                const double s1 = sums(tC, s2);
+                const double tc = (c1 * s1 - c2 * s2) * iR2;
+                tC[o0 + pos] = tc;
+                mC[o0 + pos] += q * tc;
+                if (ASYM) {
+                    double a2, b2;
+                    const double a1 = sums(tS, a2), b1 = sums(bS, b2);
+                    const double ts = (c1 * a1 - c2 * a2 + kd * (b1 - b2)) * iR2;
+                    tS[o0 + pos] = ts;
+                    bS[o0 + pos] = kd * (a1 - a2);
+                    mS[o0 + pos] += q * ts;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    double *out = a.part + (size_t)item * 2 * a.np;
+    for (int k = threadIdx.x; k < a.np; k += kBlock) {
+        const int k1 = k % n1, k2 = (k / n1) % n1, k3 = k / (n1 * n1), d = k1 + k2 + k3;
+        double sc = 0.0, ss = 0.0;
+        if (d <= p) {
+            const int idx = tet_off(d) + (d - k1) * (d - k1 + 1) / 2 + k3;
+            for (int w = 0; w < kBlock / 64; ++w) {
+                sc += sm[(size_t)w * NA * nt + nt + idx];
+                if (ASYM) ss += sm[(size_t)w * NA * nt + 4 * nt + idx];
+            }
+        }
+        out[k] = sc;
+        out[a.np + k] = ss;
+    }
+}
+
 // V[cl] = sum of the partials of its items, in item order.
 __global__ __launch_bounds__(kBlock) void k_cp_reduce(int nclusters, int np, const uint32_t *item_off,
                                                       const int *bad, const double *part, double *V)
@@ -672,7 +797,11 @@ __global__ __launch_bounds__(kBlock) void k_cp_reduce(int nclusters, int np, con
 // Children at level lvl: V[child] += (Mx (x) My (x) Mz) V[parent], with
 // M[k][m] = L^P_m(s^C_k): the parent's interpolant evaluated at the child's
 // proxy points, separably, in FP64.
-__global__ __launch_bounds__(kBlock) void k_cp_down(CpLevels L, int lvl, int degree, double *V)
+// Taylor moments (taylor != 0): M[k][m] = C(m, k) delta^(m - k) for m >= k,
+// delta = child centre - parent centre: the parent's polynomial re-expanded
+// about the child's centre, again separably.
+__global__ __launch_bounds__(kBlock) void k_cp_down(CpLevels L, int lvl, int degree, int taylor,
+                                                    double *V)
 {
     extern __shared__ double sm[];
     const int n1 = degree + 1, np = n1 * n1 * n1;
@@ -689,8 +818,22 @@ __global__ __launch_bounds__(kBlock) void k_cp_down(CpLevels L, int lvl, int deg
     cp_proxy_box(L, lvl + 1, I >> 1, J >> 1, K >> 1, pbx);
     if (threadIdx.x < 3 * n1) {
         const int ax = threadIdx.x / n1, k = threadIdx.x % n1;
-        lagrange_to(cheb_point(pick3(cb, ax), pick3(cb + 3, ax), k, degree), pick3(pbx, ax),
-                    pick3(pbx + 3, ax), degree, M + (ax * n1 + k) * n1, 1);
+        if (taylor) {
+            double cc[3], cp[3], rr;
+            cp_centre(L, lvl, I, J, K, cc, rr);
+            cp_centre(L, lvl + 1, I >> 1, J >> 1, K >> 1, cp, rr);
+            const double dl = pick3(cc, ax) - pick3(cp, ax);
+            double *row = M + (ax * n1 + k) * n1;
+            for (int m = 0; m < k; ++m) row[m] = 0.0;
+            double c = 1.0;   // C(m, k) dl^(m - k), m = k, k + 1, ...
+            for (int m = k; m < n1; ++m) {
+                row[m] = c;
+                c = c * dl * (double)(m + 1) / (double)(m + 1 - k);
+            }
+        } else {
+            lagrange_to(cheb_point(pick3(cb, ax), pick3(cb + 3, ax), k, degree), pick3(pbx, ax),
+                        pick3(pbx + 3, ax), degree, M + (ax * n1 + k) * n1, 1);
+        }
     }
     for (int comp = 0; comp < 2; ++comp) {
         __syncthreads();
@@ -733,8 +876,9 @@ struct CpLeafArgs {
     const uint32_t *nd, *ns;
     const int *order;          // block -> level-0 block, heaviest first
     const int *bad;            // lists sized too small: do nothing
-    const double *V;           // proxy values of level >= 1 clusters
+    const double *V;           // proxy values (Taylor: moments) of level >= 1 clusters
     int degree, np;
+    int taylor;                // basis: Lagrange (0) or monomials about the centre (1)
     unsigned long long *work;  // optional: [0] direct pairs, [1] short-range pairs
 };
 
@@ -814,14 +958,23 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
 
     // ------------------------------- far: first two contractions, per block
     if (L.T >= 1) {
-        double pb[6];
+        double pb[6], cc[3], rr;
         cp_proxy_box(L, 1, I >> 1, J >> 1, K >> 1, pb);
-        // level-1 ancestor basis tables: L_k(coordinate of the block's points)
+        cp_centre(L, 1, I >> 1, J >> 1, K >> 1, cc, rr);
+        // level-1 ancestor basis tables at the block's point coordinates:
+        // L_k(x), or (x - c)^k for Taylor moments
         for (int t = threadIdx.x; t < 3 * B; t += NT) {
             const int ax = t / B, l = t % B;
             const int b0 = ax == 0 ? i0 : (ax == 1 ? j0 : k0);
-            lagrange_to((b0 + l) * pick3(g.h, ax), pick3(pb, ax), pick3(pb + 3, ax), a.degree,
-                        Lb + (ax * B + l) * n1, 1);
+            double *row = Lb + (ax * B + l) * n1;
+            if (a.taylor) {
+                const double dx = (b0 + l) * pick3(g.h, ax) - pick3(cc, ax);
+                double pw = 1.0;
+                for (int k = 0; k < n1; ++k, pw *= dx) row[k] = pw;
+            } else {
+                lagrange_to((b0 + l) * pick3(g.h, ax), pick3(pb, ax), pick3(pb + 3, ax), a.degree,
+                            row, 1);
+            }
         }
         const int a1 = cp_id(L, 1, I >> 1, J >> 1, K >> 1);
         for (int comp = 0; comp < NCOMP; ++comp) {
@@ -1075,6 +1228,11 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     RISM_HIP(hipGetDevice(&dev));
     RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const size_t leaf_shm = cp_leaf_lds(B, deg, a.asym_on);
+    const bool taylor = a.opts->method == RISM_TREECODE_TAYLOR;
+    if (taylor && (deg > kMaxTaylor || cp_taylor_lds(deg, a.asym_on) > (size_t)lds_max)) {
+        set_error("Taylor treecode: order above 12 or its LDS beyond this device");
+        return RISM_E_UNSUPPORTED;
+    }
     if (leaf_shm + 2048 > (size_t)lds_max) {
         set_error("treecode_cp: degree / batch edge too large for the LDS of this device");
         return RISM_E_UNSUPPORTED;
@@ -1183,11 +1341,21 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
                 sa.degree = deg;
                 sa.np = np;
                 sa.yk = (float)a.asym.yk;
+                sa.kappa = a.asym.kappa;
                 sa.part = part;
                 sa.n_items = tot + 1;
                 sa.bad = bad;
-                if (a.asym_on) launch_sweep<true>((int)cap.c[1], np, sa, s);
-                else launch_sweep<false>((int)cap.c[1], np, sa, s);
+                if (taylor) {
+                    const size_t tshm = cp_taylor_lds(deg, a.asym_on);
+                    if (a.asym_on)
+                        hipLaunchKernelGGL(k_cp_taylor<true>, (int)cap.c[1], kBlock, tshm, s, sa);
+                    else
+                        hipLaunchKernelGGL(k_cp_taylor<false>, (int)cap.c[1], kBlock, tshm, s, sa);
+                } else if (a.asym_on) {
+                    launch_sweep<true>((int)cap.c[1], np, sa, s);
+                } else {
+                    launch_sweep<false>((int)cap.c[1], np, sa, s);
+                }
             }
         }
         if (ncl > 0) {
@@ -1197,7 +1365,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             const size_t shm = (3 * (size_t)n1 * n1 + 3 * (size_t)np) * sizeof(double);
             for (int lvl = L.T - 1; lvl >= 1; --lvl)
                 hipLaunchKernelGGL(k_cp_down, L.cx[lvl] * L.cy[lvl] * L.cz[lvl], kBlock, shm, s,
-                                   L, lvl, deg, V);
+                                   L, lvl, deg, (int)taylor, V);
         }
         RISM_HIP(hipGetLastError());
 
@@ -1218,6 +1386,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         la.V = V;
         la.degree = deg;
         la.np = np;
+        la.taylor = taylor;
         la.work = work;
         {
             PhaseTimer pl(ev, RISM_PHASE_LISTS, s);

@@ -171,7 +171,7 @@ static int check_common(const rism_solute *so, const rism_sites *si, const rism_
     if (!finite3(gr->origin)) return fail(RISM_E_INVALID, "grid origin must be finite");
     if ((double)gr->dims[0] * gr->dims[1] * gr->dims[2] > 4.0e9)
         return fail(RISM_E_INVALID, "grid too large (> 4e9 points)");
-    if (op->method < RISM_DIRECT_F64 || op->method > RISM_TREECODE_CP)
+    if (op->method < RISM_DIRECT_F64 || op->method > RISM_TREECODE_TAYLOR)
         return fail(RISM_E_INVALID, "unknown method");
     if (op->out_dtype != RISM_F32 && op->out_dtype != RISM_F64)
         return fail(RISM_E_INVALID, "out_dtype must be RISM_F32 or RISM_F64");
@@ -181,6 +181,8 @@ static int check_common(const rism_solute *so, const rism_sites *si, const rism_
     if (op->method >= RISM_TREECODE) {
         if (!(op->theta > 0 && op->theta < 1)) return fail(RISM_E_INVALID, "theta must be in (0,1)");
         if (op->degree < 1 || op->degree > 16) return fail(RISM_E_INVALID, "degree must be in 1..16");
+        if (op->method == RISM_TREECODE_TAYLOR && op->degree > 12)
+            return fail(RISM_E_INVALID, "Taylor order (degree) must be in 1..12");
         if (op->leaf_size < 1) return fail(RISM_E_INVALID, "leaf_size must be >= 1");
         if (op->batch_edge != 4 && op->batch_edge != 8 && op->batch_edge != 16)
             return fail(RISM_E_INVALID, "batch_edge must be 4, 8 or 16");
@@ -579,6 +581,8 @@ int rism_potential_backward(const rism_solute *so, const rism_sites *si, const r
     if (!w) return fail(RISM_E_INVALID, "dL_du is NULL");
     Prep p;
     prep_common(so, si, gr, op, p);
+    if (op->method == RISM_TREECODE_TAYLOR)
+        return fail(RISM_E_UNSUPPORTED, "the Taylor treecode has no adjoint; use RISM_TREECODE_CP");
     if (op->method >= RISM_TREECODE && p.lj_mode != LJ_CUT)
         return fail(RISM_E_UNSUPPORTED, "treecode backward needs an LJ cut-off");
     rism_stats st{};

@@ -81,6 +81,7 @@ def _valid():
     (lambda so, si, g, o: setattr(o, "batch_edge", 6), "batch"),
     (lambda so, si, g, o: setattr(o, "lj_tol", -1.0), "lj_tol"),
     (lambda so, si, g, o: setattr(o, "coulomb_k", float("nan")), "coulomb"),
+    (lambda so, si, g, o: (setattr(o, "method", 4), setattr(o, "degree", 13)), "Taylor order"),
 ])
 def test_host_validation(mutate, frag):
     from paper_2109_09772_amd import api
@@ -130,3 +131,17 @@ def test_reciprocal_asymptotics_validation():
     assert L.rism_asymptotics_k(*args, 1.0, 0.1, 1.0, 78.0, float("nan"), fake, None,
                                 None) == api.RISM_E_INVALID
     assert "tol" in L.rism_last_error().decode()
+
+
+def test_taylor_treecode_has_no_adjoint():
+    """The Taylor-recurrence treecode is forward only: its backward call
+    fails before touching any device memory."""
+    from paper_2109_09772_amd import api
+    so, si, g, o = _valid()
+    o.method = 4
+    o.degree = 6
+    L = api.lib()
+    rc = L.rism_potential_backward(C.byref(so), C.byref(si), C.byref(g), C.byref(o),
+                                   C.c_void_p(16), C.c_void_p(16), None, None, None, None)
+    assert rc == api.RISM_E_UNSUPPORTED
+    assert "Taylor" in L.rism_last_error().decode()
