@@ -63,10 +63,13 @@ def test_small_grids_every_entry(oracle, dims, spacing, n, out_dtype):
     assert np.all(c[:, 0, 0, 0] == 0)
 
 
-def test_cutoff_zero_pattern(oracle):
-    wl = W.tiny(n_atoms=30, dims=(24, 20, 18), seed=21, spacing=0.35)
+@pytest.mark.parametrize("dims,spacing,n,tol", [((24, 20, 18), 0.35, 30, 1e-3),
+                                                ((130, 40, 70), 0.25, 40, 1e-2)])
+def test_cutoff_zero_pattern(oracle, dims, spacing, n, tol):
+    """The cut-off's zero pattern and every kept entry.  On the 130 x 40 x 70
+    grid whole matrix-core tiles lie beyond the cut-off and are skipped."""
+    wl = W.tiny(n_atoms=n, dims=dims, seed=21, spacing=spacing)
     sol, st, g = wl.solute, wl.sites, wl.grid
-    tol = 1e-3
     kc_, kh_ = _kcuts(oracle, wl, tol)
     c, h = _gpu(wl, tol=tol)
     cr, hr = oracle.asymptotics_k(sol.xyz, sol.q, st.q, st.ionic, g.origin, g.spacing, g.dims,
