@@ -553,9 +553,11 @@ __global__ __launch_bounds__(kBlock) void k_cp_assign(CpAssignArgs a)
 
 // Far field of one work item into its cluster's proxies: every thread owns NR
 // proxies per pass (NR = ceil(np / 256) up to 4, so that no lane sweeps an
-// empty slot for the common degrees) and sweeps the item's assigned atoms,
-// which are read as wave-uniform scalar loads in the order they were written.
-// Items are launched heaviest first.
+// empty slot for the common degrees) and sweeps the item's assigned atoms.
+// The atoms pass through LDS in chunks of one per thread, double-buffered:
+// the vector load of the next chunk is in flight while the current one is
+// swept, and each atom reaches the lanes as one broadcast LDS read.  Items
+// are launched heaviest first.
 struct CpSweepArgs {
     CpLevels L;
     const int *order, *it_cl;
@@ -577,11 +579,12 @@ template <bool ASYM, int NR>
 __global__ __launch_bounds__(kBlock) void k_cp_sweep(CpSweepArgs a)
 {
     __shared__ float node[3][kMaxDeg + 1];
+    __shared__ float4 stage[2][kBlock];
     if (*a.bad || (int)blockIdx.x >= (int)*a.n_items) return;   // whole workgroup
     const int item = as_const(a.order)[blockIdx.x];
     const int cl = as_const(a.it_cl)[item];
     const int n = (int)as_const(a.it_n)[item];
-    ConstAS<Quad> *at = as_const(reinterpret_cast<const Quad *>(a.abuf + as_const(a.it_slot)[item]));
+    const float4 *at = a.abuf + as_const(a.it_slot)[item];
     const int n1 = a.degree + 1;
     if (threadIdx.x < 3 * n1) {
         int lvl, I, J, K;
@@ -607,30 +610,42 @@ __global__ __launch_bounds__(kBlock) void k_cp_sweep(CpSweepArgs a)
             pz[r] = node[2][k3];
             aC[r] = aY[r] = 0.0;
         }
-        for (int s0 = 0; s0 < n; s0 += 16) {
-            float pC[NR], pY[NR];
+        float4 nxt = threadIdx.x < n ? at[threadIdx.x] : float4{0.f, 0.f, 0.f, 0.f};
+        for (int c0 = 0, buf = 0; c0 < n; c0 += kBlock, buf ^= 1) {
+            // buffer buf was last read two chunks ago, before the barrier
+            // that every thread passed after it
+            stage[buf][threadIdx.x] = nxt;
+            __syncthreads();
+            if (c0 + kBlock + (int)threadIdx.x < n) nxt = at[c0 + kBlock + threadIdx.x];
+            const float4 *st = stage[buf];
+            const int m = min(kBlock, n - c0);
+            for (int s0 = 0; s0 < m; s0 += 16) {
+                float pC[NR], pY[NR];
 #pragma unroll
-            for (int r = 0; r < NR; ++r) pC[r] = pY[r] = 0.f;
-            const int s1 = min(s0 + 16, n);
-#pragma unroll 2
-            for (int s = s0; s < s1; ++s) {
-                ConstAS<Quad> &v = at[s];
+                for (int r = 0; r < NR; ++r) pC[r] = pY[r] = 0.f;
+                const int s1 = min(s0 + 16, m);
+#pragma unroll 4
+                for (int s = s0; s < s1; ++s) {
+                    const float4 v = st[s];
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        const float dx = px[r] - v.x, dy = py[r] - v.y, dz = pz[r] - v.z;
+                        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                        const float ri = __builtin_amdgcn_rsqf(d2);
+                        const float qr = v.w * ri;
+                        pC[r] += qr;
+                        if (ASYM)
+                            pY[r] = fmaf(qr, __builtin_amdgcn_exp2f(a.yk * (d2 * ri)), pY[r]);
+                    }
+                }
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
-                    const float dx = px[r] - v.x, dy = py[r] - v.y, dz = pz[r] - v.z;
-                    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    const float ri = __builtin_amdgcn_rsqf(d2);
-                    const float qr = v.w * ri;
-                    pC[r] += qr;
-                    if (ASYM) pY[r] = fmaf(qr, __builtin_amdgcn_exp2f(a.yk * (d2 * ri)), pY[r]);
+                    aC[r] += (double)pC[r];
+                    aY[r] += (double)pY[r];
                 }
             }
-#pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                aC[r] += (double)pC[r];
-                aY[r] += (double)pY[r];
-            }
         }
+        __syncthreads();   // the stage is rewritten by the next pass
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const int k = k0 + r * kBlock + threadIdx.x;
