@@ -49,9 +49,9 @@ constexpr int kScanPer = 8;
 constexpr int kScanTile = kScanThreads * kScanPer;
 
 struct ScanBatch {
-    uint32_t *a[4];
-    uint32_t *total[4];
-    int n, na;
+    uint32_t *a[5];
+    uint32_t *total[5];
+    int n[5], na;
 };
 
 __device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t *red)
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(ScanBatch b, uint32
     uint32_t v = 0;
     for (int k = 0; k < kScanPer; ++k) {
         const int i = base + k * kScanThreads + threadIdx.x;
-        if (i < b.n) v += a[i];
+        if (i < b.n[blockIdx.y]) v += a[i];
     }
     v = block_sum_u32(v, red);
     if (threadIdx.x == 0) bsum[blockIdx.y * ntiles + blockIdx.x] = v;
@@ -110,10 +110,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(ScanBatch b, const 
     __shared__ uint32_t tile[kScanTile];
     __shared__ uint32_t tsum[kScanThreads];
     uint32_t *a = b.a[blockIdx.y];
+    const int n = b.n[blockIdx.y];
     const int base = blockIdx.x * kScanTile;
     for (int k = 0; k < kScanPer; ++k) {
         const int j = k * kScanThreads + threadIdx.x;
-        tile[j] = base + j < b.n ? a[base + j] : 0u;
+        tile[j] = base + j < n ? a[base + j] : 0u;
     }
     __syncthreads();
     uint32_t loc[kScanPer], run = 0;
@@ -134,14 +135,67 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(ScanBatch b, const 
     __syncthreads();
     for (int k = 0; k < kScanPer; ++k) {
         const int j = k * kScanThreads + threadIdx.x;
-        if (base + j < b.n) a[base + j] = tile[j];
+        if (base + j < n) a[base + j] = tile[j];
     }
+}
+
+// The whole scan of one array per workgroup (arrays of up to kScanOneMax
+// entries): kScanOnePer consecutive entries per thread, a workgroup scan of
+// the thread sums, the total to *total[k].
+constexpr int kScanOneThreads = 1024;
+constexpr int kScanOnePer = 16;
+constexpr int kScanOneMax = kScanOneThreads * kScanOnePer;
+
+__global__ __launch_bounds__(kScanOneThreads) void k_scan_one(ScanBatch b)
+{
+    __shared__ uint32_t wsum[kScanOneThreads / 64];
+    uint32_t *a = b.a[blockIdx.x];
+    const int n = b.n[blockIdx.x];
+    const int per = (n + kScanOneThreads - 1) / kScanOneThreads;
+    const int i0 = threadIdx.x * per;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t v[kScanOnePer], run = 0;
+#pragma unroll
+    for (int k = 0; k < kScanOnePer; ++k) {
+        const int i = i0 + k;
+        v[k] = k < per && i < n ? a[i] : 0u;
+        run += v[k];
+    }
+    uint32_t x = run;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (int w = 0; w < kScanOneThreads / 64; ++w) {
+        const uint32_t t = wsum[w];
+        base += w < wave ? t : 0u;
+        tot += t;
+    }
+    uint32_t o = base + x - run;
+#pragma unroll
+    for (int k = 0; k < kScanOnePer; ++k) {
+        const int i = i0 + k;
+        if (k < per && i < n) a[i] = o;
+        o += v[k];
+    }
+    if (threadIdx.x == 0) *b.total[blockIdx.x] = tot;
 }
 
 static int scan_batch(const ScanBatch &b, Workspace &ws, hipStream_t s)
 {
-    if (b.n <= 0 || b.na <= 0) return RISM_OK;
-    const int ntiles = (b.n + kScanTile - 1) / kScanTile;
+    if (b.na <= 0) return RISM_OK;
+    int nmax = 0;
+    for (int k = 0; k < b.na; ++k) nmax = std::max(nmax, b.n[k]);
+    if (nmax <= 0) return RISM_OK;
+    if (nmax <= kScanOneMax) {
+        hipLaunchKernelGGL(k_scan_one, b.na, kScanOneThreads, 0, s, b);
+        RISM_HIP(hipGetLastError());
+        return RISM_OK;
+    }
+    const int ntiles = (nmax + kScanTile - 1) / kScanTile;
     uint32_t *bsum = ws.get<uint32_t>((size_t)ntiles * b.na);
     if (!bsum) return ws.status();
     hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles, b.na), kScanThreads, 0, s, b, bsum, ntiles);
@@ -194,13 +248,11 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane)
 // One wave per query.  The DFS pops up to 64 nodes at a time (one per lane),
 // appends the hit leaves in lane order and pushes the children of the other
 // hits; the resulting candidate order is deterministic.
-__global__ __launch_bounds__(64) void k_cp_query(CpQueryArgs a)
+__device__ __forceinline__ void cp_query(const CpQueryArgs &a, int q, int *stk)
 {
-    __shared__ int stk[kQStackW];
     const int lane = threadIdx.x;
-    const int q = blockIdx.x;
     if (a.fill && *a.bad) return;
-    if (!a.fill && blockIdx.x == 0 && threadIdx.x == 0) {
+    if (!a.fill && q == 0 && threadIdx.x == 0) {
         a.cnt[a.nq] = 0;
         if (a.items) a.items[a.nq] = 0;
         if (a.acnt) a.acnt[a.nq] = 0;
@@ -302,10 +354,21 @@ __global__ __launch_bounds__(64) void k_cp_query(CpQueryArgs a)
     }
 }
 
+// Both query sets in one launch: workgroups [0, a.nq) take a's queries, the
+// rest b's (b.nq may be 0).
+__global__ __launch_bounds__(64) void k_cp_query(CpQueryArgs a, CpQueryArgs b)
+{
+    __shared__ int stk[kQStackW];
+    const int q = blockIdx.x;
+    if (q < a.nq) cp_query(a, q, stk);
+    else cp_query(b, q - a.nq, stk);
+}
+
 // Classification of every candidate atom of a level-0 block, once: direct
 // (assigned to no level >= 1: full pair), short-range only (within the
-// short range of the block), or skipped.  One wave per block; the two index
-// lists keep the candidates' order.
+// short range of the block), or skipped.  One workgroup per block, its
+// candidate atoms dealt 256 at a time to the threads in candidate order;
+// the two index lists keep that order.
 struct CpClassArgs {
     CpLevels L;
     int nq;
@@ -321,49 +384,63 @@ struct CpClassArgs {
     const int *bad;            // lists sized too small: write nothing
 };
 
-// Candidate leaves per LDS window of the classification.
-constexpr int kClsWin = 256;
+// Candidate leaves per LDS window of the classification (one per thread).
+constexpr int kClsWin = kBlock;
+
+// Exclusive scan of v over the workgroup, in thread order, and the total.
+// `ws` holds kBlock / 64 ints; the call contains two barriers.
+__device__ __forceinline__ int group_excl_scan(int v, int *ws, int &total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int incl = wave_incl_scan(v, lane);
+    if (lane == 63) ws[wave] = incl;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        const int x = ws[w];
+        base += w < wave ? x : 0;
+        tot += x;
+    }
+    __syncthreads();   // ws is rewritten by the next scan
+    total = tot;
+    return base + incl - v;
+}
 
 __global__ __launch_bounds__(kBlock) void k_cp_classify(CpClassArgs a)
 {
-    __shared__ int wbeg[kBlock / 64][kClsWin];
-    __shared__ int wpre[kBlock / 64][kClsWin + 1];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int q = blockIdx.x * (kBlock / 64) + wave;
-    if (q >= a.nq || *a.bad) return;   // whole waves leave; no block barrier below
+    __shared__ int beg[kClsWin];
+    __shared__ int pre[kClsWin + 1];
+    __shared__ int ws[2][kBlock / 64];
+    const int q = blockIdx.x;
+    if (q >= a.nq || *a.bad) return;   // whole workgroup
     const CpLevels &L = a.L;
     const int I = q % L.cx[0], J = (q / L.cx[0]) % L.cy[0], K = q / (L.cx[0] * L.cy[0]);
     double blo[3], bhi[3];
     cp_box(L, 0, I, J, K, blo, bhi);
     const double rs2 = a.rshort * a.rshort;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint32_t base = a.aoff[q];
-    int *beg = wbeg[wave], *pre = wpre[wave];
-    uint32_t nd = 0, ns = 0;
+    uint32_t nd = 0, ns = 0;   // workgroup-uniform
     const int c0 = (int)a.cand_off[q], c1 = (int)a.cand_off[q + 1];
     for (int cw = c0; cw < c1; cw += kClsWin) {
         // window of candidate leaves: first atom and atom prefix, in list order
         const int nw = min(kClsWin, c1 - cw);
-        int run = 0;
-        for (int k0 = 0; k0 < nw; k0 += 64) {
-            const int k = k0 + lane;
-            int sz = 0;
-            if (k < nw) {
-                const int leaf = a.cand[cw + k];
-                beg[k] = a.begin[leaf];
-                sz = a.end[leaf] - a.begin[leaf];
-            }
-            const int incl = wave_incl_scan(sz, lane);
-            if (k < nw) pre[k] = run + incl - sz;
-            run += __shfl(incl, 63);
+        int sz = 0;
+        if (tid < nw) {
+            const int leaf = a.cand[cw + tid];
+            beg[tid] = a.begin[leaf];
+            sz = a.end[leaf] - a.begin[leaf];
         }
-        if (lane == 0) pre[nw] = run;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // the window's atoms, 64 at a time
-        for (int t0 = 0; t0 < run; t0 += 64) {
-            const int t = t0 + lane;
+        int run;
+        const int ex = group_excl_scan(sz, ws[0], run);
+        if (tid < nw) pre[tid] = ex;
+        if (tid == 0) pre[nw] = run;
+        __syncthreads();
+        // the window's atoms, one per thread per round
+        for (int t0 = 0, par = 0; t0 < run; t0 += kBlock, par ^= 1) {
+            const int t = t0 + tid;
             int cls = 0, i = 0;
             if (t < run) {
                 int lo = 0, hi = nw - 1;   // last k with pre[k] <= t
@@ -387,15 +464,31 @@ __global__ __launch_bounds__(kBlock) void k_cp_classify(CpClassArgs a)
                     cls = g2 < rs2 ? 2 : 0;
                 }
             }
+            // ordered compaction over the workgroup: wave counts through LDS
+            // (two count buffers alternate, so one barrier per round suffices)
             const uint64_t m1 = __ballot(cls == 1), m2 = __ballot(cls == 2);
-            if (cls == 1) a.dlist[base + nd + __popcll(m1 & lt)] = i;
-            if (cls == 2) a.slist[base + ns + __popcll(m2 & lt)] = i;
-            nd += (uint32_t)__popcll(m1);
-            ns += (uint32_t)__popcll(m2);
+            int *cnt = ws[par];
+            if (lane == 0) cnt[wave] = (__popcll(m1) << 16) | __popcll(m2);
+            __syncthreads();
+            uint32_t o1 = 0, o2 = 0, t1 = 0, t2 = 0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) {
+                const uint32_t c = (uint32_t)cnt[w];
+                if (w < wave) {
+                    o1 += c >> 16;
+                    o2 += c & 0xffffu;
+                }
+                t1 += c >> 16;
+                t2 += c & 0xffffu;
+            }
+            if (cls == 1) a.dlist[base + nd + o1 + __popcll(m1 & lt)] = i;
+            if (cls == 2) a.slist[base + ns + o2 + __popcll(m2 & lt)] = i;
+            nd += t1;
+            ns += t2;
         }
-        __builtin_amdgcn_wave_barrier();   // the window is read before the next one is written
+        __syncthreads();   // the window is read before the next one is written
     }
-    if (lane == 0) {
+    if (tid == 0) {
         a.nd[q] = nd;
         a.ns[q] = ns;
     }
@@ -809,71 +902,101 @@ __global__ __launch_bounds__(kBlock) void k_cp_reduce(int nclusters, int np, con
 
 // ----------------------------------------------------------------- downward
 
-// Children at level lvl: V[child] += (Mx (x) My (x) Mz) V[parent], with
-// M[k][m] = L^P_m(s^C_k): the parent's interpolant evaluated at the child's
-// proxy points, separably, in FP64.
-// Taylor moments (taylor != 0): M[k][m] = C(m, k) delta^(m - k) for m >= k,
-// delta = child centre - parent centre: the parent's polynomial re-expanded
-// about the child's centre, again separably.
-__global__ __launch_bounds__(kBlock) void k_cp_down(CpLevels L, int lvl, int degree, int taylor,
-                                                    double *V)
+// Level-1 clusters gather the far field of their whole ancestor chain: with
+// A_l the level-l ancestor, the proxy values carried down are
+//   acc_T = V[A_T],  acc_l = V[A_l] + (Mx (x) My (x) Mz) acc_{l+1},
+// and V[A_1] takes acc_1.  M[k][m] = L^P_m(s^C_k): the parent's interpolant
+// evaluated at the child's proxy points, separably, in FP64.  Taylor moments
+// (taylor != 0): M[k][m] = C(m, k) delta^(m - k) for m >= k, delta = child
+// centre - parent centre: the parent's polynomial re-expanded about the
+// child's centre, again separably.  One workgroup per level-1 cluster; the
+// levels above 1 keep their own values (only level 1 is read later), so
+// siblings repeat their common ancestors' steps instead of waiting for a
+// launch per level.  nc components (1 or 2, as the LDS allows) per pass.
+constexpr int kDownThreads = 1024;
+
+inline size_t cp_down_lds(int degree, int nc)
+{
+    const size_t n1 = degree + 1, np = n1 * n1 * n1;
+    return (3 * n1 * n1 + 3 * (size_t)nc * np) * sizeof(double);
+}
+
+__global__ __launch_bounds__(kDownThreads) void k_cp_down(CpLevels L, int degree, int taylor,
+                                                          int nc, double *V)
 {
     extern __shared__ double sm[];
-    const int n1 = degree + 1, np = n1 * n1 * n1;
+    const int n1 = degree + 1, np = n1 * n1 * n1, ne = nc * np;
     double *M = sm;                 // [3][n1][n1]
-    double *src = M + 3 * n1 * n1;  // [np]
-    double *t1 = src + np;          // [np]
-    double *t2 = t1 + np;           // [np]
+    double *acc = M + 3 * n1 * n1;  // [nc][np]
+    double *t1 = acc + ne;          // [nc][np]
+    double *t2 = t1 + ne;           // [nc][np]
     const int q = blockIdx.x;
-    const int I = q % L.cx[lvl], J = (q / L.cx[lvl]) % L.cy[lvl], K = q / (L.cx[lvl] * L.cy[lvl]);
-    const int id = cp_id(L, lvl, I, J, K);
-    const int pid = cp_id(L, lvl + 1, I >> 1, J >> 1, K >> 1);
-    double cb[6], pbx[6];
-    cp_proxy_box(L, lvl, I, J, K, cb);
-    cp_proxy_box(L, lvl + 1, I >> 1, J >> 1, K >> 1, pbx);
-    if (threadIdx.x < 3 * n1) {
-        const int ax = threadIdx.x / n1, k = threadIdx.x % n1;
-        if (taylor) {
-            double cc[3], cp[3], rr;
-            cp_centre(L, lvl, I, J, K, cc, rr);
-            cp_centre(L, lvl + 1, I >> 1, J >> 1, K >> 1, cp, rr);
-            const double dl = pick3(cc, ax) - pick3(cp, ax);
-            double *row = M + (ax * n1 + k) * n1;
-            for (int m = 0; m < k; ++m) row[m] = 0.0;
-            double c = 1.0;   // C(m, k) dl^(m - k), m = k, k + 1, ...
-            for (int m = k; m < n1; ++m) {
-                row[m] = c;
-                c = c * dl * (double)(m + 1) / (double)(m + 1 - k);
+    const int I1 = q % L.cx[1], J1 = (q / L.cx[1]) % L.cy[1], K1 = q / (L.cx[1] * L.cy[1]);
+    for (int comp0 = 0; comp0 < 2; comp0 += nc) {
+        __syncthreads();   // acc and M are free
+        {
+            const int sh = L.T - 1;
+            const int top = cp_id(L, L.T, I1 >> sh, J1 >> sh, K1 >> sh);
+            for (int e = threadIdx.x; e < ne; e += kDownThreads)
+                acc[e] = V[((size_t)top * 2 + comp0) * np + e];
+        }
+        for (int lvl = L.T - 1; lvl >= 1; --lvl) {
+            const int I = I1 >> (lvl - 1), J = J1 >> (lvl - 1), K = K1 >> (lvl - 1);
+            const int id = cp_id(L, lvl, I, J, K);
+            if (threadIdx.x < 3 * n1) {
+                const int ax = threadIdx.x / n1, k = threadIdx.x % n1;
+                double *row = M + (ax * n1 + k) * n1;
+                if (taylor) {
+                    double cc[3], cp[3], rr;
+                    cp_centre(L, lvl, I, J, K, cc, rr);
+                    cp_centre(L, lvl + 1, I >> 1, J >> 1, K >> 1, cp, rr);
+                    const double dl = pick3(cc, ax) - pick3(cp, ax);
+                    for (int m = 0; m < k; ++m) row[m] = 0.0;
+                    double c = 1.0;   // C(m, k) dl^(m - k), m = k, k + 1, ...
+                    for (int m = k; m < n1; ++m) {
+                        row[m] = c;
+                        c = c * dl * (double)(m + 1) / (double)(m + 1 - k);
+                    }
+                } else {
+                    double cb[6], pbx[6];
+                    cp_proxy_box(L, lvl, I, J, K, cb);
+                    cp_proxy_box(L, lvl + 1, I >> 1, J >> 1, K >> 1, pbx);
+                    lagrange_to(cheb_point(pick3(cb, ax), pick3(cb + 3, ax), k, degree),
+                                pick3(pbx, ax), pick3(pbx + 3, ax), degree, row, 1);
+                }
             }
-        } else {
-            lagrange_to(cheb_point(pick3(cb, ax), pick3(cb + 3, ax), k, degree), pick3(pbx, ax),
-                        pick3(pbx + 3, ax), degree, M + (ax * n1 + k) * n1, 1);
-        }
-    }
-    for (int comp = 0; comp < 2; ++comp) {
-        __syncthreads();
-        for (int k = threadIdx.x; k < np; k += kBlock) src[k] = V[((size_t)pid * 2 + comp) * np + k];
-        __syncthreads();
-        // index (z, y, x) with x fastest; contract x, then y, then z
-        for (int k = threadIdx.x; k < np; k += kBlock) {
-            const int k1 = k % n1, rest = k / n1;
-            double s = 0;
-            for (int m = 0; m < n1; ++m) s += M[(0 * n1 + k1) * n1 + m] * src[rest * n1 + m];
-            t1[k] = s;
-        }
-        __syncthreads();
-        for (int k = threadIdx.x; k < np; k += kBlock) {
-            const int k1 = k % n1, k2 = (k / n1) % n1, m3 = k / (n1 * n1);
-            double s = 0;
-            for (int m = 0; m < n1; ++m) s += M[(1 * n1 + k2) * n1 + m] * t1[(m3 * n1 + m) * n1 + k1];
-            t2[k] = s;
-        }
-        __syncthreads();
-        for (int k = threadIdx.x; k < np; k += kBlock) {
-            const int k12 = k % (n1 * n1), k3 = k / (n1 * n1);
-            double s = 0;
-            for (int m = 0; m < n1; ++m) s += M[(2 * n1 + k3) * n1 + m] * t2[m * n1 * n1 + k12];
-            V[((size_t)id * 2 + comp) * np + k] += s;
+            __syncthreads();   // M and acc ready
+            // entry e = c np + k, k = (z, y, x) with x fastest; contract x,
+            // then y, then z
+            for (int e = threadIdx.x; e < ne; e += kDownThreads) {
+                const int c = e / np, k = e - c * np;
+                const int k1 = k % n1, rest = k / n1;
+                const double *src = acc + c * np + rest * n1;
+                double s = 0;
+                for (int m = 0; m < n1; ++m) s += M[(0 * n1 + k1) * n1 + m] * src[m];
+                t1[e] = s;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < ne; e += kDownThreads) {
+                const int c = e / np, k = e - c * np;
+                const int k1 = k % n1, k2 = (k / n1) % n1, m3 = k / (n1 * n1);
+                const double *src = t1 + c * np + m3 * n1 * n1 + k1;
+                double s = 0;
+                for (int m = 0; m < n1; ++m) s += M[(1 * n1 + k2) * n1 + m] * src[m * n1];
+                t2[e] = s;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < ne; e += kDownThreads) {
+                const int c = e / np, k = e - c * np;
+                const int k12 = k % (n1 * n1), k3 = k / (n1 * n1);
+                const double *src = t2 + c * np + k12;
+                double s = 0;
+                for (int m = 0; m < n1; ++m) s += M[(2 * n1 + k3) * n1 + m] * src[m * n1 * n1];
+                double *v = V + ((size_t)id * 2 + comp0) * np + e;
+                if (lvl > 1) acc[e] = *v + s;
+                else *v += s;
+            }
+            __syncthreads();   // M is rewritten by the next step
         }
     }
 }
@@ -1185,9 +1308,15 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     uint32_t *ccnt = ws.get<uint32_t>(ncl + 1), *citems = ws.get<uint32_t>(ncl + 1);
     uint32_t *cacnt = ws.get<uint32_t>(ncl + 1);
     uint32_t *lcnt = ws.get<uint32_t>(nleaf + 1), *lacnt = ws.get<uint32_t>(nleaf + 1);
-    uint32_t *tot = ws.get<uint32_t>(5);
-    int *overflow = ws.get<int>(1);
+    // [0..4] totals as in CpCaps, [5] query stack overflow, [6] capacity
+    // check failed: one block, read back with one copy
+    uint32_t *flags = ws.get<uint32_t>(8);
     if (ws.status()) return ws.status();
+    uint32_t *tot = flags;
+    int *overflow = reinterpret_cast<int *>(flags + 5);
+    int *bad = reinterpret_cast<int *>(flags + 6);
+    int dev = 0;
+    RISM_HIP(hipGetDevice(&dev));
     CpQueryArgs qa{};
     qa.L = L;
     qa.rshort = rshort;
@@ -1198,49 +1327,48 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     qa.box = t.box;
     qa.n_nodes = t.n_nodes;
     qa.overflow = overflow;
-    const int wpb = kBlock / 64;
+    hipLaunchKernelGGL(k_fill_int, 1, 64, 0, s, overflow, 1, 0);
     {
+        // count pass of both query sets in one launch, then all five scans
         PhaseTimer pt(ev, RISM_PHASE_LISTS, s);
-        hipLaunchKernelGGL(k_fill_int, 1, 64, 0, s, overflow, 1, 0);
-        if (ncl > 0) {
-            qa.mode = 0;
-            qa.nq = ncl;
-            qa.cnt = ccnt;
-            qa.items = citems;
-            qa.acnt = cacnt;
-            qa.fill = 0;
-            hipLaunchKernelGGL(k_cp_query, ncl, 64, 0, s, qa);
-            ScanBatch sb{};
-            sb.a[0] = ccnt;
-            sb.a[1] = citems;
-            sb.a[2] = cacnt;
-            sb.total[0] = tot + 0;
-            sb.total[1] = tot + 1;
-            sb.total[2] = tot + 4;
-            sb.n = ncl + 1;
-            sb.na = 3;
-            if ((rc = scan_batch(sb, ws, s))) return rc;
-        }
-        qa.mode = 1;
-        qa.nq = nleaf;
-        qa.cnt = lcnt;
-        qa.items = nullptr;
-        qa.acnt = lacnt;
-        qa.fill = 0;
-        hipLaunchKernelGGL(k_cp_query, nleaf, 64, 0, s, qa);
+        CpQueryArgs qc = qa;   // clusters (none when ncl = 0)
+        qc.mode = 0;
+        qc.nq = ncl;
+        qc.cnt = ccnt;
+        qc.items = citems;
+        qc.acnt = cacnt;
+        qc.fill = 0;
+        CpQueryArgs ql = qa;   // level-0 blocks
+        ql.mode = 1;
+        ql.nq = nleaf;
+        ql.cnt = lcnt;
+        ql.items = nullptr;
+        ql.acnt = lacnt;
+        ql.fill = 0;
+        hipLaunchKernelGGL(k_cp_query, ncl + nleaf, 64, 0, s, qc, ql);
         ScanBatch sb{};
-        sb.a[0] = lcnt;
-        sb.a[1] = lacnt;
-        sb.total[0] = tot + 2;
-        sb.total[1] = tot + 3;
-        sb.n = nleaf + 1;
-        sb.na = 2;
+        int na = 0;
+        auto add = [&](uint32_t *arr, uint32_t *total, int n) {
+            sb.a[na] = arr;
+            sb.total[na] = total;
+            sb.n[na] = n;
+            ++na;
+        };
+        if (ncl > 0) {
+            add(ccnt, tot + 0, ncl + 1);
+            add(citems, tot + 1, ncl + 1);
+            add(cacnt, tot + 4, ncl + 1);
+        } else {
+            hipLaunchKernelGGL(k_fill_int, 1, 64, 0, s, reinterpret_cast<int *>(tot), 5, 0);
+        }
+        add(lcnt, tot + 2, nleaf + 1);
+        add(lacnt, tot + 3, nleaf + 1);
+        sb.na = na;
         if ((rc = scan_batch(sb, ws, s))) return rc;
     }
     RISM_HIP(hipGetLastError());
 
-    int dev = 0, lds_max = 0;
-    RISM_HIP(hipGetDevice(&dev));
+    int lds_max = 0;
     RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const size_t leaf_shm = cp_leaf_lds(B, deg, a.asym_on);
     const bool taylor = a.opts->method == RISM_TREECODE_TAYLOR;
@@ -1248,13 +1376,13 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         set_error("Taylor treecode: order above 12 or its LDS beyond this device");
         return RISM_E_UNSUPPORTED;
     }
-    if (leaf_shm + 2048 > (size_t)lds_max) {
+    if (leaf_shm + 2048 > (size_t)lds_max || cp_down_lds(deg, 1) > (size_t)lds_max) {
         set_error("treecode_cp: degree / batch edge too large for the LDS of this device");
         return RISM_E_UNSUPPORTED;
     }
+    const int down_nc = cp_down_lds(deg, 2) <= (size_t)lds_max ? 2 : 1;
     const bool want_stats = a.opts->flags & RISM_FLAG_STATS;
     unsigned long long *work = want_stats ? ws.get<unsigned long long>(4) : nullptr;
-    int *bad = ws.get<int>(1);
     uint32_t *nd = ws.get<uint32_t>(nleaf), *nsh = ws.get<uint32_t>(nleaf);
     int *order = ws.get<int>(nleaf);
     double *V = ws.get<double>((size_t)(ncl + 1) * 2 * np);
@@ -1274,30 +1402,33 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         if (ws.status()) return ws.status();
         if (work) hipLaunchKernelGGL(k_fill_u64, 1, 64, 0, s, work, 4);
         qa.bad = bad;
+        // fill pass of both query sets in one launch; far work items; the
+        // near-field classification and the leaves' launch order
         {
             PhaseTimer pt(ev, RISM_PHASE_LISTS, s);
-            if (ncl > 0) {
-                qa.mode = 0;
-                qa.nq = ncl;
-                qa.off = ccnt;
-                qa.list = ccand;
-                qa.apre = capre;
-                qa.fill = 1;
-                qa.items = nullptr;
-                qa.acnt = nullptr;
-                hipLaunchKernelGGL(k_cp_query, ncl, 64, 0, s, qa);
-                qa.apre = nullptr;
+            CpQueryArgs qc = qa;
+            qc.mode = 0;
+            qc.nq = ncl;
+            qc.off = ccnt;
+            qc.list = ccand;
+            qc.apre = capre;
+            qc.fill = 1;
+            qc.items = nullptr;
+            qc.acnt = nullptr;
+            CpQueryArgs ql = qa;
+            ql.mode = 1;
+            ql.nq = nleaf;
+            ql.off = lcnt;
+            ql.list = lcand;
+            ql.apre = nullptr;
+            ql.fill = 1;
+            ql.items = nullptr;
+            ql.acnt = nullptr;
+            hipLaunchKernelGGL(k_cp_query, ncl + nleaf, 64, 0, s, qc, ql);
+            if (ncl > 0)
                 hipLaunchKernelGGL(k_cp_items, (ncl + kBlock - 1) / kBlock, kBlock, 0, s, ncl,
                                    ccnt, citems, cacnt, capre, (const int *)bad, it_cl, it_c0,
                                    it_c1, it_slot);
-            }
-            qa.mode = 1;
-            qa.nq = nleaf;
-            qa.off = lcnt;
-            qa.list = lcand;
-            qa.fill = 1;
-            qa.acnt = nullptr;
-            hipLaunchKernelGGL(k_cp_query, nleaf, 64, 0, s, qa);
             CpClassArgs ca{};
             ca.L = L;
             ca.nq = nleaf;
@@ -1314,7 +1445,9 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             ca.nd = nd;
             ca.ns = nsh;
             ca.bad = bad;
-            hipLaunchKernelGGL(k_cp_classify, (nleaf + wpb - 1) / wpb, kBlock, 0, s, ca);
+            hipLaunchKernelGGL(k_cp_classify, nleaf, kBlock, 0, s, ca);
+            hipLaunchKernelGGL(k_order_by_cost, 1, 1024, 0, s, nleaf, (const uint32_t *)nullptr,
+                               (const int *)bad, nd, nsh, order);
         }
         RISM_HIP(hipGetLastError());
 
@@ -1377,10 +1510,9 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             PhaseTimer pt(ev, RISM_PHASE_DOWNWARD, s);
             hipLaunchKernelGGL(k_cp_reduce, ncl, kBlock, 0, s, ncl, np, citems, (const int *)bad,
                                part, V);
-            const size_t shm = (3 * (size_t)n1 * n1 + 3 * (size_t)np) * sizeof(double);
-            for (int lvl = L.T - 1; lvl >= 1; --lvl)
-                hipLaunchKernelGGL(k_cp_down, L.cx[lvl] * L.cy[lvl] * L.cz[lvl], kBlock, shm, s,
-                                   L, lvl, deg, (int)taylor, V);
+            if (L.T >= 2)
+                hipLaunchKernelGGL(k_cp_down, L.cx[1] * L.cy[1] * L.cz[1], kDownThreads,
+                                   cp_down_lds(deg, down_nc), s, L, deg, (int)taylor, down_nc, V);
         }
         RISM_HIP(hipGetLastError());
 
@@ -1404,11 +1536,6 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         la.taylor = taylor;
         la.work = work;
         {
-            PhaseTimer pl(ev, RISM_PHASE_LISTS, s);
-            hipLaunchKernelGGL(k_order_by_cost, 1, 1024, 0, s, nleaf, (const uint32_t *)nullptr,
-                               (const int *)bad, nd, nsh, order);
-        }
-        {
             PhaseTimer pt(ev, RISM_PHASE_EVAL, s);
             const int ljm = a.lj_mode == LJ_CUT && a.lj_uniform ? LJ_CUT1 : a.lj_mode;
             switch (a.sp.ns_pad) {
@@ -1430,9 +1557,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         return RISM_E_HIP;
     }
     auto read_back = [&]() -> int {
-        RISM_HIP(hipMemcpyAsync(hres, tot, 5 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        RISM_HIP(hipMemcpyAsync(hres + 5, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
-        RISM_HIP(hipMemcpyAsync(hres + 6, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        RISM_HIP(hipMemcpyAsync(hres, flags, 7 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         RISM_HIP(hipStreamSynchronize(s));
         if (hres[5]) {
             set_error("treecode_cp: neighbour query stack overflow");

@@ -403,16 +403,16 @@ __global__ __launch_bounds__(kSmallThreads) void k_tree_small(
         sk[i] = i < n ? ((unsigned long long)atom_key(rec, stride_f4, i, bb) << 32) | (unsigned)i
                       : ~0ull;
     __syncthreads();
+    // one compare-exchange pair (i, i + j) per thread and step, i with bit j clear
     for (int k = 2; k <= npow2; k <<= 1)
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < npow2; i += kSmallThreads) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const unsigned long long a = sk[i], b = sk[ixj];
-                    if ((a > b) == ((i & k) == 0)) {
-                        sk[i] = b;
-                        sk[ixj] = a;
-                    }
+            for (int p = tid; p < (npow2 >> 1); p += kSmallThreads) {
+                const int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
+                const int ixj = i | j;
+                const unsigned long long a = sk[i], b = sk[ixj];
+                if ((a > b) == ((i & k) == 0)) {
+                    sk[i] = b;
+                    sk[ixj] = a;
                 }
             }
             __syncthreads();
