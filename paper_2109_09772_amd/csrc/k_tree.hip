@@ -433,42 +433,39 @@ __global__ __launch_bounds__(kSmallThreads) void k_tree_small(
         const int s0 = ls[lvl], s1 = ls[lvl + 1];
         const int shift = 3 * (kMortonBits - 1 - lvl);
         int running = 0;
-        for (int c0 = s0; c0 < s1; c0 += kSmallThreads) {
-            const int i = c0 + tid;
-            int c = 0, b = 0, e = 0;
+        // eight threads per node: thread d finds the first atom of the node
+        // whose digit is >= d (the node's atoms are sorted, so the children
+        // are the runs between these boundaries)
+        for (int c0 = s0; c0 < s1; c0 += kSmallThreads / 8) {
+            const int i = c0 + (tid >> 3), d = tid & 7;
+            int b = 0, e = 0;
             const bool split = i < s1 && (e = end[i]) - (b = begin[i]) > leaf;
-            // child boundaries: bnd[d] = first atom whose digit is >= d
-            int bnd[9];
-            bnd[0] = b;
-            bnd[8] = e;
-            if (split) {
-                for (int d = 1; d < 8; ++d) bnd[d] = lower_digit_lds(sk, bnd[d - 1], e, shift, d);
-                for (int d = 0; d < 8; ++d) c += bnd[d + 1] > bnd[d] ? 1 : 0;
-            }
+            const int lo = split ? (d == 0 ? b : lower_digit_lds(sk, b, e, shift, d)) : 0;
+            int hi = __shfl_down(lo, 1);
+            if (d == 7) hi = e;
+            const bool ne = split && hi > lo;   // child of digit d is not empty
+            const unsigned long long m = __ballot(ne);
+            const int g0 = lane & ~7;
+            const unsigned gm = (unsigned)((m >> g0) & 0xffull);
+            const int c = __popc(gm);
             int tot;
-            const int off = block_excl_scan(c, wsum, tot);
+            const int off = block_excl_scan(d == 0 ? c : 0, wsum, tot);
+            const int base = s1 + running + __shfl(off, g0);
             if (i < s1) {
-                if (split) {
-                    const int base = s1 + running + off;
-                    child0[i] = base;
-                    int cc = 0;
-                    for (int d = 0; d < 8; ++d) {
-                        if (bnd[d + 1] > bnd[d]) {
-                            const int j = base + cc;
-                            if (j < cap) {
-                                begin[j] = bnd[d];
-                                end[j] = bnd[d + 1];
-                                level[j] = lvl + 1;
-                                child0[j] = -1;
-                                nchild[j] = 0;
-                            }
-                            ++cc;
-                        }
+                if (ne) {
+                    const int j = base + __popc(gm & ((1u << d) - 1u));
+                    if (j < cap) {
+                        begin[j] = lo;
+                        end[j] = hi;
+                        level[j] = lvl + 1;
+                        child0[j] = -1;
+                        nchild[j] = 0;
                     }
-                } else {
-                    child0[i] = -1;
                 }
-                nchild[i] = c;
+                if (d == 0) {
+                    child0[i] = split ? base : -1;
+                    nchild[i] = c;
+                }
             }
             running += tot;
         }
