@@ -314,12 +314,94 @@ __global__ __launch_bounds__(kBlock) void k_split_write(const uint32_t *keys, in
 
 // ------------------------------------------------- one-workgroup builder
 
-// The whole build of a small tree in one workgroup: key cube, Morton keys,
-// sort of the (key, input index) pairs in LDS (bitonic; unique pairs, so the
-// order equals the stable radix sort's), and the level-by-level split with
-// block-wide scans.  Produces the same permutation and nodes as the
-// multi-kernel build.
+// Small trees: keys by one workgroup, ranked by many, then one workgroup
+// places them and builds the octree level by level with block-wide scans.
+// Produces the same permutation and nodes as the multi-kernel build.
 constexpr int kSmallThreads = 1024;
+constexpr int kRankTargets = 64;   // atoms ranked per workgroup
+
+// Morton keys of a small tree's atoms, by one workgroup: the key cube from
+// a block-wide reduction, then one key per atom.
+__global__ __launch_bounds__(kSmallThreads) void k_tree_keys(const float4 *rec, int stride_f4, int n,
+                                                           uint32_t *keys)
+{
+    __shared__ double red[6][kSmallThreads / 64];
+    __shared__ double bb[6];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int i = tid; i < n; i += kSmallThreads) {
+        float4 a = rec[(size_t)i * stride_f4];
+        float4 b = rec[(size_t)i * stride_f4 + 1];
+        double v[3] = {(double)a.x + b.x, (double)a.y + b.y, (double)a.z + b.z};
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fmin(lo[k], v[k]);
+            hi[k] = fmax(hi[k], v[k]);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1)
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fmin(lo[k], __shfl_xor(lo[k], off));
+            hi[k] = fmax(hi[k], __shfl_xor(hi[k], off));
+        }
+    if (lane == 0)
+        for (int k = 0; k < 3; ++k) {
+            red[k][wave] = lo[k];
+            red[3 + k][wave] = hi[k];
+        }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < kSmallThreads / 64; ++w)
+            for (int k = 0; k < 3; ++k) {
+                red[k][0] = fmin(red[k][0], red[k][w]);
+                red[3 + k][0] = fmax(red[3 + k][0], red[3 + k][w]);
+            }
+        const double l3[3] = {red[0][0], red[1][0], red[2][0]};
+        const double h3[3] = {red[3][0], red[4][0], red[5][0]};
+        bbox_cube(l3, h3, bb);
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += kSmallThreads) keys[i] = atom_key(rec, stride_f4, i, bb);
+}
+
+// Sorted position of every atom by (key, index), i.e. the position a stable
+// sort by key gives: each workgroup copies all keys to LDS and ranks 64
+// atoms, each of its sixteen waves counting over a sixteenth of the keys
+// (four keys per broadcast read).
+constexpr int kRankThreads = 1024;
+constexpr int kRankWaves = kRankThreads / 64;
+
+__global__ __launch_bounds__(kRankThreads) void k_tree_rank(const uint32_t *keys, int n, int *rank)
+{
+    extern __shared__ uint4 k4[];   // [round_up(n, 4 kRankWaves) / 4]
+    __shared__ int part[kRankWaves][kRankTargets];
+    uint32_t *kk = reinterpret_cast<uint32_t *>(k4);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int np = (n + 4 * kRankWaves - 1) / (4 * kRankWaves) * (4 * kRankWaves);
+    for (int i = tid; i < np; i += kRankThreads) kk[i] = i < n ? keys[i] : 0xffffffffu;
+    __syncthreads();
+    const int t = blockIdx.x * kRankTargets + lane;
+    const int q = np / 4 / kRankWaves;   // units of four keys per wave
+    int c = 0;
+    if (t < n) {
+        const uint32_t key = kk[t];
+#pragma unroll 4
+        for (int j = wave * q; j < (wave + 1) * q; ++j) {
+            const uint4 v = k4[j];   // the same j on every lane: one broadcast read
+            const int jj = 4 * j;
+            c += (v.x < key || (v.x == key && jj < t)) ? 1 : 0;
+            c += (v.y < key || (v.y == key && jj + 1 < t)) ? 1 : 0;
+            c += (v.z < key || (v.z == key && jj + 2 < t)) ? 1 : 0;
+            c += (v.w < key || (v.w == key && jj + 3 < t)) ? 1 : 0;
+        }
+    }
+    part[wave][lane] = c;
+    __syncthreads();
+    if (wave == 0 && t < n) {
+        int r = 0;
+        for (int w = 0; w < kRankWaves; ++w) r += part[w][lane];
+        rank[t] = r;
+    }
+}
 
 __device__ __forceinline__ int block_excl_scan(int v, int *wsum, int &total)
 {
@@ -353,70 +435,18 @@ __device__ __forceinline__ int lower_digit_lds(const unsigned long long *sk, int
 }
 
 __global__ __launch_bounds__(kSmallThreads) void k_tree_small(
-    const float4 *rec, int stride_f4, int n, int npow2, int leaf, int cap, int *perm, int *begin,
+    const uint32_t *keys, const int *rank, int n, int leaf, int cap, int *perm, int *begin,
     int *end, int *level, int *child0, int *nchild, int *level_start_out, int *n_nodes_out,
     int *flags)
 {
-    extern __shared__ unsigned long long sk[];   // [npow2] (key << 32) | index
-    __shared__ double red[6][kSmallThreads / 64];
-    __shared__ double bb[6];
+    extern __shared__ unsigned long long sk[];   // [n] (key << 32) | index, sorted
     __shared__ int wsum[kSmallThreads / 64];
     __shared__ int ls[kMortonBits + 2];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
 
-    // key cube
-    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-    for (int i = tid; i < n; i += kSmallThreads) {
-        float4 a = rec[(size_t)i * stride_f4];
-        float4 b = rec[(size_t)i * stride_f4 + 1];
-        double v[3] = {(double)a.x + b.x, (double)a.y + b.y, (double)a.z + b.z};
-        for (int k = 0; k < 3; ++k) {
-            lo[k] = fmin(lo[k], v[k]);
-            hi[k] = fmax(hi[k], v[k]);
-        }
-    }
-    for (int off = 32; off > 0; off >>= 1)
-        for (int k = 0; k < 3; ++k) {
-            lo[k] = fmin(lo[k], __shfl_xor(lo[k], off));
-            hi[k] = fmax(hi[k], __shfl_xor(hi[k], off));
-        }
-    if (lane == 0)
-        for (int k = 0; k < 3; ++k) {
-            red[k][wave] = lo[k];
-            red[3 + k][wave] = hi[k];
-        }
+    for (int i = tid; i < n; i += kSmallThreads)
+        sk[rank[i]] = ((unsigned long long)keys[i] << 32) | (unsigned)i;
     __syncthreads();
-    if (tid == 0) {
-        for (int w = 1; w < kSmallThreads / 64; ++w)
-            for (int k = 0; k < 3; ++k) {
-                red[k][0] = fmin(red[k][0], red[k][w]);
-                red[3 + k][0] = fmax(red[3 + k][0], red[3 + k][w]);
-            }
-        const double l3[3] = {red[0][0], red[1][0], red[2][0]};
-        const double h3[3] = {red[3][0], red[4][0], red[5][0]};
-        bbox_cube(l3, h3, bb);
-    }
-    __syncthreads();
-
-    // keys and bitonic sort
-    for (int i = tid; i < npow2; i += kSmallThreads)
-        sk[i] = i < n ? ((unsigned long long)atom_key(rec, stride_f4, i, bb) << 32) | (unsigned)i
-                      : ~0ull;
-    __syncthreads();
-    // one compare-exchange pair (i, i + j) per thread and step, i with bit j clear
-    for (int k = 2; k <= npow2; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int p = tid; p < (npow2 >> 1); p += kSmallThreads) {
-                const int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
-                const int ixj = i | j;
-                const unsigned long long a = sk[i], b = sk[ixj];
-                if ((a > b) == ((i & k) == 0)) {
-                    sk[i] = b;
-                    sk[ixj] = a;
-                }
-            }
-            __syncthreads();
-        }
     for (int i = tid; i < n; i += kSmallThreads) perm[i] = (int)(sk[i] & 0xffffffffu);
 
     // octree, level by level
@@ -790,20 +820,24 @@ int build_source_tree(const TreeCallArgs &a, Workspace &ws, TreeDev &t, rism_sta
     t.sorted_rec = ws.alloc(rec32_bytes_of(a.sp.ns_pad) * a.npad);
     if (ws.status()) return ws.status();
 
-    // small trees: the whole build in one workgroup, keys sorted in LDS
-    int npow2 = 1;
-    while (npow2 < n) npow2 <<= 1;
+    // small trees: keys ranked by many workgroups, the octree built by one
     int dev = 0, lds_max = 0;
     RISM_HIP(hipGetDevice(&dev));
     RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t small_shm = (size_t)npow2 * sizeof(unsigned long long);
-    // (up to 8192 keys: beyond that the bitonic passes of one workgroup take
-    // longer than the multi-kernel radix sort)
-    const bool small = npow2 <= 8192 && small_shm + 4096 <= (size_t)lds_max;
+    const size_t small_shm = (size_t)n * sizeof(unsigned long long);
+    // (up to 8192 atoms: beyond that the quadratic ranking takes longer than
+    // the multi-kernel radix sort)
+    const bool small = n <= 8192 && small_shm + 4096 <= (size_t)lds_max;
     if (small) {
-        hipLaunchKernelGGL(k_tree_small, 1, kSmallThreads, small_shm, s, rec, stride_f4, n, npow2,
-                           leaf, t.cap_nodes, v0, t.begin, t.end, t.level, t.child0, t.nchild,
-                           t.level_start, t.n_nodes, flags);
+        if (n > 0) {
+            hipLaunchKernelGGL(k_tree_keys, 1, kSmallThreads, 0, s, rec, stride_f4, n, k0);
+            const int npad = (n + 4 * kRankWaves - 1) / (4 * kRankWaves) * (4 * kRankWaves);
+            hipLaunchKernelGGL(k_tree_rank, (n + kRankTargets - 1) / kRankTargets, kRankThreads,
+                               (size_t)npad * sizeof(uint32_t), s, (const uint32_t *)k0, n, v1);
+        }
+        hipLaunchKernelGGL(k_tree_small, 1, kSmallThreads, small_shm, s, (const uint32_t *)k0,
+                           (const int *)v1, n, leaf, t.cap_nodes, v0, t.begin, t.end, t.level,
+                           t.child0, t.nchild, t.level_start, t.n_nodes, flags);
         t.perm = v0;
     } else {
     const int nb = (n + kBlock - 1) / kBlock;
