@@ -91,6 +91,37 @@ __device__ inline bool cp_mac(const CpLevels &L, int lvl, int I, int J, int K, c
     return r2 < L.theta * L.theta * d2;
 }
 
+// The MAC terms of one cluster, formed as cp_mac forms them: the box centre
+// and the squared half-diagonal.  Kept in LDS for a cluster's chain of
+// ancestors, they turn each test into a distance and one comparison.
+struct CpMac {
+    double c[3], r2;
+};
+
+__device__ inline void cp_mac_terms(const CpLevels &L, int lvl, int I, int J, int K, CpMac &m)
+{
+    double lo[3], hi[3];
+    cp_box(L, lvl, I, J, K, lo, hi);
+    double r2 = 0;
+    for (int k = 0; k < 3; ++k) {
+        const double w = hi[k] - lo[k];
+        m.c[k] = 0.5 * (lo[k] + hi[k]);
+        r2 += 0.25 * w * w;
+    }
+    m.r2 = r2;
+}
+
+// Same result as cp_mac for the cluster whose terms m holds.
+__device__ inline bool cp_mac_at(const CpLevels &L, const CpMac &m, const double y[3])
+{
+    double d2 = 0;
+    for (int k = 0; k < 3; ++k) {
+        const double d = y[k] - m.c[k];
+        d2 += d * d;
+    }
+    return m.r2 < L.theta * L.theta * d2;
+}
+
 // Coarsest level in [stop, T] along the chain of the level-0 block (I0, J0,
 // K0) at which y is well separated; 0 if none.
 __device__ inline int cp_accept_level(const CpLevels &L, int I0, int J0, int K0, const double y[3],

@@ -412,10 +412,16 @@ __global__ __launch_bounds__(kBlock) void k_cp_classify(CpClassArgs a)
     __shared__ int beg[kClsWin];
     __shared__ int pre[kClsWin + 1];
     __shared__ int ws[2][kBlock / 64];
+    __shared__ CpMac mac[kCpMaxLev + 1];   // the block's ancestors, levels 1..T
     const int q = blockIdx.x;
     if (q >= a.nq || *a.bad) return;   // whole workgroup
     const CpLevels &L = a.L;
     const int I = q % L.cx[0], J = (q / L.cx[0]) % L.cy[0], K = q / (L.cx[0] * L.cy[0]);
+    if (threadIdx.x >= 1 && (int)threadIdx.x <= L.T) {
+        const int l = threadIdx.x;
+        cp_mac_terms(L, l, I >> l, J >> l, K >> l, mac[l]);
+    }
+    __syncthreads();
     double blo[3], bhi[3];
     cp_box(L, 0, I, J, K, blo, bhi);
     const double rs2 = a.rshort * a.rshort;
@@ -452,7 +458,12 @@ __global__ __launch_bounds__(kBlock) void k_cp_classify(CpClassArgs a)
                 i = beg[lo] + (t - pre[lo]);
                 double y[3];
                 atom_pos(a.rec, a.stride_f4, i, y);
-                const int lvl = L.T >= 1 ? cp_accept_level(L, I, J, K, y, 1) : 0;
+                int lvl = 0;   // coarsest ancestor at which y is well separated
+                for (int l = L.T; l >= 1; --l)
+                    if (cp_mac_at(L, mac[l], y)) {
+                        lvl = l;
+                        break;
+                    }
                 if (lvl == 0) {
                     cls = 1;
                 } else {
@@ -578,6 +589,7 @@ __global__ __launch_bounds__(kBlock) void k_cp_assign(CpAssignArgs a)
     __shared__ int wcount[kBlock / 64];
     __shared__ int pre[kCpChunkLeaves + 1];
     __shared__ int lbeg[kCpChunkLeaves];
+    __shared__ CpMac mac[kCpMaxLev + 1];   // the cluster and its ancestors, levels lvl..T
     const int item = blockIdx.x;
     if (*a.bad || item >= (int)*a.n_items) return;   // whole workgroup
     const int cl = a.it_cl[item];
@@ -585,6 +597,10 @@ __global__ __launch_bounds__(kBlock) void k_cp_assign(CpAssignArgs a)
     cp_decode(a.L, cl, lvl, I, J, K);
     double cc[3], rr;
     cp_centre(a.L, lvl, I, J, K, cc, rr);
+    if ((int)threadIdx.x >= lvl && (int)threadIdx.x <= a.L.T) {
+        const int l = threadIdx.x, sh = l - lvl;
+        cp_mac_terms(a.L, l, I >> sh, J >> sh, K >> sh, mac[l]);
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c0 = a.it_c0[item], nlf = a.it_c1[item] - c0;   // <= kCpChunkLeaves
     if (threadIdx.x == 0) {
@@ -618,9 +634,8 @@ __global__ __launch_bounds__(kBlock) void k_cp_assign(CpAssignArgs a)
             double y[3];
             atom_pos(a.rec, a.stride_f4, i, y);
             // well separated from this cluster and from none of its ancestors
-            acc = cp_mac(a.L, lvl, I, J, K, y) &&
-                  (lvl == a.L.T ||
-                   cp_accept_level(a.L, I << lvl, J << lvl, K << lvl, y, lvl + 1) == 0);
+            acc = cp_mac_at(a.L, mac[lvl], y);
+            for (int l = lvl + 1; acc && l <= a.L.T; ++l) acc = !cp_mac_at(a.L, mac[l], y);
             v.x = (float)(y[0] - cc[0]);
             v.y = (float)(y[1] - cc[1]);
             v.z = (float)(y[2] - cc[2]);
