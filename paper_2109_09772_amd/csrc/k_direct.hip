@@ -50,9 +50,10 @@ template <int NS>
 __global__ __launch_bounds__(kBlock) void k_stage(SiteParams sp, StageArgs a)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= a.npad) return;
+    const bool live = i < a.npad;   // every lane stays for the wave-wide maximum below
     double x = kFarAway, y = kFarAway, z = kFarAway, q = 0.0, sig = 0.0, eps = 0.0;
     bool real = i < a.n;
+    int r2max = 0;   // largest (1 + 1e-6) rc^2 of the atom's sites, as float bits
     if (real) {
         x = a.xyz[3 * i] - a.origin[0];
         y = a.xyz[3 * i + 1] - a.origin[1];
@@ -98,10 +99,16 @@ __global__ __launch_bounds__(kBlock) void k_stage(SiteParams sp, StageArgs a)
             if (a.lj_mode == LJ_CUT && rc[g] > 0.0) {
                 // positive floats order like their bit patterns
                 float r2f = (float)(rc[g] * rc[g]) * (1.0f + 1e-6f);
-                atomicMax(&a.err_flags[2], __float_as_int(r2f));
+                r2max = max(r2max, __float_as_int(r2f));
             }
         }
     }
+    if (a.lj_mode == LJ_CUT) {
+        // one atomic per wave
+        for (int off = 32; off > 0; off >>= 1) r2max = max(r2max, __shfl_xor(r2max, off));
+        if ((threadIdx.x & 63) == 0 && r2max > 0) atomicMax(&a.err_flags[2], r2max);
+    }
+    if (!live) return;
     if (a.rec64) {
         AtomF64<NS> r;
         r.x = x; r.y = y; r.z = z; r.q = q;
@@ -268,18 +275,25 @@ __device__ inline void smear_f64(const AsymParams &A, double d, double &fc, doub
     fh = (exp(-A.kappa * d) * erfc(A.a - x) - t2) / d;
 }
 
-// One thread per interval: the cubic through the four Chebyshev nodes of the
-// interval (Newton form, expanded to monomials in the local variable t).
-__global__ void k_smear_table(AsymParams A, float4 *tab)
+// Four threads per interval, one per Chebyshev node of the interval (the
+// kernel values are the costly part); the interval's first thread forms the
+// cubic through the four values (Newton form, expanded to monomials in the
+// local variable t).
+__global__ __launch_bounds__(256) void k_smear_table(AsymParams A, float4 *tab)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= kSmearIntervals) return;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = g >> 2, node = g & 3, lane = threadIdx.x & 63, lead = lane & ~3;
     const double h = 1.0 / A.tab_inv_h;
-    double t[4], vc[4], vh[4];
+    double t[4];
+    for (int j = 0; j < 4; ++j) t[j] = 0.5 * (1.0 - cos((2 * j + 1) * kPi / 8.0));
+    double fc = 0.0, fh = 0.0;
+    if (i < kSmearIntervals) smear_f64(A, (i + t[node]) * h, fc, fh);
+    double vc[4], vh[4];
     for (int j = 0; j < 4; ++j) {
-        t[j] = 0.5 * (1.0 - cos((2 * j + 1) * kPi / 8.0));
-        smear_f64(A, (i + t[j]) * h, vc[j], vh[j]);
+        vc[j] = __shfl(fc, lead + j);
+        vh[j] = __shfl(fh, lead + j);
     }
+    if (i >= kSmearIntervals || node != 0) return;
     double *v[2] = {vc, vh};
     for (int f = 0; f < 2; ++f) {
         double d0 = v[f][0], d1 = v[f][1], d2 = v[f][2], d3 = v[f][3];
@@ -303,7 +317,7 @@ __global__ void k_smear_table(AsymParams A, float4 *tab)
 
 int launch_smear_table(const AsymParams &a, float4 *tab, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_smear_table, (kSmearIntervals + 63) / 64, 64, 0, s, a, tab);
+    hipLaunchKernelGGL(k_smear_table, (4 * kSmearIntervals + 255) / 256, 256, 0, s, a, tab);
     RISM_HIP(hipGetLastError());
     return RISM_OK;
 }
