@@ -226,15 +226,20 @@ struct CpQueryArgs {
     const int *bad;                 // fill pass: lists sized too small, write nothing
     int *overflow;
     int fill;
+    int stack_w;   // LDS stack entries (cp_query_stack)
 };
 
 // Per-wave DFS stack of the neighbour queries (LDS, one wave per
 // workgroup).  A step pops up to 64 nodes from the top and pushes at most 8
 // children each; below the newest layer the stack keeps at most one partial
 // layer of at most 7 x 64 nodes per tree depth, so a tree of depth D =
-// kMortonBits needs at most 448 (D - 1) + 512 = 4544 slots.
+// kMortonBits needs at most 448 (D - 1) + 512 = 4544 slots.  Each node is
+// also pushed at most once per query (it has one parent), so the tree's node
+// capacity bounds the stack as well: the launch sizes the LDS stack to the
+// smaller bound, which lets more queries share a CU.
 constexpr int kQStackW = 4608;
 static_assert(kQStackW >= 448 * (kMortonBits - 1) + 512, "query stack bound");
+inline int cp_query_stack(int cap_nodes) { return cap_nodes < kQStackW ? cap_nodes : kQStackW; }
 
 __device__ __forceinline__ int wave_incl_scan(int v, int lane)
 {
@@ -338,7 +343,7 @@ __device__ __forceinline__ void cp_query(const CpQueryArgs &a, int q, int *stk)
             const int nc = (hit && nch > 0) ? nch : 0;
             const int incl = wave_incl_scan(nc, lane);
             const int total = __shfl(incl, 63);
-            if (sp + total > kQStackW) {
+            if (sp + total > a.stack_w) {
                 if (lane == 0) *a.overflow = 1;
                 break;
             }
@@ -358,7 +363,7 @@ __device__ __forceinline__ void cp_query(const CpQueryArgs &a, int q, int *stk)
 // rest b's (b.nq may be 0).
 __global__ __launch_bounds__(64) void k_cp_query(CpQueryArgs a, CpQueryArgs b)
 {
-    __shared__ int stk[kQStackW];
+    extern __shared__ int stk[];   // [a.stack_w]
     const int q = blockIdx.x;
     if (q < a.nq) cp_query(a, q, stk);
     else cp_query(b, q - a.nq, stk);
@@ -1351,6 +1356,8 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     qa.box = t.box;
     qa.n_nodes = t.n_nodes;
     qa.overflow = overflow;
+    qa.stack_w = cp_query_stack(t.cap_nodes);
+    const size_t qshm = (size_t)qa.stack_w * sizeof(int);
     hipLaunchKernelGGL(k_fill_int, 1, 64, 0, s, overflow, 1, 0);
     {
         // count pass of both query sets in one launch, then all five scans
@@ -1369,7 +1376,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         ql.items = nullptr;
         ql.acnt = lacnt;
         ql.fill = 0;
-        hipLaunchKernelGGL(k_cp_query, ncl + nleaf, 64, 0, s, qc, ql);
+        hipLaunchKernelGGL(k_cp_query, ncl + nleaf, 64, qshm, s, qc, ql);
         ScanBatch sb{};
         int na = 0;
         auto add = [&](uint32_t *arr, uint32_t *total, int n) {
@@ -1449,7 +1456,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             ql.fill = 1;
             ql.items = nullptr;
             ql.acnt = nullptr;
-            hipLaunchKernelGGL(k_cp_query, ncl + nleaf, 64, 0, s, qc, ql);
+            hipLaunchKernelGGL(k_cp_query, ncl + nleaf, 64, qshm, s, qc, ql);
             if (ncl > 0)
                 hipLaunchKernelGGL(k_cp_items, (ncl + kBlock - 1) / kBlock, kBlock, 0, s, ncl,
                                    ccnt, citems, cacnt, capre, (const int *)bad, it_cl, it_c0,
