@@ -535,13 +535,28 @@ __global__ __launch_bounds__(kBlock) void k_node_box(const float4 *rec, int stri
     const int nn = *n_nodes;
     for (int node = wave; node < nn; node += nw) {
         double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-        for (int i = begin[node] + lane; i < end[node]; i += 64) {
-            float4 a = rec[(size_t)i * stride_f4];
-            float4 b = rec[(size_t)i * stride_f4 + 1];
-            double v[3] = {(double)a.x + b.x, (double)a.y + b.y, (double)a.z + b.z};
-            for (int k = 0; k < 3; ++k) {
-                lo[k] = fmin(lo[k], v[k]);
-                hi[k] = fmax(hi[k], v[k]);
+        const int e = end[node];
+        // four atoms per lane per step, their loads issued together (min and
+        // max do not depend on the order)
+        for (int i0 = begin[node] + lane; i0 < e; i0 += 4 * 64) {
+            float4 a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + 64 * u;
+                if (i < e) {
+                    a[u] = rec[(size_t)i * stride_f4];
+                    b[u] = rec[(size_t)i * stride_f4 + 1];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (i0 + 64 * u >= e) break;
+                const double v[3] = {(double)a[u].x + b[u].x, (double)a[u].y + b[u].y,
+                                     (double)a[u].z + b[u].z};
+                for (int k = 0; k < 3; ++k) {
+                    lo[k] = fmin(lo[k], v[k]);
+                    hi[k] = fmax(hi[k], v[k]);
+                }
             }
         }
         for (int off = 32; off > 0; off >>= 1)

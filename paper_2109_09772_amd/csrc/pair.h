@@ -148,15 +148,19 @@ __device__ __forceinline__ void pair_eval(const Rec &at, const GridPt &g,
         dz = (g.zh - at.zh) + (g.zl - at.zl);
     }
     const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    // raw v_rsq_f32 (d2 is never denormal unless a point sits within 1e-19 A
-    // of an atom); a coincident point gets 1/d = 0: u is set to +inf through
-    // `hit`, and the smeared kernels take their d = 0 values from the table
-    const float ri = d2 > 0.f ? __builtin_amdgcn_rsqf(d2) : 0.f;
+    // raw v_rsq_f32 of d2 clamped to 1e-30: a coincident point (d2 = 0, FULL
+    // pairs only: a short-range atom is well separated from the point) gets a
+    // large finite 1/d that reaches u alone (set to +inf through `hit`), and
+    // d = d2/sqrt(d2) stays ~0, so the smeared kernels take their d = 0
+    // values from the table
+    const float ri = __builtin_amdgcn_rsqf(fmaxf(d2, 1e-30f));
     if (FULL) hit |= (d2 == 0.f);
     if (LJM != LJ_NONE) {
         const float r2 = ri * ri;
         float r6 = r2 * r2 * r2;
         if (LJM == LJ_CUT1) r6 = d2 < at.rc2[0] ? r6 : 0.f;
+        // (A r^-6 - B) r^-6: the difference is formed before the product, so
+        // near the zero crossing of the LJ term it carries no cancellation
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             float r6s = r6;
