@@ -922,25 +922,20 @@ __global__ __launch_bounds__(kBlock) void k_cp_reduce(int nclusters, int np, con
 
 // ----------------------------------------------------------------- downward
 
-// Level-1 clusters gather the far field of their whole ancestor chain: with
-// A_l the level-l ancestor, the proxy values carried down are
-//   acc_T = V[A_T],  acc_l = V[A_l] + (Mx (x) My (x) Mz) acc_{l+1},
-// and V[A_1] takes acc_1.  M[k][m] = L^P_m(s^C_k): the parent's interpolant
-// evaluated at the child's proxy points, separably, in FP64.  Taylor moments
-// (taylor != 0): M[k][m] = C(m, k) delta^(m - k) for m >= k, delta = child
-// centre - parent centre: the parent's polynomial re-expanded about the
-// child's centre, again separably.  One workgroup per level-1 cluster; the
-// levels above 1 keep their own values (only level 1 is read later), so
-// siblings repeat their common ancestors' steps instead of waiting for a
-// launch per level.  The matrices of all T - 1 steps are formed first, a row
-// per thread; nc components (1 or 2, as the LDS allows) per pass.
+// Children at level lvl: V[child] += (Mx (x) My (x) Mz) V[parent], one
+// launch per level from the top down, so that the parent already holds its
+// own ancestors' far field.  M[k][m] = L^P_m(s^C_k): the parent's
+// interpolant evaluated at the child's proxy points, separably, in FP64.
+// Taylor moments (taylor != 0): M[k][m] = C(m, k) delta^(m - k) for m >= k,
+// delta = child centre - parent centre: the parent's polynomial re-expanded
+// about the child's centre, again separably.  One workgroup per child, nc
+// components (1 or 2, as the LDS allows) per pass.
 constexpr int kDownThreads = 1024;
 
-inline size_t cp_down_lds(int degree, int T, int nc)
+inline size_t cp_down_lds(int degree, int nc)
 {
     const size_t n1 = degree + 1, np = n1 * n1 * n1;
-    const size_t steps = T > 1 ? T - 1 : 0;
-    return (steps * 3 * n1 * n1 + 3 * (size_t)nc * np) * sizeof(double);
+    return (3 * n1 * n1 + 3 * (size_t)nc * np) * sizeof(double);
 }
 
 // s = sum_m row[m] src[m stride], m < n1, unrolled to the largest degree so
@@ -955,23 +950,22 @@ __device__ __forceinline__ double dot_lds(const double *row, const double *src, 
     return s;
 }
 
-__global__ __launch_bounds__(kDownThreads) void k_cp_down(CpLevels L, int degree, int taylor,
-                                                          int nc, double *V)
+__global__ __launch_bounds__(kDownThreads) void k_cp_down(CpLevels L, int lvl, int degree,
+                                                          int taylor, int nc, double *V)
 {
     extern __shared__ double sm[];
-    const int n1 = degree + 1, np = n1 * n1 * n1, ne = nc * np, nsteps = L.T - 1;
-    double *Ms = sm;                              // [nsteps][3][n1][n1]
-    double *acc = Ms + nsteps * 3 * n1 * n1;      // [nc][np]
-    double *t1 = acc + ne;                        // [nc][np]
-    double *t2 = t1 + ne;                         // [nc][np]
+    const int n1 = degree + 1, np = n1 * n1 * n1, ne = nc * np;
+    double *M = sm;                 // [3][n1][n1]
+    double *src = M + 3 * n1 * n1;  // [nc][np]
+    double *t1 = src + ne;          // [nc][np]
+    double *t2 = t1 + ne;           // [nc][np]
     const int q = blockIdx.x;
-    const int I1 = q % L.cx[1], J1 = (q / L.cx[1]) % L.cy[1], K1 = q / (L.cx[1] * L.cy[1]);
-    // step st takes level lvl = T - 1 - st from its parent
-    for (int r = threadIdx.x; r < nsteps * 3 * n1; r += kDownThreads) {
-        const int st = r / (3 * n1), ax = (r / n1) % 3, k = r % n1;
-        const int lvl = L.T - 1 - st;
-        const int I = I1 >> (lvl - 1), J = J1 >> (lvl - 1), K = K1 >> (lvl - 1);
-        double *row = Ms + ((st * 3 + ax) * n1 + k) * n1;
+    const int I = q % L.cx[lvl], J = (q / L.cx[lvl]) % L.cy[lvl], K = q / (L.cx[lvl] * L.cy[lvl]);
+    const int id = cp_id(L, lvl, I, J, K);
+    const int pid = cp_id(L, lvl + 1, I >> 1, J >> 1, K >> 1);
+    if (threadIdx.x < 3 * n1) {
+        const int ax = threadIdx.x / n1, k = threadIdx.x % n1;
+        double *row = M + (ax * n1 + k) * n1;
         if (taylor) {
             double cc[3], cp[3], rr;
             cp_centre(L, lvl, I, J, K, cc, rr);
@@ -992,40 +986,29 @@ __global__ __launch_bounds__(kDownThreads) void k_cp_down(CpLevels L, int degree
         }
     }
     for (int comp0 = 0; comp0 < 2; comp0 += nc) {
-        __syncthreads();   // acc is free (and, at first, the matrices are formed)
-        {
-            const int sh = L.T - 1;
-            const int top = cp_id(L, L.T, I1 >> sh, J1 >> sh, K1 >> sh);
-            for (int e = threadIdx.x; e < ne; e += kDownThreads)
-                acc[e] = V[((size_t)top * 2 + comp0) * np + e];
+        if (comp0 > 0) __syncthreads();   // the previous pass is done with src
+        for (int e = threadIdx.x; e < ne; e += kDownThreads)
+            src[e] = V[((size_t)pid * 2 + comp0) * np + e];
+        __syncthreads();   // M and src ready
+        // entry e = c np + k, k = (z, y, x) with x fastest; contract x, then y,
+        // then z
+        for (int e = threadIdx.x; e < ne; e += kDownThreads) {
+            const int c = e / np, k = e - c * np;
+            const int k1 = k % n1, rest = k / n1;
+            t1[e] = dot_lds(M + (0 * n1 + k1) * n1, src + c * np + rest * n1, 1, n1);
         }
-        for (int st = 0; st < nsteps; ++st) {
-            const int lvl = L.T - 1 - st;
-            const int id = cp_id(L, lvl, I1 >> (lvl - 1), J1 >> (lvl - 1), K1 >> (lvl - 1));
-            const double *M = Ms + st * 3 * n1 * n1;
-            __syncthreads();   // acc ready
-            // entry e = c np + k, k = (z, y, x) with x fastest; contract x,
-            // then y, then z
-            for (int e = threadIdx.x; e < ne; e += kDownThreads) {
-                const int c = e / np, k = e - c * np;
-                const int k1 = k % n1, rest = k / n1;
-                t1[e] = dot_lds(M + (0 * n1 + k1) * n1, acc + c * np + rest * n1, 1, n1);
-            }
-            __syncthreads();
-            for (int e = threadIdx.x; e < ne; e += kDownThreads) {
-                const int c = e / np, k = e - c * np;
-                const int k1 = k % n1, k2 = (k / n1) % n1, m3 = k / (n1 * n1);
-                t2[e] = dot_lds(M + (1 * n1 + k2) * n1, t1 + c * np + m3 * n1 * n1 + k1, n1, n1);
-            }
-            __syncthreads();
-            for (int e = threadIdx.x; e < ne; e += kDownThreads) {
-                const int c = e / np, k = e - c * np;
-                const int k12 = k % (n1 * n1), k3 = k / (n1 * n1);
-                const double s = dot_lds(M + (2 * n1 + k3) * n1, t2 + c * np + k12, n1 * n1, n1);
-                double *v = V + ((size_t)id * 2 + comp0) * np + e;
-                if (lvl > 1) acc[e] = *v + s;
-                else *v += s;
-            }
+        __syncthreads();
+        for (int e = threadIdx.x; e < ne; e += kDownThreads) {
+            const int c = e / np, k = e - c * np;
+            const int k1 = k % n1, k2 = (k / n1) % n1, m3 = k / (n1 * n1);
+            t2[e] = dot_lds(M + (1 * n1 + k2) * n1, t1 + c * np + m3 * n1 * n1 + k1, n1, n1);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < ne; e += kDownThreads) {
+            const int c = e / np, k = e - c * np;
+            const int k12 = k % (n1 * n1), k3 = k / (n1 * n1);
+            V[((size_t)id * 2 + comp0) * np + e] +=
+                dot_lds(M + (2 * n1 + k3) * n1, t2 + c * np + k12, n1 * n1, n1);
         }
     }
 }
@@ -1407,12 +1390,11 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         set_error("Taylor treecode: order above 12 or its LDS beyond this device");
         return RISM_E_UNSUPPORTED;
     }
-    if (leaf_shm + 2048 > (size_t)lds_max || cp_down_lds(deg, L.T, 1) > (size_t)lds_max) {
-        set_error("treecode_cp: degree / batch edge / grid depth too large for the LDS of this "
-                  "device");
+    if (leaf_shm + 2048 > (size_t)lds_max || cp_down_lds(deg, 1) > (size_t)lds_max) {
+        set_error("treecode_cp: degree / batch edge too large for the LDS of this device");
         return RISM_E_UNSUPPORTED;
     }
-    const int down_nc = cp_down_lds(deg, L.T, 2) <= (size_t)lds_max ? 2 : 1;
+    const int down_nc = cp_down_lds(deg, 2) <= (size_t)lds_max ? 2 : 1;
     const bool want_stats = a.opts->flags & RISM_FLAG_STATS;
     unsigned long long *work = want_stats ? ws.get<unsigned long long>(4) : nullptr;
     uint32_t *nd = ws.get<uint32_t>(nleaf), *nsh = ws.get<uint32_t>(nleaf);
@@ -1542,9 +1524,9 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             PhaseTimer pt(ev, RISM_PHASE_DOWNWARD, s);
             hipLaunchKernelGGL(k_cp_reduce, ncl, kBlock, 0, s, ncl, np, citems, (const int *)bad,
                                part, V);
-            if (L.T >= 2)
-                hipLaunchKernelGGL(k_cp_down, L.cx[1] * L.cy[1] * L.cz[1], kDownThreads,
-                                   cp_down_lds(deg, L.T, down_nc), s, L, deg, (int)taylor, down_nc,
+            for (int lvl = L.T - 1; lvl >= 1; --lvl)
+                hipLaunchKernelGGL(k_cp_down, L.cx[lvl] * L.cy[lvl] * L.cz[lvl], kDownThreads,
+                                   cp_down_lds(deg, down_nc), s, L, lvl, deg, (int)taylor, down_nc,
                                    V);
         }
         RISM_HIP(hipGetLastError());
