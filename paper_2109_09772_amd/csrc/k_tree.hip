@@ -319,6 +319,10 @@ __global__ __launch_bounds__(kBlock) void k_split_write(const uint32_t *keys, in
 // Produces the same permutation and nodes as the multi-kernel build.
 constexpr int kSmallThreads = 1024;
 constexpr int kRankTargets = 64;   // atoms ranked per workgroup
+// Largest tree built this way: the ranking costs n^2 / 64 comparisons per
+// lane, about 20 us at 16K atoms, still below the multi-kernel radix sort and
+// level-by-level split (about 0.3 ms at 14,000 atoms).
+constexpr int kSmallTreeMax = 16384;
 
 // Morton keys of a small tree's atoms, by one workgroup: the key cube from
 // a block-wide reduction, then one key per atom.
@@ -840,9 +844,8 @@ int build_source_tree(const TreeCallArgs &a, Workspace &ws, TreeDev &t, rism_sta
     RISM_HIP(hipGetDevice(&dev));
     RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const size_t small_shm = (size_t)n * sizeof(unsigned long long);
-    // (up to 8192 atoms: beyond that the quadratic ranking takes longer than
-    // the multi-kernel radix sort)
-    const bool small = n <= 8192 && small_shm + 4096 <= (size_t)lds_max;
+    // (up to kSmallTreeMax atoms, and keys that fit the LDS of one workgroup)
+    const bool small = n <= kSmallTreeMax && small_shm + 4096 <= (size_t)lds_max;
     if (small) {
         if (n > 0) {
             hipLaunchKernelGGL(k_tree_keys, 1, kSmallThreads, 0, s, rec, stride_f4, n, k0);
