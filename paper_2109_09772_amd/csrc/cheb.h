@@ -40,6 +40,25 @@ __device__ inline void lagrange_to(double x, double lo, double hi, int n, double
         dst[k * stride] = exact >= 0 ? (k == exact ? 1.0 : 0.0) : dst[k * stride] * inv;
 }
 
+// lagrange_to with the cosines cos(k pi / n), k = 0..n, given (the same
+// values cheb_point forms): the points are lo + (hi - lo)(1 + c_k)/2.
+__device__ inline void lagrange_to_cos(double x, double lo, double hi, int n, const double *cosk,
+                                       double *dst, int stride)
+{
+    double den = 0.0;
+    int exact = -1;
+    for (int k = 0; k <= n; ++k) {
+        double d = x - (lo + (hi - lo) * 0.5 * (1.0 + cosk[k]));
+        if (d == 0.0) exact = k;
+        double t = bary_weight(k, n) / d;
+        dst[k * stride] = t;
+        den += t;
+    }
+    const double inv = 1.0 / den;
+    for (int k = 0; k <= n; ++k)
+        dst[k * stride] = exact >= 0 ? (k == exact ? 1.0 : 0.0) : dst[k * stride] * inv;
+}
+
 // Element ax (0, 1, 2) of a three-vector held in registers (a run-time index
 // into a private array would place it in scratch memory).
 __device__ __forceinline__ double pick3(const double *v, int ax)

@@ -62,6 +62,38 @@ __device__ inline void cp_proxy_box(const CpLevels &L, int lvl, int I, int J, in
     }
 }
 
+// One axis of cp_box, cp_proxy_box and the centre of cp_centre (the same
+// values: each axis of those is formed from its own index alone).
+__host__ __device__ inline void cp_box_axis(const CpLevels &L, int lvl, int ax, int I, double &lo,
+                                            double &hi)
+{
+    const int e = L.B << lvl;
+    const int n = ax == 0 ? L.nx : (ax == 1 ? L.ny : L.nz);
+    const double h = ax == 0 ? L.h[0] : (ax == 1 ? L.h[1] : L.h[2]);
+    const int il = I * e;
+    const int ih = (il + e < n ? il + e : n) - 1;
+    lo = il * h;
+    hi = ih * h;
+}
+
+__device__ inline void cp_proxy_axis(const CpLevels &L, int lvl, int ax, int I, double &lo,
+                                     double &hi)
+{
+    cp_box_axis(L, lvl, ax, I, lo, hi);
+    const double h = ax == 0 ? L.h[0] : (ax == 1 ? L.h[1] : L.h[2]);
+    if (hi - lo < 0.25 * h) {
+        lo -= 0.5 * h;
+        hi += 0.5 * h;
+    }
+}
+
+__device__ inline double cp_centre_axis(const CpLevels &L, int lvl, int ax, int I)
+{
+    double lo, hi;
+    cp_box_axis(L, lvl, ax, I, lo, hi);
+    return 0.5 * (lo + hi);
+}
+
 __device__ inline void cp_decode(const CpLevels &L, int id, int &lvl, int &I, int &J, int &K)
 {
     lvl = 1;

@@ -920,6 +920,93 @@ __global__ __launch_bounds__(kBlock) void k_cp_reduce(int nclusters, int np, con
     }
 }
 
+// ----------------------------------------------------------------- tables
+
+// One-axis tables of the target octree, formed once per call (they depend on
+// the grid, the batch edge and the degree only): the interpolation matrix
+// M[k][m] of every downward step, for each level lvl = 1..T-1, axis and
+// cluster index along that axis, and the level-1 basis at every grid
+// coordinate of each axis (rounded up to whole level-0 blocks).  One row of
+// n + 1 values per thread; the same arithmetic as forming them in place.
+struct CpTabArgs {
+    CpLevels L;
+    int degree, taylor;
+    int mrow0[kCpMaxLev + 1][3];   // first M row of (lvl, axis)
+    int nrow_m;                    // M rows in all
+    int lrow0[3], nrow_l;          // first level-1 basis row of each axis; rows in all
+    double *M, *Lg;
+};
+
+inline void cp_tab_layout(const CpLevels &L, int n1, CpTabArgs &t)
+{
+    int r = 0;
+    for (int lvl = 1; lvl < L.T; ++lvl)
+        for (int ax = 0; ax < 3; ++ax) {
+            t.mrow0[lvl][ax] = r;
+            r += (ax == 0 ? L.cx[lvl] : (ax == 1 ? L.cy[lvl] : L.cz[lvl])) * n1;
+        }
+    t.nrow_m = r;
+    r = 0;
+    for (int ax = 0; ax < 3; ++ax) {
+        t.lrow0[ax] = r;
+        r += (ax == 0 ? L.cx[0] : (ax == 1 ? L.cy[0] : L.cz[0])) * L.B;
+    }
+    t.nrow_l = r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cp_tables(CpTabArgs a)
+{
+    __shared__ double cosk[kMaxDeg + 1];   // cos(k pi / n), shared by every row
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    const CpLevels &L = a.L;
+    const int n1 = a.degree + 1;
+    if ((int)threadIdx.x < n1) cosk[threadIdx.x] = cos(kPi * threadIdx.x / a.degree);
+    __syncthreads();
+    if (r < a.nrow_m) {
+        int lvl = 1, ax = 0;
+        for (int l = 1; l < L.T; ++l)
+            for (int x = 0; x < 3; ++x)
+                if (r >= a.mrow0[l][x]) {
+                    lvl = l;
+                    ax = x;
+                }
+        const int rel = r - a.mrow0[lvl][ax], I = rel / n1, k = rel % n1;
+        double *row = a.M + (size_t)r * n1;
+        if (a.taylor) {
+            // C(m, k) delta^(m - k), delta = child centre - parent centre
+            const double dl = cp_centre_axis(L, lvl, ax, I) - cp_centre_axis(L, lvl + 1, ax, I >> 1);
+            for (int m = 0; m < k; ++m) row[m] = 0.0;
+            double c = 1.0;
+            for (int m = k; m < n1; ++m) {
+                row[m] = c;
+                c = c * dl * (double)(m + 1) / (double)(m + 1 - k);
+            }
+        } else {
+            double clo, chi, plo, phi;
+            cp_proxy_axis(L, lvl, ax, I, clo, chi);
+            cp_proxy_axis(L, lvl + 1, ax, I >> 1, plo, phi);
+            lagrange_to_cos(clo + (chi - clo) * 0.5 * (1.0 + cosk[k]), plo, phi, a.degree, cosk,
+                            row, 1);
+        }
+    } else if (r < a.nrow_m + a.nrow_l) {
+        const int rl = r - a.nrow_m;
+        const int ax = rl >= a.lrow0[2] ? 2 : (rl >= a.lrow0[1] ? 1 : 0);
+        const int i = rl - a.lrow0[ax];   // grid coordinate along ax
+        const int I1 = (i / L.B) >> 1;     // level-1 cluster along ax
+        const double x = i * (ax == 0 ? L.h[0] : (ax == 1 ? L.h[1] : L.h[2]));
+        double *row = a.Lg + (size_t)rl * n1;
+        if (a.taylor) {   // (x - c)^k about the level-1 centre
+            const double dx = x - cp_centre_axis(L, 1, ax, I1);
+            double pw = 1.0;
+            for (int k = 0; k < n1; ++k, pw *= dx) row[k] = pw;
+        } else {          // L_k(x) of the level-1 proxy points
+            double lo, hi;
+            cp_proxy_axis(L, 1, ax, I1, lo, hi);
+            lagrange_to_cos(x, lo, hi, a.degree, cosk, row, 1);
+        }
+    }
+}
+
 // ----------------------------------------------------------------- downward
 
 // Children at level lvl: V[child] += (Mx (x) My (x) Mz) V[parent], one
@@ -928,8 +1015,9 @@ __global__ __launch_bounds__(kBlock) void k_cp_reduce(int nclusters, int np, con
 // interpolant evaluated at the child's proxy points, separably, in FP64.
 // Taylor moments (taylor != 0): M[k][m] = C(m, k) delta^(m - k) for m >= k,
 // delta = child centre - parent centre: the parent's polynomial re-expanded
-// about the child's centre, again separably.  One workgroup per child, nc
-// components (1 or 2, as the LDS allows) per pass.
+// about the child's centre, again separably.  The rows come from the
+// per-call tables (k_cp_tables).  One workgroup per child, nc components (1
+// or 2, as the LDS allows) per pass.
 constexpr int kDownThreads = 1024;
 
 inline size_t cp_down_lds(int degree, int nc)
@@ -951,7 +1039,8 @@ __device__ __forceinline__ double dot_lds(const double *row, const double *src, 
 }
 
 __global__ __launch_bounds__(kDownThreads) void k_cp_down(CpLevels L, int lvl, int degree,
-                                                          int taylor, int nc, double *V)
+                                                          int nc, const double *Mtab,
+                                                          int3 mrow0, double *V)
 {
     extern __shared__ double sm[];
     const int n1 = degree + 1, np = n1 * n1 * n1, ne = nc * np;
@@ -963,27 +1052,11 @@ __global__ __launch_bounds__(kDownThreads) void k_cp_down(CpLevels L, int lvl, i
     const int I = q % L.cx[lvl], J = (q / L.cx[lvl]) % L.cy[lvl], K = q / (L.cx[lvl] * L.cy[lvl]);
     const int id = cp_id(L, lvl, I, J, K);
     const int pid = cp_id(L, lvl + 1, I >> 1, J >> 1, K >> 1);
-    if (threadIdx.x < 3 * n1) {
-        const int ax = threadIdx.x / n1, k = threadIdx.x % n1;
-        double *row = M + (ax * n1 + k) * n1;
-        if (taylor) {
-            double cc[3], cp[3], rr;
-            cp_centre(L, lvl, I, J, K, cc, rr);
-            cp_centre(L, lvl + 1, I >> 1, J >> 1, K >> 1, cp, rr);
-            const double dl = pick3(cc, ax) - pick3(cp, ax);
-            for (int m = 0; m < k; ++m) row[m] = 0.0;
-            double c = 1.0;   // C(m, k) dl^(m - k), m = k, k + 1, ...
-            for (int m = k; m < n1; ++m) {
-                row[m] = c;
-                c = c * dl * (double)(m + 1) / (double)(m + 1 - k);
-            }
-        } else {
-            double cb[6], pbx[6];
-            cp_proxy_box(L, lvl, I, J, K, cb);
-            cp_proxy_box(L, lvl + 1, I >> 1, J >> 1, K >> 1, pbx);
-            lagrange_to(cheb_point(pick3(cb, ax), pick3(cb + 3, ax), k, degree), pick3(pbx, ax),
-                        pick3(pbx + 3, ax), degree, row, 1);
-        }
+    // the step's three one-axis matrices, rows formed by k_cp_tables
+    for (int t = threadIdx.x; t < 3 * n1 * n1; t += kDownThreads) {
+        const int ax = t / (n1 * n1), km = t % (n1 * n1);
+        const int r0 = ax == 0 ? mrow0.x + I * n1 : (ax == 1 ? mrow0.y + J * n1 : mrow0.z + K * n1);
+        M[t] = Mtab[(size_t)r0 * n1 + km];
     }
     for (int comp0 = 0; comp0 < 2; comp0 += nc) {
         if (comp0 > 0) __syncthreads();   // the previous pass is done with src
@@ -1027,6 +1100,8 @@ struct CpLeafArgs {
     const int *order;          // block -> level-0 block, heaviest first
     const int *bad;            // lists sized too small: do nothing
     const double *V;           // proxy values (Taylor: moments) of level >= 1 clusters
+    const double *Lg;          // level-1 basis rows per grid coordinate (k_cp_tables)
+    int lrow0[3];              // first row of each axis in Lg
     int degree, np;
     int taylor;                // basis: Lagrange (0) or monomials about the centre (1)
     unsigned long long *work;  // optional: [0] direct pairs, [1] short-range pairs
@@ -1108,23 +1183,12 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
 
     // ------------------------------- far: first two contractions, per block
     if (L.T >= 1) {
-        double pb[6], cc[3], rr;
-        cp_proxy_box(L, 1, I >> 1, J >> 1, K >> 1, pb);
-        cp_centre(L, 1, I >> 1, J >> 1, K >> 1, cc, rr);
-        // level-1 ancestor basis tables at the block's point coordinates:
-        // L_k(x), or (x - c)^k for Taylor moments
-        for (int t = threadIdx.x; t < 3 * B; t += NT) {
-            const int ax = t / B, l = t % B;
+        // level-1 ancestor basis at the block's point coordinates, L_k(x) or
+        // (x - c)^k for Taylor moments, copied from the per-call table
+        for (int t = threadIdx.x; t < 3 * B * n1; t += NT) {
+            const int ax = t / (B * n1), lk = t % (B * n1);
             const int b0 = ax == 0 ? i0 : (ax == 1 ? j0 : k0);
-            double *row = Lb + (ax * B + l) * n1;
-            if (a.taylor) {
-                const double dx = (b0 + l) * pick3(g.h, ax) - pick3(cc, ax);
-                double pw = 1.0;
-                for (int k = 0; k < n1; ++k, pw *= dx) row[k] = pw;
-            } else {
-                lagrange_to((b0 + l) * pick3(g.h, ax), pick3(pb, ax), pick3(pb + 3, ax), a.degree,
-                            row, 1);
-            }
+            Lb[t] = a.Lg[(size_t)(a.lrow0[ax] + b0) * n1 + lk];
         }
         const int a1 = cp_id(L, 1, I >> 1, J >> 1, K >> 1);
         for (int comp = 0; comp < NCOMP; ++comp) {
@@ -1400,7 +1464,16 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     uint32_t *nd = ws.get<uint32_t>(nleaf), *nsh = ws.get<uint32_t>(nleaf);
     int *order = ws.get<int>(nleaf);
     double *V = ws.get<double>((size_t)(ncl + 1) * 2 * np);
+    CpTabArgs ta{};
+    ta.L = L;
+    ta.degree = deg;
+    ta.taylor = taylor;
+    cp_tab_layout(L, n1, ta);
+    ta.M = ws.get<double>((size_t)(ta.nrow_m + 1) * n1);
+    ta.Lg = ws.get<double>((size_t)ta.nrow_l * n1);
     if (ws.status()) return ws.status();
+    hipLaunchKernelGGL(k_cp_tables, (ta.nrow_m + ta.nrow_l + kBlock - 1) / kBlock, kBlock, 0, s,
+                       ta);
 
     // Everything after the counts, with buffers of the given capacities.
     auto second_half = [&](const CpCaps &cap) -> int {
@@ -1526,7 +1599,9 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
                                part, V);
             for (int lvl = L.T - 1; lvl >= 1; --lvl)
                 hipLaunchKernelGGL(k_cp_down, L.cx[lvl] * L.cy[lvl] * L.cz[lvl], kDownThreads,
-                                   cp_down_lds(deg, down_nc), s, L, lvl, deg, (int)taylor, down_nc,
+                                   cp_down_lds(deg, down_nc), s, L, lvl, deg, down_nc,
+                                   (const double *)ta.M,
+                                   make_int3(ta.mrow0[lvl][0], ta.mrow0[lvl][1], ta.mrow0[lvl][2]),
                                    V);
         }
         RISM_HIP(hipGetLastError());
@@ -1546,6 +1621,8 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         la.order = order;
         la.bad = bad;
         la.V = V;
+        la.Lg = ta.Lg;
+        for (int ax = 0; ax < 3; ++ax) la.lrow0[ax] = ta.lrow0[ax];
         la.degree = deg;
         la.np = np;
         la.taylor = taylor;
