@@ -108,7 +108,8 @@ def test_point_on_atom_and_kappa_zero(oracle, method):
         _check(h, hr, method, "h")
 
 
-@pytest.mark.parametrize("method", ["direct_f64", "direct_f32c"])
+@pytest.mark.parametrize("method", ["direct_f64", "direct_f32c", "treecode", "treecode_cp",
+                                    "treecode_taylor"])
 def test_no_atoms_gives_zero(method):
     api = _api()
     wl = W.tiny(n_atoms=3, dims=(5, 6, 7))

@@ -165,3 +165,25 @@ def test_cp_buffer_reuse_across_calls(oracle):
         assert_close_grid(got[0], ur, 1e-6, cap=FP32_CAP, what=f"{name} u")
         assert_close_grid(got[1], cr, 1e-6, cap=FP32_CAP, what=f"{name} c")
         assert_close_grid(got[2], hr, 1e-6, cap=FP32_CAP, what=f"{name} h")
+
+
+@pytest.mark.parametrize("method", METHODS + ["treecode_taylor"])
+@pytest.mark.parametrize("n", [1, 2, 5])
+def test_few_atoms_one_on_a_grid_point(oracle, method, n):
+    """A handful of atoms (a one-leaf source tree; with one atom the ranked
+    Morton sort and the octree are trivial), one of them exactly on a grid
+    point: u is +inf there, c and h take their d -> 0 limits, and every other
+    point matches the oracle."""
+    wl = W.tiny(n_atoms=n, dims=(17, 15, 13), seed=9, spacing=0.5)
+    g = wl.grid
+    wl.solute.q[:] = np.linspace(-0.6, 0.8, n) if n > 1 else 0.7
+    wl.solute.xyz[0] = g.origin + g.spacing * np.array([6, 5, 4])
+    th, dg = TOL_PARAMS.get(method, (0.3, 10))
+    (u, c, h), _ = _run(wl, method=method, theta=th, degree=dg)
+    ur, cr, hr = _oracle_grids(oracle, wl)
+    u = _np(u)
+    assert np.isposinf(u[:, 4, 5, 6]).all()
+    assert np.isfinite(_np(c)).all() and np.isfinite(_np(h)).all()
+    assert_close_grid(u, ur, 1e-6, cap=FP32_CAP, what="u")
+    assert_close_grid(_np(c), cr, 1e-6, cap=FP32_CAP, what="c")
+    assert_close_grid(_np(h), hr, 1e-6, cap=FP32_CAP, what="h")
