@@ -79,26 +79,34 @@ __global__ __launch_bounds__(kAkThreads) void k_phase_tables(const double *xyz, 
 // run on v_mfma_f32_32x32x2_f32 with K = 2 holding the real and imaginary
 // parts of one atom's factors: A[i][k] = (Re, Im) Z[a][jz_i], and
 //   B = (Re T, -Im T) for Re S,   B = (Im T, Re T) for Im S.
-// A workgroup owns 32 MFMA columns, 4 rows (one per wave) and 64 jz (two
-// 32-row tiles per wave: four independent accumulator chains per wave).
-// Columns are 32 consecutive jx and rows are jy (YC = false: the full
-// 32-column tiles of the half grid), or columns are jy and rows the jx
-// past the last full tile (YC = true: the Nyquist column of an even nx, or
-// every jx of a half grid narrower than 32).  The phase factors of 32 atoms
-// at a time (the columns' and rows' ex / ey and the 64 jz's Q ez: 25 KB) are
-// staged in LDS, double buffered: the next 32 atoms are fetched into
-// registers while the matrix cores work on the current ones.  T is formed
-// per lane.  FP32 matrix sums over 32 atoms are flushed into FP64 registers.
+// A workgroup owns 32 MFMA columns, 4 rows (one per wave) and 32 jz (one
+// 32-row tile per wave: two accumulator chains, real and imaginary).  The
+// single tile keeps a wave at about 160 registers, so three waves share a
+// SIMD and one wave's FP64 flushes and operand preparation run under another
+// wave's matrix instructions (two tiles per wave needed 312 registers, one
+// wave per SIMD, and kept the matrix pipe busy 56 % of the time).  Columns
+// are 32 consecutive jx and rows are jy (YC = false: the full 32-column tiles
+// of the half grid), or columns are jy and rows the jx past the last full
+// tile (YC = true: the Nyquist column of an even nx, or every jx of a half
+// grid narrower than 32).  The phase factors of 32 atoms at a time (the
+// columns' and rows' ex / ey and the 32 jz's Q ez: 17 KB) are staged in LDS,
+// double buffered: the next 32 atoms are fetched into registers while the
+// matrix cores work on the current ones.  T is formed per lane.  FP32 matrix
+// sums over 32 atoms are flushed into FP64 registers.
 // The tables are padded to a multiple of 32 atoms with Q = 0, so no atom
 // needs a test; columns and rows past the grid run on clamped indices and
 // are not stored.
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kMfCols = 32;    // MFMA columns per workgroup
-constexpr int kMfZ = 64;       // jz per workgroup
+constexpr int kMfZT = 1;       // 32-row jz tiles per wave
+constexpr int kMfZ = 32 * kMfZT;   // jz per workgroup
 constexpr int kMfWaves = 4;    // rows per workgroup, one per wave
 constexpr int kMfFlush = 32;   // atoms per LDS stage and per FP32 matrix sum
 constexpr int kMfThreads = 64 * kMfWaves;
+constexpr int kMfZPer = kMfFlush * kMfZ / kMfThreads;      // staged Q ez values per thread
+constexpr int kMfCPer = kMfFlush * kMfCols / kMfThreads;   // staged column factors per thread
+static_assert(kMfZPer >= 1 && kMfCPer >= 1 && kMfFlush * kMfWaves <= kMfThreads, "staging");
 
 struct MfStage {
     float2 c[kMfFlush][kMfCols];   // column factors
@@ -154,7 +162,7 @@ struct AkRegion {
 };
 
 template <bool YC>
-__global__ __launch_bounds__(kMfThreads) void k_asym_k_mfma(AkArgs a, AkRegion rg)
+__global__ __launch_bounds__(kMfThreads, 2) void k_asym_k_mfma(AkArgs a, AkRegion rg)
 {
     const int x0 = rg.x0;
     __shared__ MfStage st[2];
@@ -189,16 +197,17 @@ __global__ __launch_bounds__(kMfThreads) void k_asym_k_mfma(AkArgs a, AkRegion r
     const double kx2min = kx_of(YC ? r0 : c0) * kx_of(YC ? r0 : c0);
     const bool work = ce > cb && kx2min + ky2min + kz2min <= k2max;
 
-    // staging: thread tid carries 4 column, 8 Q ez and (tid < 128) 1 row value per stage
-    float2 rc[4], rz[8], rr = make_float2(0.f, 0.f);
+    // staging: thread tid carries kMfCPer column, kMfZPer Q ez and (tid < kMfFlush kMfWaves)
+    // one row value per stage
+    float2 rc[kMfCPer], rz[kMfZPer], rr = make_float2(0.f, 0.f);
     auto fetch = [&](int64_t a0) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kMfCPer; ++u) {
             const int e = tid + u * kMfThreads, at = e / kMfCols, c = e % kMfCols;
             rc[u] = ctab[(a0 + at) * cstride + min(c0 + c, clim - 1)];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < kMfZPer; ++u) {
             const int e = tid + u * kMfThreads, at = e / kMfZ, z = e % kMfZ;
             rz[u] = a.ezq[(a0 + at) * g.nz + min(jz0 + z, g.nz - 1)];
         }
@@ -209,12 +218,12 @@ __global__ __launch_bounds__(kMfThreads) void k_asym_k_mfma(AkArgs a, AkRegion r
     };
     auto stash = [&](MfStage &b) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kMfCPer; ++u) {
             const int e = tid + u * kMfThreads;
             b.c[e / kMfCols][e % kMfCols] = rc[u];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < kMfZPer; ++u) {
             const int e = tid + u * kMfThreads;
             b.z[e / kMfZ][e % kMfZ][0] = rz[u].x;
             b.z[e / kMfZ][e % kMfZ][1] = rz[u].y;
@@ -222,9 +231,9 @@ __global__ __launch_bounds__(kMfThreads) void k_asym_k_mfma(AkArgs a, AkRegion r
         if (tid < kMfFlush * kMfWaves) b.r[tid / kMfWaves][tid % kMfWaves] = rr;
     };
 
-    double Sr[2][16], Si[2][16];
+    double Sr[kMfZT][16], Si[kMfZT][16];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < kMfZT; ++t)
 #pragma unroll
         for (int r = 0; r < 16; ++r) Sr[t][r] = Si[t][r] = 0.0;
     if (work) {
@@ -234,26 +243,29 @@ __global__ __launch_bounds__(kMfThreads) void k_asym_k_mfma(AkArgs a, AkRegion r
         for (int c = cb; c < ce; ++c) {
             const MfStage &b = st[(c - cb) & 1];
             if (c + 1 < ce) fetch((int64_t)(c + 1) * kMfFlush);
-            f32x16 accR0 = {}, accI0 = {}, accR1 = {}, accI1 = {};
+            f32x16 accR[kMfZT], accI[kMfZT];
+#pragma unroll
+            for (int t = 0; t < kMfZT; ++t) accR[t] = accI[t] = f32x16{};
 #pragma unroll 8
             for (int i = 0; i < kMfFlush; ++i) {
                 const float2 X = b.c[i][col], Y = b.r[i][wave];
                 const float tr = fmaf(Y.x, X.x, -Y.y * X.y);
                 const float ti = fmaf(Y.x, X.y, Y.y * X.x);
                 const float bre = half ? -ti : tr, bim = half ? tr : ti;
-                const float za = b.z[i][col][half], zb = b.z[i][32 + col][half];
-                accR0 = __builtin_amdgcn_mfma_f32_32x32x2f32(za, bre, accR0, 0, 0, 0);
-                accI0 = __builtin_amdgcn_mfma_f32_32x32x2f32(za, bim, accI0, 0, 0, 0);
-                accR1 = __builtin_amdgcn_mfma_f32_32x32x2f32(zb, bre, accR1, 0, 0, 0);
-                accI1 = __builtin_amdgcn_mfma_f32_32x32x2f32(zb, bim, accI1, 0, 0, 0);
+#pragma unroll
+                for (int t = 0; t < kMfZT; ++t) {
+                    const float z = b.z[i][32 * t + col][half];
+                    accR[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(z, bre, accR[t], 0, 0, 0);
+                    accI[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(z, bim, accI[t], 0, 0, 0);
+                }
             }
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                Sr[0][r] += (double)accR0[r];
-                Si[0][r] += (double)accI0[r];
-                Sr[1][r] += (double)accR1[r];
-                Si[1][r] += (double)accI1[r];
-            }
+            for (int t = 0; t < kMfZT; ++t)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    Sr[t][r] += (double)accR[t][r];
+                    Si[t][r] += (double)accI[t][r];
+                }
             if (c + 1 < ce) stash(st[(c + 1 - cb) & 1]);
             __syncthreads();
         }
@@ -262,7 +274,7 @@ __global__ __launch_bounds__(kMfThreads) void k_asym_k_mfma(AkArgs a, AkRegion r
     // output: register r of this lane is row 8 (r / 4) + 4 half + r % 4 of
     // the tile, column col
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < kMfZT; ++t)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int jz = jz0 + 32 * t + 8 * (r / 4) + 4 * half + (r % 4);
@@ -403,7 +415,7 @@ int launch_asym_k(const AkArgs &a, const double *xyz, const double *q, Workspace
         grids[yc] = yc ? dim3((a.g.ny + kMfCols - 1) / kMfCols, (w + kMfWaves - 1) / kMfWaves, zt)
                        : dim3(w / kMfCols, (a.g.ny + kMfWaves - 1) / kMfWaves, zt);
         const int64_t waves = (int64_t)grids[yc].x * grids[yc].y * grids[yc].z * kMfWaves;
-        const int64_t want = (int64_t)8 * std::max(cus, 1);   // 2 waves per SIMD
+        const int64_t want = (int64_t)12 * std::max(cus, 1);   // 3 waves per SIMD
         rg[yc].ks = (int)std::max<int64_t>(1, std::min<int64_t>(nch, want / waves));
         if (rg[yc].ks > 1) rg[yc].part = ws.get<double>((size_t)2 * rg[yc].ks * rg[yc].count);
         grids[yc].z *= rg[yc].ks;
