@@ -935,6 +935,7 @@ struct CpTabArgs {
     int nrow_m;                    // M rows in all
     int lrow0[3], nrow_l;          // first level-1 basis row of each axis; rows in all
     double *M, *Lg;
+    int *zero;                     // set to 0 (a flag the later kernels start from)
 };
 
 inline void cp_tab_layout(const CpLevels &L, int n1, CpTabArgs &t)
@@ -961,6 +962,7 @@ __global__ __launch_bounds__(kBlock) void k_cp_tables(CpTabArgs a)
     const CpLevels &L = a.L;
     const int n1 = a.degree + 1;
     if ((int)threadIdx.x < n1) cosk[threadIdx.x] = cos(kPi * threadIdx.x / a.degree);
+    if (r == 0 && a.zero) *a.zero = 0;
     __syncthreads();
     if (r < a.nrow_m) {
         int lvl = 1, ax = 0;
@@ -1405,7 +1407,19 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     qa.overflow = overflow;
     qa.stack_w = cp_query_stack(t.cap_nodes);
     const size_t qshm = (size_t)qa.stack_w * sizeof(int);
-    hipLaunchKernelGGL(k_fill_int, 1, 64, 0, s, overflow, 1, 0);
+    // the per-call tables; the same launch clears the query overflow flag
+    const bool taylor = a.opts->method == RISM_TREECODE_TAYLOR;
+    CpTabArgs ta{};
+    ta.L = L;
+    ta.degree = deg;
+    ta.taylor = taylor;
+    cp_tab_layout(L, n1, ta);
+    ta.M = ws.get<double>((size_t)(ta.nrow_m + 1) * n1);
+    ta.Lg = ws.get<double>((size_t)ta.nrow_l * n1);
+    ta.zero = overflow;
+    if (ws.status()) return ws.status();
+    hipLaunchKernelGGL(k_cp_tables, (ta.nrow_m + ta.nrow_l + kBlock - 1) / kBlock, kBlock, 0, s,
+                       ta);
     {
         // count pass of both query sets in one launch, then all five scans
         PhaseTimer pt(ev, RISM_PHASE_LISTS, s);
@@ -1449,7 +1463,6 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     int lds_max = 0;
     RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const size_t leaf_shm = cp_leaf_lds(B, deg, a.asym_on);
-    const bool taylor = a.opts->method == RISM_TREECODE_TAYLOR;
     if (taylor && (deg > kMaxTaylor || cp_taylor_lds(deg, a.asym_on) > (size_t)lds_max)) {
         set_error("Taylor treecode: order above 12 or its LDS beyond this device");
         return RISM_E_UNSUPPORTED;
@@ -1464,16 +1477,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     uint32_t *nd = ws.get<uint32_t>(nleaf), *nsh = ws.get<uint32_t>(nleaf);
     int *order = ws.get<int>(nleaf);
     double *V = ws.get<double>((size_t)(ncl + 1) * 2 * np);
-    CpTabArgs ta{};
-    ta.L = L;
-    ta.degree = deg;
-    ta.taylor = taylor;
-    cp_tab_layout(L, n1, ta);
-    ta.M = ws.get<double>((size_t)(ta.nrow_m + 1) * n1);
-    ta.Lg = ws.get<double>((size_t)ta.nrow_l * n1);
     if (ws.status()) return ws.status();
-    hipLaunchKernelGGL(k_cp_tables, (ta.nrow_m + ta.nrow_l + kBlock - 1) / kBlock, kBlock, 0, s,
-                       ta);
 
     // Everything after the counts, with buffers of the given capacities.
     auto second_half = [&](const CpCaps &cap) -> int {
