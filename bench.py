@@ -284,6 +284,11 @@ def main():
             "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": d["frac"],
             "traffic": traffic, "kernel_ms": d["ms"],
             "peak_single_issue": FP32_VALU_SINGLE_ISSUE_TFLOPS,
+            "note": "algorithmic flops (FMA 2, rsqrt/exp2 1) over the kernel time; the kernel "
+                    "issues VALU instructions at the SIMDs' single-issue rate (rocprofv3 "
+                    "instruction counters in profiles/), so the remaining gap to the peak is the "
+                    "flop model against instruction count and the dual issue or packed FP32 the "
+                    "peak assumes",
             "other_phases": {k: {kk: v[kk] for kk in ("kernel", "achieved", "frac", "ms")}
                              for k, v in rl.items() if k != dom}}
     else:
