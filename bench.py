@@ -114,8 +114,8 @@ def counter_traffic(kernel, workload):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--method", default="treecode_cp",
                     choices=["treecode", "treecode_cp", "direct_f32c"])
     ap.add_argument("--theta", type=float, default=0.6)
