@@ -169,8 +169,8 @@ def cpu_baseline(wl, lj_cutoff, target_s):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: the initialisation shards the grid with no "
-              "communication, and this build measures one GPU's share (see DESIGN.md).",
+        print("bench.py runs on exactly one GPU: the initialisation shards the grid into "
+              "blocks that need no communication, and the benchmark measures one GPU's share.",
               file=sys.stderr)
         sys.exit(2)
     import torch
