@@ -262,7 +262,9 @@ def main():
                         flops_per_pair_direct_f32(st.n, True, True) * stats["pairs_direct"]
                         + flops_per_pair_short_f32(st.n, True, True) * stats["pairs_short"]
                         + leaf_interp_flops(m, blocks, args.degree, B, 2))
-        work["upward"] = ("k_cp_sweep", flops_per_far_pair(True) * stats["pairs_far"])
+        # the far sweep runs along proxy x-lines for 8, 9 and 11 nodes per axis
+        sweep = "k_cp_sweep_lines" if args.degree + 1 in (8, 9, 11) else "k_cp_sweep"
+        work["upward"] = (sweep, flops_per_far_pair(True) * stats["pairs_far"])
     elif args.method == "treecode":
         work["eval"] = ("k_tree_eval",
                         flops_per_pair_direct_f32(st.n, True, True) * stats["pairs_direct"]

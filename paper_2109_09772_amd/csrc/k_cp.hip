@@ -770,9 +770,119 @@ __global__ __launch_bounds__(kBlock) void k_cp_sweep(CpSweepArgs a)
     }
 }
 
-template <bool ASYM>
-void launch_sweep(int nitems, int np, const CpSweepArgs &sa, hipStream_t s)
+// k_cp_sweep with the proxies taken along x-lines: every thread owns NI
+// proxies of one line (fixed y and z nodes), so dy^2 + dz^2 is formed once
+// per atom and shared by the NI proxies, and a pair costs a subtraction and
+// an FMA for its distance instead of three subtractions, a product and two
+// FMAs.  d2 = fma(dx, dx, fma(dy, dy, dz dz)) is the same expression in the
+// same order as in k_cp_sweep, so both kernels give identical sums.  G =
+// ceil(n1 / NI) threads share a line; threads beyond the n1^2 lines and
+// slots beyond n1 on a line compute on node 0 and store nothing.
+template <bool ASYM, int NI>
+__global__ __launch_bounds__(kBlock) void k_cp_sweep_lines(CpSweepArgs a)
 {
+    __shared__ float node[3][kMaxDeg + 1];
+    __shared__ float4 stage[2][kBlock];
+    if (*a.bad || (int)blockIdx.x >= (int)*a.n_items) return;   // whole workgroup
+    const int item = as_const(a.order)[blockIdx.x];
+    const int cl = as_const(a.it_cl)[item];
+    const int n = (int)as_const(a.it_n)[item];
+    const float4 *at = a.abuf + as_const(a.it_slot)[item];
+    const int n1 = a.degree + 1;
+    if (threadIdx.x < 3 * n1) {
+        int lvl, I, J, K;
+        cp_decode(a.L, cl, lvl, I, J, K);
+        double pb[6], cc[3], rr;
+        cp_proxy_box(a.L, lvl, I, J, K, pb);
+        cp_centre(a.L, lvl, I, J, K, cc, rr);
+        const int ax = threadIdx.x / n1, k = threadIdx.x % n1;
+        node[ax][k] = (float)(cheb_point(pick3(pb, ax), pick3(pb + 3, ax), k, a.degree) -
+                              pick3(cc, ax));
+    }
+    __syncthreads();
+    const int G = (n1 + NI - 1) / NI;
+    const int line = (int)threadIdx.x / G, i0 = ((int)threadIdx.x % G) * NI;
+    const bool live = line < n1 * n1;
+    const float py = node[1][live ? line % n1 : 0], pz = node[2][live ? line / n1 : 0];
+    float px[NI];
+    double aC[NI], aY[NI];
+#pragma unroll
+    for (int r = 0; r < NI; ++r) {
+        px[r] = node[0][i0 + r < n1 ? i0 + r : 0];
+        aC[r] = aY[r] = 0.0;
+    }
+    float4 nxt = threadIdx.x < n ? at[threadIdx.x] : float4{0.f, 0.f, 0.f, 0.f};
+    for (int c0 = 0, buf = 0; c0 < n; c0 += kBlock, buf ^= 1) {
+        // buffer buf was last read two chunks ago, before the barrier that
+        // every thread passed after it
+        stage[buf][threadIdx.x] = nxt;
+        __syncthreads();
+        if (c0 + kBlock + (int)threadIdx.x < n) nxt = at[c0 + kBlock + threadIdx.x];
+        const float4 *st = stage[buf];
+        const int m = min(kBlock, n - c0);
+        for (int s0 = 0; s0 < m; s0 += 16) {
+            float pC[NI], pY[NI];
+#pragma unroll
+            for (int r = 0; r < NI; ++r) pC[r] = pY[r] = 0.f;
+            const int s1 = min(s0 + 16, m);
+#pragma unroll 4
+            for (int s = s0; s < s1; ++s) {
+                const float4 v = st[s];
+                const float dy = py - v.y, dz = pz - v.z;
+                const float e = fmaf(dy, dy, dz * dz);
+#pragma unroll
+                for (int r = 0; r < NI; ++r) {
+                    const float dx = px[r] - v.x;
+                    const float d2 = fmaf(dx, dx, e);
+                    const float ri = __builtin_amdgcn_rsqf(d2);
+                    const float qr = v.w * ri;
+                    pC[r] += qr;
+                    if (ASYM)
+                        pY[r] = fmaf(qr, __builtin_amdgcn_exp2f(a.yk * (d2 * ri)), pY[r]);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < NI; ++r) {
+                aC[r] += (double)pC[r];
+                aY[r] += (double)pY[r];
+            }
+        }
+    }
+    if (live) {
+#pragma unroll
+        for (int r = 0; r < NI; ++r) {
+            if (i0 + r < n1) {
+                const int k = i0 + r + n1 * line;
+                a.part[((size_t)item * 2 + 0) * a.np + k] = aC[r];
+                a.part[((size_t)item * 2 + 1) * a.np + k] = aY[r];
+            }
+        }
+    }
+}
+
+// Proxies per thread of k_cp_sweep_lines for n1 nodes per axis: the fewest
+// that fit the n1^2 lines into one workgroup, if the lines then keep at
+// least 90 % of its threads busy and that count is instantiated (n1 = 8, 9
+// and 11); otherwise 0 (k_cp_sweep).
+inline int sweep_line_ni(int n1)
+{
+    for (int ni = 1; ni <= n1; ++ni) {
+        const int busy = n1 * n1 * ((n1 + ni - 1) / ni);
+        if (busy <= kBlock)
+            return 10 * busy >= 9 * kBlock && (ni == 2 || ni == 3 || ni == 6) ? ni : 0;
+    }
+    return 0;
+}
+
+template <bool ASYM>
+void launch_sweep(int nitems, int np, int degree, const CpSweepArgs &sa, hipStream_t s)
+{
+    switch (sweep_line_ni(degree + 1)) {
+    case 2: hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 2>), nitems, kBlock, 0, s, sa); return;
+    case 3: hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 3>), nitems, kBlock, 0, s, sa); return;
+    case 6: hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 6>), nitems, kBlock, 0, s, sa); return;
+    default: break;
+    }
     const int nr = np <= 3 * kBlock ? (np + kBlock - 1) / kBlock : 4;
     switch (nr) {
     case 1: hipLaunchKernelGGL((k_cp_sweep<ASYM, 1>), nitems, kBlock, 0, s, sa); break;
@@ -1591,9 +1701,9 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
                     else
                         hipLaunchKernelGGL(k_cp_taylor<false>, (int)cap.c[1], kBlock, tshm, s, sa);
                 } else if (a.asym_on) {
-                    launch_sweep<true>((int)cap.c[1], np, sa, s);
+                    launch_sweep<true>((int)cap.c[1], np, deg, sa, s);
                 } else {
-                    launch_sweep<false>((int)cap.c[1], np, sa, s);
+                    launch_sweep<false>((int)cap.c[1], np, deg, sa, s);
                 }
             }
         }

@@ -116,6 +116,38 @@ def test_far_field_converges_with_degree(oracle, method):
     assert_close_grid(pick(h), hr, 1e-6, cap=FP32_CAP, what="h")
 
 
+def test_cp_sweep_layouts_converge(oracle):
+    """The cluster-particle far sweep takes its proxies along x-lines for 8, 9
+    and 11 nodes per axis (degrees 7, 8 and 10) and one proxy set per thread
+    pass otherwise (degree 6): on the far-field case every layout must carry
+    the interpolation's convergence, the error of c and h against the oracle
+    falling from degree 6 to 7 to 8 to 10.  u stays within 1e-6 at every
+    degree (its error, ~6e-7, is set by the LJ core, not the far field)."""
+    wl = _far_case()
+    idx = W.sample_points(wl.grid, 6000, seed=5)
+    sol, st, g = wl.solute, wl.sites, wl.grid
+    pts = g.origin + idx * g.spacing
+    rc = oracle_rcut(oracle, wl, 9.0)
+    cr, hr = oracle.asymptotics_points(sol.xyz, sol.q, st.q, st.ionic, pts, KC, ETA, KAPPA, BETA,
+                                       DIEL)
+    ur = oracle.potential_points(sol.xyz, sol.q, sol.sigma, sol.eps, st.q, st.sigma, st.eps, pts,
+                                 KC, rc)
+    pick = lambda a: _np(a)[:, idx[:, 2], idx[:, 1], idx[:, 0]]
+    rel = lambda a, r, k: np.linalg.norm(a[k] - r[k]) / np.linalg.norm(r[k])
+    errs = {}
+    for deg in (6, 7, 8, 10):
+        (u, c, h), stt = _run(wl, theta=0.7, degree=deg, leaf_size=32, method="treecode_cp")
+        assert stt["pairs_far"] > 0
+        u, c, h = pick(u), pick(c), pick(h)
+        errs[deg] = (max(rel(u, ur, k) for k in range(4)), max(rel(c, cr, k) for k in range(4)),
+                     max(rel(h, hr, k) for k in range(2)))
+    print("far-field rel-L2 (u, c, h) by degree:", errs)
+    for lo, hi in ((6, 7), (7, 8), (8, 10)):
+        for k in (1, 2):
+            assert errs[hi][k] < errs[lo][k], (lo, hi, k, errs)
+    assert max(e[0] for e in errs.values()) <= 1e-6, errs
+
+
 @pytest.mark.parametrize("method", METHODS)
 def test_protein_2500_vs_f64_direct(oracle, method):
     """The benchmark workload with a 9 A cut-off (particle-cluster theta 0.7 /
