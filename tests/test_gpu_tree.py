@@ -119,10 +119,12 @@ def test_far_field_converges_with_degree(oracle, method):
 def test_cp_sweep_layouts_converge(oracle):
     """The cluster-particle far sweep takes its proxies along x-lines for 8, 9
     and 11 nodes per axis (degrees 7, 8 and 10) and one proxy set per thread
-    pass otherwise (degree 6): on the far-field case every layout must carry
-    the interpolation's convergence, the error of c and h against the oracle
-    falling from degree 6 to 7 to 8 to 10.  u stays within 1e-6 at every
-    degree (its error, ~6e-7, is set by the LJ core, not the far field)."""
+    pass otherwise (degree 6 in one pass; degrees 11 and 12, 1,728 and 2,197
+    proxies, in several passes): on the far-field case every layout must
+    carry the interpolation's convergence, the error of c and h against the
+    oracle falling from degree 6 to 7 to 8 to 10, and degrees 11 and 12
+    meeting 1e-6.  u stays within 1e-6 at every degree (its error, ~6e-7, is
+    set by the LJ core, not the far field)."""
     wl = _far_case()
     idx = W.sample_points(wl.grid, 6000, seed=5)
     sol, st, g = wl.solute, wl.sites, wl.grid
@@ -135,7 +137,7 @@ def test_cp_sweep_layouts_converge(oracle):
     pick = lambda a: _np(a)[:, idx[:, 2], idx[:, 1], idx[:, 0]]
     rel = lambda a, r, k: np.linalg.norm(a[k] - r[k]) / np.linalg.norm(r[k])
     errs = {}
-    for deg in (6, 7, 8, 10):
+    for deg in (6, 7, 8, 10, 11, 12):
         (u, c, h), stt = _run(wl, theta=0.7, degree=deg, leaf_size=32, method="treecode_cp")
         assert stt["pairs_far"] > 0
         u, c, h = pick(u), pick(c), pick(h)
@@ -146,6 +148,7 @@ def test_cp_sweep_layouts_converge(oracle):
         for k in (1, 2):
             assert errs[hi][k] < errs[lo][k], (lo, hi, k, errs)
     assert max(e[0] for e in errs.values()) <= 1e-6, errs
+    assert max(max(errs[11]), max(errs[12])) <= 1e-6, errs
 
 
 @pytest.mark.parametrize("method", METHODS)
