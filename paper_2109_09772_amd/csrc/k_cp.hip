@@ -1226,33 +1226,56 @@ struct LeafShape {
     static constexpr int passes = (B * B * B) / threads;
 };
 
-// Dynamic LDS of the leaf kernel, in bytes (layout in k_cp_leaf).
-inline size_t cp_leaf_lds(int B, int degree, bool asym)
+// Atoms per LDS chunk of the leaf kernel (a multiple of kAtomPad, so the
+// flushes fall where they would without chunks).
+constexpr int kLeafStage = 256;
+static_assert(kLeafStage % kAtomPad == 0, "leaf chunks must keep the flush points");
+
+// Doubles of the leaf kernel's LDS before the atom chunk, rounded up to an
+// even count so that the 16-byte records start aligned.
+__host__ __device__ inline size_t cp_leaf_head(int B, int degree, bool asym)
 {
     const size_t n1 = degree + 1, np = n1 * n1 * n1;
     const size_t ncomp = asym ? 2 : 1;
-    return (asym ? 2 * kSmearIntervals * sizeof(float4) : 0) +
-           (ncomp * n1 * B * B + 3 * (size_t)B * n1 + np + n1 * n1 * B) * sizeof(double);
+    const size_t d = (asym ? 4 * (size_t)kSmearIntervals : 0) + ncomp * n1 * B * B +
+                     3 * (size_t)B * n1 + np + n1 * n1 * B;
+    return (d + 1) & ~(size_t)1;
+}
+
+// Dynamic LDS of the leaf kernel, in bytes (layout in k_cp_leaf), for atom
+// records of rec_bytes.
+inline size_t cp_leaf_lds(int B, int degree, bool asym, size_t rec_bytes)
+{
+    return cp_leaf_head(B, degree, asym) * sizeof(double) + kLeafStage * rec_bytes;
 }
 
 // The atoms of one index list against this thread's point, flushed every
-// kAtomPad atoms.  Indices and records are wave-uniform scalar loads, so the
-// pair arithmetic reads the atom's fields from scalar registers.
-template <int NS, int LJM, bool ASYM, bool EXACT, bool FULL>
-__device__ __forceinline__ void leaf_atoms(ConstAS<AtomF32<NS>> *rec, ConstAS<int> *il, int cnt,
-                                           const GridPt &gp, const PairConst &kc,
-                                           const float4 *tab, PointAcc<NS> &acc)
+// kAtomPad atoms.  The workgroup copies the records to LDS kLeafStage at a
+// time (one per thread), and every pair reads its atom's fields from there
+// into vector registers: a vector instruction takes one scalar operand at
+// most, so with the fields in scalar registers each site's
+// fma(A, r^-6, -B) would need a move of B first.  Every thread of the
+// workgroup calls this with the same list (barriers inside).
+template <int NS, int LJM, bool ASYM, bool EXACT, bool FULL, int NT>
+__device__ __forceinline__ void leaf_atoms(const AtomF32<NS> *rec, ConstAS<int> *il, int cnt,
+                                           AtomF32<NS> *stg, const GridPt &gp,
+                                           const PairConst &kc, const float4 *tab,
+                                           PointAcc<NS> &acc)
 {
-    for (int s0 = 0; s0 < cnt; s0 += kAtomPad) {
-        PairAcc<NS> p;
-        p.zero();
-        const int s1 = min(s0 + kAtomPad, cnt);
-#pragma unroll 2
-        for (int s = s0; s < s1; ++s) {
-            ConstAS<AtomF32<NS>> &at = rec[il[s]];
-            pair_eval<NS, LJM, ASYM, EXACT, FULL>(at, gp, kc, tab, p, acc.hit);
+    for (int c0 = 0; c0 < cnt; c0 += kLeafStage) {
+        const int m = min(kLeafStage, cnt - c0);
+        __syncthreads();   // every wave is done with the previous chunk
+        for (int t = threadIdx.x; t < m; t += NT) stg[t] = rec[il[c0 + t]];
+        __syncthreads();
+        for (int s0 = 0; s0 < m; s0 += kAtomPad) {
+            PairAcc<NS> p;
+            p.zero();
+            const int s1 = min(s0 + kAtomPad, m);
+#pragma unroll 1
+            for (int s = s0; s < s1; ++s)
+                pair_eval<NS, LJM, ASYM, EXACT, FULL>(stg[s], gp, kc, tab, p, acc.hit);
+            acc.template flush<LJM != LJ_NONE, ASYM>(p);
         }
-        acc.template flush<LJM != LJ_NONE, ASYM>(p);
     }
 }
 
@@ -1264,7 +1287,7 @@ __device__ __forceinline__ void leaf_atoms(ConstAS<AtomF32<NS>> *rec, ConstAS<in
 // from the block's index lists.
 //
 // LDS: [smeared table (ASYM)] [T2 per component: n1 x B x B] [Lb: 3 x B x n1]
-//      [Vs (np)] [T1 (n1 x n1 x B)]
+//      [Vs (np)] [T1 (n1 x n1 x B)] [atom chunk: kLeafStage records]
 template <int NS, int LJM, bool ASYM, int B>
 __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
 {
@@ -1278,6 +1301,7 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
     double *Lb = T2 + NCOMP * n1 * B * B;                  // [3][B][n1]
     double *Vs = Lb + 3 * B * n1;                          // [np]
     double *T1 = Vs + a.np;                                // [n1][n1][B]
+    AtomF32<NS> *stg = reinterpret_cast<AtomF32<NS> *>(sm + cp_leaf_head(B, a.degree, ASYM));
     if (*a.bad) return;   // whole workgroup
     const CpLevels &L = a.L;
     const GridParams &g = a.g;
@@ -1285,7 +1309,7 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
     const int I = q % L.cx[0], J = (q / L.cx[0]) % L.cy[0], K = q / (L.cx[0] * L.cy[0]);
     const int i0 = I * B, j0 = J * B, k0 = K * B;
     const PairConst kc = make_pair_const(a.asym);
-    ConstAS<AtomF32<NS>> *rec = as_const(static_cast<const AtomF32<NS> *>(a.rec));
+    const AtomF32<NS> *grec = static_cast<const AtomF32<NS> *>(a.rec);
     const uint32_t base = as_const(a.aoff)[q];
     ConstAS<int> *dl = as_const(a.dlist + base);
     ConstAS<int> *sl = as_const(a.slist + base);
@@ -1359,13 +1383,13 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
 
         // ---------------------------------------------- direct and short
         if (g.exact) {
-            leaf_atoms<NS, LJM, ASYM, true, true>(rec, dl, ndir, gp, kc, tab, acc);
+            leaf_atoms<NS, LJM, ASYM, true, true, NT>(grec, dl, ndir, stg, gp, kc, tab, acc);
             if (LJM != LJ_NONE || ASYM)
-                leaf_atoms<NS, LJM, ASYM, true, false>(rec, sl, nsh, gp, kc, tab, acc);
+                leaf_atoms<NS, LJM, ASYM, true, false, NT>(grec, sl, nsh, stg, gp, kc, tab, acc);
         } else {
-            leaf_atoms<NS, LJM, ASYM, false, true>(rec, dl, ndir, gp, kc, tab, acc);
+            leaf_atoms<NS, LJM, ASYM, false, true, NT>(grec, dl, ndir, stg, gp, kc, tab, acc);
             if (LJM != LJ_NONE || ASYM)
-                leaf_atoms<NS, LJM, ASYM, false, false>(rec, sl, nsh, gp, kc, tab, acc);
+                leaf_atoms<NS, LJM, ASYM, false, false, NT>(grec, sl, nsh, stg, gp, kc, tab, acc);
         }
 
         if (valid) {
@@ -1572,7 +1596,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
 
     int lds_max = 0;
     RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t leaf_shm = cp_leaf_lds(B, deg, a.asym_on);
+    const size_t leaf_shm = cp_leaf_lds(B, deg, a.asym_on, rec32_bytes_of(a.sp.ns_pad));
     if (taylor && (deg > kMaxTaylor || cp_taylor_lds(deg, a.asym_on) > (size_t)lds_max)) {
         set_error("Taylor treecode: order above 12 or its LDS beyond this device");
         return RISM_E_UNSUPPORTED;
