@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import BETA, DIEL, ETA, FP32_CAP, KAPPA, KC, assert_close_grid, oracle_rcut
+from helpers import BETA, DIEL, ETA, FP32_CAP, KAPPA, KC, assert_close_grid, oracle_rcut, rel_l2
 from paper_2109_09772_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -149,6 +149,42 @@ def test_cp_sweep_layouts_converge(oracle):
             assert errs[hi][k] < errs[lo][k], (lo, hi, k, errs)
     assert max(e[0] for e in errs.values()) <= 1e-6, errs
     assert max(max(errs[11]), max(errs[12])) <= 1e-6, errs
+
+
+def test_cp_leaf_lists_past_one_chunk(oracle):
+    """The leaf kernel copies a block's atom list to LDS 256 records at a
+    time.  With theta 0.3 on a 64^3 grid inside the 2,500-atom solute the
+    direct lists average more than 256 atoms per grid point, so most blocks
+    take several chunks.  c and h must match the oracle within 1e-6 on
+    sampled points.  Every sampled point lies inside the solute, where u is
+    set by LJ cores and its FP32 pair rounding reaches ~1e-6 for the direct
+    sum too: u must stay within 1.5x the FP32 compensated direct sum's error
+    on the same points (that kernel has no LDS chunks)."""
+    base = W.protein_2500()
+    wl = W.Workload("ellipsoid2500_grid64", base.solute, base.sites,
+                    W.centred_grid([0.0, 0.0, 0.0], 0.5, 64), base.seed)
+    idx = W.sample_points(wl.grid, 3000, seed=11)
+    sol, st, g = wl.solute, wl.sites, wl.grid
+    pts = g.origin + idx * g.spacing
+    rc = oracle_rcut(oracle, wl, 9.0)
+    cr, hr = oracle.asymptotics_points(sol.xyz, sol.q, st.q, st.ionic, pts, KC, ETA, KAPPA, BETA,
+                                       DIEL)
+    ur = oracle.potential_points(sol.xyz, sol.q, sol.sigma, sol.eps, st.q, st.sigma, st.eps, pts,
+                                 KC, rc)
+    (u, c, h), stt = _run(wl, theta=0.3, degree=6, method="treecode_cp")
+    per_point = stt["pairs_direct"] / float(np.prod(g.dims))
+    print("direct atoms per grid point", per_point)
+    assert per_point > 256
+    pick = lambda a: _np(a)[:, idx[:, 2], idx[:, 1], idx[:, 0]]
+    assert_close_grid(pick(c), cr, 1e-6, cap=FP32_CAP, what="c")
+    assert_close_grid(pick(h), hr, 1e-6, cap=FP32_CAP, what="h")
+    (ud, _, _), _ = _run(wl, method="direct_f32c")
+    u, ud = pick(u), pick(ud)
+    for k in range(4):
+        e_tree = rel_l2(u[k], ur[k], FP32_CAP)[0]
+        e_dir = rel_l2(ud[k], ur[k], FP32_CAP)[0]
+        print(f"u[{k}] rel-L2: treecode {e_tree:.3e}, FP32 direct {e_dir:.3e}")
+        assert e_tree <= max(1e-6, 1.5 * e_dir), (k, e_tree, e_dir)
 
 
 @pytest.mark.parametrize("method", METHODS)
