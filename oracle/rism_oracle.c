@@ -367,8 +367,11 @@ int oracle_lj_rcut_table(int64_t n, const double *sig, const double *eps,
         for (int64_t a = 0; a < n; ++a) {
             double s_ga, e_ga;
             lb_mix(ssig[g], seps[g], sig[a], eps[a], &s_ga, &e_ga);
-            double r = tol > 0.0 ? oracle_lj_rcut_from_tol(s_ga, e_ga, tol) : rcut;
-            if (!(r > 0.0)) return -1;
+            /* a pair with eps_ga = 0 has no LJ term: |u_LJ| = 0 <= tol at
+             * every distance, so under a tolerance its radius is 0 (dropped) */
+            double r = tol > 0.0 ? (e_ga == 0.0 ? 0.0 : oracle_lj_rcut_from_tol(s_ga, e_ga, tol))
+                                 : rcut;
+            if (!(r > 0.0) && !(tol > 0.0 && e_ga == 0.0)) return -1;
             out[(int64_t)g * n + a] = r;
         }
     return 0;
@@ -389,7 +392,7 @@ int oracle_lj_tail(int64_t n, const double *sig, const double *eps, int32_t ns,
             double B = 4.0 * e_ga * s3 * s3;
             double rc = rcut[(int64_t)g * n + a];
             double rc3 = rc * rc * rc;
-            t += A / (3.0 * rc3 * rc3 * rc3) - B / rc3;
+            if (rc > 0.0) t += A / (3.0 * rc3 * rc3 * rc3) - B / rc3;
         }
         tail[g] = 4.0 * ORACLE_PI / 3.0 * t;
     }

@@ -112,12 +112,12 @@ def _check(rc):
 
 @dataclasses.dataclass
 class Opts:
-    method: str = "treecode"
+    method: str = "treecode_cp"
     out_dtype: str = "f32"
     coulomb_k: float = _wl.COULOMB_K
     lj_cutoff: float = 9.0
     lj_tol: float = 0.0
-    theta: float = 0.7
+    theta: float = 0.6
     degree: int = 8
     leaf_size: int = 64
     batch_edge: int = 8
@@ -349,8 +349,11 @@ class RismPotential(torch.autograd.Function):
         dx, dq, ds_, de = None, None, None, None
         if any(need):
             w = g.detach().to(ctx.opts.torch_dtype).contiguous()
-            dx, dq, de, ds_ = potential_backward(xyz.detach(), q.detach(), sigma.detach(),
-                                                 eps.detach(), ctx.sites, ctx.grid, ctx.opts, w,
+            dx, dq, de, ds_ = potential_backward(xyz.detach().contiguous(),
+                                                 q.detach().contiguous(),
+                                                 sigma.detach().contiguous(),
+                                                 eps.detach().contiguous(), ctx.sites, ctx.grid,
+                                                 ctx.opts, w,
                                                  need=(need[0], need[1], need[3], need[2]))
         return dx, dq, ds_, de, None, None, None
 

@@ -79,7 +79,12 @@ __global__ __launch_bounds__(kBlock) void k_stage(SiteParams sp, StageArgs a)
             A[g] = 4.0 * e_ga * s6 * s6;
             B[g] = 4.0 * e_ga * s6;
             if (a.lj_mode == LJ_CUT) {
-                if (a.lj_tol > 0.0) {
+                if (a.lj_tol > 0.0 && e_ga == 0.0) {
+                    // eps_ga = 0: the pair has no LJ term (A = B = 0), which
+                    // is below any tolerance at every distance; radius 0
+                    // drops it and adds nothing to the tail
+                    rc[g] = 0.0;
+                } else if (a.lj_tol > 0.0) {
                     // |u(r)| = tol beyond the minimum: with t = (s_ga/r)^6,
                     // 4 e (t^2 - t) = -tol, smaller root, written without
                     // cancellation: t = (z/2) / (1 + sqrt(1 - z)), z = tol/e.
@@ -163,7 +168,8 @@ __global__ __launch_bounds__(kBlock) void k_lj_tail(SiteParams sp, const double 
         double A = 4.0 * e_ga * s6 * s6, B = 4.0 * e_ga * s6;
         double rc = rcut[(int64_t)g * n + i];
         double rc3 = rc * rc * rc;
-        acc += A / (3.0 * rc3 * rc3 * rc3) - B / rc3;
+        // rc = 0 marks a pair without LJ term (eps_ga = 0 under a tolerance)
+        if (rc > 0.0) acc += A / (3.0 * rc3 * rc3 * rc3) - B / rc3;
     }
     red[threadIdx.x] = acc;
     __syncthreads();

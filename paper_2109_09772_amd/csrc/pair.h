@@ -156,7 +156,14 @@ __device__ __forceinline__ void pair_eval(const Rec &at, const GridPt &g,
     const float ri = __builtin_amdgcn_rsqf(fmaxf(d2, 1e-30f));
     if (FULL) hit |= (d2 == 0.f);
     if (LJM != LJ_NONE) {
-        const float r2 = ri * ri;
+        // 1/d^2 for the LJ powers: ri^2 carries twice the error of the
+        // reciprocal square root, and r^-12 multiplies it by six again,
+        // enough to reach ~1.3e-6 at grid points next to an atom (where one
+        // pair dominates u).  One Newton step for the reciprocal of d2,
+        // r2 += r2 (1 - d2 r2), brings it to about half an ulp whatever the
+        // error of ri.
+        float r2 = ri * ri;
+        r2 = fmaf(r2, fmaf(-d2, r2, 1.0f), r2);
         float r6 = r2 * r2 * r2;
         if (LJM == LJ_CUT1) r6 = d2 < at.rc2[0] ? r6 : 0.f;
         // (A r^-6 - B) r^-6: the difference is formed before the product, so

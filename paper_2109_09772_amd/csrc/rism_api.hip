@@ -476,12 +476,12 @@ void rism_default_opts(rism_opts *o)
 {
     if (!o) return;
     std::memset(o, 0, sizeof(*o));
-    o->method = RISM_TREECODE;
+    o->method = RISM_TREECODE_CP;
     o->out_dtype = RISM_F32;
     o->coulomb_k = 332.0522173;
     o->lj_cutoff = 9.0;
     o->lj_tol = 0.0;
-    o->theta = 0.7;
+    o->theta = 0.6;
     o->degree = 8;
     o->leaf_size = 64;
     o->batch_edge = 8;

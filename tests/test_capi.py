@@ -38,8 +38,8 @@ def test_default_opts():
     from paper_2109_09772_amd import api
     o = api.OptsC()
     api.lib().rism_default_opts(C.byref(o))
-    assert o.method == 2 and o.out_dtype == 0 and o.degree == 8
-    assert o.theta == pytest.approx(0.7) and o.lj_cutoff == 9.0
+    assert o.method == api.METHODS["treecode_cp"] and o.out_dtype == 0 and o.degree == 8
+    assert o.theta == pytest.approx(0.6) and o.lj_cutoff == 9.0
     assert o.coulomb_k == pytest.approx(332.0522173)
 
 

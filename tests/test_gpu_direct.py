@@ -78,6 +78,41 @@ def test_ragged_salt_grid(oracle, method, cut):
     np.testing.assert_allclose(tail, tr, rtol=1e-12)
 
 
+@pytest.mark.parametrize("method", ["direct_f64", "direct_f32c"])
+def test_zero_epsilon_atom_under_tolerance(oracle, method):
+    """An atom with eps = 0 (no LJ term with any site) under a tolerance
+    cut-off: its pairs are dropped (radius 0) instead of failing the call,
+    and the tail constants match the oracle's."""
+    wl = W.tiny(n_atoms=40, dims=(23, 19, 17), seed=4, spacing=0.5)
+    wl.solute.xyz *= 1.5
+    wl.solute.eps[[3, 17]] = 0.0
+    u, c, h, tail = _run(wl, method, 0.0, 1e-4)
+    ur, cr, hr, tr = _oracle_grids(oracle, wl, 0.0, 1e-4)
+    _check(u, ur, method, "u")
+    _check(c, cr, method, "c")
+    np.testing.assert_allclose(tail, tr, rtol=1e-12)
+
+
+@pytest.mark.parametrize("method", ["direct_f64", "direct_f32c"])
+@pytest.mark.parametrize("cut", [0.0, 9.0])
+def test_interior_subgrid_every_point(oracle, method, cut):
+    """A 64^3 grid at 0.5 A centred inside the 2,500-atom solute: every point
+    lies in or next to the atom cloud, so u is set by the LJ cores of the
+    nearest atoms, the hardest case for FP32 pair rounding.  Every point of
+    u, c and h against the oracle (no sampling)."""
+    base = W.protein_2500()
+    wl = W.Workload("ellipsoid2500_grid64", base.solute, base.sites,
+                    W.centred_grid([0.0, 0.0, 0.0], 0.5, 64), base.seed)
+    u, c, h, tail = _run(wl, method, cut)
+    ur, cr, hr, tr = _oracle_grids(oracle, wl, cut)
+    for k in range(u.shape[0]):
+        print(f"{method} cut={cut} u[{k}] rel-L2 {rel_l2(u[k], ur[k], FP32_CAP)[0]:.3e}")
+    _check(u, ur, method, "u")
+    _check(c, cr, method, "c")
+    _check(h, hr, method, "h")
+    np.testing.assert_allclose(tail, tr, rtol=1e-12)
+
+
 @pytest.mark.parametrize("nsites", [1, 3, 5, 8])
 def test_site_counts(oracle, nsites):
     names = (list(W.SITES_SALT) * 2)[:nsites]

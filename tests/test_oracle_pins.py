@@ -5,6 +5,7 @@ and 7), quadrature of the LJ tail (Sec. 2.6), multipole far fields,
 invariances, Euler homogeneity, finite differences, and 40-digit brute force
 on tiny inputs.  A plausible slip in the oracle (a dropped term, a wrong sign,
 power or index, a transposed axis) fails at least one of these."""
+import dataclasses
 import math
 
 import mpmath as mp
@@ -156,6 +157,32 @@ def test_rcut_from_tolerance(oracle):
                                     KC, terms=2)[0, 0]
         assert abs(u) == pytest.approx(tol, rel=1e-9)
     assert oracle.lj_rcut_from_tol(3.0, 0.1, 0.2) < 0
+
+
+def test_tolerance_cutoff_with_zero_epsilon(oracle):
+    """An atom with eps = 0 (common for hydrogens) has eps_ga = 0 and no LJ
+    term with any site.  Under a tolerance cut-off (Sec. 2.6) its radius is
+    0: the pair is dropped and adds nothing to the tail, while the other
+    atoms keep their radii and tail terms."""
+    sol = W.ball_solute(4, 3.0, seed=9)
+    sol.eps[2] = 0.0
+    sites = W.make_sites(W.SITES_SALT)
+    rc = oracle.rcut_table(sol.sigma, sol.eps, sites.sigma, sites.eps, tol=1e-4)
+    assert (rc[:, 2] == 0).all() and (rc[:, [0, 1, 3]] > 0).all()
+    tail = oracle.lj_tail(sol.sigma, sol.eps, sites.sigma, sites.eps, rc)
+    keep = [0, 1, 3]
+    ref = oracle.lj_tail(sol.sigma[keep], sol.eps[keep], sites.sigma, sites.eps,
+                         np.ascontiguousarray(rc[:, keep]))
+    np.testing.assert_array_equal(tail, ref)
+    pts = sol.xyz[2:3] + np.array([[0.9, 0.0, 0.0]])
+    full = oracle.potential_points(sol.xyz, sol.q, sol.sigma, sol.eps, sites.q, sites.sigma,
+                                   sites.eps, pts, KC, rc)
+    part = oracle.potential_points(sol.xyz[keep], sol.q[keep], sol.sigma[keep], sol.eps[keep],
+                                   sites.q, sites.sigma, sites.eps, pts, KC,
+                                   np.ascontiguousarray(rc[:, keep]), terms=2)
+    coul = oracle.potential_points(sol.xyz, sol.q, sol.sigma, sol.eps, sites.q, sites.sigma,
+                                   sites.eps, pts, KC, terms=1)
+    np.testing.assert_allclose(full, part + coul, rtol=1e-14)
 
 
 def test_cutoff_truncates_lj_only(oracle):
@@ -346,14 +373,17 @@ def test_bruteforce_40_digits(oracle):
 
 # ----------------------------------------------------------------- backward
 
-def _per_atom_L(oracle, wl, w, a, xyz=None, q=None, sig=None, eps=None, pts=None, terms=3):
-    """sum_g sum_r w u_ga over the contribution of atom a alone."""
+def _per_atom_L(oracle, wl, w, a, xyz=None, q=None, sig=None, eps=None, pts=None, terms=3,
+                rcut=None):
+    """sum_g sum_r w u_ga over the contribution of atom a alone (``rcut``: the
+    [S][N] cut-off table of all atoms, held fixed)."""
     sol, s = wl.solute, wl.sites
     xyz = sol.xyz[a:a+1] if xyz is None else xyz
     q = sol.q[a:a+1] if q is None else q
     sig = sol.sigma[a:a+1] if sig is None else sig
     eps = sol.eps[a:a+1] if eps is None else eps
-    u = oracle.potential_points(xyz, q, sig, eps, s.q, s.sigma, s.eps, pts, KC, terms=terms)
+    rc = None if rcut is None else np.ascontiguousarray(rcut[:, a:a+1])
+    u = oracle.potential_points(xyz, q, sig, eps, s.q, s.sigma, s.eps, pts, KC, rc, terms=terms)
     return float((u * w).sum())
 
 
@@ -388,6 +418,89 @@ def test_backward_matches_finite_differences(oracle):
             fd = (_per_atom_L(oracle, wl, w, a, pts=pts, terms=2, **kw_p)
                   - _per_atom_L(oracle, wl, w, a, pts=pts, terms=2, **kw_m)) / (2 * h)
             assert grad[a] == pytest.approx(fd, rel=1e-6)
+
+
+@pytest.mark.parametrize("cut", ["global", "tolerance"])
+def test_backward_with_cutoff_matches_finite_differences(oracle, cut):
+    """The truncated-LJ branch of the gradient (Sec. 2.6, Eq. 28: LJ kept for
+    d < r_cut, Coulomb never truncated).  Central differences with Richardson
+    extrapolation of each atom's own contribution to the truncated
+    functional, on a grid where no point lies within 4h of any pair's r_cut,
+    so that no pair crosses its cut-off during the differencing.  The radii
+    are held fixed (under the tolerance rule they depend on sigma and eps;
+    their jump is not part of the gradient).  The LJ part (site charges 0)
+    and the Coulomb part (site eps 0, same radii) are differenced apart, so
+    that neither hides the other: a truncation missing from the LJ force,
+    sigma or eps terms, or one applied to the Coulomb force or dL/dQ, moves
+    the gradient by far more than the tolerance (asserted too)."""
+    # seed 30: every (point, atom, site) distance stays > 1e-3 A from its
+    # pair's cut-off radius in both modes (asserted below)
+    wl = W.tiny(n_atoms=5, dims=(7, 6, 8), seed=30, spacing=0.8)
+    sol, s, g = wl.solute, wl.sites, wl.grid
+    sol.xyz *= 1.3
+    pts = oracle.grid_points(g.origin, g.spacing, g.dims)
+    if cut == "global":
+        rc = oracle.rcut_table(sol.sigma, sol.eps, s.sigma, s.eps, rcut=3.1)
+    else:
+        rc = oracle.rcut_table(sol.sigma, sol.eps, s.sigma, s.eps, tol=2e-2)
+    h = 1e-4
+    d = np.linalg.norm(pts[None, :, :] - sol.xyz[:, None, :], axis=2)   # [N][M]
+    gap = np.abs(d[None, :, :] - rc[:, :, None])                        # [S][N][M]
+    assert gap.min() > 4 * h, gap.min()
+    inside = d[None, :, :] < rc[:, :, None]
+    assert inside.any() and (~inside).any()     # the cut-off acts on this grid
+    # weights vanish within 1.8 A of any atom, so that LJ cores do not swamp
+    # the terms near the cut-off radii
+    w = np.random.default_rng(5).uniform(0, 1, (s.n, len(pts))) * (d.min(0) >= 1.8)
+    lj_only = W.Workload("lj", sol, dataclasses.replace(s, q=np.zeros(s.n)), g, 0)
+    coul_only = W.Workload("coul", sol, dataclasses.replace(s, eps=np.zeros(s.n)), g, 0)
+    for part, wp in (("lj", lj_only), ("coulomb", coul_only)):
+        sp = wp.sites
+        grads = oracle.backward_points(sol.xyz, sol.q, sol.sigma, sol.eps, sp.q, sp.sigma,
+                                       sp.eps, pts, w, KC, rc)
+        full = oracle.backward_points(sol.xyz, sol.q, sol.sigma, sol.eps, sp.q, sp.sigma,
+                                      sp.eps, pts, w, KC)
+        dx = grads[0]
+        scale = np.abs(dx).max()
+        moved = np.abs(dx - full[0]).max()
+        if part == "lj":
+            # truncating the LJ terms moves the gradient by > 1e3 times the
+            # tolerance of the differences below
+            assert moved > 1e-5 * scale
+            for g_cut, g_full in zip(grads[2:], full[2:]):
+                assert np.abs(g_cut - g_full).max() > 1e-5 * np.abs(g_cut).max()
+        else:
+            # the Coulomb gradient ignores the radii, and most of it comes from
+            # points beyond them
+            np.testing.assert_allclose(dx, full[0], rtol=1e-13, atol=1e-13 * scale)
+            np.testing.assert_allclose(grads[1], full[1], rtol=1e-13)
+            beyond = max(np.abs(oracle.backward_points(
+                sol.xyz[a:a+1], sol.q[a:a+1], sol.sigma[a:a+1], sol.eps[a:a+1], sp.q,
+                sp.sigma, sp.eps, pts, w * ~inside[:, a, :], KC)[0]).max()
+                for a in range(sol.n))
+            assert beyond > 1e-2 * scale
+        for a in range(sol.n):
+            for k in range(3):
+                def L(hh):
+                    x = sol.xyz[a:a+1].copy()
+                    x[0, k] += hh
+                    return _per_atom_L(oracle, wp, w, a, xyz=x, pts=pts, rcut=rc)
+                d1 = (L(h) - L(-h)) / (2 * h)
+                d2 = (L(h / 2) - L(-h / 2)) / h
+                fd = (4 * d2 - d1) / 3
+                assert dx[a, k] == pytest.approx(fd, rel=1e-6, abs=1e-8 * scale), (part, a, k)
+            if part == "coulomb":
+                # linear in Q: the difference is exact
+                fq = (_per_atom_L(oracle, wp, w, a, q=sol.q[a:a+1] + 0.5, pts=pts, rcut=rc)
+                      - _per_atom_L(oracle, wp, w, a, q=sol.q[a:a+1] - 0.5, pts=pts, rcut=rc))
+                assert grads[1][a] == pytest.approx(fq, rel=1e-10)
+                continue
+            for arr, name, grad in ((sol.eps, "eps", grads[2]), (sol.sigma, "sig", grads[3])):
+                hh = 1e-6 * arr[a]
+                fd = (_per_atom_L(oracle, wp, w, a, pts=pts, rcut=rc, **{name: arr[a:a+1] + hh})
+                      - _per_atom_L(oracle, wp, w, a, pts=pts, rcut=rc,
+                                    **{name: arr[a:a+1] - hh})) / (2 * hh)
+                assert grad[a] == pytest.approx(fd, rel=1e-6, abs=1e-9 * np.abs(grad).max())
 
 
 def test_backward_euler_homogeneity(oracle):
