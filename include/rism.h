@@ -60,11 +60,18 @@ extern "C" {
  * RISM_TREECODE_CP  as RISM_TREECODE with the cluster-particle orientation of
  *                   the paper (Sec. 2.3): the tree is built on the grid
  *                   targets and atoms are interpolated into target clusters.
- * RISM_TREECODE_TAYLOR  as RISM_TREECODE_CP with the paper's own far field:
- *                   order-p Taylor polynomials of 1/d and exp(-kappa d)/d about
- *                   the target clusters' centres, their coefficients from the
- *                   recurrences of Secs. 2.3.2 and 2.4.2 (p = degree, 1..12);
- *                   no adjoint (rism_potential_backward: RISM_E_UNSUPPORTED). */
+ * RISM_TREECODE_TAYLOR  as RISM_TREECODE_CP with the paper's own far fields:
+ *                   order-p Taylor polynomials about the target clusters'
+ *                   centres of 1/d (u), erf(d/eta)/d (c^lr) and
+ *                   2 exp(-kappa d)/d (h^lr: the TCF kernel's large-distance
+ *                   form), coefficients from the recurrences of Secs. 2.3.2,
+ *                   2.4.1 and 2.4.2 (p = degree, 1..12); atoms not accepted
+ *                   take the exact kernels.  When h^lr is requested the MAC
+ *                   also requires |y - c| - r >= eta (6 + kappa eta / 2), so
+ *                   that the erfc -> 2/0 step is exact to ~1e-17 at every
+ *                   target.  RISM_FLAG_TAYLOR_SPLIT selects the exact-split
+ *                   variant.  No adjoint (rism_potential_backward:
+ *                   RISM_E_UNSUPPORTED). */
 #define RISM_DIRECT_F64 0
 #define RISM_DIRECT_F32C 1
 #define RISM_TREECODE 2
@@ -81,6 +88,12 @@ extern "C" {
                                           phase (read with rism_phase_times) */
 #define RISM_FLAG_STATS 4u            /* count evaluated interactions of the
                                           treecodes exactly (one extra sync) */
+#define RISM_FLAG_TAYLOR_SPLIT 8u     /* RISM_TREECODE_TAYLOR: the exact-split
+                                          variant (far fields 1/d and
+                                          exp(-kappa d)/d only, the smeared
+                                          kernels' remainders added exactly
+                                          within R_s) instead of the paper's
+                                          expansions of the smeared kernels */
 
 /* Kernel phases reported by rism_phase_times. */
 #define RISM_PHASE_STAGE 0        /* mixing, cut-offs, FP32/FP64 atom records */

@@ -66,8 +66,11 @@ def _load():
         lib.oracle_num_threads.restype = C.c_int
         lib.oracle_taylor_coeffs.argtypes = [C.c_int, _P, C.c_int, d, d, _P]
         lib.oracle_taylor_cp_points.argtypes = [i64, _P, _P, _P, _P, i32, _P, _P, _P, _PI, d,
-                                                _P, d, d, d, d, _P, _P, _PI, i32, d, i32, i64,
-                                                _PI, _P, _P, _P]
+                                                _P, d, d, d, d, _P, _P, _PI, i32, d, i32, d,
+                                                i64, _PI, _P, _P, _P]
+        lib.oracle_taylor_split_cp_points.argtypes = [i64, _P, _P, _P, _P, i32, _P, _P, _P,
+                                                      _PI, d, _P, d, d, d, d, _P, _P, _PI, i32,
+                                                      d, i32, i64, _PI, _P, _P, _P]
         _lib = lib
     return _lib
 
@@ -293,12 +296,16 @@ def taylor_coeffs(kind, v, p, eta=1.0, kappa=0.0):
     return out
 
 
-def taylor_cp_points(xyz, q, sigma, eps, site_q, site_sigma, site_eps, ionic, origin,
-                     spacing, dims, ijk, kc, eta, kappa, beta, diel, batch_edge, theta, p,
-                     rcut_tab=None):
-    """The Taylor-recurrence cluster-particle treecode at grid points ijk
-    (npts, 3): u [S][npts], c [S][npts], h [n_ionic][npts]."""
-    lib = _load()
+def taylor_guard(eta, kappa):
+    """Distance guard of the paper's Taylor treecode when h^lr is expanded:
+    eta (6 + kappa eta / 2), where the erfc -> 2/0 step of Sec. 2.4.2 is off
+    by about erfc(6) ~ 2e-17 (see the C file)."""
+    return eta * (6.0 + 0.5 * kappa * eta)
+
+
+def _taylor_call(fn, guard, xyz, q, sigma, eps, site_q, site_sigma, site_eps, ionic, origin,
+                 spacing, dims, ijk, kc, eta, kappa, beta, diel, batch_edge, theta, p,
+                 rcut_tab):
     xyz, q, sigma, eps = _atoms(xyz, q, sigma, eps)
     sq, ss, se = _d(site_q), _d(site_sigma), _d(site_eps)
     ion = np.ascontiguousarray(ionic, dtype=np.int32)
@@ -309,11 +316,38 @@ def taylor_cp_points(xyz, q, sigma, eps, site_q, site_sigma, site_eps, ionic, or
     u = np.empty((len(sq), len(g)))
     c = np.empty((len(sq), len(g)))
     h = np.empty((int(ion.sum()), len(g)))
-    rc = lib.oracle_taylor_cp_points(len(q), _ptr(xyz), _ptr(q), _ptr(sigma), _ptr(eps),
-                                     len(sq), _ptr(sq), _ptr(ss), _ptr(se), _ptr(ion, _PI),
-                                     float(kc), _ptr(rct), float(eta), float(kappa),
-                                     float(beta), float(diel), _ptr(o), _ptr(h_),
-                                     _ptr(dm, _PI), int(batch_edge), float(theta), int(p),
-                                     len(g), _ptr(g, _PI), _ptr(u), _ptr(c), _ptr(h))
+    args = [len(q), _ptr(xyz), _ptr(q), _ptr(sigma), _ptr(eps), len(sq), _ptr(sq), _ptr(ss),
+            _ptr(se), _ptr(ion, _PI), float(kc), _ptr(rct), float(eta), float(kappa),
+            float(beta), float(diel), _ptr(o), _ptr(h_), _ptr(dm, _PI), int(batch_edge),
+            float(theta), int(p)]
+    if guard is not None:
+        args.append(float(guard))
+    args += [len(g), _ptr(g, _PI), _ptr(u), _ptr(c), _ptr(h)]
+    rc = fn(*args)
     assert rc == 0
     return u, c, h
+
+
+def taylor_cp_points(xyz, q, sigma, eps, site_q, site_sigma, site_eps, ionic, origin,
+                     spacing, dims, ijk, kc, eta, kappa, beta, diel, batch_edge, theta, p,
+                     rcut_tab=None, guard=None):
+    """The paper's Taylor cluster-particle treecode (far fields: Taylor
+    polynomials of 1/d, erf(d/eta)/d and 2 exp(-kappa d)/d) at grid points
+    ijk (npts, 3): u [S][npts], c [S][npts], h [n_ionic][npts].  ``guard``:
+    the MAC's distance condition (default taylor_guard(eta, kappa); 0 = the
+    MAC alone)."""
+    if guard is None:
+        guard = taylor_guard(eta, kappa)
+    return _taylor_call(_load().oracle_taylor_cp_points, guard, xyz, q, sigma, eps, site_q,
+                        site_sigma, site_eps, ionic, origin, spacing, dims, ijk, kc, eta, kappa,
+                        beta, diel, batch_edge, theta, p, rcut_tab)
+
+
+def taylor_split_cp_points(xyz, q, sigma, eps, site_q, site_sigma, site_eps, ionic, origin,
+                           spacing, dims, ijk, kc, eta, kappa, beta, diel, batch_edge, theta, p,
+                           rcut_tab=None):
+    """The exact-split variant: far fields 1/d and 2 exp(-kappa d)/d only, the
+    smeared kernels' remainders added exactly within Rs (see the C file)."""
+    return _taylor_call(_load().oracle_taylor_split_cp_points, None, xyz, q, sigma, eps, site_q,
+                        site_sigma, site_eps, ionic, origin, spacing, dims, ijk, kc, eta, kappa,
+                        beta, diel, batch_edge, theta, p, rcut_tab)

@@ -578,32 +578,50 @@ static double taylor_eval(int kind, const double c[3], const double y[3], const 
 
 /*
  * The cluster-particle treecode of Sec. 2.3.1 with Taylor far fields, at
- * listed grid points (ijk [npts][3] grid indices).  Target tree: cubes of
- * B^3 grid points (level 0) merged 2 x 2 x 2 per level up to the level T
- * whose single cluster covers the grid (a cubic octree; reading of the
- * paper's splitting rule).  For a point x in level-0 block (I, J, K) and an
- * atom y, the atom is taken in the far field of the coarsest ancestor
- * cluster C (level >= 1) with r_C < theta |y - c_C|, r_C the half-diagonal
- * of C's box of grid points and c_C its centre (reading of the garbled MAC),
- * else directly.  Far fields are the order-p Taylor polynomials about c_C
- * of 1/d (u's Coulomb term and the long-range part of c^lr) and of
- * 2 exp(-kappa d)/d (h^lr's kernel at large d, Sec. 2.4.2); the remainders
+ * listed grid points (ijk [npts][3] grid indices), pair by pair.  Target
+ * tree: cubes of B^3 grid points (level 0) merged 2 x 2 x 2 per level up to
+ * the level T whose single cluster covers the grid (a cubic octree; reading
+ * of the paper's splitting rule).  For a point x in level-0 block (I, J, K)
+ * and an atom y, the atom belongs to the far field (a set I_l of Eq. 10) of
+ * the coarsest ancestor cluster C (level >= 1) it is well separated from,
+ * r_C < theta |y - c_C|, r_C the half-diagonal of C's box of grid points and
+ * c_C its centre (reading of the garbled MAC); otherwise to the direct set D.
+ * LJ is exact within each pair's cut-off either way.
+ *
+ * mode 0, the paper's far fields (oracle_taylor_cp_points):
+ *   u:    order-p Taylor polynomial of 1/d about c_C (Sec. 2.3.2);
+ *   c^lr: order-p Taylor polynomial of erf(d/eta)/d about c_C, coefficients
+ *         from the erf recurrence with its Gaussian auxiliary (Sec. 2.4.1);
+ *   h^lr: order-p Taylor polynomial of 2 exp(-kappa d)/d about c_C, the
+ *         large-distance form of the TCF kernel (Sec. 2.4.2, Eq. tcfexp),
+ *         with no correction for the erfc -> 2 and erfc -> 0 step.
+ *   Direct set: the exact kernels 1/d, erf(d/eta)/d and the Eq. 6 bracket
+ *   over d (d -> 0 limits at a coincident point).
+ *   guard > 0 adds a distance condition to the MAC: |y - c_C| - r_C >= guard,
+ *   so that no target of C lies closer to the atom than `guard`.  The
+ *   erfc -> 2/0 replacement is off by about erfc(d/eta - kappa eta/2) at
+ *   distance d; the paper relies on the MAC alone to make d large, which at
+ *   large theta it does not (reading: guard = eta (6 + kappa eta/2) bounds
+ *   that error by erfc(6) ~ 2e-17 at every target).  guard <= 0: MAC only.
+ *
+ * mode 1, the exact-split variant (oracle_taylor_split_cp_points): the far
+ * fields are the Taylor polynomials of 1/d (u, and c^lr's long-range part)
+ * and of 2 exp(-kappa d)/d (h^lr) only; for accepted atoms the remainders
  * erf(d/eta)/d - 1/d and the Eq. 6 bracket / d - 2 exp(-kappa d)/d are added
  * exactly where d < Rs = eta (5 + kappa eta/2), beyond which they are below
- * 1e-12 relative (reading: an exact split of the smeared kernels in place
- * of the erf-kernel expansion and the erfc asymptotics of Sec. 2.4).  LJ is
- * exact within each pair's cut-off.  Outputs as oracle_potential_points and
- * oracle_asymptotics_points: u [S][npts], c [S][npts], h [n_ionic][npts];
- * any may be NULL.
+ * 1e-12 relative.  No guard.
+ *
+ * Outputs as oracle_potential_points and oracle_asymptotics_points:
+ * u [S][npts], c [S][npts], h [n_ionic][npts]; any may be NULL.
  */
-int oracle_taylor_cp_points(int64_t n, const double *xyz, const double *q,
+static int taylor_cp_points(int mode, int64_t n, const double *xyz, const double *q,
                             const double *sig, const double *eps, int32_t ns,
                             const double *sq, const double *ssig, const double *seps,
                             const int32_t *ionic, double kc, const double *rcut,
                             double eta, double kappa, double beta, double diel,
                             const double *origin, const double *spacing,
                             const int32_t *dims, int32_t B, double theta, int32_t p,
-                            int64_t npts, const int32_t *ijk,
+                            double guard, int64_t npts, const int32_t *ijk,
                             double *u, double *c, double *h)
 {
     if (n < 0 || ns <= 0 || npts < 0 || B <= 0 || p < 0 || p > 40 || !(theta > 0.0))
@@ -627,6 +645,8 @@ int oracle_taylor_cp_points(int64_t n, const double *xyz, const double *q,
             const int32_t *g = ijk + 3 * i;
             const double x[3] = {origin[0] + g[0] * spacing[0], origin[1] + g[1] * spacing[1],
                                  origin[2] + g[2] * spacing[2]};
+            /* coul: 1/d sum (u); sc, sh: the c^lr and h^lr kernel sums (mode
+             * 0), or c^lr's remainders beside coul and h^lr's sum (mode 1) */
             double coul = 0.0, sc = 0.0, sh = 0.0;
             int hit = 0;
             for (int32_t s = 0; s < ns; ++s) uacc[s] = 0.0;
@@ -650,12 +670,17 @@ int oracle_taylor_cp_points(int64_t n, const double *xyz, const double *q,
                         r2 += 0.25 * (xh - xl) * (xh - xl);
                         R2 += (y[ax] - ctr[ax]) * (y[ax] - ctr[ax]);
                     }
-                    if (r2 < theta * theta * R2) {
+                    if (r2 < theta * theta * R2 &&
+                        (mode != 0 || guard <= 0.0 || sqrt(R2) - sqrt(r2) >= guard)) {
                         acc = 1;
                         for (int ax = 0; ax < 3; ++ax) cc[ax] = ctr[ax];
                     }
                 }
-                if (acc) {
+                if (acc && mode == 0) {
+                    coul += q[a] * taylor_eval(0, cc, y, x, p, eta, kappa, coef);
+                    sc += q[a] * taylor_eval(1, cc, y, x, p, eta, kappa, coef);
+                    sh += q[a] * taylor_eval(2, cc, y, x, p, eta, kappa, coef);
+                } else if (acc) {
                     coul += q[a] * taylor_eval(0, cc, y, x, p, eta, kappa, coef);
                     sh += q[a] * taylor_eval(2, cc, y, x, p, eta, kappa, coef);
                     if (d < rs) {
@@ -668,7 +693,7 @@ int oracle_taylor_cp_points(int64_t n, const double *xyz, const double *q,
                     sh += q[a] * tcf_kernel(d, eta, kappa);
                 } else {
                     coul += q[a] / d;
-                    sc += q[a] * (dcf_kernel(d, eta) - 1.0 / d);
+                    sc += q[a] * (mode == 0 ? dcf_kernel(d, eta) : dcf_kernel(d, eta) - 1.0 / d);
                     sh += q[a] * tcf_kernel(d, eta, kappa);
                 }
                 if (d > 0.0)
@@ -679,10 +704,11 @@ int oracle_taylor_cp_points(int64_t n, const double *xyz, const double *q,
                             uacc[s] += lj_pair(s_ga, e_ga, d);
                     }
             }
+            const double csum = mode == 0 ? sc : coul + sc;
             int32_t j = 0;
             for (int32_t s = 0; s < ns; ++s) {
                 if (u) u[(int64_t)s * npts + i] = hit ? INFINITY : kc * sq[s] * coul + uacc[s];
-                if (c) c[(int64_t)s * npts + i] = -beta * kc * sq[s] * (coul + sc);
+                if (c) c[(int64_t)s * npts + i] = -beta * kc * sq[s] * csum;
                 if (ionic[s]) {
                     if (h)
                         h[(int64_t)j * npts + i] = -beta * kc * sq[s] / (2.0 * diel) *
@@ -695,4 +721,34 @@ int oracle_taylor_cp_points(int64_t n, const double *xyz, const double *q,
         free(uacc);
     }
     return failed ? -1 : 0;
+}
+
+int oracle_taylor_cp_points(int64_t n, const double *xyz, const double *q,
+                            const double *sig, const double *eps, int32_t ns,
+                            const double *sq, const double *ssig, const double *seps,
+                            const int32_t *ionic, double kc, const double *rcut,
+                            double eta, double kappa, double beta, double diel,
+                            const double *origin, const double *spacing,
+                            const int32_t *dims, int32_t B, double theta, int32_t p,
+                            double guard, int64_t npts, const int32_t *ijk,
+                            double *u, double *c, double *h)
+{
+    return taylor_cp_points(0, n, xyz, q, sig, eps, ns, sq, ssig, seps, ionic, kc, rcut, eta,
+                            kappa, beta, diel, origin, spacing, dims, B, theta, p, guard, npts,
+                            ijk, u, c, h);
+}
+
+int oracle_taylor_split_cp_points(int64_t n, const double *xyz, const double *q,
+                                  const double *sig, const double *eps, int32_t ns,
+                                  const double *sq, const double *ssig, const double *seps,
+                                  const int32_t *ionic, double kc, const double *rcut,
+                                  double eta, double kappa, double beta, double diel,
+                                  const double *origin, const double *spacing,
+                                  const int32_t *dims, int32_t B, double theta, int32_t p,
+                                  int64_t npts, const int32_t *ijk,
+                                  double *u, double *c, double *h)
+{
+    return taylor_cp_points(1, n, xyz, q, sig, eps, ns, sq, ssig, seps, ionic, kc, rcut, eta,
+                            kappa, beta, diel, origin, spacing, dims, B, theta, p, 0.0, npts,
+                            ijk, u, c, h);
 }

@@ -32,6 +32,7 @@ DTYPES = {"f32": 0, "f64": 1}
 FLAG_NO_DEVICE_CHECK = 1
 FLAG_PHASE_EVENTS = 2
 FLAG_STATS = 4
+FLAG_TAYLOR_SPLIT = 8
 MAX_SITES = 8
 PHASES = ["stage", "direct_f64", "direct_f32", "tree_build", "upward", "lists", "eval",
           "downward", "adjoint", "adjoint_reduce", "other", "recip"]
@@ -124,6 +125,7 @@ class Opts:
     device_check: bool = True
     phase_events: bool = False
     stats: bool = False
+    taylor_split: bool = False
     max_workspace_bytes: int = 0
 
     def to_c(self) -> OptsC:
@@ -139,7 +141,8 @@ class Opts:
         o.leaf_size = self.leaf_size
         o.batch_edge = self.batch_edge
         o.flags = (0 if self.device_check else FLAG_NO_DEVICE_CHECK) | \
-            (FLAG_PHASE_EVENTS if self.phase_events else 0) | (FLAG_STATS if self.stats else 0)
+            (FLAG_PHASE_EVENTS if self.phase_events else 0) | \
+            (FLAG_STATS if self.stats else 0) | (FLAG_TAYLOR_SPLIT if self.taylor_split else 0)
         o.max_workspace_bytes = self.max_workspace_bytes
         return o
 

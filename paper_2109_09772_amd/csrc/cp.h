@@ -13,6 +13,9 @@ struct CpLevels {
     int B, T, nx, ny, nz;
     double h[3];
     double theta;
+    // > 0: distance condition added to the MAC, |y - c_C| - r_C >= guard (no
+    // target of an accepting cluster closer to the atom than guard); 0: none
+    double guard;
     int cx[kCpMaxLev + 1], cy[kCpMaxLev + 1], cz[kCpMaxLev + 1];
     int off[kCpMaxLev + 2];   // first id of level l (l = 1..T); off[T + 1] = clusters
 };
@@ -120,14 +123,22 @@ __device__ inline bool cp_mac(const CpLevels &L, int lvl, int I, int J, int K, c
         r2 += 0.25 * w * w;
         d2 += d * d;
     }
-    return r2 < L.theta * L.theta * d2;
+    return r2 < L.theta * L.theta * d2 && (L.guard <= 0.0 || sqrt(d2) - sqrt(r2) >= L.guard);
+}
+
+// Radius around a cluster's centre (half-diagonal r) beyond which every atom
+// is well separated from it: r / theta, or r + guard if that is larger.
+__host__ __device__ inline double cp_sep_radius(const CpLevels &L, double r)
+{
+    const double a = r / L.theta, b = r + L.guard;
+    return L.guard > 0.0 && b > a ? b : a;
 }
 
 // The MAC terms of one cluster, formed as cp_mac forms them: the box centre
 // and the squared half-diagonal.  Kept in LDS for a cluster's chain of
 // ancestors, they turn each test into a distance and one comparison.
 struct CpMac {
-    double c[3], r2;
+    double c[3], r2, r;
 };
 
 __device__ inline void cp_mac_terms(const CpLevels &L, int lvl, int I, int J, int K, CpMac &m)
@@ -141,6 +152,7 @@ __device__ inline void cp_mac_terms(const CpLevels &L, int lvl, int I, int J, in
         r2 += 0.25 * w * w;
     }
     m.r2 = r2;
+    m.r = sqrt(r2);
 }
 
 // Same result as cp_mac for the cluster whose terms m holds.
@@ -151,7 +163,7 @@ __device__ inline bool cp_mac_at(const CpLevels &L, const CpMac &m, const double
         const double d = y[k] - m.c[k];
         d2 += d * d;
     }
-    return m.r2 < L.theta * L.theta * d2;
+    return m.r2 < L.theta * L.theta * d2 && (L.guard <= 0.0 || sqrt(d2) - m.r >= L.guard);
 }
 
 // Coarsest level in [stop, T] along the chain of the level-0 block (I0, J0,

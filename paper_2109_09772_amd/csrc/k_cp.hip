@@ -208,8 +208,9 @@ static int scan_batch(const ScanBatch &b, Workspace &ws, hipStream_t s)
 // ----------------------------------------------------------------- queries
 
 // Candidate source leaves of every target query.
-//  mode 0 (clusters, levels 1..T): leaves reaching the ball (c_P, r_P/theta)
-//         of the parent P, or every leaf for the top cluster;
+//  mode 0 (clusters, levels 1..T): leaves reaching the ball around the
+//         parent P beyond which every atom is well separated from P
+//         (cp_sep_radius), or every leaf for the top cluster;
 //  mode 1 (level-0 blocks): leaves reaching the ball of the level-1 ancestor
 //         or the short range of the block.
 struct CpQueryArgs {
@@ -274,7 +275,8 @@ __device__ __forceinline__ void cp_query(const CpQueryArgs &a, int q, int *stk)
         } else {
             double r;
             cp_centre(L, lvl + 1, I >> 1, J >> 1, K >> 1, bc, r);
-            br2 = (r / L.theta) * (r / L.theta);
+            const double rb = cp_sep_radius(L, r);
+            br2 = rb * rb;
             has_ball = true;
         }
     } else {
@@ -284,7 +286,8 @@ __device__ __forceinline__ void cp_query(const CpQueryArgs &a, int q, int *stk)
         } else {
             double r;
             cp_centre(L, 1, I >> 1, J >> 1, K >> 1, bc, r);
-            br2 = (r / L.theta) * (r / L.theta);
+            const double rb = cp_sep_radius(L, r);
+            br2 = rb * rb;
             has_ball = true;
         }
         if (a.rshort > 0) {
@@ -679,7 +682,9 @@ struct CpSweepArgs {
     int degree, np;
     float yk;
     double kappa;   // Taylor moments of the screened kernel
-    double *part;   // [items][2][np]
+    double eta;     // Taylor moments of the erf kernel (paper far field)
+    int nc;         // components per item and cluster: 2, or 3 with the erf kernel
+    double *part;   // [items][nc][np]
     const uint32_t *n_items;
     const int *bad;
 };
@@ -763,8 +768,8 @@ __global__ __launch_bounds__(kBlock) void k_cp_sweep(CpSweepArgs a)
         for (int r = 0; r < NR; ++r) {
             const int k = k0 + r * kBlock + threadIdx.x;
             if (k < a.np) {
-                a.part[((size_t)item * 2 + 0) * a.np + k] = aC[r];
-                a.part[((size_t)item * 2 + 1) * a.np + k] = aY[r];
+                a.part[((size_t)item * a.nc + 0) * a.np + k] = aC[r];
+                a.part[((size_t)item * a.nc + 1) * a.np + k] = aY[r];
             }
         }
     }
@@ -853,8 +858,8 @@ __global__ __launch_bounds__(kBlock) void k_cp_sweep_lines(CpSweepArgs a)
         for (int r = 0; r < NI; ++r) {
             if (i0 + r < n1) {
                 const int k = i0 + r + n1 * line;
-                a.part[((size_t)item * 2 + 0) * a.np + k] = aC[r];
-                a.part[((size_t)item * 2 + 1) * a.np + k] = aY[r];
+                a.part[((size_t)item * a.nc + 0) * a.np + k] = aC[r];
+                a.part[((size_t)item * a.nc + 1) * a.np + k] = aY[r];
             }
         }
     }
@@ -893,38 +898,51 @@ void launch_sweep(int nitems, int np, int degree, const CpSweepArgs &sa, hipStre
 }
 
 // ----------------------------------------------------- Taylor far field
-// The paper's own far field (Secs. 2.3.1, 2.3.2, 2.4.2), as the method
+// The paper's own far field (Secs. 2.3.1, 2.3.2, 2.4.1, 2.4.2), as the method
 // RISM_TREECODE_TAYLOR: per target cluster the moments
 //   m_k = sum_atoms Q t_k(y - c),   |k| <= p,
-// of the order-p Taylor polynomials of 1/d and exp(-kappa d)/d about the
-// cluster centre c (the screened kernel's factor 2 is applied with h's other
-// terms), by the recurrences in terms of v = y - c:
+// of the order-p Taylor polynomials about the cluster centre c of 1/d (u),
+// exp(-kappa d)/d (h^lr; the factor 2 of the TCF's far-field form is applied
+// with h's other terms) and, in the paper's form, erf(d/eta)/d (c^lr), by the
+// recurrences in terms of v = y - c:
 //   t_k = [(2 - 1/|k|) sum_i v_i t_{k-e_i} - (1 - 1/|k|) sum_i t_{k-2e_i}
-//          + (kappa/|k|)(sum_i v_i b_{k-e_i} - sum_i b_{k-2e_i})] / R^2,
-//   b_k = (kappa/|k|)(sum_i v_i t_{k-e_i} - sum_i t_{k-2e_i}),
-// the b terms for the screened kernel only, with t_0 = 1/R or
-// exp(-kappa R)/R and b_0 = exp(-kappa R).  The moments take the place of
-// the proxy values: the downward pass shifts them to the children's centres
-// and the leaves evaluate the polynomial at their points.
+//          + X_k] / R^2,
+//   screened:  X_k = (kappa/|k|)(sum_i v_i b_{k-e_i} - sum_i b_{k-2e_i}),
+//              b_k = (kappa/|k|)(sum_i v_i t_{k-e_i} - sum_i t_{k-2e_i}),
+//              t_0 = exp(-kappa R)/R, b_0 = exp(-kappa R);
+//   erf:       X_k = g_k = (2/(eta^2 |k|))(sum_i v_i g_{k-e_i} - sum_i g_{k-2e_i}),
+//              t_0 = erf(R/eta)/R, g_0 = -(eta/sqrt(pi)) exp(-R^2/eta^2);
+//   1/R:       X_k = 0, t_0 = 1/R.
+// The moments take the place of the proxy values: the downward pass shifts
+// them to the children's centres and the leaves evaluate the polynomials at
+// their points.
 //
 // One workgroup per work item; its atoms are dealt to the four waves.  A
-// wave runs one atom's recurrence degree by degree, a lane per coefficient
+// wave runs one atom's recurrences degree by degree, a lane per coefficient
 // of the degree, with the coefficients in LDS in FP64 (tetrahedral layout:
 // degree d starts at d(d+1)(d+2)/6; within it, k = (k1, k2, k3) sits at
 // (d-k1)(d-k1+1)/2 + k3).  The wave's moments are in LDS too, each entry
 // owned by one lane; the four waves' moments are added in wave order into
 // the item's partial, in the cube layout [(p+1)^3] of the proxy values
-// (zero above order p).
+// (zero above order p): component 0 the 1/d moments, 1 the screened ones,
+// 2 the erf ones.
 constexpr int kMaxTaylor = 12;
 
 __host__ __device__ inline int tet_off(int d) { return d * (d + 1) * (d + 2) / 6; }
 
-inline size_t cp_taylor_lds(int p, bool asym)
+// Coefficient arrays per wave: tC, mC [, tS, bS, mS [, tE, gE, mE]].
+__host__ __device__ inline int cp_taylor_arrays(bool asym, bool paper)
 {
-    return (size_t)(kBlock / 64) * (asym ? 5 : 2) * tet_off(p + 1) * sizeof(double);
+    return asym ? (paper ? 8 : 5) : 2;
 }
 
-template <bool ASYM>
+inline size_t cp_taylor_lds(int p, bool asym, bool paper)
+{
+    return (size_t)(kBlock / 64) * cp_taylor_arrays(asym, paper) * tet_off(p + 1) *
+           sizeof(double);
+}
+
+template <bool ASYM, bool PAPER>
 __global__ __launch_bounds__(kBlock) void k_cp_taylor(CpSweepArgs a)
 {
     extern __shared__ double sm[];
@@ -935,14 +953,17 @@ __global__ __launch_bounds__(kBlock) void k_cp_taylor(CpSweepArgs a)
     const int p = a.degree, n1 = p + 1, nt = tet_off(p + 1);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    constexpr int NA = ASYM ? 5 : 2;   // per wave: tC, mC [, tS, bS, mS]
+    constexpr int NA = ASYM ? (PAPER ? 8 : 5) : 2;
     double *tC = sm + (size_t)wave * NA * nt, *mC = tC + nt;
     double *tS = tC + 2 * nt, *bS = tC + 3 * nt, *mS = tC + 4 * nt;
+    double *tE = tC + 5 * nt, *gE = tC + 6 * nt, *mE = tC + 7 * nt;
     for (int i = lane; i < nt; i += 64) {
         mC[i] = 0.0;
         if (ASYM) mS[i] = 0.0;
+        if (ASYM && PAPER) mE[i] = 0.0;
     }
-    const double kap = a.kappa;
+    const double kap = a.kappa, eta = a.eta;
+    const double ge = PAPER ? 2.0 / (eta * eta) : 0.0;
     for (int s = wave; s < n; s += kBlock / 64) {
         ConstAS<Quad> &av = at[s];
         const double v[3] = {av.x, av.y, av.z}, q = av.w;
@@ -958,12 +979,17 @@ __global__ __launch_bounds__(kBlock) void k_cp_taylor(CpSweepArgs a)
                 bS[0] = e;
                 mS[0] += q * tS[0];
             }
+            if (ASYM && PAPER) {
+                tE[0] = erf(R / eta) / R;
+                gE[0] = -(eta / sqrt(kPi)) * exp(-R2 / (eta * eta));
+                mE[0] += q * tE[0];
+            }
         }
         for (int d = 1; d <= p; ++d) {
             __builtin_amdgcn_wave_barrier();   // degree d - 1 written by every lane
             const int Ld = (d + 1) * (d + 2) / 2;
             const int o0 = tet_off(d), o1 = tet_off(d - 1), o2 = d >= 2 ? tet_off(d - 2) : 0;
-            const double c1 = 2.0 - 1.0 / d, c2 = 1.0 - 1.0 / d, kd = kap / d;
+            const double c1 = 2.0 - 1.0 / d, c2 = 1.0 - 1.0 / d, kd = kap / d, gd = ge / d;
             for (int pos = lane; pos < Ld; pos += 64) {
                 // pos = m(m+1)/2 + k3 with m = d - k1
                 int m = (int)((sqrtf(8.f * pos + 1.f) - 1.f) * 0.5f);
@@ -996,37 +1022,49 @@ __global__ __launch_bounds__(kBlock) void k_cp_taylor(CpSweepArgs a)
                     bS[o0 + pos] = kd * (a1 - a2);
                     mS[o0 + pos] += q * ts;
                 }
+                if (ASYM && PAPER) {
+                    double e2, g2;
+                    const double e1 = sums(tE, e2), g1 = sums(gE, g2);
+                    const double gk = gd * (g1 - g2);
+                    const double te = (c1 * e1 - c2 * e2 + gk) * iR2;
+                    gE[o0 + pos] = gk;
+                    tE[o0 + pos] = te;
+                    mE[o0 + pos] += q * te;
+                }
             }
         }
     }
     __syncthreads();
-    double *out = a.part + (size_t)item * 2 * a.np;
+    double *out = a.part + (size_t)item * a.nc * a.np;
     for (int k = threadIdx.x; k < a.np; k += kBlock) {
         const int k1 = k % n1, k2 = (k / n1) % n1, k3 = k / (n1 * n1), d = k1 + k2 + k3;
-        double sc = 0.0, ss = 0.0;
+        double sc = 0.0, ss = 0.0, se = 0.0;
         if (d <= p) {
             const int idx = tet_off(d) + (d - k1) * (d - k1 + 1) / 2 + k3;
             for (int w = 0; w < kBlock / 64; ++w) {
                 sc += sm[(size_t)w * NA * nt + nt + idx];
                 if (ASYM) ss += sm[(size_t)w * NA * nt + 4 * nt + idx];
+                if (ASYM && PAPER) se += sm[(size_t)w * NA * nt + 7 * nt + idx];
             }
         }
         out[k] = sc;
         out[a.np + k] = ss;
+        if (a.nc > 2) out[2 * a.np + k] = se;
     }
 }
 
-// V[cl] = sum of the partials of its items, in item order.
-__global__ __launch_bounds__(kBlock) void k_cp_reduce(int nclusters, int np, const uint32_t *item_off,
-                                                      const int *bad, const double *part, double *V)
+// V[cl] = sum of the partials of its items, in item order (nc components).
+__global__ __launch_bounds__(kBlock) void k_cp_reduce(int nclusters, int np, int nc,
+                                                      const uint32_t *item_off, const int *bad,
+                                                      const double *part, double *V)
 {
     const int cl = blockIdx.x;
     if (cl >= nclusters || *bad) return;
     const int i0 = (int)item_off[cl], i1 = (int)item_off[cl + 1];
-    for (int k = threadIdx.x; k < 2 * np; k += kBlock) {
+    for (int k = threadIdx.x; k < nc * np; k += kBlock) {
         double s = 0.0;
-        for (int it = i0; it < i1; ++it) s += part[(size_t)it * 2 * np + k];
-        V[(size_t)cl * 2 * np + k] = s;
+        for (int it = i0; it < i1; ++it) s += part[(size_t)it * nc * np + k];
+        V[(size_t)cl * nc * np + k] = s;
     }
 }
 
@@ -1151,15 +1189,15 @@ __device__ __forceinline__ double dot_lds(const double *row, const double *src, 
 }
 
 __global__ __launch_bounds__(kDownThreads) void k_cp_down(CpLevels L, int lvl, int degree,
-                                                          int nc, const double *Mtab,
+                                                          int ncomp, int nc, const double *Mtab,
                                                           int3 mrow0, double *V)
 {
     extern __shared__ double sm[];
-    const int n1 = degree + 1, np = n1 * n1 * n1, ne = nc * np;
+    const int n1 = degree + 1, np = n1 * n1 * n1;
     double *M = sm;                 // [3][n1][n1]
     double *src = M + 3 * n1 * n1;  // [nc][np]
-    double *t1 = src + ne;          // [nc][np]
-    double *t2 = t1 + ne;           // [nc][np]
+    double *t1 = src + nc * np;     // [nc][np]
+    double *t2 = t1 + nc * np;      // [nc][np]
     const int q = blockIdx.x;
     const int I = q % L.cx[lvl], J = (q / L.cx[lvl]) % L.cy[lvl], K = q / (L.cx[lvl] * L.cy[lvl]);
     const int id = cp_id(L, lvl, I, J, K);
@@ -1170,10 +1208,12 @@ __global__ __launch_bounds__(kDownThreads) void k_cp_down(CpLevels L, int lvl, i
         const int r0 = ax == 0 ? mrow0.x + I * n1 : (ax == 1 ? mrow0.y + J * n1 : mrow0.z + K * n1);
         M[t] = Mtab[(size_t)r0 * n1 + km];
     }
-    for (int comp0 = 0; comp0 < 2; comp0 += nc) {
+    // ncomp components per cluster (V [cluster][ncomp][np]), up to nc per pass
+    for (int comp0 = 0; comp0 < ncomp; comp0 += nc) {
+        const int ne = min(nc, ncomp - comp0) * np;
         if (comp0 > 0) __syncthreads();   // the previous pass is done with src
         for (int e = threadIdx.x; e < ne; e += kDownThreads)
-            src[e] = V[((size_t)pid * 2 + comp0) * np + e];
+            src[e] = V[((size_t)pid * ncomp + comp0) * np + e];
         __syncthreads();   // M and src ready
         // entry e = c np + k, k = (z, y, x) with x fastest; contract x, then y,
         // then z
@@ -1192,7 +1232,7 @@ __global__ __launch_bounds__(kDownThreads) void k_cp_down(CpLevels L, int lvl, i
         for (int e = threadIdx.x; e < ne; e += kDownThreads) {
             const int c = e / np, k = e - c * np;
             const int k12 = k % (n1 * n1), k3 = k / (n1 * n1);
-            V[((size_t)id * 2 + comp0) * np + e] +=
+            V[((size_t)id * ncomp + comp0) * np + e] +=
                 dot_lds(M + (2 * n1 + k3) * n1, t2 + c * np + k12, n1 * n1, n1);
         }
     }
@@ -1216,8 +1256,18 @@ struct CpLeafArgs {
     int lrow0[3];              // first row of each axis in Lg
     int degree, np;
     int taylor;                // basis: Lagrange (0) or monomials about the centre (1)
+    int ncomp;                 // components per cluster in V (2, or 3 with the erf kernel)
+    int paper;                 // Taylor far fields of the paper: u from the 1/d
+                               // moments, c^lr from the erf moments (component 2),
+                               // short-range atoms contribute LJ only
     unsigned long long *work;  // optional: [0] direct pairs, [1] short-range pairs
 };
+
+// Far-field components the leaf interpolates: 1/d [, exp(-kappa d)/d [, erf]].
+__host__ __device__ inline int cp_leaf_ncomp(bool asym, bool paper)
+{
+    return asym ? (paper ? 3 : 2) : 1;
+}
 
 // One grid point per thread, up to 512 threads per block.
 template <int B>
@@ -1233,10 +1283,10 @@ static_assert(kLeafStage % kAtomPad == 0, "leaf chunks must keep the flush point
 
 // Doubles of the leaf kernel's LDS before the atom chunk, rounded up to an
 // even count so that the 16-byte records start aligned.
-__host__ __device__ inline size_t cp_leaf_head(int B, int degree, bool asym)
+__host__ __device__ inline size_t cp_leaf_head(int B, int degree, bool asym, bool paper)
 {
     const size_t n1 = degree + 1, np = n1 * n1 * n1;
-    const size_t ncomp = asym ? 2 : 1;
+    const size_t ncomp = cp_leaf_ncomp(asym, paper);
     const size_t d = (asym ? 4 * (size_t)kSmearIntervals : 0) + ncomp * n1 * B * B +
                      3 * (size_t)B * n1 + np + n1 * n1 * B;
     return (d + 1) & ~(size_t)1;
@@ -1244,9 +1294,9 @@ __host__ __device__ inline size_t cp_leaf_head(int B, int degree, bool asym)
 
 // Dynamic LDS of the leaf kernel, in bytes (layout in k_cp_leaf), for atom
 // records of rec_bytes.
-inline size_t cp_leaf_lds(int B, int degree, bool asym, size_t rec_bytes)
+inline size_t cp_leaf_lds(int B, int degree, bool asym, bool paper, size_t rec_bytes)
 {
-    return cp_leaf_head(B, degree, asym) * sizeof(double) + kLeafStage * rec_bytes;
+    return cp_leaf_head(B, degree, asym, paper) * sizeof(double) + kLeafStage * rec_bytes;
 }
 
 // The atoms of one index list against this thread's point, flushed every
@@ -1293,7 +1343,8 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
 {
     using S = LeafShape<B>;
     constexpr int NT = S::threads;
-    constexpr int NCOMP = ASYM ? 2 : 1;
+    const bool paper = ASYM && a.paper;
+    const int NCOMP = cp_leaf_ncomp(ASYM, paper);
     extern __shared__ double sm[];
     const int n1 = a.degree + 1;
     float4 *tab = reinterpret_cast<float4 *>(sm);
@@ -1301,7 +1352,8 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
     double *Lb = T2 + NCOMP * n1 * B * B;                  // [3][B][n1]
     double *Vs = Lb + 3 * B * n1;                          // [np]
     double *T1 = Vs + a.np;                                // [n1][n1][B]
-    AtomF32<NS> *stg = reinterpret_cast<AtomF32<NS> *>(sm + cp_leaf_head(B, a.degree, ASYM));
+    AtomF32<NS> *stg =
+        reinterpret_cast<AtomF32<NS> *>(sm + cp_leaf_head(B, a.degree, ASYM, paper));
     if (*a.bad) return;   // whole workgroup
     const CpLevels &L = a.L;
     const GridParams &g = a.g;
@@ -1330,7 +1382,7 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
         for (int comp = 0; comp < NCOMP; ++comp) {
             __syncthreads();
             for (int k = threadIdx.x; k < a.np; k += NT)
-                Vs[k] = a.V[((size_t)a1 * 2 + comp) * a.np + k];
+                Vs[k] = a.V[((size_t)a1 * a.ncomp + comp) * a.np + k];
             __syncthreads();
             // T1[k1][k2][z] = sum_k3 V[k3][k2][k1] Lz[z][k3]
             for (int t = threadIdx.x; t < n1 * n1 * B; t += NT) {
@@ -1368,6 +1420,9 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
                                   valid ? k0 + lk : k0);
         PointAcc<NS> acc;
         acc.zero();
+        // paper's Taylor far fields: u and c^lr take the 1/d and erf(d/eta)/d
+        // expansions, so both stay out of acc.C
+        double far_u = 0.0, far_c = 0.0;
 
         // ---------------------------------------------- far: last contraction
         if (L.T >= 1) {
@@ -1376,25 +1431,33 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
                 double s = 0;
                 for (int k1 = 0; k1 < n1; ++k1)
                     s += T2c[(k1 * B + lj) * B + lk] * Lb[(0 * B + li) * n1 + k1];
-                if (comp == 0) acc.C = s;
-                else acc.Y = s;
+                if (comp == 1) acc.Y = s;
+                else if (comp == 2) far_c = s;
+                else if (paper) far_u = s;
+                else acc.C = s;
             }
         }
 
         // ---------------------------------------------- direct and short
+        // short-range atoms (far field from the clusters): LJ, and for the
+        // exact-split far fields the smeared kernels' remainders
         if (g.exact) {
             leaf_atoms<NS, LJM, ASYM, true, true, NT>(grec, dl, ndir, stg, gp, kc, tab, acc);
-            if (LJM != LJ_NONE || ASYM)
+            if (ASYM && !paper)
                 leaf_atoms<NS, LJM, ASYM, true, false, NT>(grec, sl, nsh, stg, gp, kc, tab, acc);
+            else if (LJM != LJ_NONE)
+                leaf_atoms<NS, LJM, false, true, false, NT>(grec, sl, nsh, stg, gp, kc, tab, acc);
         } else {
             leaf_atoms<NS, LJM, ASYM, false, true, NT>(grec, dl, ndir, stg, gp, kc, tab, acc);
-            if (LJM != LJ_NONE || ASYM)
+            if (ASYM && !paper)
                 leaf_atoms<NS, LJM, ASYM, false, false, NT>(grec, sl, nsh, stg, gp, kc, tab, acc);
+            else if (LJM != LJ_NONE)
+                leaf_atoms<NS, LJM, false, false, false, NT>(grec, sl, nsh, stg, gp, kc, tab, acc);
         }
 
         if (valid) {
             const int64_t p = ((int64_t)(k0 + lk) * g.ny + (j0 + lj)) * g.nx + (i0 + li);
-            store_point<NS, LJM, ASYM>(a.out, g, p, acc);
+            store_point<NS, LJM, ASYM>(a.out, g, p, acc, far_u, far_c);
         }
     }
 }
@@ -1471,7 +1534,7 @@ struct CpShape {
     int dev, leaf, deg;
     int64_t n;
     int nleaf, ncl;
-    double theta, rshort;
+    double theta, rshort, guard;
     bool operator<(const CpShape &o) const
     {
         if (dev != o.dev) return dev < o.dev;
@@ -1481,7 +1544,8 @@ struct CpShape {
         if (deg != o.deg) return deg < o.deg;
         if (leaf != o.leaf) return leaf < o.leaf;
         if (theta != o.theta) return theta < o.theta;
-        return rshort < o.rshort;
+        if (rshort != o.rshort) return rshort < o.rshort;
+        return guard < o.guard;
     }
 };
 std::mutex g_cp_caps_mu;
@@ -1503,6 +1567,17 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     }
     const int ncl = L.T >= 1 ? L.off[L.T + 1] : 0;
     const int nleaf = L.cx[0] * L.cy[0] * L.cz[0];
+    const bool taylor = a.opts->method == RISM_TREECODE_TAYLOR;
+    // the paper's Taylor far fields (expansions of 1/d, erf(d/eta)/d and
+    // 2 exp(-kappa d)/d), unless the exact-split variant is asked for
+    const bool paper = taylor && !(a.opts->flags & RISM_FLAG_TAYLOR_SPLIT);
+    // with h^lr expanded as 2 exp(-kappa d)/d (the erfc -> 2/0 step), no
+    // target of an accepting cluster may come within eta (6 + kappa eta/2)
+    // of the atom, where that step is off by more than erfc(6) ~ 2e-17
+    if (paper && a.out.want_h)
+        L.guard = a.asym.eta * (6.0 + 0.5 * a.asym.kappa * a.asym.eta);
+    // components per cluster in the proxy / moment arrays
+    const int nc = paper && a.asym_on ? 3 : 2;
 
     // source tree on the atoms (Morton sort, boxes) for the neighbour queries
     TreeDev t{};
@@ -1513,7 +1588,10 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     }
     if (rc) return rc;
     const int stride_f4 = (int)(rec32_bytes_of(a.sp.ns_pad) / sizeof(float4));
-    double rshort = a.asym_on ? std::sqrt(a.asym.rs2) : 0.0;
+    // short range of the leaves: LJ within its cut-off and, unless the far
+    // fields are the paper's own expansions of the smeared kernels, their
+    // remainders within R_s
+    double rshort = a.asym_on && !paper ? std::sqrt(a.asym.rs2) : 0.0;
     if (a.lj_mode == LJ_CUT) rshort = std::max(rshort, a.rmax_short);
 
     // queries: clusters (mode 0) and leaves (mode 1), count pass
@@ -1542,7 +1620,6 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     qa.stack_w = cp_query_stack(t.cap_nodes);
     const size_t qshm = (size_t)qa.stack_w * sizeof(int);
     // the per-call tables; the same launch clears the query overflow flag
-    const bool taylor = a.opts->method == RISM_TREECODE_TAYLOR;
     CpTabArgs ta{};
     ta.L = L;
     ta.degree = deg;
@@ -1596,8 +1673,8 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
 
     int lds_max = 0;
     RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t leaf_shm = cp_leaf_lds(B, deg, a.asym_on, rec32_bytes_of(a.sp.ns_pad));
-    if (taylor && (deg > kMaxTaylor || cp_taylor_lds(deg, a.asym_on) > (size_t)lds_max)) {
+    const size_t leaf_shm = cp_leaf_lds(B, deg, a.asym_on, paper, rec32_bytes_of(a.sp.ns_pad));
+    if (taylor && (deg > kMaxTaylor || cp_taylor_lds(deg, a.asym_on, paper) > (size_t)lds_max)) {
         set_error("Taylor treecode: order above 12 or its LDS beyond this device");
         return RISM_E_UNSUPPORTED;
     }
@@ -1610,7 +1687,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     unsigned long long *work = want_stats ? ws.get<unsigned long long>(4) : nullptr;
     uint32_t *nd = ws.get<uint32_t>(nleaf), *nsh = ws.get<uint32_t>(nleaf);
     int *order = ws.get<int>(nleaf);
-    double *V = ws.get<double>((size_t)(ncl + 1) * 2 * np);
+    double *V = ws.get<double>((size_t)(ncl + 1) * nc * np);
     if (ws.status()) return ws.status();
 
     // Everything after the counts, with buffers of the given capacities.
@@ -1623,7 +1700,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
                  *it_n = ws.get<uint32_t>(cap.c[1] + 1);
         float4 *abuf = ws.get<float4>((size_t)cap.c[4] + 1);
         int *dlist = ws.get<int>(cap.c[3] + 1), *slist = ws.get<int>(cap.c[3] + 1);
-        double *part = ws.get<double>((size_t)(cap.c[1] + 1) * 2 * np);
+        double *part = ws.get<double>((size_t)(cap.c[1] + 1) * nc * np);
         if (ws.status()) return ws.status();
         if (work) hipLaunchKernelGGL(k_fill_u64, 1, 64, 0, s, work, 4);
         qa.bad = bad;
@@ -1715,15 +1792,22 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
                 sa.np = np;
                 sa.yk = (float)a.asym.yk;
                 sa.kappa = a.asym.kappa;
+                sa.eta = a.asym.eta;
+                sa.nc = nc;
                 sa.part = part;
                 sa.n_items = tot + 1;
                 sa.bad = bad;
                 if (taylor) {
-                    const size_t tshm = cp_taylor_lds(deg, a.asym_on);
-                    if (a.asym_on)
-                        hipLaunchKernelGGL(k_cp_taylor<true>, (int)cap.c[1], kBlock, tshm, s, sa);
+                    const size_t tshm = cp_taylor_lds(deg, a.asym_on, paper);
+                    if (a.asym_on && paper)
+                        hipLaunchKernelGGL((k_cp_taylor<true, true>), (int)cap.c[1], kBlock, tshm,
+                                           s, sa);
+                    else if (a.asym_on)
+                        hipLaunchKernelGGL((k_cp_taylor<true, false>), (int)cap.c[1], kBlock, tshm,
+                                           s, sa);
                     else
-                        hipLaunchKernelGGL(k_cp_taylor<false>, (int)cap.c[1], kBlock, tshm, s, sa);
+                        hipLaunchKernelGGL((k_cp_taylor<false, false>), (int)cap.c[1], kBlock,
+                                           tshm, s, sa);
                 } else if (a.asym_on) {
                     launch_sweep<true>((int)cap.c[1], np, deg, sa, s);
                 } else {
@@ -1733,11 +1817,11 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         }
         if (ncl > 0) {
             PhaseTimer pt(ev, RISM_PHASE_DOWNWARD, s);
-            hipLaunchKernelGGL(k_cp_reduce, ncl, kBlock, 0, s, ncl, np, citems, (const int *)bad,
-                               part, V);
+            hipLaunchKernelGGL(k_cp_reduce, ncl, kBlock, 0, s, ncl, np, nc, citems,
+                               (const int *)bad, part, V);
             for (int lvl = L.T - 1; lvl >= 1; --lvl)
                 hipLaunchKernelGGL(k_cp_down, L.cx[lvl] * L.cy[lvl] * L.cz[lvl], kDownThreads,
-                                   cp_down_lds(deg, down_nc), s, L, lvl, deg, down_nc,
+                                   cp_down_lds(deg, down_nc), s, L, lvl, deg, nc, down_nc,
                                    (const double *)ta.M,
                                    make_int3(ta.mrow0[lvl][0], ta.mrow0[lvl][1], ta.mrow0[lvl][2]),
                                    V);
@@ -1764,6 +1848,8 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         la.degree = deg;
         la.np = np;
         la.taylor = taylor;
+        la.ncomp = nc;
+        la.paper = paper;
         la.work = work;
         {
             PhaseTimer pt(ev, RISM_PHASE_EVAL, s);
@@ -1796,7 +1882,8 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         if (ncl == 0) hres[0] = hres[1] = hres[4] = 0;
         return RISM_OK;
     };
-    const CpShape shape{dev, a.opts->leaf_size, deg, a.solute->n, nleaf, ncl, a.opts->theta, rshort};
+    const CpShape shape{dev,   a.opts->leaf_size, deg,    a.solute->n, nleaf,
+                        ncl,   a.opts->theta,     rshort, L.guard};
     CpCaps cached{};
     bool have = false;
     {

@@ -218,12 +218,16 @@ __device__ __forceinline__ void store_val(void *base, int f64, int64_t idx, doub
 }
 
 // Writes every requested output of one grid point from its running sums.
+// far_u / far_c: far-field sums kept apart from acc.C because u and c^lr
+// take different far fields (the Taylor treecode's 1/d and erf(d/eta)/d
+// expansions); zero elsewhere.
 template <int NS, int LJM, bool ASYM>
 __device__ __forceinline__ void store_point(const OutParams &o, const GridParams &g, int64_t p,
-                                            const PointAcc<NS> &acc)
+                                            const PointAcc<NS> &acc, double far_u = 0.0,
+                                            double far_c = 0.0)
 {
     if (o.want_u) {
-        const double coul = acc.C + acc.CN;
+        const double coul = acc.C + acc.CN + far_u;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             if (s < o.ns) {
@@ -235,7 +239,7 @@ __device__ __forceinline__ void store_point(const OutParams &o, const GridParams
     if (ASYM) {
         if (o.want_c)
             for (int s = 0; s < o.ns; ++s)
-                store_val(o.c, o.f64, s * g.m + p, o.c_scale[s] * (acc.C + acc.SC));
+                store_val(o.c, o.f64, s * g.m + p, o.c_scale[s] * (acc.C + acc.SC + far_c));
         if (o.want_h)
             for (int s = 0; s < o.n_ionic; ++s)
                 store_val(o.h, o.f64, s * g.m + p, o.h_scale[s] * (2.0 * acc.Y + acc.SH));

@@ -18,15 +18,17 @@ def _api():
     return api
 
 
-def _run(wl, p, theta, batch, cut, method="treecode_taylor", out_dtype="f32"):
+def _run(wl, p, theta, batch, cut, method="treecode_taylor", out_dtype="f32", split=False,
+         want_h=True):
     api = _api()
     xyz, q, s, e = api.solute_to_device(wl.solute)
     opts = api.Opts(method=method, out_dtype=out_dtype, lj_cutoff=cut, theta=theta, degree=p,
-                    batch_edge=batch, leaf_size=16)
+                    batch_edge=batch, leaf_size=16, taylor_split=split)
     out = api.initialize(xyz, q, s, e, api.sites_from(wl.sites), api.grid_from(wl.grid), opts,
-                         ETA, KAPPA, BETA, DIEL)
+                         ETA, KAPPA, BETA, DIEL, want_h=want_h)
     torch.cuda.synchronize()
-    return [x.double().cpu().numpy().reshape(x.shape[0], -1) for x in out]
+    return [None if x is None else x.double().cpu().numpy().reshape(x.shape[0], -1)
+            for x in out]
 
 
 def _flat_ijk(g):
@@ -40,20 +42,35 @@ def _rel(x, r):
     return float(np.linalg.norm(x[ok] - r[ok]) / np.linalg.norm(r[ok]))
 
 
-@pytest.mark.parametrize("p,theta,batch", [(2, 0.6, 4), (3, 0.5, 8), (5, 0.7, 4)])
-def test_taylor_treecode_matches_oracle_every_point(oracle, p, theta, batch):
-    """Every grid point of a ragged grid (partial blocks on every axis, atoms
-    beyond its faces): GPU and oracle Taylor treecodes agree to 1e-6 while
-    both differ from the exact sums by far more."""
+def _ragged():
     wl = W.tiny(n_atoms=45, dims=(29, 23, 19), seed=17, spacing=0.5)
     wl.solute.xyz *= 1.9
+    return wl
+
+
+def _oracle_taylor(oracle, wl, ijk, batch, theta, p, rc, variant, guard=None):
+    sol, st, g = wl.solute, wl.sites, wl.grid
+    args = (sol.xyz, sol.q, sol.sigma, sol.eps, st.q, st.sigma, st.eps, st.ionic, g.origin,
+            g.spacing, g.dims, ijk, KC, ETA, KAPPA, BETA, DIEL, batch, theta, p, rc)
+    if variant == "split":
+        return oracle.taylor_split_cp_points(*args)
+    return oracle.taylor_cp_points(*args, guard=guard)
+
+
+@pytest.mark.parametrize("variant", ["paper", "split"])
+@pytest.mark.parametrize("p,theta,batch", [(2, 0.6, 4), (3, 0.5, 8), (5, 0.7, 4)])
+def test_taylor_treecode_matches_oracle_every_point(oracle, variant, p, theta, batch):
+    """Every grid point of a ragged grid (partial blocks on every axis, atoms
+    beyond its faces): GPU and oracle Taylor treecodes agree to 1e-6 while
+    both differ from the exact sums by far more.  paper: expansions of 1/d,
+    erf(d/eta)/d and 2 exp(-kappa d)/d with the distance guard that h^lr
+    brings; split: 1/d and 2 exp(-kappa d)/d plus exact remainders."""
+    wl = _ragged()
     sol, st, g = wl.solute, wl.sites, wl.grid
     rc = oracle_rcut(oracle, wl, 6.0)
     ijk = _flat_ijk(g)
-    ref = oracle.taylor_cp_points(sol.xyz, sol.q, sol.sigma, sol.eps, st.q, st.sigma, st.eps,
-                                  st.ionic, g.origin, g.spacing, g.dims, ijk, KC, ETA, KAPPA,
-                                  BETA, DIEL, batch, theta, p, rc)
-    got = _run(wl, p, theta, batch, 6.0)
+    ref = _oracle_taylor(oracle, wl, ijk, batch, theta, p, rc, variant)
+    got = _run(wl, p, theta, batch, 6.0, split=variant == "split")
     pts = g.origin + ijk * g.spacing
     u_ex = oracle.potential_points(sol.xyz, sol.q, sol.sigma, sol.eps, st.q, st.sigma, st.eps,
                                    pts, KC, rc)
@@ -62,10 +79,36 @@ def test_taylor_treecode_matches_oracle_every_point(oracle, p, theta, batch):
     for name, x, r, ex in zip("uch", got, ref, (u_ex, c_ex, h_ex)):
         for k in range(x.shape[0]):
             err, tree_err = _rel(x[k], r[k]), _rel(r[k], ex[k])
-            print(f"p {p} {name}[{k}] gpu-vs-oracle {err:.2e}  taylor-vs-exact {tree_err:.2e}")
+            print(f"{variant} p {p} {name}[{k}] gpu-vs-oracle {err:.2e}  "
+                  f"taylor-vs-exact {tree_err:.2e}")
             assert err <= 1e-6
             if name != "u":   # u is dominated by the (exact) LJ near the atoms
                 assert tree_err > 50 * err
+
+
+@pytest.mark.parametrize("p,theta", [(2, 0.6), (5, 0.7), (3, 0.9)])
+def test_taylor_erf_far_field_matches_oracle_every_point(oracle, p, theta):
+    """c^lr alone (no h^lr, so no distance guard): atoms are accepted a few
+    angstroms from their cluster's targets, where the expansion of
+    erf(d/eta)/d (Sec. 2.4.1, the Gaussian auxiliary recurrence) differs from
+    that of 1/d.  GPU and oracle agree to 1e-6 on every point, while the
+    paper's and the split forms differ by far more."""
+    wl = _ragged()
+    g = wl.grid
+    rc = oracle_rcut(oracle, wl, 6.0)
+    ijk = _flat_ijk(g)
+    ref = _oracle_taylor(oracle, wl, ijk, 4, theta, p, rc, "paper", guard=0.0)
+    split = _oracle_taylor(oracle, wl, ijk, 4, theta, p, rc, "split")
+    got = _run(wl, p, theta, 4, 6.0, want_h=False)
+    assert got[2] is None
+    for name, x, r, sp in (("u", got[0], ref[0], split[0]), ("c", got[1], ref[1], split[1])):
+        for k in range(x.shape[0]):
+            err, diff = _rel(x[k], r[k]), _rel(sp[k], r[k])
+            print(f"p {p} theta {theta} {name}[{k}] gpu-vs-oracle {err:.2e}  "
+                  f"paper-vs-split {diff:.2e}")
+            assert err <= 1e-6
+            if name == "c":
+                assert diff > 50 * err
 
 
 def test_taylor_treecode_protein_2500():
@@ -91,11 +134,12 @@ def test_taylor_treecode_protein_2500():
             assert mism == 0 and err <= 1e-5
 
 
-def test_taylor_and_interpolation_share_the_near_field():
+@pytest.mark.parametrize("split", [False, True])
+def test_taylor_and_interpolation_share_the_near_field(split):
     """With a MAC no cluster meets, both cluster-particle variants reduce to
     the same direct and short-range sums: identical outputs."""
     wl = W.tiny(n_atoms=30, dims=(20, 18, 17), seed=3, spacing=0.5)
-    a = _run(wl, 4, 1e-3, 4, 6.0, method="treecode_taylor")
+    a = _run(wl, 4, 1e-3, 4, 6.0, method="treecode_taylor", split=split)
     b = _run(wl, 4, 1e-3, 4, 6.0, method="treecode_cp")
     for x, y in zip(a, b):
         np.testing.assert_array_equal(x, y)
