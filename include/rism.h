@@ -242,6 +242,28 @@ int rism_initialize(const rism_solute *solute, const rism_sites *sites,
                     void *u, double *lj_tail, void *c_lr, void *h_lr, void *stream);
 
 /*
+ * rism_initialize without any allocation, for callers that cannot allocate
+ * device or host memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): arguments and results as rism_initialize,
+ * for methods RISM_DIRECT_F64 and RISM_DIRECT_F32C (others:
+ * RISM_E_UNSUPPORTED).  Scratch (atom records, cut-off radii, the smeared-
+ * kernel table, flags) comes from a fixed 32 MiB device array that the
+ * library holds per GPU until the process ends; a call needing more
+ * (beyond about 116,000 atoms with 8 sites or 209,000 with 4 on the FP64
+ * path with lj_tail, 299,000 with 4 on the FP32 path) fails with
+ * RISM_E_INVALID before any work is enqueued.  Calls on one GPU
+ * share that array: calls that overlap on one GPU (several host threads or
+ * streams) race and must be serialised by the caller.  Phase events and
+ * statistics counters are not recorded.  The device-side input check and a
+ * requested lj_tail still synchronise the stream, through copies into
+ * caller or stack memory.
+ */
+int rism_initialize_noalloc(const rism_solute *solute, const rism_sites *sites,
+                            const rism_grid *grid, const rism_opts *opts,
+                            double eta, double kappa, double beta, double dielectric,
+                            void *u, double *lj_tail, void *c_lr, void *h_lr, void *stream);
+
+/*
  * Adjoint of rism_potential.  Given dL_du = dL/du_g(r) ([device],
  * [S][nz][ny][nx], out_dtype), returns ([device], FP64, each may be NULL)
  *   dL_dxyz[n][3], dL_dq[n], dL_deps[n], dL_dsigma[n]

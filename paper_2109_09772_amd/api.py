@@ -92,6 +92,8 @@ def lib():
         L.rism_asymptotics.argtypes = common + [d, d, d, d, vp, vp, vp]
         L.rism_initialize.argtypes = common + [d, d, d, d, vp, P(C.c_double), vp, vp, vp]
         L.rism_asymptotics_k.argtypes = common + [d, d, d, d, d, vp, vp, vp]
+        L.rism_initialize_noalloc.argtypes = common + [d, d, d, d, vp, P(C.c_double), vp, vp,
+                                                       vp]
         L.rism_potential_backward.argtypes = common + [vp, vp, vp, vp, vp, vp]
         L.rism_compare.argtypes = [vp, C.c_int32, vp, C.c_int64, d, P(C.c_double), vp]
         L.rism_last_stats.argtypes = [P(Stats)]
@@ -100,7 +102,7 @@ def lib():
         L.rism_phase_times.restype = C.c_int
         for f in ("rism_potential", "rism_asymptotics", "rism_initialize",
                   "rism_potential_backward", "rism_compare", "rism_last_stats",
-                  "rism_asymptotics_k"):
+                  "rism_asymptotics_k", "rism_initialize_noalloc"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -265,8 +267,11 @@ def asymptotics_k(xyz, q, sigma, eps, sites, grid, opts: Opts, eta, kappa, beta,
 
 
 def initialize(xyz, q, sigma, eps, sites, grid, opts: Opts, eta, kappa, beta, dielectric,
-               want_u=True, want_c=True, want_h=True, want_tail=False, outs=None):
-    """Fused u, c^lr, h^lr.  ``outs`` may supply preallocated (u, c, h)."""
+               want_u=True, want_c=True, want_h=True, want_tail=False, outs=None,
+               noalloc=False):
+    """Fused u, c^lr, h^lr.  ``outs`` may supply preallocated (u, c, h).
+    ``noalloc``: call rism_initialize_noalloc (direct methods; the library
+    allocates nothing, its scratch is a fixed device array)."""
     L = lib()
     so = make_solute(xyz, q, sigma, eps)
     oc = opts.to_c()
@@ -280,8 +285,9 @@ def initialize(xyz, q, sigma, eps, sites, grid, opts: Opts, eta, kappa, beta, di
     else:
         u, c, h = outs
     tail = (C.c_double * MAX_SITES)() if want_tail else None
-    _check(L.rism_initialize(C.byref(so), C.byref(sites), C.byref(grid), C.byref(oc), eta, kappa,
-                             beta, dielectric, _ptr(u), tail, _ptr(c), _ptr(h), _stream()))
+    fn = L.rism_initialize_noalloc if noalloc else L.rism_initialize
+    _check(fn(C.byref(so), C.byref(sites), C.byref(grid), C.byref(oc), eta, kappa, beta,
+              dielectric, _ptr(u), tail, _ptr(c), _ptr(h), _stream()))
     if want_tail:
         return u, c, h, np.array(tail[:sites.n])
     return u, c, h

@@ -1,6 +1,7 @@
 // C-ABI entry points of librism.so: argument validation, constant
 // preparation (Lorentz-Berthelot mixing, cut-offs, output scale factors),
 // scratch management and dispatch to the HIP kernels.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -89,6 +90,11 @@ Workspace::Workspace(int device, void *stream, uint64_t cap_bytes) : cap_(cap_by
     arena_ = it->second;
 }
 
+Workspace::Workspace(void *base, size_t bytes)
+    : fixed_(static_cast<char *>(base)), fixed_size_(bytes)
+{
+}
+
 Workspace::~Workspace() {}
 
 void *Workspace::alloc(size_t bytes)
@@ -96,6 +102,16 @@ void *Workspace::alloc(size_t bytes)
     if (status_ != RISM_OK) return nullptr;
     bytes = (bytes + 255) & ~size_t(255);
     if (bytes == 0) bytes = 256;
+    if (fixed_) {
+        if (off_ + bytes > fixed_size_) {
+            status_ = fail(RISM_E_NOMEM, "fixed scratch exhausted");
+            return nullptr;
+        }
+        void *p = fixed_ + off_;
+        off_ += bytes;
+        used_total_ = off_;
+        return p;
+    }
     used_total_ += bytes;
     if (cap_ && used_total_ > cap_) {
         status_ = fail(RISM_E_NOMEM, "workspace request exceeds max_workspace_bytes");
@@ -131,6 +147,15 @@ __global__ void k_fill_i32(int *p, int n, int v)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// Zeroes n 32-bit words (a kernel rather than hipMemsetAsync, so that the
+// call stays a plain kernel launch inside captured graphs).
+__global__ void k_zero_words(uint32_t *p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
 }
 
 // Pinned host staging for small device->host reads.
@@ -314,7 +339,10 @@ static int stage_atoms(const rism_solute *so, const Prep &p, const rism_opts *op
     if (rc) return rc;
     bool need_check = !(op->flags & RISM_FLAG_NO_DEVICE_CHECK) || op->lj_tol > 0 || check_eps;
     if (need_check && so->n > 0) {
-        int *h = pinned_flags();
+        // pinned staging (allocated once per thread), or the stack when the
+        // call may not allocate (a pageable copy, synchronous anyway here)
+        int local[4] = {0, 0, 0, 0};
+        int *h = ws.fixed() ? local : pinned_flags();
         if (!h) return fail(RISM_E_HIP, "pinned host buffer allocation failed");
         RISM_HIP(hipMemcpyAsync(h, a.err_flags, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
         RISM_HIP(hipStreamSynchronize(s));
@@ -339,13 +367,18 @@ static int stage_atoms(const rism_solute *so, const Prep &p, const rism_opts *op
 static int zero_grid(void *buf, int f64, int64_t count, hipStream_t s)
 {
     if (!buf || count == 0) return RISM_OK;
-    RISM_HIP(hipMemsetAsync(buf, 0, (size_t)count * (f64 ? 8 : 4), s));
+    const int64_t words = count * (f64 ? 2 : 1);
+    const int64_t blocks = std::min<int64_t>((words + kBlock - 1) / kBlock, 8192);
+    hipLaunchKernelGGL(k_zero_words, (int)blocks, kBlock, 0, s, static_cast<uint32_t *>(buf),
+                       words);
+    RISM_HIP(hipGetLastError());
     return RISM_OK;
 }
 
 static int forward(const rism_solute *so, const rism_sites *si, const rism_grid *gr,
                    const rism_opts *op, bool asym_call, double eta, double kappa, double beta,
-                   double diel, void *u, double *lj_tail, void *c, void *h, void *stream)
+                   double diel, void *u, double *lj_tail, void *c, void *h, void *stream,
+                   void *fixed_scratch = nullptr, size_t fixed_bytes = 0)
 {
     rism_stats st{};
     int rc = check_common(so, si, gr, op);
@@ -380,7 +413,8 @@ static int forward(const rism_solute *so, const rism_sites *si, const rism_grid 
     hipStream_t s = static_cast<hipStream_t>(stream);
     int dev = 0;
     RISM_HIP(hipGetDevice(&dev));
-    Workspace ws(dev, stream, op->max_workspace_bytes);
+    Workspace ws = fixed_scratch ? Workspace(fixed_scratch, fixed_bytes)
+                                 : Workspace(dev, stream, op->max_workspace_bytes);
 
     if (so->n == 0) {
         if ((rc = zero_grid(u, p.out.f64, p.sp.ns * p.g.m, s))) return rc;
@@ -466,11 +500,89 @@ static int forward(const rism_solute *so, const rism_sites *si, const rism_grid 
     return RISM_OK;
 }
 
+// ------------------------------------------------------- no-alloc scratch
+// Device scratch of rism_initialize_noalloc: a file-scope array that every
+// GPU the library runs on holds until the process ends.  In host code its
+// name is not a device address; the address is taken once per device with
+// hipGetSymbolAddress and only that address reaches kernels and copies.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void *> *g_scratch_ptr;
+
+// Address of this device's scratch array (the device must be current).
+static int noalloc_scratch(int dev, void **ptr)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr) g_scratch_ptr = new std::map<int, void *>();
+    auto it = g_scratch_ptr->find(dev);
+    if (it != g_scratch_ptr->end()) {
+        *ptr = it->second;
+        return RISM_OK;
+    }
+    void *p = nullptr;
+    RISM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(RISM_E_HIP, "hipGetSymbolAddress(scratch) returned a null address");
+    (*g_scratch_ptr)[dev] = p;
+    *ptr = p;
+    return RISM_OK;
+}
+
+// Scratch bytes forward() carves for a direct-sum call (the fixed-mode
+// workspace rounds every request up to 256 bytes).
+static size_t noalloc_need(const Prep &p, int64_t n, bool f64path, bool want_rcut, bool asym)
+{
+    auto r = [](size_t b) { return (b + 255) & ~size_t(255); };
+    size_t need = r(4 * sizeof(int));                                 // stage error flags
+    need += r(rec_bytes(p.sp.ns_pad, f64path) * (size_t)p.npad);      // atom records
+    if (want_rcut) need += r(sizeof(double) * p.sp.ns * (size_t)(n > 0 ? n : 1));
+    if (asym && !f64path) need += r(sizeof(float4) * 2 * kSmearIntervals);   // table
+    if (want_rcut) need += r(sizeof(double) * kMaxSites);             // tail constants
+    return need;
+}
+
 }  // namespace rism
 
 using namespace rism;
 
 extern "C" {
+
+int rism_initialize_noalloc(const rism_solute *so, const rism_sites *si, const rism_grid *gr,
+                            const rism_opts *op, double eta, double kappa, double beta,
+                            double diel, void *u, double *lj_tail, void *c, void *h,
+                            void *stream)
+{
+    int rc = check_common(so, si, gr, op);
+    if (rc) return rc;
+    if (op->method != RISM_DIRECT_F64 && op->method != RISM_DIRECT_F32C)
+        return fail(RISM_E_UNSUPPORTED,
+                    "rism_initialize_noalloc: only RISM_DIRECT_F64 and RISM_DIRECT_F32C");
+    Prep p;
+    prep_common(so, si, gr, op, p);
+    const bool f64path = op->method == RISM_DIRECT_F64;
+    const bool asym = c || (h && p.n_ionic > 0);
+    const bool want_rcut = lj_tail && p.lj_mode == LJ_CUT;
+    const size_t need = noalloc_need(p, so->n, f64path, want_rcut, asym);
+    if (need > kNoAllocScratchBytes) {
+        char msg[256];
+        std::snprintf(msg, sizeof msg,
+                      "rism_initialize_noalloc: %lld atoms with %d sites need %zu bytes of "
+                      "scratch, above its fixed %zu bytes",
+                      (long long)so->n, (int)si->n, need, kNoAllocScratchBytes);
+        return fail(RISM_E_INVALID, msg);
+    }
+    int dev = 0;
+    RISM_HIP(hipGetDevice(&dev));
+    void *base = nullptr;
+    if ((rc = noalloc_scratch(dev, &base))) return rc;
+    // phase events and the statistics counters would create events or
+    // buffers: not recorded by this entry point
+    rism_opts o = *op;
+    o.flags &= ~(RISM_FLAG_PHASE_EVENTS | RISM_FLAG_STATS);
+    return forward(so, si, gr, &o, true, eta, kappa, beta, diel, u, lj_tail, c, h, stream, base,
+                   kNoAllocScratchBytes);
+}
 
 void rism_default_opts(rism_opts *o)
 {

@@ -97,15 +97,21 @@ class Workspace {
 public:
     struct Arena;
     Workspace(int device, void *stream, uint64_t cap_bytes);
+    // Fixed mode: carves every request from [base, base + bytes) and never
+    // allocates; a request beyond it fails with RISM_E_NOMEM.
+    Workspace(void *base, size_t bytes);
     ~Workspace();
+    bool fixed() const { return fixed_ != nullptr; }
     // Returns nullptr (and sets the error) on failure.
     void *alloc(size_t bytes);
     template <class T> T *get(size_t count) { return static_cast<T *>(alloc(count * sizeof(T))); }
     uint64_t in_use() const { return used_total_; }
     int status() const { return status_; }
 private:
-    Arena *arena_;
-    uint64_t cap_;
+    Arena *arena_ = nullptr;
+    char *fixed_ = nullptr;
+    size_t fixed_size_ = 0;
+    uint64_t cap_ = 0;
     uint64_t used_total_ = 0;
     size_t chunk_ = 0, off_ = 0;
     int status_ = RISM_OK;
