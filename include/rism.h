@@ -283,20 +283,35 @@ int rism_potential_backward(const rism_solute *solute, const rism_sites *sites,
 
 /*
  * Error report of a computed grid against a reference (FP64) grid, both
- * [device] with n elements.  x has element type x_dtype.  Reduces, in FP64
- * and in a fixed order:
+ * [device] with n elements.  x has element type x_dtype.  mask: [device]
+ * n bytes or NULL; points whose byte is 0 are left out of every count (for
+ * instance rism_near_mask's points near atoms).  Reduces, in FP64 and in a
+ * fixed order, over the points the mask keeps:
  *   out[0] = sum (x - ref)^2 over points where both are finite and
- *            |ref| <= ref_cap (ref_cap <= 0: no cap)
+ *            |x|, |ref| <= ref_cap (ref_cap <= 0: no cap)
  *   out[1] = sum ref^2 over the same points
  *   out[2] = max |x - ref| over the same points
  *   out[3] = number of points excluded (non-finite on either side or over
  *            the cap)
  *   out[4] = number of excluded points where x and ref disagree in kind:
- *            one finite and below the cap, the other not
- * out: [host] double[5].  Synchronises the stream.
+ *            one finite and within the cap, the other not
+ *   out[5] = number of points compared (those of out[0])
+ * rel-L2 = sqrt(out[0] / out[1]).  out: [host] double[6].  Synchronises the
+ * stream.
  */
 int rism_compare(const void *x, int32_t x_dtype, const double *ref, int64_t n,
-                 double ref_cap, double *out, void *stream);
+                 double ref_cap, const uint8_t *mask, double *out, void *stream);
+
+/*
+ * Mask of the grid points away from the solute, for the error report:
+ * mask[p] = 1 when every atom is at least `radius` from grid point p
+ * (distances in FP64 from the absolute coordinates), else 0.  mask: [device]
+ * [nz][ny][nx] bytes, overwritten.  radius 1 A gives the report's
+ * {min_a d >= 1 A} region, which leaves out the LJ cores that dominate u's
+ * norm.  solute->q, sigma and eps are not read.
+ */
+int rism_near_mask(const rism_solute *solute, const rism_grid *grid, double radius,
+                   uint8_t *mask, void *stream);
 
 /* Counters of the calling thread's last successful call. */
 int rism_last_stats(rism_stats *stats);

@@ -64,6 +64,8 @@ def _load():
         lib.oracle_kcut.argtypes = [C.c_int, d, d, d, d, d, d, d, d]
         lib.oracle_kcut.restype = d
         lib.oracle_num_threads.restype = C.c_int
+        lib.oracle_set_num_threads.argtypes = [C.c_int]
+        lib.oracle_set_num_threads.restype = None
         lib.oracle_taylor_coeffs.argtypes = [C.c_int, _P, C.c_int, d, d, _P]
         lib.oracle_taylor_cp_points.argtypes = [i64, _P, _P, _P, _P, i32, _P, _P, _P, _PI, d,
                                                 _P, d, d, d, d, _P, _P, _PI, i32, d, i32, d,
@@ -88,6 +90,11 @@ def _ptr(a, t=_P):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the later oracle sums (n <= 0: every processor)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def _atoms(xyz, q, sigma, eps):

@@ -473,6 +473,16 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Threads of the later parallel sums (n <= 0: every processor). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------ Taylor-recurrence treecode */
 
 /*

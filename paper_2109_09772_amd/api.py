@@ -95,14 +95,15 @@ def lib():
         L.rism_initialize_noalloc.argtypes = common + [d, d, d, d, vp, P(C.c_double), vp, vp,
                                                        vp]
         L.rism_potential_backward.argtypes = common + [vp, vp, vp, vp, vp, vp]
-        L.rism_compare.argtypes = [vp, C.c_int32, vp, C.c_int64, d, P(C.c_double), vp]
+        L.rism_compare.argtypes = [vp, C.c_int32, vp, C.c_int64, d, vp, P(C.c_double), vp]
+        L.rism_near_mask.argtypes = [P(Solute), P(Grid), d, vp, vp]
         L.rism_last_stats.argtypes = [P(Stats)]
         L.rism_last_error.restype = C.c_char_p
         L.rism_phase_times.argtypes = [P(C.c_double), P(C.c_int64)]
         L.rism_phase_times.restype = C.c_int
         for f in ("rism_potential", "rism_asymptotics", "rism_initialize",
                   "rism_potential_backward", "rism_compare", "rism_last_stats",
-                  "rism_asymptotics_k", "rism_initialize_noalloc"):
+                  "rism_asymptotics_k", "rism_initialize_noalloc", "rism_near_mask"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -313,15 +314,29 @@ def potential_backward(xyz, q, sigma, eps, sites, grid, opts: Opts, dL_du, need=
     return dx, dq, de, ds
 
 
-def compare(x, ref, ref_cap=0.0):
-    """(sum sq err, sum sq ref, max abs err, excluded, kind mismatches)."""
+def compare(x, ref, ref_cap=0.0, mask=None):
+    """(sum sq err, sum sq ref, max abs err, excluded, kind mismatches,
+    compared) over the points where ``mask`` (uint8 device tensor, or None)
+    is nonzero."""
     if ref.dtype != torch.float64 or x.numel() != ref.numel():
         raise ValueError("ref must be float64 with as many elements as x")
-    out = (C.c_double * 5)()
+    if mask is not None and (mask.dtype != torch.uint8 or mask.numel() != x.numel()):
+        raise ValueError("mask must be uint8 with as many elements as x")
+    out = (C.c_double * 6)()
     dt = DTYPES["f64"] if x.dtype == torch.float64 else DTYPES["f32"]
     _check(lib().rism_compare(_ptr(x.contiguous()), dt, _ptr(ref.contiguous()), x.numel(),
-                              ref_cap, out, _stream()))
+                              ref_cap, _ptr(None if mask is None else mask.contiguous()), out,
+                              _stream()))
     return tuple(out)
+
+
+def near_mask(xyz, grid, radius=1.0):
+    """uint8 [nz][ny][nx] device tensor: 1 where every atom is >= radius away."""
+    z = torch.zeros(xyz.shape[0], dtype=torch.float64, device=xyz.device)
+    so = make_solute(xyz, z, z, z)
+    m = torch.empty(_grid_shape(grid), dtype=torch.uint8, device=xyz.device)
+    _check(lib().rism_near_mask(C.byref(so), C.byref(grid), float(radius), _ptr(m), _stream()))
+    return m
 
 
 def phase_times() -> dict:

@@ -6,6 +6,7 @@
 // write 64 contiguous bytes and its points stay within 8 A x 2 A, which keeps
 // the divergent short-range branch rare).  Every thread walks the whole atom
 // array; atom records are wave-uniform and arrive through scalar loads.
+#include <algorithm>
 #include <cmath>
 
 #include "pair.h"
@@ -404,14 +405,17 @@ int launch_direct_f32(const SiteParams &sp, const DirectArgs &a, hipStream_t s)
 // ------------------------------------------------------------- error report
 
 // Partial sums per workgroup (fixed order within the group); the host adds
-// the per-group partials in group order.
+// the per-group partials in group order.  Points whose mask byte is 0 are
+// left out entirely (mask may be null: every point).
 __global__ __launch_bounds__(kBlock) void k_compare(const void *x, int f64, const double *ref,
-                                                    int64_t n, double cap, double *part)
+                                                    const uint8_t *mask, int64_t n, double cap,
+                                                    double *part)
 {
-    __shared__ double r0[kBlock], r1[kBlock], r2[kBlock], r3[kBlock], r4[kBlock];
-    double se = 0.0, sr = 0.0, mx = 0.0, ex = 0.0, mism = 0.0;
+    __shared__ double r0[kBlock], r1[kBlock], r2[kBlock], r3[kBlock], r4[kBlock], r5[kBlock];
+    double se = 0.0, sr = 0.0, mx = 0.0, ex = 0.0, mism = 0.0, cnt = 0.0;
     int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += stride) {
+        if (mask && mask[i] == 0) continue;
         double v = f64 ? static_cast<const double *>(x)[i] : (double)static_cast<const float *>(x)[i];
         double r = ref[i];
         bool vr = isfinite(v) && (cap <= 0.0 || fabs(v) <= cap);
@@ -421,13 +425,14 @@ __global__ __launch_bounds__(kBlock) void k_compare(const void *x, int f64, cons
             se += d * d;
             sr += r * r;
             mx = fmax(mx, fabs(d));
+            cnt += 1.0;
         } else {
             ex += 1.0;
             if (vr != rr) mism += 1.0;
         }
     }
     int t = threadIdx.x;
-    r0[t] = se; r1[t] = sr; r2[t] = mx; r3[t] = ex; r4[t] = mism;
+    r0[t] = se; r1[t] = sr; r2[t] = mx; r3[t] = ex; r4[t] = mism; r5[t] = cnt;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if (t < w) {
@@ -436,22 +441,78 @@ __global__ __launch_bounds__(kBlock) void k_compare(const void *x, int f64, cons
             r2[t] = fmax(r2[t], r2[t + w]);
             r3[t] += r3[t + w];
             r4[t] += r4[t + w];
+            r5[t] += r5[t + w];
         }
         __syncthreads();
     }
     if (t == 0) {
-        part[5 * blockIdx.x + 0] = r0[0];
-        part[5 * blockIdx.x + 1] = r1[0];
-        part[5 * blockIdx.x + 2] = r2[0];
-        part[5 * blockIdx.x + 3] = r3[0];
-        part[5 * blockIdx.x + 4] = r4[0];
+        part[6 * blockIdx.x + 0] = r0[0];
+        part[6 * blockIdx.x + 1] = r1[0];
+        part[6 * blockIdx.x + 2] = r2[0];
+        part[6 * blockIdx.x + 3] = r3[0];
+        part[6 * blockIdx.x + 4] = r4[0];
+        part[6 * blockIdx.x + 5] = r5[0];
     }
 }
 
-int launch_compare(const void *x, int f64, const double *ref, int64_t n, double cap,
-                   double *partials, int nblocks, hipStream_t s)
+int launch_compare(const void *x, int f64, const double *ref, const uint8_t *mask, int64_t n,
+                   double cap, double *partials, int nblocks, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_compare, nblocks, kBlock, 0, s, x, f64, ref, n, cap, partials);
+    hipLaunchKernelGGL(k_compare, nblocks, kBlock, 0, s, x, f64, ref, mask, n, cap, partials);
+    RISM_HIP(hipGetLastError());
+    return RISM_OK;
+}
+
+// ------------------------------------------------------------ near-atom mask
+
+__global__ void k_fill_u8(uint8_t *p, int64_t n, uint8_t v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// One wave per atom: the grid points of the box around the atom that lie
+// closer than `radius` (FP64, absolute coordinates) get mask 0.  Several
+// atoms may clear one point; they all write 0.
+__global__ __launch_bounds__(64) void k_near_mask(const double *xyz, int64_t n, GridParams g,
+                                                  double radius, uint8_t *mask)
+{
+    const int64_t a = blockIdx.x;
+    if (a >= n) return;
+    const double y[3] = {xyz[3 * a], xyz[3 * a + 1], xyz[3 * a + 2]};
+    const int nd[3] = {g.nx, g.ny, g.nz};
+    int lo[3], cnt[3];
+    for (int k = 0; k < 3; ++k) {
+        // candidate indices, one spacing of slack on each side
+        double l = floor((y[k] - radius - g.o[k]) / g.h[k]) - 1.0;
+        double h = ceil((y[k] + radius - g.o[k]) / g.h[k]) + 1.0;
+        l = fmax(l, 0.0);
+        h = fmin(h, (double)(nd[k] - 1));
+        lo[k] = (int)l;
+        cnt[k] = h >= l ? (int)(h - l) + 1 : 0;
+    }
+    const int64_t tot = (int64_t)cnt[0] * cnt[1] * cnt[2];
+    for (int64_t t = threadIdx.x; t < tot; t += 64) {
+        const int i = lo[0] + (int)(t % cnt[0]);
+        const int j = lo[1] + (int)((t / cnt[0]) % cnt[1]);
+        const int k = lo[2] + (int)(t / ((int64_t)cnt[0] * cnt[1]));
+        const double dx = g.o[0] + i * g.h[0] - y[0];
+        const double dy = g.o[1] + j * g.h[1] - y[1];
+        const double dz = g.o[2] + k * g.h[2] - y[2];
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        if (sqrt(d2) < radius) mask[((int64_t)k * g.ny + j) * g.nx + i] = 0;
+    }
+}
+
+int launch_near_mask(const double *xyz, int64_t n, const GridParams &g, double radius,
+                     uint8_t *mask, hipStream_t s)
+{
+    const int64_t blocks = std::min<int64_t>((g.m + kBlock - 1) / kBlock, 16384);
+    hipLaunchKernelGGL(k_fill_u8, (int)std::max<int64_t>(blocks, 1), kBlock, 0, s, mask, g.m,
+                       (uint8_t)1);
+    if (n > 0 && radius > 0.0)
+        hipLaunchKernelGGL(k_near_mask, (unsigned)n, 64, 0, s, xyz, n, g, radius, mask);
     RISM_HIP(hipGetLastError());
     return RISM_OK;
 }

@@ -739,7 +739,7 @@ int rism_potential_backward(const rism_solute *so, const rism_sites *si, const r
 }
 
 int rism_compare(const void *x, int32_t x_dtype, const double *ref, int64_t n, double ref_cap,
-                 double *out, void *stream)
+                 const uint8_t *mask, double *out, void *stream)
 {
     if (!x || !ref || !out || n < 0) return fail(RISM_E_INVALID, "null argument or n < 0");
     if (x_dtype != RISM_F32 && x_dtype != RISM_F64) return fail(RISM_E_INVALID, "bad x_dtype");
@@ -748,24 +748,50 @@ int rism_compare(const void *x, int32_t x_dtype, const double *ref, int64_t n, d
     RISM_HIP(hipGetDevice(&dev));
     Workspace ws(dev, stream, 0);
     const int nb = 1024;
-    double *part = ws.get<double>(5 * nb);
+    double *part = ws.get<double>(6 * nb);
     if (!part) return ws.status();
-    int rc = launch_compare(x, x_dtype == RISM_F64, ref, n, ref_cap, part, nb, s);
+    int rc = launch_compare(x, x_dtype == RISM_F64, ref, mask, n, ref_cap, part, nb, s);
     if (rc) return rc;
-    std::vector<double> hpart(5 * nb);
+    std::vector<double> hpart(6 * nb);
     RISM_HIP(hipMemcpyAsync(hpart.data(), part, hpart.size() * sizeof(double),
                             hipMemcpyDeviceToHost, s));
     RISM_HIP(hipStreamSynchronize(s));
-    double r[5] = {0, 0, 0, 0, 0};
+    double r[6] = {0, 0, 0, 0, 0, 0};
     for (int b = 0; b < nb; ++b) {
-        r[0] += hpart[5 * b];
-        r[1] += hpart[5 * b + 1];
-        r[2] = std::max(r[2], hpart[5 * b + 2]);
-        r[3] += hpart[5 * b + 3];
-        r[4] += hpart[5 * b + 4];
+        r[0] += hpart[6 * b];
+        r[1] += hpart[6 * b + 1];
+        r[2] = std::max(r[2], hpart[6 * b + 2]);
+        r[3] += hpart[6 * b + 3];
+        r[4] += hpart[6 * b + 4];
+        r[5] += hpart[6 * b + 5];
     }
-    for (int k = 0; k < 5; ++k) out[k] = r[k];
+    for (int k = 0; k < 6; ++k) out[k] = r[k];
     return RISM_OK;
+}
+
+int rism_near_mask(const rism_solute *so, const rism_grid *gr, double radius, uint8_t *mask,
+                   void *stream)
+{
+    if (!so || !gr || !mask) return fail(RISM_E_INVALID, "null solute, grid or mask");
+    if (so->n < 0 || (so->n > 0 && !so->xyz)) return fail(RISM_E_INVALID, "bad solute");
+    if (so->n > (int64_t(1) << 31) - 64) return fail(RISM_E_INVALID, "too many atoms");
+    if (!std::isfinite(radius) || radius < 0) return fail(RISM_E_INVALID, "radius must be >= 0");
+    for (int a = 0; a < 3; ++a) {
+        if (gr->dims[a] <= 0) return fail(RISM_E_INVALID, "grid dims must be > 0");
+        if (!(gr->spacing[a] > 0) || !std::isfinite(gr->spacing[a]))
+            return fail(RISM_E_INVALID, "grid spacing must be finite and > 0");
+    }
+    if (!finite3(gr->origin)) return fail(RISM_E_INVALID, "grid origin must be finite");
+    GridParams g{};
+    for (int a = 0; a < 3; ++a) {
+        g.o[a] = gr->origin[a];
+        g.h[a] = gr->spacing[a];
+    }
+    g.nx = gr->dims[0];
+    g.ny = gr->dims[1];
+    g.nz = gr->dims[2];
+    g.m = (int64_t)g.nx * g.ny * g.nz;
+    return launch_near_mask(so->xyz, so->n, g, radius, mask, static_cast<hipStream_t>(stream));
 }
 
 int rism_phase_times(double *ms, int64_t *count)

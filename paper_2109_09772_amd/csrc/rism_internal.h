@@ -177,8 +177,11 @@ int launch_direct_f64(const SiteParams &sp, const DirectArgs &a, hipStream_t s);
 int launch_smear_table(const AsymParams &a, float4 *tab, hipStream_t s);
 int launch_direct_f32(const SiteParams &sp, const DirectArgs &a, hipStream_t s);
 
-int launch_compare(const void *x, int f64, const double *ref, int64_t n, double cap,
-                   double *partials, int nblocks, hipStream_t s);
+int launch_compare(const void *x, int f64, const double *ref, const uint8_t *mask, int64_t n,
+                   double cap, double *partials, int nblocks, hipStream_t s);
+// mask[p] = 1 where every atom is at least `radius` from grid point p, else 0.
+int launch_near_mask(const double *xyz, int64_t n, const GridParams &g, double radius,
+                     uint8_t *mask, hipStream_t s);
 
 // Tree forward (particle-cluster); defined in k_tree.hip.
 struct TreeCallArgs {

@@ -102,7 +102,12 @@ def test_null_structs_and_outputs():
                             None) == api.RISM_E_INVALID
     assert L.rism_asymptotics(C.byref(so), C.byref(si), C.byref(g), C.byref(o), 1.0, 0.1, 1.0,
                               78.0, None, None, None) == api.RISM_E_INVALID
-    assert L.rism_compare(None, 0, None, 5, 0.0, None, None) == api.RISM_E_INVALID
+    assert L.rism_compare(None, 0, None, 5, 0.0, None, None, None) == api.RISM_E_INVALID
+    assert L.rism_near_mask(C.byref(so), C.byref(g), 1.0, None, None) == api.RISM_E_INVALID
+    assert L.rism_near_mask(C.byref(so), C.byref(g), -1.0, C.c_void_p(16),
+                            None) == api.RISM_E_INVALID
+    assert L.rism_initialize_noalloc(None, C.byref(si), C.byref(g), C.byref(o), 1.0, 0.1, 1.0,
+                                     78.0, None, None, None, None, None) == api.RISM_E_INVALID
 
 
 def test_site_parameter_validation():

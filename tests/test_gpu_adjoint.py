@@ -88,6 +88,88 @@ def test_adjoint_protein_2500_sampled_atoms(oracle):
     assert _rel(ds[pick], rs) < 1e-5
 
 
+def test_fp64_adjoint_vs_central_differences_protein_2500():
+    """The 2,500-atom / 128^3 workload with its smooth upstream rho g(r): the
+    FP64 direct adjoint against central differences of the GPU FP64 direct
+    forward (no cut-off) on 20 seeded atoms, h = 1e-4 A with one Richardson
+    step (r^-12 at grid points a few tenths of an angstrom away makes the
+    plain difference's O(h^2) term visible).  Each atom is differenced alone
+    (a one-atom solute), so the other atoms' terms do not cancel in the
+    difference; L is linear in Q, so its difference is exact."""
+    from paper_2109_09772_amd import api
+    wl = W.protein_2500()
+    sol, st, g = wl.solute, wl.sites, wl.grid
+    w = W.smooth_upstream(g, st, seed=4)
+    wt = torch.as_tensor(w, device="cuda", dtype=torch.float64)
+    sites, grid = api.sites_from(st), api.grid_from(g)
+    o64 = api.Opts(method="direct_f64", out_dtype="f64", lj_cutoff=0.0)
+    xyz, q, s, e = api.solute_to_device(sol)
+    dx, dq, de, ds = (t.cpu().numpy() for t in
+                      api.potential_backward(xyz, q, s, e, sites, grid, o64, wt))
+    out = torch.empty((st.n,) + tuple(int(v) for v in g.dims[::-1]), dtype=torch.float64,
+                      device="cuda")
+
+    # the charge and LJ-parameter differences take the Coulomb-only (site
+    # eps 0) and LJ-only (site q 0) functionals: each is the part that
+    # depends on the parameter, without the other part's much larger values
+    # cancelling in the difference
+    coul = api.make_sites(st.q, st.sigma, np.zeros(st.n), st.ionic)
+    lj = api.make_sites(np.zeros(st.n), st.sigma, st.eps, st.ionic)
+
+    def L(x1, q1, s1, e1, sp=sites):
+        f = lambda a: torch.as_tensor(np.atleast_1d(a), dtype=torch.float64,
+                                      device="cuda").contiguous()
+        api.potential(f(x1).reshape(1, 3), f(q1), f(s1), f(e1), sp, grid, o64, out=out)
+        return float((out * wt).sum())
+
+    pick = np.random.default_rng(44).choice(sol.n, 20, replace=False)
+    h = 1e-4
+    fx, fq, fe, fs = [], [], [], []
+    for a in pick:
+        x0, q0, s0, e0 = sol.xyz[a].copy(), sol.q[a], sol.sigma[a], sol.eps[a]
+        row = []
+        for k in range(3):
+            def Lk(hh):
+                x1 = x0.copy()
+                x1[k] += hh
+                return L(x1, q0, s0, e0)
+            d1 = (Lk(h) - Lk(-h)) / (2 * h)
+            d2 = (Lk(h / 2) - Lk(-h / 2)) / h
+            row.append((4 * d2 - d1) / 3)
+        fx.append(row)
+        fq.append(L(x0, q0 + 0.5, s0, e0, coul) - L(x0, q0 - 0.5, s0, e0, coul))
+        he, hs = 1e-6 * e0, 1e-6 * s0
+        fe.append((L(x0, q0, s0, e0 + he, lj) - L(x0, q0, s0, e0 - he, lj)) / (2 * he))
+        fs.append((L(x0, q0, s0 + hs, e0, lj) - L(x0, q0, s0 - hs, e0, lj)) / (2 * hs))
+    for name, g_, fd in (("dxyz", dx[pick], np.array(fx)), ("dq", dq[pick], np.array(fq)),
+                         ("deps", de[pick], np.array(fe)), ("dsigma", ds[pick], np.array(fs))):
+        err = _rel(g_, fd)
+        print(f"{name} FP64 adjoint vs central differences {err:.2e}")
+        assert err < 1e-6, (name, err)
+
+
+def test_autograd_non_contiguous_inputs(oracle):
+    """Column views of a larger array as xyz (non-contiguous): forward and
+    backward both take contiguous copies."""
+    from paper_2109_09772_amd import api
+    wl, w = _grad_case(seed=5, n=20, dims=(16, 15, 14))
+    big = torch.as_tensor(np.concatenate([wl.solute.xyz, np.zeros((wl.solute.n, 2))], axis=1),
+                          dtype=torch.float64, device="cuda").requires_grad_(True)
+    xyz = big[:, :3]
+    assert not xyz.is_contiguous()
+    _, q, s, e = api.solute_to_device(wl.solute)
+    opts = api.Opts(method="direct_f64", out_dtype="f64", lj_cutoff=0.0)
+    u = api.RismPotential.apply(xyz, q, s, e, api.sites_from(wl.sites), api.grid_from(wl.grid),
+                                opts)
+    wt = torch.as_tensor(w, device="cuda", dtype=torch.float64)
+    (u * wt).sum().backward()
+    sol, st, g = wl.solute, wl.sites, wl.grid
+    rx, _, _, _ = oracle.backward_grid(sol.xyz, sol.q, sol.sigma, sol.eps, st.q, st.sigma,
+                                       st.eps, g.origin, g.spacing, g.dims, w, KC)
+    assert _rel(big.grad[:, :3].cpu().numpy(), rx) < 1e-11
+    assert float(big.grad[:, 3:].abs().max()) == 0.0
+
+
 # ------------------------------------------------------------------ tree adjoint
 
 def _tree_opts(method="treecode_cp", theta=0.6, degree=10, cut=6.0, batch=8):

@@ -5,8 +5,8 @@
   cluster-particle treecode (theta 0.6, degree 8, 9 A LJ cut-off) against the
   GPU FP64 direct sum on the full grid (<= 1e-6 per output grid).
 * 1.2 M atoms in a hollow cylinder, one 512x512x384 block of the grid: the
-  treecode forward against the oracle on 1,000 sampled points, and the
-  treecode adjoint against the oracle's FP64 gradient of 8 sampled atoms
+  treecode forward against the oracle on 10^4 sampled points, and the
+  treecode adjoint against the oracle's FP64 gradient of 20 sampled atoms
   (the oracle sums those atoms over the whole block).
 """
 import numpy as np
@@ -76,7 +76,7 @@ def test_tubulin_14000(oracle):
     print("stats", api.last_stats())
     for name, x, r in zip("uch", out, ref):
         for k in range(x.shape[0]):
-            se, sr, mx, excl, mism = api.compare(x[k], r[k], ref_cap=FP32_CAP)
+            se, sr, mx, excl, mism, _ = api.compare(x[k], r[k], ref_cap=FP32_CAP)
             err = (se / sr) ** 0.5
             print(f"treecode {name}[{k}] rel-L2 {err:.2e}")
             assert mism == 0 and err <= 1e-6
@@ -97,7 +97,7 @@ def test_cylinder_block_forward(oracle, cylinder):
                          ETA, KAPPA, BETA, DIEL)
     torch.cuda.synchronize()
     print("stats", api.last_stats())
-    pts, flat = _samples(wl.grid, 1000, 51)
+    pts, flat = _samples(wl.grid, 10_000, 51)
     for name, x, r in zip("uch", out, _oracle_points(oracle, wl, pts, 9.0)):
         xs = _sampled(x, flat)
         assert np.all(np.isfinite(xs))
@@ -121,7 +121,7 @@ def test_cylinder_block_adjoint(oracle, cylinder):
     torch.cuda.synchronize()
     del wt
     torch.cuda.empty_cache()
-    pick = np.random.default_rng(55).choice(sol.n, 8, replace=False)
+    pick = np.random.default_rng(55).choice(sol.n, 20, replace=False)
     rc = oracle.rcut_table(sol.sigma[pick], sol.eps[pick], st.sigma, st.eps, rcut=9.0)
     ref = oracle.backward_points(sol.xyz[pick], sol.q[pick], sol.sigma[pick], sol.eps[pick],
                                  st.q, st.sigma, st.eps,
