@@ -1317,10 +1317,10 @@ __device__ __forceinline__ void leaf_atoms(const AtomF32<NS> *rec, ConstAS<int> 
         __syncthreads();   // every wave is done with the previous chunk
         for (int t = threadIdx.x; t < m; t += NT) stg[t] = rec[il[c0 + t]];
         __syncthreads();
-        for (int s0 = 0; s0 < m; s0 += kAtomPad) {
+        for (int s0 = 0; s0 < m; s0 += 2 * kAtomPad) {
             PairAcc<NS> p;
             p.zero();
-            const int s1 = min(s0 + kAtomPad, m);
+            const int s1 = min(s0 + 2 * kAtomPad, m);
 #pragma unroll 1
             for (int s = s0; s < s1; ++s)
                 pair_eval<NS, LJM, ASYM, EXACT, FULL>(stg[s], gp, kc, tab, p, acc.hit);
@@ -1867,14 +1867,22 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
 
     // totals and flags read back at the end of a pass: [0..4] counts as in
     // CpCaps, [5] query stack overflow, [6] capacity check failed
-    uint32_t *hres = pinned_u32(8);
+    uint32_t *hres = pinned_u32(10);
     if (!hres) {
         set_error("treecode_cp: pinned host buffer allocation failed");
         return RISM_E_HIP;
     }
     auto read_back = [&]() -> int {
         RISM_HIP(hipMemcpyAsync(hres, flags, 7 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        if (a.stage_err)
+            RISM_HIP(hipMemcpyAsync(hres + 8, a.stage_err, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                                    s));
         RISM_HIP(hipStreamSynchronize(s));
+        if (a.stage_err && (hres[8] || hres[9])) {
+            set_error(hres[8] ? "non-finite atom input or negative sigma/eps"
+                              : "lj_tol must be below eps_ga of every pair");
+            return RISM_E_INVALID;
+        }
         if (hres[5]) {
             set_error("treecode_cp: neighbour query stack overflow");
             return RISM_E_UNSUPPORTED;

@@ -42,17 +42,17 @@ __device__ __forceinline__ ConstAS<T> *as_const(const T *p)
 }
 
 // Partial sums of one grid point over a block of sources.
-// C: Coulomb 1/d of the atoms beyond R_s (or of all atoms when the smeared
-// sums are off), CN: Coulomb 1/d within R_s, Y: e^{-kappa d}/d beyond R_s,
-// SC / SH: the smeared kernels themselves within R_s (or, for atoms whose far
-// field comes from proxies, their difference to 1/d and 2 e^{-kappa d}/d).
+// C: Coulomb 1/d of the directly summed atoms, Y: their e^{-kappa d}/d, SC /
+// SH: within R_s, the smeared kernels' differences erf(d/eta)/d - 1/d and
+// bracket/d - 2 e^{-kappa d}/d (of every atom within R_s, whether its far
+// form reaches the point directly or through the clusters).
 template <int NS>
 struct PairAcc {
-    float C, CN, Y, SC, SH;
+    float C, Y, SC, SH;
     float L[NS];
     __device__ __forceinline__ void zero()
     {
-        C = CN = Y = SC = SH = 0.f;
+        C = Y = SC = SH = 0.f;
 #pragma unroll
         for (int s = 0; s < NS; ++s) L[s] = 0.f;
     }
@@ -62,12 +62,12 @@ struct PairAcc {
 // sign across sources), LJ sums as TwoSum-compensated FP32 pairs.
 template <int NS>
 struct PointAcc {
-    double C, CN, Y, SC, SH;
+    double C, Y, SC, SH;
     float ls[NS], lc[NS];
     bool hit;
     __device__ __forceinline__ void zero()
     {
-        C = CN = Y = SC = SH = 0.0;
+        C = Y = SC = SH = 0.0;
         hit = false;
 #pragma unroll
         for (int s = 0; s < NS; ++s) { ls[s] = 0.f; lc[s] = 0.f; }
@@ -77,7 +77,6 @@ struct PointAcc {
     {
         C += (double)p.C;
         if (ASYM) {
-            CN += (double)p.CN;
             Y += (double)p.Y;
             SC += (double)p.SC;
             SH += (double)p.SH;
@@ -123,15 +122,13 @@ __device__ __forceinline__ void smear_eval(const float4 *tab, float tinv, float 
     gh = fmaf(fmaf(fmaf(h.w, t, h.z), t, h.y), t, h.x);
 }
 
-// One (point, atom) pair.  FULL: every term of the atom, with the smeared
-// sums split at R_s:
-//   d >= R_s:  erf(d/eta)/d -> 1/d (into C), bracket/d -> 2 e^{-kappa d}/d (into Y),
-//              exact to < 1e-12 relative there;
-//   d <  R_s:  1/d into CN (for u only) and the smeared kernels themselves
-//              from the table (into SC, SH), so nothing cancels near an atom.
+// One (point, atom) pair.  FULL: every term of the atom: 1/d (into C),
+// e^{-kappa d}/d (into Y) and, for d < R_s, the differences
+// erf(d/eta)/d - 1/d and bracket/d - 2 e^{-kappa d}/d from the table (into SC,
+// SH); beyond R_s those differences are < 1e-12 relative and dropped.  At a
+// coincident point (d = 0) only the smeared kernels' limits enter.
 // Not FULL (the atom's 1/d and e^{-kappa d}/d reach the point through
-// proxies): only LJ within the cut-off and, for d < R_s, the differences
-// erf(d/eta)/d - 1/d and bracket/d - 2 e^{-kappa d}/d.
+// proxies): only LJ within the cut-off and the differences within R_s.
 template <int NS, int LJM, bool ASYM, bool EXACT, bool FULL, class Rec>
 __device__ __forceinline__ void pair_eval(const Rec &at, const GridPt &g,
                                           const PairConst &k, const float4 *tab, PairAcc<NS> &p,
@@ -184,21 +181,20 @@ __device__ __forceinline__ void pair_eval(const Rec &at, const GridPt &g,
     const bool nearp = d2 < k.rs2;
     const float d = d2 * ri;
     const float e = __builtin_amdgcn_exp2f(k.yk * d);
+    // a FULL atom adds 1/d and e^{-kappa d}/d at every distance (a coincident
+    // point excepted: its terms are the d -> 0 limits of the smeared kernels
+    // alone), and within R_s the smeared kernels' differences to those far
+    // forms, as a short-range atom does
+    const float qe = FULL && d2 == 0.f ? 0.f : qr;
     if (FULL) {
-        p.C += nearp ? 0.f : qr;
-        p.CN += nearp ? qr : 0.f;
-        p.Y = fmaf(nearp ? 0.f : qr, e, p.Y);
+        p.C += qe;
+        p.Y = fmaf(qe, e, p.Y);
     }
     if (nearp) {
         float gc, gh;
         smear_eval(tab, k.tinv, d, gc, gh);
-        if (FULL) {
-            p.SC = fmaf(aq, gc, p.SC);
-            p.SH = fmaf(aq, gh, p.SH);
-        } else {
-            p.SC = fmaf(aq, gc, p.SC - qr);
-            p.SH = fmaf(aq, gh, fmaf(-qr, e + e, p.SH));
-        }
+        p.SC = fmaf(aq, gc, p.SC - qe);
+        p.SH = fmaf(aq, gh, fmaf(-qe, e + e, p.SH));
     }
 }
 
@@ -227,7 +223,7 @@ __device__ __forceinline__ void store_point(const OutParams &o, const GridParams
                                             double far_c = 0.0)
 {
     if (o.want_u) {
-        const double coul = acc.C + acc.CN + far_u;
+        const double coul = acc.C + far_u;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             if (s < o.ns) {

@@ -308,9 +308,15 @@ static size_t rec_bytes(int ns_pad, bool f64)
 // Stages the atoms into FP32 and/or FP64 records, optionally the cut-off
 // table, and checks the device-side error flags (one stream sync) unless the
 // caller opted out.
+// defer_err: when the checks need nothing back before later kernels run (no
+// per-pair cut-off radius from a tolerance, no eps check), skip the stream
+// sync here and hand the device flags ([0] non-finite input, [1] tolerance)
+// to the caller, which reads them with its own end-of-call read-back (the
+// kernels in between clamp every index they derive from atom data).
 static int stage_atoms(const rism_solute *so, const Prep &p, const rism_opts *op, bool want32,
                        bool want64, bool check_eps, Workspace &ws, void **rec32, void **rec64,
-                       double **rcut, hipStream_t s, double *max_rcut = nullptr)
+                       double **rcut, hipStream_t s, double *max_rcut = nullptr,
+                       const int **defer_err = nullptr)
 {
     StageArgs a{};
     a.xyz = so->xyz;
@@ -338,6 +344,11 @@ static int stage_atoms(const rism_solute *so, const Prep &p, const rism_opts *op
     }
     if (rc) return rc;
     bool need_check = !(op->flags & RISM_FLAG_NO_DEVICE_CHECK) || op->lj_tol > 0 || check_eps;
+    if (defer_err) *defer_err = nullptr;
+    if (need_check && defer_err && !(op->lj_tol > 0) && !check_eps && so->n > 0) {
+        *defer_err = a.err_flags;
+        need_check = false;
+    }
     if (need_check && so->n > 0) {
         // pinned staging (allocated once per thread), or the stack when the
         // call may not allocate (a pageable copy, synchronous anyway here)
@@ -431,8 +442,13 @@ static int forward(const rism_solute *so, const rism_sites *si, const rism_grid 
     double *rcut = nullptr;
     bool want_rcut = lj_tail && p.lj_mode == LJ_CUT;
     double max_rcut = op->lj_cutoff;
+    // the cluster-particle treecodes end with a read-back of their own: the
+    // input check joins it instead of synchronising here
+    const bool cp_method = (op->method == RISM_TREECODE_CP || op->method == RISM_TREECODE_TAYLOR) &&
+                           (u || c || h);
+    const int *stage_err = nullptr;
     rc = stage_atoms(so, p, op, !f64path, f64path, false, ws, &rec32, &rec64,
-                     want_rcut ? &rcut : nullptr, s, &max_rcut);
+                     want_rcut ? &rcut : nullptr, s, &max_rcut, cp_method ? &stage_err : nullptr);
     if (rc) return rc;
     if (asym_on && !f64path) {
         float4 *tab = ws.get<float4>(2 * kSmearIntervals);
@@ -478,6 +494,7 @@ static int forward(const rism_solute *so, const rism_sites *si, const rism_grid 
             // largest LJ cut-off radius (read back with the device checks,
             // which lj_tol > 0 always runs)
             ta.rmax_short = op->lj_tol > 0 ? max_rcut : op->lj_cutoff;
+            ta.stage_err = stage_err;
             rc = op->method == RISM_TREECODE ? tree_forward(ta, ws, st, s)
                                              : tree_forward_cp(ta, ws, st, s);
         }

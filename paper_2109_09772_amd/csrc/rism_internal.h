@@ -197,6 +197,8 @@ struct TreeCallArgs {
     const void *rec32;      // staged FP32 atom records (input order)
     int64_t npad;
     double rmax_short;      // short-range radius: max(LJ cut-off, R_s)
+    const int *stage_err;   // device flags of the input check still to read
+                            // ([0] non-finite input, [1] tolerance), or null
 };
 int tree_forward(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStream_t s);
 int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStream_t s);

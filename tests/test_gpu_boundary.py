@@ -162,3 +162,30 @@ def test_near_mask_matches_numpy(radius):
     exp = (dmin >= radius).astype(np.uint8)
     assert 0 < exp.sum() < exp.size
     np.testing.assert_array_equal(m, exp)
+
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("bad", ["nan_xyz", "inf_q", "neg_eps"])
+def test_invalid_atom_input_is_reported(method, bad):
+    """A non-finite coordinate or charge, or a negative eps, is caught by the
+    device-side input check: RISM_E_INVALID from every method (the
+    cluster-particle treecodes read the check with their end-of-call read-back),
+    and a later valid call on the same stream works."""
+    api = _api()
+    wl = _ragged()
+    sol, st, g = wl.solute, wl.sites, wl.grid
+    sites, grid = api.sites_from(st), api.grid_from(g)
+    xyz, q, s, e = api.solute_to_device(sol)
+    if bad == "nan_xyz":
+        xyz[7, 1] = float("nan")
+    elif bad == "inf_q":
+        q[3] = float("inf")
+    else:
+        e[11] = -0.01
+    with pytest.raises(api.RismError) as ei:
+        api.initialize(xyz, q, s, e, sites, grid, _opts(method), ETA, KAPPA, BETA, DIEL)
+    assert ei.value.code == api.RISM_E_INVALID
+    xyz, q, s, e = api.solute_to_device(sol)
+    u, c, h = api.initialize(xyz, q, s, e, sites, grid, _opts(method), ETA, KAPPA, BETA, DIEL)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(c).all()) and bool(torch.isfinite(h).all())
