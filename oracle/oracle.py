@@ -24,11 +24,15 @@ _P = C.POINTER(C.c_double)
 _PI = C.POINTER(C.c_int32)
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math).  sanitize:
+    instrument it with AddressSanitizer and UndefinedBehaviorSanitizer (load
+    the process with gcc's libasan preloaded to run it)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
+        san = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-g",
+               "-fno-sanitize-recover=undefined"] if sanitize else []
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", *san,
                                "-std=c99", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB

@@ -27,9 +27,21 @@ CFLAGS = [
 ]
 
 
+# RISM_HOST_SANITIZE=1: the host code (argument checks, drivers) built with
+# AddressSanitizer and UndefinedBehaviorSanitizer; device code is not
+# instrumented.  Run with clang's ASan runtime preloaded.
+HOST_SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def _sanitize() -> bool:
+    return os.environ.get("RISM_HOST_SANITIZE", "") == "1"
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-    cmd = ["hipcc", *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ["hipcc", *CFLAGS, *(HOST_SAN if _sanitize() else []), "-c", os.path.join(CSRC, src),
+           "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -41,7 +53,8 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}",
+           *(HOST_SAN if _sanitize() else []), *objs, "-o", tmp]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     if verbose:
