@@ -146,6 +146,9 @@ def parse():
     ap.add_argument("--frontier", action="store_true",
                     help="error/time frontier of the cluster-particle treecode over theta "
                          "{0.5, 0.7, 0.9} x degree {4, 8, 12} (workload default tubulin_14000)")
+    ap.add_argument("--thetas", default="0.5,0.7,0.9", help="frontier: theta values")
+    ap.add_argument("--degrees", default="4,8,12", help="frontier: degrees")
+    ap.add_argument("--batch-edges", default="8", help="frontier: target batch edges")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the run, copy a device buffer of this size (MiB) once: a "
                          "kernel of known traffic for scaling HBM byte counters")
@@ -241,7 +244,7 @@ def frontier(args, api, W):
     initialisation and the rel-L2 of every output grid against the GPU FP64
     direct sum with the same 9 A cut-off."""
     import torch
-    wl = getattr(W, args.workload if args.workload != "protein_2500" else "tubulin_14000")()
+    wl = getattr(W, args.workload if "--workload" in sys.argv else "tubulin_14000")()
     sol, st, g = wl.solute, wl.sites, wl.grid
     eta, kap, beta, diel = W.ETA, W.debye_kappa(), W.beta(), W.DIELECTRIC
     dev = torch.device("cuda:0")
@@ -261,27 +264,29 @@ def frontier(args, api, W):
     print(f"fp64 direct {t64:.3f} s", file=sys.stderr, flush=True)
     outs = tuple(torch.empty(r.shape, device=dev) for r in refs)
     rows = []
-    for th in (0.5, 0.7, 0.9):
-        for dg in (4, 8, 12):
-            o = api.Opts(method="treecode_cp", out_dtype="f32", lj_cutoff=args.lj_cutoff,
-                         theta=th, degree=dg)
-            for _ in range(2):
-                api.initialize(xyz, q, s, e, sites, grid, o, eta, kap, beta, diel, outs=outs)
-            torch.cuda.synchronize()
-            reps = 5
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                api.initialize(xyz, q, s, e, sites, grid, o, eta, kap, beta, diel, outs=outs)
-            torch.cuda.synchronize()
-            t = (time.perf_counter() - t0) / reps
-            errs = {name: grid_errors(api, x, r) for name, x, r in zip("uch", outs, refs)}
-            worst = max(max(v) for v in errs.values())
-            rows.append({"theta": th, "degree": dg, "init_time_s": t,
-                         "gpair_per_s": sol.n * g.npoints / t / 1e9,
-                         "rel_l2_vs_fp64_direct": errs, "worst": worst,
-                         "meets_1e-6": worst <= 1e-6})
-            print(f"theta {th} degree {dg}: {t * 1e3:.3f} ms, worst rel-L2 {worst:.2e}",
-                  file=sys.stderr, flush=True)
+    combos = [(th, dg, be) for be in (int(v) for v in args.batch_edges.split(","))
+              for th in (float(v) for v in args.thetas.split(","))
+              for dg in (int(v) for v in args.degrees.split(","))]
+    for th, dg, be in combos:
+        o = api.Opts(method="treecode_cp", out_dtype="f32", lj_cutoff=args.lj_cutoff,
+                     theta=th, degree=dg, batch_edge=be)
+        for _ in range(2):
+            api.initialize(xyz, q, s, e, sites, grid, o, eta, kap, beta, diel, outs=outs)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            api.initialize(xyz, q, s, e, sites, grid, o, eta, kap, beta, diel, outs=outs)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        errs = {name: grid_errors(api, x, r) for name, x, r in zip("uch", outs, refs)}
+        worst = max(max(v) for v in errs.values())
+        rows.append({"theta": th, "degree": dg, "batch_edge": be, "init_time_s": t,
+                     "gpair_per_s": sol.n * g.npoints / t / 1e9,
+                     "rel_l2_vs_fp64_direct": errs, "worst": worst,
+                     "meets_1e-6": worst <= 1e-6})
+        print(f"theta {th} degree {dg} batch {be}: {t * 1e3:.3f} ms, worst rel-L2 "
+              f"{worst:.2e}", file=sys.stderr, flush=True)
     ok = [r for r in rows if r["meets_1e-6"]]
     best = min(ok, key=lambda r: r["init_time_s"]) if ok else None
     print(json.dumps({"frontier": rows, "workload": wl.name, "atoms": sol.n,
@@ -289,6 +294,7 @@ def frontier(args, api, W):
                       "fp64_direct_s": t64,
                       "fastest_meeting_1e-6": None if best is None else
                       {"theta": best["theta"], "degree": best["degree"],
+                       "batch_edge": best["batch_edge"],
                        "init_time_s": best["init_time_s"], "worst": best["worst"]}}))
 
 
