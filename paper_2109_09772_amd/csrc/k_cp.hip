@@ -52,7 +52,19 @@ struct ScanBatch {
     uint32_t *a[5];
     uint32_t *total[5];
     int n[5], na;
+    // optional capacity check: a total above cap[k] (or a set *overflow)
+    // sets *bad, which starts at 0
+    uint32_t cap[5];
+    int *bad;
+    const int *overflow;
 };
+
+// The capacity check of array k's total.
+__device__ __forceinline__ void scan_check(const ScanBatch &b, int k, uint32_t tot)
+{
+    if (!b.bad) return;
+    if (tot > b.cap[k] || (k == 0 && *b.overflow)) atomicOr(b.bad, 1);
+}
 
 __device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t *red)
 {
@@ -101,7 +113,10 @@ __global__ __launch_bounds__(1024) void k_scan_sums(ScanBatch b, uint32_t *bsum,
         carry += sc[1023];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *b.total[blockIdx.x] = carry;
+    if (threadIdx.x == 0) {
+        *b.total[blockIdx.x] = carry;
+        scan_check(b, blockIdx.x, carry);
+    }
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(ScanBatch b, const uint32_t *bsum,
@@ -181,7 +196,10 @@ __global__ __launch_bounds__(kScanOneThreads) void k_scan_one(ScanBatch b)
         if (k < per && i < n) a[i] = o;
         o += v[k];
     }
-    if (threadIdx.x == 0) *b.total[blockIdx.x] = tot;
+    if (threadIdx.x == 0) {
+        *b.total[blockIdx.x] = tot;
+        scan_check(b, blockIdx.x, tot);
+    }
 }
 
 static int scan_batch(const ScanBatch &b, Workspace &ws, hipStream_t s)
@@ -213,6 +231,102 @@ static int scan_batch(const ScanBatch &b, Workspace &ws, hipStream_t s)
 //         (cp_sep_radius), or every leaf for the top cluster;
 //  mode 1 (level-0 blocks): leaves reaching the ball of the level-1 ancestor
 //         or the short range of the block.
+// ----------------------------------------------------------------- tables
+
+// One-axis tables of the target octree, formed once per call (they depend on
+// the grid, the batch edge and the degree only): the interpolation matrix
+// M[k][m] of every downward step, for each level lvl = 1..T-1, axis and
+// cluster index along that axis, and the level-1 basis at every grid
+// coordinate of each axis (rounded up to whole level-0 blocks).  One row of
+// n + 1 values per thread; the same arithmetic as forming them in place.
+struct CpTabArgs {
+    CpLevels L;
+    int degree, taylor;
+    int mrow0[kCpMaxLev + 1][3];   // first M row of (lvl, axis)
+    int nrow_m;                    // M rows in all
+    int lrow0[3], nrow_l;          // first level-1 basis row of each axis; rows in all
+    double *M, *Lg;
+    // optional: two words copied from err_src to err_dst (the input check's
+    // flags, gathered with the lists' counts for one read-back)
+    const int *err_src;
+    uint32_t *err_dst;
+};
+
+// Threads of the neighbour-query workgroups (one wave), which also form the
+// tables: the workgroups after the queries, one row per thread.
+constexpr int kQueryThreads = 64;
+inline int cp_table_blocks(const CpTabArgs &t)
+{
+    return (t.nrow_m + t.nrow_l + kQueryThreads - 1) / kQueryThreads;
+}
+
+inline void cp_tab_layout(const CpLevels &L, int n1, CpTabArgs &t)
+{
+    int r = 0;
+    for (int lvl = 1; lvl < L.T; ++lvl)
+        for (int ax = 0; ax < 3; ++ax) {
+            t.mrow0[lvl][ax] = r;
+            r += (ax == 0 ? L.cx[lvl] : (ax == 1 ? L.cy[lvl] : L.cz[lvl])) * n1;
+        }
+    t.nrow_m = r;
+    r = 0;
+    for (int ax = 0; ax < 3; ++ax) {
+        t.lrow0[ax] = r;
+        r += (ax == 0 ? L.cx[0] : (ax == 1 ? L.cy[0] : L.cz[0])) * L.B;
+    }
+    t.nrow_l = r;
+}
+
+// Row r of the tables; cosk holds cos(k pi / n), k = 0..n.
+__device__ __forceinline__ void cp_table_row(const CpTabArgs &a, int r, const double *cosk)
+{
+    const CpLevels &L = a.L;
+    const int n1 = a.degree + 1;
+    if (r < a.nrow_m) {
+        int lvl = 1, ax = 0;
+        for (int l = 1; l < L.T; ++l)
+            for (int x = 0; x < 3; ++x)
+                if (r >= a.mrow0[l][x]) {
+                    lvl = l;
+                    ax = x;
+                }
+        const int rel = r - a.mrow0[lvl][ax], I = rel / n1, k = rel % n1;
+        double *row = a.M + (size_t)r * n1;
+        if (a.taylor) {
+            // C(m, k) delta^(m - k), delta = child centre - parent centre
+            const double dl = cp_centre_axis(L, lvl, ax, I) - cp_centre_axis(L, lvl + 1, ax, I >> 1);
+            for (int m = 0; m < k; ++m) row[m] = 0.0;
+            double c = 1.0;
+            for (int m = k; m < n1; ++m) {
+                row[m] = c;
+                c = c * dl * (double)(m + 1) / (double)(m + 1 - k);
+            }
+        } else {
+            double clo, chi, plo, phi;
+            cp_proxy_axis(L, lvl, ax, I, clo, chi);
+            cp_proxy_axis(L, lvl + 1, ax, I >> 1, plo, phi);
+            lagrange_to_cos(clo + (chi - clo) * 0.5 * (1.0 + cosk[k]), plo, phi, a.degree, cosk,
+                            row, 1);
+        }
+    } else if (r < a.nrow_m + a.nrow_l) {
+        const int rl = r - a.nrow_m;
+        const int ax = rl >= a.lrow0[2] ? 2 : (rl >= a.lrow0[1] ? 1 : 0);
+        const int i = rl - a.lrow0[ax];   // grid coordinate along ax
+        const int I1 = (i / L.B) >> 1;     // level-1 cluster along ax
+        const double x = i * (ax == 0 ? L.h[0] : (ax == 1 ? L.h[1] : L.h[2]));
+        double *row = a.Lg + (size_t)rl * n1;
+        if (a.taylor) {   // (x - c)^k about the level-1 centre
+            const double dx = x - cp_centre_axis(L, 1, ax, I1);
+            double pw = 1.0;
+            for (int k = 0; k < n1; ++k, pw *= dx) row[k] = pw;
+        } else {          // L_k(x) of the level-1 proxy points
+            double lo, hi;
+            cp_proxy_axis(L, 1, ax, I1, lo, hi);
+            lagrange_to_cos(x, lo, hi, a.degree, cosk, row, 1);
+        }
+    }
+}
+
 struct CpQueryArgs {
     CpLevels L;
     int mode, nq;
@@ -223,7 +337,11 @@ struct CpQueryArgs {
     uint32_t *cnt, *items, *acnt;   // count pass (nq + 1 entries each; items, acnt optional)
     const uint32_t *off;            // fill pass
     int *list;
-    uint32_t *apre;                 // fill pass, optional: candidate atoms before each entry
+    // fill pass, clusters: the far work items (chunks of kCpChunkLeaves
+    // candidates) from each query's first item and first assigned-atom slot
+    const uint32_t *item_off, *atom_off;
+    int *it_cl, *it_c0, *it_c1;
+    uint32_t *it_slot;
     const int *bad;                 // fill pass: lists sized too small, write nothing
     int *overflow;
     int fill;
@@ -239,6 +357,8 @@ struct CpQueryArgs {
 // capacity bounds the stack as well: the launch sizes the LDS stack to the
 // smaller bound, which lets more queries share a CU.
 constexpr int kQStackW = 4608;
+// Trees of at most this many nodes are scanned flat instead of descended.
+constexpr int kQFlatNodes = 256;
 static_assert(kQStackW >= 448 * (kMortonBits - 1) + 512, "query stack bound");
 inline int cp_query_stack(int cap_nodes) { return cap_nodes < kQStackW ? cap_nodes : kQStackW; }
 
@@ -251,9 +371,10 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane)
     return v;
 }
 
-// One wave per query.  The DFS pops up to 64 nodes at a time (one per lane),
+// One wave per query.  Small trees are scanned flat, node by node; larger
+// ones descended: the DFS pops up to 64 nodes at a time (one per lane),
 // appends the hit leaves in lane order and pushes the children of the other
-// hits; the resulting candidate order is deterministic.
+// hits.  Either way the candidate order is deterministic.
 __device__ __forceinline__ void cp_query(const CpQueryArgs &a, int q, int *stk)
 {
     const int lane = threadIdx.x;
@@ -279,19 +400,19 @@ __device__ __forceinline__ void cp_query(const CpQueryArgs &a, int q, int *stk)
             br2 = rb * rb;
             has_ball = true;
         }
+    } else if (L.T == 0) {
+        all = true;   // one level-0 block
     } else {
-        const int I = q % L.cx[0], J = (q / L.cx[0]) % L.cy[0], K = q / (L.cx[0] * L.cy[0]);
-        if (L.T == 0) {
-            all = true;
-        } else {
-            double r;
-            cp_centre(L, 1, I >> 1, J >> 1, K >> 1, bc, r);
-            const double rb = cp_sep_radius(L, r);
-            br2 = rb * rb;
-            has_ball = true;
-        }
+        // the level-0 blocks of level-1 cluster q: atoms not well separated
+        // from it, and atoms within the short range of its box
+        const int I = q % L.cx[1], J = (q / L.cx[1]) % L.cy[1], K = q / (L.cx[1] * L.cy[1]);
+        double r;
+        cp_centre(L, 1, I, J, K, bc, r);
+        const double rb = cp_sep_radius(L, r);
+        br2 = rb * rb;
+        has_ball = true;
         if (a.rshort > 0) {
-            cp_box(L, 0, I, J, K, blo, bhi);
+            cp_box(L, 1, I, J, K, blo, bhi);
             has_box = true;
         }
     }
@@ -299,22 +420,67 @@ __device__ __forceinline__ void cp_query(const CpQueryArgs &a, int q, int *stk)
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint32_t o = a.fill ? a.off[q] : 0u;
     uint32_t n = 0, nat = 0;   // wave-uniform running counts of leaves and atoms
-    if (all) {
+    // appends this lane's leaf (lf) of sz atoms in lane order
+    auto append = [&](bool lf, int node, int sz) {
+        const uint64_t m = __ballot(lf);
+        if (!lf) sz = 0;
+        const int incl = wave_incl_scan(sz, lane);
+        if (lf && a.fill) {
+            const uint32_t li = n + (uint32_t)__popcll(m & lt);
+            a.list[o + li] = node;
+            if (a.it_cl && li % kCpChunkLeaves == 0) {
+                // item (cluster, first candidate, end candidate) and its slot
+                // range in the buffer of assigned atoms: the cluster's
+                // candidate atoms start at atom_off[q], items follow in
+                // order, each with room for all of its candidate atoms
+                const int it = (int)(a.item_off[q] + li / kCpChunkLeaves);
+                const uint32_t c0 = o + li;
+                a.it_cl[it] = q;
+                a.it_c0[it] = (int)c0;
+                a.it_c1[it] = (int)min(c0 + (uint32_t)kCpChunkLeaves, a.off[q + 1]);
+                a.it_slot[it] = a.atom_off[q] + nat + (uint32_t)(incl - sz);
+            }
+        }
+        n += (uint32_t)__popcll(m);
+        nat += (uint32_t)__shfl(incl, 63);
+    };
+    const int nn = *a.n_nodes;
+    if (nn <= kQFlatNodes) {
+        // small trees: every node tested directly, in node order, with all
+        // loads issued up front (a leaf that meets the query has every
+        // ancestor meeting it as well, so this is the set the descent finds)
+        constexpr int NCH = kQFlatNodes / 64;
+        double nb[NCH][6];
+        int nch[NCH], sz[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int node = c * 64 + lane;
+            nch[c] = -1;
+            sz[c] = 0;
+            if (node < nn) {
+                nch[c] = a.nchild[node];
+                sz[c] = a.end[node] - a.begin[node];
+                if (!all)
+                    for (int k = 0; k < 6; ++k) nb[c][k] = a.box[6 * node + k];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            if (c * 64 >= nn) break;   // wave-uniform
+            bool lf = nch[c] == 0;
+            if (lf && !all) {
+                bool hit = has_ball && gap2_point_box(bc, nb[c]) < br2;
+                if (!hit && has_box) hit = gap2_box_box(blo, bhi, nb[c]) < rs2;
+                lf = hit;
+            }
+            append(lf, c * 64 + lane, sz[c]);
+        }
+    } else if (all) {
         // every leaf, in node order
-        const int nn = *a.n_nodes;
         for (int i0 = 0; i0 < nn; i0 += 64) {
             const int node = i0 + lane;
             const bool lf = node < nn && a.nchild[node] == 0;
-            const uint64_t m = __ballot(lf);
-            const int sz = lf ? a.end[node] - a.begin[node] : 0;
-            const int incl = wave_incl_scan(sz, lane);
-            if (lf && a.fill) {
-                const uint32_t at = o + n + (uint32_t)__popcll(m & lt);
-                a.list[at] = node;
-                if (a.apre) a.apre[at] = nat + (uint32_t)(incl - sz);
-            }
-            n += (uint32_t)__popcll(m);
-            nat += (uint32_t)__shfl(incl, 63);
+            append(lf, node, lf ? a.end[node] - a.begin[node] : 0);
         }
     } else {
         int *st = stk;
@@ -333,16 +499,7 @@ __device__ __forceinline__ void cp_query(const CpQueryArgs &a, int q, int *stk)
             }
             const int nch = node >= 0 ? a.nchild[node] : 0;
             const bool lf = hit && nch == 0;
-            const uint64_t m = __ballot(lf);
-            const int sz = lf ? a.end[node] - a.begin[node] : 0;
-            const int isz = wave_incl_scan(sz, lane);
-            if (lf && a.fill) {
-                const uint32_t at = o + n + (uint32_t)__popcll(m & lt);
-                a.list[at] = node;
-                if (a.apre) a.apre[at] = nat + (uint32_t)(isz - sz);
-            }
-            n += (uint32_t)__popcll(m);
-            nat += (uint32_t)__shfl(isz, 63);
+            append(lf, node, lf ? a.end[node] - a.begin[node] : 0);
             const int nc = (hit && nch > 0) ? nch : 0;
             const int incl = wave_incl_scan(nc, lane);
             const int total = __shfl(incl, 63);
@@ -362,41 +519,79 @@ __device__ __forceinline__ void cp_query(const CpQueryArgs &a, int q, int *stk)
     }
 }
 
-// Both query sets in one launch: workgroups [0, a.nq) take a's queries, the
-// rest b's (b.nq may be 0).
-__global__ __launch_bounds__(64) void k_cp_query(CpQueryArgs a, CpQueryArgs b)
+// Both query sets in one launch: workgroups [0, a.nq) take a's queries,
+// the next b.nq b's (b.nq may be 0), and any further ones form the per-call
+// tables (cp_table_row, one row per thread).
+__global__ __launch_bounds__(kQueryThreads) void k_cp_query(CpQueryArgs a, CpQueryArgs b,
+                                                            CpTabArgs t)
 {
     extern __shared__ int stk[];   // [a.stack_w]
     const int q = blockIdx.x;
-    if (q < a.nq) cp_query(a, q, stk);
-    else cp_query(b, q - a.nq, stk);
+    if (q < a.nq) {
+        cp_query(a, q, stk);
+    } else if (q < a.nq + b.nq) {
+        cp_query(b, q - a.nq, stk);
+    } else {
+        __shared__ double cosk[kMaxDeg + 1];   // cos(k pi / n), shared by the rows
+        const int n1 = t.degree + 1;
+        if ((int)threadIdx.x < n1) cosk[threadIdx.x] = cos(kPi * threadIdx.x / t.degree);
+        __syncthreads();
+        const int r = (q - a.nq - b.nq) * kQueryThreads + (int)threadIdx.x;
+        if (r < t.nrow_m + t.nrow_l) cp_table_row(t, r, cosk);
+        if (t.err_src && r < 2) t.err_dst[r] = (uint32_t)t.err_src[r];
+    }
 }
 
-// Classification of every candidate atom of a level-0 block, once: direct
-// (assigned to no level >= 1: full pair), short-range only (within the
-// short range of the block), or skipped.  One workgroup per block, its
-// candidate atoms dealt 256 at a time to the threads in candidate order;
-// the two index lists keep that order.
+// Level-0 blocks are classified in groups: the (up to eight) blocks of one
+// level-1 cluster (the one block when the tree has no level 1).  The blocks
+// of a group share every ancestor, so an atom assigned to no level >= 1 is
+// direct for all of them: one direct list per group.  An atom assigned to
+// some level is short-range for each block of the group within whose short
+// range it lies: one short list per block.
+__host__ __device__ inline int cp_groups(const CpLevels &L)
+{
+    return L.T >= 1 ? L.cx[1] * L.cy[1] * L.cz[1] : 1;
+}
+
+// Group of level-0 block (I, J, K) and its place (0..7) in the group.
+__device__ __forceinline__ int cp_group_of(const CpLevels &L, int I, int J, int K, int &child)
+{
+    child = (I & 1) | ((J & 1) << 1) | ((K & 1) << 2);
+    return L.T >= 1 ? ((K >> 1) * L.cy[1] + (J >> 1)) * L.cx[1] + (I >> 1) : 0;
+}
+
+// Classification of every candidate atom of a group, once: direct, short-range
+// for some of its blocks, or skipped.  One workgroup per group, its candidate
+// atoms dealt 256 at a time to the threads in candidate order; every list
+// keeps that order.  The direct list of group g starts at aoff[g], the short
+// list of its block c at 8 aoff[g] + c (aoff[g + 1] - aoff[g]): each has room
+// for all of the group's candidate atoms.
 struct CpClassArgs {
     CpLevels L;
-    int nq;
+    int nq;                    // groups
     double rshort;
-    const uint32_t *cand_off;
+    const uint32_t *cand_off;  // candidate leaves of each group (prefix)
     const int *cand;
     const int *begin, *end;
     const float4 *rec;
     int stride_f4;
-    const uint32_t *aoff;      // first slot of each block's lists
+    const uint32_t *aoff;      // candidate atoms of each group (prefix)
     int *dlist, *slist;
-    uint32_t *nd, *ns;
+    uint32_t *nd;              // direct atoms per group
+    uint32_t *ns;              // short-range atoms per level-0 block
+    uint32_t *cost;            // per level-0 block: its direct and short-range atoms
     const int *bad;            // lists sized too small: write nothing
 };
 
-// Candidate leaves per LDS window of the classification (one per thread).
-constexpr int kClsWin = kBlock;
+// Threads of the classification, and candidate leaves per LDS window (one
+// per thread).
+constexpr int kClsThreads = 512;
+constexpr int kClsWin = kClsThreads;
+constexpr int kClsLists = 9;   // the direct list and eight short lists
 
-// Exclusive scan of v over the workgroup, in thread order, and the total.
-// `ws` holds kBlock / 64 ints; the call contains two barriers.
+// Exclusive scan of v over the workgroup of NT threads, in thread order, and
+// the total.  `ws` holds NT / 64 ints; the call contains two barriers.
+template <int NT>
 __device__ __forceinline__ int group_excl_scan(int v, int *ws, int &total)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -405,7 +600,7 @@ __device__ __forceinline__ int group_excl_scan(int v, int *ws, int &total)
     __syncthreads();
     int base = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
         const int x = ws[w];
         base += w < wave ? x : 0;
         tot += x;
@@ -415,29 +610,49 @@ __device__ __forceinline__ int group_excl_scan(int v, int *ws, int &total)
     return base + incl - v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cp_classify(CpClassArgs a)
+__global__ __launch_bounds__(kClsThreads) void k_cp_classify(CpClassArgs a)
 {
+    constexpr int NW = kClsThreads / 64;
     __shared__ int beg[kClsWin];
     __shared__ int pre[kClsWin + 1];
-    __shared__ int ws[2][kBlock / 64];
-    __shared__ CpMac mac[kCpMaxLev + 1];   // the block's ancestors, levels 1..T
-    const int q = blockIdx.x;
-    if (q >= a.nq || *a.bad) return;   // whole workgroup
+    __shared__ int ws[NW];
+    __shared__ uint32_t cnt[2][kClsLists][NW];
+    __shared__ CpMac mac[kCpMaxLev + 1];   // the group's ancestors, levels 1..T
+    __shared__ double cbox[8][6];          // its blocks' boxes (empty if absent)
+    __shared__ int cleaf[8];               // their ids (-1 if absent)
+    const int g = blockIdx.x;
+    if (g >= a.nq || *a.bad) return;   // whole workgroup
     const CpLevels &L = a.L;
-    const int I = q % L.cx[0], J = (q / L.cx[0]) % L.cy[0], K = q / (L.cx[0] * L.cy[0]);
-    if (threadIdx.x >= 1 && (int)threadIdx.x <= L.T) {
-        const int l = threadIdx.x;
-        cp_mac_terms(L, l, I >> l, J >> l, K >> l, mac[l]);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int I1 = 0, J1 = 0, K1 = 0;
+    if (L.T >= 1) {
+        I1 = g % L.cx[1];
+        J1 = (g / L.cx[1]) % L.cy[1];
+        K1 = g / (L.cx[1] * L.cy[1]);
+    }
+    if (tid >= 1 && tid <= L.T) {
+        const int sh = tid - 1;
+        cp_mac_terms(L, tid, I1 >> sh, J1 >> sh, K1 >> sh, mac[tid]);
+    }
+    if (tid < 8) {
+        const int I = 2 * I1 + (tid & 1), J = 2 * J1 + ((tid >> 1) & 1), K = 2 * K1 + (tid >> 2);
+        const bool in = (L.T >= 1 || tid == 0) && I < L.cx[0] && J < L.cy[0] && K < L.cz[0];
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        if (in) cp_box(L, 0, I, J, K, lo, hi);
+        for (int k = 0; k < 3; ++k) {
+            cbox[tid][k] = lo[k];
+            cbox[tid][3 + k] = hi[k];
+        }
+        cleaf[tid] = in ? (K * L.cy[0] + J) * L.cx[0] + I : -1;
     }
     __syncthreads();
-    double blo[3], bhi[3];
-    cp_box(L, 0, I, J, K, blo, bhi);
     const double rs2 = a.rshort * a.rshort;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    const uint32_t base = a.aoff[q];
-    uint32_t nd = 0, ns = 0;   // workgroup-uniform
-    const int c0 = (int)a.cand_off[q], c1 = (int)a.cand_off[q + 1];
+    const uint32_t base = a.aoff[g], na = a.aoff[g + 1] - base;
+    uint32_t nl[kClsLists];   // workgroup-uniform list lengths
+#pragma unroll
+    for (int l = 0; l < kClsLists; ++l) nl[l] = 0;
+    const int c0 = (int)a.cand_off[g], c1 = (int)a.cand_off[g + 1];
     for (int cw = c0; cw < c1; cw += kClsWin) {
         // window of candidate leaves: first atom and atom prefix, in list order
         const int nw = min(kClsWin, c1 - cw);
@@ -448,14 +663,15 @@ __global__ __launch_bounds__(kBlock) void k_cp_classify(CpClassArgs a)
             sz = a.end[leaf] - a.begin[leaf];
         }
         int run;
-        const int ex = group_excl_scan(sz, ws[0], run);
+        const int ex = group_excl_scan<kClsThreads>(sz, ws, run);
         if (tid < nw) pre[tid] = ex;
         if (tid == 0) pre[nw] = run;
         __syncthreads();
         // the window's atoms, one per thread per round
-        for (int t0 = 0, par = 0; t0 < run; t0 += kBlock, par ^= 1) {
+        for (int t0 = 0, par = 0; t0 < run; t0 += kClsThreads, par ^= 1) {
             const int t = t0 + tid;
-            int cls = 0, i = 0;
+            uint32_t cls = 0;   // bit 0: direct; bit 1 + c: short-range for block c
+            int i = 0;
             if (t < run) {
                 int lo = 0, hi = nw - 1;   // last k with pre[k] <= t
                 while (lo < hi) {
@@ -473,62 +689,82 @@ __global__ __launch_bounds__(kBlock) void k_cp_classify(CpClassArgs a)
                         break;
                     }
                 if (lvl == 0) {
-                    cls = 1;
+                    cls = 1u;
                 } else {
-                    double g2 = 0;
-                    for (int k = 0; k < 3; ++k) {
-                        const double gg = fmax(0.0, fmax(blo[k] - y[k], y[k] - bhi[k]));
-                        g2 += gg * gg;
-                    }
-                    cls = g2 < rs2 ? 2 : 0;
-                }
-            }
-            // ordered compaction over the workgroup: wave counts through LDS
-            // (two count buffers alternate, so one barrier per round suffices)
-            const uint64_t m1 = __ballot(cls == 1), m2 = __ballot(cls == 2);
-            int *cnt = ws[par];
-            if (lane == 0) cnt[wave] = (__popcll(m1) << 16) | __popcll(m2);
-            __syncthreads();
-            uint32_t o1 = 0, o2 = 0, t1 = 0, t2 = 0;
 #pragma unroll
-            for (int w = 0; w < kBlock / 64; ++w) {
-                const uint32_t c = (uint32_t)cnt[w];
-                if (w < wave) {
-                    o1 += c >> 16;
-                    o2 += c & 0xffffu;
+                    for (int c = 0; c < 8; ++c) {
+                        double g2 = 0;
+                        for (int k = 0; k < 3; ++k) {
+                            const double gg = fmax(0.0, fmax(cbox[c][k] - y[k], y[k] - cbox[c][3 + k]));
+                            g2 += gg * gg;
+                        }
+                        if (g2 < rs2) cls |= 2u << c;
+                    }
                 }
-                t1 += c >> 16;
-                t2 += c & 0xffffu;
             }
-            if (cls == 1) a.dlist[base + nd + o1 + __popcll(m1 & lt)] = i;
-            if (cls == 2) a.slist[base + ns + o2 + __popcll(m2 & lt)] = i;
-            nd += t1;
-            ns += t2;
+            // ordered compaction of every list over the workgroup: wave counts
+            // through LDS (two count buffers alternate, so one barrier per
+            // round suffices)
+            uint64_t m[kClsLists];
+#pragma unroll
+            for (int l = 0; l < kClsLists; ++l) {
+                m[l] = __ballot((cls >> l) & 1u);
+                if (lane == 0) cnt[par][l][wave] = (uint32_t)__popcll(m[l]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int l = 0; l < kClsLists; ++l) {
+                uint32_t o = 0, tot = 0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    const uint32_t c = cnt[par][l][w];
+                    o += w < wave ? c : 0u;
+                    tot += c;
+                }
+                if ((cls >> l) & 1u) {
+                    const uint32_t at = nl[l] + o + (uint32_t)__popcll(m[l] & lt);
+                    if (l == 0) a.dlist[base + at] = i;
+                    else a.slist[8 * (size_t)base + (size_t)(l - 1) * na + at] = i;
+                }
+                nl[l] += tot;
+            }
         }
         __syncthreads();   // the window is read before the next one is written
     }
-    if (tid == 0) {
-        a.nd[q] = nd;
-        a.ns[q] = ns;
+    if (tid == 0) a.nd[g] = nl[0];
+    if (tid < 8 && cleaf[tid] >= 0) {
+        uint32_t nsc = 0;
+#pragma unroll
+        for (int l = 1; l < kClsLists; ++l) nsc = l - 1 == tid ? nl[l] : nsc;
+        a.ns[cleaf[tid]] = nsc;
+        a.cost[cleaf[tid]] = nl[0] + nsc;
     }
 }
 
 // Launch orders: work items sorted by decreasing cost (c1 + c2, in
 // power-of-two classes), so that the heaviest items start first and the light
 // ones fill the end of the launch.  Results do not depend on the order.  One
-// workgroup.
+// workgroup per order (the leaves' and the far work items').
 constexpr int kCostClasses = 33;
 __device__ __forceinline__ int cost_class(uint32_t c)
 {
     return c == 0 ? 0 : 32 - __clz(c);
 }
-__global__ __launch_bounds__(1024) void k_order_by_cost(int n, const uint32_t *n_dev,
-                                                        const int *bad, const uint32_t *c1,
-                                                        const uint32_t *c2, int *order)
+struct OrderJob {
+    int n;                         // items (an upper bound if n_dev is set)
+    const uint32_t *n_dev;         // optional: item count on the device
+    const uint32_t *c1, *c2;       // costs (c2 optional)
+    int *order;
+};
+__global__ __launch_bounds__(1024) void k_order_by_cost(OrderJob j0, OrderJob j1, const int *bad)
 {
     __shared__ unsigned int cnt[kCostClasses];
     if (*bad) return;
-    if (n_dev) n = min(n, (int)*n_dev);
+    const OrderJob &j = blockIdx.x == 0 ? j0 : j1;
+    const uint32_t *c1 = j.c1, *c2 = j.c2;
+    int *order = j.order;
+    int n = j.n;
+    if (j.n_dev) n = min(n, (int)*j.n_dev);
     if (threadIdx.x < kCostClasses) cnt[threadIdx.x] = 0u;
     __syncthreads();
     for (int q = threadIdx.x; q < n; q += blockDim.x)
@@ -545,29 +781,6 @@ __global__ __launch_bounds__(1024) void k_order_by_cost(int n, const uint32_t *n
     __syncthreads();
     for (int q = threadIdx.x; q < n; q += blockDim.x)
         order[atomicAdd(&cnt[cost_class(c1[q] + (c2 ? c2[q] : 0u))], 1u)] = q;
-}
-
-// Work items of the far field: (cluster, first candidate, last candidate),
-// and the item's slot range in the buffer of assigned atoms: the cluster's
-// candidate atoms start at atom_off[cluster], items follow in order, each
-// with room for all of its candidate atoms.
-__global__ __launch_bounds__(kBlock) void k_cp_items(int nq, const uint32_t *cand_off,
-                                                     const uint32_t *item_off,
-                                                     const uint32_t *atom_off,
-                                                     const uint32_t *cand_apre, const int *bad,
-                                                     int *it_cl, int *it_c0, int *it_c1,
-                                                     uint32_t *it_slot)
-{
-    const int q = blockIdx.x * kBlock + threadIdx.x;
-    if (q >= nq || *bad) return;
-    const int c0 = (int)cand_off[q], c1 = (int)cand_off[q + 1];
-    int it = (int)item_off[q];
-    for (int c = c0; c < c1; c += kCpChunkLeaves, ++it) {
-        it_cl[it] = q;
-        it_c0[it] = c;
-        it_c1[it] = c + kCpChunkLeaves < c1 ? c + kCpChunkLeaves : c1;
-        it_slot[it] = atom_off[q] + cand_apre[c];
-    }
 }
 
 // ----------------------------------------------------------------- far
@@ -780,19 +993,29 @@ __global__ __launch_bounds__(kBlock) void k_cp_sweep(CpSweepArgs a)
 // per atom and shared by the NI proxies, and a pair costs a subtraction and
 // an FMA for its distance instead of three subtractions, a product and two
 // FMAs.  d2 = fma(dx, dx, fma(dy, dy, dz dz)) is the same expression in the
-// same order as in k_cp_sweep, so both kernels give identical sums.  G =
-// ceil(n1 / NI) threads share a line; threads beyond the n1^2 lines and
-// slots beyond n1 on a line compute on node 0 and store nothing.
+// same order as in k_cp_sweep.  G = ceil(n1 / NI) threads share a line;
+// threads beyond the n1^2 lines and slots beyond n1 on a line compute on
+// node 0 and store nothing.
+//
+// Work items differ in size by up to two orders of magnitude, and all of
+// them are resident at once, so the heaviest one sets the launch's length:
+// kSweepGroups groups of kBlock threads split an item's atoms into as many
+// contiguous ranges, each group sweeping its range over all proxies, and
+// their sums are added in group order at the end (the result does not
+// depend on the schedule).
+constexpr int kSweepGroups = 4;
+constexpr int kSweepThreads = kSweepGroups * kBlock;
+
 template <bool ASYM, int NI>
-__global__ __launch_bounds__(kBlock) void k_cp_sweep_lines(CpSweepArgs a)
+__global__ __launch_bounds__(kSweepThreads) void k_cp_sweep_lines(CpSweepArgs a)
 {
     __shared__ float node[3][kMaxDeg + 1];
-    __shared__ float4 stage[2][kBlock];
+    __shared__ float4 stage[kSweepGroups][2][kBlock];
+    __shared__ double red[kSweepGroups - 1][kBlock];
     if (*a.bad || (int)blockIdx.x >= (int)*a.n_items) return;   // whole workgroup
     const int item = as_const(a.order)[blockIdx.x];
     const int cl = as_const(a.it_cl)[item];
     const int n = (int)as_const(a.it_n)[item];
-    const float4 *at = a.abuf + as_const(a.it_slot)[item];
     const int n1 = a.degree + 1;
     if (threadIdx.x < 3 * n1) {
         int lvl, I, J, K;
@@ -805,8 +1028,15 @@ __global__ __launch_bounds__(kBlock) void k_cp_sweep_lines(CpSweepArgs a)
                               pick3(cc, ax));
     }
     __syncthreads();
+    // this thread's group, its atom range, and its place in the group
+    const int grp = (int)threadIdx.x / kBlock, tl = (int)threadIdx.x % kBlock;
+    const int b0 = (int)((long long)n * grp / kSweepGroups);
+    const int na = (int)((long long)n * (grp + 1) / kSweepGroups) - b0;
+    const float4 *at = a.abuf + as_const(a.it_slot)[item] + b0;
+    // chunks per group: the same count in every group (barriers inside)
+    const int nchunk = ((n + kSweepGroups - 1) / kSweepGroups + kBlock - 1) / kBlock;
     const int G = (n1 + NI - 1) / NI;
-    const int line = (int)threadIdx.x / G, i0 = ((int)threadIdx.x % G) * NI;
+    const int line = tl / G, i0 = (tl % G) * NI;
     const bool live = line < n1 * n1;
     const float py = node[1][live ? line % n1 : 0], pz = node[2][live ? line / n1 : 0];
     float px[NI];
@@ -816,15 +1046,16 @@ __global__ __launch_bounds__(kBlock) void k_cp_sweep_lines(CpSweepArgs a)
         px[r] = node[0][i0 + r < n1 ? i0 + r : 0];
         aC[r] = aY[r] = 0.0;
     }
-    float4 nxt = threadIdx.x < n ? at[threadIdx.x] : float4{0.f, 0.f, 0.f, 0.f};
-    for (int c0 = 0, buf = 0; c0 < n; c0 += kBlock, buf ^= 1) {
+    float4 nxt = tl < na ? at[tl] : float4{0.f, 0.f, 0.f, 0.f};
+    for (int ch = 0, buf = 0; ch < nchunk; ++ch, buf ^= 1) {
+        const int c0 = ch * kBlock;
         // buffer buf was last read two chunks ago, before the barrier that
         // every thread passed after it
-        stage[buf][threadIdx.x] = nxt;
+        stage[grp][buf][tl] = nxt;
         __syncthreads();
-        if (c0 + kBlock + (int)threadIdx.x < n) nxt = at[c0 + kBlock + threadIdx.x];
-        const float4 *st = stage[buf];
-        const int m = min(kBlock, n - c0);
+        if (c0 + kBlock + tl < na) nxt = at[c0 + kBlock + tl];
+        const float4 *st = stage[grp][buf];
+        const int m = max(0, min(kBlock, na - c0));
         for (int s0 = 0; s0 < m; s0 += 16) {
             float pC[NI], pY[NI];
 #pragma unroll
@@ -853,7 +1084,21 @@ __global__ __launch_bounds__(kBlock) void k_cp_sweep_lines(CpSweepArgs a)
             }
         }
     }
-    if (live) {
+    // the groups' sums, added in group order by group 0
+#pragma unroll
+    for (int r = 0; r < NI; ++r) {
+        __syncthreads();   // red is free
+        if (grp > 0) red[grp - 1][tl] = aC[r];
+        __syncthreads();
+        if (grp == 0)
+            for (int g = 0; g < kSweepGroups - 1; ++g) aC[r] += red[g][tl];
+        __syncthreads();
+        if (grp > 0) red[grp - 1][tl] = aY[r];
+        __syncthreads();
+        if (grp == 0)
+            for (int g = 0; g < kSweepGroups - 1; ++g) aY[r] += red[g][tl];
+    }
+    if (grp == 0 && live) {
 #pragma unroll
         for (int r = 0; r < NI; ++r) {
             if (i0 + r < n1) {
@@ -866,7 +1111,7 @@ __global__ __launch_bounds__(kBlock) void k_cp_sweep_lines(CpSweepArgs a)
 }
 
 // Proxies per thread of k_cp_sweep_lines for n1 nodes per axis: the fewest
-// that fit the n1^2 lines into one workgroup, if the lines then keep at
+// that fit the n1^2 lines into one group of kBlock threads, if the lines then keep at
 // least 90 % of its threads busy and that count is instantiated (n1 = 8, 9
 // and 11); otherwise 0 (k_cp_sweep).
 inline int sweep_line_ni(int n1)
@@ -883,9 +1128,9 @@ template <bool ASYM>
 void launch_sweep(int nitems, int np, int degree, const CpSweepArgs &sa, hipStream_t s)
 {
     switch (sweep_line_ni(degree + 1)) {
-    case 2: hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 2>), nitems, kBlock, 0, s, sa); return;
-    case 3: hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 3>), nitems, kBlock, 0, s, sa); return;
-    case 6: hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 6>), nitems, kBlock, 0, s, sa); return;
+    case 2: hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 2>), nitems, kSweepThreads, 0, s, sa); return;
+    case 3: hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 3>), nitems, kSweepThreads, 0, s, sa); return;
+    case 6: hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 6>), nitems, kSweepThreads, 0, s, sa); return;
     default: break;
     }
     const int nr = np <= 3 * kBlock ? (np + kBlock - 1) / kBlock : 4;
@@ -1053,122 +1298,25 @@ __global__ __launch_bounds__(kBlock) void k_cp_taylor(CpSweepArgs a)
     }
 }
 
-// V[cl] = sum of the partials of its items, in item order (nc components).
-__global__ __launch_bounds__(kBlock) void k_cp_reduce(int nclusters, int np, int nc,
-                                                      const uint32_t *item_off, const int *bad,
-                                                      const double *part, double *V)
-{
-    const int cl = blockIdx.x;
-    if (cl >= nclusters || *bad) return;
-    const int i0 = (int)item_off[cl], i1 = (int)item_off[cl + 1];
-    for (int k = threadIdx.x; k < nc * np; k += kBlock) {
-        double s = 0.0;
-        for (int it = i0; it < i1; ++it) s += part[(size_t)it * nc * np + k];
-        V[(size_t)cl * nc * np + k] = s;
-    }
-}
-
-// ----------------------------------------------------------------- tables
-
-// One-axis tables of the target octree, formed once per call (they depend on
-// the grid, the batch edge and the degree only): the interpolation matrix
-// M[k][m] of every downward step, for each level lvl = 1..T-1, axis and
-// cluster index along that axis, and the level-1 basis at every grid
-// coordinate of each axis (rounded up to whole level-0 blocks).  One row of
-// n + 1 values per thread; the same arithmetic as forming them in place.
-struct CpTabArgs {
-    CpLevels L;
-    int degree, taylor;
-    int mrow0[kCpMaxLev + 1][3];   // first M row of (lvl, axis)
-    int nrow_m;                    // M rows in all
-    int lrow0[3], nrow_l;          // first level-1 basis row of each axis; rows in all
-    double *M, *Lg;
-    int *zero;                     // set to 0 (a flag the later kernels start from)
-};
-
-inline void cp_tab_layout(const CpLevels &L, int n1, CpTabArgs &t)
-{
-    int r = 0;
-    for (int lvl = 1; lvl < L.T; ++lvl)
-        for (int ax = 0; ax < 3; ++ax) {
-            t.mrow0[lvl][ax] = r;
-            r += (ax == 0 ? L.cx[lvl] : (ax == 1 ? L.cy[lvl] : L.cz[lvl])) * n1;
-        }
-    t.nrow_m = r;
-    r = 0;
-    for (int ax = 0; ax < 3; ++ax) {
-        t.lrow0[ax] = r;
-        r += (ax == 0 ? L.cx[0] : (ax == 1 ? L.cy[0] : L.cz[0])) * L.B;
-    }
-    t.nrow_l = r;
-}
-
-__global__ __launch_bounds__(kBlock) void k_cp_tables(CpTabArgs a)
-{
-    __shared__ double cosk[kMaxDeg + 1];   // cos(k pi / n), shared by every row
-    const int r = blockIdx.x * kBlock + threadIdx.x;
-    const CpLevels &L = a.L;
-    const int n1 = a.degree + 1;
-    if ((int)threadIdx.x < n1) cosk[threadIdx.x] = cos(kPi * threadIdx.x / a.degree);
-    if (r == 0 && a.zero) *a.zero = 0;
-    __syncthreads();
-    if (r < a.nrow_m) {
-        int lvl = 1, ax = 0;
-        for (int l = 1; l < L.T; ++l)
-            for (int x = 0; x < 3; ++x)
-                if (r >= a.mrow0[l][x]) {
-                    lvl = l;
-                    ax = x;
-                }
-        const int rel = r - a.mrow0[lvl][ax], I = rel / n1, k = rel % n1;
-        double *row = a.M + (size_t)r * n1;
-        if (a.taylor) {
-            // C(m, k) delta^(m - k), delta = child centre - parent centre
-            const double dl = cp_centre_axis(L, lvl, ax, I) - cp_centre_axis(L, lvl + 1, ax, I >> 1);
-            for (int m = 0; m < k; ++m) row[m] = 0.0;
-            double c = 1.0;
-            for (int m = k; m < n1; ++m) {
-                row[m] = c;
-                c = c * dl * (double)(m + 1) / (double)(m + 1 - k);
-            }
-        } else {
-            double clo, chi, plo, phi;
-            cp_proxy_axis(L, lvl, ax, I, clo, chi);
-            cp_proxy_axis(L, lvl + 1, ax, I >> 1, plo, phi);
-            lagrange_to_cos(clo + (chi - clo) * 0.5 * (1.0 + cosk[k]), plo, phi, a.degree, cosk,
-                            row, 1);
-        }
-    } else if (r < a.nrow_m + a.nrow_l) {
-        const int rl = r - a.nrow_m;
-        const int ax = rl >= a.lrow0[2] ? 2 : (rl >= a.lrow0[1] ? 1 : 0);
-        const int i = rl - a.lrow0[ax];   // grid coordinate along ax
-        const int I1 = (i / L.B) >> 1;     // level-1 cluster along ax
-        const double x = i * (ax == 0 ? L.h[0] : (ax == 1 ? L.h[1] : L.h[2]));
-        double *row = a.Lg + (size_t)rl * n1;
-        if (a.taylor) {   // (x - c)^k about the level-1 centre
-            const double dx = x - cp_centre_axis(L, 1, ax, I1);
-            double pw = 1.0;
-            for (int k = 0; k < n1; ++k, pw *= dx) row[k] = pw;
-        } else {          // L_k(x) of the level-1 proxy points
-            double lo, hi;
-            cp_proxy_axis(L, 1, ax, I1, lo, hi);
-            lagrange_to_cos(x, lo, hi, a.degree, cosk, row, 1);
-        }
-    }
-}
-
 // ----------------------------------------------------------------- downward
 
-// Children at level lvl: V[child] += (Mx (x) My (x) Mz) V[parent], one
-// launch per level from the top down, so that the parent already holds its
-// own ancestors' far field.  M[k][m] = L^P_m(s^C_k): the parent's
-// interpolant evaluated at the child's proxy points, separably, in FP64.
-// Taylor moments (taylor != 0): M[k][m] = C(m, k) delta^(m - k) for m >= k,
-// delta = child centre - parent centre: the parent's polynomial re-expanded
-// about the child's centre, again separably.  The rows come from the
-// per-call tables (k_cp_tables).  One workgroup per child, nc components (1
-// or 2, as the LDS allows) per pass.
-constexpr int kDownThreads = 1024;
+// The far field of every level-1 cluster in one launch.  With P_l the sum
+// of the partials of cluster l's work items (in item order), the downward
+// pass is V_T = P_T and V_l = P_l + (Mx (x) My (x) Mz)_l V_{l+1} for
+// l = T-1 .. 1: the parent's far field carried onto the child's proxies.
+// M[k][m] = L^P_m(s^C_k), the parent's interpolant evaluated at the child's
+// proxy points, separably, in FP64; Taylor moments (taylor != 0) take
+// M[k][m] = C(m, k) delta^(m - k) for m >= k, delta = child centre - parent
+// centre: the parent's polynomial re-expanded about the child's centre, again
+// separably.  The rows come from the per-call tables (cp_table_row).
+//
+// One workgroup per level-1 cluster walks its chain of ancestors from the top
+// in LDS and writes V_1 only (the leaves read nothing else).  Each ancestor's
+// V is formed by every one of its level-1 descendants: a few redundant
+// contractions in place of one dependent launch per level.  nc of the ncomp
+// components per pass, as the LDS allows.
+constexpr int kDownThreads = 512;
+static_assert(3 * (kMaxDeg + 1) * (kMaxDeg + 1) <= 2 * kDownThreads, "two matrix entries per thread");
 
 inline size_t cp_down_lds(int degree, int nc)
 {
@@ -1188,54 +1336,162 @@ __device__ __forceinline__ double dot_lds(const double *row, const double *src, 
     return s;
 }
 
-__global__ __launch_bounds__(kDownThreads) void k_cp_down(CpLevels L, int lvl, int degree,
-                                                          int ncomp, int nc, const double *Mtab,
-                                                          int3 mrow0, double *V)
+struct CpDownArgs {
+    CpLevels L;
+    int degree;
+    int ncomp;                     // components per cluster in part and V
+    int nc;                        // components per pass
+    const double *M;               // rows of the per-call tables
+    int mrow0[kCpMaxLev + 1][3];   // first row of (lvl, axis)
+    const uint32_t *item_off;      // first work item of each cluster (clusters + 1)
+    const int *bad;                // buffers sized too small: do nothing
+    const double *part;            // [item][ncomp][np]
+    double *V;                     // [cluster][ncomp][np]; level-1 entries written
+};
+
+// Partials of one cluster's first few work items at this thread's S entries,
+// loaded ahead of the contractions that precede their sum (fewer items for
+// more entries, within the registers of two workgroups per CU).
+template <int S>
+struct DownPartials {
+    static constexpr int PF = S <= 2 ? 6 : (S == 4 ? 4 : (S == 8 ? 2 : 1));
+    double v[S][PF];
+    int i0, ni;   // the cluster's first item and item count (workgroup-uniform)
+};
+
+template <int S>
+__device__ __forceinline__ void down_fetch(const CpDownArgs &a, int cl, int e0, int ne, int stride,
+                                           DownPartials<S> &p)
+{
+    p.i0 = (int)a.item_off[cl];
+    p.ni = (int)a.item_off[cl + 1] - p.i0;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int e = threadIdx.x + j * kDownThreads;
+#pragma unroll
+        for (int k = 0; k < DownPartials<S>::PF; ++k)
+            p.v[j][k] = e < ne && k < p.ni ? a.part[(size_t)(p.i0 + k) * stride + e0 + e] : 0.0;
+    }
+}
+
+// Sum of the cluster's partials at entry e (slot j), in item order.
+template <int S>
+__device__ __forceinline__ double down_sum(const CpDownArgs &a, const DownPartials<S> &p, int j,
+                                           int e0, int e, int stride)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < DownPartials<S>::PF; ++k)
+        if (k < p.ni) s += p.v[j][k];
+    for (int it = DownPartials<S>::PF; it < p.ni; ++it)
+        s += a.part[(size_t)(p.i0 + it) * stride + e0 + e];
+    return s;
+}
+
+// Matrix entry t of the step to level lvl for the level-1 cluster (I1, J1,
+// K1): row of its level-lvl ancestor along axis t / n1^2 (per-call tables).
+__device__ __forceinline__ double down_mrow(const CpDownArgs &a, int lvl, int t, int I1, int J1,
+                                            int K1, int n1)
+{
+    if (lvl < 1 || t >= 3 * n1 * n1) return 0.0;
+    const int sh = lvl - 1, ax = t / (n1 * n1), km = t % (n1 * n1);
+    const int ix = ax == 0 ? I1 >> sh : (ax == 1 ? J1 >> sh : K1 >> sh);
+    return a.M[(size_t)(a.mrow0[lvl][ax] + ix * n1) * n1 + km];
+}
+
+// dot_lds with the number of terms fixed at compile time (N1 > 0) or not.
+template <int N1>
+__device__ __forceinline__ double dot_n(const double *row, const double *src, int stride, int n1)
+{
+    if (N1 == 0) return dot_lds(row, src, stride, n1);
+    double s = 0;
+#pragma unroll
+    for (int m = 0; m < N1; ++m) s += row[m] * src[m * stride];
+    return s;
+}
+
+// S: entry slots per thread, nc np <= S kDownThreads; N1: degree + 1 when
+// fixed at compile time, else 0.  The partials of each level are fetched
+// before the two contractions that precede their sum, and each step's
+// matrix rows one step ahead.
+template <int S, int N1>
+__global__ __launch_bounds__(kDownThreads) void k_cp_down_chain(CpDownArgs a)
 {
     extern __shared__ double sm[];
-    const int n1 = degree + 1, np = n1 * n1 * n1;
-    double *M = sm;                 // [3][n1][n1]
-    double *src = M + 3 * n1 * n1;  // [nc][np]
-    double *t1 = src + nc * np;     // [nc][np]
-    double *t2 = t1 + nc * np;      // [nc][np]
-    const int q = blockIdx.x;
-    const int I = q % L.cx[lvl], J = (q / L.cx[lvl]) % L.cy[lvl], K = q / (L.cx[lvl] * L.cy[lvl]);
-    const int id = cp_id(L, lvl, I, J, K);
-    const int pid = cp_id(L, lvl + 1, I >> 1, J >> 1, K >> 1);
-    // the step's three one-axis matrices, rows formed by k_cp_tables
-    for (int t = threadIdx.x; t < 3 * n1 * n1; t += kDownThreads) {
-        const int ax = t / (n1 * n1), km = t % (n1 * n1);
-        const int r0 = ax == 0 ? mrow0.x + I * n1 : (ax == 1 ? mrow0.y + J * n1 : mrow0.z + K * n1);
-        M[t] = Mtab[(size_t)r0 * n1 + km];
-    }
-    // ncomp components per cluster (V [cluster][ncomp][np]), up to nc per pass
-    for (int comp0 = 0; comp0 < ncomp; comp0 += nc) {
-        const int ne = min(nc, ncomp - comp0) * np;
-        if (comp0 > 0) __syncthreads();   // the previous pass is done with src
-        for (int e = threadIdx.x; e < ne; e += kDownThreads)
-            src[e] = V[((size_t)pid * ncomp + comp0) * np + e];
-        __syncthreads();   // M and src ready
-        // entry e = c np + k, k = (z, y, x) with x fastest; contract x, then y,
-        // then z
-        for (int e = threadIdx.x; e < ne; e += kDownThreads) {
-            const int c = e / np, k = e - c * np;
-            const int k1 = k % n1, rest = k / n1;
-            t1[e] = dot_lds(M + (0 * n1 + k1) * n1, src + c * np + rest * n1, 1, n1);
+    const CpLevels &L = a.L;
+    const int n1 = N1 > 0 ? N1 : a.degree + 1;
+    const int np = n1 * n1 * n1, stride = a.ncomp * np, nm = 3 * n1 * n1;
+    double *M = sm;                   // [3][n1][n1]
+    double *src = M + nm;             // [nc][np]: V of the current level
+    double *t1 = src + a.nc * np;     // [nc][np]
+    double *t2 = t1 + a.nc * np;      // [nc][np]
+    if (*a.bad) return;   // whole workgroup
+    const int q = blockIdx.x;   // level-1 cluster
+    const int I1 = q % L.cx[1], J1 = (q / L.cx[1]) % L.cy[1], K1 = q / (L.cx[1] * L.cy[1]);
+    const int tid = threadIdx.x;
+    for (int comp0 = 0; comp0 < a.ncomp; comp0 += a.nc) {
+        const int ne = min(a.nc, a.ncomp - comp0) * np, e0 = comp0 * np;
+        DownPartials<S> p;
+        {
+            const int sh = L.T - 1;
+            down_fetch<S>(a, cp_id(L, L.T, I1 >> sh, J1 >> sh, K1 >> sh), e0, ne, stride, p);
+        }
+        double mr0 = down_mrow(a, L.T - 1, tid, I1, J1, K1, n1);
+        double mr1 = down_mrow(a, L.T - 1, tid + kDownThreads, I1, J1, K1, n1);
+        __syncthreads();   // the previous pass is done with src
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int e = tid + j * kDownThreads;
+            if (e < ne) src[e] = down_sum<S>(a, p, j, e0, e, stride);
+        }
+        for (int lvl = L.T - 1; lvl >= 1; --lvl) {
+            const int sh = lvl - 1;
+            down_fetch<S>(a, cp_id(L, lvl, I1 >> sh, J1 >> sh, K1 >> sh), e0, ne, stride, p);
+            __syncthreads();   // src written; the previous step's z pass is done with M
+            if (tid < nm) M[tid] = mr0;
+            if (tid + kDownThreads < nm) M[tid + kDownThreads] = mr1;
+            mr0 = down_mrow(a, lvl - 1, tid, I1, J1, K1, n1);
+            mr1 = down_mrow(a, lvl - 1, tid + kDownThreads, I1, J1, K1, n1);
+            __syncthreads();
+            // entry e = c np + k, k = (z, y, x) with x fastest; contract x,
+            // then y, then z
+            for (int e = tid; e < ne; e += kDownThreads) {
+                const int c = e / np, k = e - c * np;
+                const int k1 = k % n1, rest = k / n1;
+                t1[e] = dot_n<N1>(M + (0 * n1 + k1) * n1, src + c * np + rest * n1, 1, n1);
+            }
+            __syncthreads();
+            for (int e = tid; e < ne; e += kDownThreads) {
+                const int c = e / np, k = e - c * np;
+                const int k1 = k % n1, k2 = (k / n1) % n1, m3 = k / (n1 * n1);
+                t2[e] = dot_n<N1>(M + (1 * n1 + k2) * n1, t1 + c * np + m3 * n1 * n1 + k1, n1, n1);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                const int e = tid + j * kDownThreads;
+                if (e < ne) {
+                    const int c = e / np, k = e - c * np;
+                    const int k12 = k % (n1 * n1), k3 = k / (n1 * n1);
+                    src[e] = down_sum<S>(a, p, j, e0, e, stride) +
+                             dot_n<N1>(M + (2 * n1 + k3) * n1, t2 + c * np + k12, n1 * n1, n1);
+                }
+            }
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < ne; e += kDownThreads) {
-            const int c = e / np, k = e - c * np;
-            const int k1 = k % n1, k2 = (k / n1) % n1, m3 = k / (n1 * n1);
-            t2[e] = dot_lds(M + (1 * n1 + k2) * n1, t1 + c * np + m3 * n1 * n1 + k1, n1, n1);
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < ne; e += kDownThreads) {
-            const int c = e / np, k = e - c * np;
-            const int k12 = k % (n1 * n1), k3 = k / (n1 * n1);
-            V[((size_t)id * ncomp + comp0) * np + e] +=
-                dot_lds(M + (2 * n1 + k3) * n1, t2 + c * np + k12, n1 * n1, n1);
-        }
+        const int id1 = cp_id(L, 1, I1, J1, K1);
+        for (int e = tid; e < ne; e += kDownThreads) a.V[(size_t)id1 * stride + e0 + e] = src[e];
     }
+}
+
+// Entry slots per thread of the downward kernel for nc components of degree
+// `degree`: 1, 2, 4, 8 or 16 (enough for every degree the LDS admits).
+inline int cp_down_slots(int degree, int nc)
+{
+    const int n1 = degree + 1, ne = nc * n1 * n1 * n1;
+    int sl = 1;
+    while (sl < 16 && sl * kDownThreads < ne) sl *= 2;
+    return sl;
 }
 
 // ----------------------------------------------------------------- leaves
@@ -1246,13 +1502,13 @@ struct CpLeafArgs {
     OutParams out;
     AsymParams asym;
     const void *rec;
-    const uint32_t *aoff;      // first slot of each block's index lists
-    const int *dlist, *slist;  // direct / short-range atoms per block
-    const uint32_t *nd, *ns;
+    const uint32_t *aoff;      // candidate atoms of each group (prefix; k_cp_classify)
+    const int *dlist, *slist;  // direct atoms per group / short-range atoms per block
+    const uint32_t *nd, *ns;   // their counts
     const int *order;          // block -> level-0 block, heaviest first
     const int *bad;            // lists sized too small: do nothing
     const double *V;           // proxy values (Taylor: moments) of level >= 1 clusters
-    const double *Lg;          // level-1 basis rows per grid coordinate (k_cp_tables)
+    const double *Lg;          // level-1 basis rows per grid coordinate (per-call tables)
     int lrow0[3];              // first row of each axis in Lg
     int degree, np;
     int taylor;                // basis: Lagrange (0) or monomials about the centre (1)
@@ -1300,7 +1556,7 @@ inline size_t cp_leaf_lds(int B, int degree, bool asym, bool paper, size_t rec_b
 }
 
 // The atoms of one index list against this thread's point, flushed every
-// kAtomPad atoms.  The workgroup copies the records to LDS kLeafStage at a
+// 2 kAtomPad atoms.  The workgroup copies the records to LDS kLeafStage at a
 // time (one per thread), and every pair reads its atom's fields from there
 // into vector registers: a vector instruction takes one scalar operand at
 // most, so with the fields in scalar registers each site's
@@ -1362,10 +1618,12 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
     const int i0 = I * B, j0 = J * B, k0 = K * B;
     const PairConst kc = make_pair_const(a.asym);
     const AtomF32<NS> *grec = static_cast<const AtomF32<NS> *>(a.rec);
-    const uint32_t base = as_const(a.aoff)[q];
+    int child;
+    const int grp = cp_group_of(L, I, J, K, child);
+    const uint32_t base = as_const(a.aoff)[grp], na = as_const(a.aoff)[grp + 1] - base;
     ConstAS<int> *dl = as_const(a.dlist + base);
-    ConstAS<int> *sl = as_const(a.slist + base);
-    const int ndir = (int)as_const(a.nd)[q], nsh = (int)as_const(a.ns)[q];
+    ConstAS<int> *sl = as_const(a.slist + 8 * (size_t)base + (size_t)child * na);
+    const int ndir = (int)as_const(a.nd)[grp], nsh = (int)as_const(a.ns)[q];
     if (ASYM)
         for (int i = threadIdx.x; i < 2 * kSmearIntervals; i += NT) tab[i] = a.asym.tab[i];
 
@@ -1516,14 +1774,6 @@ struct CpCaps {
     uint32_t c[5];
 };
 
-// bad = some total exceeds its capacity, or a neighbour query overflowed.
-__global__ void k_cp_check(const uint32_t *tot, CpCaps cap, const int *overflow, int *bad)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int b = *overflow != 0;
-    for (int k = 0; k < 5; ++k) b |= tot[k] > cap.c[k];
-    *bad = b;
-}
 
 // Capacities seen for a problem shape (device, atoms, blocks, clusters,
 // degree, theta, leaf size, short range): a later call of the same shape sizes
@@ -1567,6 +1817,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     }
     const int ncl = L.T >= 1 ? L.off[L.T + 1] : 0;
     const int nleaf = L.cx[0] * L.cy[0] * L.cz[0];
+    const int ngrp = cp_groups(L);   // groups of level-0 blocks (k_cp_classify)
     const bool taylor = a.opts->method == RISM_TREECODE_TAYLOR;
     // the paper's Taylor far fields (expansions of 1/d, erf(d/eta)/d and
     // 2 exp(-kappa d)/d), unless the exact-split variant is asked for
@@ -1579,8 +1830,19 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     // components per cluster in the proxy / moment arrays
     const int nc = paper && a.asym_on ? 3 : 2;
 
+    // [0..4] totals as in CpCaps, [5] query stack overflow, [6] capacity
+    // check failed, [8..9] the input check's flags: one block, read back with
+    // one copy; the tree build clears [0..6]
+    uint32_t *flags = ws.get<uint32_t>(10);
+    if (ws.status()) return ws.status();
+    uint32_t *tot = flags;
+    int *overflow = reinterpret_cast<int *>(flags + 5);
+    int *bad = reinterpret_cast<int *>(flags + 6);
+
     // source tree on the atoms (Morton sort, boxes) for the neighbour queries
     TreeDev t{};
+    t.clear = reinterpret_cast<int *>(flags);
+    t.n_clear = 7;
     int rc;
     {
         PhaseTimer pt(ev, RISM_PHASE_TREE_BUILD, s);
@@ -1597,14 +1859,8 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     // queries: clusters (mode 0) and leaves (mode 1), count pass
     uint32_t *ccnt = ws.get<uint32_t>(ncl + 1), *citems = ws.get<uint32_t>(ncl + 1);
     uint32_t *cacnt = ws.get<uint32_t>(ncl + 1);
-    uint32_t *lcnt = ws.get<uint32_t>(nleaf + 1), *lacnt = ws.get<uint32_t>(nleaf + 1);
-    // [0..4] totals as in CpCaps, [5] query stack overflow, [6] capacity
-    // check failed: one block, read back with one copy
-    uint32_t *flags = ws.get<uint32_t>(8);
+    uint32_t *lcnt = ws.get<uint32_t>(ngrp + 1), *lacnt = ws.get<uint32_t>(ngrp + 1);
     if (ws.status()) return ws.status();
-    uint32_t *tot = flags;
-    int *overflow = reinterpret_cast<int *>(flags + 5);
-    int *bad = reinterpret_cast<int *>(flags + 6);
     int dev = 0;
     RISM_HIP(hipGetDevice(&dev));
     CpQueryArgs qa{};
@@ -1619,20 +1875,34 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     qa.overflow = overflow;
     qa.stack_w = cp_query_stack(t.cap_nodes);
     const size_t qshm = (size_t)qa.stack_w * sizeof(int);
-    // the per-call tables; the same launch clears the query overflow flag
+    // the per-call tables, formed by the count pass's launch
     CpTabArgs ta{};
     ta.L = L;
     ta.degree = deg;
     ta.taylor = taylor;
     cp_tab_layout(L, n1, ta);
+    ta.err_src = a.stage_err;
+    ta.err_dst = flags + 8;
     ta.M = ws.get<double>((size_t)(ta.nrow_m + 1) * n1);
     ta.Lg = ws.get<double>((size_t)ta.nrow_l * n1);
-    ta.zero = overflow;
     if (ws.status()) return ws.status();
-    hipLaunchKernelGGL(k_cp_tables, (ta.nrow_m + ta.nrow_l + kBlock - 1) / kBlock, kBlock, 0, s,
-                       ta);
+    // list capacities of an earlier call of the same shape: the scans check
+    // the counts against them, and the lists are filled speculatively
+    const CpShape shape{dev,   a.opts->leaf_size, deg,    a.solute->n, nleaf,
+                        ncl,   a.opts->theta,     rshort, L.guard};
+    CpCaps cached{};
+    bool have = false;
     {
-        // count pass of both query sets in one launch, then all five scans
+        std::lock_guard<std::mutex> lk(g_cp_caps_mu);
+        auto it = g_cp_caps.find(shape);
+        if (it != g_cp_caps.end()) {
+            cached = it->second;
+            have = true;
+        }
+    }
+    {
+        // count pass of both query sets (and the tables) in one launch, then
+        // all five scans
         PhaseTimer pt(ev, RISM_PHASE_LISTS, s);
         CpQueryArgs qc = qa;   // clusters (none when ncl = 0)
         qc.mode = 0;
@@ -1641,32 +1911,36 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         qc.items = citems;
         qc.acnt = cacnt;
         qc.fill = 0;
-        CpQueryArgs ql = qa;   // level-0 blocks
+        CpQueryArgs ql = qa;   // groups of level-0 blocks
         ql.mode = 1;
-        ql.nq = nleaf;
+        ql.nq = ngrp;
         ql.cnt = lcnt;
         ql.items = nullptr;
         ql.acnt = lacnt;
         ql.fill = 0;
-        hipLaunchKernelGGL(k_cp_query, ncl + nleaf, 64, qshm, s, qc, ql);
+        hipLaunchKernelGGL(k_cp_query, ncl + ngrp + cp_table_blocks(ta), kQueryThreads, qshm, s,
+                           qc, ql, ta);
         ScanBatch sb{};
         int na = 0;
-        auto add = [&](uint32_t *arr, uint32_t *total, int n) {
+        auto add = [&](uint32_t *arr, int k, int n) {
             sb.a[na] = arr;
-            sb.total[na] = total;
+            sb.total[na] = tot + k;
             sb.n[na] = n;
+            sb.cap[na] = cached.c[k];
             ++na;
         };
-        if (ncl > 0) {
-            add(ccnt, tot + 0, ncl + 1);
-            add(citems, tot + 1, ncl + 1);
-            add(cacnt, tot + 4, ncl + 1);
-        } else {
-            hipLaunchKernelGGL(k_fill_int, 1, 64, 0, s, reinterpret_cast<int *>(tot), 5, 0);
+        if (ncl > 0) {   // (otherwise their totals stay 0)
+            add(ccnt, 0, ncl + 1);
+            add(citems, 1, ncl + 1);
+            add(cacnt, 4, ncl + 1);
         }
-        add(lcnt, tot + 2, nleaf + 1);
-        add(lacnt, tot + 3, nleaf + 1);
+        add(lcnt, 2, ngrp + 1);
+        add(lacnt, 3, ngrp + 1);
         sb.na = na;
+        if (have) {
+            sb.bad = bad;
+            sb.overflow = overflow;
+        }
         if ((rc = scan_batch(sb, ws, s))) return rc;
     }
     RISM_HIP(hipGetLastError());
@@ -1682,10 +1956,13 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         set_error("treecode_cp: degree / batch edge too large for the LDS of this device");
         return RISM_E_UNSUPPORTED;
     }
-    const int down_nc = cp_down_lds(deg, 2) <= (size_t)lds_max ? 2 : 1;
+    // components per pass of the downward kernel: all of them if the LDS allows
+    int down_nc = nc;
+    while (down_nc > 1 && cp_down_lds(deg, down_nc) > (size_t)lds_max) --down_nc;
     const bool want_stats = a.opts->flags & RISM_FLAG_STATS;
     unsigned long long *work = want_stats ? ws.get<unsigned long long>(4) : nullptr;
-    uint32_t *nd = ws.get<uint32_t>(nleaf), *nsh = ws.get<uint32_t>(nleaf);
+    uint32_t *nd = ws.get<uint32_t>(ngrp), *nsh = ws.get<uint32_t>(nleaf);
+    uint32_t *cost = ws.get<uint32_t>(nleaf);
     int *order = ws.get<int>(nleaf);
     double *V = ws.get<double>((size_t)(ncl + 1) * nc * np);
     if (ws.status()) return ws.status();
@@ -1693,19 +1970,18 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     // Everything after the counts, with buffers of the given capacities.
     auto second_half = [&](const CpCaps &cap) -> int {
         int *ccand = ws.get<int>(cap.c[0] + 1), *lcand = ws.get<int>(cap.c[2] + 1);
-        uint32_t *capre = ws.get<uint32_t>(cap.c[0] + 1);
         int *it_cl = ws.get<int>(cap.c[1] + 1), *it_c0 = ws.get<int>(cap.c[1] + 1),
             *it_c1 = ws.get<int>(cap.c[1] + 1), *it_order = ws.get<int>(cap.c[1] + 1);
         uint32_t *it_slot = ws.get<uint32_t>(cap.c[1] + 1),
                  *it_n = ws.get<uint32_t>(cap.c[1] + 1);
         float4 *abuf = ws.get<float4>((size_t)cap.c[4] + 1);
-        int *dlist = ws.get<int>(cap.c[3] + 1), *slist = ws.get<int>(cap.c[3] + 1);
+        int *dlist = ws.get<int>(cap.c[3] + 1), *slist = ws.get<int>(8 * (size_t)cap.c[3] + 1);
         double *part = ws.get<double>((size_t)(cap.c[1] + 1) * nc * np);
         if (ws.status()) return ws.status();
         if (work) hipLaunchKernelGGL(k_fill_u64, 1, 64, 0, s, work, 4);
         qa.bad = bad;
-        // fill pass of both query sets in one launch; far work items; the
-        // near-field classification and the leaves' launch order
+        // fill pass of both query sets in one launch (with the far work
+        // items), then the near-field classification
         {
             PhaseTimer pt(ev, RISM_PHASE_LISTS, s);
             CpQueryArgs qc = qa;
@@ -1713,27 +1989,28 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             qc.nq = ncl;
             qc.off = ccnt;
             qc.list = ccand;
-            qc.apre = capre;
+            qc.item_off = citems;
+            qc.atom_off = cacnt;
+            qc.it_cl = it_cl;
+            qc.it_c0 = it_c0;
+            qc.it_c1 = it_c1;
+            qc.it_slot = it_slot;
             qc.fill = 1;
             qc.items = nullptr;
             qc.acnt = nullptr;
             CpQueryArgs ql = qa;
             ql.mode = 1;
-            ql.nq = nleaf;
+            ql.nq = ngrp;
             ql.off = lcnt;
             ql.list = lcand;
-            ql.apre = nullptr;
             ql.fill = 1;
             ql.items = nullptr;
             ql.acnt = nullptr;
-            hipLaunchKernelGGL(k_cp_query, ncl + nleaf, 64, qshm, s, qc, ql);
-            if (ncl > 0)
-                hipLaunchKernelGGL(k_cp_items, (ncl + kBlock - 1) / kBlock, kBlock, 0, s, ncl,
-                                   ccnt, citems, cacnt, capre, (const int *)bad, it_cl, it_c0,
-                                   it_c1, it_slot);
+            hipLaunchKernelGGL(k_cp_query, ncl + ngrp, kQueryThreads, qshm, s, qc, ql,
+                               CpTabArgs{});
             CpClassArgs ca{};
             ca.L = L;
-            ca.nq = nleaf;
+            ca.nq = ngrp;
             ca.rshort = rshort;
             ca.cand_off = lcnt;
             ca.cand = lcand;
@@ -1746,10 +2023,16 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             ca.slist = slist;
             ca.nd = nd;
             ca.ns = nsh;
+            ca.cost = cost;
             ca.bad = bad;
-            hipLaunchKernelGGL(k_cp_classify, nleaf, kBlock, 0, s, ca);
-            hipLaunchKernelGGL(k_order_by_cost, 1, 1024, 0, s, nleaf, (const uint32_t *)nullptr,
-                               (const int *)bad, nd, nsh, order);
+            hipLaunchKernelGGL(k_cp_classify, ngrp, kClsThreads, 0, s, ca);
+        }
+        // the leaves' launch order (with the far work items' when there are any)
+        const OrderJob leaf_order{nleaf, nullptr, cost, nullptr, order};
+        if (!(ncl > 0 && cap.c[1] > 0)) {
+            PhaseTimer pt(ev, RISM_PHASE_LISTS, s);
+            hipLaunchKernelGGL(k_order_by_cost, 1, 1024, 0, s, leaf_order, leaf_order,
+                               (const int *)bad);
         }
         RISM_HIP(hipGetLastError());
 
@@ -1775,9 +2058,9 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
                 aa.n_items = tot + 1;
                 aa.bad = bad;
                 hipLaunchKernelGGL(k_cp_assign, (int)cap.c[1], kBlock, 0, s, aa);
-                hipLaunchKernelGGL(k_order_by_cost, 1, 1024, 0, s, (int)cap.c[1],
-                                   (const uint32_t *)(tot + 1), (const int *)bad, it_n,
-                                   (const uint32_t *)nullptr, it_order);
+                const OrderJob item_order{(int)cap.c[1], tot + 1, it_n, nullptr, it_order};
+                hipLaunchKernelGGL(k_order_by_cost, 2, 1024, 0, s, leaf_order, item_order,
+                                   (const int *)bad);
             }
             {
                 PhaseTimer pu(ev, RISM_PHASE_UPWARD, s);
@@ -1817,14 +2100,31 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         }
         if (ncl > 0) {
             PhaseTimer pt(ev, RISM_PHASE_DOWNWARD, s);
-            hipLaunchKernelGGL(k_cp_reduce, ncl, kBlock, 0, s, ncl, np, nc, citems,
-                               (const int *)bad, part, V);
-            for (int lvl = L.T - 1; lvl >= 1; --lvl)
-                hipLaunchKernelGGL(k_cp_down, L.cx[lvl] * L.cy[lvl] * L.cz[lvl], kDownThreads,
-                                   cp_down_lds(deg, down_nc), s, L, lvl, deg, nc, down_nc,
-                                   (const double *)ta.M,
-                                   make_int3(ta.mrow0[lvl][0], ta.mrow0[lvl][1], ta.mrow0[lvl][2]),
-                                   V);
+            CpDownArgs da{};
+            da.L = L;
+            da.degree = deg;
+            da.ncomp = nc;
+            da.nc = down_nc;
+            da.M = ta.M;
+            for (int l = 0; l <= kCpMaxLev; ++l)
+                for (int ax = 0; ax < 3; ++ax) da.mrow0[l][ax] = ta.mrow0[l][ax];
+            da.item_off = citems;
+            da.bad = bad;
+            da.part = part;
+            da.V = V;
+            const int ng1 = L.cx[1] * L.cy[1] * L.cz[1];
+            const size_t dshm = cp_down_lds(deg, down_nc);
+            const int slots = cp_down_slots(deg, down_nc);
+            if (deg == 8 && slots == 4)   // the usual degree, two components
+                hipLaunchKernelGGL((k_cp_down_chain<4, 9>), ng1, kDownThreads, dshm, s, da);
+            else
+                switch (slots) {
+                case 1: hipLaunchKernelGGL((k_cp_down_chain<1, 0>), ng1, kDownThreads, dshm, s, da); break;
+                case 2: hipLaunchKernelGGL((k_cp_down_chain<2, 0>), ng1, kDownThreads, dshm, s, da); break;
+                case 4: hipLaunchKernelGGL((k_cp_down_chain<4, 0>), ng1, kDownThreads, dshm, s, da); break;
+                case 8: hipLaunchKernelGGL((k_cp_down_chain<8, 0>), ng1, kDownThreads, dshm, s, da); break;
+                default: hipLaunchKernelGGL((k_cp_down_chain<16, 0>), ng1, kDownThreads, dshm, s, da); break;
+                }
         }
         RISM_HIP(hipGetLastError());
 
@@ -1866,17 +2166,15 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     };
 
     // totals and flags read back at the end of a pass: [0..4] counts as in
-    // CpCaps, [5] query stack overflow, [6] capacity check failed
+    // CpCaps, [5] query stack overflow, [6] capacity check failed, [8..9] the
+    // input check's flags (when deferred to here)
     uint32_t *hres = pinned_u32(10);
     if (!hres) {
         set_error("treecode_cp: pinned host buffer allocation failed");
         return RISM_E_HIP;
     }
     auto read_back = [&]() -> int {
-        RISM_HIP(hipMemcpyAsync(hres, flags, 7 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        if (a.stage_err)
-            RISM_HIP(hipMemcpyAsync(hres + 8, a.stage_err, 2 * sizeof(int), hipMemcpyDeviceToHost,
-                                    s));
+        RISM_HIP(hipMemcpyAsync(hres, flags, 10 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         RISM_HIP(hipStreamSynchronize(s));
         if (a.stage_err && (hres[8] || hres[9])) {
             set_error(hres[8] ? "non-finite atom input or negative sigma/eps"
@@ -1890,23 +2188,9 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         if (ncl == 0) hres[0] = hres[1] = hres[4] = 0;
         return RISM_OK;
     };
-    const CpShape shape{dev,   a.opts->leaf_size, deg,    a.solute->n, nleaf,
-                        ncl,   a.opts->theta,     rshort, L.guard};
-    CpCaps cached{};
-    bool have = false;
-    {
-        std::lock_guard<std::mutex> lk(g_cp_caps_mu);
-        auto it = g_cp_caps.find(shape);
-        if (it != g_cp_caps.end()) {
-            cached = it->second;
-            have = true;
-        }
-    }
     bool done = false;
     if (have) {
-        // speculative pass with the cached capacities
-        hipLaunchKernelGGL(k_cp_check, 1, 1, 0, s, (const uint32_t *)tot, cached,
-                           (const int *)overflow, bad);
+        // speculative pass with the cached capacities (checked by the scans)
         if ((rc = second_half(cached))) return rc;
         if ((rc = read_back())) return rc;
         done = hres[6] == 0;

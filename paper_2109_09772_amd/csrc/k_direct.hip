@@ -42,14 +42,78 @@ inline int brick_blocks(const GridParams &g)
     return ((g.nx + 15) / 16) * ((g.ny + 3) / 4) * ((g.nz + 3) / 4);
 }
 
+// ------------------------------------------------------ smeared-kernel table
+
+// erf(d/eta)/d and [e^{-kappa d} erfc(a - d/eta) - e^{kappa d} erfc(a + d/eta)]/d
+// (a = kappa eta / 2) in FP64, with their d -> 0 limits.
+__device__ inline void smear_f64(const AsymParams &A, double d, double &fc, double &fh)
+{
+    if (d == 0.0) {
+        fc = A.dcf0;
+        fh = A.tcf0;
+        return;
+    }
+    const double x = d * A.inv_eta;
+    fc = erf(x) / d;
+    const double t2 = A.a + x < 27.0 ? exp(A.kappa * d) * erfc(A.a + x) : 0.0;
+    fh = (exp(-A.kappa * d) * erfc(A.a - x) - t2) / d;
+}
+
+// Four threads per interval, one per Chebyshev node of the interval (the
+// kernel values are the costly part); the interval's first thread forms the
+// cubic through the four values (Newton form, expanded to monomials in the
+// local variable t).
+__device__ __forceinline__ void smear_table_block(const AsymParams &A, float4 *tab, int blk)
+{
+    const int g = blk * kBlock + threadIdx.x;
+    const int i = g >> 2, node = g & 3, lane = threadIdx.x & 63, lead = lane & ~3;
+    const double h = 1.0 / A.tab_inv_h;
+    double t[4];
+    for (int j = 0; j < 4; ++j) t[j] = 0.5 * (1.0 - cos((2 * j + 1) * kPi / 8.0));
+    double fc = 0.0, fh = 0.0;
+    if (i < kSmearIntervals) smear_f64(A, (i + t[node]) * h, fc, fh);
+    double vc[4], vh[4];
+    for (int j = 0; j < 4; ++j) {
+        vc[j] = __shfl(fc, lead + j);
+        vh[j] = __shfl(fh, lead + j);
+    }
+    if (i >= kSmearIntervals || node != 0) return;
+    double *v[2] = {vc, vh};
+    for (int f = 0; f < 2; ++f) {
+        double d0 = v[f][0], d1 = v[f][1], d2 = v[f][2], d3 = v[f][3];
+        // divided differences
+        const double a1 = (d1 - d0) / (t[1] - t[0]);
+        const double b1 = (d2 - d1) / (t[2] - t[1]);
+        const double c1 = (d3 - d2) / (t[3] - t[2]);
+        const double a2 = (b1 - a1) / (t[2] - t[0]);
+        const double b2 = (c1 - b1) / (t[3] - t[1]);
+        const double a3 = (b2 - a2) / (t[3] - t[0]);
+        const double s3 = t[0] + t[1] + t[2];
+        const double p2 = t[0] * t[1] + t[0] * t[2] + t[1] * t[2];
+        float4 c;
+        c.w = (float)a3;
+        c.z = (float)(a2 - a3 * s3);
+        c.y = (float)(a1 - a2 * (t[0] + t[1]) + a3 * p2);
+        c.x = (float)(d0 - a1 * t[0] + a2 * t[0] * t[1] - a3 * t[0] * t[1] * t[2]);
+        tab[2 * i + f] = c;
+    }
+}
+
 // ------------------------------------------------------------------ staging
 
 // Lorentz-Berthelot mixing and the A, B, r_cut of every (site, atom) pair,
 // plus the FP32 hi/lo split of the atom coordinates relative to the grid
 // origin.  Padding atoms (a >= n) carry no charge and no LJ and sit far away.
+// With a.smear_tab, kSmearBlocks more workgroups form the smeared-kernel
+// table in the same launch.
 template <int NS>
 __global__ __launch_bounds__(kBlock) void k_stage(SiteParams sp, StageArgs a)
 {
+    const int nstage = (int)((a.npad + kBlock - 1) / kBlock);
+    if ((int)blockIdx.x >= nstage) {   // whole workgroup
+        smear_table_block(a.smear, a.smear_tab, blockIdx.x - nstage);
+        return;
+    }
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const bool live = i < a.npad;   // every lane stays for the wave-wide maximum below
     double x = kFarAway, y = kFarAway, z = kFarAway, q = 0.0, sig = 0.0, eps = 0.0;
@@ -142,6 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_stage(SiteParams sp, StageArgs a)
 int launch_stage(const SiteParams &sp, const StageArgs &a, hipStream_t s)
 {
     int blocks = (int)((a.npad + kBlock - 1) / kBlock);
+    if (a.smear_tab) blocks += kSmearBlocks;
     if (blocks == 0) return RISM_OK;
     switch (sp.ns_pad) {
     case 1: hipLaunchKernelGGL(k_stage<1>, blocks, kBlock, 0, s, sp, a); break;
@@ -265,69 +330,6 @@ int launch_direct_f64(const SiteParams &sp, const DirectArgs &a, hipStream_t s)
     return RISM_OK;
 }
 
-// ------------------------------------------------------ smeared-kernel table
-
-// erf(d/eta)/d and [e^{-kappa d} erfc(a - d/eta) - e^{kappa d} erfc(a + d/eta)]/d
-// (a = kappa eta / 2) in FP64, with their d -> 0 limits.
-__device__ inline void smear_f64(const AsymParams &A, double d, double &fc, double &fh)
-{
-    if (d == 0.0) {
-        fc = A.dcf0;
-        fh = A.tcf0;
-        return;
-    }
-    const double x = d * A.inv_eta;
-    fc = erf(x) / d;
-    const double t2 = A.a + x < 27.0 ? exp(A.kappa * d) * erfc(A.a + x) : 0.0;
-    fh = (exp(-A.kappa * d) * erfc(A.a - x) - t2) / d;
-}
-
-// Four threads per interval, one per Chebyshev node of the interval (the
-// kernel values are the costly part); the interval's first thread forms the
-// cubic through the four values (Newton form, expanded to monomials in the
-// local variable t).
-__global__ __launch_bounds__(256) void k_smear_table(AsymParams A, float4 *tab)
-{
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = g >> 2, node = g & 3, lane = threadIdx.x & 63, lead = lane & ~3;
-    const double h = 1.0 / A.tab_inv_h;
-    double t[4];
-    for (int j = 0; j < 4; ++j) t[j] = 0.5 * (1.0 - cos((2 * j + 1) * kPi / 8.0));
-    double fc = 0.0, fh = 0.0;
-    if (i < kSmearIntervals) smear_f64(A, (i + t[node]) * h, fc, fh);
-    double vc[4], vh[4];
-    for (int j = 0; j < 4; ++j) {
-        vc[j] = __shfl(fc, lead + j);
-        vh[j] = __shfl(fh, lead + j);
-    }
-    if (i >= kSmearIntervals || node != 0) return;
-    double *v[2] = {vc, vh};
-    for (int f = 0; f < 2; ++f) {
-        double d0 = v[f][0], d1 = v[f][1], d2 = v[f][2], d3 = v[f][3];
-        // divided differences
-        const double a1 = (d1 - d0) / (t[1] - t[0]);
-        const double b1 = (d2 - d1) / (t[2] - t[1]);
-        const double c1 = (d3 - d2) / (t[3] - t[2]);
-        const double a2 = (b1 - a1) / (t[2] - t[0]);
-        const double b2 = (c1 - b1) / (t[3] - t[1]);
-        const double a3 = (b2 - a2) / (t[3] - t[0]);
-        const double s3 = t[0] + t[1] + t[2];
-        const double p2 = t[0] * t[1] + t[0] * t[2] + t[1] * t[2];
-        float4 c;
-        c.w = (float)a3;
-        c.z = (float)(a2 - a3 * s3);
-        c.y = (float)(a1 - a2 * (t[0] + t[1]) + a3 * p2);
-        c.x = (float)(d0 - a1 * t[0] + a2 * t[0] * t[1] - a3 * t[0] * t[1] * t[2]);
-        tab[2 * i + f] = c;
-    }
-}
-
-int launch_smear_table(const AsymParams &a, float4 *tab, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_smear_table, (4 * kSmearIntervals + 255) / 256, 256, 0, s, a, tab);
-    RISM_HIP(hipGetLastError());
-    return RISM_OK;
-}
 
 // ------------------------------------------------- FP32 compensated direct sum
 

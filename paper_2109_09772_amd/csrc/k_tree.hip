@@ -214,9 +214,10 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *kin, cons
 // ------------------------------------------------------------ octree
 
 __global__ void k_tree_root(int n, int *begin, int *end, int *level, int *level_start, int *n_nodes,
-                            int *flags)
+                            int *flags, int *clear, int n_clear)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int k = 0; k < n_clear; ++k) clear[k] = 0;
     begin[0] = 0;
     end[0] = n;
     level[0] = 0;
@@ -314,8 +315,10 @@ __global__ __launch_bounds__(kBlock) void k_split_write(const uint32_t *keys, in
 
 // ------------------------------------------------- one-workgroup builder
 
-// Small trees: keys by one workgroup, ranked by many, then one workgroup
-// places them and builds the octree level by level with block-wide scans.
+// Small trees: keys formed and ranked by many workgroups (each forms every
+// key, since it counts over all of them), which also place the atom records
+// in key order; then one workgroup builds the octree level by level with
+// block-wide scans.
 // Produces the same permutation and nodes as the multi-kernel build.
 constexpr int kSmallThreads = 1024;
 constexpr int kRankTargets = 64;   // atoms ranked per workgroup
@@ -324,13 +327,12 @@ constexpr int kRankTargets = 64;   // atoms ranked per workgroup
 // level-by-level split (about 0.3 ms at 14,000 atoms).
 constexpr int kSmallTreeMax = 16384;
 
-// Morton keys of a small tree's atoms, by one workgroup: the key cube from
-// a block-wide reduction, then one key per atom.
-__global__ __launch_bounds__(kSmallThreads) void k_tree_keys(const float4 *rec, int stride_f4, int n,
-                                                           uint32_t *keys)
+// Key cube of a small tree's atoms by one workgroup of kSmallThreads: a
+// block-wide reduction of the positions.  bb: 6 doubles in LDS.
+__device__ __forceinline__ void small_key_cube(const float4 *rec, int stride_f4, int n,
+                                               double *bb)
 {
     __shared__ double red[6][kSmallThreads / 64];
-    __shared__ double bb[6];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int i = tid; i < n; i += kSmallThreads) {
@@ -364,24 +366,34 @@ __global__ __launch_bounds__(kSmallThreads) void k_tree_keys(const float4 *rec, 
         bbox_cube(l3, h3, bb);
     }
     __syncthreads();
-    for (int i = tid; i < n; i += kSmallThreads) keys[i] = atom_key(rec, stride_f4, i, bb);
 }
 
 // Sorted position of every atom by (key, index), i.e. the position a stable
-// sort by key gives: each workgroup copies all keys to LDS and ranks 64
-// atoms, each of its sixteen waves counting over a sixteenth of the keys
-// (four keys per broadcast read).
-constexpr int kRankThreads = 1024;
+// sort by key gives: each workgroup forms all keys in LDS (workgroup 0 also
+// stores them) and ranks 64 atoms, each of its sixteen waves counting over a
+// sixteenth of the keys (four keys per broadcast read).  The ranked atoms'
+// records are then placed at their sorted positions (the padding records,
+// n <= i < npad, stay last).
+constexpr int kRankThreads = kSmallThreads;
 constexpr int kRankWaves = kRankThreads / 64;
 
-__global__ __launch_bounds__(kRankThreads) void k_tree_rank(const uint32_t *keys, int n, int *rank)
+__global__ __launch_bounds__(kRankThreads) void k_tree_rank(const float4 *rec, int stride_f4,
+                                                            int n, int npad, int *rank,
+                                                            uint32_t *keys, int *perm,
+                                                            float4 *sorted)
 {
     extern __shared__ uint4 k4[];   // [round_up(n, 4 kRankWaves) / 4]
     __shared__ int part[kRankWaves][kRankTargets];
+    __shared__ double bb[6];
     uint32_t *kk = reinterpret_cast<uint32_t *>(k4);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    small_key_cube(rec, stride_f4, n, bb);
     const int np = (n + 4 * kRankWaves - 1) / (4 * kRankWaves) * (4 * kRankWaves);
-    for (int i = tid; i < np; i += kRankThreads) kk[i] = i < n ? keys[i] : 0xffffffffu;
+    for (int i = tid; i < np; i += kRankThreads) {
+        const uint32_t key = i < n ? atom_key(rec, stride_f4, i, bb) : 0xffffffffu;
+        kk[i] = key;
+        if (blockIdx.x == 0 && i < n) keys[i] = key;
+    }
     __syncthreads();
     const int t = blockIdx.x * kRankTargets + lane;
     const int q = np / 4 / kRankWaves;   // units of four keys per wave
@@ -400,11 +412,23 @@ __global__ __launch_bounds__(kRankThreads) void k_tree_rank(const uint32_t *keys
     }
     part[wave][lane] = c;
     __syncthreads();
+    __shared__ int rk[kRankTargets];
     if (wave == 0 && t < n) {
         int r = 0;
         for (int w = 0; w < kRankWaves; ++w) r += part[w][lane];
         rank[t] = r;
+        perm[r] = t;
+        rk[lane] = r;
     }
+    __syncthreads();
+    // the ranked atoms' records, one float4 per thread
+    for (int u = tid; u < kRankTargets * stride_f4; u += kRankThreads) {
+        const int j = u / stride_f4, k = u - j * stride_f4, tj = blockIdx.x * kRankTargets + j;
+        if (tj < n) sorted[(size_t)rk[j] * stride_f4 + k] = rec[(size_t)tj * stride_f4 + k];
+    }
+    if (blockIdx.x == 0)
+        for (int u = tid; u < (npad - n) * stride_f4; u += kRankThreads)
+            sorted[(size_t)n * stride_f4 + u] = rec[(size_t)n * stride_f4 + u];
 }
 
 __device__ __forceinline__ int block_excl_scan(int v, int *wsum, int &total)
@@ -438,21 +462,34 @@ __device__ __forceinline__ int lower_digit_lds(const unsigned long long *sk, int
     return lo;
 }
 
-__global__ __launch_bounds__(kSmallThreads) void k_tree_small(
-    const uint32_t *keys, const int *rank, int n, int leaf, int cap, int *perm, int *begin,
-    int *end, int *level, int *child0, int *nchild, int *level_start_out, int *n_nodes_out,
-    int *flags)
+struct SmallTreeArgs {
+    const uint32_t *keys;
+    const int *rank;
+    int n, leaf, cap;
+    int *begin, *end, *level, *child0, *nchild, *level_start, *n_nodes, *flags;
+    int *clear, n_clear;   // words set to 0 (TreeDev::clear)
+};
+
+// Dynamic LDS of k_tree_small: the sorted keys.
+inline size_t small_tree_lds(int n)
+{
+    return (size_t)n * sizeof(unsigned long long);
+}
+
+__global__ __launch_bounds__(kSmallThreads) void k_tree_small(SmallTreeArgs a)
 {
     extern __shared__ unsigned long long sk[];   // [n] (key << 32) | index, sorted
     __shared__ int wsum[kSmallThreads / 64];
     __shared__ int ls[kMortonBits + 2];
     const int tid = threadIdx.x, lane = tid & 63;
+    const int n = a.n, leaf = a.leaf, cap = a.cap;
+    int *begin = a.begin, *end = a.end, *level = a.level, *child0 = a.child0,
+        *nchild = a.nchild, *flags = a.flags;
 
+    if (tid < a.n_clear) a.clear[tid] = 0;
     for (int i = tid; i < n; i += kSmallThreads)
-        sk[rank[i]] = ((unsigned long long)keys[i] << 32) | (unsigned)i;
+        sk[a.rank[i]] = ((unsigned long long)a.keys[i] << 32) | (unsigned)i;
     __syncthreads();
-    for (int i = tid; i < n; i += kSmallThreads) perm[i] = (int)(sk[i] & 0xffffffffu);
-
     // octree, level by level
     if (tid == 0) {
         begin[0] = 0;
@@ -514,8 +551,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_tree_small(
         }
         __syncthreads();
     }
-    if (tid < kMortonBits + 2) level_start_out[tid] = ls[tid];
-    if (tid == 0) *n_nodes_out = ls[kMortonBits + 1];
+    if (tid < kMortonBits + 2) a.level_start[tid] = ls[tid];
+    if (tid == 0) *a.n_nodes = ls[kMortonBits + 1];
 }
 
 template <int NS>
@@ -839,23 +876,38 @@ int build_source_tree(const TreeCallArgs &a, Workspace &ws, TreeDev &t, rism_sta
     t.sorted_rec = ws.alloc(rec32_bytes_of(a.sp.ns_pad) * a.npad);
     if (ws.status()) return ws.status();
 
-    // small trees: keys ranked by many workgroups, the octree built by one
+    // small trees: keys formed and ranked (and the records placed) by many
+    // workgroups, the octree built by one
     int dev = 0, lds_max = 0;
     RISM_HIP(hipGetDevice(&dev));
     RISM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t small_shm = (size_t)n * sizeof(unsigned long long);
     // (up to kSmallTreeMax atoms, and keys that fit the LDS of one workgroup)
-    const bool small = n <= kSmallTreeMax && small_shm + 4096 <= (size_t)lds_max;
+    const bool small = n <= kSmallTreeMax && small_tree_lds(n) + 4096 <= (size_t)lds_max;
     if (small) {
-        if (n > 0) {
-            hipLaunchKernelGGL(k_tree_keys, 1, kSmallThreads, 0, s, rec, stride_f4, n, k0);
+        {
+            // (one workgroup at least: it also places the padding records)
             const int npad = (n + 4 * kRankWaves - 1) / (4 * kRankWaves) * (4 * kRankWaves);
-            hipLaunchKernelGGL(k_tree_rank, (n + kRankTargets - 1) / kRankTargets, kRankThreads,
-                               (size_t)npad * sizeof(uint32_t), s, (const uint32_t *)k0, n, v1);
+            hipLaunchKernelGGL(k_tree_rank, std::max(1, (n + kRankTargets - 1) / kRankTargets),
+                               kRankThreads, (size_t)npad * sizeof(uint32_t), s, rec, stride_f4,
+                               n, (int)a.npad, v1, k0, v0, static_cast<float4 *>(t.sorted_rec));
         }
-        hipLaunchKernelGGL(k_tree_small, 1, kSmallThreads, small_shm, s, (const uint32_t *)k0,
-                           (const int *)v1, n, leaf, t.cap_nodes, v0, t.begin, t.end, t.level,
-                           t.child0, t.nchild, t.level_start, t.n_nodes, flags);
+        SmallTreeArgs sa{};
+        sa.keys = k0;
+        sa.rank = v1;
+        sa.n = n;
+        sa.leaf = leaf;
+        sa.cap = t.cap_nodes;
+        sa.begin = t.begin;
+        sa.end = t.end;
+        sa.level = t.level;
+        sa.child0 = t.child0;
+        sa.nchild = t.nchild;
+        sa.level_start = t.level_start;
+        sa.n_nodes = t.n_nodes;
+        sa.flags = flags;
+        sa.clear = t.clear;
+        sa.n_clear = t.n_clear;
+        hipLaunchKernelGGL(k_tree_small, 1, kSmallThreads, small_tree_lds(n), s, sa);
         t.perm = v0;
     } else {
     const int nb = (n + kBlock - 1) / kBlock;
@@ -873,7 +925,7 @@ int build_source_tree(const TreeCallArgs &a, Workspace &ws, TreeDev &t, rism_sta
     }
     t.perm = v0;
     hipLaunchKernelGGL(k_tree_root, 1, 1, 0, s, n, t.begin, t.end, t.level, t.level_start,
-                       t.n_nodes, flags);
+                       t.n_nodes, flags, t.clear, t.n_clear);
     const int gb = 256;
     for (int lvl = 0; lvl < kMortonBits; ++lvl) {
         hipLaunchKernelGGL(k_split_count, gb, kBlock, 0, s, k0, t.begin, t.end, t.level_start, lvl,
@@ -887,11 +939,13 @@ int build_source_tree(const TreeCallArgs &a, Workspace &ws, TreeDev &t, rism_sta
     }
     }
     RISM_HIP(hipGetLastError());
+    if (!small) {
     switch (a.sp.ns_pad) {
     case 1: hipLaunchKernelGGL(k_permute<1>, (int)((a.npad + kBlock - 1) / kBlock), kBlock, 0, s, (const AtomF32<1> *)a.rec32, t.perm, n, (int)a.npad, (AtomF32<1> *)t.sorted_rec); break;
     case 2: hipLaunchKernelGGL(k_permute<2>, (int)((a.npad + kBlock - 1) / kBlock), kBlock, 0, s, (const AtomF32<2> *)a.rec32, t.perm, n, (int)a.npad, (AtomF32<2> *)t.sorted_rec); break;
     case 4: hipLaunchKernelGGL(k_permute<4>, (int)((a.npad + kBlock - 1) / kBlock), kBlock, 0, s, (const AtomF32<4> *)a.rec32, t.perm, n, (int)a.npad, (AtomF32<4> *)t.sorted_rec); break;
     default: hipLaunchKernelGGL(k_permute<8>, (int)((a.npad + kBlock - 1) / kBlock), kBlock, 0, s, (const AtomF32<8> *)a.rec32, t.perm, n, (int)a.npad, (AtomF32<8> *)t.sorted_rec); break;
+    }
     }
     hipLaunchKernelGGL(k_node_box, 1024, kBlock, 0, s, (const float4 *)t.sorted_rec, stride_f4,
                        t.begin, t.end, t.n_nodes, t.box, t.centre);

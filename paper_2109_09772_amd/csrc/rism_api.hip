@@ -313,12 +313,15 @@ static size_t rec_bytes(int ns_pad, bool f64)
 // sync here and hand the device flags ([0] non-finite input, [1] tolerance)
 // to the caller, which reads them with its own end-of-call read-back (the
 // kernels in between clamp every index they derive from atom data).
+// smear_tab: also form the smeared-kernel table of p.asym there (same launch).
 static int stage_atoms(const rism_solute *so, const Prep &p, const rism_opts *op, bool want32,
                        bool want64, bool check_eps, Workspace &ws, void **rec32, void **rec64,
                        double **rcut, hipStream_t s, double *max_rcut = nullptr,
-                       const int **defer_err = nullptr)
+                       const int **defer_err = nullptr, float4 *smear_tab = nullptr)
 {
     StageArgs a{};
+    a.smear_tab = smear_tab;
+    a.smear = p.asym;
     a.xyz = so->xyz;
     a.q = so->q;
     a.sig = so->sigma;
@@ -447,15 +450,17 @@ static int forward(const rism_solute *so, const rism_sites *si, const rism_grid 
     const bool cp_method = (op->method == RISM_TREECODE_CP || op->method == RISM_TREECODE_TAYLOR) &&
                            (u || c || h);
     const int *stage_err = nullptr;
-    rc = stage_atoms(so, p, op, !f64path, f64path, false, ws, &rec32, &rec64,
-                     want_rcut ? &rcut : nullptr, s, &max_rcut, cp_method ? &stage_err : nullptr);
-    if (rc) return rc;
+    // the FP32 paths' smeared-kernel table, formed by the staging launch
+    float4 *tab = nullptr;
     if (asym_on && !f64path) {
-        float4 *tab = ws.get<float4>(2 * kSmearIntervals);
+        tab = ws.get<float4>(2 * kSmearIntervals);
         if (!tab) return ws.status();
-        if ((rc = launch_smear_table(p.asym, tab, s))) return rc;
-        p.asym.tab = tab;
     }
+    rc = stage_atoms(so, p, op, !f64path, f64path, false, ws, &rec32, &rec64,
+                     want_rcut ? &rcut : nullptr, s, &max_rcut, cp_method ? &stage_err : nullptr,
+                     tab);
+    if (rc) return rc;
+    if (tab) p.asym.tab = tab;
 
     if (u || c || h) {
         DirectArgs da{};

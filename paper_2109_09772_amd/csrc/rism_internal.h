@@ -77,6 +77,8 @@ struct OutParams {
 // local variable t in [0, 1) of each interval): tab[2 i] for erf(d/eta)/d and
 // tab[2 i + 1] for the Eq. 6 bracket over d, each as (c0, c1, c2, c3).
 constexpr int kSmearIntervals = 256;
+// workgroups of kBlock threads that form the table (four threads per interval)
+constexpr int kSmearBlocks = (4 * kSmearIntervals + kBlock - 1) / kBlock;
 
 struct AsymParams {
     const float4 *tab;  // device table, 2 * kSmearIntervals entries (FP32 paths)
@@ -155,6 +157,8 @@ struct StageArgs {
     void *rec32;        // AtomF32<ns_pad>[npad] or null
     void *rec64;        // AtomF64<ns_pad>[npad] or null
     double *rcut;       // [ns][n] FP64 cut-off radii or null
+    float4 *smear_tab;  // or null: the smeared-kernel table of `smear` (cubic
+    AsymParams smear;   // pieces per interval), formed by the same launch
 };
 int launch_stage(const SiteParams &sp, const StageArgs &a, hipStream_t s);
 int launch_lj_tail(const SiteParams &sp, const double *rcut, const double *sig, const double *eps,
@@ -174,7 +178,6 @@ struct DirectArgs {
 int launch_direct_f64(const SiteParams &sp, const DirectArgs &a, hipStream_t s);
 // Fills the 2 * kSmearIntervals cubic pieces of erf(d/eta)/d and of the Eq. 6
 // bracket over d on [0, R_s] (FP64 evaluation, FP32 coefficients).
-int launch_smear_table(const AsymParams &a, float4 *tab, hipStream_t s);
 int launch_direct_f32(const SiteParams &sp, const DirectArgs &a, hipStream_t s);
 
 int launch_compare(const void *x, int f64, const double *ref, const uint8_t *mask, int64_t n,

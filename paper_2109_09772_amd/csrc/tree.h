@@ -21,6 +21,10 @@ struct TreeDev {
     double *centre;        // [cap][4]: centre x, y, z, radius (half-diagonal)
     int *perm;             // sorted position -> input index
     void *sorted_rec;      // AtomF32<ns_pad> in sorted order
+    // in: n_clear words the build sets to 0 (flags of the caller's later
+    // kernels), or none
+    int *clear;
+    int n_clear;
 };
 
 // Proxy charges of the barycentric Chebyshev interpolation (upward pass).
