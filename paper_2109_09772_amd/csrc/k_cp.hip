@@ -36,7 +36,6 @@ namespace rism {
 
 namespace {
 
-constexpr int kCpChunkLeaves = 32;   // candidate source leaves per far work item
 
 // ----------------------------------------------------------------- scans
 
@@ -334,14 +333,9 @@ struct CpQueryArgs {
     const int *begin, *end, *child0, *nchild;
     const double *box;
     const int *n_nodes;
-    uint32_t *cnt, *items, *acnt;   // count pass (nq + 1 entries each; items, acnt optional)
+    uint32_t *cnt, *acnt;           // count pass (nq + 1 entries each; acnt optional)
     const uint32_t *off;            // fill pass
     int *list;
-    // fill pass, clusters: the far work items (chunks of kCpChunkLeaves
-    // candidates) from each query's first item and first assigned-atom slot
-    const uint32_t *item_off, *atom_off;
-    int *it_cl, *it_c0, *it_c1;
-    uint32_t *it_slot;
     const int *bad;                 // fill pass: lists sized too small, write nothing
     int *overflow;
     int fill;
@@ -381,7 +375,6 @@ __device__ __forceinline__ void cp_query(const CpQueryArgs &a, int q, int *stk)
     if (a.fill && *a.bad) return;
     if (!a.fill && q == 0 && threadIdx.x == 0) {
         a.cnt[a.nq] = 0;
-        if (a.items) a.items[a.nq] = 0;
         if (a.acnt) a.acnt[a.nq] = 0;
     }
     if (q >= a.nq) return;   // the whole wave leaves together
@@ -425,22 +418,7 @@ __device__ __forceinline__ void cp_query(const CpQueryArgs &a, int q, int *stk)
         const uint64_t m = __ballot(lf);
         if (!lf) sz = 0;
         const int incl = wave_incl_scan(sz, lane);
-        if (lf && a.fill) {
-            const uint32_t li = n + (uint32_t)__popcll(m & lt);
-            a.list[o + li] = node;
-            if (a.it_cl && li % kCpChunkLeaves == 0) {
-                // item (cluster, first candidate, end candidate) and its slot
-                // range in the buffer of assigned atoms: the cluster's
-                // candidate atoms start at atom_off[q], items follow in
-                // order, each with room for all of its candidate atoms
-                const int it = (int)(a.item_off[q] + li / kCpChunkLeaves);
-                const uint32_t c0 = o + li;
-                a.it_cl[it] = q;
-                a.it_c0[it] = (int)c0;
-                a.it_c1[it] = (int)min(c0 + (uint32_t)kCpChunkLeaves, a.off[q + 1]);
-                a.it_slot[it] = a.atom_off[q] + nat + (uint32_t)(incl - sz);
-            }
-        }
+        if (lf && a.fill) a.list[o + n + (uint32_t)__popcll(m & lt)] = node;
         n += (uint32_t)__popcll(m);
         nat += (uint32_t)__shfl(incl, 63);
     };
@@ -514,7 +492,6 @@ __device__ __forceinline__ void cp_query(const CpQueryArgs &a, int q, int *stk)
     }
     if (!a.fill && lane == 0) {
         a.cnt[q] = n;
-        if (a.items) a.items[q] = (n + kCpChunkLeaves - 1) / kCpChunkLeaves;
         if (a.acnt) a.acnt[q] = nat;
     }
 }
@@ -580,7 +557,6 @@ struct CpClassArgs {
     uint32_t *nd;              // direct atoms per group
     uint32_t *ns;              // short-range atoms per level-0 block
     uint32_t *cost;            // per level-0 block: its direct and short-range atoms
-    const int *bad;            // lists sized too small: write nothing
 };
 
 // Threads of the classification, and candidate leaves per LDS window (one
@@ -610,7 +586,8 @@ __device__ __forceinline__ int group_excl_scan(int v, int *ws, int &total)
     return base + incl - v;
 }
 
-__global__ __launch_bounds__(kClsThreads) void k_cp_classify(CpClassArgs a)
+// One workgroup of kClsThreads threads classifies group g.
+__device__ __forceinline__ void cp_classify_group(const CpClassArgs &a, int g)
 {
     constexpr int NW = kClsThreads / 64;
     __shared__ int beg[kClsWin];
@@ -620,8 +597,6 @@ __global__ __launch_bounds__(kClsThreads) void k_cp_classify(CpClassArgs a)
     __shared__ CpMac mac[kCpMaxLev + 1];   // the group's ancestors, levels 1..T
     __shared__ double cbox[8][6];          // its blocks' boxes (empty if absent)
     __shared__ int cleaf[8];               // their ids (-1 if absent)
-    const int g = blockIdx.x;
-    if (g >= a.nq || *a.bad) return;   // whole workgroup
     const CpLevels &L = a.L;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int I1 = 0, J1 = 0, K1 = 0;
@@ -744,8 +719,12 @@ __global__ __launch_bounds__(kClsThreads) void k_cp_classify(CpClassArgs a)
 // Launch orders: work items sorted by decreasing cost (c1 + c2, in
 // power-of-two classes), so that the heaviest items start first and the light
 // ones fill the end of the launch.  Results do not depend on the order.  One
-// workgroup per order (the leaves' and the far work items').
+// workgroup per order.
 constexpr int kCostClasses = 33;
+constexpr int kPlanThreads = 1024;
+// Atoms per far work item at most: a cluster's assigned atoms are swept in
+// runs of this many, one workgroup each (kSweepGroups ranges of kBlock).
+constexpr int kItemAtoms = 1024;
 __device__ __forceinline__ int cost_class(uint32_t c)
 {
     return c == 0 ? 0 : 32 - __clz(c);
@@ -756,15 +735,14 @@ struct OrderJob {
     const uint32_t *c1, *c2;       // costs (c2 optional)
     int *order;
 };
-__global__ __launch_bounds__(1024) void k_order_by_cost(OrderJob j0, OrderJob j1, const int *bad)
+__device__ __forceinline__ void order_by_cost(const OrderJob &j)
 {
     __shared__ unsigned int cnt[kCostClasses];
-    if (*bad) return;
-    const OrderJob &j = blockIdx.x == 0 ? j0 : j1;
     const uint32_t *c1 = j.c1, *c2 = j.c2;
     int *order = j.order;
     int n = j.n;
     if (j.n_dev) n = min(n, (int)*j.n_dev);
+    __syncthreads();   // a previous order of this workgroup is done with cnt
     if (threadIdx.x < kCostClasses) cnt[threadIdx.x] = 0u;
     __syncthreads();
     for (int q = threadIdx.x; q < n; q += blockDim.x)
@@ -783,100 +761,203 @@ __global__ __launch_bounds__(1024) void k_order_by_cost(OrderJob j0, OrderJob j1
         order[atomicAdd(&cnt[cost_class(c1[q] + (c2 ? c2[q] : 0u))], 1u)] = q;
 }
 
-// ----------------------------------------------------------------- far
+// Far work items: each cluster's assigned atoms in runs of at most amax (at
+// least one item per cluster, so that every cluster's far field is formed),
+// numbered cluster by cluster; item_off[cl] is the first item of cluster cl.
+struct CpItemArgs {
+    int ncl;
+    const uint32_t *n;     // assigned atoms per cluster
+    uint32_t amax;         // atoms per item at most
+    uint32_t *item_off;    // [ncl + 1]
+    int *it_cl;            // cluster of each item
+    uint32_t *it_a0;       // first atom of the item within its cluster's run
+    uint32_t *it_na;       // atoms of the item
+    uint32_t *n_items;     // items in all
+};
 
-// Assignment of the candidate atoms of one far work item: an atom belongs to
-// this cluster when the cluster is the coarsest one on the atom's chain that
-// satisfies the MAC.  The assigned atoms are written, in candidate order, as
-// (position relative to the cluster centre, charge) from the item's slot on.
+__device__ __forceinline__ void cp_make_items(const CpItemArgs &a)
+{
+    __shared__ uint32_t wsum[kPlanThreads / 64];
+    __shared__ uint32_t carry;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < a.ncl; c0 += kPlanThreads) {
+        const int cl = c0 + tid;
+        const uint32_t na = cl < a.ncl ? a.n[cl] : 0u;
+        const uint32_t k = cl < a.ncl ? max(1u, (na + a.amax - 1) / a.amax) : 0u;
+        uint32_t x = k;   // inclusive scan over the workgroup
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        uint32_t base = carry, tot = 0;
+        for (int w = 0; w < kPlanThreads / 64; ++w) {
+            base += w < wave ? wsum[w] : 0u;
+            tot += wsum[w];
+        }
+        const uint32_t first = base + x - k;
+        if (cl < a.ncl) {
+            a.item_off[cl] = first;
+            for (uint32_t j = 0; j < k; ++j) {
+                a.it_cl[first + j] = cl;
+                a.it_a0[first + j] = j * a.amax;
+                a.it_na[first + j] = min(a.amax, na - j * a.amax);
+            }
+        }
+        __syncthreads();   // every thread has read carry and wsum
+        if (tid == 0) carry += tot;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        a.item_off[a.ncl] = carry;
+        *a.n_items = carry;
+    }
+}
+
+// The launch plan after the lists: workgroup 0 orders the level-0 blocks;
+// workgroup 1 (with clusters) forms the far work items and orders them.
+__global__ __launch_bounds__(kPlanThreads) void k_cp_plan(OrderJob leaves, CpItemArgs items,
+                                                         OrderJob item_order, const int *bad)
+{
+    if (*bad) return;
+    if (blockIdx.x == 0) {
+        order_by_cost(leaves);
+    } else {
+        cp_make_items(items);
+        __syncthreads();   // the items are written before they are ordered
+        order_by_cost(item_order);
+    }
+}
+
+// Far-field assignment of one target cluster's candidate atoms: an atom
+// belongs to the cluster when the cluster is the coarsest one on the atom's
+// chain that satisfies the MAC.  The assigned atoms are written, in candidate
+// order, as (position relative to the cluster centre, charge) from the
+// cluster's slot on (room for all of its candidate atoms); their count goes
+// to n[cl].
 struct CpAssignArgs {
     CpLevels L;
-    const int *it_cl, *it_c0, *it_c1;
-    const uint32_t *it_slot;
+    const uint32_t *cand_off;  // candidate leaves of each cluster (prefix)
     const int *cand;
     const int *begin, *end;
     const float4 *rec;
     int stride_f4;
+    const uint32_t *slot;      // candidate atoms of each cluster (prefix): first slot
     float4 *abuf;              // assigned atoms
-    uint32_t *it_n;            // assigned atoms per item
+    uint32_t *n;               // assigned atoms per cluster
     unsigned long long *work;  // optional: (atom, proxy) pairs
     int np;
-    const uint32_t *n_items;   // items on the device (the launch may have more blocks)
-    const int *bad;            // buffers sized too small: do nothing
 };
 
-__global__ __launch_bounds__(kBlock) void k_cp_assign(CpAssignArgs a)
+// One workgroup of NT threads assigns cluster cl's candidates, windows of NT
+// candidate leaves at a time, their atoms dealt NT at a time to the threads.
+template <int NT>
+__device__ __forceinline__ void cp_assign_cluster(const CpAssignArgs &a, int cl)
 {
-    __shared__ int wcount[kBlock / 64];
-    __shared__ int pre[kCpChunkLeaves + 1];
-    __shared__ int lbeg[kCpChunkLeaves];
+    constexpr int NW = NT / 64;
+    __shared__ int beg[NT];
+    __shared__ int pre[NT + 1];
+    __shared__ int ws[NW];
+    __shared__ int wcnt[2][NW];
     __shared__ CpMac mac[kCpMaxLev + 1];   // the cluster and its ancestors, levels lvl..T
-    const int item = blockIdx.x;
-    if (*a.bad || item >= (int)*a.n_items) return;   // whole workgroup
-    const int cl = a.it_cl[item];
+    const CpLevels &L = a.L;
     int lvl, I, J, K;
-    cp_decode(a.L, cl, lvl, I, J, K);
+    cp_decode(L, cl, lvl, I, J, K);
     double cc[3], rr;
-    cp_centre(a.L, lvl, I, J, K, cc, rr);
-    if ((int)threadIdx.x >= lvl && (int)threadIdx.x <= a.L.T) {
-        const int l = threadIdx.x, sh = l - lvl;
-        cp_mac_terms(a.L, l, I >> sh, J >> sh, K >> sh, mac[l]);
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int c0 = a.it_c0[item], nlf = a.it_c1[item] - c0;   // <= kCpChunkLeaves
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int l = 0; l < nlf; ++l) {
-            const int leaf = a.cand[c0 + l];
-            pre[l] = acc;
-            lbeg[l] = a.begin[leaf];
-            acc += a.end[leaf] - a.begin[leaf];
-        }
-        pre[nlf] = acc;
+    cp_centre(L, lvl, I, J, K, cc, rr);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid >= lvl && tid <= L.T) {
+        const int sh = tid - lvl;
+        cp_mac_terms(L, tid, I >> sh, J >> sh, K >> sh, mac[tid]);
     }
     __syncthreads();
-    const int natoms = pre[nlf];
-    float4 *out = a.abuf + a.it_slot[item];
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    int filled = 0;
-    for (int t0 = 0; t0 < natoms; t0 += kBlock) {
-        const int t = t0 + threadIdx.x;
-        bool acc = false;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (t < natoms) {
-            // leaf of candidate t: the last l with pre[l] <= t
-            int l = 0, hi = nlf - 1;
-            while (l < hi) {
-                const int mid = (l + hi + 1) >> 1;
-                if (pre[mid] <= t) l = mid;
-                else hi = mid - 1;
-            }
-            const int i = lbeg[l] + (t - pre[l]);
-            double y[3];
-            atom_pos(a.rec, a.stride_f4, i, y);
-            // well separated from this cluster and from none of its ancestors
-            acc = cp_mac_at(a.L, mac[lvl], y);
-            for (int l = lvl + 1; acc && l <= a.L.T; ++l) acc = !cp_mac_at(a.L, mac[l], y);
-            v.x = (float)(y[0] - cc[0]);
-            v.y = (float)(y[1] - cc[1]);
-            v.z = (float)(y[2] - cc[2]);
-            v.w = a.rec[(size_t)i * a.stride_f4].w;
+    float4 *out = a.abuf + a.slot[cl];
+    uint32_t filled = 0;   // workgroup-uniform
+    const int c0 = (int)a.cand_off[cl], c1 = (int)a.cand_off[cl + 1];
+    for (int cw = c0; cw < c1; cw += NT) {
+        // window of candidate leaves: first atom and atom prefix, in list order
+        const int nw = min(NT, c1 - cw);
+        int sz = 0;
+        if (tid < nw) {
+            const int leaf = a.cand[cw + tid];
+            const int b = a.begin[leaf];
+            beg[tid] = b;
+            sz = a.end[leaf] - b;
         }
-        const uint64_t m = __ballot(acc);
-        if (lane == 0) wcount[wave] = __popcll(m);
+        int run;
+        const int ex = group_excl_scan<NT>(sz, ws, run);
+        if (tid < nw) pre[tid] = ex;
+        if (tid == 0) pre[nw] = run;
         __syncthreads();
-        int base = filled, total = 0;
-        for (int w = 0; w < kBlock / 64; ++w) {
-            if (w < wave) base += wcount[w];
-            total += wcount[w];
+        for (int t0 = 0, par = 0; t0 < run; t0 += NT, par ^= 1) {
+            const int t = t0 + tid;
+            bool acc = false;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (t < run) {
+                int lo = 0, hi = nw - 1;   // last k with pre[k] <= t
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (pre[mid] <= t) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int i = beg[lo] + (t - pre[lo]);
+                double y[3];
+                atom_pos(a.rec, a.stride_f4, i, y);
+                // well separated from this cluster and from none of its ancestors
+                acc = cp_mac_at(L, mac[lvl], y);
+                for (int l = lvl + 1; acc && l <= L.T; ++l) acc = !cp_mac_at(L, mac[l], y);
+                v.x = (float)(y[0] - cc[0]);
+                v.y = (float)(y[1] - cc[1]);
+                v.z = (float)(y[2] - cc[2]);
+                v.w = a.rec[(size_t)i * a.stride_f4].w;
+            }
+            // ordered compaction (two count buffers alternate: one barrier a round)
+            const uint64_t m = __ballot(acc);
+            if (lane == 0) wcnt[par][wave] = __popcll(m);
+            __syncthreads();
+            uint32_t base = 0, total = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const uint32_t c = (uint32_t)wcnt[par][w];
+                base += w < wave ? c : 0u;
+                total += c;
+            }
+            if (acc) out[filled + base + __popcll(m & lt)] = v;
+            filled += total;
         }
-        if (acc) out[base + __popcll(m & lt)] = v;
-        filled += total;
-        __syncthreads();   // wcount is rewritten by the next step
+        __syncthreads();   // the window is read before the next one is written
     }
-    if (threadIdx.x == 0) {
-        a.it_n[item] = (uint32_t)filled;
+    if (tid == 0) {
+        a.n[cl] = filled;
         if (a.work) atomicAdd(a.work, (unsigned long long)filled * (unsigned long long)a.np);
+    }
+}
+
+// Fill pass of the neighbour queries with the work that reads their lists:
+// workgroups [0, qc.nq) query a target cluster and assign its far-field
+// atoms, the rest query a group of level-0 blocks and classify its near
+// field.  The query runs on the first wave; the whole workgroup then reads
+// the list it wrote.
+constexpr int kFillThreads = kClsThreads;
+
+__global__ __launch_bounds__(kFillThreads, 4) void k_cp_fill(CpQueryArgs qc, CpQueryArgs ql,
+                                                         CpAssignArgs aa, CpClassArgs ca)
+{
+    extern __shared__ int stk[];   // [qc.stack_w]
+    if (*qc.bad) return;           // whole workgroup: lists sized too small
+    const int q = blockIdx.x;
+    if (q < qc.nq) {
+        if (threadIdx.x < 64) cp_query(qc, q, stk);
+        __syncthreads();
+        cp_assign_cluster<kFillThreads>(aa, q);
+    } else {
+        if (threadIdx.x < 64) cp_query(ql, q - qc.nq, stk);
+        __syncthreads();
+        cp_classify_group(ca, q - qc.nq);
     }
 }
 
@@ -889,18 +970,35 @@ __global__ __launch_bounds__(kBlock) void k_cp_assign(CpAssignArgs a)
 // are launched heaviest first.
 struct CpSweepArgs {
     CpLevels L;
-    const int *order, *it_cl;
-    const uint32_t *it_slot, *it_n;
+    const int *order;              // items, heaviest first (one workgroup each)
+    const int *it_cl;              // item -> cluster
+    const uint32_t *it_a0, *it_na; // item's first atom in its cluster's run, atoms
+    const uint32_t *slot;          // each cluster's first assigned atom in abuf
     const float4 *abuf;
     int degree, np;
     float yk;
     double kappa;   // Taylor moments of the screened kernel
     double eta;     // Taylor moments of the erf kernel (paper far field)
     int nc;         // components per item and cluster: 2, or 3 with the erf kernel
-    double *part;   // [items][nc][np]
-    const uint32_t *n_items;
+    double *part;   // [items][nc][np]: each item's part of its cluster's far field
+    const uint32_t *n_items;   // items on the device (the launch may have more)
     const int *bad;
 };
+
+// Workgroup's item: its cluster, atom count and first atom.
+struct SweepItem {
+    int item, cl, n;
+    const float4 *at;
+};
+__device__ __forceinline__ SweepItem sweep_item(const CpSweepArgs &a)
+{
+    SweepItem r;
+    r.item = as_const(a.order)[blockIdx.x];
+    r.cl = as_const(a.it_cl)[r.item];
+    r.n = (int)as_const(a.it_na)[r.item];
+    r.at = a.abuf + as_const(a.slot)[r.cl] + as_const(a.it_a0)[r.item];
+    return r;
+}
 
 struct Quad {
     float x, y, z, w;
@@ -912,10 +1010,9 @@ __global__ __launch_bounds__(kBlock) void k_cp_sweep(CpSweepArgs a)
     __shared__ float node[3][kMaxDeg + 1];
     __shared__ float4 stage[2][kBlock];
     if (*a.bad || (int)blockIdx.x >= (int)*a.n_items) return;   // whole workgroup
-    const int item = as_const(a.order)[blockIdx.x];
-    const int cl = as_const(a.it_cl)[item];
-    const int n = (int)as_const(a.it_n)[item];
-    const float4 *at = a.abuf + as_const(a.it_slot)[item];
+    const SweepItem w = sweep_item(a);
+    const int cl = w.cl, item = w.item, n = w.n;
+    const float4 *at = w.at;
     const int n1 = a.degree + 1;
     if (threadIdx.x < 3 * n1) {
         int lvl, I, J, K;
@@ -1013,9 +1110,8 @@ __global__ __launch_bounds__(kSweepThreads) void k_cp_sweep_lines(CpSweepArgs a)
     __shared__ float4 stage[kSweepGroups][2][kBlock];
     __shared__ double red[kSweepGroups - 1][kBlock];
     if (*a.bad || (int)blockIdx.x >= (int)*a.n_items) return;   // whole workgroup
-    const int item = as_const(a.order)[blockIdx.x];
-    const int cl = as_const(a.it_cl)[item];
-    const int n = (int)as_const(a.it_n)[item];
+    const SweepItem w = sweep_item(a);
+    const int cl = w.cl, item = w.item, n = w.n;
     const int n1 = a.degree + 1;
     if (threadIdx.x < 3 * n1) {
         int lvl, I, J, K;
@@ -1032,7 +1128,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_cp_sweep_lines(CpSweepArgs a)
     const int grp = (int)threadIdx.x / kBlock, tl = (int)threadIdx.x % kBlock;
     const int b0 = (int)((long long)n * grp / kSweepGroups);
     const int na = (int)((long long)n * (grp + 1) / kSweepGroups) - b0;
-    const float4 *at = a.abuf + as_const(a.it_slot)[item] + b0;
+    const float4 *at = w.at + b0;
     // chunks per group: the same count in every group (barriers inside)
     const int nchunk = ((n + kSweepGroups - 1) / kSweepGroups + kBlock - 1) / kBlock;
     const int G = (n1 + NI - 1) / NI;
@@ -1192,9 +1288,9 @@ __global__ __launch_bounds__(kBlock) void k_cp_taylor(CpSweepArgs a)
 {
     extern __shared__ double sm[];
     if (*a.bad || (int)blockIdx.x >= (int)*a.n_items) return;   // whole workgroup
-    const int item = as_const(a.order)[blockIdx.x];
-    const int n = (int)as_const(a.it_n)[item];
-    ConstAS<Quad> *at = as_const(reinterpret_cast<const Quad *>(a.abuf + as_const(a.it_slot)[item]));
+    const SweepItem w = sweep_item(a);
+    const int cl = w.cl, item = w.item, n = w.n;
+    ConstAS<Quad> *at = as_const(reinterpret_cast<const Quad *>(w.at));
     const int p = a.degree, n1 = p + 1, nt = tet_off(p + 1);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1300,21 +1396,23 @@ __global__ __launch_bounds__(kBlock) void k_cp_taylor(CpSweepArgs a)
 
 // ----------------------------------------------------------------- downward
 
-// The far field of every level-1 cluster in one launch.  With P_l the sum
-// of the partials of cluster l's work items (in item order), the downward
-// pass is V_T = P_T and V_l = P_l + (Mx (x) My (x) Mz)_l V_{l+1} for
-// l = T-1 .. 1: the parent's far field carried onto the child's proxies.
+// The far field of every level-1 cluster in one launch.  With P_l cluster
+// l's own far field (the sum of its items' parts, in item order), the
+// downward pass is V_T = P_T and V_l = P_l + (Mx (x) My (x) Mz)_l V_{l+1}
+// for l = T-1 .. 1: the parent's far field carried onto the child's proxies.
 // M[k][m] = L^P_m(s^C_k), the parent's interpolant evaluated at the child's
 // proxy points, separably, in FP64; Taylor moments (taylor != 0) take
 // M[k][m] = C(m, k) delta^(m - k) for m >= k, delta = child centre - parent
 // centre: the parent's polynomial re-expanded about the child's centre, again
 // separably.  The rows come from the per-call tables (cp_table_row).
 //
-// One workgroup per level-1 cluster walks its chain of ancestors from the top
-// in LDS and writes V_1 only (the leaves read nothing else).  Each ancestor's
-// V is formed by every one of its level-1 descendants: a few redundant
-// contractions in place of one dependent launch per level.  nc of the ncomp
-// components per pass, as the LDS allows.
+// One workgroup per cluster of level lo walks its chain of ancestors from
+// level hi down in LDS and writes V_lo only.  Two launches: the level-2
+// clusters from the top (each ancestor's V formed by every one of its
+// level-2 descendants: a few redundant contractions in place of one
+// dependent launch per level), then the level-1 clusters from the level-2
+// V (the leaves read nothing else).  nc of the ncomp components per pass, as
+// the LDS allows.
 constexpr int kDownThreads = 512;
 static_assert(3 * (kMaxDeg + 1) * (kMaxDeg + 1) <= 2 * kDownThreads, "two matrix entries per thread");
 
@@ -1346,12 +1444,14 @@ struct CpDownArgs {
     const uint32_t *item_off;      // first work item of each cluster (clusters + 1)
     const int *bad;                // buffers sized too small: do nothing
     const double *part;            // [item][ncomp][np]
-    double *V;                     // [cluster][ncomp][np]; level-1 entries written
+    double *V;                     // [cluster][ncomp][np]; level-lo entries written
+    int lo, hi;                    // one workgroup per level-lo cluster, from level hi down
+    int top_v;                     // level hi's V is final in V (else its items' sum)
 };
 
-// Partials of one cluster's first few work items at this thread's S entries,
-// loaded ahead of the contractions that precede their sum (fewer items for
-// more entries, within the registers of two workgroups per CU).
+// Parts of one cluster's first few items at this thread's S entries, loaded
+// ahead of the contractions that precede their sum (fewer items for more
+// entries, within the registers of two workgroups per CU).
 template <int S>
 struct DownPartials {
     static constexpr int PF = S <= 2 ? 6 : (S == 4 ? 4 : (S == 8 ? 2 : 1));
@@ -1374,7 +1474,7 @@ __device__ __forceinline__ void down_fetch(const CpDownArgs &a, int cl, int e0, 
     }
 }
 
-// Sum of the cluster's partials at entry e (slot j), in item order.
+// Sum of the cluster's parts at entry e (slot j), in item order.
 template <int S>
 __device__ __forceinline__ double down_sum(const CpDownArgs &a, const DownPartials<S> &p, int j,
                                            int e0, int e, int stride)
@@ -1388,14 +1488,14 @@ __device__ __forceinline__ double down_sum(const CpDownArgs &a, const DownPartia
     return s;
 }
 
-// Matrix entry t of the step to level lvl for the level-1 cluster (I1, J1,
-// K1): row of its level-lvl ancestor along axis t / n1^2 (per-call tables).
-__device__ __forceinline__ double down_mrow(const CpDownArgs &a, int lvl, int t, int I1, int J1,
-                                            int K1, int n1)
+// Matrix entry t of the step to level lvl for the level-lo cluster (I0, J0,
+// K0): row of its level-lvl ancestor along axis t / n1^2 (per-call tables).
+__device__ __forceinline__ double down_mrow(const CpDownArgs &a, int lvl, int t, int I0, int J0,
+                                            int K0, int n1)
 {
-    if (lvl < 1 || t >= 3 * n1 * n1) return 0.0;
-    const int sh = lvl - 1, ax = t / (n1 * n1), km = t % (n1 * n1);
-    const int ix = ax == 0 ? I1 >> sh : (ax == 1 ? J1 >> sh : K1 >> sh);
+    if (lvl < a.lo || t >= 3 * n1 * n1) return 0.0;
+    const int sh = lvl - a.lo, ax = t / (n1 * n1), km = t % (n1 * n1);
+    const int ix = ax == 0 ? I0 >> sh : (ax == 1 ? J0 >> sh : K0 >> sh);
     return a.M[(size_t)(a.mrow0[lvl][ax] + ix * n1) * n1 + km];
 }
 
@@ -1411,7 +1511,7 @@ __device__ __forceinline__ double dot_n(const double *row, const double *src, in
 }
 
 // S: entry slots per thread, nc np <= S kDownThreads; N1: degree + 1 when
-// fixed at compile time, else 0.  The partials of each level are fetched
+// fixed at compile time, else 0.  The parts of each level are fetched
 // before the two contractions that precede their sum, and each step's
 // matrix rows one step ahead.
 template <int S, int N1>
@@ -1426,32 +1526,34 @@ __global__ __launch_bounds__(kDownThreads) void k_cp_down_chain(CpDownArgs a)
     double *t1 = src + a.nc * np;     // [nc][np]
     double *t2 = t1 + a.nc * np;      // [nc][np]
     if (*a.bad) return;   // whole workgroup
-    const int q = blockIdx.x;   // level-1 cluster
-    const int I1 = q % L.cx[1], J1 = (q / L.cx[1]) % L.cy[1], K1 = q / (L.cx[1] * L.cy[1]);
+    const int lo = a.lo, hi = a.hi;
+    const int q = blockIdx.x;   // level-lo cluster
+    const int I0 = q % L.cx[lo], J0 = (q / L.cx[lo]) % L.cy[lo], K0 = q / (L.cx[lo] * L.cy[lo]);
     const int tid = threadIdx.x;
     for (int comp0 = 0; comp0 < a.ncomp; comp0 += a.nc) {
         const int ne = min(a.nc, a.ncomp - comp0) * np, e0 = comp0 * np;
         DownPartials<S> p;
-        {
-            const int sh = L.T - 1;
-            down_fetch<S>(a, cp_id(L, L.T, I1 >> sh, J1 >> sh, K1 >> sh), e0, ne, stride, p);
-        }
-        double mr0 = down_mrow(a, L.T - 1, tid, I1, J1, K1, n1);
-        double mr1 = down_mrow(a, L.T - 1, tid + kDownThreads, I1, J1, K1, n1);
+        const int sh_top = hi - lo;
+        const int top = cp_id(L, hi, I0 >> sh_top, J0 >> sh_top, K0 >> sh_top);
+        if (!a.top_v) down_fetch<S>(a, top, e0, ne, stride, p);
+        double mr0 = down_mrow(a, hi - 1, tid, I0, J0, K0, n1);
+        double mr1 = down_mrow(a, hi - 1, tid + kDownThreads, I0, J0, K0, n1);
         __syncthreads();   // the previous pass is done with src
 #pragma unroll
         for (int j = 0; j < S; ++j) {
             const int e = tid + j * kDownThreads;
-            if (e < ne) src[e] = down_sum<S>(a, p, j, e0, e, stride);
+            if (e < ne)
+                src[e] = a.top_v ? a.V[(size_t)top * stride + e0 + e]
+                                 : down_sum<S>(a, p, j, e0, e, stride);
         }
-        for (int lvl = L.T - 1; lvl >= 1; --lvl) {
-            const int sh = lvl - 1;
-            down_fetch<S>(a, cp_id(L, lvl, I1 >> sh, J1 >> sh, K1 >> sh), e0, ne, stride, p);
+        for (int lvl = hi - 1; lvl >= lo; --lvl) {
+            const int sh = lvl - lo;
+            down_fetch<S>(a, cp_id(L, lvl, I0 >> sh, J0 >> sh, K0 >> sh), e0, ne, stride, p);
             __syncthreads();   // src written; the previous step's z pass is done with M
             if (tid < nm) M[tid] = mr0;
             if (tid + kDownThreads < nm) M[tid + kDownThreads] = mr1;
-            mr0 = down_mrow(a, lvl - 1, tid, I1, J1, K1, n1);
-            mr1 = down_mrow(a, lvl - 1, tid + kDownThreads, I1, J1, K1, n1);
+            mr0 = down_mrow(a, lvl - 1, tid, I0, J0, K0, n1);
+            mr1 = down_mrow(a, lvl - 1, tid + kDownThreads, I0, J0, K0, n1);
             __syncthreads();
             // entry e = c np + k, k = (z, y, x) with x fastest; contract x,
             // then y, then z
@@ -1479,8 +1581,8 @@ __global__ __launch_bounds__(kDownThreads) void k_cp_down_chain(CpDownArgs a)
             }
         }
         __syncthreads();
-        const int id1 = cp_id(L, 1, I1, J1, K1);
-        for (int e = tid; e < ne; e += kDownThreads) a.V[(size_t)id1 * stride + e0 + e] = src[e];
+        const int id = cp_id(L, lo, I0, J0, K0);
+        for (int e = tid; e < ne; e += kDownThreads) a.V[(size_t)id * stride + e0 + e] = src[e];
     }
 }
 
@@ -1502,7 +1604,7 @@ struct CpLeafArgs {
     OutParams out;
     AsymParams asym;
     const void *rec;
-    const uint32_t *aoff;      // candidate atoms of each group (prefix; k_cp_classify)
+    const uint32_t *aoff;      // candidate atoms of each group (prefix; cp_classify_group)
     const int *dlist, *slist;  // direct atoms per group / short-range atoms per block
     const uint32_t *nd, *ns;   // their counts
     const int *order;          // block -> level-0 block, heaviest first
@@ -1768,8 +1870,8 @@ uint32_t *pinned_u32(int n)
     return n <= 64 ? p : nullptr;
 }
 
-// Sizes of the list buffers: [0] cluster candidates, [1] far items, [2] leaf
-// candidates, [3] leaf candidate atoms, [4] cluster candidate atoms.
+// Sizes of the list buffers: [0] cluster candidates, [1] unused (0), [2]
+// group candidates, [3] group candidate atoms, [4] cluster candidate atoms.
 struct CpCaps {
     uint32_t c[5];
 };
@@ -1817,7 +1919,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     }
     const int ncl = L.T >= 1 ? L.off[L.T + 1] : 0;
     const int nleaf = L.cx[0] * L.cy[0] * L.cz[0];
-    const int ngrp = cp_groups(L);   // groups of level-0 blocks (k_cp_classify)
+    const int ngrp = cp_groups(L);   // groups of level-0 blocks (cp_classify_group)
     const bool taylor = a.opts->method == RISM_TREECODE_TAYLOR;
     // the paper's Taylor far fields (expansions of 1/d, erf(d/eta)/d and
     // 2 exp(-kappa d)/d), unless the exact-split variant is asked for
@@ -1856,9 +1958,8 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     double rshort = a.asym_on && !paper ? std::sqrt(a.asym.rs2) : 0.0;
     if (a.lj_mode == LJ_CUT) rshort = std::max(rshort, a.rmax_short);
 
-    // queries: clusters (mode 0) and leaves (mode 1), count pass
-    uint32_t *ccnt = ws.get<uint32_t>(ncl + 1), *citems = ws.get<uint32_t>(ncl + 1);
-    uint32_t *cacnt = ws.get<uint32_t>(ncl + 1);
+    // queries: clusters (mode 0) and groups of leaves (mode 1), count pass
+    uint32_t *ccnt = ws.get<uint32_t>(ncl + 1), *cacnt = ws.get<uint32_t>(ncl + 1);
     uint32_t *lcnt = ws.get<uint32_t>(ngrp + 1), *lacnt = ws.get<uint32_t>(ngrp + 1);
     if (ws.status()) return ws.status();
     int dev = 0;
@@ -1902,20 +2003,18 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     }
     {
         // count pass of both query sets (and the tables) in one launch, then
-        // all five scans
+        // the four scans
         PhaseTimer pt(ev, RISM_PHASE_LISTS, s);
         CpQueryArgs qc = qa;   // clusters (none when ncl = 0)
         qc.mode = 0;
         qc.nq = ncl;
         qc.cnt = ccnt;
-        qc.items = citems;
         qc.acnt = cacnt;
         qc.fill = 0;
         CpQueryArgs ql = qa;   // groups of level-0 blocks
         ql.mode = 1;
         ql.nq = ngrp;
         ql.cnt = lcnt;
-        ql.items = nullptr;
         ql.acnt = lacnt;
         ql.fill = 0;
         hipLaunchKernelGGL(k_cp_query, ncl + ngrp + cp_table_blocks(ta), kQueryThreads, qshm, s,
@@ -1931,7 +2030,6 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         };
         if (ncl > 0) {   // (otherwise their totals stay 0)
             add(ccnt, 0, ncl + 1);
-            add(citems, 1, ncl + 1);
             add(cacnt, 4, ncl + 1);
         }
         add(lcnt, 2, ngrp + 1);
@@ -1970,18 +2068,21 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     // Everything after the counts, with buffers of the given capacities.
     auto second_half = [&](const CpCaps &cap) -> int {
         int *ccand = ws.get<int>(cap.c[0] + 1), *lcand = ws.get<int>(cap.c[2] + 1);
-        int *it_cl = ws.get<int>(cap.c[1] + 1), *it_c0 = ws.get<int>(cap.c[1] + 1),
-            *it_c1 = ws.get<int>(cap.c[1] + 1), *it_order = ws.get<int>(cap.c[1] + 1);
-        uint32_t *it_slot = ws.get<uint32_t>(cap.c[1] + 1),
-                 *it_n = ws.get<uint32_t>(cap.c[1] + 1);
+        uint32_t *cl_n = ws.get<uint32_t>(ncl + 1), *item_off = ws.get<uint32_t>(ncl + 1);
+        // far work items: runs of at most kItemAtoms of a cluster's atoms
+        const int max_items = ncl + (int)((cap.c[4] + kItemAtoms - 1) / kItemAtoms);
+        int *it_cl = ws.get<int>(max_items + 1), *it_order = ws.get<int>(max_items + 1);
+        uint32_t *it_a0 = ws.get<uint32_t>(max_items + 1), *it_na = ws.get<uint32_t>(max_items + 1);
+        uint32_t *n_items = ws.get<uint32_t>(1);
+        double *part = ws.get<double>((size_t)(max_items + 1) * nc * np);
         float4 *abuf = ws.get<float4>((size_t)cap.c[4] + 1);
         int *dlist = ws.get<int>(cap.c[3] + 1), *slist = ws.get<int>(8 * (size_t)cap.c[3] + 1);
-        double *part = ws.get<double>((size_t)(cap.c[1] + 1) * nc * np);
         if (ws.status()) return ws.status();
         if (work) hipLaunchKernelGGL(k_fill_u64, 1, 64, 0, s, work, 4);
         qa.bad = bad;
-        // fill pass of both query sets in one launch (with the far work
-        // items), then the near-field classification
+        // fill pass of both query sets in one launch, with the far-field
+        // assignment of every cluster and the near-field classification of
+        // every group; then the launch orders
         {
             PhaseTimer pt(ev, RISM_PHASE_LISTS, s);
             CpQueryArgs qc = qa;
@@ -1989,14 +2090,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             qc.nq = ncl;
             qc.off = ccnt;
             qc.list = ccand;
-            qc.item_off = citems;
-            qc.atom_off = cacnt;
-            qc.it_cl = it_cl;
-            qc.it_c0 = it_c0;
-            qc.it_c1 = it_c1;
-            qc.it_slot = it_slot;
             qc.fill = 1;
-            qc.items = nullptr;
             qc.acnt = nullptr;
             CpQueryArgs ql = qa;
             ql.mode = 1;
@@ -2004,10 +2098,20 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             ql.off = lcnt;
             ql.list = lcand;
             ql.fill = 1;
-            ql.items = nullptr;
             ql.acnt = nullptr;
-            hipLaunchKernelGGL(k_cp_query, ncl + ngrp, kQueryThreads, qshm, s, qc, ql,
-                               CpTabArgs{});
+            CpAssignArgs aa{};
+            aa.L = L;
+            aa.cand_off = ccnt;
+            aa.cand = ccand;
+            aa.begin = t.begin;
+            aa.end = t.end;
+            aa.rec = static_cast<const float4 *>(t.sorted_rec);
+            aa.stride_f4 = stride_f4;
+            aa.slot = cacnt;
+            aa.abuf = abuf;
+            aa.n = cl_n;
+            aa.work = work ? work + 2 : nullptr;
+            aa.np = np;
             CpClassArgs ca{};
             ca.L = L;
             ca.nq = ngrp;
@@ -2024,78 +2128,57 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             ca.nd = nd;
             ca.ns = nsh;
             ca.cost = cost;
-            ca.bad = bad;
-            hipLaunchKernelGGL(k_cp_classify, ngrp, kClsThreads, 0, s, ca);
-        }
-        // the leaves' launch order (with the far work items' when there are any)
-        const OrderJob leaf_order{nleaf, nullptr, cost, nullptr, order};
-        if (!(ncl > 0 && cap.c[1] > 0)) {
-            PhaseTimer pt(ev, RISM_PHASE_LISTS, s);
-            hipLaunchKernelGGL(k_order_by_cost, 1, 1024, 0, s, leaf_order, leaf_order,
-                               (const int *)bad);
+            hipLaunchKernelGGL(k_cp_fill, ncl + ngrp, kFillThreads, qshm, s, qc, ql, aa, ca);
+            const OrderJob leaf_order{nleaf, nullptr, cost, nullptr, order};
+            CpItemArgs ia{};
+            ia.ncl = ncl;
+            ia.n = cl_n;
+            ia.amax = kItemAtoms;
+            ia.item_off = item_off;
+            ia.it_cl = it_cl;
+            ia.it_a0 = it_a0;
+            ia.it_na = it_na;
+            ia.n_items = n_items;
+            const OrderJob item_order{max_items, n_items, it_na, nullptr, it_order};
+            hipLaunchKernelGGL(k_cp_plan, ncl > 0 ? 2 : 1, kPlanThreads, 0, s, leaf_order, ia,
+                               item_order, (const int *)bad);
         }
         RISM_HIP(hipGetLastError());
 
-        // far field into the target proxies, reduction, downward pass
-        if (ncl > 0 && cap.c[1] > 0) {
-            {
-                PhaseTimer pl(ev, RISM_PHASE_LISTS, s);
-                CpAssignArgs aa{};
-                aa.L = L;
-                aa.it_cl = it_cl;
-                aa.it_c0 = it_c0;
-                aa.it_c1 = it_c1;
-                aa.it_slot = it_slot;
-                aa.cand = ccand;
-                aa.begin = t.begin;
-                aa.end = t.end;
-                aa.rec = static_cast<const float4 *>(t.sorted_rec);
-                aa.stride_f4 = stride_f4;
-                aa.abuf = abuf;
-                aa.it_n = it_n;
-                aa.work = work ? work + 2 : nullptr;
-                aa.np = np;
-                aa.n_items = tot + 1;
-                aa.bad = bad;
-                hipLaunchKernelGGL(k_cp_assign, (int)cap.c[1], kBlock, 0, s, aa);
-                const OrderJob item_order{(int)cap.c[1], tot + 1, it_n, nullptr, it_order};
-                hipLaunchKernelGGL(k_order_by_cost, 2, 1024, 0, s, leaf_order, item_order,
-                                   (const int *)bad);
-            }
-            {
-                PhaseTimer pu(ev, RISM_PHASE_UPWARD, s);
-                CpSweepArgs sa{};
-                sa.L = L;
-                sa.order = it_order;
-                sa.it_cl = it_cl;
-                sa.it_slot = it_slot;
-                sa.it_n = it_n;
-                sa.abuf = abuf;
-                sa.degree = deg;
-                sa.np = np;
-                sa.yk = (float)a.asym.yk;
-                sa.kappa = a.asym.kappa;
-                sa.eta = a.asym.eta;
-                sa.nc = nc;
-                sa.part = part;
-                sa.n_items = tot + 1;
-                sa.bad = bad;
-                if (taylor) {
-                    const size_t tshm = cp_taylor_lds(deg, a.asym_on, paper);
-                    if (a.asym_on && paper)
-                        hipLaunchKernelGGL((k_cp_taylor<true, true>), (int)cap.c[1], kBlock, tshm,
-                                           s, sa);
-                    else if (a.asym_on)
-                        hipLaunchKernelGGL((k_cp_taylor<true, false>), (int)cap.c[1], kBlock, tshm,
-                                           s, sa);
-                    else
-                        hipLaunchKernelGGL((k_cp_taylor<false, false>), (int)cap.c[1], kBlock,
-                                           tshm, s, sa);
-                } else if (a.asym_on) {
-                    launch_sweep<true>((int)cap.c[1], np, deg, sa, s);
-                } else {
-                    launch_sweep<false>((int)cap.c[1], np, deg, sa, s);
-                }
+        // far field of every item into its part of its cluster's proxies
+        // (heaviest first), then the downward pass
+        if (ncl > 0) {
+            PhaseTimer pu(ev, RISM_PHASE_UPWARD, s);
+            CpSweepArgs sa{};
+            sa.L = L;
+            sa.order = it_order;
+            sa.it_cl = it_cl;
+            sa.it_a0 = it_a0;
+            sa.it_na = it_na;
+            sa.slot = cacnt;
+            sa.abuf = abuf;
+            sa.degree = deg;
+            sa.np = np;
+            sa.yk = (float)a.asym.yk;
+            sa.kappa = a.asym.kappa;
+            sa.eta = a.asym.eta;
+            sa.nc = nc;
+            sa.part = part;
+            sa.n_items = n_items;
+            sa.bad = bad;
+            if (taylor) {
+                const size_t tshm = cp_taylor_lds(deg, a.asym_on, paper);
+                if (a.asym_on && paper)
+                    hipLaunchKernelGGL((k_cp_taylor<true, true>), max_items, kBlock, tshm, s, sa);
+                else if (a.asym_on)
+                    hipLaunchKernelGGL((k_cp_taylor<true, false>), max_items, kBlock, tshm, s, sa);
+                else
+                    hipLaunchKernelGGL((k_cp_taylor<false, false>), max_items, kBlock, tshm, s,
+                                       sa);
+            } else if (a.asym_on) {
+                launch_sweep<true>(max_items, np, deg, sa, s);
+            } else {
+                launch_sweep<false>(max_items, np, deg, sa, s);
             }
         }
         if (ncl > 0) {
@@ -2108,23 +2191,34 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             da.M = ta.M;
             for (int l = 0; l <= kCpMaxLev; ++l)
                 for (int ax = 0; ax < 3; ++ax) da.mrow0[l][ax] = ta.mrow0[l][ax];
-            da.item_off = citems;
+            da.item_off = item_off;
             da.bad = bad;
             da.part = part;
             da.V = V;
-            const int ng1 = L.cx[1] * L.cy[1] * L.cz[1];
             const size_t dshm = cp_down_lds(deg, down_nc);
             const int slots = cp_down_slots(deg, down_nc);
-            if (deg == 8 && slots == 4)   // the usual degree, two components
-                hipLaunchKernelGGL((k_cp_down_chain<4, 9>), ng1, kDownThreads, dshm, s, da);
-            else
-                switch (slots) {
-                case 1: hipLaunchKernelGGL((k_cp_down_chain<1, 0>), ng1, kDownThreads, dshm, s, da); break;
-                case 2: hipLaunchKernelGGL((k_cp_down_chain<2, 0>), ng1, kDownThreads, dshm, s, da); break;
-                case 4: hipLaunchKernelGGL((k_cp_down_chain<4, 0>), ng1, kDownThreads, dshm, s, da); break;
-                case 8: hipLaunchKernelGGL((k_cp_down_chain<8, 0>), ng1, kDownThreads, dshm, s, da); break;
-                default: hipLaunchKernelGGL((k_cp_down_chain<16, 0>), ng1, kDownThreads, dshm, s, da); break;
-                }
+            auto chain = [&](int lo, int hi, int top_v) {
+                da.lo = lo;
+                da.hi = hi;
+                da.top_v = top_v;
+                const int ng = L.cx[lo] * L.cy[lo] * L.cz[lo];
+                if (deg == 8 && slots == 4)   // the usual degree, two components
+                    hipLaunchKernelGGL((k_cp_down_chain<4, 9>), ng, kDownThreads, dshm, s, da);
+                else
+                    switch (slots) {
+                    case 1: hipLaunchKernelGGL((k_cp_down_chain<1, 0>), ng, kDownThreads, dshm, s, da); break;
+                    case 2: hipLaunchKernelGGL((k_cp_down_chain<2, 0>), ng, kDownThreads, dshm, s, da); break;
+                    case 4: hipLaunchKernelGGL((k_cp_down_chain<4, 0>), ng, kDownThreads, dshm, s, da); break;
+                    case 8: hipLaunchKernelGGL((k_cp_down_chain<8, 0>), ng, kDownThreads, dshm, s, da); break;
+                    default: hipLaunchKernelGGL((k_cp_down_chain<16, 0>), ng, kDownThreads, dshm, s, da); break;
+                    }
+            };
+            if (L.T >= 3) {
+                chain(2, L.T, 0);   // V_2 from the top
+                chain(1, 2, 1);     // V_1 from V_2
+            } else {
+                chain(1, L.T, 0);
+            }
         }
         RISM_HIP(hipGetLastError());
 
