@@ -819,9 +819,16 @@ __device__ __forceinline__ void cp_make_items(const CpItemArgs &a)
 
 // The launch plan after the lists: workgroup 0 orders the level-0 blocks;
 // workgroup 1 (with clusters) forms the far work items and orders them.
+// Workgroup 0 first copies the call's nflags flag words to host_flags
+// (mapped pinned host memory), which the host reads after the call's last
+// kernel, without a copy of its own.
 __global__ __launch_bounds__(kPlanThreads) void k_cp_plan(OrderJob leaves, CpItemArgs items,
-                                                         OrderJob item_order, const int *bad)
+                                                         OrderJob item_order, const int *bad,
+                                                         const uint32_t *flags,
+                                                         uint32_t *host_flags, int nflags)
 {
+    if (blockIdx.x == 0 && host_flags && (int)threadIdx.x < nflags)
+        host_flags[threadIdx.x] = flags[threadIdx.x];
     if (*bad) return;
     if (blockIdx.x == 0) {
         order_by_cost(leaves);
@@ -1609,7 +1616,7 @@ struct CpLeafArgs {
     const uint32_t *nd, *ns;   // their counts
     const int *order;          // block -> level-0 block, heaviest first
     const int *bad;            // lists sized too small: do nothing
-    const double *V;           // proxy values (Taylor: moments) of level >= 1 clusters
+    const double *V;           // proxy values (Taylor: moments) of level-1 clusters
     const double *Lg;          // level-1 basis rows per grid coordinate (per-call tables)
     int lrow0[3];              // first row of each axis in Lg
     int degree, np;
@@ -1870,6 +1877,9 @@ uint32_t *pinned_u32(int n)
     return n <= 64 ? p : nullptr;
 }
 
+// Flag words of a cluster-particle call (layout at their allocation).
+constexpr int kFlagWords = 10;
+
 // Sizes of the list buffers: [0] cluster candidates, [1] unused (0), [2]
 // group candidates, [3] group candidate atoms, [4] cluster candidate atoms.
 struct CpCaps {
@@ -1935,7 +1945,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     // [0..4] totals as in CpCaps, [5] query stack overflow, [6] capacity
     // check failed, [8..9] the input check's flags: one block, read back with
     // one copy; the tree build clears [0..6]
-    uint32_t *flags = ws.get<uint32_t>(10);
+    uint32_t *flags = ws.get<uint32_t>(kFlagWords);
     if (ws.status()) return ws.status();
     uint32_t *tot = flags;
     int *overflow = reinterpret_cast<int *>(flags + 5);
@@ -2065,6 +2075,14 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     double *V = ws.get<double>((size_t)(ncl + 1) * nc * np);
     if (ws.status()) return ws.status();
 
+    // totals and flags read back at the end of a pass: [0..4] counts as in
+    // CpCaps, [5] query stack overflow, [6] capacity check failed, [8..9] the
+    // input check's flags (when deferred to here)
+    uint32_t *hres = pinned_u32(kFlagWords);
+    if (!hres) {
+        set_error("treecode_cp: pinned host buffer allocation failed");
+        return RISM_E_HIP;
+    }
     // Everything after the counts, with buffers of the given capacities.
     auto second_half = [&](const CpCaps &cap) -> int {
         int *ccand = ws.get<int>(cap.c[0] + 1), *lcand = ws.get<int>(cap.c[2] + 1);
@@ -2141,7 +2159,8 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             ia.n_items = n_items;
             const OrderJob item_order{max_items, n_items, it_na, nullptr, it_order};
             hipLaunchKernelGGL(k_cp_plan, ncl > 0 ? 2 : 1, kPlanThreads, 0, s, leaf_order, ia,
-                               item_order, (const int *)bad);
+                               item_order, (const int *)bad, (const uint32_t *)flags, hres,
+                               kFlagWords);
         }
         RISM_HIP(hipGetLastError());
 
@@ -2259,16 +2278,11 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         return RISM_OK;
     };
 
-    // totals and flags read back at the end of a pass: [0..4] counts as in
-    // CpCaps, [5] query stack overflow, [6] capacity check failed, [8..9] the
-    // input check's flags (when deferred to here)
-    uint32_t *hres = pinned_u32(10);
-    if (!hres) {
-        set_error("treecode_cp: pinned host buffer allocation failed");
-        return RISM_E_HIP;
-    }
-    auto read_back = [&]() -> int {
-        RISM_HIP(hipMemcpyAsync(hres, flags, 10 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    // copied: the flags reached hres through k_cp_plan (a full pass)
+    auto read_back = [&](bool copied) -> int {
+        if (!copied)
+            RISM_HIP(hipMemcpyAsync(hres, flags, kFlagWords * sizeof(uint32_t),
+                                    hipMemcpyDeviceToHost, s));
         RISM_HIP(hipStreamSynchronize(s));
         if (a.stage_err && (hres[8] || hres[9])) {
             set_error(hres[8] ? "non-finite atom input or negative sigma/eps"
@@ -2286,10 +2300,10 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     if (have) {
         // speculative pass with the cached capacities (checked by the scans)
         if ((rc = second_half(cached))) return rc;
-        if ((rc = read_back())) return rc;
+        if ((rc = read_back(true))) return rc;
         done = hres[6] == 0;
     } else {
-        if ((rc = read_back())) return rc;
+        if ((rc = read_back(false))) return rc;
     }
     if (!done) {
         // exact capacities from the counts just read
