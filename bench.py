@@ -239,12 +239,14 @@ def grid_errors(api, x, ref, mask=None):
 
 
 def frontier(args, api, W):
-    """Error/time frontier of the cluster-particle treecode on the workload
+    """Error/time frontier of the cluster-particle treecode (interpolation, or
+    the Taylor variant with --method treecode_taylor) on the workload
     (default: 14,000 atoms on 256^3): for theta x degree, the time per
     initialisation and the rel-L2 of every output grid against the GPU FP64
     direct sum with the same 9 A cut-off."""
     import torch
     wl = getattr(W, args.workload if "--workload" in sys.argv else "tubulin_14000")()
+    method = args.method if args.method == "treecode_taylor" else "treecode_cp"
     sol, st, g = wl.solute, wl.sites, wl.grid
     eta, kap, beta, diel = W.ETA, W.debye_kappa(), W.beta(), W.DIELECTRIC
     dev = torch.device("cuda:0")
@@ -268,7 +270,7 @@ def frontier(args, api, W):
               for th in (float(v) for v in args.thetas.split(","))
               for dg in (int(v) for v in args.degrees.split(","))]
     for th, dg, be in combos:
-        o = api.Opts(method="treecode_cp", out_dtype="f32", lj_cutoff=args.lj_cutoff,
+        o = api.Opts(method=method, out_dtype="f32", lj_cutoff=args.lj_cutoff,
                      theta=th, degree=dg, batch_edge=be)
         for _ in range(2):
             api.initialize(xyz, q, s, e, sites, grid, o, eta, kap, beta, diel, outs=outs)
@@ -289,7 +291,8 @@ def frontier(args, api, W):
               f"{worst:.2e}", file=sys.stderr, flush=True)
     ok = [r for r in rows if r["meets_1e-6"]]
     best = min(ok, key=lambda r: r["init_time_s"]) if ok else None
-    print(json.dumps({"frontier": rows, "workload": wl.name, "atoms": sol.n,
+    print(json.dumps({"frontier": rows, "method": method, "workload": wl.name,
+                      "atoms": sol.n,
                       "grid": [int(v) for v in g.dims], "lj_cutoff_A": args.lj_cutoff,
                       "fp64_direct_s": t64,
                       "fastest_meeting_1e-6": None if best is None else
@@ -341,6 +344,32 @@ def main():
             step(o)
         torch.cuda.synchronize()
         return 1e3 * (time.perf_counter() - t0) / steps
+
+    # FP64 direct reference first: it is the comparison of the metric and the
+    # accuracy reference, and its ~50 ms of GPU work also brings the clocks up
+    # before the warm-up steps
+    f64 = None
+    if not args.no_f64 and not big:
+        o64 = api.Opts(method="direct_f64", out_dtype="f64", lj_cutoff=args.lj_cutoff,
+                       device_check=not args.no_device_check)
+        refs = (torch.empty((st.n,) + shp, device=dev, dtype=torch.float64),
+                torch.empty((st.n,) + shp, device=dev, dtype=torch.float64),
+                torch.empty((ni,) + shp, device=dev, dtype=torch.float64) if ni else None)
+        api.initialize(xyz, q, s, e, sites, grid, o64, eta, kap, beta, diel, outs=refs)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            api.initialize(xyz, q, s, e, sites, grid, o64, eta, kap, beta, diel, outs=refs)
+        torch.cuda.synchronize()
+        t64 = (time.perf_counter() - t0) / reps
+        # its kernel alone (HIP events on the call's stream)
+        api.phase_times()
+        api.initialize(xyz, q, s, e, sites, grid, api.Opts(**{**o64.__dict__,
+                                                             "phase_events": True}),
+                       eta, kap, beta, diel, outs=refs)
+        ph64 = api.phase_times()
+        f64 = (o64, refs, t64, ph64["direct_f64"][0] / ph64["direct_f64"][1])
 
     for _ in range(args.warmup):
         step(opts)
@@ -444,27 +473,8 @@ def main():
                               "traffic": None}
 
     # FP64 direct: the comparison of the metric, and the accuracy reference
-    if not args.no_f64 and not big:
-        o64 = api.Opts(method="direct_f64", out_dtype="f64", lj_cutoff=args.lj_cutoff,
-                       device_check=not args.no_device_check)
-        refs = (torch.empty((st.n,) + shp, device=dev, dtype=torch.float64),
-                torch.empty((st.n,) + shp, device=dev, dtype=torch.float64),
-                torch.empty((ni,) + shp, device=dev, dtype=torch.float64) if ni else None)
-        api.initialize(xyz, q, s, e, sites, grid, o64, eta, kap, beta, diel, outs=refs)
-        torch.cuda.synchronize()
-        reps = 3
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            api.initialize(xyz, q, s, e, sites, grid, o64, eta, kap, beta, diel, outs=refs)
-        torch.cuda.synchronize()
-        t64 = (time.perf_counter() - t0) / reps
-        # its kernel alone (HIP events on the call's stream)
-        api.phase_times()
-        api.initialize(xyz, q, s, e, sites, grid, api.Opts(**{**o64.__dict__,
-                                                             "phase_events": True}),
-                       eta, kap, beta, diel, outs=refs)
-        ph64 = api.phase_times()
-        k64_ms = ph64["direct_f64"][0] / ph64["direct_f64"][1]
+    if f64 is not None:
+        o64, refs, t64, k64_ms = f64
         fl64 = flops_per_pair_direct_f64(st.n) * n * m
         ach64 = fl64 / (k64_ms * 1e-3) / 1e12
         step(opts)
@@ -500,6 +510,7 @@ def main():
             "points_away_from_atoms": int(mask.sum()),
             "u_coulomb_only": parts["coulomb"], "u_lj_only": parts["lj"]}
         del refs, mask
+        f64 = None
 
     if big:
         # no FP64 direct sum at this size (1.2e14 pairs): the oracle on

@@ -555,6 +555,7 @@ struct CpClassArgs {
     const uint32_t *aoff;      // candidate atoms of each group (prefix)
     int *dlist, *slist;
     uint32_t *nd;              // direct atoms per group
+    uint32_t *on_grid;         // per group: 1 if a direct atom sits on a grid point
     uint32_t *ns;              // short-range atoms per level-0 block
     uint32_t *cost;            // per level-0 block: its direct and short-range atoms
 };
@@ -597,6 +598,7 @@ __device__ __forceinline__ void cp_classify_group(const CpClassArgs &a, int g)
     __shared__ CpMac mac[kCpMaxLev + 1];   // the group's ancestors, levels 1..T
     __shared__ double cbox[8][6];          // its blocks' boxes (empty if absent)
     __shared__ int cleaf[8];               // their ids (-1 if absent)
+    __shared__ int on_any;                 // a direct atom sits on a grid point
     const CpLevels &L = a.L;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int I1 = 0, J1 = 0, K1 = 0;
@@ -620,6 +622,7 @@ __device__ __forceinline__ void cp_classify_group(const CpClassArgs &a, int g)
         }
         cleaf[tid] = in ? (K * L.cy[0] + J) * L.cx[0] + I : -1;
     }
+    if (tid == 0) on_any = 0;
     __syncthreads();
     const double rs2 = a.rshort * a.rshort;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -665,6 +668,7 @@ __device__ __forceinline__ void cp_classify_group(const CpClassArgs &a, int g)
                     }
                 if (lvl == 0) {
                     cls = 1u;
+                    if (a.rec[(size_t)i * a.stride_f4 + 1].w != 0.f) on_any = 1;   // on_grid
                 } else {
 #pragma unroll
                     for (int c = 0; c < 8; ++c) {
@@ -706,7 +710,10 @@ __device__ __forceinline__ void cp_classify_group(const CpClassArgs &a, int g)
         }
         __syncthreads();   // the window is read before the next one is written
     }
-    if (tid == 0) a.nd[g] = nl[0];
+    if (tid == 0) {
+        a.nd[g] = nl[0];
+        a.on_grid[g] = on_any;   // set before the last barrier of the window loop
+    }
     if (tid < 8 && cleaf[tid] >= 0) {
         uint32_t nsc = 0;
 #pragma unroll
@@ -725,6 +732,9 @@ constexpr int kPlanThreads = 1024;
 // Atoms per far work item at most: a cluster's assigned atoms are swept in
 // runs of this many, one workgroup each (kSweepGroups ranges of kBlock).
 constexpr int kItemAtoms = 1024;
+// The Taylor sweep takes one atom per wave at a time (four waves), through
+// recurrences of dependent steps: runs of 64 atoms give it more workgroups.
+constexpr int kTaylorItemAtoms = 64;
 __device__ __forceinline__ int cost_class(uint32_t c)
 {
     return c == 0 ? 0 : 32 - __clz(c);
@@ -827,8 +837,13 @@ __global__ __launch_bounds__(kPlanThreads) void k_cp_plan(OrderJob leaves, CpIte
                                                          const uint32_t *flags,
                                                          uint32_t *host_flags, int nflags)
 {
-    if (blockIdx.x == 0 && host_flags && (int)threadIdx.x < nflags)
-        host_flags[threadIdx.x] = flags[threadIdx.x];
+    if (blockIdx.x == 0 && host_flags && (int)threadIdx.x < nflags) {
+        // system-scope stores into coherent host memory, complete before the
+        // wave ends: the event the host waits on needs no cache write-back
+        __hip_atomic_store(&host_flags[threadIdx.x], flags[threadIdx.x], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+        __builtin_amdgcn_s_waitcnt(0);
+    }
     if (*bad) return;
     if (blockIdx.x == 0) {
         order_by_cost(leaves);
@@ -1593,6 +1608,11 @@ __global__ __launch_bounds__(kDownThreads) void k_cp_down_chain(CpDownArgs a)
     }
 }
 
+// Above this many atoms the downward pass takes one launch per level: each
+// workgroup of a chain sums the items of every ancestor again, and a large
+// solute gives the top clusters up to n / kItemAtoms items each.
+constexpr int64_t kChainMaxAtoms = 32768;
+
 // Entry slots per thread of the downward kernel for nc components of degree
 // `degree`: 1, 2, 4, 8 or 16 (enough for every degree the LDS admits).
 inline int cp_down_slots(int degree, int nc)
@@ -1614,6 +1634,7 @@ struct CpLeafArgs {
     const uint32_t *aoff;      // candidate atoms of each group (prefix; cp_classify_group)
     const int *dlist, *slist;  // direct atoms per group / short-range atoms per block
     const uint32_t *nd, *ns;   // their counts
+    const uint32_t *on_grid;   // per group: a direct atom sits on a grid point
     const int *order;          // block -> level-0 block, heaviest first
     const int *bad;            // lists sized too small: do nothing
     const double *V;           // proxy values (Taylor: moments) of level-1 clusters
@@ -1664,16 +1685,51 @@ inline size_t cp_leaf_lds(int B, int degree, bool asym, bool paper, size_t rec_b
     return cp_leaf_head(B, degree, asym, paper) * sizeof(double) + kLeafStage * rec_bytes;
 }
 
-// The atoms of one index list against this thread's point, flushed every
-// 2 kAtomPad atoms.  The workgroup copies the records to LDS kLeafStage at a
-// time (one per thread), and every pair reads its atom's fields from there
-// into vector registers: a vector instruction takes one scalar operand at
-// most, so with the fields in scalar registers each site's
-// fma(A, r^-6, -B) would need a move of B first.  Every thread of the
-// workgroup calls this with the same list (barriers inside).
+// Staged atoms [s0, s1) against this thread's point, into fresh partial sums.
+template <int NS, int LJM, bool ASYM, bool EXACT, bool FULL, bool GUARD>
+__device__ __forceinline__ PairAcc<NS> leaf_group(const AtomF32<NS> *stg, int s0, int s1,
+                                                  const GridPt &gp, const PairConst &kc,
+                                                  const float4 *tab, bool &hit)
+{
+    PairAcc<NS> p;
+    p.zero();
+#pragma unroll 1
+    for (int s = s0; s < s1; ++s)
+        pair_eval<NS, LJM, ASYM, EXACT, FULL, GUARD>(stg[s], gp, kc, tab, p, hit);
+    return p;
+}
+
+// The staged atoms [0, m) against this thread's point, flushed every
+// 2 kAtomPad atoms.  guard (full pairs): some staged atom sits on a grid
+// point.  The choice is made per group of atoms, so that the running sums
+// stay outside the two versions of the loop.
+template <int NS, int LJM, bool ASYM, bool EXACT, bool FULL>
+__device__ __forceinline__ void leaf_chunk(const AtomF32<NS> *stg, int m, bool guard,
+                                           const GridPt &gp, const PairConst &kc,
+                                           const float4 *tab, PointAcc<NS> &acc)
+{
+    for (int s0 = 0; s0 < m; s0 += 2 * kAtomPad) {
+        const int s1 = min(s0 + 2 * kAtomPad, m);
+        const PairAcc<NS> p =
+            !FULL || guard
+                ? leaf_group<NS, LJM, ASYM, EXACT, FULL, true>(stg, s0, s1, gp, kc, tab, acc.hit)
+                : leaf_group<NS, LJM, ASYM, EXACT, FULL, false>(stg, s0, s1, gp, kc, tab,
+                                                                acc.hit);
+        acc.template flush<LJM != LJ_NONE, ASYM>(p);
+    }
+}
+
+// The atoms of one index list against this thread's point.  The workgroup
+// copies the records to LDS kLeafStage at a time (one per thread), and every
+// pair reads its atom's fields from there into vector registers: a vector
+// instruction takes one scalar operand at most, so with the fields in scalar
+// registers each site's fma(A, r^-6, -B) would need a move of B first.
+// guard: the list holds an atom that sits on a grid point (full pairs only;
+// without one the pair loop leaves out the coincidence handling).  Every
+// thread of the workgroup calls this with the same list (barriers inside).
 template <int NS, int LJM, bool ASYM, bool EXACT, bool FULL, int NT>
 __device__ __forceinline__ void leaf_atoms(const AtomF32<NS> *rec, ConstAS<int> *il, int cnt,
-                                           AtomF32<NS> *stg, const GridPt &gp,
+                                           bool guard, AtomF32<NS> *stg, const GridPt &gp,
                                            const PairConst &kc, const float4 *tab,
                                            PointAcc<NS> &acc)
 {
@@ -1682,15 +1738,7 @@ __device__ __forceinline__ void leaf_atoms(const AtomF32<NS> *rec, ConstAS<int> 
         __syncthreads();   // every wave is done with the previous chunk
         for (int t = threadIdx.x; t < m; t += NT) stg[t] = rec[il[c0 + t]];
         __syncthreads();
-        for (int s0 = 0; s0 < m; s0 += 2 * kAtomPad) {
-            PairAcc<NS> p;
-            p.zero();
-            const int s1 = min(s0 + 2 * kAtomPad, m);
-#pragma unroll 1
-            for (int s = s0; s < s1; ++s)
-                pair_eval<NS, LJM, ASYM, EXACT, FULL>(stg[s], gp, kc, tab, p, acc.hit);
-            acc.template flush<LJM != LJ_NONE, ASYM>(p);
-        }
+        leaf_chunk<NS, LJM, ASYM, EXACT, FULL>(stg, m, guard, gp, kc, tab, acc);
     }
 }
 
@@ -1703,7 +1751,8 @@ __device__ __forceinline__ void leaf_atoms(const AtomF32<NS> *rec, ConstAS<int> 
 //
 // LDS: [smeared table (ASYM)] [T2 per component: n1 x B x B] [Lb: 3 x B x n1]
 //      [Vs (np)] [T1 (n1 x n1 x B)] [atom chunk: kLeafStage records]
-template <int NS, int LJM, bool ASYM, int B>
+// N1: degree + 1 when fixed at compile time (the contractions unrolled), else 0.
+template <int NS, int LJM, bool ASYM, int B, int N1>
 __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
 {
     using S = LeafShape<B>;
@@ -1711,12 +1760,12 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
     const bool paper = ASYM && a.paper;
     const int NCOMP = cp_leaf_ncomp(ASYM, paper);
     extern __shared__ double sm[];
-    const int n1 = a.degree + 1;
+    const int n1 = N1 > 0 ? N1 : a.degree + 1, np = N1 > 0 ? N1 * N1 * N1 : a.np;
     float4 *tab = reinterpret_cast<float4 *>(sm);
     double *T2 = sm + (ASYM ? 4 * kSmearIntervals : 0);   // [NCOMP][n1][B][B]
     double *Lb = T2 + NCOMP * n1 * B * B;                  // [3][B][n1]
     double *Vs = Lb + 3 * B * n1;                          // [np]
-    double *T1 = Vs + a.np;                                // [n1][n1][B]
+    double *T1 = Vs + np;                                  // [n1][n1][B]
     AtomF32<NS> *stg =
         reinterpret_cast<AtomF32<NS> *>(sm + cp_leaf_head(B, a.degree, ASYM, paper));
     if (*a.bad) return;   // whole workgroup
@@ -1733,6 +1782,7 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
     ConstAS<int> *dl = as_const(a.dlist + base);
     ConstAS<int> *sl = as_const(a.slist + 8 * (size_t)base + (size_t)child * na);
     const int ndir = (int)as_const(a.nd)[grp], nsh = (int)as_const(a.ns)[q];
+    const bool dguard = as_const(a.on_grid)[grp] != 0;
     if (ASYM)
         for (int i = threadIdx.x; i < 2 * kSmearIntervals; i += NT) tab[i] = a.asym.tab[i];
 
@@ -1748,8 +1798,8 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
         const int a1 = cp_id(L, 1, I >> 1, J >> 1, K >> 1);
         for (int comp = 0; comp < NCOMP; ++comp) {
             __syncthreads();
-            for (int k = threadIdx.x; k < a.np; k += NT)
-                Vs[k] = a.V[((size_t)a1 * a.ncomp + comp) * a.np + k];
+            for (int k = threadIdx.x; k < np; k += NT)
+                Vs[k] = a.V[((size_t)a1 * a.ncomp + comp) * np + k];
             __syncthreads();
             // T1[k1][k2][z] = sum_k3 V[k3][k2][k1] Lz[z][k3]
             for (int t = threadIdx.x; t < n1 * n1 * B; t += NT) {
@@ -1809,17 +1859,23 @@ __global__ __launch_bounds__(LeafShape<B>::threads) void k_cp_leaf(CpLeafArgs a)
         // short-range atoms (far field from the clusters): LJ, and for the
         // exact-split far fields the smeared kernels' remainders
         if (g.exact) {
-            leaf_atoms<NS, LJM, ASYM, true, true, NT>(grec, dl, ndir, stg, gp, kc, tab, acc);
+            leaf_atoms<NS, LJM, ASYM, true, true, NT>(grec, dl, ndir, dguard,
+                                                      stg, gp, kc, tab, acc);
             if (ASYM && !paper)
-                leaf_atoms<NS, LJM, ASYM, true, false, NT>(grec, sl, nsh, stg, gp, kc, tab, acc);
+                leaf_atoms<NS, LJM, ASYM, true, false, NT>(grec, sl, nsh, true,
+                                                           stg, gp, kc, tab, acc);
             else if (LJM != LJ_NONE)
-                leaf_atoms<NS, LJM, false, true, false, NT>(grec, sl, nsh, stg, gp, kc, tab, acc);
+                leaf_atoms<NS, LJM, false, true, false, NT>(grec, sl, nsh, true,
+                                                            stg, gp, kc, tab, acc);
         } else {
-            leaf_atoms<NS, LJM, ASYM, false, true, NT>(grec, dl, ndir, stg, gp, kc, tab, acc);
+            leaf_atoms<NS, LJM, ASYM, false, true, NT>(grec, dl, ndir, dguard,
+                                                       stg, gp, kc, tab, acc);
             if (ASYM && !paper)
-                leaf_atoms<NS, LJM, ASYM, false, false, NT>(grec, sl, nsh, stg, gp, kc, tab, acc);
+                leaf_atoms<NS, LJM, ASYM, false, false, NT>(grec, sl, nsh, true,
+                                                            stg, gp, kc, tab, acc);
             else if (LJM != LJ_NONE)
-                leaf_atoms<NS, LJM, false, false, false, NT>(grec, sl, nsh, stg, gp, kc, tab, acc);
+                leaf_atoms<NS, LJM, false, false, false, NT>(grec, sl, nsh, true,
+                                                             stg, gp, kc, tab, acc);
         }
 
         if (valid) {
@@ -1833,11 +1889,17 @@ template <int NS, int LJM, bool ASYM>
 void launch_leaf_b(int B, int nleaf, size_t shm, const CpLeafArgs &a, hipStream_t s)
 {
     if (B == 4)
-        hipLaunchKernelGGL((k_cp_leaf<NS, LJM, ASYM, 4>), nleaf, LeafShape<4>::threads, shm, s, a);
+        hipLaunchKernelGGL((k_cp_leaf<NS, LJM, ASYM, 4, 0>), nleaf, LeafShape<4>::threads, shm, s,
+                           a);
+    else if (B == 8 && a.degree == 8)   // the usual batch edge and degree
+        hipLaunchKernelGGL((k_cp_leaf<NS, LJM, ASYM, 8, 9>), nleaf, LeafShape<8>::threads, shm, s,
+                           a);
     else if (B == 8)
-        hipLaunchKernelGGL((k_cp_leaf<NS, LJM, ASYM, 8>), nleaf, LeafShape<8>::threads, shm, s, a);
+        hipLaunchKernelGGL((k_cp_leaf<NS, LJM, ASYM, 8, 0>), nleaf, LeafShape<8>::threads, shm, s,
+                           a);
     else
-        hipLaunchKernelGGL((k_cp_leaf<NS, LJM, ASYM, 16>), nleaf, LeafShape<16>::threads, shm, s, a);
+        hipLaunchKernelGGL((k_cp_leaf<NS, LJM, ASYM, 16, 0>), nleaf, LeafShape<16>::threads, shm,
+                           s, a);
 }
 
 template <int NS>
@@ -1868,17 +1930,33 @@ __global__ void k_fill_u64(unsigned long long *p, int n)
     if (i < n) p[i] = 0ull;
 }
 
-// Pinned host staging for the small end-of-call read-back.
+// Pinned, coherent host memory for the flag words read at the end of a pass.
 uint32_t *pinned_u32(int n)
 {
     static thread_local uint32_t *p = nullptr;
-    if (!p && hipHostMalloc((void **)&p, 64 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
+    if (!p && hipHostMalloc((void **)&p, 64 * sizeof(uint32_t), hipHostMallocCoherent) != hipSuccess)
         p = nullptr;
     return n <= 64 ? p : nullptr;
 }
 
 // Flag words of a cluster-particle call (layout at their allocation).
 constexpr int kFlagWords = 10;
+
+// Event recorded after the plan kernel, which copies the flag words to host
+// memory: the host waits for it, and the far sweep, the downward pass and the
+// leaves keep running after the call returns.  One per device and host thread.
+// Without the system-scope fence: the flags reach host memory through the
+// plan kernel's own system-scope stores.
+constexpr int kMaxEventDevices = 64;
+hipEvent_t flags_event(int dev)
+{
+    static thread_local hipEvent_t ev[kMaxEventDevices] = {};
+    if (dev < 0 || dev >= kMaxEventDevices) return nullptr;
+    if (!ev[dev] && hipEventCreateWithFlags(&ev[dev], hipEventDisableTiming |
+                                                          hipEventDisableSystemFence) != hipSuccess)
+        ev[dev] = nullptr;
+    return ev[dev];
+}
 
 // Sizes of the list buffers: [0] cluster candidates, [1] unused (0), [2]
 // group candidates, [3] group candidate atoms, [4] cluster candidate atoms.
@@ -1934,6 +2012,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     // the paper's Taylor far fields (expansions of 1/d, erf(d/eta)/d and
     // 2 exp(-kappa d)/d), unless the exact-split variant is asked for
     const bool paper = taylor && !(a.opts->flags & RISM_FLAG_TAYLOR_SPLIT);
+    const int item_atoms = taylor ? kTaylorItemAtoms : kItemAtoms;
     // with h^lr expanded as 2 exp(-kappa d)/d (the erfc -> 2/0 step), no
     // target of an accepting cluster may come within eta (6 + kappa eta/2)
     // of the atom, where that step is off by more than erfc(6) ~ 2e-17
@@ -2070,6 +2149,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     const bool want_stats = a.opts->flags & RISM_FLAG_STATS;
     unsigned long long *work = want_stats ? ws.get<unsigned long long>(4) : nullptr;
     uint32_t *nd = ws.get<uint32_t>(ngrp), *nsh = ws.get<uint32_t>(nleaf);
+    uint32_t *dguard = ws.get<uint32_t>(ngrp);
     uint32_t *cost = ws.get<uint32_t>(nleaf);
     int *order = ws.get<int>(nleaf);
     double *V = ws.get<double>((size_t)(ncl + 1) * nc * np);
@@ -2079,6 +2159,11 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     // CpCaps, [5] query stack overflow, [6] capacity check failed, [8..9] the
     // input check's flags (when deferred to here)
     uint32_t *hres = pinned_u32(kFlagWords);
+    const hipEvent_t fev = flags_event(dev);
+    if (!fev) {
+        set_error("treecode_cp: event creation failed");
+        return RISM_E_HIP;
+    }
     if (!hres) {
         set_error("treecode_cp: pinned host buffer allocation failed");
         return RISM_E_HIP;
@@ -2087,8 +2172,8 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     auto second_half = [&](const CpCaps &cap) -> int {
         int *ccand = ws.get<int>(cap.c[0] + 1), *lcand = ws.get<int>(cap.c[2] + 1);
         uint32_t *cl_n = ws.get<uint32_t>(ncl + 1), *item_off = ws.get<uint32_t>(ncl + 1);
-        // far work items: runs of at most kItemAtoms of a cluster's atoms
-        const int max_items = ncl + (int)((cap.c[4] + kItemAtoms - 1) / kItemAtoms);
+        // far work items: runs of at most item_atoms of a cluster's atoms
+        const int max_items = ncl + (int)((cap.c[4] + item_atoms - 1) / item_atoms);
         int *it_cl = ws.get<int>(max_items + 1), *it_order = ws.get<int>(max_items + 1);
         uint32_t *it_a0 = ws.get<uint32_t>(max_items + 1), *it_na = ws.get<uint32_t>(max_items + 1);
         uint32_t *n_items = ws.get<uint32_t>(1);
@@ -2144,6 +2229,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             ca.dlist = dlist;
             ca.slist = slist;
             ca.nd = nd;
+            ca.on_grid = dguard;
             ca.ns = nsh;
             ca.cost = cost;
             hipLaunchKernelGGL(k_cp_fill, ncl + ngrp, kFillThreads, qshm, s, qc, ql, aa, ca);
@@ -2151,7 +2237,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             CpItemArgs ia{};
             ia.ncl = ncl;
             ia.n = cl_n;
-            ia.amax = kItemAtoms;
+            ia.amax = item_atoms;
             ia.item_off = item_off;
             ia.it_cl = it_cl;
             ia.it_a0 = it_a0;
@@ -2161,6 +2247,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             hipLaunchKernelGGL(k_cp_plan, ncl > 0 ? 2 : 1, kPlanThreads, 0, s, leaf_order, ia,
                                item_order, (const int *)bad, (const uint32_t *)flags, hres,
                                kFlagWords);
+            RISM_HIP(hipEventRecord(fev, s));
         }
         RISM_HIP(hipGetLastError());
 
@@ -2232,7 +2319,11 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
                     default: hipLaunchKernelGGL((k_cp_down_chain<16, 0>), ng, kDownThreads, dshm, s, da); break;
                     }
             };
-            if (L.T >= 3) {
+            if (a.solute->n > kChainMaxAtoms) {
+                // one launch per level: every cluster's items are summed once
+                chain(L.T, L.T, 0);
+                for (int l = L.T - 1; l >= 1; --l) chain(l, l + 1, 1);
+            } else if (L.T >= 3) {
                 chain(2, L.T, 0);   // V_2 from the top
                 chain(1, 2, 1);     // V_1 from V_2
             } else {
@@ -2252,6 +2343,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         la.dlist = dlist;
         la.slist = slist;
         la.nd = nd;
+        la.on_grid = dguard;
         la.ns = nsh;
         la.order = order;
         la.bad = bad;
@@ -2278,12 +2370,16 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         return RISM_OK;
     };
 
-    // copied: the flags reached hres through k_cp_plan (a full pass)
+    // copied: the flags reached hres through k_cp_plan (a full pass); only
+    // that kernel is waited for
     auto read_back = [&](bool copied) -> int {
-        if (!copied)
+        if (copied) {
+            RISM_HIP(hipEventSynchronize(fev));
+        } else {
             RISM_HIP(hipMemcpyAsync(hres, flags, kFlagWords * sizeof(uint32_t),
                                     hipMemcpyDeviceToHost, s));
-        RISM_HIP(hipStreamSynchronize(s));
+            RISM_HIP(hipStreamSynchronize(s));
+        }
         if (a.stage_err && (hres[8] || hres[9])) {
             set_error(hres[8] ? "non-finite atom input or negative sigma/eps"
                               : "lj_tol must be below eps_ga of every pair");

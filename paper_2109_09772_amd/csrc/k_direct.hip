@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_stage(SiteParams sp, StageArgs a)
         r.yh = (float)y; r.yl = (float)(y - (double)r.yh);
         r.zh = (float)z; r.zl = (float)(z - (double)r.zh);
         r.q = (float)q;
-        r.pad = 0.f;
+        r.on_grid = real && on_grid_point(r, a.grid) ? 1.f : 0.f;
 #pragma unroll
         for (int g = 0; g < NS; ++g) {
             r.A[g] = (float)A[g];

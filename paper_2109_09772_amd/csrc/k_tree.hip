@@ -147,8 +147,16 @@ __global__ __launch_bounds__(1024) void k_scan_excl(uint32_t *a, int n_host, con
     const int per = (n + 1023) / 1024;
     const int lo = t * per < n ? t * per : n;
     const int hi = lo + per < n ? lo + per : n;
+    // each thread's segment in runs of kScanRun loads issued together
+    constexpr int kScanRun = 16;
     uint32_t sum = 0;
-    for (int i = lo; i < hi; ++i) sum += a[i];
+    for (int i0 = lo; i0 < hi; i0 += kScanRun) {
+        uint32_t v[kScanRun];
+#pragma unroll
+        for (int u = 0; u < kScanRun; ++u) v[u] = i0 + u < hi ? a[i0 + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < kScanRun; ++u) sum += v[u];
+    }
     s[t] = sum;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -158,10 +166,15 @@ __global__ __launch_bounds__(1024) void k_scan_excl(uint32_t *a, int n_host, con
         __syncthreads();
     }
     uint32_t run = s[t] - sum;
-    for (int i = lo; i < hi; ++i) {
-        uint32_t v = a[i];
-        a[i] = run;
-        run += v;
+    for (int i0 = lo; i0 < hi; i0 += kScanRun) {
+        uint32_t v[kScanRun];
+#pragma unroll
+        for (int u = 0; u < kScanRun; ++u) v[u] = i0 + u < hi ? a[i0 + u] : 0u;
+#pragma unroll
+        for (int u = 0; u < kScanRun; ++u) {
+            if (i0 + u < hi) a[i0 + u] = run;
+            run += v[u];
+        }
     }
     if (total_out && t == 1023) *total_out = s[1023];
 }
@@ -564,11 +577,73 @@ __global__ __launch_bounds__(kBlock) void k_permute(const AtomF32<NS> *in, const
     else if (i < npad) out[i] = in[i];   // padding records stay last
 }
 
-// Tight box, centre and radius of every node: one wave per node.
+// Atoms per chunk of the chunk boxes: a node of more than 2 kBoxChunk atoms
+// takes the boxes of the whole chunks it covers and reads only the atoms of
+// its two partial chunks.
+constexpr int kBoxChunk = 2048;
+
+// Box of the sorted atoms [b, e) of this wave, accumulated into lo / hi
+// (lane-partial; four atoms per lane per step, their loads issued together).
+__device__ __forceinline__ void atoms_box(const float4 *rec, int stride_f4, int b, int e,
+                                          int lane, double lo[3], double hi[3])
+{
+    for (int i0 = b + lane; i0 < e; i0 += 4 * 64) {
+        float4 a[4], c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + 64 * u;
+            if (i < e) {
+                a[u] = rec[(size_t)i * stride_f4];
+                c[u] = rec[(size_t)i * stride_f4 + 1];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (i0 + 64 * u >= e) break;
+            const double v[3] = {(double)a[u].x + c[u].x, (double)a[u].y + c[u].y,
+                                 (double)a[u].z + c[u].z};
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = fmin(lo[k], v[k]);
+                hi[k] = fmax(hi[k], v[k]);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void wave_box(double lo[3], double hi[3])
+{
+    for (int off = 32; off > 0; off >>= 1)
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fmin(lo[k], __shfl_xor(lo[k], off));
+            hi[k] = fmax(hi[k], __shfl_xor(hi[k], off));
+        }
+}
+
+// Box of every chunk of kBoxChunk sorted atoms: one wave per chunk.
+__global__ __launch_bounds__(kBlock) void k_chunk_box(const float4 *rec, int stride_f4, int n,
+                                                      double *cbox)
+{
+    const int lane = threadIdx.x & 63;
+    const int c = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int b = c * kBoxChunk;
+    if (b >= n) return;   // whole wave
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    atoms_box(rec, stride_f4, b, min(b + kBoxChunk, n), lane, lo, hi);
+    wave_box(lo, hi);
+    if (lane == 0)
+        for (int k = 0; k < 3; ++k) {
+            cbox[6 * c + k] = lo[k];
+            cbox[6 * c + 3 + k] = hi[k];
+        }
+}
+
+// Tight box, centre and radius of every node: one wave per node.  With
+// cbox (the chunk boxes), a node of more than 2 kBoxChunk atoms reads the
+// boxes of its whole chunks instead of their atoms.
 __global__ __launch_bounds__(kBlock) void k_node_box(const float4 *rec, int stride_f4,
                                                      const int *begin, const int *end,
-                                                     const int *n_nodes, double *box,
-                                                     double *centre)
+                                                     const int *n_nodes, const double *cbox,
+                                                     double *box, double *centre)
 {
     const int lane = threadIdx.x & 63;
     const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
@@ -576,35 +651,20 @@ __global__ __launch_bounds__(kBlock) void k_node_box(const float4 *rec, int stri
     const int nn = *n_nodes;
     for (int node = wave; node < nn; node += nw) {
         double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-        const int e = end[node];
-        // four atoms per lane per step, their loads issued together (min and
-        // max do not depend on the order)
-        for (int i0 = begin[node] + lane; i0 < e; i0 += 4 * 64) {
-            float4 a[4], b[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = i0 + 64 * u;
-                if (i < e) {
-                    a[u] = rec[(size_t)i * stride_f4];
-                    b[u] = rec[(size_t)i * stride_f4 + 1];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (i0 + 64 * u >= e) break;
-                const double v[3] = {(double)a[u].x + b[u].x, (double)a[u].y + b[u].y,
-                                     (double)a[u].z + b[u].z};
+        const int b = begin[node], e = end[node];
+        if (cbox && e - b > 2 * kBoxChunk) {
+            const int c0 = (b + kBoxChunk - 1) / kBoxChunk, c1 = e / kBoxChunk;
+            atoms_box(rec, stride_f4, b, c0 * kBoxChunk, lane, lo, hi);
+            atoms_box(rec, stride_f4, c1 * kBoxChunk, e, lane, lo, hi);
+            for (int c = c0 + lane; c < c1; c += 64)
                 for (int k = 0; k < 3; ++k) {
-                    lo[k] = fmin(lo[k], v[k]);
-                    hi[k] = fmax(hi[k], v[k]);
+                    lo[k] = fmin(lo[k], cbox[6 * c + k]);
+                    hi[k] = fmax(hi[k], cbox[6 * c + 3 + k]);
                 }
-            }
+        } else {
+            atoms_box(rec, stride_f4, b, e, lane, lo, hi);
         }
-        for (int off = 32; off > 0; off >>= 1)
-            for (int k = 0; k < 3; ++k) {
-                lo[k] = fmin(lo[k], __shfl_xor(lo[k], off));
-                hi[k] = fmax(hi[k], __shfl_xor(hi[k], off));
-            }
+        wave_box(lo, hi);
         if (lane == 0) {
             double r2 = 0;
             for (int k = 0; k < 3; ++k) {
@@ -947,8 +1007,16 @@ int build_source_tree(const TreeCallArgs &a, Workspace &ws, TreeDev &t, rism_sta
     default: hipLaunchKernelGGL(k_permute<8>, (int)((a.npad + kBlock - 1) / kBlock), kBlock, 0, s, (const AtomF32<8> *)a.rec32, t.perm, n, (int)a.npad, (AtomF32<8> *)t.sorted_rec); break;
     }
     }
+    double *cbox = nullptr;
+    if (n > 2 * kBoxChunk) {
+        const int nch = (n + kBoxChunk - 1) / kBoxChunk;
+        cbox = ws.get<double>(6 * (size_t)nch);
+        if (ws.status()) return ws.status();
+        hipLaunchKernelGGL(k_chunk_box, (nch + kBlock / 64 - 1) / (kBlock / 64), kBlock, 0, s,
+                           (const float4 *)t.sorted_rec, stride_f4, n, cbox);
+    }
     hipLaunchKernelGGL(k_node_box, 1024, kBlock, 0, s, (const float4 *)t.sorted_rec, stride_f4,
-                       t.begin, t.end, t.n_nodes, t.box, t.centre);
+                       t.begin, t.end, t.n_nodes, cbox, t.box, t.centre);
     RISM_HIP(hipGetLastError());
     (void)st;
     return RISM_OK;

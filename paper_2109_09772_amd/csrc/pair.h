@@ -122,17 +122,12 @@ __device__ __forceinline__ void smear_eval(const float4 *tab, float tinv, float 
     gh = fmaf(fmaf(fmaf(h.w, t, h.z), t, h.y), t, h.x);
 }
 
-// One (point, atom) pair.  FULL: every term of the atom: 1/d (into C),
-// e^{-kappa d}/d (into Y) and, for d < R_s, the differences
-// erf(d/eta)/d - 1/d and bracket/d - 2 e^{-kappa d}/d from the table (into SC,
-// SH); beyond R_s those differences are < 1e-12 relative and dropped.  At a
-// coincident point (d = 0) only the smeared kernels' limits enter.
-// Not FULL (the atom's 1/d and e^{-kappa d}/d reach the point through
-// proxies): only LJ within the cut-off and the differences within R_s.
-template <int NS, int LJM, bool ASYM, bool EXACT, bool FULL, class Rec>
-__device__ __forceinline__ void pair_eval(const Rec &at, const GridPt &g,
-                                          const PairConst &k, const float4 *tab, PairAcc<NS> &p,
-                                          bool &hit)
+// Squared FP32 distance of a pair from the hi/lo coordinates.  EXACT: the
+// point's coordinates are exact in FP32 (no lo words).  Every kernel forms d2
+// through this function, so a test of d2 == 0 made elsewhere (a coincident
+// atom) agrees with the pair loops bit for bit.
+template <bool EXACT, class Rec>
+__device__ __forceinline__ float pair_d2(const Rec &at, const GridPt &g)
 {
     float dx, dy, dz;
     if (EXACT) {
@@ -144,14 +139,47 @@ __device__ __forceinline__ void pair_eval(const Rec &at, const GridPt &g,
         dy = (g.yh - at.yh) + (g.yl - at.yl);
         dz = (g.zh - at.zh) + (g.zl - at.zl);
     }
-    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+}
+
+// Whether the atom sits on a grid point in the FP32 pair arithmetic: d2 == 0
+// for that point, formed as the pair loops form it.  d2 underflows to zero
+// only when every coordinate difference is below ~1e-22 A, so only the atom's
+// nearest grid point can give it.
+template <class Rec>
+__device__ __forceinline__ bool on_grid_point(const Rec &at, const GridParams &g)
+{
+    const double u = rint(((double)at.xh + (double)at.xl) / g.h[0]);
+    const double v = rint(((double)at.yh + (double)at.yl) / g.h[1]);
+    const double w = rint(((double)at.zh + (double)at.zl) / g.h[2]);
+    if (!(u >= 0.0 && u < g.nx && v >= 0.0 && v < g.ny && w >= 0.0 && w < g.nz)) return false;
+    const GridPt p = grid_pt(g, (int)u, (int)v, (int)w);
+    return (g.exact ? pair_d2<true>(at, p) : pair_d2<false>(at, p)) == 0.f;
+}
+
+// One (point, atom) pair.  FULL: every term of the atom: 1/d (into C),
+// e^{-kappa d}/d (into Y) and, for d < R_s, the differences
+// erf(d/eta)/d - 1/d and bracket/d - 2 e^{-kappa d}/d from the table (into SC,
+// SH); beyond R_s those differences are < 1e-12 relative and dropped.  At a
+// coincident point (d = 0) only the smeared kernels' limits enter.
+// Not FULL (the atom's 1/d and e^{-kappa d}/d reach the point through
+// proxies): only LJ within the cut-off and the differences within R_s.
+// GUARD false (FULL pairs only): the caller has established that d2 > 0 for
+// every pair of the call, so the coincidence handling is left out.
+template <int NS, int LJM, bool ASYM, bool EXACT, bool FULL, bool GUARD = true, class Rec>
+__device__ __forceinline__ void pair_eval(const Rec &at, const GridPt &g,
+                                          const PairConst &k, const float4 *tab, PairAcc<NS> &p,
+                                          bool &hit)
+{
+    constexpr bool G = GUARD || !FULL;
+    const float d2 = pair_d2<EXACT>(at, g);
     // raw v_rsq_f32 of d2 clamped to 1e-30: a coincident point (d2 = 0, FULL
     // pairs only: a short-range atom is well separated from the point) gets a
     // large finite 1/d that reaches u alone (set to +inf through `hit`), and
     // d = d2/sqrt(d2) stays ~0, so the smeared kernels take their d = 0
     // values from the table
-    const float ri = __builtin_amdgcn_rsqf(fmaxf(d2, 1e-30f));
-    if (FULL) hit |= (d2 == 0.f);
+    const float ri = __builtin_amdgcn_rsqf(G ? fmaxf(d2, 1e-30f) : d2);
+    if (FULL && G) hit |= (d2 == 0.f);
     if (LJM != LJ_NONE) {
         // 1/d^2 for the LJ powers: ri^2 carries twice the error of the
         // reciprocal square root, and r^-12 multiplies it by six again,
@@ -185,7 +213,7 @@ __device__ __forceinline__ void pair_eval(const Rec &at, const GridPt &g,
     // point excepted: its terms are the d -> 0 limits of the smeared kernels
     // alone), and within R_s the smeared kernels' differences to those far
     // forms, as a short-range atom does
-    const float qe = FULL && d2 == 0.f ? 0.f : qr;
+    const float qe = FULL && G && d2 == 0.f ? 0.f : qr;
     if (FULL) {
         p.C += qe;
         p.Y = fmaf(qe, e, p.Y);

@@ -329,6 +329,7 @@ static int stage_atoms(const rism_solute *so, const Prep &p, const rism_opts *op
     a.n = so->n;
     a.npad = p.npad;
     for (int k = 0; k < 3; ++k) a.origin[k] = p.g.o[k];
+    a.grid = p.g;
     a.lj_cutoff = op->lj_cutoff;
     a.lj_tol = op->lj_tol;
     a.lj_mode = p.lj_mode;

@@ -29,7 +29,9 @@ constexpr double kFarAway = 1.0e5;    // padding atoms sit this far from the gri
 template <int NS>
 struct alignas(16) AtomF32 {
     float xh, yh, zh, q;
-    float xl, yl, zl, pad;
+    float xl, yl, zl;
+    float on_grid;   // 1 when the atom sits on a grid point (d2 == 0 in the
+                     // FP32 pair arithmetic for that point), else 0
     float A[NS];     // 4 eps_ga sigma_ga^12
     float B[NS];     // 4 eps_ga sigma_ga^6
     float rc2[NS];   // squared LJ cut-off radius (inf: no cut-off)
@@ -159,6 +161,7 @@ struct StageArgs {
     double *rcut;       // [ns][n] FP64 cut-off radii or null
     float4 *smear_tab;  // or null: the smeared-kernel table of `smear` (cubic
     AsymParams smear;   // pieces per interval), formed by the same launch
+    GridParams grid;    // for AtomF32::on_grid
 };
 int launch_stage(const SiteParams &sp, const StageArgs &a, hipStream_t s);
 int launch_lj_tail(const SiteParams &sp, const double *rcut, const double *sig, const double *eps,

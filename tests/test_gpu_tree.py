@@ -259,3 +259,28 @@ def test_few_atoms_one_on_a_grid_point(oracle, method, n):
     assert_close_grid(u, ur, 1e-6, cap=FP32_CAP, what="u")
     assert_close_grid(_np(c), cr, 1e-6, cap=FP32_CAP, what="c")
     assert_close_grid(_np(h), hr, 1e-6, cap=FP32_CAP, what="h")
+
+
+@pytest.mark.parametrize("method", ["treecode_cp", "treecode_taylor"])
+def test_many_atoms_some_on_grid_points(oracle, method):
+    """Two of 300 atoms sit exactly on grid points, so some leaf blocks take
+    the pair loop with the coincidence handling and the rest the one without
+    it in the same call: u is +inf at those two points, c and h are finite
+    everywhere, and every grid matches the oracle."""
+    wl = W.tiny(n_atoms=5, dims=(48, 44, 40), seed=21, spacing=0.5)
+    wl.solute = W.ball_solute(300, 9.0, 21)
+    g = wl.grid
+    wl.solute.xyz += g.origin + g.spacing * (g.dims - 1) / 2.0
+    on = [(30, 20, 10), (19, 27, 26)]
+    for a, (i, j, k) in enumerate(on):
+        wl.solute.xyz[7 * a + 3] = g.origin + g.spacing * np.array([i, j, k])
+    th, dg = TOL_PARAMS.get(method, (0.3, 10))
+    (u, c, h), _ = _run(wl, method=method, theta=th, degree=dg)
+    ur, cr, hr = _oracle_grids(oracle, wl)
+    u = _np(u)
+    for i, j, k in on:
+        assert np.isposinf(u[:, k, j, i]).all()
+    assert np.isfinite(_np(c)).all() and np.isfinite(_np(h)).all()
+    assert_close_grid(u, ur, 1e-6, cap=FP32_CAP, what="u")
+    assert_close_grid(_np(c), cr, 1e-6, cap=FP32_CAP, what="c")
+    assert_close_grid(_np(h), hr, 1e-6, cap=FP32_CAP, what="h")
