@@ -1124,8 +1124,13 @@ __global__ __launch_bounds__(kBlock) void k_cp_sweep(CpSweepArgs a)
 // depend on the schedule).
 constexpr int kSweepGroups = 4;
 constexpr int kSweepThreads = kSweepGroups * kBlock;
+// Launches of more items than this many per CU take the atom loop unrolled
+// twice instead of four times: fewer registers (60 against 83), so two
+// workgroups share a CU, which pays once there are enough items to fill
+// them; with fewer items the deeper unrolling is faster.
+constexpr int kSweepItemsPerCuUnroll2 = 16;
 
-template <bool ASYM, int NI>
+template <bool ASYM, int NI, int UNROLL>
 __global__ __launch_bounds__(kSweepThreads) void k_cp_sweep_lines(CpSweepArgs a)
 {
     __shared__ float node[3][kMaxDeg + 1];
@@ -1179,7 +1184,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_cp_sweep_lines(CpSweepArgs a)
 #pragma unroll
             for (int r = 0; r < NI; ++r) pC[r] = pY[r] = 0.f;
             const int s1 = min(s0 + 16, m);
-#pragma unroll 4
+#pragma unroll UNROLL
             for (int s = s0; s < s1; ++s) {
                 const float4 v = st[s];
                 const float dy = py - v.y, dz = pz - v.z;
@@ -1243,12 +1248,19 @@ inline int sweep_line_ni(int n1)
 }
 
 template <bool ASYM>
-void launch_sweep(int nitems, int np, int degree, const CpSweepArgs &sa, hipStream_t s)
+void launch_sweep(int nitems, int np, int degree, int n_cu, const CpSweepArgs &sa,
+                  hipStream_t s)
 {
+    const bool many = nitems > kSweepItemsPerCuUnroll2 * n_cu;
     switch (sweep_line_ni(degree + 1)) {
-    case 2: hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 2>), nitems, kSweepThreads, 0, s, sa); return;
-    case 3: hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 3>), nitems, kSweepThreads, 0, s, sa); return;
-    case 6: hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 6>), nitems, kSweepThreads, 0, s, sa); return;
+    case 2: hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 2, 4>), nitems, kSweepThreads, 0, s, sa); return;
+    case 3:
+        if (many)
+            hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 3, 2>), nitems, kSweepThreads, 0, s, sa);
+        else
+            hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 3, 4>), nitems, kSweepThreads, 0, s, sa);
+        return;
+    case 6: hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 6, 4>), nitems, kSweepThreads, 0, s, sa); return;
     default: break;
     }
     const int nr = np <= 3 * kBlock ? (np + kBlock - 1) / kBlock : 4;
@@ -2053,6 +2065,8 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     if (ws.status()) return ws.status();
     int dev = 0;
     RISM_HIP(hipGetDevice(&dev));
+    int n_cu = 0;
+    RISM_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     CpQueryArgs qa{};
     qa.L = L;
     qa.rshort = rshort;
@@ -2282,9 +2296,9 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
                     hipLaunchKernelGGL((k_cp_taylor<false, false>), max_items, kBlock, tshm, s,
                                        sa);
             } else if (a.asym_on) {
-                launch_sweep<true>(max_items, np, deg, sa, s);
+                launch_sweep<true>(max_items, np, deg, n_cu, sa, s);
             } else {
-                launch_sweep<false>(max_items, np, deg, sa, s);
+                launch_sweep<false>(max_items, np, deg, n_cu, sa, s);
             }
         }
         if (ncl > 0) {

@@ -178,6 +178,38 @@ __global__ __launch_bounds__(kBlock) void k_stage(SiteParams sp, StageArgs a)
         for (int off = 32; off > 0; off >>= 1) r2max = max(r2max, __shfl_xor(r2max, off));
         if ((threadIdx.x & 63) == 0 && r2max > 0) atomicMax(&a.err_flags[2], r2max);
     }
+    if (a.bbox_part) {
+        // the workgroup's box of the positions the FP32 records carry, as the
+        // tree forms them: (double)hi + lo
+        __shared__ double wbox[6][kBlock / 64];
+        double bl[3], bh[3];
+        const double v[3] = {(double)(float)x + (double)(float)(x - (double)(float)x),
+                             (double)(float)y + (double)(float)(y - (double)(float)y),
+                             (double)(float)z + (double)(float)(z - (double)(float)z)};
+        for (int k = 0; k < 3; ++k) {
+            bl[k] = real ? v[k] : 1e300;
+            bh[k] = real ? v[k] : -1e300;
+        }
+        for (int off = 32; off > 0; off >>= 1)
+            for (int k = 0; k < 3; ++k) {
+                bl[k] = fmin(bl[k], __shfl_xor(bl[k], off));
+                bh[k] = fmax(bh[k], __shfl_xor(bh[k], off));
+            }
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        if (lane == 0)
+            for (int k = 0; k < 3; ++k) {
+                wbox[k][wave] = bl[k];
+                wbox[3 + k][wave] = bh[k];
+            }
+        __syncthreads();
+        if (threadIdx.x < 6) {
+            const int k = threadIdx.x;
+            double r = wbox[k][0];
+            for (int w = 1; w < kBlock / 64; ++w)
+                r = k < 3 ? fmin(r, wbox[k][w]) : fmax(r, wbox[k][w]);
+            a.bbox_part[6 * blockIdx.x + k] = r;
+        }
+    }
     if (!live) return;
     if (a.rec64) {
         AtomF64<NS> r;
@@ -336,9 +368,8 @@ int launch_direct_f64(const SiteParams &sp, const DirectArgs &a, hipStream_t s)
 // Per pair, in FP32: d from hi/lo coordinates, 1/d by rsqrt, Coulomb Q/d,
 // LJ (A r^-6 - B) r^-6 per site; beyond R_s the smeared kernels are 1/d and
 // 2 e^{-kappa d}/d (exp2) to < 1e-12, within R_s they come from the cubic
-// table in LDS.  Partial sums over 8 atoms are flushed into FP64
-// (electrostatic sums, which cancel in sign) or into TwoSum-compensated FP32
-// (LJ).
+// table in LDS.  Partial sums over 8 atoms are flushed into FP64 running
+// sums.
 template <int NS, int LJM, bool ASYM, bool EXACT>
 __global__ __launch_bounds__(kBlock) void k_direct_f32(SiteParams sp, DirectArgs a)
 {

@@ -69,16 +69,37 @@ __device__ __forceinline__ void bbox_cube(const double lo[3], const double hi[3]
     }
 }
 
-__global__ void k_bbox_final(const double *part, int nparts, double *bbox)
+// The key cube from per-workgroup boxes: one workgroup of kBlock threads.
+__global__ __launch_bounds__(kBlock) void k_bbox_final(const double *part, int nparts,
+                                                       double *bbox)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double red[6][kBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-    for (int p = 0; p < nparts; ++p)
+    for (int p = threadIdx.x; p < nparts; p += kBlock)
         for (int k = 0; k < 3; ++k) {
             lo[k] = fmin(lo[k], part[6 * p + k]);
             hi[k] = fmax(hi[k], part[6 * p + 3 + k]);
         }
-    bbox_cube(lo, hi, bbox);
+    for (int off = 32; off > 0; off >>= 1)
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fmin(lo[k], __shfl_xor(lo[k], off));
+            hi[k] = fmax(hi[k], __shfl_xor(hi[k], off));
+        }
+    if (lane == 0)
+        for (int k = 0; k < 3; ++k) {
+            red[k][wave] = lo[k];
+            red[3 + k][wave] = hi[k];
+        }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = fmin(lo[k], red[k][w]);
+                hi[k] = fmax(hi[k], red[3 + k][w]);
+            }
+        bbox_cube(lo, hi, bbox);
+    }
 }
 
 // ------------------------------------------------------------ Morton keys
@@ -343,18 +364,26 @@ constexpr int kSmallTreeMax = 16384;
 // Key cube of a small tree's atoms by one workgroup of kSmallThreads: a
 // block-wide reduction of the positions.  bb: 6 doubles in LDS.
 __device__ __forceinline__ void small_key_cube(const float4 *rec, int stride_f4, int n,
-                                               double *bb)
+                                               const double *bpart, int nbpart, double *bb)
 {
     __shared__ double red[6][kSmallThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-    for (int i = tid; i < n; i += kSmallThreads) {
-        float4 a = rec[(size_t)i * stride_f4];
-        float4 b = rec[(size_t)i * stride_f4 + 1];
-        double v[3] = {(double)a.x + b.x, (double)a.y + b.y, (double)a.z + b.z};
-        for (int k = 0; k < 3; ++k) {
-            lo[k] = fmin(lo[k], v[k]);
-            hi[k] = fmax(hi[k], v[k]);
+    if (bpart) {   // the staging's per-workgroup boxes of the same positions
+        for (int i = tid; i < nbpart; i += kSmallThreads)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = fmin(lo[k], bpart[6 * i + k]);
+                hi[k] = fmax(hi[k], bpart[6 * i + 3 + k]);
+            }
+    } else {
+        for (int i = tid; i < n; i += kSmallThreads) {
+            float4 a = rec[(size_t)i * stride_f4];
+            float4 b = rec[(size_t)i * stride_f4 + 1];
+            double v[3] = {(double)a.x + b.x, (double)a.y + b.y, (double)a.z + b.z};
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = fmin(lo[k], v[k]);
+                hi[k] = fmax(hi[k], v[k]);
+            }
         }
     }
     for (int off = 32; off > 0; off >>= 1)
@@ -391,8 +420,9 @@ constexpr int kRankThreads = kSmallThreads;
 constexpr int kRankWaves = kRankThreads / 64;
 
 __global__ __launch_bounds__(kRankThreads) void k_tree_rank(const float4 *rec, int stride_f4,
-                                                            int n, int npad, int *rank,
-                                                            uint32_t *keys, int *perm,
+                                                            int n, int npad,
+                                                            const double *bpart, int nbpart,
+                                                            int *rank, uint32_t *keys, int *perm,
                                                             float4 *sorted)
 {
     extern __shared__ uint4 k4[];   // [round_up(n, 4 kRankWaves) / 4]
@@ -400,7 +430,7 @@ __global__ __launch_bounds__(kRankThreads) void k_tree_rank(const float4 *rec, i
     __shared__ double bb[6];
     uint32_t *kk = reinterpret_cast<uint32_t *>(k4);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    small_key_cube(rec, stride_f4, n, bb);
+    small_key_cube(rec, stride_f4, n, bpart, nbpart, bb);
     const int np = (n + 4 * kRankWaves - 1) / (4 * kRankWaves) * (4 * kRankWaves);
     for (int i = tid; i < np; i += kRankThreads) {
         const uint32_t key = i < n ? atom_key(rec, stride_f4, i, bb) : 0xffffffffu;
@@ -949,7 +979,8 @@ int build_source_tree(const TreeCallArgs &a, Workspace &ws, TreeDev &t, rism_sta
             const int npad = (n + 4 * kRankWaves - 1) / (4 * kRankWaves) * (4 * kRankWaves);
             hipLaunchKernelGGL(k_tree_rank, std::max(1, (n + kRankTargets - 1) / kRankTargets),
                                kRankThreads, (size_t)npad * sizeof(uint32_t), s, rec, stride_f4,
-                               n, (int)a.npad, v1, k0, v0, static_cast<float4 *>(t.sorted_rec));
+                               n, (int)a.npad, a.bbox_part, a.n_bbox_part, v1, k0, v0,
+                               static_cast<float4 *>(t.sorted_rec));
         }
         SmallTreeArgs sa{};
         sa.keys = k0;
@@ -971,8 +1002,12 @@ int build_source_tree(const TreeCallArgs &a, Workspace &ws, TreeDev &t, rism_sta
         t.perm = v0;
     } else {
     const int nb = (n + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_bbox_partial, nparts, kBlock, 0, s, rec, stride_f4, n, part);
-    hipLaunchKernelGGL(k_bbox_final, 1, 1, 0, s, part, nparts, bbox);
+    if (a.bbox_part) {
+        hipLaunchKernelGGL(k_bbox_final, 1, kBlock, 0, s, a.bbox_part, a.n_bbox_part, bbox);
+    } else {
+        hipLaunchKernelGGL(k_bbox_partial, nparts, kBlock, 0, s, rec, stride_f4, n, part);
+        hipLaunchKernelGGL(k_bbox_final, 1, kBlock, 0, s, part, nparts, bbox);
+    }
     hipLaunchKernelGGL(k_morton, nb, kBlock, 0, s, rec, stride_f4, n, bbox, k0, v0);
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 8 * pass;

@@ -317,7 +317,8 @@ static size_t rec_bytes(int ns_pad, bool f64)
 static int stage_atoms(const rism_solute *so, const Prep &p, const rism_opts *op, bool want32,
                        bool want64, bool check_eps, Workspace &ws, void **rec32, void **rec64,
                        double **rcut, hipStream_t s, double *max_rcut = nullptr,
-                       const int **defer_err = nullptr, float4 *smear_tab = nullptr)
+                       const int **defer_err = nullptr, float4 *smear_tab = nullptr,
+                       const double **bbox_part = nullptr)
 {
     StageArgs a{};
     a.smear_tab = smear_tab;
@@ -338,6 +339,9 @@ static int stage_atoms(const rism_solute *so, const Prep &p, const rism_opts *op
     a.rec32 = want32 ? ws.alloc(rec_bytes(p.sp.ns_pad, false) * p.npad) : nullptr;
     a.rec64 = want64 ? ws.alloc(rec_bytes(p.sp.ns_pad, true) * p.npad) : nullptr;
     a.rcut = rcut ? ws.get<double>((size_t)p.sp.ns * (so->n > 0 ? so->n : 1)) : nullptr;
+    a.bbox_part = bbox_part ? ws.get<double>(6 * (size_t)((p.npad + kBlock - 1) / kBlock))
+                            : nullptr;
+    if (bbox_part) *bbox_part = a.bbox_part;
     if (ws.status() != RISM_OK) return ws.status();
     hipLaunchKernelGGL(k_fill_i32, 1, 64, 0, s, a.err_flags, 4, 0);
     RISM_HIP(hipGetLastError());
@@ -451,6 +455,8 @@ static int forward(const rism_solute *so, const rism_sites *si, const rism_grid 
     const bool cp_method = (op->method == RISM_TREECODE_CP || op->method == RISM_TREECODE_TAYLOR) &&
                            (u || c || h);
     const int *stage_err = nullptr;
+    const double *bbox_part = nullptr;   // per-workgroup atom boxes, for the trees
+    const bool tree_method = op->method == RISM_TREECODE || cp_method;
     // the FP32 paths' smeared-kernel table, formed by the staging launch
     float4 *tab = nullptr;
     if (asym_on && !f64path) {
@@ -459,7 +465,7 @@ static int forward(const rism_solute *so, const rism_sites *si, const rism_grid 
     }
     rc = stage_atoms(so, p, op, !f64path, f64path, false, ws, &rec32, &rec64,
                      want_rcut ? &rcut : nullptr, s, &max_rcut, cp_method ? &stage_err : nullptr,
-                     tab);
+                     tab, tree_method ? &bbox_part : nullptr);
     if (rc) return rc;
     if (tab) p.asym.tab = tab;
 
@@ -501,6 +507,8 @@ static int forward(const rism_solute *so, const rism_sites *si, const rism_grid 
             // which lj_tol > 0 always runs)
             ta.rmax_short = op->lj_tol > 0 ? max_rcut : op->lj_cutoff;
             ta.stage_err = stage_err;
+            ta.bbox_part = bbox_part;
+            ta.n_bbox_part = (int)((p.npad + kBlock - 1) / kBlock);
             rc = op->method == RISM_TREECODE ? tree_forward(ta, ws, st, s)
                                              : tree_forward_cp(ta, ws, st, s);
         }

@@ -162,6 +162,8 @@ struct StageArgs {
     float4 *smear_tab;  // or null: the smeared-kernel table of `smear` (cubic
     AsymParams smear;   // pieces per interval), formed by the same launch
     GridParams grid;    // for AtomF32::on_grid
+    double *bbox_part;  // or null: per staging workgroup (the first npad / kBlock),
+                        // the box of its atoms' FP32 record positions: lo[3], hi[3]
 };
 int launch_stage(const SiteParams &sp, const StageArgs &a, hipStream_t s);
 int launch_lj_tail(const SiteParams &sp, const double *rcut, const double *sig, const double *eps,
@@ -205,6 +207,8 @@ struct TreeCallArgs {
     double rmax_short;      // short-range radius: max(LJ cut-off, R_s)
     const int *stage_err;   // device flags of the input check still to read
                             // ([0] non-finite input, [1] tolerance), or null
+    const double *bbox_part;  // per-workgroup boxes of the staged atoms, or null
+    int n_bbox_part;
 };
 int tree_forward(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStream_t s);
 int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStream_t s);
