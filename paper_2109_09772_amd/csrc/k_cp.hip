@@ -365,6 +365,21 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane)
     return v;
 }
 
+// Families of target clusters (siblings share one query and one pass over
+// their candidates): family f < nfam - 1 is the children of the f-th cluster
+// at levels 2..T (its parent, at level lp); the last family is the top
+// cluster alone (lp = T + 1).
+__device__ __forceinline__ void cp_family(const CpLevels &L, int f, int nfam, int &lp, int &I,
+                                          int &J, int &K)
+{
+    if (f == nfam - 1) {
+        lp = L.T + 1;
+        I = J = K = 0;
+    } else {
+        cp_decode(L, L.off[2] + f, lp, I, J, K);
+    }
+}
+
 // One wave per query.  Small trees are scanned flat, node by node; larger
 // ones descended: the DFS pops up to 64 nodes at a time (one per lane),
 // appends the hit leaves in lane order and pushes the children of the other
@@ -382,13 +397,14 @@ __device__ __forceinline__ void cp_query(const CpQueryArgs &a, int q, int *stk)
     bool all = false, has_ball = false, has_box = false;
     double bc[3] = {0, 0, 0}, br2 = 0, blo[3] = {0, 0, 0}, bhi[3] = {0, 0, 0};
     if (a.mode == 0) {
-        int lvl, I, J, K;
-        cp_decode(L, q, lvl, I, J, K);
-        if (lvl == L.T) {
+        // a family of target clusters: the leaves near their parent
+        int lp, I, J, K;
+        cp_family(L, q, a.nq, lp, I, J, K);
+        if (lp > L.T) {
             all = true;
         } else {
             double r;
-            cp_centre(L, lvl + 1, I >> 1, J >> 1, K >> 1, bc, r);
+            cp_centre(L, lp, I, J, K, bc, r);
             const double rb = cp_sep_radius(L, r);
             br2 = rb * rb;
             has_ball = true;
@@ -854,52 +870,76 @@ __global__ __launch_bounds__(kPlanThreads) void k_cp_plan(OrderJob leaves, CpIte
     }
 }
 
-// Far-field assignment of one target cluster's candidate atoms: an atom
-// belongs to the cluster when the cluster is the coarsest one on the atom's
-// chain that satisfies the MAC.  The assigned atoms are written, in candidate
-// order, as (position relative to the cluster centre, charge) from the
-// cluster's slot on (room for all of its candidate atoms); their count goes
-// to n[cl].
+// Far-field assignment by families: the children of one parent cluster share
+// their candidates (the leaves near the parent), so each candidate atom is
+// read and tested once for all of them; the top cluster forms a family of its
+// own, every leaf a candidate.  An atom belongs to a child when the child
+// satisfies the MAC and the parent and its ancestors do not (the coarsest
+// cluster on the atom's chain that satisfies it).  Child j's assigned atoms
+// are written, in candidate order, as (position relative to the child's
+// centre, charge) from 8 aoff[f] + j (aoff[f + 1] - aoff[f]) on, where aoff
+// is the prefix of the families' candidate atoms; the counts go to n[cl], the
+// first positions to slot[cl].
 struct CpAssignArgs {
     CpLevels L;
-    const uint32_t *cand_off;  // candidate leaves of each cluster (prefix)
+    int nfam;                  // families: parents at levels 2..T, then the top cluster
+    const uint32_t *cand_off;  // candidate leaves of each family (prefix)
     const int *cand;
     const int *begin, *end;
     const float4 *rec;
     int stride_f4;
-    const uint32_t *slot;      // candidate atoms of each cluster (prefix): first slot
+    const uint32_t *aoff;      // candidate atoms of each family (prefix)
     float4 *abuf;              // assigned atoms
     uint32_t *n;               // assigned atoms per cluster
+    uint32_t *slot;            // first position of each cluster's atoms in abuf
     unsigned long long *work;  // optional: (atom, proxy) pairs
     int np;
 };
 
-// One workgroup of NT threads assigns cluster cl's candidates, windows of NT
+// One workgroup of NT threads assigns family f's candidates, windows of NT
 // candidate leaves at a time, their atoms dealt NT at a time to the threads.
 template <int NT>
-__device__ __forceinline__ void cp_assign_cluster(const CpAssignArgs &a, int cl)
+__device__ __forceinline__ void cp_assign_family(const CpAssignArgs &a, int f)
 {
     constexpr int NW = NT / 64;
     __shared__ int beg[NT];
     __shared__ int pre[NT + 1];
     __shared__ int ws[NW];
-    __shared__ int wcnt[2][NW];
-    __shared__ CpMac mac[kCpMaxLev + 1];   // the cluster and its ancestors, levels lvl..T
+    __shared__ uint32_t wcnt[2][8][NW];
+    __shared__ CpMac mac[kCpMaxLev + 1];   // the parent and its ancestors, levels lp..T
+    __shared__ CpMac cmac[8];              // the children
+    __shared__ double ccen64[8][3];        // their centres
+    __shared__ int cid[8];                 // their cluster ids (-1: beyond the grid)
     const CpLevels &L = a.L;
-    int lvl, I, J, K;
-    cp_decode(L, cl, lvl, I, J, K);
-    double cc[3], rr;
-    cp_centre(L, lvl, I, J, K, cc, rr);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid >= lvl && tid <= L.T) {
-        const int sh = tid - lvl;
-        cp_mac_terms(L, tid, I >> sh, J >> sh, K >> sh, mac[tid]);
+    int lp, Ip, Jp, Kp;
+    cp_family(L, f, a.nfam, lp, Ip, Jp, Kp);
+    const int lc = lp - 1;   // the children's level
+    if (tid >= lp && tid <= L.T) {
+        const int sh = tid - lp;
+        cp_mac_terms(L, tid, Ip >> sh, Jp >> sh, Kp >> sh, mac[tid]);
+    }
+    if (tid >= 64 && tid < 72) {
+        const int j = tid - 64;
+        const int I = lp > L.T ? 0 : 2 * Ip + (j & 1), J = lp > L.T ? 0 : 2 * Jp + ((j >> 1) & 1);
+        const int K = lp > L.T ? 0 : 2 * Kp + (j >> 2);
+        const bool in = (lp <= L.T || j == 0) && I < L.cx[lc] && J < L.cy[lc] && K < L.cz[lc];
+        cid[j] = in ? cp_id(L, lc, I, J, K) : -1;
+        if (in) {
+            cp_mac_terms(L, lc, I, J, K, cmac[j]);
+            double cc[3], rr;
+            cp_centre(L, lc, I, J, K, cc, rr);
+            for (int k = 0; k < 3; ++k) ccen64[j][k] = cc[k];
+        }
     }
     __syncthreads();
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    float4 *out = a.abuf + a.slot[cl];
-    uint32_t filled = 0;   // workgroup-uniform
-    const int c0 = (int)a.cand_off[cl], c1 = (int)a.cand_off[cl + 1];
+    const uint32_t base0 = a.aoff[f], naf = a.aoff[f + 1] - base0;
+    float4 *out = a.abuf + 8 * (size_t)base0;
+    uint32_t filled[8];   // workgroup-uniform
+#pragma unroll
+    for (int j = 0; j < 8; ++j) filled[j] = 0;
+    const int c0 = (int)a.cand_off[f], c1 = (int)a.cand_off[f + 1];
     for (int cw = c0; cw < c1; cw += NT) {
         // window of candidate leaves: first atom and atom prefix, in list order
         const int nw = min(NT, c1 - cw);
@@ -917,8 +957,9 @@ __device__ __forceinline__ void cp_assign_cluster(const CpAssignArgs &a, int cl)
         __syncthreads();
         for (int t0 = 0, par = 0; t0 < run; t0 += NT, par ^= 1) {
             const int t = t0 + tid;
-            bool acc = false;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            uint32_t acc = 0;   // bit j: assigned to child j
+            double y[3] = {0.0, 0.0, 0.0};
+            float q = 0.f;
             if (t < run) {
                 int lo = 0, hi = nw - 1;   // last k with pre[k] <= t
                 while (lo < hi) {
@@ -927,42 +968,66 @@ __device__ __forceinline__ void cp_assign_cluster(const CpAssignArgs &a, int cl)
                     else hi = mid - 1;
                 }
                 const int i = beg[lo] + (t - pre[lo]);
-                double y[3];
                 atom_pos(a.rec, a.stride_f4, i, y);
-                // well separated from this cluster and from none of its ancestors
-                acc = cp_mac_at(L, mac[lvl], y);
-                for (int l = lvl + 1; acc && l <= L.T; ++l) acc = !cp_mac_at(L, mac[l], y);
-                v.x = (float)(y[0] - cc[0]);
-                v.y = (float)(y[1] - cc[1]);
-                v.z = (float)(y[2] - cc[2]);
-                v.w = a.rec[(size_t)i * a.stride_f4].w;
-            }
-            // ordered compaction (two count buffers alternate: one barrier a round)
-            const uint64_t m = __ballot(acc);
-            if (lane == 0) wcnt[par][wave] = __popcll(m);
-            __syncthreads();
-            uint32_t base = 0, total = 0;
+                q = a.rec[(size_t)i * a.stride_f4].w;
+                // well separated from none of the parent's chain ...
+                bool up = true;
+                for (int l = lp; up && l <= L.T; ++l) up = !cp_mac_at(L, mac[l], y);
+                // ... and from the child
+                if (up)
 #pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                const uint32_t c = (uint32_t)wcnt[par][w];
-                base += w < wave ? c : 0u;
-                total += c;
+                    for (int j = 0; j < 8; ++j)
+                        if (cid[j] >= 0 && cp_mac_at(L, cmac[j], y)) acc |= 1u << j;
             }
-            if (acc) out[filled + base + __popcll(m & lt)] = v;
-            filled += total;
+            // ordered compaction of every child's list (two count buffers
+            // alternate: one barrier a round)
+            uint64_t m[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                m[j] = __ballot((acc >> j) & 1u);
+                if (lane == 0) wcnt[par][j][wave] = (uint32_t)__popcll(m[j]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                uint32_t o = 0, tot = 0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    const uint32_t c = wcnt[par][j][w];
+                    o += w < wave ? c : 0u;
+                    tot += c;
+                }
+                if ((acc >> j) & 1u) {
+                    const float4 v = make_float4((float)(y[0] - ccen64[j][0]),
+                                                 (float)(y[1] - ccen64[j][1]),
+                                                 (float)(y[2] - ccen64[j][2]), q);
+                    out[(size_t)j * naf + filled[j] + o + (uint32_t)__popcll(m[j] & lt)] = v;
+                }
+                // workgroup-uniform: kept in a scalar register
+                filled[j] = __builtin_amdgcn_readfirstlane(filled[j] + tot);
+            }
         }
         __syncthreads();   // the window is read before the next one is written
     }
-    if (tid == 0) {
-        a.n[cl] = filled;
-        if (a.work) atomicAdd(a.work, (unsigned long long)filled * (unsigned long long)a.np);
+    if (tid < 8 && cid[tid] >= 0) {
+        uint32_t fj = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) fj = j == tid ? filled[j] : fj;
+        a.n[cid[tid]] = fj;
+        a.slot[cid[tid]] = 8 * base0 + (uint32_t)tid * naf;
+    }
+    if (tid == 0 && a.work) {
+        unsigned long long tot = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) tot += filled[j];
+        atomicAdd(a.work, tot * (unsigned long long)a.np);
     }
 }
 
 // Fill pass of the neighbour queries with the work that reads their lists:
-// workgroups [0, qc.nq) query a target cluster and assign its far-field
-// atoms, the rest query a group of level-0 blocks and classify its near
-// field.  The query runs on the first wave; the whole workgroup then reads
+// workgroups [0, qc.nq) query a family of target clusters and assign their
+// far-field atoms, the rest query a group of level-0 blocks and classify its
+// near field.  The query runs on the first wave; the whole workgroup then reads
 // the list it wrote.
 constexpr int kFillThreads = kClsThreads;
 
@@ -975,7 +1040,7 @@ __global__ __launch_bounds__(kFillThreads, 4) void k_cp_fill(CpQueryArgs qc, CpQ
     if (q < qc.nq) {
         if (threadIdx.x < 64) cp_query(qc, q, stk);
         __syncthreads();
-        cp_assign_cluster<kFillThreads>(aa, q);
+        cp_assign_family<kFillThreads>(aa, q);
     } else {
         if (threadIdx.x < 64) cp_query(ql, q - qc.nq, stk);
         __syncthreads();
@@ -2060,7 +2125,10 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     if (a.lj_mode == LJ_CUT) rshort = std::max(rshort, a.rmax_short);
 
     // queries: clusters (mode 0) and groups of leaves (mode 1), count pass
-    uint32_t *ccnt = ws.get<uint32_t>(ncl + 1), *cacnt = ws.get<uint32_t>(ncl + 1);
+    // families of target clusters: the children of each cluster at levels
+    // 2..T, and the top cluster alone
+    const int nfam = ncl > 0 ? ncl - L.off[2] + 1 : 0;
+    uint32_t *ccnt = ws.get<uint32_t>(nfam + 1), *cacnt = ws.get<uint32_t>(nfam + 1);
     uint32_t *lcnt = ws.get<uint32_t>(ngrp + 1), *lacnt = ws.get<uint32_t>(ngrp + 1);
     if (ws.status()) return ws.status();
     int dev = 0;
@@ -2108,9 +2176,9 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         // count pass of both query sets (and the tables) in one launch, then
         // the four scans
         PhaseTimer pt(ev, RISM_PHASE_LISTS, s);
-        CpQueryArgs qc = qa;   // clusters (none when ncl = 0)
+        CpQueryArgs qc = qa;   // families of clusters (none when ncl = 0)
         qc.mode = 0;
-        qc.nq = ncl;
+        qc.nq = nfam;
         qc.cnt = ccnt;
         qc.acnt = cacnt;
         qc.fill = 0;
@@ -2120,7 +2188,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         ql.cnt = lcnt;
         ql.acnt = lacnt;
         ql.fill = 0;
-        hipLaunchKernelGGL(k_cp_query, ncl + ngrp + cp_table_blocks(ta), kQueryThreads, qshm, s,
+        hipLaunchKernelGGL(k_cp_query, nfam + ngrp + cp_table_blocks(ta), kQueryThreads, qshm, s,
                            qc, ql, ta);
         ScanBatch sb{};
         int na = 0;
@@ -2132,8 +2200,8 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             ++na;
         };
         if (ncl > 0) {   // (otherwise their totals stay 0)
-            add(ccnt, 0, ncl + 1);
-            add(cacnt, 4, ncl + 1);
+            add(ccnt, 0, nfam + 1);
+            add(cacnt, 4, nfam + 1);
         }
         add(lcnt, 2, ngrp + 1);
         add(lacnt, 3, ngrp + 1);
@@ -2186,13 +2254,16 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     auto second_half = [&](const CpCaps &cap) -> int {
         int *ccand = ws.get<int>(cap.c[0] + 1), *lcand = ws.get<int>(cap.c[2] + 1);
         uint32_t *cl_n = ws.get<uint32_t>(ncl + 1), *item_off = ws.get<uint32_t>(ncl + 1);
-        // far work items: runs of at most item_atoms of a cluster's atoms
-        const int max_items = ncl + (int)((cap.c[4] + item_atoms - 1) / item_atoms);
+        uint32_t *cslot = ws.get<uint32_t>(ncl + 1);
+        // far work items: runs of at most item_atoms of a cluster's atoms (a
+        // family's children have room for all of its candidate atoms each)
+        const size_t max_assigned = 8 * (size_t)cap.c[4];
+        const int max_items = ncl + (int)((max_assigned + item_atoms - 1) / item_atoms);
         int *it_cl = ws.get<int>(max_items + 1), *it_order = ws.get<int>(max_items + 1);
         uint32_t *it_a0 = ws.get<uint32_t>(max_items + 1), *it_na = ws.get<uint32_t>(max_items + 1);
         uint32_t *n_items = ws.get<uint32_t>(1);
         double *part = ws.get<double>((size_t)(max_items + 1) * nc * np);
-        float4 *abuf = ws.get<float4>((size_t)cap.c[4] + 1);
+        float4 *abuf = ws.get<float4>(max_assigned + 1);
         int *dlist = ws.get<int>(cap.c[3] + 1), *slist = ws.get<int>(8 * (size_t)cap.c[3] + 1);
         if (ws.status()) return ws.status();
         if (work) hipLaunchKernelGGL(k_fill_u64, 1, 64, 0, s, work, 4);
@@ -2204,7 +2275,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             PhaseTimer pt(ev, RISM_PHASE_LISTS, s);
             CpQueryArgs qc = qa;
             qc.mode = 0;
-            qc.nq = ncl;
+            qc.nq = nfam;
             qc.off = ccnt;
             qc.list = ccand;
             qc.fill = 1;
@@ -2218,15 +2289,17 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             ql.acnt = nullptr;
             CpAssignArgs aa{};
             aa.L = L;
+            aa.nfam = nfam;
             aa.cand_off = ccnt;
             aa.cand = ccand;
             aa.begin = t.begin;
             aa.end = t.end;
             aa.rec = static_cast<const float4 *>(t.sorted_rec);
             aa.stride_f4 = stride_f4;
-            aa.slot = cacnt;
+            aa.aoff = cacnt;
             aa.abuf = abuf;
             aa.n = cl_n;
+            aa.slot = cslot;
             aa.work = work ? work + 2 : nullptr;
             aa.np = np;
             CpClassArgs ca{};
@@ -2246,7 +2319,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             ca.on_grid = dguard;
             ca.ns = nsh;
             ca.cost = cost;
-            hipLaunchKernelGGL(k_cp_fill, ncl + ngrp, kFillThreads, qshm, s, qc, ql, aa, ca);
+            hipLaunchKernelGGL(k_cp_fill, nfam + ngrp, kFillThreads, qshm, s, qc, ql, aa, ca);
             const OrderJob leaf_order{nleaf, nullptr, cost, nullptr, order};
             CpItemArgs ia{};
             ia.ncl = ncl;
@@ -2275,7 +2348,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             sa.it_cl = it_cl;
             sa.it_a0 = it_a0;
             sa.it_na = it_na;
-            sa.slot = cacnt;
+            sa.slot = cslot;
             sa.abuf = abuf;
             sa.degree = deg;
             sa.np = np;
