@@ -50,7 +50,8 @@ extern "C" {
  *                   definitions term by term (GPU reference).
  * RISM_DIRECT_F32C  FP32 pair arithmetic over every pair (hi/lo
  *                   coordinates), blocked partial sums flushed into FP64
- *                   accumulators; the smeared kernels are 1/d and
+ *                   (electrostatics) or compensated FP32 (LJ) accumulators;
+ *                   the smeared kernels are 1/d and
  *                   2 exp(-kappa d)/d beyond R_s (to < 1e-12) and come from a
  *                   cubic table (FP64-fitted) within R_s.
  * RISM_TREECODE     as DIRECT_F32C, but the far parts 1/d and exp(-kappa d)/d

@@ -368,8 +368,9 @@ int launch_direct_f64(const SiteParams &sp, const DirectArgs &a, hipStream_t s)
 // Per pair, in FP32: d from hi/lo coordinates, 1/d by rsqrt, Coulomb Q/d,
 // LJ (A r^-6 - B) r^-6 per site; beyond R_s the smeared kernels are 1/d and
 // 2 e^{-kappa d}/d (exp2) to < 1e-12, within R_s they come from the cubic
-// table in LDS.  Partial sums over 8 atoms are flushed into FP64 running
-// sums.
+// table in LDS.  Partial sums over 8 atoms are flushed into FP64
+// (electrostatic sums, which cancel in sign) or into TwoSum-compensated FP32
+// (LJ).
 template <int NS, int LJM, bool ASYM, bool EXACT>
 __global__ __launch_bounds__(kBlock) void k_direct_f32(SiteParams sp, DirectArgs a)
 {

@@ -9,8 +9,8 @@
 //  short : atoms of leaves inside accepted clusters that still come within
 //          the short range of the batch -> LJ, and the smeared kernels less
 //          1/d and 2 e^{-kappa d}/d within R_s.
-// Partial sums over 16 proxies / 8 atoms are flushed into FP64 running sums,
-// as in the direct kernel.
+// Partial sums over 16 proxies / 8 atoms are flushed into FP64 (electrostatic
+// sums) and TwoSum FP32 (LJ), as in the direct kernel.
 #include <cmath>
 
 #include "pair.h"

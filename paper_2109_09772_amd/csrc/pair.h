@@ -58,21 +58,19 @@ struct PairAcc {
     }
 };
 
-// Running sums of one grid point, in FP64: each block partial is exact in
-// FP64, the electrostatic sums cancel in sign across sources, and the LJ sums
-// span many orders of magnitude.  A conversion and an FP64 add per sum and
-// flush (FP64 adds issue at the FP32 rate here).
+// Running sums of one grid point: electrostatic sums in FP64 (they cancel in
+// sign across sources), LJ sums as TwoSum-compensated FP32 pairs.
 template <int NS>
 struct PointAcc {
     double C, Y, SC, SH;
-    double L[NS];
+    float ls[NS], lc[NS];
     bool hit;
     __device__ __forceinline__ void zero()
     {
         C = Y = SC = SH = 0.0;
         hit = false;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) L[s] = 0.0;
+        for (int s = 0; s < NS; ++s) { ls[s] = 0.f; lc[s] = 0.f; }
     }
     template <bool LJ, bool ASYM>
     __device__ __forceinline__ void flush(const PairAcc<NS> &p)
@@ -85,7 +83,13 @@ struct PointAcc {
         }
         if (LJ) {
 #pragma unroll
-            for (int s = 0; s < NS; ++s) L[s] += (double)p.L[s];
+            for (int s = 0; s < NS; ++s) {
+                // Knuth's TwoSum
+                float t = ls[s] + p.L[s];
+                float z = t - ls[s];
+                lc[s] += (ls[s] - (t - z)) + (p.L[s] - z);
+                ls[s] = t;
+            }
         }
     }
 };
@@ -251,7 +255,7 @@ __device__ __forceinline__ void store_point(const OutParams &o, const GridParams
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             if (s < o.ns) {
-                double lj = LJM != LJ_NONE ? acc.L[s] : 0.0;
+                double lj = LJM != LJ_NONE ? (double)acc.ls[s] + (double)acc.lc[s] : 0.0;
                 store_val(o.u, o.f64, s * g.m + p, acc.hit ? INFINITY : o.u_coul[s] * coul + lj);
             }
         }
