@@ -1200,7 +1200,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_cp_sweep_lines(CpSweepArgs a)
 {
     __shared__ float node[3][kMaxDeg + 1];
     __shared__ float4 stage[kSweepGroups][2][kBlock];
-    __shared__ double red[kSweepGroups - 1][kBlock];
+    __shared__ double red[kSweepGroups - 1][2 * NI][kBlock];
     if (*a.bad || (int)blockIdx.x >= (int)*a.n_items) return;   // whole workgroup
     const SweepItem w = sweep_item(a);
     const int cl = w.cl, item = w.item, n = w.n;
@@ -1272,19 +1272,23 @@ __global__ __launch_bounds__(kSweepThreads) void k_cp_sweep_lines(CpSweepArgs a)
             }
         }
     }
-    // the groups' sums, added in group order by group 0
+    // the groups' sums, added in group order by group 0 (all of a thread's
+    // sums through LDS at once: one barrier)
+    if (grp > 0) {
 #pragma unroll
-    for (int r = 0; r < NI; ++r) {
-        __syncthreads();   // red is free
-        if (grp > 0) red[grp - 1][tl] = aC[r];
-        __syncthreads();
-        if (grp == 0)
-            for (int g = 0; g < kSweepGroups - 1; ++g) aC[r] += red[g][tl];
-        __syncthreads();
-        if (grp > 0) red[grp - 1][tl] = aY[r];
-        __syncthreads();
-        if (grp == 0)
-            for (int g = 0; g < kSweepGroups - 1; ++g) aY[r] += red[g][tl];
+        for (int r = 0; r < NI; ++r) {
+            red[grp - 1][r][tl] = aC[r];
+            red[grp - 1][NI + r][tl] = aY[r];
+        }
+    }
+    __syncthreads();
+    if (grp == 0) {
+#pragma unroll
+        for (int r = 0; r < NI; ++r)
+            for (int g = 0; g < kSweepGroups - 1; ++g) {
+                aC[r] += red[g][r][tl];
+                aY[r] += red[g][NI + r][tl];
+            }
     }
     if (grp == 0 && live) {
 #pragma unroll
