@@ -603,6 +603,38 @@ __device__ __forceinline__ int group_excl_scan(int v, int *ws, int &total)
     return base + incl - v;
 }
 
+// Offsets of NL ordered compactions over the NW waves of a workgroup, from
+// the per-wave counts cnt[l][w] in LDS: lane l < NL of every wave gets list
+// l's count in the waves before its own (o) and over all waves (tot), so that
+// each wave forms the sums once, in parallel over the lists, and reads them
+// back per list with lane_word.
+template <int NL, int NW>
+__device__ __forceinline__ void list_offsets(const uint32_t *cnt, int lane, int wave, uint32_t &o,
+                                             uint32_t &tot)
+{
+    o = tot = 0;
+    if (lane < NL) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t c = cnt[lane * NW + w];
+            o += w < wave ? c : 0u;
+            tot += c;
+        }
+    }
+}
+
+// Lane l's value of v (wave-uniform result).
+__device__ __forceinline__ uint32_t lane_word(uint32_t v, int l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+
+// Set bits of the wave mask m below this lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // One workgroup of kClsThreads threads classifies group g.
 __device__ __forceinline__ void cp_classify_group(const CpClassArgs &a, int g)
 {
@@ -641,7 +673,6 @@ __device__ __forceinline__ void cp_classify_group(const CpClassArgs &a, int g)
     if (tid == 0) on_any = 0;
     __syncthreads();
     const double rs2 = a.rshort * a.rshort;
-    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint32_t base = a.aoff[g], na = a.aoff[g + 1] - base;
     uint32_t nl[kClsLists];   // workgroup-uniform list lengths
 #pragma unroll
@@ -686,13 +717,22 @@ __device__ __forceinline__ void cp_classify_group(const CpClassArgs &a, int g)
                     cls = 1u;
                     if (a.rec[(size_t)i * a.stride_f4 + 1].w != 0.f) on_any = 1;   // on_grid
                 } else {
+                    // the blocks' boxes share their extents along each axis
+                    // (block c takes the lower or upper one by bit k of c), so
+                    // the gaps are formed once per axis and extent; a block
+                    // beyond the grid has an empty box and an infinite gap
+                    double gg[3][2];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const int c = h << k;
+                            gg[k][h] = fmax(0.0, fmax(cbox[c][k] - y[k], y[k] - cbox[c][3 + k]));
+                        }
 #pragma unroll
                     for (int c = 0; c < 8; ++c) {
-                        double g2 = 0;
-                        for (int k = 0; k < 3; ++k) {
-                            const double gg = fmax(0.0, fmax(cbox[c][k] - y[k], y[k] - cbox[c][3 + k]));
-                            g2 += gg * gg;
-                        }
+                        const double gx = gg[0][c & 1], gy = gg[1][(c >> 1) & 1], gz = gg[2][c >> 2];
+                        const double g2 = fma(gz, gz, fma(gy, gy, gx * gx));
                         if (g2 < rs2) cls |= 2u << c;
                     }
                 }
@@ -707,21 +747,16 @@ __device__ __forceinline__ void cp_classify_group(const CpClassArgs &a, int g)
                 if (lane == 0) cnt[par][l][wave] = (uint32_t)__popcll(m[l]);
             }
             __syncthreads();
+            uint32_t ol, tl;
+            list_offsets<kClsLists, NW>(&cnt[par][0][0], lane, wave, ol, tl);
 #pragma unroll
             for (int l = 0; l < kClsLists; ++l) {
-                uint32_t o = 0, tot = 0;
-#pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    const uint32_t c = cnt[par][l][w];
-                    o += w < wave ? c : 0u;
-                    tot += c;
-                }
                 if ((cls >> l) & 1u) {
-                    const uint32_t at = nl[l] + o + (uint32_t)__popcll(m[l] & lt);
+                    const uint32_t at = nl[l] + lane_word(ol, l) + lanes_below(m[l]);
                     if (l == 0) a.dlist[base + at] = i;
                     else a.slist[8 * (size_t)base + (size_t)(l - 1) * na + at] = i;
                 }
-                nl[l] += tot;
+                nl[l] += lane_word(tl, l);
             }
         }
         __syncthreads();   // the window is read before the next one is written
@@ -933,7 +968,6 @@ __device__ __forceinline__ void cp_assign_family(const CpAssignArgs &a, int f)
         }
     }
     __syncthreads();
-    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const uint32_t base0 = a.aoff[f], naf = a.aoff[f + 1] - base0;
     float4 *out = a.abuf + 8 * (size_t)base0;
     uint32_t filled[8];   // workgroup-uniform
@@ -988,23 +1022,17 @@ __device__ __forceinline__ void cp_assign_family(const CpAssignArgs &a, int f)
                 if (lane == 0) wcnt[par][j][wave] = (uint32_t)__popcll(m[j]);
             }
             __syncthreads();
+            uint32_t oj, tj;
+            list_offsets<8, NW>(&wcnt[par][0][0], lane, wave, oj, tj);
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                uint32_t o = 0, tot = 0;
-#pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    const uint32_t c = wcnt[par][j][w];
-                    o += w < wave ? c : 0u;
-                    tot += c;
-                }
                 if ((acc >> j) & 1u) {
                     const float4 v = make_float4((float)(y[0] - ccen64[j][0]),
                                                  (float)(y[1] - ccen64[j][1]),
                                                  (float)(y[2] - ccen64[j][2]), q);
-                    out[(size_t)j * naf + filled[j] + o + (uint32_t)__popcll(m[j] & lt)] = v;
+                    out[(size_t)j * naf + filled[j] + lane_word(oj, j) + lanes_below(m[j])] = v;
                 }
-                // workgroup-uniform: kept in a scalar register
-                filled[j] = __builtin_amdgcn_readfirstlane(filled[j] + tot);
+                filled[j] += lane_word(tj, j);   // workgroup-uniform
             }
         }
         __syncthreads();   // the window is read before the next one is written
