@@ -245,9 +245,11 @@ struct CpTabArgs {
     int nrow_m;                    // M rows in all
     int lrow0[3], nrow_l;          // first level-1 basis row of each axis; rows in all
     double *M, *Lg;
-    // optional: two words copied from err_src to err_dst (the input check's
-    // flags, gathered with the lists' counts for one read-back)
+    // optional: the input check's flag words of err_n staging workgroups
+    // (three each), reduced into err_dst[0] (non-finite input) and err_dst[1]
+    // (tolerance), gathered with the lists' counts for one read-back
     const int *err_src;
+    int err_n;
     uint32_t *err_dst;
 };
 
@@ -531,7 +533,18 @@ __global__ __launch_bounds__(kQueryThreads) void k_cp_query(CpQueryArgs a, CpQue
         __syncthreads();
         const int r = (q - a.nq - b.nq) * kQueryThreads + (int)threadIdx.x;
         if (r < t.nrow_m + t.nrow_l) cp_table_row(t, r, cosk);
-        if (t.err_src && r < 2) t.err_dst[r] = (uint32_t)t.err_src[r];
+        if (t.err_src && q == a.nq + b.nq) {   // the first table workgroup (one wave)
+            int f0 = 0, f1 = 0;
+            for (int i = threadIdx.x; i < t.err_n; i += kQueryThreads) {
+                f0 |= t.err_src[3 * i];
+                f1 |= t.err_src[3 * i + 1];
+            }
+            const bool b0 = __ballot(f0 != 0) != 0, b1 = __ballot(f1 != 0) != 0;
+            if (threadIdx.x == 0) {
+                t.err_dst[0] = b0 ? 1u : 0u;
+                t.err_dst[1] = b1 ? 1u : 0u;
+            }
+        }
     }
 }
 
@@ -2186,6 +2199,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     ta.taylor = taylor;
     cp_tab_layout(L, n1, ta);
     ta.err_src = a.stage_err;
+    ta.err_n = a.n_stage_err;
     ta.err_dst = flags + 8;
     ta.M = ws.get<double>((size_t)(ta.nrow_m + 1) * n1);
     ta.Lg = ws.get<double>((size_t)ta.nrow_l * n1);

@@ -119,6 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_stage(SiteParams sp, StageArgs a)
     double x = kFarAway, y = kFarAway, z = kFarAway, q = 0.0, sig = 0.0, eps = 0.0;
     bool real = i < a.n;
     int r2max = 0;   // largest (1 + 1e-6) rc^2 of the atom's sites, as float bits
+    bool f_bad = false, f_tol = false;   // this atom's input-check flags
     if (real) {
         x = a.xyz[3 * i] - a.origin[0];
         y = a.xyz[3 * i + 1] - a.origin[1];
@@ -128,8 +129,8 @@ __global__ __launch_bounds__(kBlock) void k_stage(SiteParams sp, StageArgs a)
         eps = a.eps[i];
         bool bad = !(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(q) &&
                      isfinite(sig) && isfinite(eps)) || sig < 0.0 || eps < 0.0;
-        if (bad) a.err_flags[0] = 1;
-        if (a.check_eps && !(eps > 0.0)) a.err_flags[1] = 1;
+        f_bad = bad;
+        f_tol = a.check_eps && !(eps > 0.0);
     }
     double A[NS], B[NS], rc[NS];
 #pragma unroll
@@ -155,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_stage(SiteParams sp, StageArgs a)
                     // cancellation: t = (z/2) / (1 + sqrt(1 - z)), z = tol/e.
                     double zz = a.lj_tol / e_ga;
                     if (!(zz < 1.0)) {
-                        a.err_flags[1] = 1;
+                        f_tol = true;
                         rc[g] = 0.0;
                     } else {
                         double t = 0.5 * zz / (1.0 + sqrt(1.0 - zz));
@@ -173,37 +174,49 @@ __global__ __launch_bounds__(kBlock) void k_stage(SiteParams sp, StageArgs a)
             }
         }
     }
-    if (a.lj_mode == LJ_CUT) {
-        // one atomic per wave
-        for (int off = 32; off > 0; off >>= 1) r2max = max(r2max, __shfl_xor(r2max, off));
-        if ((threadIdx.x & 63) == 0 && r2max > 0) atomicMax(&a.err_flags[2], r2max);
-    }
-    if (a.bbox_part) {
-        // the workgroup's box of the positions the FP32 records carry, as the
-        // tree forms them: (double)hi + lo
+    // the workgroup's flags and largest cut-off radius, and with bbox_part its
+    // box of the positions the FP32 records carry, as the tree forms them
+    // ((double)hi + lo): wave reductions, then the waves' values through LDS
+    {
+        __shared__ int wflag[3][kBlock / 64];
         __shared__ double wbox[6][kBlock / 64];
-        double bl[3], bh[3];
-        const double v[3] = {(double)(float)x + (double)(float)(x - (double)(float)x),
-                             (double)(float)y + (double)(float)(y - (double)(float)y),
-                             (double)(float)z + (double)(float)(z - (double)(float)z)};
-        for (int k = 0; k < 3; ++k) {
-            bl[k] = real ? v[k] : 1e300;
-            bh[k] = real ? v[k] : -1e300;
-        }
-        for (int off = 32; off > 0; off >>= 1)
-            for (int k = 0; k < 3; ++k) {
-                bl[k] = fmin(bl[k], __shfl_xor(bl[k], off));
-                bh[k] = fmax(bh[k], __shfl_xor(bh[k], off));
-            }
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        if (lane == 0)
+        for (int off = 32; off > 0; off >>= 1) r2max = max(r2max, __shfl_xor(r2max, off));
+        const bool any_bad = __ballot(f_bad) != 0, any_tol = __ballot(f_tol) != 0;
+        if (lane == 0) {
+            wflag[0][wave] = any_bad ? 1 : 0;
+            wflag[1][wave] = any_tol ? 1 : 0;
+            wflag[2][wave] = r2max;
+        }
+        if (a.bbox_part) {
+            double bl[3], bh[3];
+            const double v[3] = {(double)(float)x + (double)(float)(x - (double)(float)x),
+                                 (double)(float)y + (double)(float)(y - (double)(float)y),
+                                 (double)(float)z + (double)(float)(z - (double)(float)z)};
             for (int k = 0; k < 3; ++k) {
-                wbox[k][wave] = bl[k];
-                wbox[3 + k][wave] = bh[k];
+                bl[k] = real ? v[k] : 1e300;
+                bh[k] = real ? v[k] : -1e300;
             }
+            for (int off = 32; off > 0; off >>= 1)
+                for (int k = 0; k < 3; ++k) {
+                    bl[k] = fmin(bl[k], __shfl_xor(bl[k], off));
+                    bh[k] = fmax(bh[k], __shfl_xor(bh[k], off));
+                }
+            if (lane == 0)
+                for (int k = 0; k < 3; ++k) {
+                    wbox[k][wave] = bl[k];
+                    wbox[3 + k][wave] = bh[k];
+                }
+        }
         __syncthreads();
-        if (threadIdx.x < 6) {
+        if (threadIdx.x < 3) {
             const int k = threadIdx.x;
+            int r = wflag[k][0];
+            for (int w = 1; w < kBlock / 64; ++w) r = k < 2 ? (r | wflag[k][w]) : max(r, wflag[k][w]);
+            a.err_part[3 * blockIdx.x + k] = r;
+        }
+        if (a.bbox_part && threadIdx.x >= 64 && threadIdx.x < 70) {
+            const int k = threadIdx.x - 64;
             double r = wbox[k][0];
             for (int w = 1; w < kBlock / 64; ++w)
                 r = k < 3 ? fmin(r, wbox[k][w]) : fmax(r, wbox[k][w]);
@@ -233,6 +246,45 @@ __global__ __launch_bounds__(kBlock) void k_stage(SiteParams sp, StageArgs a)
         }
         static_cast<AtomF32<NS> *>(a.rec32)[i] = r;
     }
+}
+
+// The staging workgroups' flag words [3 * nparts] into flags[0..2]: any
+// non-finite input, any tolerance / eps failure, the largest squared cut-off
+// radius (float bits).  One workgroup.
+__global__ __launch_bounds__(kBlock) void k_stage_flags(const int *part, int nparts, int *flags)
+{
+    __shared__ int w[3][kBlock / 64];
+    int f0 = 0, f1 = 0, f2 = 0;
+    for (int i = threadIdx.x; i < nparts; i += kBlock) {
+        f0 |= part[3 * i];
+        f1 |= part[3 * i + 1];
+        f2 = max(f2, part[3 * i + 2]);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        f0 |= __shfl_xor(f0, off);
+        f1 |= __shfl_xor(f1, off);
+        f2 = max(f2, __shfl_xor(f2, off));
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        w[0][wave] = f0;
+        w[1][wave] = f1;
+        w[2][wave] = f2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int k = threadIdx.x;
+        int r = w[k][0];
+        for (int v = 1; v < kBlock / 64; ++v) r = k < 2 ? (r | w[k][v]) : max(r, w[k][v]);
+        flags[k] = r;
+    }
+}
+
+int launch_stage_flags(const int *part, int nparts, int *flags, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stage_flags, 1, kBlock, 0, s, part, nparts, flags);
+    RISM_HIP(hipGetLastError());
+    return RISM_OK;
 }
 
 int launch_stage(const SiteParams &sp, const StageArgs &a, hipStream_t s)

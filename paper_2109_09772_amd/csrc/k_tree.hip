@@ -361,10 +361,26 @@ constexpr int kRankTargets = 64;   // atoms ranked per workgroup
 // level-by-level split (about 0.3 ms at 14,000 atoms).
 constexpr int kSmallTreeMax = 16384;
 
+// Stores node's box and its centre and radius (half-diagonal) from the
+// box's corners.
+__device__ __forceinline__ void store_node_box(int node, const double lo[3], const double hi[3],
+                                               double *box, double *centre)
+{
+    double r2 = 0;
+    for (int k = 0; k < 3; ++k) {
+        box[6 * node + k] = lo[k];
+        box[6 * node + 3 + k] = hi[k];
+        centre[4 * node + k] = 0.5 * (lo[k] + hi[k]);
+        r2 += 0.25 * (hi[k] - lo[k]) * (hi[k] - lo[k]);
+    }
+    centre[4 * node + 3] = sqrt(r2);
+}
+
 // Key cube of a small tree's atoms by one workgroup of kSmallThreads: a
 // block-wide reduction of the positions.  bb: 6 doubles in LDS.
 __device__ __forceinline__ void small_key_cube(const float4 *rec, int stride_f4, int n,
-                                               const double *bpart, int nbpart, double *bb)
+                                               const double *bpart, int nbpart, double *bb,
+                                               double *tight)
 {
     __shared__ double red[6][kSmallThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -405,6 +421,10 @@ __device__ __forceinline__ void small_key_cube(const float4 *rec, int stride_f4,
             }
         const double l3[3] = {red[0][0], red[1][0], red[2][0]};
         const double h3[3] = {red[3][0], red[4][0], red[5][0]};
+        for (int k = 0; k < 3; ++k) {
+            tight[k] = l3[k];
+            tight[3 + k] = h3[k];
+        }
         bbox_cube(l3, h3, bb);
     }
     __syncthreads();
@@ -415,7 +435,9 @@ __device__ __forceinline__ void small_key_cube(const float4 *rec, int stride_f4,
 // stores them) and ranks 64 atoms, each of its sixteen waves counting over a
 // sixteenth of the keys (four keys per broadcast read).  The ranked atoms'
 // records are then placed at their sorted positions (the padding records,
-// n <= i < npad, stay last).
+// n <= i < npad, stay last).  Workgroup 0 also stores the box of the root
+// node (all n atoms, node 0) from the same reduction, so that the node-box
+// pass can leave out its longest node.
 constexpr int kRankThreads = kSmallThreads;
 constexpr int kRankWaves = kRankThreads / 64;
 
@@ -423,14 +445,16 @@ __global__ __launch_bounds__(kRankThreads) void k_tree_rank(const float4 *rec, i
                                                             int n, int npad,
                                                             const double *bpart, int nbpart,
                                                             int *rank, uint32_t *keys, int *perm,
-                                                            float4 *sorted)
+                                                            float4 *sorted, double *root_box,
+                                                            double *root_centre)
 {
     extern __shared__ uint4 k4[];   // [round_up(n, 4 kRankWaves) / 4]
     __shared__ int part[kRankWaves][kRankTargets];
-    __shared__ double bb[6];
+    __shared__ double bb[6], tb[6];
     uint32_t *kk = reinterpret_cast<uint32_t *>(k4);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    small_key_cube(rec, stride_f4, n, bpart, nbpart, bb);
+    small_key_cube(rec, stride_f4, n, bpart, nbpart, bb, tb);
+    if (blockIdx.x == 0 && tid == 0) store_node_box(0, tb, tb + 3, root_box, root_centre);
     const int np = (n + 4 * kRankWaves - 1) / (4 * kRankWaves) * (4 * kRankWaves);
     for (int i = tid; i < np; i += kRankThreads) {
         const uint32_t key = i < n ? atom_key(rec, stride_f4, i, bb) : 0xffffffffu;
@@ -593,6 +617,12 @@ __global__ __launch_bounds__(kSmallThreads) void k_tree_small(SmallTreeArgs a)
             ls[lvl + 2] = t;
         }
         __syncthreads();
+        if (ls[lvl + 2] == s1) {
+            // no node at the next level, so none at any later one
+            if (tid > lvl + 2 && tid < kMortonBits + 2) ls[tid] = s1;
+            __syncthreads();
+            break;
+        }
     }
     if (tid < kMortonBits + 2) a.level_start[tid] = ls[tid];
     if (tid == 0) *a.n_nodes = ls[kMortonBits + 1];
@@ -667,19 +697,20 @@ __global__ __launch_bounds__(kBlock) void k_chunk_box(const float4 *rec, int str
         }
 }
 
-// Tight box, centre and radius of every node: one wave per node.  With
-// cbox (the chunk boxes), a node of more than 2 kBoxChunk atoms reads the
-// boxes of its whole chunks instead of their atoms.
+// Tight box, centre and radius of every node from `first` on (the nodes
+// before it are done): one wave per node.  With cbox (the chunk boxes), a
+// node of more than 2 kBoxChunk atoms reads the boxes of its whole chunks
+// instead of their atoms.
 __global__ __launch_bounds__(kBlock) void k_node_box(const float4 *rec, int stride_f4,
                                                      const int *begin, const int *end,
                                                      const int *n_nodes, const double *cbox,
-                                                     double *box, double *centre)
+                                                     double *box, double *centre, int first)
 {
     const int lane = threadIdx.x & 63;
     const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
     const int nw = gridDim.x * (kBlock / 64);
     const int nn = *n_nodes;
-    for (int node = wave; node < nn; node += nw) {
+    for (int node = first + wave; node < nn; node += nw) {
         double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
         const int b = begin[node], e = end[node];
         if (cbox && e - b > 2 * kBoxChunk) {
@@ -695,16 +726,7 @@ __global__ __launch_bounds__(kBlock) void k_node_box(const float4 *rec, int stri
             atoms_box(rec, stride_f4, b, e, lane, lo, hi);
         }
         wave_box(lo, hi);
-        if (lane == 0) {
-            double r2 = 0;
-            for (int k = 0; k < 3; ++k) {
-                box[6 * node + k] = lo[k];
-                box[6 * node + 3 + k] = hi[k];
-                centre[4 * node + k] = 0.5 * (lo[k] + hi[k]);
-                r2 += 0.25 * (hi[k] - lo[k]) * (hi[k] - lo[k]);
-            }
-            centre[4 * node + 3] = sqrt(r2);
-        }
+        if (lane == 0) store_node_box(node, lo, hi, box, centre);
     }
 }
 
@@ -980,7 +1002,7 @@ int build_source_tree(const TreeCallArgs &a, Workspace &ws, TreeDev &t, rism_sta
             hipLaunchKernelGGL(k_tree_rank, std::max(1, (n + kRankTargets - 1) / kRankTargets),
                                kRankThreads, (size_t)npad * sizeof(uint32_t), s, rec, stride_f4,
                                n, (int)a.npad, a.bbox_part, a.n_bbox_part, v1, k0, v0,
-                               static_cast<float4 *>(t.sorted_rec));
+                               static_cast<float4 *>(t.sorted_rec), t.box, t.centre);
         }
         SmallTreeArgs sa{};
         sa.keys = k0;
@@ -1051,7 +1073,7 @@ int build_source_tree(const TreeCallArgs &a, Workspace &ws, TreeDev &t, rism_sta
                            (const float4 *)t.sorted_rec, stride_f4, n, cbox);
     }
     hipLaunchKernelGGL(k_node_box, 1024, kBlock, 0, s, (const float4 *)t.sorted_rec, stride_f4,
-                       t.begin, t.end, t.n_nodes, cbox, t.box, t.centre);
+                       t.begin, t.end, t.n_nodes, cbox, t.box, t.centre, small ? 1 : 0);
     RISM_HIP(hipGetLastError());
     (void)st;
     return RISM_OK;

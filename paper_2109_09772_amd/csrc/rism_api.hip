@@ -143,12 +143,6 @@ void *Workspace::alloc(size_t bytes)
 
 // ----------------------------------------------------------- small kernels
 
-__global__ void k_fill_i32(int *p, int n, int v)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
 // Zeroes n 32-bit words (a kernel rather than hipMemsetAsync, so that the
 // call stays a plain kernel launch inside captured graphs).
 __global__ void k_zero_words(uint32_t *p, int64_t n)
@@ -310,15 +304,16 @@ static size_t rec_bytes(int ns_pad, bool f64)
 // caller opted out.
 // defer_err: when the checks need nothing back before later kernels run (no
 // per-pair cut-off radius from a tolerance, no eps check), skip the stream
-// sync here and hand the device flags ([0] non-finite input, [1] tolerance)
-// to the caller, which reads them with its own end-of-call read-back (the
-// kernels in between clamp every index they derive from atom data).
+// sync here and hand the staging workgroups' flag words (StageArgs::err_part,
+// *defer_n workgroups) to the caller, which reads them with its own
+// end-of-call read-back (the kernels in between clamp every index they
+// derive from atom data).
 // smear_tab: also form the smeared-kernel table of p.asym there (same launch).
 static int stage_atoms(const rism_solute *so, const Prep &p, const rism_opts *op, bool want32,
                        bool want64, bool check_eps, Workspace &ws, void **rec32, void **rec64,
                        double **rcut, hipStream_t s, double *max_rcut = nullptr,
-                       const int **defer_err = nullptr, float4 *smear_tab = nullptr,
-                       const double **bbox_part = nullptr)
+                       const int **defer_err = nullptr, int *defer_n = nullptr,
+                       float4 *smear_tab = nullptr, const double **bbox_part = nullptr)
 {
     StageArgs a{};
     a.smear_tab = smear_tab;
@@ -335,7 +330,9 @@ static int stage_atoms(const rism_solute *so, const Prep &p, const rism_opts *op
     a.lj_tol = op->lj_tol;
     a.lj_mode = p.lj_mode;
     a.check_eps = check_eps;
-    a.err_flags = ws.get<int>(4);
+    const int nstage = (int)((p.npad + kBlock - 1) / kBlock);
+    a.err_part = ws.get<int>(3 * (size_t)nstage);
+    int *err_flags = ws.get<int>(4);
     a.rec32 = want32 ? ws.alloc(rec_bytes(p.sp.ns_pad, false) * p.npad) : nullptr;
     a.rec64 = want64 ? ws.alloc(rec_bytes(p.sp.ns_pad, true) * p.npad) : nullptr;
     a.rcut = rcut ? ws.get<double>((size_t)p.sp.ns * (so->n > 0 ? so->n : 1)) : nullptr;
@@ -343,8 +340,6 @@ static int stage_atoms(const rism_solute *so, const Prep &p, const rism_opts *op
                             : nullptr;
     if (bbox_part) *bbox_part = a.bbox_part;
     if (ws.status() != RISM_OK) return ws.status();
-    hipLaunchKernelGGL(k_fill_i32, 1, 64, 0, s, a.err_flags, 4, 0);
-    RISM_HIP(hipGetLastError());
     int rc;
     {
         PhaseTimer pt(op->flags & RISM_FLAG_PHASE_EVENTS, RISM_PHASE_STAGE, s);
@@ -354,7 +349,8 @@ static int stage_atoms(const rism_solute *so, const Prep &p, const rism_opts *op
     bool need_check = !(op->flags & RISM_FLAG_NO_DEVICE_CHECK) || op->lj_tol > 0 || check_eps;
     if (defer_err) *defer_err = nullptr;
     if (need_check && defer_err && !(op->lj_tol > 0) && !check_eps && so->n > 0) {
-        *defer_err = a.err_flags;
+        *defer_err = a.err_part;
+        if (defer_n) *defer_n = nstage;
         need_check = false;
     }
     if (need_check && so->n > 0) {
@@ -363,7 +359,8 @@ static int stage_atoms(const rism_solute *so, const Prep &p, const rism_opts *op
         int local[4] = {0, 0, 0, 0};
         int *h = ws.fixed() ? local : pinned_flags();
         if (!h) return fail(RISM_E_HIP, "pinned host buffer allocation failed");
-        RISM_HIP(hipMemcpyAsync(h, a.err_flags, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+        if ((rc = launch_stage_flags(a.err_part, nstage, err_flags, s))) return rc;
+        RISM_HIP(hipMemcpyAsync(h, err_flags, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
         RISM_HIP(hipStreamSynchronize(s));
         if (h[0]) return fail(RISM_E_INVALID, "non-finite atom input or negative sigma/eps");
         if (h[1])
@@ -455,6 +452,7 @@ static int forward(const rism_solute *so, const rism_sites *si, const rism_grid 
     const bool cp_method = (op->method == RISM_TREECODE_CP || op->method == RISM_TREECODE_TAYLOR) &&
                            (u || c || h);
     const int *stage_err = nullptr;
+    int n_stage_err = 0;
     const double *bbox_part = nullptr;   // per-workgroup atom boxes, for the trees
     const bool tree_method = op->method == RISM_TREECODE || cp_method;
     // the FP32 paths' smeared-kernel table, formed by the staging launch
@@ -465,7 +463,7 @@ static int forward(const rism_solute *so, const rism_sites *si, const rism_grid 
     }
     rc = stage_atoms(so, p, op, !f64path, f64path, false, ws, &rec32, &rec64,
                      want_rcut ? &rcut : nullptr, s, &max_rcut, cp_method ? &stage_err : nullptr,
-                     tab, tree_method ? &bbox_part : nullptr);
+                     &n_stage_err, tab, tree_method ? &bbox_part : nullptr);
     if (rc) return rc;
     if (tab) p.asym.tab = tab;
 
@@ -507,6 +505,7 @@ static int forward(const rism_solute *so, const rism_sites *si, const rism_grid 
             // which lj_tol > 0 always runs)
             ta.rmax_short = op->lj_tol > 0 ? max_rcut : op->lj_cutoff;
             ta.stage_err = stage_err;
+            ta.n_stage_err = n_stage_err;
             ta.bbox_part = bbox_part;
             ta.n_bbox_part = (int)((p.npad + kBlock - 1) / kBlock);
             rc = op->method == RISM_TREECODE ? tree_forward(ta, ws, st, s)

@@ -154,7 +154,8 @@ struct StageArgs {
     double lj_tol;      // > 0 per-pair radius from tolerance (overrides)
     int lj_mode;        // LjMode
     int check_eps;      // flag eps_a <= 0 as an error (backward dL/deps)
-    int *err_flags;     // device int[3]: [0] non-finite input, [1] tol >= eps_ga / eps <= 0,
+    int *err_part;      // device int[3] per staging workgroup (the first npad / kBlock), all
+                        // written: [0] non-finite input, [1] tol >= eps_ga / eps <= 0,
                         // [2] bits of the largest squared cut-off radius (float)
     void *rec32;        // AtomF32<ns_pad>[npad] or null
     void *rec64;        // AtomF64<ns_pad>[npad] or null
@@ -166,6 +167,9 @@ struct StageArgs {
                         // the box of its atoms' FP32 record positions: lo[3], hi[3]
 };
 int launch_stage(const SiteParams &sp, const StageArgs &a, hipStream_t s);
+// Reduces the staging workgroups' words (err_part of nparts workgroups) into
+// flags[0..2]: OR, OR, max.
+int launch_stage_flags(const int *part, int nparts, int *flags, hipStream_t s);
 int launch_lj_tail(const SiteParams &sp, const double *rcut, const double *sig, const double *eps,
                    int64_t n, double *tail_dev, hipStream_t s);
 
@@ -205,8 +209,9 @@ struct TreeCallArgs {
     const void *rec32;      // staged FP32 atom records (input order)
     int64_t npad;
     double rmax_short;      // short-range radius: max(LJ cut-off, R_s)
-    const int *stage_err;   // device flags of the input check still to read
-                            // ([0] non-finite input, [1] tolerance), or null
+    const int *stage_err;   // device flag words of the input check still to read
+                            // (StageArgs::err_part), or null
+    int n_stage_err;        // staging workgroups in stage_err
     const double *bbox_part;  // per-workgroup boxes of the staged atoms, or null
     int n_bbox_part;
 };
