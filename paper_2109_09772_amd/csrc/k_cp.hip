@@ -942,6 +942,8 @@ struct CpAssignArgs {
     uint32_t *slot;            // first position of each cluster's atoms in abuf
     unsigned long long *work;  // optional: (atom, proxy) pairs
     int np;
+    double psc;                // scale of the assigned atoms' positions and charges
+                               // (CpSweepArgs::psc)
 };
 
 // One workgroup of NT threads assigns family f's candidates, windows of NT
@@ -1040,9 +1042,10 @@ __device__ __forceinline__ void cp_assign_family(const CpAssignArgs &a, int f)
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 if ((acc >> j) & 1u) {
-                    const float4 v = make_float4((float)(y[0] - ccen64[j][0]),
-                                                 (float)(y[1] - ccen64[j][1]),
-                                                 (float)(y[2] - ccen64[j][2]), q);
+                    const float4 v = make_float4((float)((y[0] - ccen64[j][0]) * a.psc),
+                                                 (float)((y[1] - ccen64[j][1]) * a.psc),
+                                                 (float)((y[2] - ccen64[j][2]) * a.psc),
+                                                 (float)((double)q * a.psc));
                     out[(size_t)j * naf + filled[j] + lane_word(oj, j) + lanes_below(m[j])] = v;
                 }
                 filled[j] += lane_word(tj, j);   // workgroup-uniform
@@ -1111,6 +1114,12 @@ struct CpSweepArgs {
     double *part;   // [items][nc][np]: each item's part of its cluster's far field
     const uint32_t *n_items;   // items on the device (the launch may have more)
     const int *bad;
+    // scale s of the assigned atoms' positions (relative to their cluster's
+    // centre) and charges, and of the proxies' positions: with s = -yk =
+    // kappa log2(e), the scaled distance d' = s d gives exp(-kappa d) =
+    // exp2(-d') and q'/d' = q/d, which saves the product by yk per pair; 1
+    // where unused
+    double psc;
 };
 
 // Workgroup's item: its cluster, atom count and first atom.
@@ -1236,7 +1245,7 @@ constexpr int kSweepThreads = kSweepGroups * kBlock;
 // them; with fewer items the deeper unrolling is faster.
 constexpr int kSweepItemsPerCuUnroll2 = 16;
 
-template <bool ASYM, int NI, int UNROLL>
+template <bool ASYM, int NI, int UNROLL, bool SC>
 __global__ __launch_bounds__(kSweepThreads) void k_cp_sweep_lines(CpSweepArgs a)
 {
     __shared__ float node[3][kMaxDeg + 1];
@@ -1253,8 +1262,8 @@ __global__ __launch_bounds__(kSweepThreads) void k_cp_sweep_lines(CpSweepArgs a)
         cp_proxy_box(a.L, lvl, I, J, K, pb);
         cp_centre(a.L, lvl, I, J, K, cc, rr);
         const int ax = threadIdx.x / n1, k = threadIdx.x % n1;
-        node[ax][k] = (float)(cheb_point(pick3(pb, ax), pick3(pb + 3, ax), k, a.degree) -
-                              pick3(cc, ax));
+        node[ax][k] = (float)((cheb_point(pick3(pb, ax), pick3(pb + 3, ax), k, a.degree) -
+                               pick3(cc, ax)) * a.psc);
     }
     __syncthreads();
     // this thread's group, its atom range, and its place in the group
@@ -1303,7 +1312,8 @@ __global__ __launch_bounds__(kSweepThreads) void k_cp_sweep_lines(CpSweepArgs a)
                     const float qr = v.w * ri;
                     pC[r] += qr;
                     if (ASYM)
-                        pY[r] = fmaf(qr, __builtin_amdgcn_exp2f(a.yk * (d2 * ri)), pY[r]);
+                        pY[r] = fmaf(qr, __builtin_amdgcn_exp2f(SC ? -(d2 * ri) : a.yk * (d2 * ri)),
+                                     pY[r]);
                 }
             }
 #pragma unroll
@@ -1362,15 +1372,27 @@ void launch_sweep(int nitems, int np, int degree, int n_cu, const CpSweepArgs &s
                   hipStream_t s)
 {
     const bool many = nitems > kSweepItemsPerCuUnroll2 * n_cu;
+    // (the scaled variant exists for the screened kernel only)
+    const bool sc = ASYM && sa.psc != 1.0;
     switch (sweep_line_ni(degree + 1)) {
-    case 2: hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 2, 4>), nitems, kSweepThreads, 0, s, sa); return;
-    case 3:
-        if (many)
-            hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 3, 2>), nitems, kSweepThreads, 0, s, sa);
-        else
-            hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 3, 4>), nitems, kSweepThreads, 0, s, sa);
+    case 2:
+        if (sc) hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 2, 4, ASYM>), nitems, kSweepThreads, 0, s, sa);
+        else hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 2, 4, false>), nitems, kSweepThreads, 0, s, sa);
         return;
-    case 6: hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 6, 4>), nitems, kSweepThreads, 0, s, sa); return;
+    case 3:
+        if (many && sc)
+            hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 3, 2, ASYM>), nitems, kSweepThreads, 0, s, sa);
+        else if (many)
+            hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 3, 2, false>), nitems, kSweepThreads, 0, s, sa);
+        else if (sc)
+            hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 3, 4, ASYM>), nitems, kSweepThreads, 0, s, sa);
+        else
+            hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 3, 4, false>), nitems, kSweepThreads, 0, s, sa);
+        return;
+    case 6:
+        if (sc) hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 6, 4, ASYM>), nitems, kSweepThreads, 0, s, sa);
+        else hipLaunchKernelGGL((k_cp_sweep_lines<ASYM, 6, 4, false>), nitems, kSweepThreads, 0, s, sa);
+        return;
     default: break;
     }
     const int nr = np <= 3 * kBlock ? (np + kBlock - 1) / kBlock : 4;
@@ -2296,6 +2318,11 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         set_error("treecode_cp: pinned host buffer allocation failed");
         return RISM_E_HIP;
     }
+    // scale of the far-field sweep's atom and proxy positions (CpSweepArgs::psc):
+    // the line kernels with the screened kernel, kappa > 0
+    const double psc = !taylor && a.asym_on && a.asym.kappa > 0.0 && sweep_line_ni(deg + 1) != 0
+                           ? -a.asym.yk
+                           : 1.0;
     // Everything after the counts, with buffers of the given capacities.
     auto second_half = [&](const CpCaps &cap) -> int {
         int *ccand = ws.get<int>(cap.c[0] + 1), *lcand = ws.get<int>(cap.c[2] + 1);
@@ -2348,6 +2375,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             aa.slot = cslot;
             aa.work = work ? work + 2 : nullptr;
             aa.np = np;
+            aa.psc = psc;
             CpClassArgs ca{};
             ca.L = L;
             ca.nq = ngrp;
@@ -2405,6 +2433,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             sa.part = part;
             sa.n_items = n_items;
             sa.bad = bad;
+            sa.psc = psc;
             if (taylor) {
                 const size_t tshm = cp_taylor_lds(deg, a.asym_on, paper);
                 if (a.asym_on && paper)
