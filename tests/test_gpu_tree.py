@@ -15,13 +15,13 @@ def _api():
     return api
 
 
-def _run(wl, cut=9.0, tol=0.0, **kw):
+def _run(wl, cut=9.0, tol=0.0, kappa=KAPPA, **kw):
     api = _api()
     xyz, q, s, e = api.solute_to_device(wl.solute)
     opts = api.Opts(method=kw.pop("method", "treecode"), out_dtype="f32", lj_cutoff=cut,
                     lj_tol=tol, stats=True, **kw)
     out = api.initialize(xyz, q, s, e, api.sites_from(wl.sites), api.grid_from(wl.grid), opts,
-                         ETA, KAPPA, BETA, DIEL)
+                         ETA, kappa, BETA, DIEL)
     torch.cuda.synchronize()
     return out, api.last_stats()
 
@@ -149,6 +149,37 @@ def test_cp_sweep_layouts_converge(oracle):
             assert errs[hi][k] < errs[lo][k], (lo, hi, k, errs)
     assert max(e[0] for e in errs.values()) <= 1e-6, errs
     assert max(max(errs[11]), max(errs[12])) <= 1e-6, errs
+
+
+@pytest.mark.parametrize("degree", [8, 10])
+@pytest.mark.parametrize("kappa", [KAPPA, 0.0])
+def test_cp_far_sweep_screened_and_unscreened(oracle, kappa, degree):
+    """With screening the far sweep stores the assigned atoms and the proxies
+    in coordinates scaled by kappa log2(e) (so exp(-kappa d) is 2^-d' with no
+    product per pair); without it (kappa = 0: the exponential is 1) it keeps
+    them unscaled.  Both, at degree 8 (three proxies per thread) and 10 (six),
+    against the oracle at sampled points of the far-field case: the far
+    field is exercised and every grid is within 1e-6 at degree 10 and 3e-6
+    at degree 8 (theta 0.6)."""
+    wl = _far_case()
+    idx = W.sample_points(wl.grid, 5000, seed=9)
+    sol, st, g = wl.solute, wl.sites, wl.grid
+    pts = g.origin + idx * g.spacing
+    rc = oracle_rcut(oracle, wl, 9.0)
+    cr, hr = oracle.asymptotics_points(sol.xyz, sol.q, st.q, st.ionic, pts, KC, ETA, kappa, BETA,
+                                       DIEL)
+    ur = oracle.potential_points(sol.xyz, sol.q, sol.sigma, sol.eps, st.q, st.sigma, st.eps, pts,
+                                 KC, rc)
+    (u, c, h), stt = _run(wl, kappa=kappa, theta=0.6, degree=degree, leaf_size=32,
+                          method="treecode_cp")
+    assert stt["pairs_far"] > 0
+    pick = lambda a: _np(a)[:, idx[:, 2], idx[:, 1], idx[:, 0]]
+    u, c, h = pick(u), pick(c), pick(h)
+    rel = lambda a, r, k: np.linalg.norm(a[k] - r[k]) / np.linalg.norm(r[k])
+    errs = (max(rel(u, ur, k) for k in range(4)), max(rel(c, cr, k) for k in range(4)),
+            max(rel(h, hr, k) for k in range(2)))
+    print(f"kappa {kappa} degree {degree}: rel-L2 (u, c, h)", errs)
+    assert max(errs) <= (1e-6 if degree == 10 else 3e-6), errs
 
 
 def test_cp_leaf_lists_past_one_chunk(oracle):
