@@ -189,3 +189,27 @@ def test_invalid_atom_input_is_reported(method, bad):
     u, c, h = api.initialize(xyz, q, s, e, sites, grid, _opts(method), ETA, KAPPA, BETA, DIEL)
     torch.cuda.synchronize()
     assert bool(torch.isfinite(c).all()) and bool(torch.isfinite(h).all())
+
+
+@pytest.mark.parametrize("method", ["direct_f32c", "treecode_cp"])
+def test_invalid_atom_in_a_later_staging_workgroup(method):
+    """700 atoms span three staging workgroups, each writing its own check
+    words: a NaN charge on atom 650 (the third workgroup) is reported by the
+    synchronous check (direct) and by the deferred one read with the
+    cluster-particle pass's flags, and a valid call after it on the same
+    stream (whose words replace the old ones) passes."""
+    api = _api()
+    wl = W.tiny(n_atoms=5, dims=(40, 36, 32), seed=13, spacing=0.5)
+    wl.solute = W.ball_solute(700, 12.0, 13)
+    wl.solute.xyz += wl.grid.origin + 0.5 * wl.grid.spacing * (np.asarray(wl.grid.dims) - 1)
+    sol, st, g = wl.solute, wl.sites, wl.grid
+    sites, grid = api.sites_from(st), api.grid_from(g)
+    xyz, q, s, e = api.solute_to_device(sol)
+    q[650] = float("nan")
+    with pytest.raises(api.RismError) as ei:
+        api.initialize(xyz, q, s, e, sites, grid, _opts(method), ETA, KAPPA, BETA, DIEL)
+    assert ei.value.code == api.RISM_E_INVALID
+    xyz, q, s, e = api.solute_to_device(sol)
+    u, c, h = api.initialize(xyz, q, s, e, sites, grid, _opts(method), ETA, KAPPA, BETA, DIEL)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(c).all()) and bool(torch.isfinite(h).all())
