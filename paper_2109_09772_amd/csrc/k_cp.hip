@@ -328,6 +328,16 @@ __device__ __forceinline__ void cp_table_row(const CpTabArgs &a, int r, const do
     }
 }
 
+// Candidate atoms of a family that its fill workgroup assigns (eight rounds
+// of 512); above kAssignExtraMinAtoms atoms the rest go, in chunks of as
+// many, to the workgroups of a second launch (k_cp_assign_extra), so that a
+// family whose candidates are most of the atoms does not hold up the pass.
+// Below it the groups' classification spans the fill launch about as long
+// as the largest family, and the second launch would only add its own time
+// (at 14,000 atoms the lists took 0.233 ms with it, 0.214 without).
+constexpr int kAssignChunk = 4096;
+constexpr int64_t kAssignExtraMinAtoms = 32768;
+
 struct CpQueryArgs {
     CpLevels L;
     int mode, nq;
@@ -336,6 +346,8 @@ struct CpQueryArgs {
     const double *box;
     const int *n_nodes;
     uint32_t *cnt, *acnt;           // count pass (nq + 1 entries each; acnt optional)
+    uint32_t *ecnt;                 // count pass, optional (nq + 1): chunks of
+                                    // kAssignChunk candidate atoms after the first
     const uint32_t *off;            // fill pass
     int *list;
     const int *bad;                 // fill pass: lists sized too small, write nothing
@@ -393,6 +405,7 @@ __device__ __forceinline__ void cp_query(const CpQueryArgs &a, int q, int *stk)
     if (!a.fill && q == 0 && threadIdx.x == 0) {
         a.cnt[a.nq] = 0;
         if (a.acnt) a.acnt[a.nq] = 0;
+        if (a.ecnt) a.ecnt[a.nq] = 0;
     }
     if (q >= a.nq) return;   // the whole wave leaves together
     const CpLevels &L = a.L;
@@ -511,6 +524,7 @@ __device__ __forceinline__ void cp_query(const CpQueryArgs &a, int q, int *stk)
     if (!a.fill && lane == 0) {
         a.cnt[q] = n;
         if (a.acnt) a.acnt[q] = nat;
+        if (a.ecnt) a.ecnt[q] = nat > (uint32_t)kAssignChunk ? (nat - 1) / kAssignChunk : 0u;
     }
 }
 
@@ -838,16 +852,46 @@ __device__ __forceinline__ void order_by_cost(const OrderJob &j)
 // Far work items: each cluster's assigned atoms in runs of at most amax (at
 // least one item per cluster, so that every cluster's far field is formed),
 // numbered cluster by cluster; item_off[cl] is the first item of cluster cl.
+// A cluster's atoms come in pieces, one per assignment chunk of its family
+// (chunk c from position c kAssignChunk of the cluster's region on).
 struct CpItemArgs {
-    int ncl;
-    const uint32_t *n;     // assigned atoms per cluster
+    CpLevels L;
+    int ncl, nfam;
+    const uint32_t *n;     // assigned atoms per cluster (chunk 0)
+    const uint32_t *eoff;  // extra chunks before each family (prefix), or null
+    const uint32_t *pc;    // atoms of each extra chunk per child (CpAssignArgs::pc)
     uint32_t amax;         // atoms per item at most
     uint32_t *item_off;    // [ncl + 1]
     int *it_cl;            // cluster of each item
-    uint32_t *it_a0;       // first atom of the item within its cluster's run
+    uint32_t *it_a0;       // first atom of the item within its cluster's region
     uint32_t *it_na;       // atoms of the item
     uint32_t *n_items;     // items in all
 };
+
+// Cluster cl's family and its place (child) in it.
+__device__ __forceinline__ void cp_family_of(const CpLevels &L, int nfam, int cl, int &f, int &j)
+{
+    int lvl, I, J, K;
+    cp_decode(L, cl, lvl, I, J, K);
+    if (lvl >= L.T) {
+        f = nfam - 1;
+        j = 0;
+    } else {
+        f = cp_id(L, lvl + 1, I >> 1, J >> 1, K >> 1) - L.off[2];
+        j = (I & 1) | ((J & 1) << 1) | ((K & 1) << 2);
+    }
+}
+
+// The items of a piece of count atoms from position first: runs of at most
+// amax atoms, each passed to emit(a0, na); returns their number.
+template <class F>
+__device__ __forceinline__ uint32_t piece_items(uint32_t first, uint32_t count, uint32_t amax,
+                                                F emit)
+{
+    uint32_t k = 0;
+    for (uint32_t u = 0; u * amax < count; ++u, ++k) emit(first + u * amax, min(amax, count - u * amax));
+    return k;
+}
 
 __device__ __forceinline__ void cp_make_items(const CpItemArgs &a)
 {
@@ -859,7 +903,19 @@ __device__ __forceinline__ void cp_make_items(const CpItemArgs &a)
     for (int c0 = 0; c0 < a.ncl; c0 += kPlanThreads) {
         const int cl = c0 + tid;
         const uint32_t na = cl < a.ncl ? a.n[cl] : 0u;
-        const uint32_t k = cl < a.ncl ? max(1u, (na + a.amax - 1) / a.amax) : 0u;
+        int f = 0, jc = 0;
+        uint32_t e0 = 0, e1 = 0;   // the family's extra chunks
+        if (cl < a.ncl && a.eoff) {
+            cp_family_of(a.L, a.nfam, cl, f, jc);
+            e0 = a.eoff[f];
+            e1 = a.eoff[f + 1];
+        }
+        uint32_t k = 0;
+        if (cl < a.ncl) {
+            k = (na + a.amax - 1) / a.amax;
+            for (uint32_t e = e0; e < e1; ++e) k += (a.pc[8 * (size_t)e + jc] + a.amax - 1) / a.amax;
+            k = max(1u, k);
+        }
         uint32_t x = k;   // inclusive scan over the workgroup
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t y = __shfl_up(x, off);
@@ -875,11 +931,18 @@ __device__ __forceinline__ void cp_make_items(const CpItemArgs &a)
         const uint32_t first = base + x - k;
         if (cl < a.ncl) {
             a.item_off[cl] = first;
-            for (uint32_t j = 0; j < k; ++j) {
-                a.it_cl[first + j] = cl;
-                a.it_a0[first + j] = j * a.amax;
-                a.it_na[first + j] = min(a.amax, na - j * a.amax);
-            }
+            uint32_t w = first;
+            auto emit = [&](uint32_t a0, uint32_t n_at) {
+                a.it_cl[w] = cl;
+                a.it_a0[w] = a0;
+                a.it_na[w] = n_at;
+                ++w;
+            };
+            piece_items(0u, na, a.amax, emit);
+            for (uint32_t e = e0; e < e1; ++e)
+                piece_items((e - e0 + 1) * (uint32_t)kAssignChunk, a.pc[8 * (size_t)e + jc], a.amax,
+                            emit);
+            if (w == first) emit(0u, 0u);   // an empty cluster still has its item
         }
         __syncthreads();   // every thread has read carry and wsum
         if (tid == 0) carry += tot;
@@ -944,12 +1007,25 @@ struct CpAssignArgs {
     int np;
     double psc;                // scale of the assigned atoms' positions and charges
                                // (CpSweepArgs::psc)
+    // families of more than kAssignChunk candidate atoms: chunk c >= 1 (atoms
+    // [c, c + 1) kAssignChunk in candidate order) is extra chunk
+    // eoff[f] + c - 1, assigned by k_cp_assign_extra
+    const uint32_t *eoff;      // [nfam + 1] extra chunks before each family (prefix)
+    uint32_t *apre;            // per candidate leaf (as cand): atoms before it in its
+                               // family's order, written by chunk 0 when there are extra
+                               // chunks; or null
+    uint32_t *pc;              // [8 per extra chunk]: its atoms assigned to each child
+    const int *bad;
 };
 
-// One workgroup of NT threads assigns family f's candidates, windows of NT
-// candidate leaves at a time, their atoms dealt NT at a time to the threads.
+// One workgroup of NT threads assigns chunk c of family f's candidate atoms
+// (atoms [c, c + 1) kAssignChunk in candidate order; chunk 0 is the fill
+// workgroup's, extra chunk e = eoff[f] + c - 1 a workgroup of the extra
+// launch), windows of NT candidate leaves at a time, their atoms dealt NT at a
+// time to the threads.  Child j's atoms of the chunk go to its part of the
+// family's region from position c kAssignChunk on, in candidate order.
 template <int NT>
-__device__ __forceinline__ void cp_assign_family(const CpAssignArgs &a, int f)
+__device__ __forceinline__ void cp_assign_family(const CpAssignArgs &a, int f, int c, int e)
 {
     constexpr int NW = NT / 64;
     __shared__ int beg[NT];
@@ -984,12 +1060,36 @@ __device__ __forceinline__ void cp_assign_family(const CpAssignArgs &a, int f)
     }
     __syncthreads();
     const uint32_t base0 = a.aoff[f], naf = a.aoff[f + 1] - base0;
-    float4 *out = a.abuf + 8 * (size_t)base0;
+    const uint32_t alo = (uint32_t)c * kAssignChunk;
+    // (without extra chunks, chunk 0 is every candidate)
+    const uint32_t ahi = a.eoff ? min(naf, alo + (uint32_t)kAssignChunk) : naf;
+    const bool write_pre = c == 0 && a.apre && naf > (uint32_t)kAssignChunk;
+    float4 *out = a.abuf + 8 * (size_t)base0 + alo;
     uint32_t filled[8];   // workgroup-uniform
 #pragma unroll
     for (int j = 0; j < 8; ++j) filled[j] = 0;
     const int c0 = (int)a.cand_off[f], c1 = (int)a.cand_off[f + 1];
-    for (int cw = c0; cw < c1; cw += NT) {
+    int cstart = c0;
+    uint32_t wbase = 0;   // the family's atoms before the window (workgroup-uniform)
+    if (c > 0) {
+        // the chunk's first candidate leaf: the last with apre <= alo
+        __shared__ int kstart;
+        if (tid == 0) {
+            int lo = c0, hi = c1 - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (a.apre[mid] <= alo) lo = mid;
+                else hi = mid - 1;
+            }
+            kstart = lo;
+        }
+        __syncthreads();
+        cstart = kstart;
+        wbase = a.apre[cstart];
+    }
+    // (chunk 0 of a family with extra chunks runs through every window, for
+    // the prefixes; the others stop after their chunk's last atom)
+    for (int cw = cstart; cw < c1 && (write_pre || wbase < ahi); cw += NT) {
         // window of candidate leaves: first atom and atom prefix, in list order
         const int nw = min(NT, c1 - cw);
         int sz = 0;
@@ -1003,13 +1103,19 @@ __device__ __forceinline__ void cp_assign_family(const CpAssignArgs &a, int f)
         const int ex = group_excl_scan<NT>(sz, ws, run);
         if (tid < nw) pre[tid] = ex;
         if (tid == 0) pre[nw] = run;
+        if (write_pre && tid < nw) a.apre[cw + tid] = wbase + (uint32_t)ex;
         __syncthreads();
-        for (int t0 = 0, par = 0; t0 < run; t0 += NT, par ^= 1) {
+        // the window's atoms within the chunk: [tlo, thi) of its run
+        const uint32_t wend = wbase + (uint32_t)run;
+        const uint32_t glo = max(wbase, alo), ghi = min(wend, ahi);
+        const int tlo = (int)(glo - wbase), thi = ghi > glo ? (int)(ghi - wbase) : tlo;
+        wbase = wend;
+        for (int t0 = tlo, par = 0; t0 < thi; t0 += NT, par ^= 1) {
             const int t = t0 + tid;
             uint32_t acc = 0;   // bit j: assigned to child j
             double y[3] = {0.0, 0.0, 0.0};
             float q = 0.f;
-            if (t < run) {
+            if (t < thi) {
                 int lo = 0, hi = nw - 1;   // last k with pre[k] <= t
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
@@ -1053,12 +1159,16 @@ __device__ __forceinline__ void cp_assign_family(const CpAssignArgs &a, int f)
         }
         __syncthreads();   // the window is read before the next one is written
     }
-    if (tid < 8 && cid[tid] >= 0) {
+    if (tid < 8) {
         uint32_t fj = 0;
 #pragma unroll
         for (int j = 0; j < 8; ++j) fj = j == tid ? filled[j] : fj;
-        a.n[cid[tid]] = fj;
-        a.slot[cid[tid]] = 8 * base0 + (uint32_t)tid * naf;
+        if (c > 0) {
+            a.pc[8 * (size_t)e + tid] = fj;
+        } else if (cid[tid] >= 0) {
+            a.n[cid[tid]] = fj;
+            a.slot[cid[tid]] = 8 * base0 + (uint32_t)tid * naf;
+        }
     }
     if (tid == 0 && a.work) {
         unsigned long long tot = 0;
@@ -1084,12 +1194,31 @@ __global__ __launch_bounds__(kFillThreads, 4) void k_cp_fill(CpQueryArgs qc, CpQ
     if (q < qc.nq) {
         if (threadIdx.x < 64) cp_query(qc, q, stk);
         __syncthreads();
-        cp_assign_family<kFillThreads>(aa, q);
+        cp_assign_family<kFillThreads>(aa, q, 0, 0);
     } else {
         if (threadIdx.x < 64) cp_query(ql, q - qc.nq, stk);
         __syncthreads();
         cp_classify_group(ca, q - qc.nq);
     }
+}
+
+// Extra chunks of the families with more than kAssignChunk candidate atoms
+// (after k_cp_fill, which wrote their candidate lists and prefixes): one
+// workgroup per chunk, grid from an upper bound (the workgroups past the
+// device's count leave at once).  Workgroup e takes the family f with
+// eoff[f] <= e < eoff[f + 1], found in two rounds of loads.
+__global__ __launch_bounds__(kFillThreads, 4) void k_cp_assign_extra(CpAssignArgs aa)
+{
+    if (*aa.bad) return;   // whole workgroup: lists sized too small
+    const uint32_t e = blockIdx.x;
+    if (e >= aa.eoff[aa.nfam]) return;
+    const int n = aa.nfam + 1;
+    const int stride = (n + kFillThreads - 1) / kFillThreads;
+    const int t = threadIdx.x;
+    const int k1 = __syncthreads_count(t * stride < n && aa.eoff[t * stride] <= e) - 1;
+    const int base = k1 * stride;
+    const int f = base - 1 + __syncthreads_count(t < stride && base + t < n && aa.eoff[base + t] <= e);
+    cp_assign_family<kFillThreads>(aa, f, (int)(e - aa.eoff[f]) + 1, (int)e);
 }
 
 // Far field of one work item into its cluster's proxies: every thread owns NR
@@ -2196,6 +2325,9 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
     // 2..T, and the top cluster alone
     const int nfam = ncl > 0 ? ncl - L.off[2] + 1 : 0;
     uint32_t *ccnt = ws.get<uint32_t>(nfam + 1), *cacnt = ws.get<uint32_t>(nfam + 1);
+    // extra assignment chunks per family (prefix after the scan)
+    const bool extra_chunks = ncl > 0 && a.solute->n > kAssignExtraMinAtoms;
+    uint32_t *ecnt = extra_chunks ? ws.get<uint32_t>(nfam + 1) : nullptr;
     uint32_t *lcnt = ws.get<uint32_t>(ngrp + 1), *lacnt = ws.get<uint32_t>(ngrp + 1);
     if (ws.status()) return ws.status();
     int dev = 0;
@@ -2249,6 +2381,7 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         qc.nq = nfam;
         qc.cnt = ccnt;
         qc.acnt = cacnt;
+        qc.ecnt = ecnt;
         qc.fill = 0;
         CpQueryArgs ql = qa;   // groups of level-0 blocks
         ql.mode = 1;
@@ -2270,6 +2403,13 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         if (ncl > 0) {   // (otherwise their totals stay 0)
             add(ccnt, 0, nfam + 1);
             add(cacnt, 4, nfam + 1);
+        }
+        if (ecnt) {   // total into flags[7], no capacity of its own
+            sb.a[na] = ecnt;
+            sb.total[na] = tot + 7;
+            sb.n[na] = nfam + 1;
+            sb.cap[na] = 0xffffffffu;
+            ++na;
         }
         add(lcnt, 2, ngrp + 1);
         add(lacnt, 3, ngrp + 1);
@@ -2331,7 +2471,12 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
         // far work items: runs of at most item_atoms of a cluster's atoms (a
         // family's children have room for all of its candidate atoms each)
         const size_t max_assigned = 8 * (size_t)cap.c[4];
-        const int max_items = ncl + (int)((max_assigned + item_atoms - 1) / item_atoms);
+        // extra assignment chunks (at most one per kAssignChunk candidate
+        // atoms), each adding up to eight partial items
+        const int n_extra = ecnt ? (int)(cap.c[4] / kAssignChunk) : 0;
+        const int max_items = ncl + (int)((max_assigned + item_atoms - 1) / item_atoms) + 8 * n_extra;
+        uint32_t *apre = n_extra > 0 ? ws.get<uint32_t>(cap.c[0] + 1) : nullptr;
+        uint32_t *pc = n_extra > 0 ? ws.get<uint32_t>(8 * (size_t)n_extra) : nullptr;
         int *it_cl = ws.get<int>(max_items + 1), *it_order = ws.get<int>(max_items + 1);
         uint32_t *it_a0 = ws.get<uint32_t>(max_items + 1), *it_na = ws.get<uint32_t>(max_items + 1);
         uint32_t *n_items = ws.get<uint32_t>(1);
@@ -2376,6 +2521,10 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             aa.work = work ? work + 2 : nullptr;
             aa.np = np;
             aa.psc = psc;
+            aa.eoff = n_extra > 0 ? ecnt : nullptr;
+            aa.apre = apre;
+            aa.pc = pc;
+            aa.bad = bad;
             CpClassArgs ca{};
             ca.L = L;
             ca.nq = ngrp;
@@ -2394,10 +2543,16 @@ int tree_forward_cp(const TreeCallArgs &a, Workspace &ws, rism_stats &st, hipStr
             ca.ns = nsh;
             ca.cost = cost;
             hipLaunchKernelGGL(k_cp_fill, nfam + ngrp, kFillThreads, qshm, s, qc, ql, aa, ca);
+            if (n_extra > 0)
+                hipLaunchKernelGGL(k_cp_assign_extra, n_extra, kFillThreads, 0, s, aa);
             const OrderJob leaf_order{nleaf, nullptr, cost, nullptr, order};
             CpItemArgs ia{};
+            ia.L = L;
             ia.ncl = ncl;
+            ia.nfam = nfam;
             ia.n = cl_n;
+            ia.eoff = n_extra > 0 ? ecnt : nullptr;
+            ia.pc = pc;
             ia.amax = item_atoms;
             ia.item_off = item_off;
             ia.it_cl = it_cl;
