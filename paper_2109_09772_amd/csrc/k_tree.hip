@@ -360,6 +360,7 @@ constexpr int kRankTargets = 64;   // atoms ranked per workgroup
 // lane, about 20 us at 16K atoms, still below the multi-kernel radix sort and
 // level-by-level split (about 0.3 ms at 14,000 atoms).
 constexpr int kSmallTreeMax = 16384;
+static_assert(kSmallTreeMax <= (1 << 14), "k_tree_rank packs the atom index into 14 bits");
 
 // Stores node's box and its centre and radius (half-diagonal) from the
 // box's corners.
@@ -448,33 +449,33 @@ __global__ __launch_bounds__(kRankThreads) void k_tree_rank(const float4 *rec, i
                                                             float4 *sorted, double *root_box,
                                                             double *root_centre)
 {
-    extern __shared__ uint4 k4[];   // [round_up(n, 4 kRankWaves) / 4]
+    // every atom's (key, index) as one 64-bit word, key << 14 | index (the
+    // index is below kSmallTreeMax = 2^14): the words are distinct, so one
+    // unsigned comparison orders them as the stable sort does
+    extern __shared__ uint4 k4[];   // [round_up(n, 4 kRankWaves) / 2]
     __shared__ int part[kRankWaves][kRankTargets];
     __shared__ double bb[6], tb[6];
-    uint32_t *kk = reinterpret_cast<uint32_t *>(k4);
+    unsigned long long *kk = reinterpret_cast<unsigned long long *>(k4);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     small_key_cube(rec, stride_f4, n, bpart, nbpart, bb, tb);
     if (blockIdx.x == 0 && tid == 0) store_node_box(0, tb, tb + 3, root_box, root_centre);
     const int np = (n + 4 * kRankWaves - 1) / (4 * kRankWaves) * (4 * kRankWaves);
     for (int i = tid; i < np; i += kRankThreads) {
-        const uint32_t key = i < n ? atom_key(rec, stride_f4, i, bb) : 0xffffffffu;
-        kk[i] = key;
+        const uint32_t key = i < n ? atom_key(rec, stride_f4, i, bb) : 0u;
+        kk[i] = i < n ? ((unsigned long long)key << 14) | (unsigned)i : ~0ull;
         if (blockIdx.x == 0 && i < n) keys[i] = key;
     }
     __syncthreads();
     const int t = blockIdx.x * kRankTargets + lane;
-    const int q = np / 4 / kRankWaves;   // units of four keys per wave
+    const int q = np / 2 / kRankWaves;   // units of two words per wave
     int c = 0;
     if (t < n) {
-        const uint32_t key = kk[t];
+        const unsigned long long w = kk[t];
 #pragma unroll 4
         for (int j = wave * q; j < (wave + 1) * q; ++j) {
             const uint4 v = k4[j];   // the same j on every lane: one broadcast read
-            const int jj = 4 * j;
-            c += (v.x < key || (v.x == key && jj < t)) ? 1 : 0;
-            c += (v.y < key || (v.y == key && jj + 1 < t)) ? 1 : 0;
-            c += (v.z < key || (v.z == key && jj + 2 < t)) ? 1 : 0;
-            c += (v.w < key || (v.w == key && jj + 3 < t)) ? 1 : 0;
+            c += (((unsigned long long)v.y << 32) | v.x) < w ? 1 : 0;
+            c += (((unsigned long long)v.w << 32) | v.z) < w ? 1 : 0;
         }
     }
     part[wave][lane] = c;
@@ -1000,7 +1001,7 @@ int build_source_tree(const TreeCallArgs &a, Workspace &ws, TreeDev &t, rism_sta
             // (one workgroup at least: it also places the padding records)
             const int npad = (n + 4 * kRankWaves - 1) / (4 * kRankWaves) * (4 * kRankWaves);
             hipLaunchKernelGGL(k_tree_rank, std::max(1, (n + kRankTargets - 1) / kRankTargets),
-                               kRankThreads, (size_t)npad * sizeof(uint32_t), s, rec, stride_f4,
+                               kRankThreads, (size_t)npad * sizeof(unsigned long long), s, rec, stride_f4,
                                n, (int)a.npad, a.bbox_part, a.n_bbox_part, v1, k0, v0,
                                static_cast<float4 *>(t.sorted_rec), t.box, t.centre);
         }
